@@ -1,0 +1,265 @@
+/*
+ * sph.h -- C ABI of the MI355X DFSPH time step (libsph.so).
+ *
+ * The library advances a particle fluid by one Divergence-Free SPH step as
+ * arXiv 2403.11156 ("Journey into SPH Simulation") states the problem:
+ * particles carry mass, position and velocity (Sec. 3.2); fluid and rigid
+ * particle sets with radius r, support radius h, rest density rho0, a
+ * viscosity model and a domain are configured up front (Sec. 4.1); one call
+ * runs one simulation iteration in the order of Algorithm 1 and Sec. 4.2
+ * (gravity, viscosity, pressure, then rigid and fluid update), with the
+ * pressure found by the iterative scheme of Algorithm 2 applied to the
+ * velocity-source (Eq. 10) and density-source (Eqs. 8-9) problems.
+ *
+ * Conventions for every call:
+ *   - Status codes: SPH_OK (0) or a negative SPH_ERR_*.  No C++ exception
+ *     crosses this boundary.  sph_last_error() returns the message of the
+ *     most recent failure on a context (thread-local for sph_create).
+ *   - Host arrays passed in are copied; the caller keeps ownership.  Host
+ *     arrays passed out are caller-owned and filled by the call.
+ *   - Arrays of 3-vectors are array-of-structures float32 [n][3].  Particle
+ *     arrays exchanged with the host are in ORIGINAL order (the index the
+ *     particle had in the scene), whatever order the device keeps them in.
+ *   - "Device pointer" means memory from hipMalloc (or a torch tensor on
+ *     the same device); the library never frees memory it did not allocate.
+ *   - All device work is queued on the stream given to sph_create (NULL =
+ *     the legacy default stream).  Calls that return host data synchronise
+ *     that stream.  One context per stream; a context is not thread-safe.
+ */
+#ifndef SPH_H_
+#define SPH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPH_ABI_VERSION 1
+
+/* status codes */
+#define SPH_OK 0
+#define SPH_ERR_INVALID -1  /* bad argument or parameter */
+#define SPH_ERR_OOM -2      /* device or host allocation failed */
+#define SPH_ERR_DEVICE -3   /* a HIP call failed */
+#define SPH_ERR_CAPACITY -4 /* a neighbour list exceeded its capacity */
+#define SPH_ERR_STATE -5    /* call out of order (e.g. step without fresh neighbours) */
+#define SPH_ERR_NUMERIC -6  /* non-finite state after a step */
+
+/* viscosity models (Sec. 3.6) */
+#define SPH_VISC_NONE 0
+#define SPH_VISC_XSPH 1      /* v* += eps sum_j (m/rho_j)(v_j - v_i) W_ij */
+#define SPH_VISC_LAPLACIAN 2 /* explicit Laplacian, Eq. (15), nu in m^2/s */
+#define SPH_VISC_IMPLICIT 3  /* implicit solve (I - dt A) v* = v~, Eqs. (16)-(19), CG */
+
+/* initial stiffness of the two pressure solves (Algorithm 2, "initialize p^l") */
+#define SPH_WARM_ZERO 0
+#define SPH_WARM_PREVIOUS 1 /* warm_factor * the previous step's accumulated stiffness */
+#define SPH_WARM_LEARNED 2  /* density solve: per-particle MLP prediction (sph_set_warm_start) */
+
+typedef struct sph_ctx sph_ctx;
+typedef struct sph_mlp sph_mlp;
+
+/*
+ * Simulation parameters (Sec. 4.1).  All lengths in metres, SI units.
+ *   r, h            particle radius and kernel support radius (Sec. 3.2);
+ *                   the fluid mass is m = rho0 (2r)^3.
+ *   rho0            rest density (Sec. 5: 1000 kg/m^3).
+ *   gravity         body acceleration (Eq. 3, f_ext / rho).
+ *   domain_min/max  fluid container interior; the uniform grid covers it
+ *                   with one cell of margin, particles outside are clamped
+ *                   into the border cells (neighbour sets stay exact).
+ *   eta_density     stop threshold of the density solve: mean over fluid
+ *                   particles of max(rho* - rho0, 0) / rho0 (Algorithm 2).
+ *   eta_divergence  stop threshold of the divergence solve: dt/rho0 times
+ *                   the mean of max(D rho / Dt, 0).
+ *   max_iters       iteration cap of each solve (non-convergence is flagged
+ *                   in the stats, it is not an error).
+ *   dt_max          the time step when cfl_lambda == 0, else its upper bound.
+ *   cfl_lambda      > 0: dt = fl32(min(dt_max, cfl_lambda * 2r / max|v|)).
+ *   visc_model/visc SPH_VISC_*; visc is the XSPH epsilon or the kinematic
+ *                   viscosity nu [m^2/s] (mu = nu rho0).
+ *   cg_tol/cg_max_iters  implicit viscosity: relative residual and cap.
+ *   warm_start      SPH_WARM_*; warm_factor scales the previous stiffness.
+ *   max_neighbors, max_boundary_neighbors  list capacities per particle.
+ *   auto_rebuild    1: sph_step rebuilds stale neighbour lists itself.
+ */
+typedef struct sph_params {
+    double r, h, rho0;
+    double gravity[3];
+    double domain_min[3], domain_max[3];
+    double eta_density, eta_divergence;
+    int32_t max_iters;
+    double dt_max, cfl_lambda;
+    int32_t visc_model;
+    double visc;
+    double cg_tol;
+    int32_t cg_max_iters;
+    int32_t warm_start;
+    double warm_factor;
+    int32_t max_neighbors, max_boundary_neighbors;
+    int32_t auto_rebuild;
+} sph_params;
+
+/* A rigid body (Sec. 3.5): mass, principal moments of inertia (body frame,
+ * diagonal), centre of mass, orientation quaternion (w, x, y, z), linear and
+ * angular velocity (world frame).  FP64. */
+typedef struct sph_rigid_desc {
+    double mass;
+    double inertia[3];
+    double com[3];
+    double quat[4];
+    double vel[3];
+    double omega[3];
+} sph_rigid_desc;
+
+/* Initial scene (Sec. 4.1: fluid blocks and rigid bodies sampled as Akinci
+ * boundary particles).  body_of_boundary[k] = -1 for the static tank, else
+ * the index of the rigid body particle k samples; rigid particles move with
+ * their body. */
+typedef struct sph_scene {
+    int64_t n_fluid, n_boundary;
+    int32_t n_rigid;
+    const float *x_fluid;            /* [n_fluid][3] */
+    const float *v_fluid;            /* [n_fluid][3], NULL = zero */
+    const float *x_boundary;         /* [n_boundary][3] */
+    const int32_t *body_of_boundary; /* [n_boundary], NULL = all static */
+    const sph_rigid_desc *rigid;     /* [n_rigid] */
+} sph_scene;
+
+/* Host statistics of one sph_step. */
+typedef struct sph_step_stats {
+    double dt;
+    int32_t iters_div, iters_dens;         /* Jacobi iterations of the two solves */
+    int32_t converged_div, converged_dens; /* err <= eta at exit */
+    double err_div, err_dens;              /* final errors (FP64 reductions) */
+    int32_t cg_iters;                      /* implicit viscosity */
+    double cg_resid;                       /* final |r| / |b| */
+    int32_t nbr_min, nbr_max;              /* fluid + boundary neighbours per fluid particle */
+    double nbr_mean;
+    int32_t warm_fallback;                 /* learned warm start fell back to PREVIOUS */
+    int64_t step_index;                    /* steps completed, including this one */
+} sph_step_stats;
+
+/* field mask for sph_read_state / sph_write_state */
+#define SPH_FIELD_X (1u << 0)        /* fluid positions (read, write) */
+#define SPH_FIELD_V (1u << 1)        /* fluid velocities (read, write) */
+#define SPH_FIELD_RHO (1u << 2)      /* density of the last step, Eq. (12) */
+#define SPH_FIELD_ALPHA (1u << 3)    /* DFSPH factor of the last step */
+#define SPH_FIELD_K (1u << 4)        /* accumulated density stiffness (read, write) */
+#define SPH_FIELD_KV (1u << 5)       /* accumulated divergence stiffness (read, write) */
+#define SPH_FIELD_KAPPA (1u << 6)    /* stiffness applied in the last density iteration */
+#define SPH_FIELD_ACCEL (1u << 7)    /* (v_new - v_old) / dt of the last step */
+#define SPH_FIELD_NBR (1u << 8)      /* fluid and boundary neighbour counts */
+#define SPH_FIELD_PSI (1u << 9)      /* Akinci boundary mass Psi, Eq. (11) */
+#define SPH_FIELD_BOUNDARY (1u << 10)/* boundary positions and velocities (read, write) */
+#define SPH_FIELD_RIGID (1u << 11)   /* rigid states (read, write), force and torque (read) */
+
+/* Host buffers for sph_read_state / sph_write_state; NULL members are
+ * skipped.  Fluid arrays have n_fluid entries, boundary arrays n_boundary,
+ * rigid arrays n_rigid; all in original order. */
+typedef struct sph_host_view {
+    float *x, *v;
+    float *rho, *alpha, *K, *Kv, *kappa, *accel;
+    int32_t *n_fluid_nbrs, *n_boundary_nbrs;
+    float *psi;
+    float *x_boundary, *v_boundary;
+    sph_rigid_desc *rigid;
+    double *rigid_force, *rigid_torque; /* [n_rigid][3], Eq. (14) summed per body */
+} sph_host_view;
+
+/* Static facts about a context. */
+typedef struct sph_info {
+    int64_t n_fluid, n_boundary;
+    int32_t n_rigid;
+    int32_t grid_n[3];       /* cells per axis */
+    float cell, inv_cell;    /* cell edge fl32(h (1 + 2^-10)) and fl32(1/cell) */
+    float origin[3];         /* fl32(domain_min - cell) */
+    float h2;                /* fl32(h)^2, the neighbour predicate d^2 < h2 */
+    int32_t max_neighbors, max_boundary_neighbors;
+    int64_t device_bytes;    /* device memory the context holds */
+} sph_info;
+
+/* ---- life cycle -------------------------------------------------------- */
+
+/* Create a context: validate, allocate device buffers, upload the scene.
+ * hip_stream is a hipStream_t (borrowed) or NULL.  On failure *out stays
+ * NULL and a negative status is returned. */
+int sph_create(const sph_params *params, const sph_scene *scene, void *hip_stream, sph_ctx **out);
+
+void sph_destroy(sph_ctx *ctx);
+
+/* ---- the time step ----------------------------------------------------- */
+
+/* Uniform-grid neighbour search (Sec. 5.6, prefix sums): cell keys of the
+ * current positions, counting sort by (cell key, particle id), reordering of
+ * the particle state, fluid and boundary neighbour lists (d^2 < h^2 in FP32,
+ * ascending sorted index), and the boundary mass Psi of Eq. (11) when the
+ * boundary moved.  Queued on the stream; synchronises once to read the
+ * capacity flag.  SPH_ERR_CAPACITY: a list overflowed; the lists are left
+ * stale and the state unchanged apart from its order. */
+int sph_build_neighbors(sph_ctx *ctx);
+
+/* One DFSPH step (Algorithm 1 with Algorithm 2): time step, density and
+ * factor alpha (Eq. 12), divergence-free solve (Eq. 10), non-pressure
+ * accelerations (gravity and viscosity, Sec. 3.6), warm start, constant-
+ * density solve (Eqs. 8-9, pressure acceleration Eq. 7 and boundary term
+ * Eq. 13), reaction on rigid bodies (Eq. 14) and their FP64 update,
+ * symplectic Euler.  Needs fresh neighbours (else SPH_ERR_STATE unless
+ * auto_rebuild).  stats may be NULL.  SPH_ERR_NUMERIC if the new state is not
+ * finite (the state is kept for inspection). */
+int sph_step(sph_ctx *ctx, sph_step_stats *stats);
+
+/* ---- state exchange ---------------------------------------------------- */
+
+/* Blocking copy of the fields in field_mask into dst (original order). */
+int sph_read_state(sph_ctx *ctx, uint32_t field_mask, const sph_host_view *dst);
+
+/* Overwrite x, v, K, Kv, boundary and rigid state from host buffers
+ * (original order); marks the neighbour lists stale.  Used to resume from a
+ * checkpoint or to re-anchor a test on given inputs. */
+int sph_write_state(sph_ctx *ctx, uint32_t field_mask, const sph_host_view *src);
+
+int sph_get_info(const sph_ctx *ctx, sph_info *info);
+
+/* ---- diagnostics ------------------------------------------------------- */
+
+/* Neighbour structure of the last build, for bit-exact comparison, all in
+ * sorted-index space.  Fluid: keys_f[n_fluid] (cell key of the particle at
+ * each sorted position), perm_f[n_fluid] (its original index), start_f
+ * [ncell+1] (first sorted position of each cell), counts_f[n_fluid] and
+ * lists_f (CSR concatenation, capacity cap_f entries) of fluid neighbours,
+ * counts_b/lists_b (capacity cap_b) of boundary neighbours (indices into the
+ * sorted boundary set); keys_b, perm_b, start_b for the boundary set.  NULL
+ * pointers are skipped.  SPH_ERR_CAPACITY if a CSR capacity is too small,
+ * SPH_ERR_STATE if no build happened since the last change of state. */
+typedef struct sph_nbr_view {
+    uint32_t *keys_f, *perm_f, *start_f, *counts_f, *lists_f;
+    uint32_t *keys_b, *perm_b, *start_b, *counts_b, *lists_b;
+    int64_t cap_f, cap_b;
+} sph_nbr_view;
+int sph_read_neighbors(sph_ctx *ctx, const sph_nbr_view *dst);
+
+/* Run exactly div / dens iterations in the next steps regardless of the
+ * error (-1 restores the stop rule).  For parity runs against a reference
+ * whose stop decision falls within rounding of eta. */
+int sph_set_forced_iters(sph_ctx *ctx, int32_t div, int32_t dens);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch of the named kernels while enabled.  sph_profile_read returns
+ * the launch count and the summed event time [ms] of one kernel name, and the
+ * algorithmic bytes those launches moved by the model stated in the design
+ * notes.  Names: "nbr_build", "density_alpha", "pressure_update", "predict",
+ * "xsph", "visc", "sort", "integrate". */
+int sph_profile_enable(sph_ctx *ctx, int32_t enable);
+int sph_profile_read(sph_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms, double *bytes);
+
+/* ---- errors -------------------------------------------------------------- */
+const char *sph_last_error(const sph_ctx *ctx);
+const char *sph_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPH_H_ */
