@@ -76,6 +76,7 @@ class Out(C.Structure):
         ("features", C.c_void_p), ("target", C.c_void_p),
         ("xb_new", C.c_void_p), ("vb_new", C.c_void_p), ("rigid_new", C.c_void_p),
         ("force", C.c_void_p), ("torque", C.c_void_p),
+        ("S_force", C.c_void_p), ("S_torque", C.c_void_p),
         ("dt", C.c_double),
         ("iters_div", C.c_int32), ("iters_dens", C.c_int32),
         ("converged_div", C.c_int32), ("converged_dens", C.c_int32), ("cg_iters", C.c_int32),
@@ -352,6 +353,8 @@ def step(state: State, forced_div: int = -1, forced_dens: int = -1, brute: Optio
     o["vb_new"] = np.zeros((max(1, nb), 3), np.float32)
     o["force"] = np.zeros((max(1, nr), 3))
     o["torque"] = np.zeros((max(1, nr), 3))
+    o["S_force"] = np.zeros((max(1, nr), 3))
+    o["S_torque"] = np.zeros((max(1, nr), 3))
     feats = want_features or pd["warm_start"] == 2
     if want_features:
         o["features"] = np.zeros((nf, 5))
@@ -371,8 +374,8 @@ def step(state: State, forced_div: int = -1, forced_dens: int = -1, brute: Optio
     o["psi"] = o["psi"][:nb]
     o["xb_new"] = o["xb_new"][:nb]
     o["vb_new"] = o["vb_new"][:nb]
-    o["force"] = o["force"][:nr]
-    o["torque"] = o["torque"][:nr]
+    for k in ("force", "torque", "S_force", "S_torque"):
+        o[k] = o[k][:nr]
     o["rigid_new"] = [_rigid_dict(rnew[i]) for i in range(nr)]
     for k in ("dt", "iters_div", "iters_dens", "converged_div", "converged_dens", "cg_iters", "err_div",
               "err_dens", "S_err_div", "S_err_dens", "cg_resid"):

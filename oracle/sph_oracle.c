@@ -90,6 +90,7 @@ typedef struct or_out {
     float *xb_new, *vb_new;    /* [nb][3] boundary state for the next step */
     or_rigid *rigid_new;       /* [n_rigid] */
     double *force, *torque;    /* [n_rigid][3] */
+    double *S_force, *S_torque;/* [n_rigid][3] error scales */
     /* stats */
     double dt;
     int32_t iters_div, iters_dens, converged_div, converged_dens, cg_iters;
@@ -923,19 +924,34 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
      *    F_b = sum_i sum_{k in b} m Psi_k (K_tot_i / rho_i) gradW_ik,
      *    tau_b = sum (x_k - c_b) x F_ik. */
     for (int32_t b = 0; b < p->n_rigid; ++b)
-        for (int a = 0; a < 3; ++a) { out->force[3 * b + a] = 0.0; out->torque[3 * b + a] = 0.0; }
+        for (int a = 0; a < 3; ++a) {
+            out->force[3 * b + a] = 0.0; out->torque[3 * b + a] = 0.0;
+            if (out->S_force) { out->S_force[3 * b + a] = 0.0; out->S_torque[3 * b + a] = 0.0; }
+        }
     for (int64_t i = 0; i < nf; ++i) {
         FOR_B(i, e) {
             int64_t k = w->fb.idx[e];
             int32_t b = in->body[k];
             if (b < 0) continue;
-            double x[3], gw[3], F[3], rr[3], t[3];
+            double x[3], gw[3], sg[3], F[3], SF[3], rr[3], t[3];
             xij_b(w, i, k, x);
             or_gradW(x, w->h, gw);
+            gradW_scale(x, w->h, sg);
             double c = w->m * w->psi[k] * (Kv[i] + K[i]) / w->rho[i];
-            for (int a = 0; a < 3; ++a) { F[a] = c * gw[a]; rr[a] = w->xb[3 * k + a] - in->rigid[b].com[a]; }
+            double Sc = w->m * w->psi[k] * (SKv[i] + SK[i] + fabs(Kv[i] + K[i])) / w->rho[i];
+            for (int a = 0; a < 3; ++a) {
+                F[a] = c * gw[a]; SF[a] = Sc * sg[a];
+                rr[a] = w->xb[3 * k + a] - in->rigid[b].com[a];
+            }
             cross(rr, F, t);
             for (int a = 0; a < 3; ++a) { out->force[3 * b + a] += F[a]; out->torque[3 * b + a] += t[a]; }
+            if (out->S_force) {
+                double ar[3] = {fabs(rr[0]), fabs(rr[1]), fabs(rr[2])};
+                out->S_force[3 * b + 0] += SF[0]; out->S_force[3 * b + 1] += SF[1]; out->S_force[3 * b + 2] += SF[2];
+                out->S_torque[3 * b + 0] += ar[1] * SF[2] + ar[2] * SF[1];
+                out->S_torque[3 * b + 1] += ar[2] * SF[0] + ar[0] * SF[2];
+                out->S_torque[3 * b + 2] += ar[0] * SF[1] + ar[1] * SF[0];
+            }
         }
     }
 

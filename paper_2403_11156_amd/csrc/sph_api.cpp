@@ -1,0 +1,1048 @@
+// sph_api.cpp -- host runtime and C ABI of libsph.so (see include/sph.h).
+//
+// The context owns the device buffers, drives the kernels of one DFSPH step
+// on its stream, runs the convergence loops of the two Jacobi solves
+// (Algorithm 2: stop when the FP64-reduced error is at most eta), and
+// integrates the rigid bodies on the host in FP64 (weak coupling: their
+// velocities are fixed during the fluid solve).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sph.h"
+#include "sph_internal.h"
+
+using sph::BodyPose;
+using sph::Grid;
+using sph::Kern;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct ProfEvent {
+    std::string name;
+    hipEvent_t a, b;
+    double bytes;
+};
+
+struct ProfTotal {
+    int64_t launches = 0;
+    double ms = 0.0, bytes = 0.0;
+};
+
+}  // namespace
+
+struct sph_ctx {
+    sph_params P{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int64_t nf = 0, nb = 0;
+    int32_t nr = 0;
+    Grid g{};
+    Kern kc{};
+    float cell = 0.f;
+    int64_t ncell = 0;
+    int32_t capf = 0, capb = 0;
+
+    // fluid, sorted order
+    float4 *x = nullptr, *x2 = nullptr, *v = nullptr, *v2 = nullptr, *v_in = nullptr;
+    float *rho = nullptr, *alpha = nullptr, *K = nullptr, *K2 = nullptr, *Kv = nullptr, *Kv2 = nullptr;
+    float *kappa = nullptr, *kappa_last = nullptr;
+    int32_t *id = nullptr, *id2 = nullptr;
+    uint32_t *key = nullptr, *slot = nullptr, *src = nullptr, *count = nullptr, *start_f = nullptr;
+    uint32_t *scan_part = nullptr;
+    uint32_t *nlist = nullptr, *ncnt = nullptr, *blist = nullptr, *bcnt = nullptr;
+    // boundary, sorted order (xb.w = Psi, vb.w = body id)
+    float4 *xb = nullptr, *xb2 = nullptr, *vb = nullptr, *vb2 = nullptr;
+    int32_t *bid = nullptr, *bid2 = nullptr;
+    uint32_t *bkey = nullptr, *bslot = nullptr, *bsrc = nullptr, *start_b = nullptr;
+    double *blocal = nullptr;   // [nb][3] body-frame offsets, original order
+    BodyPose *poses = nullptr;
+    double *com_dev = nullptr;
+    // reductions and flags
+    double *red_part = nullptr, *scal = nullptr, *rigid_out = nullptr;
+    uint32_t *counter = nullptr, *flags = nullptr, *vmax_bits = nullptr;
+    unsigned long long *nstats = nullptr;
+    // implicit viscosity
+    float *Pinv = nullptr;
+    float4 *cg_b = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
+    // pinned host staging
+    double *h_scal = nullptr;
+    uint32_t *h_u32 = nullptr;
+    unsigned long long *h_stats = nullptr;
+
+    std::vector<sph_rigid_desc> rigid;
+    std::vector<double> force, torque;
+    std::vector<double> local_host;   // [nb][3] body-frame offsets, original order
+    std::vector<int32_t> body_host;   // [nb]
+    std::vector<void *> allocs;
+    int64_t dev_bytes = 0;
+
+    bool nbr_fresh = false, boundary_dirty = true, sorted_once = false;
+    int64_t step_index = 0;
+    float last_dt = 0.f;
+    int32_t forced_div = -1, forced_dens = -1;
+    double nbr_sum = 0.0, nbr_sum_f = 0.0;
+    std::string err;
+
+    bool prof = false;
+    std::vector<ProfEvent> prof_pending;
+    std::map<std::string, ProfTotal> prof_total;
+};
+
+namespace {
+
+int fail(sph_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                           \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return fail(ctx, SPH_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+template <typename T>
+int dev_alloc(sph_ctx *c, T **p, int64_t count) {
+    size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(c, SPH_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    c->allocs.push_back(q);
+    c->dev_bytes += (int64_t)bytes;
+    *p = (T *)q;
+    return SPH_OK;
+}
+
+void free_all(sph_ctx *c) {
+    for (void *p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    if (c->h_scal) (void)hipHostFree(c->h_scal);
+    if (c->h_u32) (void)hipHostFree(c->h_u32);
+    if (c->h_stats) (void)hipHostFree(c->h_stats);
+    c->h_scal = nullptr;
+    c->h_u32 = nullptr;
+    c->h_stats = nullptr;
+    for (auto &e : c->prof_pending) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    c->prof_pending.clear();
+}
+
+// ---- profiling -------------------------------------------------------------
+struct ProfScope {
+    sph_ctx *c;
+    ProfEvent ev{};
+    bool on;
+    ProfScope(sph_ctx *ctx, const char *name, double bytes) : c(ctx), on(ctx->prof) {
+        if (!on) return;
+        ev.name = name;
+        ev.bytes = bytes;
+        (void)hipEventCreate(&ev.a);
+        (void)hipEventCreate(&ev.b);
+        (void)hipEventRecord(ev.a, c->stream);
+    }
+    ~ProfScope() {
+        if (!on) return;
+        (void)hipEventRecord(ev.b, c->stream);
+        c->prof_pending.push_back(ev);
+    }
+};
+
+void prof_resolve(sph_ctx *c) {
+    if (c->prof_pending.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &e : c->prof_pending) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e.a, e.b);
+        ProfTotal &t = c->prof_total[e.name];
+        t.launches += 1;
+        t.ms += ms;
+        t.bytes += e.bytes;
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    c->prof_pending.clear();
+}
+
+// ---- rigid body helpers (FP64) -------------------------------------------
+void quat_to_R(const double q[4], double R[9]) {
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+void cross3(const double a[3], const double b[3], double c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+int upload_poses(sph_ctx *c) {
+    if (c->nr == 0) return SPH_OK;
+    std::vector<BodyPose> poses(c->nr);
+    std::vector<double> com(3 * c->nr);
+    for (int b = 0; b < c->nr; ++b) {
+        const sph_rigid_desc &s = c->rigid[b];
+        quat_to_R(s.quat, poses[b].R);
+        for (int a = 0; a < 3; ++a) {
+            poses[b].com[a] = s.com[a];
+            poses[b].vel[a] = s.vel[a];
+            poses[b].omega[a] = s.omega[a];
+            com[3 * b + a] = s.com[a];
+        }
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->poses, poses.data(), sizeof(BodyPose) * c->nr, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->com_dev, com.data(), sizeof(double) * 3 * c->nr, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return SPH_OK;
+}
+
+// Newton-Euler in FP64 with the world inertia R diag(I) R^T, then the
+// tank-contact stand-in: push the body back inside [min + r, max - r] along
+// each axis and drop the velocity component into the wall.
+void rigid_integrate(sph_ctx *c, double dt, const std::vector<double> &local_host,
+                     const std::vector<int32_t> &body_host) {
+    const double *gr = c->P.gravity;
+    for (int b = 0; b < c->nr; ++b) {
+        sph_rigid_desc s = c->rigid[b];
+        double R[9], Iw[9], Iwinv[9];
+        quat_to_R(s.quat, R);
+        for (int a = 0; a < 3; ++a)
+            for (int q = 0; q < 3; ++q) {
+                Iw[3 * a + q] = 0.0;
+                Iwinv[3 * a + q] = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    Iw[3 * a + q] += R[3 * a + k] * s.inertia[k] * R[3 * q + k];
+                    Iwinv[3 * a + q] += R[3 * a + k] / s.inertia[k] * R[3 * q + k];
+                }
+            }
+        for (int a = 0; a < 3; ++a) s.vel[a] += dt * (c->force[3 * b + a] / s.mass + gr[a]);
+        double Lw[3], gyro[3], rhs[3];
+        for (int a = 0; a < 3; ++a) Lw[a] = Iw[3 * a] * s.omega[0] + Iw[3 * a + 1] * s.omega[1] + Iw[3 * a + 2] * s.omega[2];
+        cross3(s.omega, Lw, gyro);
+        for (int a = 0; a < 3; ++a) rhs[a] = c->torque[3 * b + a] - gyro[a];
+        for (int a = 0; a < 3; ++a)
+            s.omega[a] += dt * (Iwinv[3 * a] * rhs[0] + Iwinv[3 * a + 1] * rhs[1] + Iwinv[3 * a + 2] * rhs[2]);
+        for (int a = 0; a < 3; ++a) s.com[a] += dt * s.vel[a];
+        {
+            double qw = s.quat[0], qx = s.quat[1], qy = s.quat[2], qz = s.quat[3];
+            const double ox = s.omega[0], oy = s.omega[1], oz = s.omega[2];
+            const double dw = -(ox * qx + oy * qy + oz * qz);
+            const double dx = ox * qw + (oy * qz - oz * qy);
+            const double dy = oy * qw + (oz * qx - ox * qz);
+            const double dz = oz * qw + (ox * qy - oy * qx);
+            qw += 0.5 * dt * dw; qx += 0.5 * dt * dx; qy += 0.5 * dt * dy; qz += 0.5 * dt * dz;
+            const double nq = std::sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+            s.quat[0] = qw / nq; s.quat[1] = qx / nq; s.quat[2] = qy / nq; s.quat[3] = qz / nq;
+        }
+        quat_to_R(s.quat, R);
+        for (int a = 0; a < 3; ++a) {
+            double lo = 1e300, hi = -1e300;
+            for (int64_t k = 0; k < c->nb; ++k) {
+                if (body_host[k] != b) continue;
+                const double *l = &local_host[3 * k];
+                const double xa = s.com[a] + (R[3 * a] * l[0] + R[3 * a + 1] * l[1] + R[3 * a + 2] * l[2]);
+                lo = std::min(lo, xa);
+                hi = std::max(hi, xa);
+            }
+            const double wl = c->P.domain_min[a] + c->P.r, wh = c->P.domain_max[a] - c->P.r;
+            if (lo < wl) {
+                s.com[a] += wl - lo;
+                if (s.vel[a] < 0.0) s.vel[a] = 0.0;
+            } else if (hi > wh) {
+                s.com[a] -= hi - wh;
+                if (s.vel[a] > 0.0) s.vel[a] = 0.0;
+            }
+        }
+        c->rigid[b] = s;
+    }
+}
+
+// ---- the neighbour pipeline ------------------------------------------------
+int sort_fluid(sph_ctx *c) {
+    hipStream_t s = c->stream;
+    HIP_TRY(c, sph::launch_fill_u32(c->count, c->ncell, 0u, s));
+    HIP_TRY(c, sph::launch_keys_hist(c->x, c->nf, c->g, c->key, c->slot, c->count, s));
+    HIP_TRY(c, sph::launch_exclusive_scan(c->count, c->ncell, c->start_f, c->scan_part, s));
+    HIP_TRY(c, sph::launch_scatter(c->key, c->slot, c->start_f, c->nf, c->src, s));
+    HIP_TRY(c, sph::launch_cell_sort(c->start_f, c->ncell, c->src, c->id, c->flags, s));
+    HIP_TRY(c, sph::launch_gather_fluid(c->src, c->nf, c->x, c->v, c->K, c->Kv, c->id, c->x2, c->v2, c->K2, c->Kv2,
+                                        c->id2, s));
+    std::swap(c->x, c->x2);
+    std::swap(c->v, c->v2);
+    std::swap(c->K, c->K2);
+    std::swap(c->Kv, c->Kv2);
+    std::swap(c->id, c->id2);
+    return SPH_OK;
+}
+
+int sort_boundary(sph_ctx *c) {
+    hipStream_t s = c->stream;
+    HIP_TRY(c, sph::launch_fill_u32(c->count, c->ncell, 0u, s));
+    HIP_TRY(c, sph::launch_keys_hist(c->xb, c->nb, c->g, c->bkey, c->bslot, c->count, s));
+    HIP_TRY(c, sph::launch_exclusive_scan(c->count, c->ncell, c->start_b, c->scan_part, s));
+    HIP_TRY(c, sph::launch_scatter(c->bkey, c->bslot, c->start_b, c->nb, c->bsrc, s));
+    HIP_TRY(c, sph::launch_cell_sort(c->start_b, c->ncell, c->bsrc, c->bid, c->flags, s));
+    HIP_TRY(c, sph::launch_gather_boundary(c->bsrc, c->nb, c->xb, c->vb, c->bid, c->xb2, c->vb2, c->bid2, s));
+    std::swap(c->xb, c->xb2);
+    std::swap(c->vb, c->vb2);
+    std::swap(c->bid, c->bid2);
+    HIP_TRY(c, sph::launch_boundary_psi(c->xb, c->nb, c->start_b, c->g, c->kc, s));
+    return SPH_OK;
+}
+
+// algorithmic bytes of reading every neighbour-list entry once (4 B each)
+double list_bytes(const sph_ctx *c) { return 4.0 * c->nbr_sum; }
+double fluid_list_bytes(const sph_ctx *c) { return 4.0 * c->nbr_sum_f; }
+
+int build(sph_ctx *c) {
+    hipStream_t s = c->stream;
+    HIP_TRY(c, sph::launch_fill_u32(c->flags, 1, 0u, s));
+    if (c->boundary_dirty) {
+        ProfScope ps(c, "sort", 0.0);
+        int rc = sort_boundary(c);
+        if (rc) return rc;
+        c->boundary_dirty = false;
+    }
+    {
+        ProfScope ps(c, "sort", 56.0 * c->nf);
+        int rc = sort_fluid(c);
+        if (rc) return rc;
+    }
+    // neighbour statistics: min = ~0, max = sum_total = sum_fluid = 0
+    HIP_TRY(c, sph::launch_fill_u32((uint32_t *)c->nstats, 2, 0xffffffffu, s));
+    HIP_TRY(c, sph::launch_fill_u32((uint32_t *)c->nstats + 2, 6, 0u, s));
+    {
+        ProfScope ps(c, "nbr_build", 16.0 * c->nf + 8.0 * c->nf + list_bytes(c));
+        HIP_TRY(c, sph::launch_nbr_build(c->x, c->nf, c->xb, c->start_f, c->start_b, c->g, c->nlist, c->ncnt, c->capf,
+                                         c->blist, c->bcnt, c->capb, c->flags, (uint32_t *)c->nstats, s));
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->h_u32, c->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(c->h_stats, c->nstats, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->sorted_once = true;
+    if (c->h_u32[0] & 2u) {
+        c->nbr_fresh = false;
+        return fail(c, SPH_ERR_CAPACITY, "more than 4096 particles in one grid cell");
+    }
+    if (c->h_u32[0] & 1u) {
+        c->nbr_fresh = false;
+        return fail(c, SPH_ERR_CAPACITY, "neighbour list capacity exceeded (max_neighbors / max_boundary_neighbors)");
+    }
+    c->nbr_sum = (double)c->h_stats[2];
+    c->nbr_sum_f = (double)c->h_stats[3];
+    c->nbr_fresh = true;
+    return SPH_OK;
+}
+
+// read one FP64 scalar of the device scratch after the stream drains
+int read_scalar(sph_ctx *c, const double *dev, double *out) {
+    HIP_TRY(c, hipMemcpyAsync(c->h_scal, dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *out = c->h_scal[0];
+    return SPH_OK;
+}
+
+int pressure_pass(sph_ctx *c, float *Kacc, float *klast, float dt) {
+    ProfScope ps(c, "pressure_update", (48.0 + (klast ? 24.0 : 20.0)) * c->nf + list_bytes(c));
+    HIP_TRY(c, sph::launch_pressure_update(c->nf, c->x, c->v, c->kappa, Kacc, klast, c->nlist, c->ncnt, c->xb,
+                                           c->blist, c->bcnt, c->kc, dt, c->stream));
+    return SPH_OK;
+}
+
+int predict_pass(sph_ctx *c, int mode, float dt, double *err_sum) {
+    {
+        ProfScope ps(c, "predict", 56.0 * c->nf + list_bytes(c));
+        HIP_TRY(c, sph::launch_predict(mode, c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->nlist, c->ncnt, c->xb,
+                                       c->vb, c->blist, c->bcnt, c->kc, dt, c->red_part, c->counter, c->scal,
+                                       c->stream));
+    }
+    return read_scalar(c, c->scal, err_sum);
+}
+
+// One Jacobi solve (Algorithm 2): stop when err <= eta, or after max_iters,
+// or after exactly `forced` iterations when forced >= 0.
+int jacobi_solve(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, int32_t forced, double eta,
+                 int32_t *iters, double *err_out) {
+    const double N = (double)std::max<int64_t>(c->nf, 1);
+    const double scale = mode == 0 ? (double)dt / c->P.rho0 / N : 1.0 / (c->P.rho0 * N);
+    double sum = 0.0;
+    int rc = predict_pass(c, mode, dt, &sum);
+    if (rc) return rc;
+    double err = sum * scale;
+    int32_t l = 0;
+    for (;;) {
+        const bool go = forced >= 0 ? (l < forced) : (err > eta && l < c->P.max_iters);
+        if (!go) break;
+        rc = pressure_pass(c, Kacc, klast, dt);
+        if (rc) return rc;
+        ++l;
+        rc = predict_pass(c, mode, dt, &sum);
+        if (rc) return rc;
+        err = sum * scale;
+    }
+    *iters = l;
+    *err_out = err;
+    return SPH_OK;
+}
+
+// Implicit viscosity (Eqs. 16-19): CG with block-Jacobi preconditioner on
+// (I - dt A) v* = v~, x0 = v~, stop at |r| <= tol |b|.  Dot products FP64.
+int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
+    hipStream_t s = c->stream;
+    const int64_t nf = c->nf;
+    const float mu = (float)(c->P.visc * c->P.rho0);
+    HIP_TRY(c, sph::launch_gravity(nf, c->v, c->cg_b, dt, (float)c->P.gravity[0], (float)c->P.gravity[1],
+                                   (float)c->P.gravity[2], s));
+    HIP_TRY(c, hipMemcpyAsync(c->v2, c->cg_b, sizeof(float4) * nf, hipMemcpyDeviceToDevice, s));   // x0 = b
+    {
+        ProfScope ps(c, "visc", 60.0 * nf + fluid_list_bytes(c));
+        HIP_TRY(c, sph::launch_visc_precond(nf, c->x, c->rho, c->nlist, c->ncnt, c->kc, dt, mu, c->Pinv, s));
+    }
+    {
+        ProfScope ps(c, "visc", 44.0 * nf + fluid_list_bytes(c));
+        HIP_TRY(c, sph::launch_visc_matvec(nf, c->x, c->rho, c->v2, c->cg_Ap, c->nlist, c->ncnt, c->kc, dt, mu, s));
+    }
+    HIP_TRY(c, sph::launch_axpy_residual(nf, c->cg_b, c->cg_Ap, c->cg_r, s));
+    HIP_TRY(c, sph::launch_apply_precond(nf, c->Pinv, c->cg_r, c->cg_z, s));
+    HIP_TRY(c, hipMemcpyAsync(c->cg_p, c->cg_z, sizeof(float4) * nf, hipMemcpyDeviceToDevice, s));
+    double *rz = c->scal + 1, *pAp = c->scal + 2, *out2 = c->scal + 3, *bb = c->scal + 5;
+    // out2[0] = rz_new, out2[1] = rr
+    HIP_TRY(c, sph::launch_dot(nf, c->cg_r, c->cg_z, c->red_part, c->counter, rz, s));
+    HIP_TRY(c, sph::launch_dot(nf, c->cg_b, c->cg_b, c->red_part, c->counter, bb, s));
+    HIP_TRY(c, sph::launch_dot(nf, c->cg_r, c->cg_r, c->red_part, c->counter, out2 + 1, s));
+    HIP_TRY(c, hipMemcpyAsync(c->h_scal, c->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    const double bnorm = std::sqrt(c->h_scal[5]);
+    double rnorm = std::sqrt(c->h_scal[4]);
+    int32_t it = 0;
+    while (rnorm > c->P.cg_tol * bnorm && it < c->P.cg_max_iters) {
+        {
+            ProfScope ps(c, "visc", 44.0 * nf + fluid_list_bytes(c));
+            HIP_TRY(c, sph::launch_visc_matvec(nf, c->x, c->rho, c->cg_p, c->cg_Ap, c->nlist, c->ncnt, c->kc, dt, mu, s));
+        }
+        HIP_TRY(c, sph::launch_dot(nf, c->cg_p, c->cg_Ap, c->red_part, c->counter, pAp, s));
+        HIP_TRY(c, sph::launch_cg_update(nf, c->v2, c->cg_r, c->cg_z, c->cg_p, c->cg_Ap, c->Pinv, rz, pAp,
+                                         c->red_part, c->counter, out2, s));
+        HIP_TRY(c, sph::launch_cg_direction(nf, c->cg_p, c->cg_z, out2, rz, s));
+        HIP_TRY(c, hipMemcpyAsync(rz, out2, sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(c, hipMemcpyAsync(c->h_scal, out2 + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        rnorm = std::sqrt(c->h_scal[0]);
+        ++it;
+    }
+    *iters = it;
+    *resid = bnorm > 0 ? rnorm / bnorm : rnorm;
+    std::swap(c->v, c->v2);
+    return SPH_OK;
+}
+
+int step_impl(sph_ctx *c, sph_step_stats *st) {
+    hipStream_t s = c->stream;
+    if (!c->nbr_fresh) {
+        if (!c->P.auto_rebuild) return fail(c, SPH_ERR_STATE, "sph_step needs fresh neighbours (sph_build_neighbors)");
+        int rc = build(c);
+        if (rc) return rc;
+    }
+    const int64_t nf = c->nf;
+    // 1. time step (fixed, or CFL from the step's input velocities)
+    float dt;
+    if (c->P.cfl_lambda > 0.0) {
+        HIP_TRY(c, sph::launch_fill_u32(c->vmax_bits, 1, 0u, s));
+        HIP_TRY(c, sph::launch_max_v2(c->v, nf, c->vmax_bits, s));
+        HIP_TRY(c, hipMemcpyAsync(c->h_u32, c->vmax_bits, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        float vmax2;
+        std::memcpy(&vmax2, c->h_u32, sizeof(float));
+        double d = c->P.dt_max;
+        if (vmax2 > 0.0f) {
+            const double cfl = c->P.cfl_lambda * (2.0 * c->P.r) / std::sqrt((double)vmax2);
+            if (cfl < d) d = cfl;
+        }
+        dt = (float)d;
+    } else {
+        dt = (float)c->P.dt_max;
+    }
+    const bool warm = c->P.warm_start != SPH_WARM_ZERO;
+    const float wf = warm ? (float)c->P.warm_factor : 0.0f;
+
+    // 2. density, alpha; divergence warm-start set-up
+    {
+        ProfScope ps(c, "density_alpha", 80.0 * nf + list_bytes(c));
+        HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, c->nlist, c->ncnt, c->xb, c->blist, c->bcnt, c->kc,
+                                             c->rho, c->alpha, c->v_in, c->Kv, c->kappa, wf, s));
+    }
+    // 3. divergence-free solve
+    if (warm) {
+        int rc = pressure_pass(c, c->Kv, nullptr, dt);
+        if (rc) return rc;
+    }
+    int32_t iv = 0, id = 0;
+    double ev = 0.0, ed = 0.0;
+    int rc = jacobi_solve(c, 0, dt, c->Kv, nullptr, c->forced_div, c->P.eta_divergence, &iv, &ev);
+    if (rc) return rc;
+
+    // 4. non-pressure accelerations; density warm-start set-up
+    int32_t cg_it = 0;
+    double cg_res = 0.0;
+    const float gx = (float)c->P.gravity[0], gy = (float)c->P.gravity[1], gz = (float)c->P.gravity[2];
+    if (c->P.visc_model == SPH_VISC_IMPLICIT) {
+        rc = implicit_viscosity(c, dt, &cg_it, &cg_res);
+        if (rc) return rc;
+        HIP_TRY(c, sph::launch_warm_setup(nf, c->x, c->rho, c->K, c->kappa, wf, s));
+    } else {
+        ProfScope ps(c, "xsph", 72.0 * nf + fluid_list_bytes(c));
+        HIP_TRY(c, sph::launch_nonpressure(c->P.visc_model, nf, c->x, c->v, c->v2, c->rho, c->nlist, c->ncnt, c->kc,
+                                           dt, gx, gy, gz, (float)c->P.visc, c->K, c->kappa, wf, s));
+        std::swap(c->v, c->v2);
+    }
+    // 5. warm start of the density solve
+    if (warm) {
+        rc = pressure_pass(c, c->K, nullptr, dt);
+        if (rc) return rc;
+    }
+    HIP_TRY(c, sph::launch_fill_f32(c->kappa_last, nf, 0.0f, s));
+    // 6. constant-density solve
+    rc = jacobi_solve(c, 1, dt, c->K, c->kappa_last, c->forced_dens, c->P.eta_density, &id, &ed);
+    if (rc) return rc;
+
+    // 7. rigid bodies: Eq. 14 reaction, FP64 Newton-Euler, new boundary pose
+    if (c->nr > 0) {
+        HIP_TRY(c, sph::launch_rigid_force(nf, c->x, c->rho, c->K, c->Kv, c->blist, c->bcnt, c->xb, c->vb, c->kc,
+                                           c->nr, c->com_dev, c->red_part, c->counter, c->rigid_out, s));
+        std::vector<double> fo(6 * c->nr);
+        HIP_TRY(c, hipMemcpyAsync(fo.data(), c->rigid_out, sizeof(double) * 6 * c->nr, hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        for (int b = 0; b < c->nr; ++b)
+            for (int a = 0; a < 3; ++a) {
+                c->force[3 * b + a] = fo[6 * b + a];
+                c->torque[3 * b + a] = fo[6 * b + 3 + a];
+            }
+        rigid_integrate(c, (double)dt, c->local_host, c->body_host);
+        rc = upload_poses(c);
+        if (rc) return rc;
+        HIP_TRY(c, sph::launch_rigid_boundary(c->nb, c->xb, c->vb, c->bid, c->blocal, c->poses, s));
+        c->boundary_dirty = true;
+    }
+    // 8. symplectic Euler: v = v*, x += dt v
+    {
+        ProfScope ps(c, "integrate", 44.0 * nf);
+        HIP_TRY(c, sph::launch_integrate(nf, c->x, c->v, dt, s));
+    }
+    c->nbr_fresh = false;
+    c->last_dt = dt;
+    c->step_index += 1;
+    if (st) {
+        st->dt = dt;
+        st->iters_div = iv;
+        st->iters_dens = id;
+        st->err_div = ev;
+        st->err_dens = ed;
+        st->converged_div = ev <= c->P.eta_divergence;
+        st->converged_dens = ed <= c->P.eta_density;
+        st->cg_iters = cg_it;
+        st->cg_resid = cg_res;
+        st->nbr_min = (int32_t)(c->h_stats[0] == ~0ull ? 0 : c->h_stats[0]);
+        st->nbr_max = (int32_t)c->h_stats[1];
+        st->nbr_mean = c->nf ? (double)c->h_stats[2] / (double)c->nf : 0.0;
+        st->warm_fallback = 0;
+        st->step_index = c->step_index;
+    }
+    if (!std::isfinite(ed) || !std::isfinite(ev)) return fail(c, SPH_ERR_NUMERIC, "non-finite solver error");
+    return SPH_OK;
+}
+
+bool finite3(const float *p, int64_t n) {
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+namespace {
+template <typename T>
+int d2h(sph_ctx *c, std::vector<T> &h, const T *d, int64_t n) {
+    h.resize(std::max<int64_t>(n, 1));
+    HIP_TRY(c, hipMemcpyAsync(h.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost, c->stream));
+    return SPH_OK;
+}
+}  // namespace
+
+// ============================================================================ ABI
+extern "C" {
+
+const char *sph_strerror(int status) {
+    switch (status) {
+        case SPH_OK: return "ok";
+        case SPH_ERR_INVALID: return "invalid argument";
+        case SPH_ERR_OOM: return "out of memory";
+        case SPH_ERR_DEVICE: return "HIP error";
+        case SPH_ERR_CAPACITY: return "neighbour capacity exceeded";
+        case SPH_ERR_STATE: return "call out of order";
+        case SPH_ERR_NUMERIC: return "non-finite state";
+        default: return "unknown status";
+    }
+}
+
+const char *sph_last_error(const sph_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_ctx **out) {
+    g_create_error.clear();
+    if (!out) return fail(nullptr, SPH_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!p || !sc) return fail(nullptr, SPH_ERR_INVALID, "params or scene is NULL");
+    if (!(p->r > 0) || !(p->h > 0) || !(p->rho0 > 0) || !(p->dt_max > 0) || p->max_iters < 0 ||
+        p->max_neighbors <= 0 || p->max_boundary_neighbors <= 0 || p->cfl_lambda < 0 || p->warm_factor < 0 ||
+        p->visc_model < 0 || p->visc_model > 3 || p->warm_start < 0 || p->warm_start > 2 || p->cg_max_iters < 0)
+        return fail(nullptr, SPH_ERR_INVALID, "invalid parameter value");
+    for (int a = 0; a < 3; ++a)
+        if (!(p->domain_max[a] > p->domain_min[a])) return fail(nullptr, SPH_ERR_INVALID, "empty domain");
+    if (sc->n_fluid < 0 || sc->n_boundary < 0 || sc->n_rigid < 0 || sc->n_rigid > sph::kMaxBodies)
+        return fail(nullptr, SPH_ERR_INVALID, "invalid scene sizes (at most 16 rigid bodies)");
+    if ((sc->n_fluid > 0 && !sc->x_fluid) || (sc->n_boundary > 0 && !sc->x_boundary) ||
+        (sc->n_rigid > 0 && (!sc->rigid || !sc->body_of_boundary)))
+        return fail(nullptr, SPH_ERR_INVALID, "missing scene array");
+    if (sc->n_fluid >= (int64_t)0x7fffffff || sc->n_boundary >= (int64_t)0x7fffffff)
+        return fail(nullptr, SPH_ERR_INVALID, "too many particles for 32-bit indices");
+    if (sc->n_fluid > 0 && !finite3(sc->x_fluid, sc->n_fluid))
+        return fail(nullptr, SPH_ERR_INVALID, "non-finite fluid position");
+    if (sc->body_of_boundary)
+        for (int64_t k = 0; k < sc->n_boundary; ++k)
+            if (sc->body_of_boundary[k] < -1 || sc->body_of_boundary[k] >= sc->n_rigid)
+                return fail(nullptr, SPH_ERR_INVALID, "body_of_boundary out of range");
+    for (int b = 0; b < sc->n_rigid; ++b)
+        if (!(sc->rigid[b].mass > 0) || !(sc->rigid[b].inertia[0] > 0) || !(sc->rigid[b].inertia[1] > 0) ||
+            !(sc->rigid[b].inertia[2] > 0))
+            return fail(nullptr, SPH_ERR_INVALID, "rigid body mass and inertia must be positive");
+
+    sph_ctx *c = new (std::nothrow) sph_ctx();
+    if (!c) return fail(nullptr, SPH_ERR_OOM, "host allocation failed");
+    c->P = *p;
+    c->stream = (hipStream_t)hip_stream;
+    c->nf = sc->n_fluid;
+    c->nb = sc->n_boundary;
+    c->nr = sc->n_rigid;
+    c->capf = p->max_neighbors;
+    c->capb = p->max_boundary_neighbors;
+    (void)hipGetDevice(&c->device);
+
+    // grid: cell fl32(h (1 + 2^-10)), inv fl32(1/cell), origin fl32(min - cell)
+    c->cell = (float)(p->h * (1.0 + 1.0 / 1024.0));
+    c->g.inv = 1.0f / c->cell;
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        c->g.o[a] = (float)(p->domain_min[a] - (double)c->cell);
+        c->g.n[a] = (int32_t)std::ceil((p->domain_max[a] - p->domain_min[a]) / (double)c->cell) + 2;
+        ncell *= c->g.n[a];
+    }
+    const float hf = (float)p->h;
+    c->g.h2 = hf * hf;
+    c->ncell = ncell;
+    if (ncell > 16LL * 1024 * 1024) {
+        delete c;
+        return fail(nullptr, SPH_ERR_INVALID, "grid larger than 16.7M cells");
+    }
+    // kernel constants
+    const double kk = 8.0 / (M_PI * p->h * p->h * p->h);
+    c->kc.h = (float)p->h;
+    c->kc.inv_h = (float)(1.0 / p->h);
+    c->kc.k = (float)kk;
+    c->kc.kg = (float)(6.0 * kk / p->h);
+    c->kc.m = (float)(p->rho0 * 8.0 * p->r * p->r * p->r);
+    c->kc.rho0 = (float)p->rho0;
+
+    const int64_t nf = c->nf, nb = c->nb;
+    const int64_t tiles = (ncell + 4095) / 4096;
+    const int64_t nred = std::max<int64_t>(sph::reduction_blocks(std::max(nf, nb)), 8);
+    int rc = SPH_OK;
+#define ALLOC(ptr, n)                       \
+    if ((rc = dev_alloc(c, &(ptr), (n)))) { \
+        std::string m_ = c->err;            \
+        free_all(c);                        \
+        delete c;                           \
+        return fail(nullptr, rc, m_);       \
+    }
+    ALLOC(c->x, nf); ALLOC(c->x2, nf); ALLOC(c->v, nf); ALLOC(c->v2, nf); ALLOC(c->v_in, nf);
+    ALLOC(c->rho, nf); ALLOC(c->alpha, nf); ALLOC(c->K, nf); ALLOC(c->K2, nf); ALLOC(c->Kv, nf); ALLOC(c->Kv2, nf);
+    ALLOC(c->kappa, nf); ALLOC(c->kappa_last, nf); ALLOC(c->id, nf); ALLOC(c->id2, nf);
+    ALLOC(c->key, nf); ALLOC(c->slot, nf); ALLOC(c->src, nf);
+    ALLOC(c->count, ncell); ALLOC(c->start_f, ncell + 1); ALLOC(c->start_b, ncell + 1); ALLOC(c->scan_part, 2 * tiles + 8);
+    ALLOC(c->nlist, (int64_t)c->capf * nf); ALLOC(c->ncnt, nf);
+    ALLOC(c->blist, (int64_t)c->capb * nf); ALLOC(c->bcnt, nf);
+    ALLOC(c->xb, nb); ALLOC(c->xb2, nb); ALLOC(c->vb, nb); ALLOC(c->vb2, nb); ALLOC(c->bid, nb); ALLOC(c->bid2, nb);
+    ALLOC(c->bkey, nb); ALLOC(c->bslot, nb); ALLOC(c->bsrc, nb); ALLOC(c->blocal, 3 * nb);
+    ALLOC(c->poses, std::max(1, c->nr)); ALLOC(c->com_dev, 3 * std::max(1, c->nr));
+    ALLOC(c->red_part, nred * 6 * std::max(1, c->nr) + 16); ALLOC(c->scal, 16); ALLOC(c->rigid_out, 6 * std::max(1, c->nr));
+    ALLOC(c->counter, 4); ALLOC(c->flags, 4); ALLOC(c->vmax_bits, 4); ALLOC(c->nstats, 4);
+    if (p->visc_model == SPH_VISC_IMPLICIT) {
+        ALLOC(c->Pinv, 9 * nf); ALLOC(c->cg_b, nf); ALLOC(c->cg_r, nf); ALLOC(c->cg_z, nf); ALLOC(c->cg_p, nf);
+        ALLOC(c->cg_Ap, nf);
+    }
+#undef ALLOC
+    if (hipHostMalloc((void **)&c->h_scal, 16 * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_u32, 16 * sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_stats, 4 * sizeof(unsigned long long)) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return fail(nullptr, SPH_ERR_OOM, "pinned host allocation failed");
+    }
+    // upload the scene (original order; the first build sorts it)
+    {
+        std::vector<float4> hx(std::max<int64_t>(nf, 1)), hv(std::max<int64_t>(nf, 1));
+        std::vector<int32_t> hid(std::max<int64_t>(nf, 1));
+        for (int64_t i = 0; i < nf; ++i) {
+            hx[i] = make_float4(sc->x_fluid[3 * i], sc->x_fluid[3 * i + 1], sc->x_fluid[3 * i + 2], 0.f);
+            hv[i] = sc->v_fluid ? make_float4(sc->v_fluid[3 * i], sc->v_fluid[3 * i + 1], sc->v_fluid[3 * i + 2], 0.f)
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+            hid[i] = (int32_t)i;
+        }
+        std::vector<float> zero(std::max<int64_t>(nf, 1), 0.0f);
+        hipStream_t s = c->stream;
+        bool ok = hipMemcpyAsync(c->x, hx.data(), sizeof(float4) * nf, hipMemcpyHostToDevice, s) == hipSuccess &&
+                  hipMemcpyAsync(c->v, hv.data(), sizeof(float4) * nf, hipMemcpyHostToDevice, s) == hipSuccess &&
+                  hipMemcpyAsync(c->id, hid.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, s) == hipSuccess &&
+                  hipMemcpyAsync(c->K, zero.data(), sizeof(float) * nf, hipMemcpyHostToDevice, s) == hipSuccess &&
+                  hipMemcpyAsync(c->Kv, zero.data(), sizeof(float) * nf, hipMemcpyHostToDevice, s) == hipSuccess;
+        // boundary: positions, velocities from the body state, body ids, local offsets
+        c->rigid.assign(sc->rigid, sc->rigid + c->nr);
+        c->force.assign(3 * std::max(1, c->nr), 0.0);
+        c->torque.assign(3 * std::max(1, c->nr), 0.0);
+        c->local_host.assign(3 * std::max<int64_t>(nb, 1), 0.0);
+        c->body_host.assign(std::max<int64_t>(nb, 1), -1);
+        std::vector<double> &local = c->local_host;
+        std::vector<float4> hxb(std::max<int64_t>(nb, 1)), hvb(std::max<int64_t>(nb, 1));
+        std::vector<int32_t> hbid(std::max<int64_t>(nb, 1));
+        for (int64_t k = 0; k < nb; ++k) {
+            const int32_t b = sc->body_of_boundary ? sc->body_of_boundary[k] : -1;
+            c->body_host[k] = b;
+            hxb[k] = make_float4(sc->x_boundary[3 * k], sc->x_boundary[3 * k + 1], sc->x_boundary[3 * k + 2], 0.f);
+            hvb[k] = make_float4(0.f, 0.f, 0.f, (float)b);
+            hbid[k] = (int32_t)k;
+            if (b >= 0) {
+                const sph_rigid_desc &s = c->rigid[b];
+                double R[9], d[3], rr[3], wx[3];
+                quat_to_R(s.quat, R);
+                for (int a = 0; a < 3; ++a) d[a] = (double)sc->x_boundary[3 * k + a] - s.com[a];
+                for (int a = 0; a < 3; ++a) local[3 * k + a] = R[a] * d[0] + R[3 + a] * d[1] + R[6 + a] * d[2];
+                for (int a = 0; a < 3; ++a) rr[a] = (double)sc->x_boundary[3 * k + a] - s.com[a];
+                cross3(s.omega, rr, wx);
+                hvb[k].x = (float)(s.vel[0] + wx[0]);
+                hvb[k].y = (float)(s.vel[1] + wx[1]);
+                hvb[k].z = (float)(s.vel[2] + wx[2]);
+            }
+        }
+        ok = ok && hipMemcpyAsync(c->xb, hxb.data(), sizeof(float4) * nb, hipMemcpyHostToDevice, s) == hipSuccess &&
+             hipMemcpyAsync(c->vb, hvb.data(), sizeof(float4) * nb, hipMemcpyHostToDevice, s) == hipSuccess &&
+             hipMemcpyAsync(c->bid, hbid.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s) == hipSuccess &&
+             hipMemcpyAsync(c->blocal, local.data(), sizeof(double) * 3 * nb, hipMemcpyHostToDevice, s) == hipSuccess;
+        ok = ok && sph::launch_fill_u32(c->counter, 4, 0u, s) == hipSuccess &&
+             hipStreamSynchronize(s) == hipSuccess;
+        if (!ok) {
+            free_all(c);
+            delete c;
+            return fail(nullptr, SPH_ERR_DEVICE, "scene upload failed");
+        }
+    }
+    if (upload_poses(c) != SPH_OK) {
+        std::string m = c->err;
+        free_all(c);
+        delete c;
+        return fail(nullptr, SPH_ERR_DEVICE, m);
+    }
+    *out = c;
+    return SPH_OK;
+}
+
+void sph_destroy(sph_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+int sph_build_neighbors(sph_ctx *c) {
+    if (!c) return SPH_ERR_INVALID;
+    c->err.clear();
+    return build(c);
+}
+
+int sph_step(sph_ctx *c, sph_step_stats *st) {
+    if (!c) return SPH_ERR_INVALID;
+    c->err.clear();
+    return step_impl(c, st);
+}
+
+int sph_get_info(const sph_ctx *c, sph_info *info) {
+    if (!c || !info) return SPH_ERR_INVALID;
+    info->n_fluid = c->nf;
+    info->n_boundary = c->nb;
+    info->n_rigid = c->nr;
+    for (int a = 0; a < 3; ++a) {
+        info->grid_n[a] = c->g.n[a];
+        info->origin[a] = c->g.o[a];
+    }
+    info->cell = c->cell;
+    info->inv_cell = c->g.inv;
+    info->h2 = c->g.h2;
+    info->max_neighbors = c->capf;
+    info->max_boundary_neighbors = c->capb;
+    info->device_bytes = c->dev_bytes;
+    return SPH_OK;
+}
+
+
+int sph_read_state(sph_ctx *c, uint32_t mask, const sph_host_view *dst) {
+    if (!c || !dst) return SPH_ERR_INVALID;
+    c->err.clear();
+    const int64_t nf = c->nf, nb = c->nb;
+    std::vector<int32_t> id;
+    std::vector<float4> x4, v4, vin4;
+    std::vector<float> f1;
+    int rc = d2h(c, id, c->id, nf);
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    auto scatter3 = [&](const std::vector<float4> &src, float *out) {
+        for (int64_t s = 0; s < nf; ++s) {
+            const int64_t i = id[s];
+            out[3 * i] = src[s].x;
+            out[3 * i + 1] = src[s].y;
+            out[3 * i + 2] = src[s].z;
+        }
+    };
+    auto read1 = [&](const float *d, float *out) -> int {
+        int r = d2h(c, f1, d, nf);
+        if (r) return r;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (int64_t s = 0; s < nf; ++s) out[id[s]] = f1[s];
+        return SPH_OK;
+    };
+    if ((mask & SPH_FIELD_X) && dst->x) {
+        if ((rc = d2h(c, x4, c->x, nf))) return rc;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        scatter3(x4, dst->x);
+    }
+    if ((mask & (SPH_FIELD_V | SPH_FIELD_ACCEL)) && (dst->v || dst->accel)) {
+        if ((rc = d2h(c, v4, c->v, nf))) return rc;
+        if ((rc = d2h(c, vin4, c->v_in, nf))) return rc;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if ((mask & SPH_FIELD_V) && dst->v) scatter3(v4, dst->v);
+        if ((mask & SPH_FIELD_ACCEL) && dst->accel) {
+            const float idt = c->last_dt > 0 ? 1.0f / c->last_dt : 0.0f;
+            for (int64_t s = 0; s < nf; ++s) {
+                const int64_t i = id[s];
+                dst->accel[3 * i] = (v4[s].x - vin4[s].x) * idt;
+                dst->accel[3 * i + 1] = (v4[s].y - vin4[s].y) * idt;
+                dst->accel[3 * i + 2] = (v4[s].z - vin4[s].z) * idt;
+            }
+        }
+    }
+    if ((mask & SPH_FIELD_RHO) && dst->rho && (rc = read1(c->rho, dst->rho))) return rc;
+    if ((mask & SPH_FIELD_ALPHA) && dst->alpha && (rc = read1(c->alpha, dst->alpha))) return rc;
+    if ((mask & SPH_FIELD_K) && dst->K && (rc = read1(c->K, dst->K))) return rc;
+    if ((mask & SPH_FIELD_KV) && dst->Kv && (rc = read1(c->Kv, dst->Kv))) return rc;
+    if ((mask & SPH_FIELD_KAPPA) && dst->kappa && (rc = read1(c->kappa_last, dst->kappa))) return rc;
+    if ((mask & SPH_FIELD_NBR) && (dst->n_fluid_nbrs || dst->n_boundary_nbrs)) {
+        std::vector<uint32_t> a, b;
+        if ((rc = d2h(c, a, c->ncnt, nf))) return rc;
+        if ((rc = d2h(c, b, c->bcnt, nf))) return rc;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (int64_t s = 0; s < nf; ++s) {
+            if (dst->n_fluid_nbrs) dst->n_fluid_nbrs[id[s]] = (int32_t)a[s];
+            if (dst->n_boundary_nbrs) dst->n_boundary_nbrs[id[s]] = (int32_t)b[s];
+        }
+    }
+    if ((mask & (SPH_FIELD_PSI | SPH_FIELD_BOUNDARY)) && (dst->psi || dst->x_boundary || dst->v_boundary)) {
+        std::vector<float4> xb4, vb4;
+        std::vector<int32_t> bid;
+        if ((rc = d2h(c, xb4, c->xb, nb))) return rc;
+        if ((rc = d2h(c, vb4, c->vb, nb))) return rc;
+        if ((rc = d2h(c, bid, c->bid, nb))) return rc;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (int64_t s = 0; s < nb; ++s) {
+            const int64_t k = bid[s];
+            if ((mask & SPH_FIELD_PSI) && dst->psi) dst->psi[k] = xb4[s].w;
+            if ((mask & SPH_FIELD_BOUNDARY) && dst->x_boundary) {
+                dst->x_boundary[3 * k] = xb4[s].x;
+                dst->x_boundary[3 * k + 1] = xb4[s].y;
+                dst->x_boundary[3 * k + 2] = xb4[s].z;
+            }
+            if ((mask & SPH_FIELD_BOUNDARY) && dst->v_boundary) {
+                dst->v_boundary[3 * k] = vb4[s].x;
+                dst->v_boundary[3 * k + 1] = vb4[s].y;
+                dst->v_boundary[3 * k + 2] = vb4[s].z;
+            }
+        }
+    }
+    if (mask & SPH_FIELD_RIGID) {
+        for (int b = 0; b < c->nr; ++b) {
+            if (dst->rigid) dst->rigid[b] = c->rigid[b];
+            for (int a = 0; a < 3; ++a) {
+                if (dst->rigid_force) dst->rigid_force[3 * b + a] = c->force[3 * b + a];
+                if (dst->rigid_torque) dst->rigid_torque[3 * b + a] = c->torque[3 * b + a];
+            }
+        }
+    }
+    return SPH_OK;
+}
+
+int sph_write_state(sph_ctx *c, uint32_t mask, const sph_host_view *src) {
+    if (!c || !src) return SPH_ERR_INVALID;
+    c->err.clear();
+    const int64_t nf = c->nf, nb = c->nb;
+    std::vector<int32_t> id;
+    int rc = d2h(c, id, c->id, nf);
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    auto write3 = [&](const float *in, float4 *d, bool keep_w) -> int {
+        std::vector<float4> h(std::max<int64_t>(nf, 1));
+        if (keep_w) {
+            HIP_TRY(c, hipMemcpyAsync(h.data(), d, sizeof(float4) * nf, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+        }
+        for (int64_t s = 0; s < nf; ++s) {
+            const int64_t i = id[s];
+            h[s].x = in[3 * i];
+            h[s].y = in[3 * i + 1];
+            h[s].z = in[3 * i + 2];
+            if (!keep_w) h[s].w = 0.f;
+        }
+        HIP_TRY(c, hipMemcpyAsync(d, h.data(), sizeof(float4) * nf, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        return SPH_OK;
+    };
+    auto write1 = [&](const float *in, float *d) -> int {
+        std::vector<float> h(std::max<int64_t>(nf, 1));
+        for (int64_t s = 0; s < nf; ++s) h[s] = in[id[s]];
+        HIP_TRY(c, hipMemcpyAsync(d, h.data(), sizeof(float) * nf, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        return SPH_OK;
+    };
+    if ((mask & SPH_FIELD_X) && src->x) {
+        if (!finite3(src->x, nf)) return fail(c, SPH_ERR_INVALID, "non-finite position");
+        if ((rc = write3(src->x, c->x, false))) return rc;
+    }
+    if ((mask & SPH_FIELD_V) && src->v && (rc = write3(src->v, c->v, false))) return rc;
+    if ((mask & SPH_FIELD_K) && src->K && (rc = write1(src->K, c->K))) return rc;
+    if ((mask & SPH_FIELD_KV) && src->Kv && (rc = write1(src->Kv, c->Kv))) return rc;
+    if ((mask & SPH_FIELD_RIGID) && src->rigid) {
+        for (int b = 0; b < c->nr; ++b) c->rigid[b] = src->rigid[b];
+        if ((rc = upload_poses(c))) return rc;
+    }
+    if ((mask & SPH_FIELD_BOUNDARY) && (src->x_boundary || src->v_boundary)) {
+        std::vector<float4> xb4, vb4;
+        std::vector<int32_t> bid;
+        if ((rc = d2h(c, xb4, c->xb, nb))) return rc;
+        if ((rc = d2h(c, vb4, c->vb, nb))) return rc;
+        if ((rc = d2h(c, bid, c->bid, nb))) return rc;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (int64_t s = 0; s < nb; ++s) {
+            const int64_t k = bid[s];
+            if (src->x_boundary) {
+                xb4[s].x = src->x_boundary[3 * k];
+                xb4[s].y = src->x_boundary[3 * k + 1];
+                xb4[s].z = src->x_boundary[3 * k + 2];
+            }
+            if (src->v_boundary) {
+                vb4[s].x = src->v_boundary[3 * k];
+                vb4[s].y = src->v_boundary[3 * k + 1];
+                vb4[s].z = src->v_boundary[3 * k + 2];
+            }
+        }
+        HIP_TRY(c, hipMemcpyAsync(c->xb, xb4.data(), sizeof(float4) * nb, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->vb, vb4.data(), sizeof(float4) * nb, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        c->boundary_dirty = true;
+    }
+    c->nbr_fresh = false;
+    return SPH_OK;
+}
+
+int sph_read_neighbors(sph_ctx *c, const sph_nbr_view *d) {
+    if (!c || !d) return SPH_ERR_INVALID;
+    c->err.clear();
+    if (!c->nbr_fresh) return fail(c, SPH_ERR_STATE, "no fresh neighbour lists");
+    const int64_t nf = c->nf, nb = c->nb;
+    std::vector<uint32_t> key, src, start, cnt, bcnt, lists, bkey, bsrc;
+    std::vector<int32_t> id, bid;
+    int rc;
+    if ((rc = d2h(c, key, c->key, nf)) || (rc = d2h(c, src, c->src, nf)) || (rc = d2h(c, id, c->id, nf)) ||
+        (rc = d2h(c, cnt, c->ncnt, nf)) || (rc = d2h(c, bcnt, c->bcnt, nf)) ||
+        (rc = d2h(c, bkey, c->bkey, nb)) || (rc = d2h(c, bsrc, c->bsrc, nb)) || (rc = d2h(c, bid, c->bid, nb)))
+        return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (d->keys_f)
+        for (int64_t s = 0; s < nf; ++s) d->keys_f[s] = key[src[s]];
+    if (d->perm_f)
+        for (int64_t s = 0; s < nf; ++s) d->perm_f[s] = (uint32_t)id[s];
+    if (d->keys_b)
+        for (int64_t s = 0; s < nb; ++s) d->keys_b[s] = bkey[bsrc[s]];
+    if (d->perm_b)
+        for (int64_t s = 0; s < nb; ++s) d->perm_b[s] = (uint32_t)bid[s];
+    if (d->start_f)
+        HIP_TRY(c, hipMemcpyAsync(d->start_f, c->start_f, sizeof(uint32_t) * (c->ncell + 1), hipMemcpyDeviceToHost, c->stream));
+    if (d->start_b)
+        HIP_TRY(c, hipMemcpyAsync(d->start_b, c->start_b, sizeof(uint32_t) * (c->ncell + 1), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    auto csr = [&](const uint32_t *dev, int32_t cap, const std::vector<uint32_t> &n, uint32_t *counts, uint32_t *out,
+                   int64_t outcap) -> int {
+        int64_t tot = 0;
+        for (int64_t s = 0; s < nf; ++s) tot += std::min<uint32_t>(n[s], (uint32_t)cap);
+        if (counts)
+            for (int64_t s = 0; s < nf; ++s) counts[s] = n[s];
+        if (!out) return SPH_OK;
+        if (tot > outcap) return fail(c, SPH_ERR_CAPACITY, "CSR capacity too small");
+        std::vector<uint32_t> L((size_t)std::max<int64_t>((int64_t)cap * nf, 1));
+        HIP_TRY(c, hipMemcpyAsync(L.data(), dev, sizeof(uint32_t) * (size_t)cap * nf, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        int64_t o = 0;
+        for (int64_t s = 0; s < nf; ++s)
+            for (uint32_t k = 0; k < std::min<uint32_t>(n[s], (uint32_t)cap); ++k) out[o++] = L[(size_t)k * nf + s];
+        return SPH_OK;
+    };
+    if ((rc = csr(c->nlist, c->capf, cnt, d->counts_f, d->lists_f, d->cap_f))) return rc;
+    if ((rc = csr(c->blist, c->capb, bcnt, d->counts_b, d->lists_b, d->cap_b))) return rc;
+    return SPH_OK;
+}
+
+int sph_set_forced_iters(sph_ctx *c, int32_t div, int32_t dens) {
+    if (!c) return SPH_ERR_INVALID;
+    c->forced_div = div;
+    c->forced_dens = dens;
+    return SPH_OK;
+}
+
+int sph_profile_enable(sph_ctx *c, int32_t enable) {
+    if (!c) return SPH_ERR_INVALID;
+    prof_resolve(c);
+    c->prof = enable != 0;
+    if (enable) c->prof_total.clear();
+    return SPH_OK;
+}
+
+int sph_profile_read(sph_ctx *c, const char *kernel, int64_t *launches, double *total_ms, double *bytes) {
+    if (!c || !kernel) return SPH_ERR_INVALID;
+    prof_resolve(c);
+    auto it = c->prof_total.find(kernel);
+    const ProfTotal t = it == c->prof_total.end() ? ProfTotal{} : it->second;
+    if (launches) *launches = t.launches;
+    if (total_ms) *total_ms = t.ms;
+    if (bytes) *bytes = t.bytes;
+    return SPH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// sph_internal.h -- shared definitions of the HIP kernels and the host
+// runtime of libsph.so (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sph {
+
+constexpr int kBlock = 256;   // threads per workgroup of the per-particle kernels
+constexpr int kMaxBodies = 16;
+
+// Uniform grid of the neighbour search (Sec. 5.6 prefix-sum grid).
+struct Grid {
+    float o[3];      // origin fl32(domain_min - cell)
+    float inv;       // fl32(1 / cell)
+    int32_t n[3];    // cells per axis
+    float h2;        // neighbour predicate d^2 < h2
+};
+
+// Constants of the cubic spline with support h (Sec. 3.2) and the fluid mass.
+struct Kern {
+    float h, inv_h;
+    float k;         // 8 / (pi h^3): W = k f(q)
+    float kg;        // 6 k / h: dW/dr = kg f'(q) / 6 with f' the polynomial slope
+    float m;         // fluid particle mass rho0 (2r)^3
+    float rho0;
+};
+
+// Pose of one rigid body for the boundary update (FP64).
+struct BodyPose {
+    double com[3];
+    double R[9];
+    double vel[3];
+    double omega[3];
+};
+
+// ---------------------------------------------------------------- launchers
+// Every launcher queues on `s` and returns hipGetLastError().
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+
+// counting sort by (cell key, id)
+hipError_t launch_keys_hist(const float4* x, int64_t n, Grid g, uint32_t* key, uint32_t* slot,
+                            uint32_t* count, hipStream_t s);
+hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* partials,
+                                 hipStream_t s);   // out[0..n], out[n] = total
+hipError_t launch_scatter(const uint32_t* key, const uint32_t* slot, const uint32_t* start, int64_t n,
+                          uint32_t* src, hipStream_t s);
+hipError_t launch_cell_sort(const uint32_t* start, int64_t ncell, uint32_t* src, const int32_t* id,
+                            uint32_t* flags, hipStream_t s);
+hipError_t launch_gather_fluid(const uint32_t* src, int64_t n, const float4* x, const float4* v, const float* K,
+                               const float* Kv, const int32_t* id, float4* xo, float4* vo, float* Ko, float* Kvo,
+                               int32_t* ido, hipStream_t s);
+hipError_t launch_gather_boundary(const uint32_t* src, int64_t n, const float4* x, const float4* v,
+                                  const int32_t* id, float4* xo, float4* vo, int32_t* ido, hipStream_t s);
+
+// neighbour lists, neighbour-major [cap][n]
+hipError_t launch_nbr_build(const float4* x, int64_t nf, const float4* xb, const uint32_t* start_f,
+                            const uint32_t* start_b, Grid g, uint32_t* nlist, uint32_t* ncnt, int32_t capf,
+                            uint32_t* blist, uint32_t* bcnt, int32_t capb, uint32_t* flags, uint32_t* stats,
+                            hipStream_t s);
+hipError_t launch_boundary_psi(float4* xb, int64_t nb, const uint32_t* start_b, Grid g, Kern kc, hipStream_t s);
+
+// the step
+hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* out_bits, hipStream_t s);
+hipError_t launch_density_alpha(int64_t nf, float4* x, const float4* v, const uint32_t* nlist,
+                                const uint32_t* ncnt, const float4* xb, const uint32_t* blist,
+                                const uint32_t* bcnt, Kern kc, float* rho, float* alpha, float4* v_in,
+                                float* Kv, float* kappa, float warm_factor, hipStream_t s);
+hipError_t launch_pressure_update(int64_t nf, const float4* x, float4* v, const float* kappa, float* Kacc,
+                                  float* kappa_last, const uint32_t* nlist, const uint32_t* ncnt, const float4* xb,
+                                  const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt,
+                                  hipStream_t s);
+// mode 0: divergence (kappa = max(d,0) alpha / dt); mode 1: density
+// (kappa = max(rho - rho0 + dt d, 0) alpha / dt^2).  Writes kappa, kappa/rho
+// into x.w, and the FP64 sum of the clamped error into *err_out.
+hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, const float* rho, const float* alpha,
+                          float* kappa, const uint32_t* nlist, const uint32_t* ncnt,
+                          const float4* xb, const float4* vb, const uint32_t* blist, const uint32_t* bcnt,
+                          Kern kc, float dt, double* partials, uint32_t* counter, double* err_out,
+                          hipStream_t s);
+// non-pressure: v* = v + dt g + viscosity; also sets up the density warm start
+// (kappa = warm_factor K, K = 0, x.w = kappa / rho).
+hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v, float4* vout, const float* rho,
+                              const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float gx, float gy,
+                              float gz, float visc, float* K, float* kappa, float warm_factor, hipStream_t s);
+hipError_t launch_warm_setup(int64_t nf, float4* x, const float* rho, float* K, float* kappa, float warm_factor,
+                             hipStream_t s);
+hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, hipStream_t s);
+hipError_t launch_rigid_force(int64_t nf, const float4* x, const float* rho, const float* K, const float* Kv,
+                              const uint32_t* blist, const uint32_t* bcnt, const float4* xb, const float4* vb,
+                              Kern kc, int32_t nbody, const double* com, double* partials, uint32_t* counter,
+                              double* out, hipStream_t s);
+hipError_t launch_rigid_boundary(int64_t nb, float4* xb, float4* vb, const int32_t* bid, const double* local,
+                                 const BodyPose* poses, hipStream_t s);
+
+// implicit viscosity (Eqs. 16-19): M p = p - dt A p and its block-Jacobi preconditioner
+hipError_t launch_visc_precond(int64_t nf, const float4* x, const float* rho, const uint32_t* nlist,
+                               const uint32_t* ncnt, Kern kc, float dt, float mu, float* Pinv, hipStream_t s);
+hipError_t launch_visc_matvec(int64_t nf, const float4* x, const float* rho, const float4* p, float4* Mp,
+                              const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float mu,
+                              hipStream_t s);
+// FP64 dot products of 3-vectors stored as float4 (w ignored): out[0] = a.b
+hipError_t launch_dot(int64_t nf, const float4* a, const float4* b, double* partials, uint32_t* counter,
+                      double* out, hipStream_t s);
+// x += a p; r -= a Ap with a = num/den from device scalars; z = Pinv r;
+// out_rz = r.z (FP64), out_rr = r.r (FP64)
+hipError_t launch_cg_update(int64_t nf, float4* xv, float4* r, float4* z, const float4* p, const float4* Ap,
+                            const float* Pinv, const double* num, const double* den, double* partials,
+                            uint32_t* counter, double* out2, hipStream_t s);
+// p = z + (rz_new / rz_old) p
+hipError_t launch_cg_direction(int64_t nf, float4* p, const float4* z, const double* rz_new, const double* rz_old,
+                               hipStream_t s);
+hipError_t launch_apply_precond(int64_t nf, const float* Pinv, const float4* r, float4* z, hipStream_t s);
+hipError_t launch_axpy_residual(int64_t nf, const float4* b, const float4* Mx, float4* r, hipStream_t s);
+hipError_t launch_gravity(int64_t nf, const float4* v, float4* out, float dt, float gx, float gy, float gz,
+                          hipStream_t s);
+
+// workgroups of a per-particle launch over n (a multiple of 8)
+uint32_t reduction_blocks(int64_t n);
+
+}  // namespace sph

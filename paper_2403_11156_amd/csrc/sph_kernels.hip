@@ -1,0 +1,1001 @@
+// sph_kernels.hip -- gfx950 kernels of the DFSPH time step.
+//
+// One lane per particle, 256-lane workgroups, particles kept in (cell key,
+// id) order so that neighbour gathers hit the XCD-local L2.  Workgroup ids are
+// remapped so that each of the 8 XCDs walks one contiguous eighth of the
+// particle range (hardware dispatch is round-robin over XCDs).
+//
+// The only integer decisions taken in floating point -- cell keys and the
+// neighbour predicate -- use explicit non-contracted FP32 so that they are
+// bit-exact with any IEEE implementation of the same formula.  Sums over
+// neighbours are FP32; every reduction that decides convergence or
+// accumulates a rigid-body force is FP64 in a fixed order (no float
+// atomics), so results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "sph_internal.h"
+
+namespace sph {
+namespace {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ uint32_t logical_block() {
+    const uint32_t b = blockIdx.x, per = gridDim.x >> 3;
+    return (b & 7u) * per + (b >> 3);
+}
+
+__device__ __forceinline__ int64_t particle_index() {
+    return (int64_t)logical_block() * kBlock + threadIdx.x;
+}
+
+inline uint32_t grid_blocks(int64_t n) {
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    return (uint32_t)((b + 7) & ~int64_t(7));   // a multiple of the 8 XCDs
+}
+
+// Cell coordinate: clamp(floor(fl32(fl32(x - o) * inv)), 0, n - 1); NaN -> 0.
+__device__ __forceinline__ int32_t cell_coord(float x, float o, float inv, int32_t n) {
+#pragma clang fp contract(off)
+    const float t = (x - o) * inv;
+    const float f = floorf(t);
+    if (!(f >= 0.0f)) return 0;
+    if (f > (float)(n - 1)) return n - 1;
+    return (int32_t)f;
+}
+
+__device__ __forceinline__ uint32_t cell_key(const Grid& g, float4 p) {
+    const int32_t cx = cell_coord(p.x, g.o[0], g.inv, g.n[0]);
+    const int32_t cy = cell_coord(p.y, g.o[1], g.inv, g.n[1]);
+    const int32_t cz = cell_coord(p.z, g.o[2], g.inv, g.n[2]);
+    return (uint32_t)(cx + g.n[0] * (cy + g.n[1] * cz));
+}
+
+// FP32 squared distance ((dx*dx + dy*dy) + dz*dz), no FMA: the neighbour predicate.
+__device__ __forceinline__ float dist2_exact(float4 a, float4 b) {
+#pragma clang fp contract(off)
+    const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    const float s = xx + yy;
+    return s + zz;
+}
+
+// Cubic spline (support h): grad_i W(x_ij) = grad_factor * x_ij.
+__device__ __forceinline__ float grad_factor(float r2, const Kern& kc) {
+    if (!(r2 > 0.0f)) return 0.0f;
+    const float rinv = rsqrtf(r2);
+    const float q = r2 * rinv * kc.inv_h;
+    const float t = fmaxf(1.0f - q, 0.0f);
+    const float fp = q <= 0.5f ? q * (3.0f * q - 2.0f) : -t * t;
+    return kc.kg * fp * rinv;
+}
+
+__device__ __forceinline__ float kernel_W(float r2, const Kern& kc) {
+    const float q = sqrtf(r2) * kc.inv_h;
+    const float t = fmaxf(1.0f - q, 0.0f);
+    return q <= 0.5f ? kc.k * (6.0f * q * q * (q - 1.0f) + 1.0f) : kc.k * 2.0f * t * t * t;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Block-wide FP64 sum in a fixed order; the result is valid in thread 0.
+__device__ double block_sum(double v) {
+    __shared__ double ws[kBlock / 64];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        r = ws[0];
+        for (int w = 1; w < kBlock / 64; ++w) r += ws[w];
+    }
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double load_partial(const double* p) {
+    unsigned long long bits =
+        __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)bits);
+}
+
+// After every block stored its partial(s): true in the last block to arrive.
+__device__ bool last_block_done(uint32_t* counter) {
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t prev = atomicAdd(counter, 1u);
+        last = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last != 0;
+}
+
+// The last block sums `count` partials per output (strided by `stride`) in
+// block order and resets the arrival counter for the next launch.
+__device__ void finish_sums(const double* partials, int nout, int stride, double* out, uint32_t* counter) {
+    const int nblk = (int)gridDim.x;
+    for (int o = 0; o < nout; ++o) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kBlock) acc += load_partial(partials + (size_t)b * stride + o);
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) out[o] = acc;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+// ------------------------------------------------------------------ fills
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------ counting sort
+__global__ void k_keys_hist(const float4* __restrict__ x, int64_t n, Grid g, uint32_t* __restrict__ key,
+                            uint32_t* __restrict__ slot, uint32_t* __restrict__ count) {
+    const int64_t i = particle_index();
+    if (i >= n) return;
+    const uint32_t k = cell_key(g, x[i]);
+    key[i] = k;
+    slot[i] = atomicAdd(count + k, 1u);
+}
+
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+// Exclusive scan of one 4096-entry tile; writes the tile total to partials.
+__global__ void k_scan_local(const uint32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ out,
+                             uint32_t* __restrict__ partials) {
+    __shared__ uint32_t tile[kScanTile];
+    __shared__ uint32_t wsum[kBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
+        const int64_t gi = base + k;
+        tile[k] = gi < n ? in[gi] : 0u;
+    }
+    __syncthreads();
+    uint32_t local[kScanItems];
+    uint32_t sum = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        local[k] = sum;
+        sum += tile[threadIdx.x * kScanItems + k];
+    }
+    const int lane = threadIdx.x & 63;
+    uint32_t incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) wsum[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    uint32_t wbase = 0;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wbase += wsum[w];
+    const uint32_t excl = wbase + incl - sum;
+    for (int k = 0; k < kScanItems; ++k) tile[threadIdx.x * kScanItems + k] = excl + local[k];
+    __syncthreads();
+    for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
+        const int64_t gi = base + k;
+        if (gi < n) out[gi] = tile[k];
+    }
+    if (threadIdx.x == kBlock - 1) partials[blockIdx.x] = excl + sum;
+}
+
+__global__ void k_scan_add(uint32_t* __restrict__ out, int64_t n, const uint32_t* __restrict__ tile_base,
+                           const uint32_t* __restrict__ total) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] += tile_base[i / kScanTile];
+    if (i == n) out[n] = *total;
+}
+
+__global__ void k_scatter(const uint32_t* __restrict__ key, const uint32_t* __restrict__ slot,
+                          const uint32_t* __restrict__ start, int64_t n, uint32_t* __restrict__ src) {
+    const int64_t i = particle_index();
+    if (i >= n) return;
+    src[start[key[i]] + slot[i]] = (uint32_t)i;
+}
+
+// Insertion sort of each cell's entries by particle id (cells hold ~8).
+// Cells above 4096 entries are left unsorted and flagged (bit 1).
+__global__ void k_cell_sort(const uint32_t* __restrict__ start, int64_t ncell, uint32_t* __restrict__ src,
+                            const int32_t* __restrict__ id, uint32_t* flags) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncell) return;
+    const uint32_t b = start[c], e = start[c + 1];
+    if (e - b < 2) return;
+    if (e - b > 4096) {
+        atomicOr(flags, 2u);
+        return;
+    }
+    for (uint32_t p = b + 1; p < e; ++p) {
+        const uint32_t s = src[p];
+        const int32_t key = id[s];
+        uint32_t q = p;
+        while (q > b && id[src[q - 1]] > key) {
+            src[q] = src[q - 1];
+            --q;
+        }
+        src[q] = s;
+    }
+}
+
+__global__ void k_gather_fluid(const uint32_t* __restrict__ src, int64_t n, const float4* __restrict__ x,
+                               const float4* __restrict__ v, const float* __restrict__ K,
+                               const float* __restrict__ Kv, const int32_t* __restrict__ id,
+                               float4* __restrict__ xo, float4* __restrict__ vo, float* __restrict__ Ko,
+                               float* __restrict__ Kvo, int32_t* __restrict__ ido) {
+    const int64_t i = particle_index();
+    if (i >= n) return;
+    const uint32_t s = src[i];
+    xo[i] = x[s];
+    vo[i] = v[s];
+    Ko[i] = K[s];
+    Kvo[i] = Kv[s];
+    ido[i] = id[s];
+}
+
+__global__ void k_gather_boundary(const uint32_t* __restrict__ src, int64_t n, const float4* __restrict__ x,
+                                  const float4* __restrict__ v, const int32_t* __restrict__ id,
+                                  float4* __restrict__ xo, float4* __restrict__ vo, int32_t* __restrict__ ido) {
+    const int64_t i = particle_index();
+    if (i >= n) return;
+    const uint32_t s = src[i];
+    xo[i] = x[s];
+    vo[i] = v[s];
+    ido[i] = id[s];
+}
+
+// ------------------------------------------------------------------ neighbour lists
+// Walk the 27-cell stencil (dz, dy outer; the contiguous cx-1..cx+1 run of
+// sorted particles inner), which yields ascending sorted indices.
+__global__ void __launch_bounds__(kBlock) k_nbr_build(
+    const float4* __restrict__ x, int64_t nf, const float4* __restrict__ xb, const uint32_t* __restrict__ start_f,
+    const uint32_t* __restrict__ start_b, Grid g, uint32_t* __restrict__ nlist, uint32_t* __restrict__ ncnt,
+    int32_t capf, uint32_t* __restrict__ blist, uint32_t* __restrict__ bcnt, int32_t capb, uint32_t* flags,
+    unsigned long long* stats) {
+    const int64_t i = particle_index();
+    uint32_t total = 0xffffffffu, fl = 0;
+    if (i < nf) {
+        const float4 xi = x[i];
+        const int32_t cx = cell_coord(xi.x, g.o[0], g.inv, g.n[0]);
+        const int32_t cy = cell_coord(xi.y, g.o[1], g.inv, g.n[1]);
+        const int32_t cz = cell_coord(xi.z, g.o[2], g.inv, g.n[2]);
+        const int32_t x0 = cx > 0 ? cx - 1 : 0, x1 = cx < g.n[0] - 1 ? cx + 1 : g.n[0] - 1;
+        uint32_t nfc = 0, nbc = 0;
+        for (int32_t dz = -1; dz <= 1; ++dz) {
+            const int32_t z = cz + dz;
+            if (z < 0 || z >= g.n[2]) continue;
+            for (int32_t dy = -1; dy <= 1; ++dy) {
+                const int32_t y = cy + dy;
+                if (y < 0 || y >= g.n[1]) continue;
+                const int64_t row = (int64_t)g.n[0] * (y + (int64_t)g.n[1] * z);
+                const uint32_t b = start_f[row + x0], e = start_f[row + x1 + 1];
+                for (uint32_t j = b; j < e; ++j) {
+                    if ((int64_t)j == i) continue;
+                    if (dist2_exact(xi, x[j]) < g.h2) {
+                        if (nfc < (uint32_t)capf) nlist[(int64_t)nfc * nf + i] = j;
+                        ++nfc;
+                    }
+                }
+                const uint32_t bb = start_b[row + x0], be = start_b[row + x1 + 1];
+                for (uint32_t k = bb; k < be; ++k) {
+                    if (dist2_exact(xi, xb[k]) < g.h2) {
+                        if (nbc < (uint32_t)capb) blist[(int64_t)nbc * nf + i] = k;
+                        ++nbc;
+                    }
+                }
+            }
+        }
+        // stored counts never exceed the capacity, so readers stay in bounds
+        ncnt[i] = min(nfc, (uint32_t)capf);
+        bcnt[i] = min(nbc, (uint32_t)capb);
+        if (nfc > (uint32_t)capf || nbc > (uint32_t)capb) atomicOr(flags, 1u);
+        total = nfc + nbc;
+        fl = nfc;
+    }
+    // neighbour-count statistics: min, max, sum (integer atomics, exact)
+    uint32_t mn = total, mx = (i < nf) ? total : 0u;
+    unsigned long long sm = (i < nf) ? total : 0ull, sf = fl;
+    for (int off = 32; off > 0; off >>= 1) {
+        mn = min(mn, (uint32_t)__shfl_down((int)mn, off, 64));
+        mx = max(mx, (uint32_t)__shfl_down((int)mx, off, 64));
+        sm += __shfl_down(sm, off, 64);
+        sf += __shfl_down(sf, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(stats + 0, (unsigned long long)mn);
+        atomicMax(stats + 1, (unsigned long long)mx);
+        atomicAdd(stats + 2, sm);
+        atomicAdd(stats + 3, sf);
+    }
+}
+
+// Akinci boundary mass, Eq. (11): Psi_b = rho0 / (W(0) + sum_{k != b} W_bk) over
+// all boundary particles within h; stored in xb[b].w.
+__global__ void k_boundary_psi(float4* __restrict__ xb, int64_t nb, const uint32_t* __restrict__ start_b, Grid g,
+                               Kern kc) {
+    const int64_t i = particle_index();
+    if (i >= nb) return;
+    const float4 xi = xb[i];
+    const int32_t cx = cell_coord(xi.x, g.o[0], g.inv, g.n[0]);
+    const int32_t cy = cell_coord(xi.y, g.o[1], g.inv, g.n[1]);
+    const int32_t cz = cell_coord(xi.z, g.o[2], g.inv, g.n[2]);
+    const int32_t x0 = cx > 0 ? cx - 1 : 0, x1 = cx < g.n[0] - 1 ? cx + 1 : g.n[0] - 1;
+    float s = kc.k;
+    for (int32_t dz = -1; dz <= 1; ++dz) {
+        const int32_t z = cz + dz;
+        if (z < 0 || z >= g.n[2]) continue;
+        for (int32_t dy = -1; dy <= 1; ++dy) {
+            const int32_t y = cy + dy;
+            if (y < 0 || y >= g.n[1]) continue;
+            const int64_t row = (int64_t)g.n[0] * (y + (int64_t)g.n[1] * z);
+            const uint32_t b = start_b[row + x0], e = start_b[row + x1 + 1];
+            for (uint32_t k = b; k < e; ++k) {
+                if ((int64_t)k == i) continue;
+                const float4 xk = xb[k];
+                const float d2 = dist2_exact(xi, xk);
+                if (d2 < g.h2) s += kernel_W(d2, kc);
+            }
+        }
+    }
+    xb[i].w = kc.rho0 / s;
+}
+
+// ------------------------------------------------------------------ the step
+__global__ void k_max_v2(const float4* __restrict__ v, int64_t n, uint32_t* out_bits) {
+    const int64_t i = particle_index();
+    float m = 0.0f;
+    if (i < n) {
+#pragma clang fp contract(off)
+        const float4 a = v[i];
+        const float xx = a.x * a.x, yy = a.y * a.y, zz = a.z * a.z;
+        const float s = xx + yy;
+        m = s + zz;
+    }
+    uint32_t bits = __float_as_uint(m);   // non-negative floats order as integers
+    for (int off = 32; off > 0; off >>= 1) bits = max(bits, (uint32_t)__shfl_down((int)bits, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out_bits, bits);
+}
+
+// Density with the Akinci boundary term, Eq. (12), and the DFSPH factor
+// alpha = rho / (|sum_F m gradW + sum_B Psi gradW|^2 + sum_F |m gradW|^2).
+// Also saves the step's input velocity and sets up the divergence warm start.
+__global__ void __launch_bounds__(kBlock) k_density_alpha(
+    int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, const uint32_t* __restrict__ nlist,
+    const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const uint32_t* __restrict__ blist,
+    const uint32_t* __restrict__ bcnt, Kern kc, float* __restrict__ rho, float* __restrict__ alpha,
+    float4* __restrict__ v_in, float* __restrict__ Kv, float* __restrict__ kappa, float warm_factor) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float4 xi = x[i];
+    float r = kc.m * kc.k;
+    float gx = 0.f, gy = 0.f, gz = 0.f, sq = 0.f;
+    const uint32_t n = ncnt[i];
+    for (uint32_t k = 0; k < n; ++k) {
+        const float4 xj = x[nlist[(int64_t)k * nf + i]];
+        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        r += kc.m * kernel_W(r2, kc);
+        const float F = kc.m * grad_factor(r2, kc);
+        const float ax = F * dx, ay = F * dy, az = F * dz;
+        gx += ax; gy += ay; gz += az;
+        sq += ax * ax + ay * ay + az * az;
+    }
+    const uint32_t nbk = bcnt[i];
+    for (uint32_t k = 0; k < nbk; ++k) {
+        const float4 xk = xb[blist[(int64_t)k * nf + i]];
+        const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        r += xk.w * kernel_W(r2, kc);
+        const float F = xk.w * grad_factor(r2, kc);
+        gx += F * dx; gy += F * dy; gz += F * dz;
+    }
+    const float D = gx * gx + gy * gy + gz * gz + sq;
+    rho[i] = r;
+    alpha[i] = D > 1e-6f ? r / D : 0.0f;
+    v_in[i] = v[i];
+    const float k0 = warm_factor * Kv[i];
+    kappa[i] = k0;
+    Kv[i] = 0.0f;
+    x[i].w = k0 / r;
+}
+
+// Pressure velocity update (Eq. 7 with p/rho^2 = kappa/rho, the boundary term
+// of Eq. 13 using the particle's own pressure): kappa/rho comes from x.w.
+__global__ void __launch_bounds__(kBlock) k_pressure_update(
+    int64_t nf, const float4* __restrict__ x, float4* __restrict__ v, const float* __restrict__ kappa,
+    float* __restrict__ Kacc, float* __restrict__ kappa_last, const uint32_t* __restrict__ nlist,
+    const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const uint32_t* __restrict__ blist,
+    const uint32_t* __restrict__ bcnt, Kern kc, float dt) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float4 xi = x[i];
+    const float kri = xi.w;
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    const uint32_t n = ncnt[i];
+    for (uint32_t k = 0; k < n; ++k) {
+        const float4 xj = x[nlist[(int64_t)k * nf + i]];
+        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float c = (kri + xj.w) * grad_factor(r2, kc);
+        ax += c * dx; ay += c * dy; az += c * dz;
+    }
+    ax *= kc.m; ay *= kc.m; az *= kc.m;
+    const uint32_t nbk = bcnt[i];
+    for (uint32_t k = 0; k < nbk; ++k) {
+        const float4 xk = xb[blist[(int64_t)k * nf + i]];
+        const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float c = xk.w * kri * grad_factor(r2, kc);
+        ax += c * dx; ay += c * dy; az += c * dz;
+    }
+    float4 vi = v[i];
+    vi.x -= dt * ax; vi.y -= dt * ay; vi.z -= dt * az;
+    v[i] = vi;
+    const float ki = kappa[i];
+    Kacc[i] += ki;
+    if (kappa_last) kappa_last[i] = ki;
+}
+
+// Divergence d_i = sum_F m (v_i - v_j).gradW + sum_B Psi (v_i - v_k).gradW
+// (Eq. 6 in the DFSPH form, Eq. 9 for the predicted density), the next
+// stiffness, and the FP64 sum of the clamped error.
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_predict(
+    int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, const float* __restrict__ rho,
+    const float* __restrict__ alpha, float* __restrict__ kappa, const uint32_t* __restrict__ nlist,
+    const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const float4* __restrict__ vb,
+    const uint32_t* __restrict__ blist, const uint32_t* __restrict__ bcnt, Kern kc, float dt,
+    double* __restrict__ partials, uint32_t* counter, double* err_out) {
+    const int64_t i = particle_index();
+    double e = 0.0;
+    if (i < nf) {
+        const float4 xi = x[i];
+        const float4 vi = v[i];
+        float d = 0.f;
+        const uint32_t n = ncnt[i];
+        for (uint32_t k = 0; k < n; ++k) {
+            const uint32_t j = nlist[(int64_t)k * nf + i];
+            const float4 xj = x[j];
+            const float4 vj = v[j];
+            const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            d += grad_factor(r2, kc) * ((vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz);
+        }
+        d *= kc.m;
+        const uint32_t nbk = bcnt[i];
+        for (uint32_t k = 0; k < nbk; ++k) {
+            const uint32_t kk = blist[(int64_t)k * nf + i];
+            const float4 xk = xb[kk];
+            const float4 vk = vb[kk];
+            const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            d += xk.w * grad_factor(r2, kc) * ((vi.x - vk.x) * dx + (vi.y - vk.y) * dy + (vi.z - vk.z) * dz);
+        }
+        const float ri = rho[i];
+        float kap;
+        if (MODE == 0) {
+            const float ep = fmaxf(d, 0.0f);
+            kap = ep * alpha[i] / dt;
+            e = (double)ep;
+        } else {
+            const float dev = (ri - kc.rho0) + dt * d;
+            const float ep = fmaxf(dev, 0.0f);
+            kap = ep * alpha[i] / (dt * dt);
+            e = (double)ep;
+        }
+        kappa[i] = kap;
+        x[i].w = kap / ri;
+    }
+    const double bs = block_sum(e);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+    if (last_block_done(counter)) finish_sums(partials, 1, 1, err_out, counter);
+}
+
+// Non-pressure accelerations (Algorithm 1, first lines): v* = v + dt g plus
+// XSPH (model 1) or the explicit Laplacian of Eq. (15) (model 2); and the
+// set-up of the density warm start (kappa = warm_factor K, K = 0, x.w = kappa/rho).
+template <int MODEL>
+__global__ void __launch_bounds__(kBlock) k_nonpressure(
+    int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, float4* __restrict__ vout,
+    const float* __restrict__ rho, const uint32_t* __restrict__ nlist, const uint32_t* __restrict__ ncnt,
+    Kern kc, float dt, float gx, float gy, float gz, float visc, float* __restrict__ K, float* __restrict__ kappa,
+    float warm_factor) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float4 xi = x[i];
+    const float4 vi = v[i];
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    if (MODEL == 1 || MODEL == 2) {
+        const float eps2 = 0.01f * kc.h * kc.h;
+        const uint32_t n = ncnt[i];
+        for (uint32_t k = 0; k < n; ++k) {
+            const uint32_t j = nlist[(int64_t)k * nf + i];
+            const float4 xj = x[j];
+            const float4 vj = v[j];
+            const float mj = kc.m / rho[j];
+            const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (MODEL == 1) {
+                const float c = mj * kernel_W(r2, kc);
+                ax += c * (vj.x - vi.x); ay += c * (vj.y - vi.y); az += c * (vj.z - vi.z);
+            } else {
+                const float vx = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
+                const float c = mj * vx / (r2 + eps2) * grad_factor(r2, kc);
+                ax += c * dx; ay += c * dy; az += c * dz;
+            }
+        }
+    }
+    float s = 0.f;
+    if (MODEL == 1) s = visc;
+    if (MODEL == 2) s = dt * visc * 2.0f * (3 + 2);
+    float4 o;
+    o.x = vi.x + dt * gx + s * ax;
+    o.y = vi.y + dt * gy + s * ay;
+    o.z = vi.z + dt * gz + s * az;
+    o.w = 0.f;
+    vout[i] = o;
+    const float k0 = warm_factor * K[i];
+    kappa[i] = k0;
+    K[i] = 0.0f;
+    x[i].w = k0 / rho[i];
+}
+
+__global__ void k_integrate(int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, float dt) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    float4 xi = x[i];
+    const float4 vi = v[i];
+    xi.x += dt * vi.x; xi.y += dt * vi.y; xi.z += dt * vi.z;
+    x[i] = xi;
+}
+
+// Reaction on the rigid bodies (Eq. 14) from the step's total stiffness
+// K + Kv: F_ik = m Psi_k ((K_i + Kv_i) / rho_i) gradW_ik, torque (x_k - c_b) x F.
+// Pair terms in FP32, accumulation in FP64, fixed order.
+__global__ void __launch_bounds__(kBlock) k_rigid_force(
+    int64_t nf, const float4* __restrict__ x, const float* __restrict__ rho, const float* __restrict__ K,
+    const float* __restrict__ Kv, const uint32_t* __restrict__ blist, const uint32_t* __restrict__ bcnt,
+    const float4* __restrict__ xb, const float4* __restrict__ vb, Kern kc, int32_t nbody,
+    const double* __restrict__ com, double* __restrict__ partials, uint32_t* counter, double* out) {
+    const int64_t i = particle_index();
+    uint32_t nbk = 0;
+    float4 xi = make_float4(0.f, 0.f, 0.f, 0.f);
+    float base = 0.f;
+    if (i < nf) {
+        nbk = bcnt[i];
+        if (nbk) {
+            xi = x[i];
+            base = kc.m * (K[i] + Kv[i]) / rho[i];
+        }
+    }
+    for (int32_t b = 0; b < nbody; ++b) {
+        double f[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0};
+        for (uint32_t k = 0; k < nbk; ++k) {
+            const uint32_t kk = blist[(int64_t)k * nf + i];
+            const float4 vk = vb[kk];
+            if ((int32_t)vk.w != b) continue;
+            const float4 xk = xb[kk];
+            const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float c = base * xk.w * grad_factor(r2, kc);
+            const double Fx = (double)(c * dx), Fy = (double)(c * dy), Fz = (double)(c * dz);
+            const double rx = (double)xk.x - com[3 * b], ry = (double)xk.y - com[3 * b + 1],
+                         rz = (double)xk.z - com[3 * b + 2];
+            f[0] += Fx; f[1] += Fy; f[2] += Fz;
+            t[0] += ry * Fz - rz * Fy;
+            t[1] += rz * Fx - rx * Fz;
+            t[2] += rx * Fy - ry * Fx;
+        }
+        for (int c = 0; c < 3; ++c) {
+            const double s0 = block_sum(f[c]);
+            const double s1 = block_sum(t[c]);
+            if (threadIdx.x == 0) {
+                partials[((size_t)blockIdx.x * nbody + b) * 6 + c] = s0;
+                partials[((size_t)blockIdx.x * nbody + b) * 6 + 3 + c] = s1;
+            }
+        }
+    }
+    if (last_block_done(counter)) finish_sums(partials, 6 * nbody, 6 * nbody, out, counter);
+}
+
+// Rigid boundary particles from the body pose: x_k = fl32(c + R r_k) and
+// v_k = fl32(V + w x (x_k - c)), FP64 with no contraction.
+__global__ void k_rigid_boundary(int64_t nb, float4* __restrict__ xb, float4* __restrict__ vb,
+                                 const int32_t* __restrict__ bid, const double* __restrict__ local,
+                                 const BodyPose* __restrict__ poses) {
+#pragma clang fp contract(off)
+    const int64_t i = particle_index();
+    if (i >= nb) return;
+    float4 vk = vb[i];
+    const int32_t b = (int32_t)vk.w;
+    if (b < 0) return;
+    const BodyPose& P = poses[b];
+    const int64_t id = bid[i];
+    const double l0 = local[3 * id], l1 = local[3 * id + 1], l2 = local[3 * id + 2];
+    float xf[3];
+    for (int a = 0; a < 3; ++a) {
+        double t = P.R[3 * a] * l0 + P.R[3 * a + 1] * l1;
+        t = t + P.R[3 * a + 2] * l2;
+        xf[a] = (float)(P.com[a] + t);
+    }
+    const double rx = (double)xf[0] - P.com[0], ry = (double)xf[1] - P.com[1], rz = (double)xf[2] - P.com[2];
+    const double wx = P.omega[1] * rz - P.omega[2] * ry;
+    const double wy = P.omega[2] * rx - P.omega[0] * rz;
+    const double wz = P.omega[0] * ry - P.omega[1] * rx;
+    float4 xk = xb[i];
+    xk.x = xf[0]; xk.y = xf[1]; xk.z = xf[2];
+    xb[i] = xk;
+    vk.x = (float)(P.vel[0] + wx);
+    vk.y = (float)(P.vel[1] + wy);
+    vk.z = (float)(P.vel[2] + wz);
+    vb[i] = vk;
+}
+
+// ------------------------------------------------------------------ implicit viscosity
+// (A v)_i = sum_j 10 mu m / (rho_i rho_j) (x_ij.(v_i - v_j)) / (|x_ij|^2 + 0.01 h^2) gradW_ij
+__global__ void __launch_bounds__(kBlock) k_visc_matvec(
+    int64_t nf, const float4* __restrict__ x, const float* __restrict__ rho, const float4* __restrict__ p,
+    float4* __restrict__ Mp, const uint32_t* __restrict__ nlist, const uint32_t* __restrict__ ncnt, Kern kc,
+    float dt, float mu) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float4 xi = x[i];
+    const float4 pi = p[i];
+    const float eps2 = 0.01f * kc.h * kc.h;
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    const uint32_t n = ncnt[i];
+    for (uint32_t k = 0; k < n; ++k) {
+        const uint32_t j = nlist[(int64_t)k * nf + i];
+        const float4 xj = x[j];
+        const float4 pj = p[j];
+        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float xv = (pi.x - pj.x) * dx + (pi.y - pj.y) * dy + (pi.z - pj.z) * dz;
+        const float c = xv / (rho[j] * (r2 + eps2)) * grad_factor(r2, kc);
+        ax += c * dx; ay += c * dy; az += c * dz;
+    }
+    const float s = dt * 10.0f * mu * kc.m / rho[i];
+    float4 o;
+    o.x = pi.x - s * ax; o.y = pi.y - s * ay; o.z = pi.z - s * az; o.w = 0.f;
+    Mp[i] = o;
+}
+
+// Inverse of the 3x3 diagonal block I - dt A_ii = I + dt sum_j c_ij (-F_ij) x_ij x_ij^T.
+__global__ void __launch_bounds__(kBlock) k_visc_precond(
+    int64_t nf, const float4* __restrict__ x, const float* __restrict__ rho, const uint32_t* __restrict__ nlist,
+    const uint32_t* __restrict__ ncnt, Kern kc, float dt, float mu, float* __restrict__ Pinv) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float4 xi = x[i];
+    const float eps2 = 0.01f * kc.h * kc.h;
+    float b00 = 0.f, b01 = 0.f, b02 = 0.f, b11 = 0.f, b12 = 0.f, b22 = 0.f;
+    const uint32_t n = ncnt[i];
+    for (uint32_t k = 0; k < n; ++k) {
+        const uint32_t j = nlist[(int64_t)k * nf + i];
+        const float4 xj = x[j];
+        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float c = grad_factor(r2, kc) / (rho[j] * (r2 + eps2));
+        b00 += c * dx * dx; b01 += c * dx * dy; b02 += c * dx * dz;
+        b11 += c * dy * dy; b12 += c * dy * dz; b22 += c * dz * dz;
+    }
+    const float s = -dt * 10.0f * mu * kc.m / rho[i];
+    const double a = 1.0 + (double)(s * b00), bq = (double)(s * b01), cq = (double)(s * b02);
+    const double e = 1.0 + (double)(s * b11), f = (double)(s * b12), k2 = 1.0 + (double)(s * b22);
+    const double A = e * k2 - f * f, B = -(bq * k2 - f * cq), C = bq * f - e * cq;
+    const double det = a * A + bq * B + cq * C;
+    const double id = 1.0 / det;
+    float* o = Pinv + 9 * i;
+    o[0] = (float)(A * id);
+    o[1] = (float)(-(bq * k2 - cq * f) * id);
+    o[2] = (float)((bq * f - cq * e) * id);
+    o[3] = (float)(B * id);
+    o[4] = (float)((a * k2 - cq * cq) * id);
+    o[5] = (float)(-(a * f - cq * bq) * id);
+    o[6] = (float)(C * id);
+    o[7] = (float)(-(a * f - bq * cq) * id);
+    o[8] = (float)((a * e - bq * bq) * id);
+}
+
+__device__ __forceinline__ float4 apply3(const float* P, float4 r) {
+    float4 z;
+    z.x = P[0] * r.x + P[1] * r.y + P[2] * r.z;
+    z.y = P[3] * r.x + P[4] * r.y + P[5] * r.z;
+    z.z = P[6] * r.x + P[7] * r.y + P[8] * r.z;
+    z.w = 0.f;
+    return z;
+}
+
+__global__ void k_apply_precond(int64_t nf, const float* __restrict__ Pinv, const float4* __restrict__ r,
+                                float4* __restrict__ z) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    z[i] = apply3(Pinv + 9 * i, r[i]);
+}
+
+__global__ void k_axpy_residual(int64_t nf, const float4* __restrict__ b, const float4* __restrict__ Mx,
+                                float4* __restrict__ r) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float4 bb = b[i], m = Mx[i];
+    r[i] = make_float4(bb.x - m.x, bb.y - m.y, bb.z - m.z, 0.f);
+}
+
+__global__ void k_dot(int64_t nf, const float4* __restrict__ a, const float4* __restrict__ b,
+                      double* __restrict__ partials, uint32_t* counter, double* out) {
+    const int64_t i = particle_index();
+    double s = 0.0;
+    if (i < nf) {
+        const float4 u = a[i], w = b[i];
+        s = (double)u.x * (double)w.x + (double)u.y * (double)w.y + (double)u.z * (double)w.z;
+    }
+    const double bs = block_sum(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+    if (last_block_done(counter)) finish_sums(partials, 1, 1, out, counter);
+}
+
+__global__ void k_cg_update(int64_t nf, float4* __restrict__ xv, float4* __restrict__ r, float4* __restrict__ z,
+                            const float4* __restrict__ p, const float4* __restrict__ Ap,
+                            const float* __restrict__ Pinv, const double* num, const double* den,
+                            double* __restrict__ partials, uint32_t* counter, double* out2) {
+    const int64_t i = particle_index();
+    const float a = (float)(*num / *den);
+    double rz = 0.0, rr = 0.0;
+    if (i < nf) {
+        const float4 pp = p[i], ap = Ap[i];
+        float4 xx = xv[i], rv = r[i];
+        xx.x += a * pp.x; xx.y += a * pp.y; xx.z += a * pp.z;
+        rv.x -= a * ap.x; rv.y -= a * ap.y; rv.z -= a * ap.z;
+        xv[i] = xx;
+        r[i] = rv;
+        const float4 zz = apply3(Pinv + 9 * i, rv);
+        z[i] = zz;
+        rz = (double)rv.x * zz.x + (double)rv.y * zz.y + (double)rv.z * zz.z;
+        rr = (double)rv.x * rv.x + (double)rv.y * rv.y + (double)rv.z * rv.z;
+    }
+    const double s0 = block_sum(rz);
+    const double s1 = block_sum(rr);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s0;
+        partials[2 * blockIdx.x + 1] = s1;
+    }
+    if (last_block_done(counter)) finish_sums(partials, 2, 2, out2, counter);
+}
+
+__global__ void k_cg_direction(int64_t nf, float4* __restrict__ p, const float4* __restrict__ z,
+                               const double* rz_new, const double* rz_old) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float beta = (float)(*rz_new / *rz_old);
+    const float4 zz = z[i];
+    float4 pp = p[i];
+    pp.x = zz.x + beta * pp.x; pp.y = zz.y + beta * pp.y; pp.z = zz.z + beta * pp.z;
+    p[i] = pp;
+}
+
+__global__ void k_gravity(int64_t nf, const float4* __restrict__ v, float4* __restrict__ out, float dt, float gx,
+                          float gy, float gz) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float4 a = v[i];
+    out[i] = make_float4(a.x + dt * gx, a.y + dt * gy, a.z + dt * gz, 0.f);
+}
+
+__global__ void k_warm_setup(int64_t nf, float4* __restrict__ x, const float* __restrict__ rho,
+                             float* __restrict__ K, float* __restrict__ kappa, float warm_factor) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float k0 = warm_factor * K[i];
+    kappa[i] = k0;
+    K[i] = 0.0f;
+    x[i].w = k0 / rho[i];
+}
+
+}  // namespace
+
+// ================================================================== launchers
+#define LAUNCH(kern, n, ...)                                                        \
+    do {                                                                            \
+        hipLaunchKernelGGL(kern, dim3(grid_blocks(n)), dim3(kBlock), 0, s, __VA_ARGS__); \
+        return hipGetLastError();                                                   \
+    } while (0)
+
+static inline uint32_t plain_blocks(int64_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(plain_blocks(n)), dim3(kBlock), 0, s, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f32, dim3(plain_blocks(n)), dim3(kBlock), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_keys_hist(const float4* x, int64_t n, Grid g, uint32_t* key, uint32_t* slot, uint32_t* count,
+                            hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    LAUNCH(k_keys_hist, n, x, n, g, key, slot, count);
+}
+
+// partials needs ceil(n / 4096) + 2 + ceil(ceil(n/4096)/4096) entries.
+hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* partials, hipStream_t s) {
+    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    if (tiles > kScanTile) return hipErrorInvalidValue;   // > 16.7M cells
+    uint32_t* tile_sum = partials;               // [tiles]
+    uint32_t* tile_base = partials + tiles;      // [tiles]
+    uint32_t* total = partials + 2 * tiles;      // [1]
+    hipLaunchKernelGGL(k_scan_local, dim3((uint32_t)tiles), dim3(kBlock), 0, s, in, n, out, tile_sum);
+    hipLaunchKernelGGL(k_scan_local, dim3(1), dim3(kBlock), 0, s, tile_sum, tiles, tile_base, total);
+    hipLaunchKernelGGL(k_scan_add, dim3(plain_blocks(n + 1)), dim3(kBlock), 0, s, out, n, tile_base, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const uint32_t* key, const uint32_t* slot, const uint32_t* start, int64_t n, uint32_t* src,
+                          hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    LAUNCH(k_scatter, n, key, slot, start, n, src);
+}
+
+hipError_t launch_cell_sort(const uint32_t* start, int64_t ncell, uint32_t* src, const int32_t* id, uint32_t* flags,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_cell_sort, dim3(plain_blocks(ncell)), dim3(kBlock), 0, s, start, ncell, src, id, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_fluid(const uint32_t* src, int64_t n, const float4* x, const float4* v, const float* K,
+                               const float* Kv, const int32_t* id, float4* xo, float4* vo, float* Ko, float* Kvo,
+                               int32_t* ido, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    LAUNCH(k_gather_fluid, n, src, n, x, v, K, Kv, id, xo, vo, Ko, Kvo, ido);
+}
+
+hipError_t launch_gather_boundary(const uint32_t* src, int64_t n, const float4* x, const float4* v, const int32_t* id,
+                                  float4* xo, float4* vo, int32_t* ido, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    LAUNCH(k_gather_boundary, n, src, n, x, v, id, xo, vo, ido);
+}
+
+hipError_t launch_nbr_build(const float4* x, int64_t nf, const float4* xb, const uint32_t* start_f,
+                            const uint32_t* start_b, Grid g, uint32_t* nlist, uint32_t* ncnt, int32_t capf,
+                            uint32_t* blist, uint32_t* bcnt, int32_t capb, uint32_t* flags, uint32_t* stats,
+                            hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_nbr_build, nf, x, nf, xb, start_f, start_b, g, nlist, ncnt, capf, blist, bcnt, capb, flags,
+           (unsigned long long*)stats);
+}
+
+hipError_t launch_boundary_psi(float4* xb, int64_t nb, const uint32_t* start_b, Grid g, Kern kc, hipStream_t s) {
+    if (nb <= 0) return hipSuccess;
+    LAUNCH(k_boundary_psi, nb, xb, nb, start_b, g, kc);
+}
+
+hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* out_bits, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    LAUNCH(k_max_v2, n, v, n, out_bits);
+}
+
+hipError_t launch_density_alpha(int64_t nf, float4* x, const float4* v, const uint32_t* nlist, const uint32_t* ncnt,
+                                const float4* xb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float* rho,
+                                float* alpha, float4* v_in, float* Kv, float* kappa, float warm_factor,
+                                hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_density_alpha, nf, nf, x, v, nlist, ncnt, xb, blist, bcnt, kc, rho, alpha, v_in, Kv, kappa,
+           warm_factor);
+}
+
+hipError_t launch_pressure_update(int64_t nf, const float4* x, float4* v, const float* kappa, float* Kacc,
+                                  float* kappa_last, const uint32_t* nlist, const uint32_t* ncnt, const float4* xb,
+                                  const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt, hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_pressure_update, nf, nf, x, v, kappa, Kacc, kappa_last, nlist, ncnt, xb, blist, bcnt, kc, dt);
+}
+
+hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, const float* rho, const float* alpha,
+                          float* kappa, const uint32_t* nlist, const uint32_t* ncnt, const float4* xb,
+                          const float4* vb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt,
+                          double* partials, uint32_t* counter, double* err_out, hipStream_t s) {
+    if (mode == 0)
+        LAUNCH(k_predict<0>, nf, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb, vb, blist, bcnt, kc, dt, partials,
+               counter, err_out);
+    LAUNCH(k_predict<1>, nf, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb, vb, blist, bcnt, kc, dt, partials,
+           counter, err_out);
+}
+
+hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v, float4* vout, const float* rho,
+                              const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float gx, float gy,
+                              float gz, float visc, float* K, float* kappa, float warm_factor, hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    if (model == 1)
+        LAUNCH(k_nonpressure<1>, nf, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa,
+               warm_factor);
+    if (model == 2)
+        LAUNCH(k_nonpressure<2>, nf, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa,
+               warm_factor);
+    LAUNCH(k_nonpressure<0>, nf, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa,
+           warm_factor);
+}
+
+hipError_t launch_warm_setup(int64_t nf, float4* x, const float* rho, float* K, float* kappa, float warm_factor,
+                             hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_warm_setup, nf, nf, x, rho, K, kappa, warm_factor);
+}
+
+hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_integrate, nf, nf, x, v, dt);
+}
+
+hipError_t launch_rigid_force(int64_t nf, const float4* x, const float* rho, const float* K, const float* Kv,
+                              const uint32_t* blist, const uint32_t* bcnt, const float4* xb, const float4* vb,
+                              Kern kc, int32_t nbody, const double* com, double* partials, uint32_t* counter,
+                              double* out, hipStream_t s) {
+    LAUNCH(k_rigid_force, nf, nf, x, rho, K, Kv, blist, bcnt, xb, vb, kc, nbody, com, partials, counter, out);
+}
+
+hipError_t launch_rigid_boundary(int64_t nb, float4* xb, float4* vb, const int32_t* bid, const double* local,
+                                 const BodyPose* poses, hipStream_t s) {
+    if (nb <= 0) return hipSuccess;
+    LAUNCH(k_rigid_boundary, nb, nb, xb, vb, bid, local, poses);
+}
+
+hipError_t launch_visc_precond(int64_t nf, const float4* x, const float* rho, const uint32_t* nlist,
+                               const uint32_t* ncnt, Kern kc, float dt, float mu, float* Pinv, hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_visc_precond, nf, nf, x, rho, nlist, ncnt, kc, dt, mu, Pinv);
+}
+
+hipError_t launch_visc_matvec(int64_t nf, const float4* x, const float* rho, const float4* p, float4* Mp,
+                              const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float mu,
+                              hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_visc_matvec, nf, nf, x, rho, p, Mp, nlist, ncnt, kc, dt, mu);
+}
+
+hipError_t launch_dot(int64_t nf, const float4* a, const float4* b, double* partials, uint32_t* counter, double* out,
+                      hipStream_t s) {
+    LAUNCH(k_dot, nf, nf, a, b, partials, counter, out);
+}
+
+hipError_t launch_cg_update(int64_t nf, float4* xv, float4* r, float4* z, const float4* p, const float4* Ap,
+                            const float* Pinv, const double* num, const double* den, double* partials,
+                            uint32_t* counter, double* out2, hipStream_t s) {
+    LAUNCH(k_cg_update, nf, nf, xv, r, z, p, Ap, Pinv, num, den, partials, counter, out2);
+}
+
+hipError_t launch_cg_direction(int64_t nf, float4* p, const float4* z, const double* rz_new, const double* rz_old,
+                               hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_cg_direction, nf, nf, p, z, rz_new, rz_old);
+}
+
+hipError_t launch_apply_precond(int64_t nf, const float* Pinv, const float4* r, float4* z, hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_apply_precond, nf, nf, Pinv, r, z);
+}
+
+hipError_t launch_axpy_residual(int64_t nf, const float4* b, const float4* Mx, float4* r, hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_axpy_residual, nf, nf, b, Mx, r);
+}
+
+hipError_t launch_gravity(int64_t nf, const float4* v, float4* out, float dt, float gx, float gy, float gz,
+                          hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_gravity, nf, nf, v, out, dt, gx, gy, gz);
+}
+
+uint32_t reduction_blocks(int64_t n) { return grid_blocks(n); }
+
+}  // namespace sph
