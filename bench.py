@@ -1,0 +1,164 @@
+"""Throughput of the DFSPH time step on one MI355X.
+
+One step = sph_build_neighbors + sph_step (grid sort, neighbour lists, density
+and alpha, divergence-free solve, non-pressure forces, warm start,
+constant-density solve, rigid coupling, integration) on a synthetic scene
+already resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c5|c2|c3|c4|c1]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+
+# per-launch algorithmic bytes are computed inside the library (see the
+# design notes: own fields of every particle read/written once plus 4 B per
+# neighbour-list entry)
+PROFILED = ("pressure_update", "predict", "density_alpha", "xsph", "nbr_build", "sort", "integrate", "visc")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", default="c5")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (counter calibration)")
+    return ap.parse_args()
+
+
+def measured_traffic(config: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs (scaled FETCH_SIZE + WRITE_SIZE), or None if they were taken on a
+    different kernel source than the one built now."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{config}.txt")
+    src = os.path.join(ROOT, "paper_2403_11156_amd", "csrc", "sph_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    table, recorded = {}, None
+    for line in open(path):
+        parts = line.split()
+        if not parts or parts[0].startswith("#"):
+            continue
+        if parts[0] == "source_sha":
+            recorded = parts[1]
+        elif len(parts) == 3:
+            table[parts[0]] = int(parts[1]) + int(parts[2])
+    if recorded != sha:
+        return None
+    return table.get(kernel)
+
+
+def cpu_baseline(scene_name: str, steps: int):
+    """The FP64 oracle, as it stands, on the host: `steps` steps of the same
+    workload from its initial state (single-threaded)."""
+    from oracle import oracle as O
+    from paper_2403_11156_amd import scenes
+    O.build(force=False)
+    sc = scenes.scene(scene_name)
+    st = O.State(sc)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = O.step(st)
+        st = O.advance(st, out)
+    dt = time.perf_counter() - t0
+    return {"value": sc.n_fluid * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} step(s) of {sc.name} from its initial state, FP64, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    from paper_2403_11156_amd import scenes, sph
+
+    if args.calib_copy_mb > 0:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {args.calib_copy_mb} MiB read + {args.calib_copy_mb} MiB written", flush=True)
+        del a, b
+    sc = scenes.scene(args.config)
+    sim = sph.Simulation(sc)
+    print(f"[bench] {sc.name}: {sc.n_fluid} fluid, {sc.n_boundary} boundary, warmup {args.warmup}", flush=True)
+    for _ in range(args.warmup):
+        sim.advance()
+    torch.cuda.synchronize()
+    sim.profile_enable(True)
+    iters = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = sim.advance()
+        iters.append((st["iters_div"], st["iters_dens"], st["cg_iters"]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = {k: sim.profile_read(k) for k in PROFILED}
+    sim.profile_enable(False)
+    print(f"[bench] timed {args.steps} steps in {wall:.3f} s", flush=True)
+
+    ms_step = wall * 1e3 / args.steps
+    value = sc.n_fluid * args.steps / wall
+    # dominant kernel: most event time over the timed region
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    avg_ms = d["ms"] / max(d["launches"], 1)
+    achieved = (d["bytes"] / max(d["launches"], 1)) / (avg_ms * 1e-3) / 1e9 if d["launches"] else 0.0
+    kernels = {k: {"launches": v["launches"], "avg_us": (1e3 * v["ms"] / v["launches"]) if v["launches"] else 0.0,
+                   "GBs": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else 0.0,
+                   "share": v["ms"] / max(1e-9, wall * 1e3)} for k, v in prof.items() if v["launches"]}
+    n = len(iters)
+    line = {
+        "metric": "particle-steps/sec at eta=0.1% (DFSPH), plain previous-step warm start",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": sc.name, "n_fluid": sc.n_fluid, "n_boundary": sc.n_boundary,
+                   "n_rigid": len(sc.rigid), "r": sc.params["r"], "eta": sc.params["eta_density"],
+                   "warm_start": "previous", "parallelism": "none (1 GPU)"},
+        "iters_per_step": {"div": sum(i[0] for i in iters) / n, "dens": sum(i[1] for i in iters) / n,
+                           "cg": sum(i[2] for i in iters) / n},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config, dom),
+                     "bytes_per_launch": d["bytes"] / max(d["launches"], 1)},
+        "kernels": kernels,
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.config, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -69,8 +69,8 @@ struct sph_ctx {
     double *com_dev = nullptr;
     // reductions and flags
     double *red_part = nullptr, *scal = nullptr, *rigid_out = nullptr;
-    uint32_t *counter = nullptr, *flags = nullptr, *vmax_bits = nullptr;
-    unsigned long long *nstats = nullptr;
+    uint32_t *flags = nullptr, *vmax_bits = nullptr;
+    unsigned long long *nstats = nullptr, *nstat_part = nullptr;
     // implicit viscosity
     float *Pinv = nullptr;
     float4 *cg_b = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
@@ -95,6 +95,7 @@ struct sph_ctx {
 
     bool prof = false;
     std::vector<ProfEvent> prof_pending;
+    std::vector<hipEvent_t> event_pool;
     std::map<std::string, ProfTotal> prof_total;
 };
 
@@ -139,6 +140,19 @@ void free_all(sph_ctx *c) {
         (void)hipEventDestroy(e.b);
     }
     c->prof_pending.clear();
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+    c->event_pool.clear();
+}
+
+hipEvent_t take_event(sph_ctx *c) {
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
 }
 
 // ---- profiling -------------------------------------------------------------
@@ -150,8 +164,8 @@ struct ProfScope {
         if (!on) return;
         ev.name = name;
         ev.bytes = bytes;
-        (void)hipEventCreate(&ev.a);
-        (void)hipEventCreate(&ev.b);
+        ev.a = take_event(c);
+        ev.b = take_event(c);
         (void)hipEventRecord(ev.a, c->stream);
     }
     ~ProfScope() {
@@ -171,8 +185,8 @@ void prof_resolve(sph_ctx *c) {
         t.launches += 1;
         t.ms += ms;
         t.bytes += e.bytes;
-        (void)hipEventDestroy(e.a);
-        (void)hipEventDestroy(e.b);
+        c->event_pool.push_back(e.a);
+        c->event_pool.push_back(e.b);
     }
     c->prof_pending.clear();
 }
@@ -323,13 +337,10 @@ int build(sph_ctx *c) {
         int rc = sort_fluid(c);
         if (rc) return rc;
     }
-    // neighbour statistics: min = ~0, max = sum_total = sum_fluid = 0
-    HIP_TRY(c, sph::launch_fill_u32((uint32_t *)c->nstats, 2, 0xffffffffu, s));
-    HIP_TRY(c, sph::launch_fill_u32((uint32_t *)c->nstats + 2, 6, 0u, s));
     {
         ProfScope ps(c, "nbr_build", 16.0 * c->nf + 8.0 * c->nf + list_bytes(c));
         HIP_TRY(c, sph::launch_nbr_build(c->x, c->nf, c->xb, c->start_f, c->start_b, c->g, c->nlist, c->ncnt, c->capf,
-                                         c->blist, c->bcnt, c->capb, c->flags, (uint32_t *)c->nstats, s));
+                                         c->blist, c->bcnt, c->capb, c->flags, c->nstat_part, c->nstats, s));
     }
     HIP_TRY(c, hipMemcpyAsync(c->h_u32, c->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(c->h_stats, c->nstats, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -368,7 +379,7 @@ int predict_pass(sph_ctx *c, int mode, float dt, double *err_sum) {
     {
         ProfScope ps(c, "predict", 56.0 * c->nf + list_bytes(c));
         HIP_TRY(c, sph::launch_predict(mode, c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->nlist, c->ncnt, c->xb,
-                                       c->vb, c->blist, c->bcnt, c->kc, dt, c->red_part, c->counter, c->scal,
+                                       c->vb, c->blist, c->bcnt, c->kc, dt, c->red_part, c->scal,
                                        c->stream));
     }
     return read_scalar(c, c->scal, err_sum);
@@ -422,9 +433,9 @@ int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
     HIP_TRY(c, hipMemcpyAsync(c->cg_p, c->cg_z, sizeof(float4) * nf, hipMemcpyDeviceToDevice, s));
     double *rz = c->scal + 1, *pAp = c->scal + 2, *out2 = c->scal + 3, *bb = c->scal + 5;
     // out2[0] = rz_new, out2[1] = rr
-    HIP_TRY(c, sph::launch_dot(nf, c->cg_r, c->cg_z, c->red_part, c->counter, rz, s));
-    HIP_TRY(c, sph::launch_dot(nf, c->cg_b, c->cg_b, c->red_part, c->counter, bb, s));
-    HIP_TRY(c, sph::launch_dot(nf, c->cg_r, c->cg_r, c->red_part, c->counter, out2 + 1, s));
+    HIP_TRY(c, sph::launch_dot(nf, c->cg_r, c->cg_z, c->red_part, rz, s));
+    HIP_TRY(c, sph::launch_dot(nf, c->cg_b, c->cg_b, c->red_part, bb, s));
+    HIP_TRY(c, sph::launch_dot(nf, c->cg_r, c->cg_r, c->red_part, out2 + 1, s));
     HIP_TRY(c, hipMemcpyAsync(c->h_scal, c->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     const double bnorm = std::sqrt(c->h_scal[5]);
@@ -435,9 +446,9 @@ int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
             ProfScope ps(c, "visc", 44.0 * nf + fluid_list_bytes(c));
             HIP_TRY(c, sph::launch_visc_matvec(nf, c->x, c->rho, c->cg_p, c->cg_Ap, c->nlist, c->ncnt, c->kc, dt, mu, s));
         }
-        HIP_TRY(c, sph::launch_dot(nf, c->cg_p, c->cg_Ap, c->red_part, c->counter, pAp, s));
+        HIP_TRY(c, sph::launch_dot(nf, c->cg_p, c->cg_Ap, c->red_part, pAp, s));
         HIP_TRY(c, sph::launch_cg_update(nf, c->v2, c->cg_r, c->cg_z, c->cg_p, c->cg_Ap, c->Pinv, rz, pAp,
-                                         c->red_part, c->counter, out2, s));
+                                         c->red_part, out2, s));
         HIP_TRY(c, sph::launch_cg_direction(nf, c->cg_p, c->cg_z, out2, rz, s));
         HIP_TRY(c, hipMemcpyAsync(rz, out2, sizeof(double), hipMemcpyDeviceToDevice, s));
         HIP_TRY(c, hipMemcpyAsync(c->h_scal, out2 + 1, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -462,8 +473,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     // 1. time step (fixed, or CFL from the step's input velocities)
     float dt;
     if (c->P.cfl_lambda > 0.0) {
-        HIP_TRY(c, sph::launch_fill_u32(c->vmax_bits, 1, 0u, s));
-        HIP_TRY(c, sph::launch_max_v2(c->v, nf, c->vmax_bits, s));
+        HIP_TRY(c, sph::launch_max_v2(c->v, nf, (uint32_t *)c->red_part, c->vmax_bits, s));
         HIP_TRY(c, hipMemcpyAsync(c->h_u32, c->vmax_bits, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
         float vmax2;
@@ -523,7 +533,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     // 7. rigid bodies: Eq. 14 reaction, FP64 Newton-Euler, new boundary pose
     if (c->nr > 0) {
         HIP_TRY(c, sph::launch_rigid_force(nf, c->x, c->rho, c->K, c->Kv, c->blist, c->bcnt, c->xb, c->vb, c->kc,
-                                           c->nr, c->com_dev, c->red_part, c->counter, c->rigid_out, s));
+                                           c->nr, c->com_dev, c->red_part, c->rigid_out, s));
         std::vector<double> fo(6 * c->nr);
         HIP_TRY(c, hipMemcpyAsync(fo.data(), c->rigid_out, sizeof(double) * 6 * c->nr, hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
@@ -688,7 +698,8 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     ALLOC(c->bkey, nb); ALLOC(c->bslot, nb); ALLOC(c->bsrc, nb); ALLOC(c->blocal, 3 * nb);
     ALLOC(c->poses, std::max(1, c->nr)); ALLOC(c->com_dev, 3 * std::max(1, c->nr));
     ALLOC(c->red_part, nred * 6 * std::max(1, c->nr) + 16); ALLOC(c->scal, 16); ALLOC(c->rigid_out, 6 * std::max(1, c->nr));
-    ALLOC(c->counter, 4); ALLOC(c->flags, 4); ALLOC(c->vmax_bits, 4); ALLOC(c->nstats, 4);
+    ALLOC(c->flags, 4); ALLOC(c->vmax_bits, 4); ALLOC(c->nstats, 4);
+    ALLOC(c->nstat_part, 4 * nred);
     if (p->visc_model == SPH_VISC_IMPLICIT) {
         ALLOC(c->Pinv, 9 * nf); ALLOC(c->cg_b, nf); ALLOC(c->cg_r, nf); ALLOC(c->cg_z, nf); ALLOC(c->cg_p, nf);
         ALLOC(c->cg_Ap, nf);
@@ -750,8 +761,7 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
              hipMemcpyAsync(c->vb, hvb.data(), sizeof(float4) * nb, hipMemcpyHostToDevice, s) == hipSuccess &&
              hipMemcpyAsync(c->bid, hbid.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s) == hipSuccess &&
              hipMemcpyAsync(c->blocal, local.data(), sizeof(double) * 3 * nb, hipMemcpyHostToDevice, s) == hipSuccess;
-        ok = ok && sph::launch_fill_u32(c->counter, 4, 0u, s) == hipSuccess &&
-             hipStreamSynchronize(s) == hipSuccess;
+        ok = ok && hipStreamSynchronize(s) == hipSuccess;
         if (!ok) {
             free_all(c);
             delete c;

@@ -36,7 +36,9 @@ struct BodyPose {
 };
 
 // ---------------------------------------------------------------- launchers
-// Every launcher queues on `s` and returns hipGetLastError().
+// Every launcher queues on `s` and returns hipGetLastError().  Reductions
+// store one partial per workgroup in `partials` (reduction_blocks(n) entries
+// times the outputs) and finish in a one-workgroup kernel.
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 
@@ -58,12 +60,12 @@ hipError_t launch_gather_boundary(const uint32_t* src, int64_t n, const float4* 
 // neighbour lists, neighbour-major [cap][n]
 hipError_t launch_nbr_build(const float4* x, int64_t nf, const float4* xb, const uint32_t* start_f,
                             const uint32_t* start_b, Grid g, uint32_t* nlist, uint32_t* ncnt, int32_t capf,
-                            uint32_t* blist, uint32_t* bcnt, int32_t capb, uint32_t* flags, uint32_t* stats,
-                            hipStream_t s);
+                            uint32_t* blist, uint32_t* bcnt, int32_t capb, uint32_t* flags,
+                            unsigned long long* partials, unsigned long long* stats, hipStream_t s);
 hipError_t launch_boundary_psi(float4* xb, int64_t nb, const uint32_t* start_b, Grid g, Kern kc, hipStream_t s);
 
 // the step
-hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* out_bits, hipStream_t s);
+hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, uint32_t* out_bits, hipStream_t s);
 hipError_t launch_density_alpha(int64_t nf, float4* x, const float4* v, const uint32_t* nlist,
                                 const uint32_t* ncnt, const float4* xb, const uint32_t* blist,
                                 const uint32_t* bcnt, Kern kc, float* rho, float* alpha, float4* v_in,
@@ -78,8 +80,7 @@ hipError_t launch_pressure_update(int64_t nf, const float4* x, float4* v, const 
 hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, const float* rho, const float* alpha,
                           float* kappa, const uint32_t* nlist, const uint32_t* ncnt,
                           const float4* xb, const float4* vb, const uint32_t* blist, const uint32_t* bcnt,
-                          Kern kc, float dt, double* partials, uint32_t* counter, double* err_out,
-                          hipStream_t s);
+                          Kern kc, float dt, double* partials, double* err_out, hipStream_t s);
 // non-pressure: v* = v + dt g + viscosity; also sets up the density warm start
 // (kappa = warm_factor K, K = 0, x.w = kappa / rho).
 hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v, float4* vout, const float* rho,
@@ -90,8 +91,8 @@ hipError_t launch_warm_setup(int64_t nf, float4* x, const float* rho, float* K, 
 hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, hipStream_t s);
 hipError_t launch_rigid_force(int64_t nf, const float4* x, const float* rho, const float* K, const float* Kv,
                               const uint32_t* blist, const uint32_t* bcnt, const float4* xb, const float4* vb,
-                              Kern kc, int32_t nbody, const double* com, double* partials, uint32_t* counter,
-                              double* out, hipStream_t s);
+                              Kern kc, int32_t nbody, const double* com, double* partials, double* out,
+                              hipStream_t s);
 hipError_t launch_rigid_boundary(int64_t nb, float4* xb, float4* vb, const int32_t* bid, const double* local,
                                  const BodyPose* poses, hipStream_t s);
 
@@ -102,13 +103,13 @@ hipError_t launch_visc_matvec(int64_t nf, const float4* x, const float* rho, con
                               const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float mu,
                               hipStream_t s);
 // FP64 dot products of 3-vectors stored as float4 (w ignored): out[0] = a.b
-hipError_t launch_dot(int64_t nf, const float4* a, const float4* b, double* partials, uint32_t* counter,
-                      double* out, hipStream_t s);
+hipError_t launch_dot(int64_t nf, const float4* a, const float4* b, double* partials, double* out,
+                      hipStream_t s);
 // x += a p; r -= a Ap with a = num/den from device scalars; z = Pinv r;
 // out_rz = r.z (FP64), out_rr = r.r (FP64)
 hipError_t launch_cg_update(int64_t nf, float4* xv, float4* r, float4* z, const float4* p, const float4* Ap,
                             const float* Pinv, const double* num, const double* den, double* partials,
-                            uint32_t* counter, double* out2, hipStream_t s);
+                            double* out2, hipStream_t s);
 // p = z + (rz_new / rz_old) p
 hipError_t launch_cg_direction(int64_t nf, float4* p, const float4* z, const double* rz_new, const double* rz_old,
                                hipStream_t s);

@@ -60,10 +60,14 @@ __device__ __forceinline__ float dist2_exact(float4 a, float4 b) {
     return s + zz;
 }
 
-// Cubic spline (support h): grad_i W(x_ij) = grad_factor * x_ij.
+// Cubic spline (support h): grad_i W(x_ij) = grad_factor * x_ij.  Branch-free
+// (coincident particles select 0) so that neighbour loops can issue their
+// gathers ahead of the arithmetic; v_rsq_f32 directly (r^2 is never denormal
+// for distinct particles).
+__device__ __forceinline__ float inv_dist(float r2) { return r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f; }
+
 __device__ __forceinline__ float grad_factor(float r2, const Kern& kc) {
-    if (!(r2 > 0.0f)) return 0.0f;
-    const float rinv = rsqrtf(r2);
+    const float rinv = inv_dist(r2);
     const float q = r2 * rinv * kc.inv_h;
     const float t = fmaxf(1.0f - q, 0.0f);
     const float fp = q <= 0.5f ? q * (3.0f * q - 2.0f) : -t * t;
@@ -71,9 +75,31 @@ __device__ __forceinline__ float grad_factor(float r2, const Kern& kc) {
 }
 
 __device__ __forceinline__ float kernel_W(float r2, const Kern& kc) {
-    const float q = sqrtf(r2) * kc.inv_h;
+    const float q = r2 * inv_dist(r2) * kc.inv_h;
     const float t = fmaxf(1.0f - q, 0.0f);
     return q <= 0.5f ? kc.k * (6.0f * q * q * (q - 1.0f) + 1.0f) : kc.k * 2.0f * t * t * t;
+}
+
+// Visit the first n entries of particle i's neighbour-major list in chunks of
+// four: the four list loads, then the four gathers done by `f`, are issued
+// before any of the arithmetic, so each wave keeps several gathers in flight.
+template <class F>
+__device__ __forceinline__ void for_each_nbr(const uint32_t* __restrict__ list, int64_t nf, int64_t i, uint32_t n,
+                                             F&& f) {
+    const uint32_t* p = list + i;
+    uint32_t k = 0;
+    for (; k + 4 <= n; k += 4) {
+        const uint32_t j0 = p[0], j1 = p[nf], j2 = p[2 * nf], j3 = p[3 * nf];
+        p += 4 * nf;
+        f(j0);
+        f(j1);
+        f(j2);
+        f(j3);
+    }
+    for (; k < n; ++k) {
+        f(*p);
+        p += nf;
+    }
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -96,37 +122,56 @@ __device__ double block_sum(double v) {
     return r;
 }
 
-__device__ __forceinline__ double load_partial(const double* p) {
-    unsigned long long bits =
-        __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double((long long)bits);
-}
-
-// After every block stored its partial(s): true in the last block to arrive.
-__device__ bool last_block_done(uint32_t* counter) {
-    __shared__ int last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t prev = atomicAdd(counter, 1u);
-        last = (prev == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last != 0;
-}
-
-// The last block sums `count` partials per output (strided by `stride`) in
-// block order and resets the arrival counter for the next launch.
-__device__ void finish_sums(const double* partials, int nout, int stride, double* out, uint32_t* counter) {
-    const int nblk = (int)gridDim.x;
+// Reductions are two-phase: every workgroup stores its partial with a plain
+// store, and a one-workgroup finishing kernel sums the partials in workgroup
+// order.  The kernel boundary orders the two phases; no device-scope fence or
+// atomic is needed (an agent-scope fence on the multi-XCD part writes back the
+// XCD's L2, which costs far more than one extra launch).
+__global__ void k_finish_f64(const double* __restrict__ partials, int nblk, int nout, double* __restrict__ out) {
     for (int o = 0; o < nout; ++o) {
         double acc = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += kBlock) acc += load_partial(partials + (size_t)b * stride + o);
+        for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partials[(size_t)b * nout + o];
         acc = block_sum(acc);
         if (threadIdx.x == 0) out[o] = acc;
     }
-    if (threadIdx.x == 0) *counter = 0u;
+}
+
+// neighbour statistics per workgroup: [min, max, sum, sum_fluid]
+__global__ void k_finish_nstats(const unsigned long long* __restrict__ partials, int nblk,
+                                unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long s[4][kBlock];
+    unsigned long long mn = ~0ull, mx = 0ull, sm = 0ull, sf = 0ull;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) {
+        mn = min(mn, partials[4 * (size_t)b]);
+        mx = max(mx, partials[4 * (size_t)b + 1]);
+        sm += partials[4 * (size_t)b + 2];
+        sf += partials[4 * (size_t)b + 3];
+    }
+    s[0][threadIdx.x] = mn; s[1][threadIdx.x] = mx; s[2][threadIdx.x] = sm; s[3][threadIdx.x] = sf;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s[0][threadIdx.x] = min(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+            s[1][threadIdx.x] = max(s[1][threadIdx.x], s[1][threadIdx.x + w]);
+            s[2][threadIdx.x] += s[2][threadIdx.x + w];
+            s[3][threadIdx.x] += s[3][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk, uint32_t* __restrict__ out) {
+    __shared__ uint32_t s[kBlock];
+    uint32_t m = 0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) m = max(m, partials[b]);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
 }
 
 // ------------------------------------------------------------------ fills
@@ -254,13 +299,36 @@ __global__ void k_gather_boundary(const uint32_t* __restrict__ src, int64_t n, c
 }
 
 // ------------------------------------------------------------------ neighbour lists
+// Append the candidates c in [b, e) (ascending) with c != skip and the FP32
+// predicate d^2 < h^2 to row i of the neighbour-major list; candidates are
+// loaded four at a time ahead of the tests.
+__device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, uint32_t b, uint32_t e, float4 xi,
+                                                int64_t i, int64_t skip, float h2, uint32_t* __restrict__ list,
+                                                int64_t nf, int32_t cap, uint32_t& cnt) {
+    auto take = [&](uint32_t c, float4 p) {
+        if ((int64_t)c != skip && dist2_exact(xi, p) < h2) {
+            if (cnt < (uint32_t)cap) list[(int64_t)cnt * nf + i] = c;
+            ++cnt;
+        }
+    };
+    uint32_t c = b;
+    for (; c + 4 <= e; c += 4) {
+        const float4 p0 = pos[c], p1 = pos[c + 1], p2 = pos[c + 2], p3 = pos[c + 3];
+        take(c, p0);
+        take(c + 1, p1);
+        take(c + 2, p2);
+        take(c + 3, p3);
+    }
+    for (; c < e; ++c) take(c, pos[c]);
+}
+
 // Walk the 27-cell stencil (dz, dy outer; the contiguous cx-1..cx+1 run of
 // sorted particles inner), which yields ascending sorted indices.
 __global__ void __launch_bounds__(kBlock) k_nbr_build(
     const float4* __restrict__ x, int64_t nf, const float4* __restrict__ xb, const uint32_t* __restrict__ start_f,
     const uint32_t* __restrict__ start_b, Grid g, uint32_t* __restrict__ nlist, uint32_t* __restrict__ ncnt,
     int32_t capf, uint32_t* __restrict__ blist, uint32_t* __restrict__ bcnt, int32_t capb, uint32_t* flags,
-    unsigned long long* stats) {
+    unsigned long long* __restrict__ stats) {
     const int64_t i = particle_index();
     uint32_t total = 0xffffffffu, fl = 0;
     if (i < nf) {
@@ -278,20 +346,9 @@ __global__ void __launch_bounds__(kBlock) k_nbr_build(
                 if (y < 0 || y >= g.n[1]) continue;
                 const int64_t row = (int64_t)g.n[0] * (y + (int64_t)g.n[1] * z);
                 const uint32_t b = start_f[row + x0], e = start_f[row + x1 + 1];
-                for (uint32_t j = b; j < e; ++j) {
-                    if ((int64_t)j == i) continue;
-                    if (dist2_exact(xi, x[j]) < g.h2) {
-                        if (nfc < (uint32_t)capf) nlist[(int64_t)nfc * nf + i] = j;
-                        ++nfc;
-                    }
-                }
+                scan_candidates(x, b, e, xi, i, i, g.h2, nlist, nf, capf, nfc);
                 const uint32_t bb = start_b[row + x0], be = start_b[row + x1 + 1];
-                for (uint32_t k = bb; k < be; ++k) {
-                    if (dist2_exact(xi, xb[k]) < g.h2) {
-                        if (nbc < (uint32_t)capb) blist[(int64_t)nbc * nf + i] = k;
-                        ++nbc;
-                    }
-                }
+                scan_candidates(xb, bb, be, xi, i, -1, g.h2, blist, nf, capb, nbc);
             }
         }
         // stored counts never exceed the capacity, so readers stay in bounds
@@ -310,11 +367,26 @@ __global__ void __launch_bounds__(kBlock) k_nbr_build(
         sm += __shfl_down(sm, off, 64);
         sf += __shfl_down(sf, off, 64);
     }
+    __shared__ unsigned long long ws[kBlock / 64][4];
     if ((threadIdx.x & 63) == 0) {
-        atomicMin(stats + 0, (unsigned long long)mn);
-        atomicMax(stats + 1, (unsigned long long)mx);
-        atomicAdd(stats + 2, sm);
-        atomicAdd(stats + 3, sf);
+        ws[threadIdx.x >> 6][0] = mn;
+        ws[threadIdx.x >> 6][1] = mx;
+        ws[threadIdx.x >> 6][2] = sm;
+        ws[threadIdx.x >> 6][3] = sf;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = ws[0][0], b = ws[0][1], c = ws[0][2], d = ws[0][3];
+        for (int w = 1; w < kBlock / 64; ++w) {
+            a = min(a, ws[w][0]);
+            b = max(b, ws[w][1]);
+            c += ws[w][2];
+            d += ws[w][3];
+        }
+        stats[4 * (size_t)blockIdx.x] = a;
+        stats[4 * (size_t)blockIdx.x + 1] = b;
+        stats[4 * (size_t)blockIdx.x + 2] = c;
+        stats[4 * (size_t)blockIdx.x + 3] = d;
     }
 }
 
@@ -362,7 +434,14 @@ __global__ void k_max_v2(const float4* __restrict__ v, int64_t n, uint32_t* out_
     }
     uint32_t bits = __float_as_uint(m);   // non-negative floats order as integers
     for (int off = 32; off > 0; off >>= 1) bits = max(bits, (uint32_t)__shfl_down((int)bits, off, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(out_bits, bits);
+    __shared__ uint32_t ws[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = bits;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t m = ws[0];
+        for (int w = 1; w < kBlock / 64; ++w) m = max(m, ws[w]);
+        out_bits[blockIdx.x] = m;
+    }
 }
 
 // Density with the Akinci boundary term, Eq. (12), and the DFSPH factor
@@ -378,9 +457,8 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
     const float4 xi = x[i];
     float r = kc.m * kc.k;
     float gx = 0.f, gy = 0.f, gz = 0.f, sq = 0.f;
-    const uint32_t n = ncnt[i];
-    for (uint32_t k = 0; k < n; ++k) {
-        const float4 xj = x[nlist[(int64_t)k * nf + i]];
+    for_each_nbr(nlist, nf, i, ncnt[i], [&](uint32_t j) {
+        const float4 xj = x[j];
         const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
         r += kc.m * kernel_W(r2, kc);
@@ -388,16 +466,15 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
         const float ax = F * dx, ay = F * dy, az = F * dz;
         gx += ax; gy += ay; gz += az;
         sq += ax * ax + ay * ay + az * az;
-    }
-    const uint32_t nbk = bcnt[i];
-    for (uint32_t k = 0; k < nbk; ++k) {
-        const float4 xk = xb[blist[(int64_t)k * nf + i]];
+    });
+    for_each_nbr(blist, nf, i, bcnt[i], [&](uint32_t kk) {
+        const float4 xk = xb[kk];
         const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
         r += xk.w * kernel_W(r2, kc);
         const float F = xk.w * grad_factor(r2, kc);
         gx += F * dx; gy += F * dy; gz += F * dz;
-    }
+    });
     const float D = gx * gx + gy * gy + gz * gz + sq;
     rho[i] = r;
     alpha[i] = D > 1e-6f ? r / D : 0.0f;
@@ -420,23 +497,21 @@ __global__ void __launch_bounds__(kBlock) k_pressure_update(
     const float4 xi = x[i];
     const float kri = xi.w;
     float ax = 0.f, ay = 0.f, az = 0.f;
-    const uint32_t n = ncnt[i];
-    for (uint32_t k = 0; k < n; ++k) {
-        const float4 xj = x[nlist[(int64_t)k * nf + i]];
+    for_each_nbr(nlist, nf, i, ncnt[i], [&](uint32_t j) {
+        const float4 xj = x[j];
         const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
         const float c = (kri + xj.w) * grad_factor(r2, kc);
         ax += c * dx; ay += c * dy; az += c * dz;
-    }
+    });
     ax *= kc.m; ay *= kc.m; az *= kc.m;
-    const uint32_t nbk = bcnt[i];
-    for (uint32_t k = 0; k < nbk; ++k) {
-        const float4 xk = xb[blist[(int64_t)k * nf + i]];
+    for_each_nbr(blist, nf, i, bcnt[i], [&](uint32_t kk) {
+        const float4 xk = xb[kk];
         const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
         const float c = xk.w * kri * grad_factor(r2, kc);
         ax += c * dx; ay += c * dy; az += c * dz;
-    }
+    });
     float4 vi = v[i];
     vi.x -= dt * ax; vi.y -= dt * ay; vi.z -= dt * az;
     v[i] = vi;
@@ -454,32 +529,28 @@ __global__ void __launch_bounds__(kBlock) k_predict(
     const float* __restrict__ alpha, float* __restrict__ kappa, const uint32_t* __restrict__ nlist,
     const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const float4* __restrict__ vb,
     const uint32_t* __restrict__ blist, const uint32_t* __restrict__ bcnt, Kern kc, float dt,
-    double* __restrict__ partials, uint32_t* counter, double* err_out) {
+    double* __restrict__ partials) {
     const int64_t i = particle_index();
     double e = 0.0;
     if (i < nf) {
         const float4 xi = x[i];
         const float4 vi = v[i];
         float d = 0.f;
-        const uint32_t n = ncnt[i];
-        for (uint32_t k = 0; k < n; ++k) {
-            const uint32_t j = nlist[(int64_t)k * nf + i];
+        for_each_nbr(nlist, nf, i, ncnt[i], [&](uint32_t j) {
             const float4 xj = x[j];
             const float4 vj = v[j];
             const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             d += grad_factor(r2, kc) * ((vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz);
-        }
+        });
         d *= kc.m;
-        const uint32_t nbk = bcnt[i];
-        for (uint32_t k = 0; k < nbk; ++k) {
-            const uint32_t kk = blist[(int64_t)k * nf + i];
+        for_each_nbr(blist, nf, i, bcnt[i], [&](uint32_t kk) {
             const float4 xk = xb[kk];
             const float4 vk = vb[kk];
             const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             d += xk.w * grad_factor(r2, kc) * ((vi.x - vk.x) * dx + (vi.y - vk.y) * dy + (vi.z - vk.z) * dz);
-        }
+        });
         const float ri = rho[i];
         float kap;
         if (MODE == 0) {
@@ -497,7 +568,6 @@ __global__ void __launch_bounds__(kBlock) k_predict(
     }
     const double bs = block_sum(e);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-    if (last_block_done(counter)) finish_sums(partials, 1, 1, err_out, counter);
 }
 
 // Non-pressure accelerations (Algorithm 1, first lines): v* = v + dt g plus
@@ -516,9 +586,7 @@ __global__ void __launch_bounds__(kBlock) k_nonpressure(
     float ax = 0.f, ay = 0.f, az = 0.f;
     if (MODEL == 1 || MODEL == 2) {
         const float eps2 = 0.01f * kc.h * kc.h;
-        const uint32_t n = ncnt[i];
-        for (uint32_t k = 0; k < n; ++k) {
-            const uint32_t j = nlist[(int64_t)k * nf + i];
+        for_each_nbr(nlist, nf, i, ncnt[i], [&](uint32_t j) {
             const float4 xj = x[j];
             const float4 vj = v[j];
             const float mj = kc.m / rho[j];
@@ -532,7 +600,7 @@ __global__ void __launch_bounds__(kBlock) k_nonpressure(
                 const float c = mj * vx / (r2 + eps2) * grad_factor(r2, kc);
                 ax += c * dx; ay += c * dy; az += c * dz;
             }
-        }
+        });
     }
     float s = 0.f;
     if (MODEL == 1) s = visc;
@@ -565,7 +633,7 @@ __global__ void __launch_bounds__(kBlock) k_rigid_force(
     int64_t nf, const float4* __restrict__ x, const float* __restrict__ rho, const float* __restrict__ K,
     const float* __restrict__ Kv, const uint32_t* __restrict__ blist, const uint32_t* __restrict__ bcnt,
     const float4* __restrict__ xb, const float4* __restrict__ vb, Kern kc, int32_t nbody,
-    const double* __restrict__ com, double* __restrict__ partials, uint32_t* counter, double* out) {
+    const double* __restrict__ com, double* __restrict__ partials) {
     const int64_t i = particle_index();
     uint32_t nbk = 0;
     float4 xi = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -604,7 +672,6 @@ __global__ void __launch_bounds__(kBlock) k_rigid_force(
             }
         }
     }
-    if (last_block_done(counter)) finish_sums(partials, 6 * nbody, 6 * nbody, out, counter);
 }
 
 // Rigid boundary particles from the body pose: x_k = fl32(c + R r_k) and
@@ -652,9 +719,7 @@ __global__ void __launch_bounds__(kBlock) k_visc_matvec(
     const float4 pi = p[i];
     const float eps2 = 0.01f * kc.h * kc.h;
     float ax = 0.f, ay = 0.f, az = 0.f;
-    const uint32_t n = ncnt[i];
-    for (uint32_t k = 0; k < n; ++k) {
-        const uint32_t j = nlist[(int64_t)k * nf + i];
+    for_each_nbr(nlist, nf, i, ncnt[i], [&](uint32_t j) {
         const float4 xj = x[j];
         const float4 pj = p[j];
         const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
@@ -662,7 +727,7 @@ __global__ void __launch_bounds__(kBlock) k_visc_matvec(
         const float xv = (pi.x - pj.x) * dx + (pi.y - pj.y) * dy + (pi.z - pj.z) * dz;
         const float c = xv / (rho[j] * (r2 + eps2)) * grad_factor(r2, kc);
         ax += c * dx; ay += c * dy; az += c * dz;
-    }
+    });
     const float s = dt * 10.0f * mu * kc.m / rho[i];
     float4 o;
     o.x = pi.x - s * ax; o.y = pi.y - s * ay; o.z = pi.z - s * az; o.w = 0.f;
@@ -678,16 +743,14 @@ __global__ void __launch_bounds__(kBlock) k_visc_precond(
     const float4 xi = x[i];
     const float eps2 = 0.01f * kc.h * kc.h;
     float b00 = 0.f, b01 = 0.f, b02 = 0.f, b11 = 0.f, b12 = 0.f, b22 = 0.f;
-    const uint32_t n = ncnt[i];
-    for (uint32_t k = 0; k < n; ++k) {
-        const uint32_t j = nlist[(int64_t)k * nf + i];
+    for_each_nbr(nlist, nf, i, ncnt[i], [&](uint32_t j) {
         const float4 xj = x[j];
         const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
         const float c = grad_factor(r2, kc) / (rho[j] * (r2 + eps2));
         b00 += c * dx * dx; b01 += c * dx * dy; b02 += c * dx * dz;
         b11 += c * dy * dy; b12 += c * dy * dz; b22 += c * dz * dz;
-    }
+    });
     const float s = -dt * 10.0f * mu * kc.m / rho[i];
     const double a = 1.0 + (double)(s * b00), bq = (double)(s * b01), cq = (double)(s * b02);
     const double e = 1.0 + (double)(s * b11), f = (double)(s * b12), k2 = 1.0 + (double)(s * b22);
@@ -731,7 +794,7 @@ __global__ void k_axpy_residual(int64_t nf, const float4* __restrict__ b, const 
 }
 
 __global__ void k_dot(int64_t nf, const float4* __restrict__ a, const float4* __restrict__ b,
-                      double* __restrict__ partials, uint32_t* counter, double* out) {
+                      double* __restrict__ partials) {
     const int64_t i = particle_index();
     double s = 0.0;
     if (i < nf) {
@@ -740,13 +803,12 @@ __global__ void k_dot(int64_t nf, const float4* __restrict__ a, const float4* __
     }
     const double bs = block_sum(s);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-    if (last_block_done(counter)) finish_sums(partials, 1, 1, out, counter);
 }
 
 __global__ void k_cg_update(int64_t nf, float4* __restrict__ xv, float4* __restrict__ r, float4* __restrict__ z,
                             const float4* __restrict__ p, const float4* __restrict__ Ap,
                             const float* __restrict__ Pinv, const double* num, const double* den,
-                            double* __restrict__ partials, uint32_t* counter, double* out2) {
+                            double* __restrict__ partials) {
     const int64_t i = particle_index();
     const float a = (float)(*num / *den);
     double rz = 0.0, rr = 0.0;
@@ -768,7 +830,6 @@ __global__ void k_cg_update(int64_t nf, float4* __restrict__ xv, float4* __restr
         partials[2 * blockIdx.x] = s0;
         partials[2 * blockIdx.x + 1] = s1;
     }
-    if (last_block_done(counter)) finish_sums(partials, 2, 2, out2, counter);
 }
 
 __global__ void k_cg_direction(int64_t nf, float4* __restrict__ p, const float4* __restrict__ z,
@@ -868,11 +929,13 @@ hipError_t launch_gather_boundary(const uint32_t* src, int64_t n, const float4* 
 
 hipError_t launch_nbr_build(const float4* x, int64_t nf, const float4* xb, const uint32_t* start_f,
                             const uint32_t* start_b, Grid g, uint32_t* nlist, uint32_t* ncnt, int32_t capf,
-                            uint32_t* blist, uint32_t* bcnt, int32_t capb, uint32_t* flags, uint32_t* stats,
-                            hipStream_t s) {
-    if (nf <= 0) return hipSuccess;
-    LAUNCH(k_nbr_build, nf, x, nf, xb, start_f, start_b, g, nlist, ncnt, capf, blist, bcnt, capb, flags,
-           (unsigned long long*)stats);
+                            uint32_t* blist, uint32_t* bcnt, int32_t capb, uint32_t* flags,
+                            unsigned long long* partials, unsigned long long* stats, hipStream_t s) {
+    const uint32_t nblk = grid_blocks(nf);
+    hipLaunchKernelGGL(k_nbr_build, dim3(nblk), dim3(kBlock), 0, s, x, nf, xb, start_f, start_b, g, nlist, ncnt,
+                       capf, blist, bcnt, capb, flags, partials);
+    hipLaunchKernelGGL(k_finish_nstats, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, stats);
+    return hipGetLastError();
 }
 
 hipError_t launch_boundary_psi(float4* xb, int64_t nb, const uint32_t* start_b, Grid g, Kern kc, hipStream_t s) {
@@ -880,9 +943,11 @@ hipError_t launch_boundary_psi(float4* xb, int64_t nb, const uint32_t* start_b, 
     LAUNCH(k_boundary_psi, nb, xb, nb, start_b, g, kc);
 }
 
-hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* out_bits, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    LAUNCH(k_max_v2, n, v, n, out_bits);
+hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, uint32_t* out_bits, hipStream_t s) {
+    const uint32_t nblk = grid_blocks(n);
+    hipLaunchKernelGGL(k_max_v2, dim3(nblk), dim3(kBlock), 0, s, v, n, partials);
+    hipLaunchKernelGGL(k_finish_max_u32, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, out_bits);
+    return hipGetLastError();
 }
 
 hipError_t launch_density_alpha(int64_t nf, float4* x, const float4* v, const uint32_t* nlist, const uint32_t* ncnt,
@@ -904,12 +969,16 @@ hipError_t launch_pressure_update(int64_t nf, const float4* x, float4* v, const 
 hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, const float* rho, const float* alpha,
                           float* kappa, const uint32_t* nlist, const uint32_t* ncnt, const float4* xb,
                           const float4* vb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt,
-                          double* partials, uint32_t* counter, double* err_out, hipStream_t s) {
+                          double* partials, double* err_out, hipStream_t s) {
+    const uint32_t nblk = grid_blocks(nf);
     if (mode == 0)
-        LAUNCH(k_predict<0>, nf, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb, vb, blist, bcnt, kc, dt, partials,
-               counter, err_out);
-    LAUNCH(k_predict<1>, nf, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb, vb, blist, bcnt, kc, dt, partials,
-           counter, err_out);
+        hipLaunchKernelGGL(k_predict<0>, dim3(nblk), dim3(kBlock), 0, s, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb,
+                           vb, blist, bcnt, kc, dt, partials);
+    else
+        hipLaunchKernelGGL(k_predict<1>, dim3(nblk), dim3(kBlock), 0, s, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb,
+                           vb, blist, bcnt, kc, dt, partials);
+    hipLaunchKernelGGL(k_finish_f64, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, 1, err_out);
+    return hipGetLastError();
 }
 
 hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v, float4* vout, const float* rho,
@@ -939,9 +1008,13 @@ hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, hi
 
 hipError_t launch_rigid_force(int64_t nf, const float4* x, const float* rho, const float* K, const float* Kv,
                               const uint32_t* blist, const uint32_t* bcnt, const float4* xb, const float4* vb,
-                              Kern kc, int32_t nbody, const double* com, double* partials, uint32_t* counter,
-                              double* out, hipStream_t s) {
-    LAUNCH(k_rigid_force, nf, nf, x, rho, K, Kv, blist, bcnt, xb, vb, kc, nbody, com, partials, counter, out);
+                              Kern kc, int32_t nbody, const double* com, double* partials, double* out,
+                              hipStream_t s) {
+    const uint32_t nblk = grid_blocks(nf);
+    hipLaunchKernelGGL(k_rigid_force, dim3(nblk), dim3(kBlock), 0, s, nf, x, rho, K, Kv, blist, bcnt, xb, vb, kc,
+                       nbody, com, partials);
+    hipLaunchKernelGGL(k_finish_f64, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, 6 * nbody, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_rigid_boundary(int64_t nb, float4* xb, float4* vb, const int32_t* bid, const double* local,
@@ -963,15 +1036,20 @@ hipError_t launch_visc_matvec(int64_t nf, const float4* x, const float* rho, con
     LAUNCH(k_visc_matvec, nf, nf, x, rho, p, Mp, nlist, ncnt, kc, dt, mu);
 }
 
-hipError_t launch_dot(int64_t nf, const float4* a, const float4* b, double* partials, uint32_t* counter, double* out,
-                      hipStream_t s) {
-    LAUNCH(k_dot, nf, nf, a, b, partials, counter, out);
+hipError_t launch_dot(int64_t nf, const float4* a, const float4* b, double* partials, double* out, hipStream_t s) {
+    const uint32_t nblk = grid_blocks(nf);
+    hipLaunchKernelGGL(k_dot, dim3(nblk), dim3(kBlock), 0, s, nf, a, b, partials);
+    hipLaunchKernelGGL(k_finish_f64, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, 1, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_cg_update(int64_t nf, float4* xv, float4* r, float4* z, const float4* p, const float4* Ap,
-                            const float* Pinv, const double* num, const double* den, double* partials,
-                            uint32_t* counter, double* out2, hipStream_t s) {
-    LAUNCH(k_cg_update, nf, nf, xv, r, z, p, Ap, Pinv, num, den, partials, counter, out2);
+                            const float* Pinv, const double* num, const double* den, double* partials, double* out2,
+                            hipStream_t s) {
+    const uint32_t nblk = grid_blocks(nf);
+    hipLaunchKernelGGL(k_cg_update, dim3(nblk), dim3(kBlock), 0, s, nf, xv, r, z, p, Ap, Pinv, num, den, partials);
+    hipLaunchKernelGGL(k_finish_f64, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, 2, out2);
+    return hipGetLastError();
 }
 
 hipError_t launch_cg_direction(int64_t nf, float4* p, const float4* z, const double* rz_new, const double* rz_old,
