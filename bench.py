@@ -24,7 +24,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 # per-launch algorithmic bytes are computed inside the library (see the
 # design notes: own fields of every particle read/written once plus 4 B per
 # neighbour-list entry)
-PROFILED = ("pressure_update", "predict", "density_alpha", "xsph", "nbr_build", "sort", "integrate", "visc")
+PROFILED = ("pressure_update", "predict", "density_alpha", "xsph", "nbr_build", "sort", "integrate", "visc",
+            "warm_features", "mlp")
 
 
 def parse():
@@ -35,6 +36,8 @@ def parse():
     ap.add_argument("--config", default="c5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--arm", choices=("plain", "learned", "both"), default="both",
+                    help="warm start of the density solve: previous-step (plain) and/or the trained MLP")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -102,22 +105,40 @@ def main():
         print(f"[bench] calibration copy: {args.calib_copy_mb} MiB read + {args.calib_copy_mb} MiB written", flush=True)
         del a, b
     sc = scenes.scene(args.config)
-    sim = sph.Simulation(sc)
-    print(f"[bench] {sc.name}: {sc.n_fluid} fluid, {sc.n_boundary} boundary, warmup {args.warmup}", flush=True)
-    for _ in range(args.warmup):
-        sim.advance()
-    torch.cuda.synchronize()
-    sim.profile_enable(True)
-    iters = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st = sim.advance()
-        iters.append((st["iters_div"], st["iters_dens"], st["cg_iters"]))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = {k: sim.profile_read(k) for k in PROFILED}
-    sim.profile_enable(False)
-    print(f"[bench] timed {args.steps} steps in {wall:.3f} s", flush=True)
+    weights = os.path.join(ROOT, "paper_2403_11156_amd", "weights", "warm_start_mlp.f32")
+    arms = ["plain", "learned"] if args.arm == "both" else [args.arm]
+    if "learned" in arms and not os.path.exists(weights):
+        print("[bench] no trained warm-start weights; learned arm skipped", flush=True)
+        arms = [a for a in arms if a != "learned"] or ["plain"]
+    results = {}
+    for arm in arms:
+        sim = sph.Simulation(sc)
+        net = None
+        if arm == "learned":
+            import numpy as np
+            net = sph.MLP(np.fromfile(weights, dtype=np.float32))
+            sim.set_warm_start(2, net)
+        print(f"[bench] {sc.name} ({arm}): {sc.n_fluid} fluid, {sc.n_boundary} boundary, warmup {args.warmup}",
+              flush=True)
+        for _ in range(args.warmup):
+            sim.advance()
+        torch.cuda.synchronize()
+        sim.profile_enable(True)
+        iters = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            st = sim.advance()
+            iters.append((st["iters_div"], st["iters_dens"], st["cg_iters"], st["err_dens"], st["err_div"]))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = {k: sim.profile_read(k) for k in PROFILED}
+        sim.profile_enable(False)
+        sim.close()
+        if net is not None:
+            net.close()
+        print(f"[bench] {arm}: timed {args.steps} steps in {wall:.3f} s", flush=True)
+        results[arm] = (wall, prof, iters)
+    wall, prof, iters = results[arms[0]]
 
     ms_step = wall * 1e3 / args.steps
     value = sc.n_fluid * args.steps / wall
@@ -131,7 +152,7 @@ def main():
                    "share": v["ms"] / max(1e-9, wall * 1e3)} for k, v in prof.items() if v["launches"]}
     n = len(iters)
     line = {
-        "metric": "particle-steps/sec at eta=0.1% (DFSPH), plain previous-step warm start",
+        "metric": "particle-steps/sec at eta=0.1% (DFSPH), plain vs learned warm start",
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -145,15 +166,25 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc.name, "n_fluid": sc.n_fluid, "n_boundary": sc.n_boundary,
                    "n_rigid": len(sc.rigid), "r": sc.params["r"], "eta": sc.params["eta_density"],
-                   "warm_start": "previous", "parallelism": "none (1 GPU)"},
+                   "warm_start": arms[0], "parallelism": "none (1 GPU)"},
         "iters_per_step": {"div": sum(i[0] for i in iters) / n, "dens": sum(i[1] for i in iters) / n,
                            "cg": sum(i[2] for i in iters) / n},
+        "max_err_dens": max(i[3] for i in iters), "max_err_div": max(i[4] for i in iters),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config, dom),
                      "bytes_per_launch": d["bytes"] / max(d["launches"], 1)},
         "kernels": kernels,
     }
-    sim.close()
+    if "learned" in results:
+        lw, lprof, lit = results["learned"]
+        line["learned"] = {
+            "value": sc.n_fluid * args.steps / lw, "ms_per_step": lw * 1e3 / args.steps,
+            "iters_per_step": {"div": sum(i[0] for i in lit) / len(lit), "dens": sum(i[1] for i in lit) / len(lit)},
+            "max_err_dens": max(i[3] for i in lit),
+            "warm_start_overhead_us": {k: (1e3 * lprof[k]["ms"] / max(1, lprof[k]["launches"]))
+                                       for k in ("warm_features", "mlp") if lprof[k]["launches"]},
+        }
+        line["learned"]["speedup_vs_plain"] = line["learned"]["value"] / line["value"]
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", flush=True)
         line["cpu_baseline"] = cpu_baseline(args.config, args.cpu_steps)

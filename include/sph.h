@@ -255,6 +255,55 @@ int sph_set_forced_iters(sph_ctx *ctx, int32_t div, int32_t dens);
 int sph_profile_enable(sph_ctx *ctx, int32_t enable);
 int sph_profile_read(sph_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms, double *bytes);
 
+/* ---- learned warm start ---------------------------------------------------- */
+/*
+ * A per-particle MLP predicts the initial stiffness of the constant-density
+ * solve (Algorithm 2, "initialize p^l"); the solve still iterates to the same
+ * eta, so the prediction only changes how many iterations are needed.
+ * Network: 5 features -> 64 -> 64 -> 1, ReLU, bf16 weights and activations,
+ * FP32 accumulation on the matrix cores, FP32 biases.  Packed FP32 parameters
+ * (SPH_MLP_PARAMS floats): W1[64][5] b1[64] W2[64][64] b2[64] w3[64] b3
+ * in_shift[5] in_scale[5] out_scale; output y = out_scale * z with
+ * z = h2 . w3 + b3 and inputs normalised as (f - in_shift) * in_scale.
+ * Features of particle i, all dimensionless: (rho_i - rho0)/rho0,
+ * dt d*_i/rho0 (d* the density change rate of v*, after the non-pressure
+ * forces), n_i/26 (fluid + boundary neighbours), K_prev dt^2/(alpha_i rho0),
+ * alpha_i/alpha_ref (alpha_ref = 2.35376 (2r)^2/rho0).  Prediction y is the
+ * step's final density stiffness in the same units: K0 = max(0, y alpha rho0
+ * / dt^2).
+ */
+#define SPH_MLP_PARAMS 4620
+
+/* Create an MLP from host parameters (copied); its work runs on hip_stream. */
+int sph_mlp_create(const float *params, void *hip_stream, sph_mlp **out);
+void sph_mlp_destroy(sph_mlp *mlp);
+int sph_mlp_get_params(sph_mlp *mlp, float *params);
+int sph_mlp_set_params(sph_mlp *mlp, const float *params);
+/* y[i] = MLP(features[i]) for device arrays features[n][5], y[n]. */
+int sph_mlp_forward(sph_mlp *mlp, const float *features, float *y, int64_t n);
+/* Gradient of mean((z - t / out_scale)^2) over n samples (device features
+ * [n][5], targets [n]), copied to host grad[SPH_MLP_PARAMS] (zeros for the
+ * fixed normalisation entries); *loss gets the mean.  Deterministic. */
+int sph_mlp_grad(sph_mlp *mlp, const float *features, const float *targets, int64_t n, float *grad, double *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the same loss; the
+ * step counter lives in the MLP object.  *loss (may be NULL) gets the loss
+ * before the update. */
+int sph_mlp_train_step(sph_mlp *mlp, const float *features, const float *targets, int64_t n, float lr, double *loss);
+
+/* Select the warm start of the density solve: SPH_WARM_ZERO, _PREVIOUS, or
+ * _LEARNED with mlp (borrowed; must outlive its use).  Non-finite MLP
+ * parameters make the context fall back to PREVIOUS with
+ * stats.warm_fallback = 1. */
+int sph_set_warm_start(sph_ctx *ctx, int32_t mode, sph_mlp *mlp);
+
+/* Trace capture for training: every following sph_step appends n_fluid rows
+ * of features (device float [capacity][5]) and targets (device float
+ * [capacity], the final stiffness K dt^2 / (alpha rho0)) until capacity rows
+ * are used.  features == NULL stops capturing.  *rows (sph_trace_rows) is the
+ * number of rows written so far. */
+int sph_enable_trace(sph_ctx *ctx, float *features, float *targets, int64_t capacity);
+int sph_trace_rows(const sph_ctx *ctx, int64_t *rows);
+
 /* ---- errors -------------------------------------------------------------- */
 const char *sph_last_error(const sph_ctx *ctx);
 const char *sph_strerror(int status);

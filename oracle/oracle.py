@@ -52,7 +52,8 @@ class Rigid(C.Structure):
                 ("quat", C.c_double * 4), ("vel", C.c_double * 3), ("omega", C.c_double * 3)]
 
 
-MLP_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_double), C.c_void_p)
+MLP_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_double),
+                     C.c_void_p)
 
 
 class In(C.Structure):
@@ -74,6 +75,7 @@ class Out(C.Structure):
         ("S_kappa", C.c_void_p), ("S_accel", C.c_void_p), ("S_alpha", C.c_void_p),
         ("nf_count", C.c_void_p), ("nb_count", C.c_void_p),
         ("features", C.c_void_p), ("target", C.c_void_p),
+        ("S_features", C.c_void_p), ("S_target", C.c_void_p),
         ("xb_new", C.c_void_p), ("vb_new", C.c_void_p), ("rigid_new", C.c_void_p),
         ("force", C.c_void_p), ("torque", C.c_void_p),
         ("S_force", C.c_void_p), ("S_torque", C.c_void_p),
@@ -333,10 +335,14 @@ def step(state: State, forced_div: int = -1, forced_dens: int = -1, brute: Optio
     ci.brute_force = int(bool(brute))
     keep = []
     if mlp is not None:
-        def _cb(fp, n, yp, user):
+        def _cb(fp, sp, n, yp, user):
             F = np.ctypeslib.as_array(fp, shape=(n, 5)).copy()
-            y = np.asarray(mlp(F), np.float64).reshape(n)
-            np.ctypeslib.as_array(yp, shape=(n,))[:] = y
+            SF = np.ctypeslib.as_array(sp, shape=(n, 5)).copy()
+            res = mlp(F, SF)
+            y, err = (res if isinstance(res, tuple) else (res, np.zeros(n)))
+            out = np.ctypeslib.as_array(yp, shape=(2 * n,))
+            out[:n] = np.asarray(y, np.float64).reshape(n)
+            out[n:] = np.asarray(err, np.float64).reshape(n)
         cb = MLP_FN(_cb)
         keep.append(cb)
         ci.mlp = cb
@@ -359,6 +365,8 @@ def step(state: State, forced_div: int = -1, forced_dens: int = -1, brute: Optio
     if want_features:
         o["features"] = np.zeros((nf, 5))
         o["target"] = np.zeros(nf)
+        o["S_features"] = np.zeros((nf, 5))
+        o["S_target"] = np.zeros(nf)
     rnew = (Rigid * max(1, nr))()
     co = Out()
     for k, a in o.items():
@@ -367,6 +375,8 @@ def step(state: State, forced_div: int = -1, forced_dens: int = -1, brute: Optio
     if not want_features:
         co.features = None
         co.target = None
+        co.S_features = None
+        co.S_target = None
     rc = lib().or_step(C.byref(p), C.byref(ci), C.byref(co))
     if rc != 0:
         raise RuntimeError(f"or_step failed: {rc}")

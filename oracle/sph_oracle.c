@@ -64,8 +64,10 @@ typedef struct or_rigid {
     double mass, inertia[3], com[3], quat[4], vel[3], omega[3];
 } or_rigid;
 
-/* learned warm start: out[i] = MLP(features[i*5 .. i*5+4]) */
-typedef void (*or_mlp_fn)(const double *features, int64_t n, double *out, void *user);
+/* learned warm start: out[i] = MLP(features[i*5 .. i*5+4]) and out[n + i] the
+ * error scale of that prediction (in the units of the S fields) given the
+ * features' error scales S_features[i*5 ..] */
+typedef void (*or_mlp_fn)(const double *features, const double *S_features, int64_t n, double *out, void *user);
 
 typedef struct or_in {
     int64_t nf, nb;
@@ -87,6 +89,7 @@ typedef struct or_out {
     int32_t *nf_count, *nb_count;
     double *features;          /* [nf][5] learned-warm-start inputs (may be NULL) */
     double *target;            /* [nf] learned-warm-start target (may be NULL) */
+    double *S_features, *S_target; /* their error scales (with features/target) */
     float *xb_new, *vb_new;    /* [nb][3] boundary state for the next step */
     or_rigid *rigid_new;       /* [n_rigid] */
     double *force, *torque;    /* [n_rigid][3] */
@@ -848,9 +851,10 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
      *    max(0, y alpha rho0 / dt^2) of the step's final stiffness, y = MLP of
      *    five dimensionless features; the target is K_final dt^2 / (alpha rho0). */
     const double alpha_ref = 2.35376 * (2.0 * p->r) * (2.0 * p->r) / p->rho0;
-    double *feat = NULL;
+    double *feat = NULL, *Sfeat = NULL;
     if (p->warm_start == 2 || out->features) {
         feat = malloc(sizeof(double) * 5 * (nf ? nf : 1));
+        Sfeat = malloc(sizeof(double) * 5 * (nf ? nf : 1));
         divergence(w, w->v, w->Sv, d, Sd);   /* divergence of v* */
         for (int64_t i = 0; i < nf; ++i) {
             int64_t n_i = (w->ff.start[i + 1] - w->ff.start[i]) + (w->fb.start[i + 1] - w->fb.start[i]);
@@ -860,20 +864,29 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
             feat[5 * i + 2] = (double)n_i / 26.0;
             feat[5 * i + 3] = a > 0.0 ? (double)in->K[i] * dt * dt / (a * p->rho0) : 0.0;
             feat[5 * i + 4] = a / alpha_ref;
+            {
+                double *S = Sfeat + 5 * i;
+                S[0] = (w->rho[i] + p->rho0) / p->rho0;
+                S[1] = dt * Sd[i] / p->rho0;
+                S[2] = 0.0;
+                S[3] = a > 0.0 ? fabs(feat[5 * i + 3]) * (1.0 + w->Salpha[i] / a) : 0.0;
+                S[4] = w->Salpha[i] / alpha_ref;
+            }
         }
         if (out->features) memcpy(out->features, feat, sizeof(double) * 5 * nf);
+        if (out->S_features) memcpy(out->S_features, Sfeat, sizeof(double) * 5 * nf);
     }
     for (int64_t i = 0; i < nf; ++i) {
         K[i] = p->warm_start == 0 ? 0.0 : p->warm_factor * (double)in->K[i];
         SK[i] = fabs(K[i]);
     }
     if (p->warm_start == 2) {
-        double *y = malloc(s1);
-        in->mlp(feat, nf, y, in->mlp_user);
+        double *y = malloc(2 * s1);
+        in->mlp(feat, Sfeat, nf, y, in->mlp_user);
         for (int64_t i = 0; i < nf; ++i) {
             double k0 = y[i] * w->alpha[i] * p->rho0 / (dt * dt);
             K[i] = k0 > 0.0 ? k0 : 0.0;
-            SK[i] = fabs(k0);
+            SK[i] = fabs(k0) + (y[nf + i] + fabs(y[i]) * w->Salpha[i] / w->alpha[i]) * w->alpha[i] * p->rho0 / (dt * dt);
         }
         free(y);
     }
@@ -977,6 +990,8 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
         if (out->target) {
             double a = w->alpha[i];
             out->target[i] = a > 0.0 ? K[i] * dt * dt / (a * p->rho0) : 0.0;
+            if (out->S_target)
+                out->S_target[i] = a > 0.0 ? (SK[i] + fabs(K[i]) * w->Salpha[i] / a) * dt * dt / (a * p->rho0) : 0.0;
         }
     }
     if (out->psi) memcpy(out->psi, w->psi, sizeof(double) * nb);
@@ -1057,6 +1072,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     }
 
     free(feat);
+    free(Sfeat);
     free(rs); free(Srs); free(vs); free(Svs);
     free(v_in); free(d); free(Sd); free(kap); free(Skap); free(Kv); free(SKv); free(K); free(SK);
     free(kappa_last); free(Skappa_last);

@@ -93,10 +93,26 @@ struct sph_ctx {
     double nbr_sum = 0.0, nbr_sum_f = 0.0;
     std::string err;
 
+    // learned warm start and trace capture
+    int32_t warm_mode = SPH_WARM_PREVIOUS;
+    sph_mlp *mlp = nullptr;
+    bool warm_fallback = false;
+    float *feat = nullptr, *ybuf = nullptr;
+    float *trace_feat = nullptr, *trace_target = nullptr;
+    int64_t trace_cap = 0, trace_rows = 0;
+
     bool prof = false;
     std::vector<ProfEvent> prof_pending;
     std::vector<hipEvent_t> event_pool;
     std::map<std::string, ProfTotal> prof_total;
+};
+
+struct sph_mlp {
+    hipStream_t stream = nullptr;
+    float *P = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *part = nullptr;
+    double *loss_part = nullptr, *loss = nullptr;
+    int64_t step = 0;
+    bool finite = true;
 };
 
 namespace {
@@ -487,8 +503,10 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     } else {
         dt = (float)c->P.dt_max;
     }
-    const bool warm = c->P.warm_start != SPH_WARM_ZERO;
+    const bool warm = c->warm_mode != SPH_WARM_ZERO;
     const float wf = warm ? (float)c->P.warm_factor : 0.0f;
+    const bool learned = c->warm_mode == SPH_WARM_LEARNED && c->mlp != nullptr;
+    const bool tracing = c->trace_feat != nullptr && c->trace_rows + nf <= c->trace_cap;
 
     // 2. density, alpha; divergence warm-start set-up
     {
@@ -510,17 +528,39 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     int32_t cg_it = 0;
     double cg_res = 0.0;
     const float gx = (float)c->P.gravity[0], gy = (float)c->P.gravity[1], gz = (float)c->P.gravity[2];
+    const bool setup_in_pass = !(learned || tracing);
     if (c->P.visc_model == SPH_VISC_IMPLICIT) {
         rc = implicit_viscosity(c, dt, &cg_it, &cg_res);
         if (rc) return rc;
-        HIP_TRY(c, sph::launch_warm_setup(nf, c->x, c->rho, c->K, c->kappa, wf, s));
+        if (setup_in_pass) HIP_TRY(c, sph::launch_warm_setup(nf, c->x, c->rho, c->K, c->kappa, wf, s));
     } else {
         ProfScope ps(c, "xsph", 72.0 * nf + fluid_list_bytes(c));
         HIP_TRY(c, sph::launch_nonpressure(c->P.visc_model, nf, c->x, c->v, c->v2, c->rho, c->nlist, c->ncnt, c->kc,
-                                           dt, gx, gy, gz, (float)c->P.visc, c->K, c->kappa, wf, s));
+                                           dt, gx, gy, gz, (float)c->P.visc, c->K, c->kappa, wf, setup_in_pass, s));
         std::swap(c->v, c->v2);
     }
-    // 5. warm start of the density solve
+    // 5. warm start of the density solve: the previous stiffness, or the MLP's
+    //    prediction from per-particle features of v* (features also feed the
+    //    training trace)
+    if (!setup_in_pass) {
+        const float alpha_ref = (float)(2.35376 * 4.0 * c->P.r * c->P.r / c->P.rho0);
+        float *feat = tracing ? c->trace_feat + 5 * c->trace_rows : c->feat;
+        {
+            ProfScope ps(c, "warm_features", 56.0 * nf + list_bytes(c));
+            HIP_TRY(c, sph::launch_warm_features(nf, c->x, c->v, c->rho, c->alpha, c->K, c->nlist, c->ncnt, c->xb, c->vb,
+                                                 c->blist, c->bcnt, c->kc, dt, alpha_ref, feat, s));
+        }
+        if (learned) {
+            {
+                ProfScope ps(c, "mlp", 24.0 * nf);
+                HIP_TRY(c, sph::launch_mlp_forward(c->mlp->P, feat, nf, c->ybuf, s));
+            }
+            HIP_TRY(c, sph::launch_warm_learned(nf, c->x, c->rho, c->alpha, c->ybuf, c->K, c->kappa, dt,
+                                                (float)c->P.rho0, s));
+        } else {
+            HIP_TRY(c, sph::launch_warm_setup(nf, c->x, c->rho, c->K, c->kappa, wf, s));
+        }
+    }
     if (warm) {
         rc = pressure_pass(c, c->K, nullptr, dt);
         if (rc) return rc;
@@ -530,6 +570,10 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     rc = jacobi_solve(c, 1, dt, c->K, c->kappa_last, c->forced_dens, c->P.eta_density, &id, &ed);
     if (rc) return rc;
 
+    if (tracing) {
+        HIP_TRY(c, sph::launch_trace_target(nf, c->alpha, c->K, dt, (float)c->P.rho0, c->trace_target + c->trace_rows, s));
+        c->trace_rows += nf;
+    }
     // 7. rigid bodies: Eq. 14 reaction, FP64 Newton-Euler, new boundary pose
     if (c->nr > 0) {
         HIP_TRY(c, sph::launch_rigid_force(nf, c->x, c->rho, c->K, c->Kv, c->blist, c->bcnt, c->xb, c->vb, c->kc,
@@ -569,7 +613,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         st->nbr_min = (int32_t)(c->h_stats[0] == ~0ull ? 0 : c->h_stats[0]);
         st->nbr_max = (int32_t)c->h_stats[1];
         st->nbr_mean = c->nf ? (double)c->h_stats[2] / (double)c->nf : 0.0;
-        st->warm_fallback = 0;
+        st->warm_fallback = c->warm_fallback ? 1 : 0;
         st->step_index = c->step_index;
     }
     if (!std::isfinite(ed) || !std::isfinite(ev)) return fail(c, SPH_ERR_NUMERIC, "non-finite solver error");
@@ -643,6 +687,7 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     sph_ctx *c = new (std::nothrow) sph_ctx();
     if (!c) return fail(nullptr, SPH_ERR_OOM, "host allocation failed");
     c->P = *p;
+    c->warm_mode = p->warm_start == SPH_WARM_LEARNED ? SPH_WARM_PREVIOUS : p->warm_start;
     c->stream = (hipStream_t)hip_stream;
     c->nf = sc->n_fluid;
     c->nb = sc->n_boundary;
@@ -700,6 +745,7 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     ALLOC(c->red_part, nred * 6 * std::max(1, c->nr) + 16); ALLOC(c->scal, 16); ALLOC(c->rigid_out, 6 * std::max(1, c->nr));
     ALLOC(c->flags, 4); ALLOC(c->vmax_bits, 4); ALLOC(c->nstats, 4);
     ALLOC(c->nstat_part, 4 * nred);
+    ALLOC(c->feat, 5 * nf); ALLOC(c->ybuf, nf);
     if (p->visc_model == SPH_VISC_IMPLICIT) {
         ALLOC(c->Pinv, 9 * nf); ALLOC(c->cg_b, nf); ALLOC(c->cg_r, nf); ALLOC(c->cg_z, nf); ALLOC(c->cg_p, nf);
         ALLOC(c->cg_Ap, nf);
@@ -1026,6 +1072,148 @@ int sph_read_neighbors(sph_ctx *c, const sph_nbr_view *d) {
     };
     if ((rc = csr(c->nlist, c->capf, cnt, d->counts_f, d->lists_f, d->cap_f))) return rc;
     if ((rc = csr(c->blist, c->capb, bcnt, d->counts_b, d->lists_b, d->cap_b))) return rc;
+    return SPH_OK;
+}
+
+int sph_mlp_create(const float *params, void *hip_stream, sph_mlp **out) {
+    g_create_error.clear();
+    if (!out || !params) return fail(nullptr, SPH_ERR_INVALID, "params or out is NULL");
+    *out = nullptr;
+    sph_mlp *m = new (std::nothrow) sph_mlp();
+    if (!m) return fail(nullptr, SPH_ERR_OOM, "host allocation failed");
+    m->stream = (hipStream_t)hip_stream;
+    const int np = sph::mlp_param_count(), nb = sph::mlp_grad_blocks();
+    bool ok = hipMalloc(&m->P, sizeof(float) * np) == hipSuccess && hipMalloc(&m->m, sizeof(float) * np) == hipSuccess &&
+              hipMalloc(&m->v, sizeof(float) * np) == hipSuccess && hipMalloc(&m->grad, sizeof(float) * np) == hipSuccess &&
+              hipMalloc(&m->part, sizeof(float) * (size_t)np * nb) == hipSuccess &&
+              hipMalloc(&m->loss_part, sizeof(double) * nb) == hipSuccess &&
+              hipMalloc(&m->loss, sizeof(double) * 2) == hipSuccess;
+    if (!ok) {
+        sph_mlp_destroy(m);
+        return fail(nullptr, SPH_ERR_OOM, "MLP device allocation failed");
+    }
+    std::vector<float> zero(np, 0.0f);
+    ok = hipMemcpyAsync(m->m, zero.data(), sizeof(float) * np, hipMemcpyHostToDevice, m->stream) == hipSuccess &&
+         hipMemcpyAsync(m->v, zero.data(), sizeof(float) * np, hipMemcpyHostToDevice, m->stream) == hipSuccess &&
+         hipStreamSynchronize(m->stream) == hipSuccess;
+    if (!ok || sph_mlp_set_params(m, params) != SPH_OK) {
+        sph_mlp_destroy(m);
+        return fail(nullptr, SPH_ERR_DEVICE, "MLP upload failed");
+    }
+    *out = m;
+    return SPH_OK;
+}
+
+void sph_mlp_destroy(sph_mlp *m) {
+    if (!m) return;
+    (void)hipStreamSynchronize(m->stream);
+    for (void *p : {(void *)m->P, (void *)m->m, (void *)m->v, (void *)m->grad, (void *)m->part, (void *)m->loss_part,
+                    (void *)m->loss})
+        if (p) (void)hipFree(p);
+    delete m;
+}
+
+int sph_mlp_set_params(sph_mlp *m, const float *params) {
+    if (!m || !params) return SPH_ERR_INVALID;
+    const int np = sph::mlp_param_count();
+    m->finite = true;
+    for (int i = 0; i < np; ++i)
+        if (!std::isfinite(params[i])) m->finite = false;
+    if (hipMemcpyAsync(m->P, params, sizeof(float) * np, hipMemcpyHostToDevice, m->stream) != hipSuccess ||
+        hipStreamSynchronize(m->stream) != hipSuccess)
+        return SPH_ERR_DEVICE;
+    return SPH_OK;
+}
+
+int sph_mlp_get_params(sph_mlp *m, float *params) {
+    if (!m || !params) return SPH_ERR_INVALID;
+    if (hipMemcpyAsync(params, m->P, sizeof(float) * sph::mlp_param_count(), hipMemcpyDeviceToHost, m->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(m->stream) != hipSuccess)
+        return SPH_ERR_DEVICE;
+    return SPH_OK;
+}
+
+int sph_mlp_forward(sph_mlp *m, const float *features, float *y, int64_t n) {
+    if (!m || n < 0 || (n > 0 && (!features || !y))) return SPH_ERR_INVALID;
+    if (sph::launch_mlp_forward(m->P, features, n, y, m->stream) != hipSuccess) return SPH_ERR_DEVICE;
+    return hipStreamSynchronize(m->stream) == hipSuccess ? SPH_OK : SPH_ERR_DEVICE;
+}
+
+namespace {
+int mlp_grad_dev(sph_mlp *m, const float *features, const float *targets, int64_t n) {
+    if (sph::launch_mlp_grad(m->P, features, targets, n, m->part, m->loss_part, m->grad, m->loss, m->stream) !=
+        hipSuccess)
+        return SPH_ERR_DEVICE;
+    return SPH_OK;
+}
+}  // namespace
+
+int sph_mlp_grad(sph_mlp *m, const float *features, const float *targets, int64_t n, float *grad, double *loss) {
+    if (!m || n <= 0 || !features || !targets) return SPH_ERR_INVALID;
+    int rc = mlp_grad_dev(m, features, targets, n);
+    if (rc) return rc;
+    double l = 0.0;
+    if ((grad && hipMemcpyAsync(grad, m->grad, sizeof(float) * sph::mlp_param_count(), hipMemcpyDeviceToHost,
+                                m->stream) != hipSuccess) ||
+        hipMemcpyAsync(&l, m->loss, sizeof(double), hipMemcpyDeviceToHost, m->stream) != hipSuccess ||
+        hipStreamSynchronize(m->stream) != hipSuccess)
+        return SPH_ERR_DEVICE;
+    if (loss) *loss = l / (double)n;
+    return SPH_OK;
+}
+
+int sph_mlp_train_step(sph_mlp *m, const float *features, const float *targets, int64_t n, float lr, double *loss) {
+    if (!m || n <= 0 || !features || !targets || !(lr > 0)) return SPH_ERR_INVALID;
+    int rc = mlp_grad_dev(m, features, targets, n);
+    if (rc) return rc;
+    m->step += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 - std::pow(b1, (double)m->step)), c2 = (float)(1.0 - std::pow(b2, (double)m->step));
+    if (sph::launch_mlp_adam(m->P, m->grad, m->m, m->v, lr, (float)b1, (float)b2, 1e-8f, c1, c2, m->stream) !=
+        hipSuccess)
+        return SPH_ERR_DEVICE;
+    if (loss) {
+        double l = 0.0;
+        if (hipMemcpyAsync(&l, m->loss, sizeof(double), hipMemcpyDeviceToHost, m->stream) != hipSuccess ||
+            hipStreamSynchronize(m->stream) != hipSuccess)
+            return SPH_ERR_DEVICE;
+        *loss = l / (double)n;
+    }
+    return SPH_OK;
+}
+
+int sph_set_warm_start(sph_ctx *c, int32_t mode, sph_mlp *mlp) {
+    if (!c || mode < SPH_WARM_ZERO || mode > SPH_WARM_LEARNED) return SPH_ERR_INVALID;
+    c->warm_fallback = false;
+    if (mode == SPH_WARM_LEARNED) {
+        if (!mlp) return fail(c, SPH_ERR_INVALID, "learned warm start needs an MLP");
+        if (!mlp->finite) {
+            c->warm_fallback = true;
+            c->warm_mode = SPH_WARM_PREVIOUS;
+            c->mlp = nullptr;
+            return SPH_OK;
+        }
+        c->mlp = mlp;
+    } else {
+        c->mlp = nullptr;
+    }
+    c->warm_mode = mode;
+    return SPH_OK;
+}
+
+int sph_enable_trace(sph_ctx *c, float *features, float *targets, int64_t capacity) {
+    if (!c || capacity < 0 || (features && !targets)) return SPH_ERR_INVALID;
+    c->trace_feat = features;
+    c->trace_target = targets;
+    c->trace_cap = features ? capacity : 0;
+    c->trace_rows = 0;
+    return SPH_OK;
+}
+
+int sph_trace_rows(const sph_ctx *c, int64_t *rows) {
+    if (!c || !rows) return SPH_ERR_INVALID;
+    *rows = c->trace_rows;
     return SPH_OK;
 }
 

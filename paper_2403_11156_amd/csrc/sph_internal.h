@@ -85,7 +85,8 @@ hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, cons
 // (kappa = warm_factor K, K = 0, x.w = kappa / rho).
 hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v, float4* vout, const float* rho,
                               const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float gx, float gy,
-                              float gz, float visc, float* K, float* kappa, float warm_factor, hipStream_t s);
+                              float gz, float visc, float* K, float* kappa, float warm_factor, bool setup_warm,
+                              hipStream_t s);
 hipError_t launch_warm_setup(int64_t nf, float4* x, const float* rho, float* K, float* kappa, float warm_factor,
                              hipStream_t s);
 hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, hipStream_t s);
@@ -117,6 +118,25 @@ hipError_t launch_apply_precond(int64_t nf, const float* Pinv, const float4* r, 
 hipError_t launch_axpy_residual(int64_t nf, const float4* b, const float4* Mx, float4* r, hipStream_t s);
 hipError_t launch_gravity(int64_t nf, const float4* v, float4* out, float dt, float gx, float gy, float gz,
                           hipStream_t s);
+
+// learned warm start: the features pass, the learned stiffness, trace targets
+hipError_t launch_warm_features(int64_t nf, const float4* x, const float4* v, const float* rho, const float* alpha,
+                                const float* K, const uint32_t* nlist, const uint32_t* ncnt, const float4* xb,
+                                const float4* vb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt,
+                                float alpha_ref, float* feat, hipStream_t s);
+hipError_t launch_warm_learned(int64_t nf, float4* x, const float* rho, const float* alpha, const float* y, float* K,
+                               float* kappa, float dt, float rho0, hipStream_t s);
+hipError_t launch_trace_target(int64_t nf, const float* alpha, const float* K, float dt, float rho0, float* target,
+                               hipStream_t s);
+
+// the MLP (sph_mlp.hip)
+int mlp_param_count();
+int mlp_grad_blocks();
+hipError_t launch_mlp_forward(const float* P, const float* feat, int64_t n, float* y, hipStream_t s);
+hipError_t launch_mlp_grad(const float* P, const float* feat, const float* target, int64_t n, float* part,
+                           double* loss_part, float* grad, double* loss_sum, hipStream_t s);
+hipError_t launch_mlp_adam(float* P, const float* grad, float* m, float* v, float lr, float beta1, float beta2,
+                           float eps, float c1, float c2, hipStream_t s);
 
 // workgroups of a per-particle launch over n (a multiple of 8)
 uint32_t reduction_blocks(int64_t n);

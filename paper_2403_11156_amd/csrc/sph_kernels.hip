@@ -578,7 +578,7 @@ __global__ void __launch_bounds__(kBlock) k_nonpressure(
     int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, float4* __restrict__ vout,
     const float* __restrict__ rho, const uint32_t* __restrict__ nlist, const uint32_t* __restrict__ ncnt,
     Kern kc, float dt, float gx, float gy, float gz, float visc, float* __restrict__ K, float* __restrict__ kappa,
-    float warm_factor) {
+    float warm_factor, bool setup_warm) {
     const int64_t i = particle_index();
     if (i >= nf) return;
     const float4 xi = x[i];
@@ -611,10 +611,72 @@ __global__ void __launch_bounds__(kBlock) k_nonpressure(
     o.z = vi.z + dt * gz + s * az;
     o.w = 0.f;
     vout[i] = o;
-    const float k0 = warm_factor * K[i];
+    if (setup_warm) {
+        const float k0 = warm_factor * K[i];
+        kappa[i] = k0;
+        K[i] = 0.0f;
+        x[i].w = k0 / rho[i];
+    }
+}
+
+// Learned warm start, features of each particle at the start of the density
+// solve: (rho - rho0)/rho0, dt d*/rho0 with d* the density change rate of v*,
+// (n_f + n_b)/26, K_prev dt^2/(alpha rho0), alpha/alpha_ref.
+__global__ void __launch_bounds__(kBlock) k_warm_features(
+    int64_t nf, const float4* __restrict__ x, const float4* __restrict__ v, const float* __restrict__ rho,
+    const float* __restrict__ alpha, const float* __restrict__ K, const uint32_t* __restrict__ nlist,
+    const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const float4* __restrict__ vb,
+    const uint32_t* __restrict__ blist, const uint32_t* __restrict__ bcnt, Kern kc, float dt, float alpha_ref,
+    float* __restrict__ feat) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float4 xi = x[i];
+    const float4 vi = v[i];
+    float d = 0.f;
+    const uint32_t nfc = ncnt[i], nbc = bcnt[i];
+    for_each_nbr(nlist, nf, i, nfc, [&](uint32_t j) {
+        const float4 xj = x[j];
+        const float4 vj = v[j];
+        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        d += grad_factor(r2, kc) * ((vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz);
+    });
+    d *= kc.m;
+    for_each_nbr(blist, nf, i, nbc, [&](uint32_t kk) {
+        const float4 xk = xb[kk];
+        const float4 vk = vb[kk];
+        const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        d += xk.w * grad_factor(r2, kc) * ((vi.x - vk.x) * dx + (vi.y - vk.y) * dy + (vi.z - vk.z) * dz);
+    });
+    const float a = alpha[i];
+    float* f = feat + 5 * i;
+    f[0] = (rho[i] - kc.rho0) / kc.rho0;
+    f[1] = dt * d / kc.rho0;
+    f[2] = (float)(nfc + nbc) / 26.0f;
+    f[3] = a > 0.0f ? K[i] * dt * dt / (a * kc.rho0) : 0.0f;
+    f[4] = a / alpha_ref;
+}
+
+// K0 = max(0, y alpha rho0 / dt^2) from the MLP output y.
+__global__ void k_warm_learned(int64_t nf, float4* __restrict__ x, const float* __restrict__ rho,
+                               const float* __restrict__ alpha, const float* __restrict__ y, float* __restrict__ K,
+                               float* __restrict__ kappa, float dt, float rho0) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float k0 = fmaxf(y[i] * alpha[i] * rho0 / (dt * dt), 0.0f);
     kappa[i] = k0;
     K[i] = 0.0f;
     x[i].w = k0 / rho[i];
+}
+
+// training target: the step's final density stiffness, K dt^2 / (alpha rho0)
+__global__ void k_trace_target(int64_t nf, const float* __restrict__ alpha, const float* __restrict__ K, float dt,
+                               float rho0, float* __restrict__ target) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float a = alpha[i];
+    target[i] = a > 0.0f ? K[i] * dt * dt / (a * rho0) : 0.0f;
 }
 
 __global__ void k_integrate(int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, float dt) {
@@ -983,16 +1045,37 @@ hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, cons
 
 hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v, float4* vout, const float* rho,
                               const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float gx, float gy,
-                              float gz, float visc, float* K, float* kappa, float warm_factor, hipStream_t s) {
+                              float gz, float visc, float* K, float* kappa, float warm_factor, bool setup_warm,
+                              hipStream_t s) {
     if (nf <= 0) return hipSuccess;
     if (model == 1)
         LAUNCH(k_nonpressure<1>, nf, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa,
-               warm_factor);
+               warm_factor, setup_warm);
     if (model == 2)
         LAUNCH(k_nonpressure<2>, nf, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa,
-               warm_factor);
+               warm_factor, setup_warm);
     LAUNCH(k_nonpressure<0>, nf, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa,
-           warm_factor);
+           warm_factor, setup_warm);
+}
+
+hipError_t launch_warm_features(int64_t nf, const float4* x, const float4* v, const float* rho, const float* alpha,
+                                const float* K, const uint32_t* nlist, const uint32_t* ncnt, const float4* xb,
+                                const float4* vb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt,
+                                float alpha_ref, float* feat, hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_warm_features, nf, nf, x, v, rho, alpha, K, nlist, ncnt, xb, vb, blist, bcnt, kc, dt, alpha_ref, feat);
+}
+
+hipError_t launch_warm_learned(int64_t nf, float4* x, const float* rho, const float* alpha, const float* y, float* K,
+                               float* kappa, float dt, float rho0, hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_warm_learned, nf, nf, x, rho, alpha, y, K, kappa, dt, rho0);
+}
+
+hipError_t launch_trace_target(int64_t nf, const float* alpha, const float* K, float dt, float rho0, float* target,
+                               hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_trace_target, nf, nf, alpha, K, dt, rho0, target);
 }
 
 hipError_t launch_warm_setup(int64_t nf, float4* x, const float* rho, float* K, float* kappa, float warm_factor,

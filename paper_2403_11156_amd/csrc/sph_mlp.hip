@@ -1,0 +1,372 @@
+// sph_mlp.hip -- the learned warm-start MLP on gfx950 matrix cores.
+//
+// Network per particle: five dimensionless features -> 64 -> 64 -> 1, ReLU;
+// bf16 weights and activations (round to nearest even), FP32 accumulation,
+// FP32 biases.  Parameter vector (FP32 masters, 4620 floats):
+//   W1[64][5] b1[64] W2[64][64] b2[64] w3[64] b3 in_shift[5] in_scale[5] out_scale
+//
+// A wave processes 32 samples per tile with v_mfma_f32_32x32x8_bf16.  Every
+// layer is computed transposed (hidden units as rows, samples as columns):
+// then the D registers of one layer, lane = sample + 32*half, register r =
+// row 8*(r/4) + 4*half + r%4, are exactly the B operand of the next layer's
+// 8-row k-chunks (registers 4c..4c+3 of chunk c), so activations never leave
+// registers in the forward pass.  Training adds the backward product through
+// W2^T (same trick), the weight-gradient GEMM dZ2^T H1 over the samples of a
+// tile (operands transposed through LDS), and FP32 row sums for the small
+// gradients; per-workgroup partials are summed in a fixed order, no float
+// atomics.
+#include <hip/hip_runtime.h>
+
+#include "sph_internal.h"
+
+namespace sph {
+namespace {
+
+constexpr int H = 64;
+constexpr int NF = 5;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + H * NF, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 + H * H, OFF_W3 = OFF_B2 + H,
+              OFF_B3 = OFF_W3 + H, OFF_SHIFT = OFF_B3 + 1, OFF_SCALE = OFF_SHIFT + NF, OFF_OUT = OFF_SCALE + NF,
+              NPARAM = OFF_OUT + 1;
+static_assert(NPARAM == 4620, "parameter layout");
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ f32x16 mfma(bf16x4 a, bf16x4 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// D-layout row of register r in a 32-row tile for a lane in half h
+__device__ __forceinline__ int drow(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+
+__device__ __forceinline__ bf16x4 pack4(const uint16_t* p) {
+    bf16x4 v;
+    v[0] = (short)p[0]; v[1] = (short)p[1]; v[2] = (short)p[2]; v[3] = (short)p[3];
+    return v;
+}
+
+// Weights as bf16 in LDS: W1b[64][8] (k padded with zeros), W2b[64][64], W2t[64][64] (transposed)
+struct WeightsLDS {
+    uint16_t W1b[H * 8];
+    uint16_t W2b[H * H];
+    uint16_t W2t[H * H];
+    float b1[H], b2[H], w3[H];     // w3 as the bf16-rounded value in FP32
+    float shift[8], scale[8];
+    float b3, out_scale;
+};
+
+__device__ void load_weights(WeightsLDS& W, const float* __restrict__ P, bool transposed) {
+    for (int t = threadIdx.x; t < H * 8; t += blockDim.x) {
+        const int j = t >> 3, k = t & 7;
+        W.W1b[t] = k < NF ? to_bf16(P[OFF_W1 + j * NF + k]) : (uint16_t)0;
+    }
+    for (int t = threadIdx.x; t < H * H; t += blockDim.x) {
+        const uint16_t b = to_bf16(P[OFF_W2 + t]);
+        W.W2b[t] = b;
+        if (transposed) W.W2t[(t % H) * H + t / H] = b;
+    }
+    for (int t = threadIdx.x; t < H; t += blockDim.x) {
+        W.b1[t] = P[OFF_B1 + t];
+        W.b2[t] = P[OFF_B2 + t];
+        W.w3[t] = from_bf16(to_bf16(P[OFF_W3 + t]));
+    }
+    if (threadIdx.x < 8) {
+        W.shift[threadIdx.x] = threadIdx.x < NF ? P[OFF_SHIFT + threadIdx.x] : 0.f;
+        W.scale[threadIdx.x] = threadIdx.x < NF ? P[OFF_SCALE + threadIdx.x] : 0.f;
+    }
+    if (threadIdx.x == 0) {
+        W.b3 = P[OFF_B3];
+        W.out_scale = P[OFF_OUT];
+    }
+    __syncthreads();
+}
+
+// Forward of one 32-sample tile in one wave.  lane = p + 32 h.
+struct Fwd {
+    f32x16 z1[2], z2[2];   // pre-activations, transposed tiles (rows = hidden units)
+    bf16x4 h1[2][4];       // bf16(relu(z1)) as B operands, chunk c of tile t
+    float h2[2][16];       // bf16(relu(z2)) as FP32
+    float z;               // output before out_scale (every lane, for its sample p)
+    bf16x4 xb;             // normalised features as the layer-1 B operand
+};
+
+__device__ __forceinline__ void forward_tile(const WeightsLDS& W, const float* __restrict__ feat, int64_t n,
+                                             int64_t base, Fwd& f) {
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+    const int64_t s = base + p;
+    // features 4h..4h+3 of sample p, normalised in FP32 then rounded to bf16
+    uint16_t xv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int k = 4 * h + c;
+        float v = 0.f;
+        if (k < NF && s < n) {
+#pragma clang fp contract(off)
+            v = (feat[s * NF + k] - W.shift[k]) * W.scale[k];
+        }
+        xv[c] = to_bf16(v);
+    }
+    f.xb = pack4(xv);
+    // layer 1: z1^T[j][p] = sum_k W1[j][k] x[p][k] + b1[j]
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        f32x16 c;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) c[r] = W.b1[32 * t + drow(r, h)];
+        const bf16x4 a = pack4(&W.W1b[(32 * t + p) * 8 + 4 * h]);
+        f.z1[t] = mfma(a, f.xb, c);
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            uint16_t q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = to_bf16(fmaxf(f.z1[t][4 * cc + u], 0.f));
+            f.h1[t][cc] = pack4(q);
+        }
+    }
+    // layer 2: z2^T[j][p] = sum_k W2[j][k] h1[p][k] + b2[j]; k-chunk b covers 8b..8b+7
+    float part = 0.f;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        f32x16 c;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) c[r] = W.b2[32 * t + drow(r, h)];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bf16x4 a = pack4(&W.W2b[(32 * t + p) * H + 8 * b + 4 * h]);
+            c = mfma(a, f.h1[b >> 2][b & 3], c);
+        }
+        f.z2[t] = c;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float hv = from_bf16(to_bf16(fmaxf(c[r], 0.f)));
+            f.h2[t][r] = hv;
+            part += hv * W.w3[32 * t + drow(r, h)];
+        }
+    }
+    // layer 3: the two halves of the wave hold complementary rows
+    part += __shfl_xor(part, 32, 64);
+    f.z = part + W.b3;
+}
+
+// ---------------------------------------------------------------- inference
+__global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ P, const float* __restrict__ feat,
+                                                     int64_t n, float* __restrict__ y) {
+    __shared__ WeightsLDS W;
+    load_weights(W, P, false);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t tiles = (n + 31) / 32;
+    for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < tiles; t += (int64_t)gridDim.x * 4) {
+        Fwd f;
+        forward_tile(W, feat, n, 32 * t, f);
+        const int64_t s = 32 * t + lane;
+        if (lane < 32 && s < n) y[s] = f.z * W.out_scale;
+    }
+}
+
+// ---------------------------------------------------------------- training
+// One wave per workgroup.  Partial gradient (packed like the parameters) and
+// FP64 loss sum of this workgroup's tiles go to part[blockIdx.x].
+__global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ P, const float* __restrict__ feat,
+                                                 const float* __restrict__ target, int64_t n,
+                                                 float* __restrict__ part, double* __restrict__ loss_part) {
+    __shared__ WeightsLDS W;
+    __shared__ uint16_t dz2t[H][32], dz1t[H][32], h1t[H][32];
+    __shared__ float h2t[H][32], xf[8][32], dzs[32];
+    load_weights(W, P, true);
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+    const float inv_out = 1.0f / W.out_scale;
+    f32x16 gW2[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) gW2[a][b][r] = 0.f;
+    float gb1 = 0.f, gb2 = 0.f, gw3 = 0.f, gb3 = 0.f, gW1[NF] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    double loss = 0.0;
+    const int64_t tiles = (n + 31) / 32;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t base = 32 * tile, s = base + p;
+        Fwd f;
+        forward_tile(W, feat, n, base, f);
+        // dz = 2 (z - t/out_scale) / n for real samples
+        float dz = 0.f;
+        if (s < n) {
+            const float r = f.z - target[s] * inv_out;
+            dz = 2.0f * r / (float)n;
+            if (h == 0) loss += (double)r * (double)r;
+        }
+        if (h == 0) dzs[p] = dz;
+        // stash x (FP32 of the bf16 value) and h1^T, h2^T for the row sums and the GEMM
+#pragma unroll
+        for (int c = 0; c < 4; ++c) xf[4 * h + c][p] = from_bf16((uint16_t)f.xb[c]);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int j = 32 * t + drow(r, h);
+                h1t[j][p] = (uint16_t)f.h1[t][r >> 2][r & 3];
+                h2t[j][p] = f.h2[t][r];
+            }
+        // dZ2^T = bf16(dz w3 [z2 > 0]) in registers (B operands of W2^T) and in LDS
+        bf16x4 dz2[2][4];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                uint16_t q[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int r = 4 * cc + u, j = 32 * t + drow(r, h);
+                    q[u] = to_bf16(f.z2[t][r] > 0.f ? dz * W.w3[j] : 0.f);
+                    dz2t[j][p] = q[u];
+                }
+                dz2[t][cc] = pack4(q);
+            }
+        // dH1^T = W2^T dZ2^T, dZ1^T = bf16(dH1^T [z1 > 0])
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            f32x16 c;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) c[r] = 0.f;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bf16x4 a = pack4(&W.W2t[(32 * t + p) * H + 8 * b + 4 * h]);
+                c = mfma(a, dz2[b >> 2][b & 3], c);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int j = 32 * t + drow(r, h);
+                dz1t[j][p] = to_bf16(f.z1[t][r] > 0.f ? c[r] : 0.f);
+            }
+        }
+        __syncthreads();
+        // gW2[j2][j1] += sum_p dZ2^T[j2][p] H1^T[j1][p]: K = the tile's 32 samples
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            bf16x4 A[2], B[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                A[t] = pack4(&dz2t[32 * t + p][8 * b + 4 * h]);
+                B[t] = pack4(&h1t[32 * t + p][8 * b + 4 * h]);
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) gW2[t][u] = mfma(A[t], B[u], gW2[t][u]);
+        }
+        // row sums: thread j owns hidden unit j
+        {
+            const int j = lane;
+            float s1 = 0.f, s2 = 0.f, s3 = 0.f, sw[NF] = {0.f, 0.f, 0.f, 0.f, 0.f};
+            for (int q = 0; q < 32; ++q) {
+                const float d1 = from_bf16(dz1t[j][q]);
+                s1 += d1;
+                s2 += from_bf16(dz2t[j][q]);
+                s3 += h2t[j][q] * dzs[q];
+#pragma unroll
+                for (int k = 0; k < NF; ++k) sw[k] += d1 * xf[k][q];
+            }
+            gb1 += s1;
+            gb2 += s2;
+            gw3 += s3;
+#pragma unroll
+            for (int k = 0; k < NF; ++k) gW1[k] += sw[k];
+            if (j == 0) {
+                float sd = 0.f;
+                for (int q = 0; q < 32; ++q) sd += dzs[q];
+                gb3 += sd;
+            }
+        }
+        __syncthreads();
+    }
+    // write this workgroup's partial gradient
+    float* o = part + (size_t)blockIdx.x * NPARAM;
+    const int j = lane;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) o[OFF_W1 + j * NF + k] = gW1[k];
+    o[OFF_B1 + j] = gb1;
+    o[OFF_B2 + j] = gb2;
+    o[OFF_W3 + j] = gw3;
+    if (j == 0) o[OFF_B3] = gb3;
+    if (j < 2 * NF + 1) o[OFF_SHIFT + j] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) o[OFF_W2 + (32 * t + drow(r, h)) * H + 32 * u + p] = gW2[t][u][r];
+    // FP64 loss of the wave (lanes 0..31 hold one sample each)
+    for (int off = 32; off > 0; off >>= 1) loss += __shfl_down(loss, off, 64);
+    if (lane == 0) loss_part[blockIdx.x] = loss;
+}
+
+__global__ void k_mlp_grad_finish(const float* __restrict__ part, int nblk, float* __restrict__ grad,
+                                  const double* __restrict__ loss_part, double* __restrict__ loss) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < NPARAM) {
+        float g = 0.f;
+        for (int b = 0; b < nblk; ++b) g += part[(size_t)b * NPARAM + i];
+        grad[i] = g;
+    }
+    if (i == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += loss_part[b];
+        *loss = s;
+    }
+}
+
+// Adam (Kingma and Ba) on the trainable entries; bias-correction denominators
+// c1 = 1 - beta1^t, c2 = 1 - beta2^t come from the host.
+__global__ void k_mlp_adam(float* __restrict__ P, const float* __restrict__ grad, float* __restrict__ m,
+                           float* __restrict__ v, float lr, float beta1, float beta2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= OFF_SHIFT) return;
+    const float g = grad[i];
+    const float mi = beta1 * m[i] + (1.0f - beta1) * g;
+    const float vi = beta2 * v[i] + (1.0f - beta2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace
+
+constexpr int kMlpGradBlocks = 256;
+
+int mlp_param_count() { return NPARAM; }
+int mlp_grad_blocks() { return kMlpGradBlocks; }
+
+hipError_t launch_mlp_forward(const float* P, const float* feat, int64_t n, float* y, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t tiles = (n + 31) / 32;
+    int64_t blocks = (tiles + 3) / 4;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_mlp_forward, dim3((uint32_t)blocks), dim3(256), 0, s, P, feat, n, y);
+    return hipGetLastError();
+}
+
+// grad[NPARAM] and *loss_sum (sum of squared residuals in units of out_scale)
+hipError_t launch_mlp_grad(const float* P, const float* feat, const float* target, int64_t n, float* part,
+                           double* loss_part, float* grad, double* loss_sum, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_grad, dim3(kMlpGradBlocks), dim3(64), 0, s, P, feat, target, n, part, loss_part);
+    hipLaunchKernelGGL(k_mlp_grad_finish, dim3((NPARAM + 255) / 256), dim3(256), 0, s, part, kMlpGradBlocks, grad,
+                       loss_part, loss_sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float* P, const float* grad, float* m, float* v, float lr, float beta1, float beta2,
+                           float eps, float c1, float c2, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, s, P, grad, m, v, lr, beta1, beta2, eps,
+                       c1, c2);
+    return hipGetLastError();
+}
+
+}  // namespace sph

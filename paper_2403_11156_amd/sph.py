@@ -119,6 +119,16 @@ def _load():
         "sph_profile_read": (C.c_int, [P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double)]),
         "sph_last_error": (C.c_char_p, [P]),
+        "sph_mlp_create": (C.c_int, [P, P, C.POINTER(P)]),
+        "sph_mlp_destroy": (None, [P]),
+        "sph_mlp_get_params": (C.c_int, [P, P]),
+        "sph_mlp_set_params": (C.c_int, [P, P]),
+        "sph_mlp_forward": (C.c_int, [P, P, P, C.c_int64]),
+        "sph_mlp_grad": (C.c_int, [P, P, P, C.c_int64, P, C.POINTER(C.c_double)]),
+        "sph_mlp_train_step": (C.c_int, [P, P, P, C.c_int64, C.c_float, C.POINTER(C.c_double)]),
+        "sph_set_warm_start": (C.c_int, [P, C.c_int32, P]),
+        "sph_enable_trace": (C.c_int, [P, P, P, C.c_int64]),
+        "sph_trace_rows": (C.c_int, [P, C.POINTER(C.c_int64)]),
         "sph_strerror": (C.c_char_p, [C.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -144,6 +154,18 @@ sph_profile_enable = lib.sph_profile_enable
 sph_profile_read = lib.sph_profile_read
 sph_last_error = lib.sph_last_error
 sph_strerror = lib.sph_strerror
+sph_mlp_create = lib.sph_mlp_create
+sph_mlp_destroy = lib.sph_mlp_destroy
+sph_mlp_get_params = lib.sph_mlp_get_params
+sph_mlp_set_params = lib.sph_mlp_set_params
+sph_mlp_forward = lib.sph_mlp_forward
+sph_mlp_grad = lib.sph_mlp_grad
+sph_mlp_train_step = lib.sph_mlp_train_step
+sph_set_warm_start = lib.sph_set_warm_start
+sph_enable_trace = lib.sph_enable_trace
+sph_trace_rows = lib.sph_trace_rows
+
+MLP_PARAMS = 4620
 
 
 class SphError(RuntimeError):
@@ -360,6 +382,22 @@ class Simulation:
         o["lists_b"] = o["lists_b"][: int(o["counts_b"].astype(np.int64).sum())]
         return o
 
+    def set_warm_start(self, mode: int, mlp: Optional["MLP"] = None):
+        self._warm_mlp = mlp
+        self._check(sph_set_warm_start(self.ctx, mode, mlp.h if mlp is not None else None))
+
+    def enable_trace(self, features, targets, capacity: int):
+        """features, targets: device tensors (torch) of [capacity, 5] and [capacity] float32."""
+        self._trace = (features, targets)
+        fp = None if features is None else C.c_void_p(features.data_ptr())
+        tp = None if targets is None else C.c_void_p(targets.data_ptr())
+        self._check(sph_enable_trace(self.ctx, fp, tp, capacity))
+
+    def trace_rows(self) -> int:
+        n = C.c_int64()
+        self._check(sph_trace_rows(self.ctx, C.byref(n)))
+        return n.value
+
     def profile_enable(self, on: bool = True):
         self._check(sph_profile_enable(self.ctx, 1 if on else 0))
 
@@ -369,3 +407,57 @@ class Simulation:
         by = C.c_double()
         self._check(sph_profile_read(self.ctx, kernel.encode(), C.byref(n), C.byref(ms), C.byref(by)))
         return {"launches": n.value, "ms": ms.value, "bytes": by.value}
+
+
+class MLP:
+    """The warm-start MLP on the device (sph_mlp_*); tensors are torch device
+    tensors, parameters a float32 numpy vector of MLP_PARAMS entries."""
+
+    def __init__(self, params: np.ndarray, stream: Optional[int] = None):
+        p = np.ascontiguousarray(params, np.float32)
+        assert p.size == MLP_PARAMS
+        h = C.c_void_p()
+        if stream is None:
+            stream = current_stream_handle()
+        rc = sph_mlp_create(_ptr(p), C.c_void_p(stream) if stream else None, C.byref(h))
+        if rc != SPH_OK:
+            raise SphError(rc, sph_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            sph_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc):
+        if rc != SPH_OK:
+            raise SphError(rc, "mlp call failed")
+
+    def params(self) -> np.ndarray:
+        p = np.zeros(MLP_PARAMS, np.float32)
+        self._check(sph_mlp_get_params(self.h, _ptr(p)))
+        return p
+
+    def set_params(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, np.float32)
+        self._check(sph_mlp_set_params(self.h, _ptr(p)))
+
+    def forward(self, features, y):
+        n = features.shape[0]
+        self._check(sph_mlp_forward(self.h, C.c_void_p(features.data_ptr()), C.c_void_p(y.data_ptr()), n))
+
+    def grad(self, features, targets):
+        g = np.zeros(MLP_PARAMS, np.float32)
+        loss = C.c_double()
+        self._check(sph_mlp_grad(self.h, C.c_void_p(features.data_ptr()), C.c_void_p(targets.data_ptr()),
+                                 features.shape[0], _ptr(g), C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, features, targets, lr: float) -> float:
+        loss = C.c_double()
+        self._check(sph_mlp_train_step(self.h, C.c_void_p(features.data_ptr()), C.c_void_p(targets.data_ptr()),
+                                       features.shape[0], lr, C.byref(loss)))
+        return loss.value

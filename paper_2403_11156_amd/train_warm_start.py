@@ -1,0 +1,131 @@
+"""Train the learned warm start of the density solve on the device.
+
+1. Trace collection: run the plain solver (previous-step warm start) on the
+   8k dam break (c1, all 100 steps) and the 125k dam break (c2, every 10th of
+   1000 steps); each traced step appends, per fluid particle, the five
+   features at the start of the density solve and the step's final stiffness
+   (sph_enable_trace) into device tensors.
+2. Training: mean squared error of the normalised prediction, Adam on the
+   device (sph_mlp_train_step: bf16 matrix-core forward and backward, FP32
+   master weights), shuffled mini-batches.
+3. The FP32 parameters go to weights/warm_start_mlp.f32 with a JSON record.
+
+    python -m paper_2403_11156_amd.train_warm_start [--epochs 12] [--quick]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(HERE, "weights", "warm_start_mlp.f32")
+RECORD = os.path.join(HERE, "weights", "warm_start_mlp.json")
+H = 64
+
+
+def init_params(seed, shift, scale, out_scale):
+    """He-uniform initial weights, normalisation folded into the layout."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.uniform(-1, 1, (H, 5)) * np.sqrt(6.0 / 5), np.zeros(H),
+             rng.uniform(-1, 1, (H, H)) * np.sqrt(6.0 / H), np.zeros(H),
+             rng.uniform(-1, 1, H) * np.sqrt(6.0 / H) * 0.1, np.zeros(1),
+             np.asarray(shift, np.float64), np.asarray(scale, np.float64), np.array([out_scale])]
+    return np.concatenate([np.asarray(a, np.float64).reshape(-1) for a in parts]).astype(np.float32)
+
+
+def collect(runs, torch, sph, scenes, log=print):
+    """runs: list of (scene name, steps, trace every k-th step)."""
+    total = 0
+    for name, steps, every in runs:
+        total += scenes.scene(name).n_fluid * len(range(0, steps, every))
+    F = torch.zeros((total, 5), dtype=torch.float32, device="cuda")
+    T = torch.zeros(total, dtype=torch.float32, device="cuda")
+    row = 0
+    for name, steps, every in runs:
+        sc = scenes.scene(name)
+        sim = sph.Simulation(sc)
+        t0 = time.time()
+        iters = []
+        for s in range(steps):
+            traced = s % every == 0
+            if traced:
+                sim.enable_trace(F[row:], T[row:], sc.n_fluid)
+            st = sim.advance()
+            iters.append(st["iters_dens"])
+            if traced:
+                assert sim.trace_rows() == sc.n_fluid
+                row += sc.n_fluid
+                sim.enable_trace(None, None, 0)
+        torch.cuda.synchronize()
+        log(f"[trace] {sc.name}: {steps} steps in {time.time() - t0:.1f} s, "
+            f"mean density iterations {np.mean(iters):.2f}, rows so far {row}")
+        sim.close()
+    return F, T
+
+
+def train(F, T, torch, sph, epochs=12, batch=65536, lr=2e-3, seed=0, log=print):
+    n = F.shape[0]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    perm = torch.randperm(n, generator=g, device="cuda")
+    n_val = max(1, n // 20)
+    val, tr = perm[:n_val], perm[n_val:]
+    Fv, Tv = F[val].contiguous(), T[val].contiguous()
+    Ft, Tt = F[tr].contiguous(), T[tr].contiguous()
+    shift = Ft.mean(0).cpu().numpy()
+    scale = 1.0 / np.maximum(Ft.std(0).cpu().numpy(), 1e-12)
+    out_scale = float(max(Tt.std().item(), 1e-12))
+    p0 = init_params(seed + 1, shift, scale, out_scale)
+    net = sph.MLP(p0)
+    hist = []
+    base, _ = net.grad(Fv, Tv)
+    # loss of the plain warm start on the same samples, for reference:
+    # K0 = warm_factor * K_prev is feature 3 times the warm factor
+    log(f"[train] {Ft.shape[0]} training / {n_val} validation samples; initial validation loss {base:.4g}")
+    steps_per_epoch = max(1, Ft.shape[0] // batch)
+    step = 0
+    t0 = time.time()
+    for ep in range(epochs):
+        order = torch.randperm(Ft.shape[0], generator=g, device="cuda")
+        rate = lr * (0.5 ** (ep // 4))
+        for b in range(steps_per_epoch):
+            idx = order[b * batch:(b + 1) * batch]
+            net.train_step(Ft[idx].contiguous(), Tt[idx].contiguous(), rate)
+            step += 1
+        v, _ = net.grad(Fv, Tv)
+        hist.append(v)
+        log(f"[train] epoch {ep + 1}/{epochs} lr {rate:.2e} validation loss {v:.4g} ({time.time() - t0:.1f} s)")
+    params = net.params()
+    net.close()
+    return params, {"validation_loss": hist, "initial_validation_loss": base, "samples": int(n),
+                    "train_steps": step, "batch": batch, "epochs": epochs, "lr": lr}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--quick", action="store_true", help="c1 only, 2 epochs (smoke of the driver)")
+    ap.add_argument("--out", default=WEIGHTS)
+    args = ap.parse_args()
+    import torch
+    from paper_2403_11156_amd import scenes, sph
+    torch.cuda.set_device(0)
+    runs = [("c1", 100, 1)] if args.quick else [("c1", 100, 1), ("c2", 1000, 10)]
+    F, T = collect(runs, torch, sph, scenes)
+    params, rec = train(F, T, torch, sph, epochs=2 if args.quick else args.epochs)
+    os.makedirs(os.path.dirname(args.out), exist_ok=True)
+    params.astype(np.float32).tofile(args.out)
+    rec["runs"] = runs
+    with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps({"weights": args.out, **{k: rec[k] for k in ("samples", "train_steps")},
+                      "final_validation_loss": rec["validation_loss"][-1]}))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,54 @@
+"""Parity at the benchmark's full sizes (1.23 M fluid particles), in the
+launch configuration bench.py times: the whole neighbour structure bit-exact
+and one complete step within the field tolerance, against the FP64 oracle
+(grid search; about 25 s of oracle time per step)."""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2403_11156_amd import scenes
+
+from tests.parity import compare_step, ratio
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sph():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2403_11156_amd import sph as mod
+    O.build(force=False)
+    return mod
+
+
+@pytest.mark.parametrize("name", ["c5", "c3"])
+def test_full_size_step(sph, name):
+    sc = scenes.scene(name)
+    print(f"[fullsize] {sc.name}: nf={sc.n_fluid} nb={sc.n_boundary} bodies={len(sc.rigid)}", flush=True)
+    sim = sph.Simulation(sc)
+    sim.build_neighbors()
+    g_nbr = sim.read_neighbors()
+    ref_nbr = O.sorted_neighbor_structure(sc.params, sc.x_fluid, sc.x_boundary, brute=False)
+    for k_g, k_r in (("perm_f", "perm_f"), ("start_f", "start_f"), ("perm_b", "perm_b"), ("start_b", "start_b")):
+        np.testing.assert_array_equal(g_nbr[k_g], ref_nbr[k_r])
+    np.testing.assert_array_equal(g_nbr["keys_f"], ref_nbr["key_f"][ref_nbr["perm_f"]])
+    np.testing.assert_array_equal(g_nbr["counts_f"], ref_nbr["nf"][0])
+    np.testing.assert_array_equal(g_nbr["lists_f"], ref_nbr["nf"][1])
+    np.testing.assert_array_equal(g_nbr["counts_b"], ref_nbr["nb"][0])
+    np.testing.assert_array_equal(g_nbr["lists_b"], ref_nbr["nb"][1])
+    print("[fullsize] neighbour structure bit-exact", flush=True)
+    st = sim.step()
+    g = sim.read()
+    local = O.rigid_local(sc.x_boundary, sc.body_of_boundary, sc.rigid)
+    ref = O.step(O.State(sc, local), forced_div=st["iters_div"], forced_dens=st["iters_dens"], brute=False)
+    r = compare_step(g, ref, st)
+    print("[fullsize]", name, st["iters_div"], st["iters_dens"], {k: f"{v:.3g}" for k, v in r.items()}, flush=True)
+    for k, v in r.items():
+        assert v <= 1.0, (k, v)
+    assert ratio(g["psi"], ref["psi"]) <= 1.0
+    if sc.rigid:
+        assert ratio(g["force"], ref["force"], ref["S_force"]) <= 1.0
+        assert ratio(g["torque"], ref["torque"], ref["S_torque"]) <= 1.0
+    sim.close()

@@ -1,0 +1,199 @@
+"""Learned warm start on the device against the numpy MLP oracle and the FP64
+step oracle: forward, gradients, one Adam step, training, the learned step
+and trace capture.  bf16 tolerances come from oracle.mlp.error_scale /
+grad_scale (one bf16 step in any rounded operand, propagated with absolute
+values)."""
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from oracle import oracle as O
+from paper_2403_11156_amd import scenes
+
+from tests.parity import compare_step, oracle_state_from_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2403_11156_amd import sph
+    O.build(force=False)
+    return torch, sph
+
+
+def _features(n, seed=0):
+    rng = np.random.default_rng(seed)
+    F = np.stack([rng.normal(0, 5e-3, n), rng.normal(0, 2e-3, n), rng.normal(1.1, 0.15, n),
+                  np.abs(rng.normal(0, 2e-3, n)), rng.normal(1.0, 0.3, n)], axis=1)
+    return F.astype(np.float32)
+
+
+def _params(F, seed=1):
+    R = _features(4096, seed=99)     # normalisation from a fixed reference sample
+    return M.init(seed=seed, in_shift=R.mean(0), in_scale=1.0 / R.std(0), out_scale=1e-3)
+
+
+@pytest.mark.parametrize("n", [1, 31, 1000, 70001])
+def test_forward_matches_oracle(env, n):
+    torch, sph = env
+    F = _features(n)
+    p = _params(F)
+    net = sph.MLP(p)
+    Fd = torch.from_numpy(F).cuda()
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    net.forward(Fd, y)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy().astype(np.float64)
+    ref = M.forward(p, F)
+    tol = M.error_scale(p, F)
+    ratio = np.abs(y - ref) / tol
+    print("forward n", n, "max ratio", ratio.max(), "max |dy|", np.abs(y - ref).max(), flush=True)
+    assert (ratio <= 1.0).all()
+    net.close()
+
+
+@pytest.mark.parametrize("n", [33, 777, 20000])
+def test_gradient_matches_oracle(env, n):
+    torch, sph = env
+    F = _features(n, seed=2)
+    p = _params(F, seed=3)
+    t = (1e-3 * np.tanh(F[:, 0] * 100 + F[:, 3] * 300)).astype(np.float32)
+    net = sph.MLP(p)
+    loss, g = net.grad(torch.from_numpy(F).cuda(), torch.from_numpy(t).cuda())
+    loss_ref, g_ref = M.loss_and_grads(p, F, t)
+    scale = M.grad_scale(p, F, t)
+    tol = 2.0 ** -6 * scale + 1e-12
+    ratio = np.abs(g - g_ref) / tol
+    print("grad n", n, "max ratio", ratio.max(), "loss", loss, loss_ref, flush=True)
+    assert ratio.max() <= 1.0
+    assert abs(loss - loss_ref) <= 1e-2 * loss_ref
+    trainable = np.concatenate([np.full(int(np.prod(s)), k in M.TRAINABLE) for k, s in M.SIZES])
+    assert np.all(g[~trainable] == 0.0)
+    net.close()
+
+
+def test_adam_step_matches_oracle(env):
+    torch, sph = env
+    n = 4096
+    F = _features(n, seed=4)
+    p = _params(F, seed=5)
+    t = (1e-3 * np.tanh(F[:, 1] * 400)).astype(np.float32)
+    net = sph.MLP(p)
+    Fd, td = torch.from_numpy(F).cuda(), torch.from_numpy(t).cuda()
+    _, g_dev = net.grad(Fd, td)
+    lr = 1e-3
+    net.train_step(Fd, td, lr)
+    p1 = net.params().astype(np.float64)
+    # Adam's first step is lr * g / (|g| + eps) per entry: compare with the
+    # device's own gradient (the update rule is what is checked here)
+    p_ref, _, _ = M.adam(p, g_dev.astype(np.float64), np.zeros(M.N_PARAMS), np.zeros(M.N_PARAMS), 1, lr)
+    assert np.abs(p1 - p_ref).max() <= 1e-6 * max(1.0, np.abs(p).max())
+    net.close()
+
+
+def test_training_reduces_loss(env):
+    torch, sph = env
+    n = 65536
+    F = _features(n, seed=6)
+    t = (1e-3 * np.tanh(F[:, 0] * 150 - F[:, 1] * 200 + (F[:, 4] - 1.0))).astype(np.float32)
+    p = _params(F, seed=7)
+    net = sph.MLP(p)
+    Fd, td = torch.from_numpy(F).cuda(), torch.from_numpy(t).cuda()
+    l0, _ = net.grad(Fd, td)
+    for _ in range(300):
+        net.train_step(Fd, td, 3e-3)
+    l1, _ = net.grad(Fd, td)
+    print("loss", l0, "->", l1, flush=True)
+    assert l1 < 0.2 * l0
+    net.close()
+
+
+def _learned_params(sc):
+    # a fixed, untrained network with the feature normalisation of a real
+    # scene: it predicts some stiffness, which is all the step parity needs
+    rng = np.random.default_rng(9)
+    shift = np.array([0.0, 0.0, 1.0, 0.0, 1.0])
+    scale = np.array([100.0, 300.0, 5.0, 300.0, 3.0])
+    p = M.unpack(M.init(seed=11, in_shift=shift, in_scale=scale, out_scale=2e-3))
+    p["b3"] = np.array([0.5])
+    del rng
+    return M.pack(p)
+
+
+@pytest.mark.parametrize("name", ["small", "c1"])
+def test_learned_step_matches_oracle(env, name):
+    torch, sph = env
+    sc = scenes.small_scene(7, 6, 5) if name == "small" else scenes.scene("c1")
+    p = _learned_params(sc)
+    sim = sph.Simulation(sc)
+    net = sph.MLP(p)
+    local = O.rigid_local(sc.x_boundary, sc.body_of_boundary, sc.rigid)
+    worst = {}
+    for k in range(3):
+        sim.build_neighbors()
+        state = oracle_state_from_gpu(sim, sc, local)
+        if k == 1:
+            sim.set_warm_start(2, net)
+        st = sim.step()
+        if k >= 1:
+            g = sim.read()
+            pd = dict(state.params, warm_start=2)
+            ref = O.step(state, forced_div=st["iters_div"], forced_dens=st["iters_dens"], params=pd,
+                         mlp=M.step_callback(p))
+            r = compare_step(g, ref, st)
+            for f, v in r.items():
+                worst[f] = max(worst.get(f, 0.0), v)
+    print(name, "worst", worst, flush=True)
+    for f, v in worst.items():
+        assert v <= 1.0, (f, v)
+    sim.close()
+    net.close()
+
+
+def test_nan_weights_fall_back(env):
+    torch, sph = env
+    sc = scenes.small_scene(4, 4, 4)
+    p = _learned_params(sc)
+    p[5] = np.nan
+    sim = sph.Simulation(sc)
+    net = sph.MLP(p)
+    sim.set_warm_start(2, net)
+    st = sim.advance()
+    assert st["warm_fallback"] == 1
+    sim.close()
+    net.close()
+
+
+def test_trace_capture_matches_oracle(env):
+    torch, sph = env
+    sc = scenes.scene("c1")
+    sim = sph.Simulation(sc)
+    local = O.rigid_local(sc.x_boundary, sc.body_of_boundary, sc.rigid)
+    cap = 3 * sc.n_fluid
+    feats = torch.zeros((cap, 5), dtype=torch.float32, device="cuda")
+    targ = torch.zeros(cap, dtype=torch.float32, device="cuda")
+    sim.build_neighbors()
+    sim.step()                      # a first step so that K_prev is non-zero
+    sim.enable_trace(feats, targ, cap)
+    for k in range(3):
+        sim.build_neighbors()
+        state = oracle_state_from_gpu(sim, sc, local)
+        perm = sim.read_neighbors()["perm_f"]
+        st = sim.step()
+        ref = O.step(state, forced_div=st["iters_div"], forced_dens=st["iters_dens"], want_features=True)
+        rows = slice(k * sc.n_fluid, (k + 1) * sc.n_fluid)
+        gf = feats[rows].cpu().numpy().astype(np.float64)
+        gt = targ[rows].cpu().numpy().astype(np.float64)
+        # trace rows are in the step's sorted order
+        rf, rS = ref["features"][perm], ref["S_features"][perm]
+        rt, rtS = ref["target"][perm], ref["S_target"][perm]
+        fr = np.abs(gf - rf) / (1e-5 * (np.abs(rf) + rS) + 1e-30)
+        tr = np.abs(gt - rt) / (1e-5 * (np.abs(rt) + rtS) + 1e-30)
+        print("trace step", k, "feature ratios", fr.max(axis=0), "target", tr.max(), flush=True)
+        assert fr.max() <= 1.0 and tr.max() <= 1.0
+    assert sim.trace_rows() == cap
+    sim.close()
