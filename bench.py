@@ -24,8 +24,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 # per-launch algorithmic bytes are computed inside the library (see the
 # design notes: own fields of every particle read/written once plus 4 B per
 # neighbour-list entry)
-PROFILED = ("pressure_update", "predict", "density_alpha", "xsph", "nbr_build", "sort", "integrate", "visc",
-            "warm_features", "mlp")
+PROFILED = ("pressure_update", "predict", "density_alpha", "xsph", "nbr_build", "sort", "tiles", "integrate",
+            "visc", "warm_features", "mlp")
+KERNEL_SOURCES = ("sph_kernels.hip", "sph_tiled.hip", "sph_device.h", "sph_internal.h")
 
 
 def parse():
@@ -38,9 +39,20 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--arm", choices=("plain", "learned", "both"), default="both",
                     help="warm start of the density solve: previous-step (plain) and/or the trained MLP")
+    ap.add_argument("--layout", choices=("tiled", "untiled"), default="tiled",
+                    help="neighbour passes over LDS-staged cell-row tiles or one thread per particle")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
+
+
+def kernel_sha() -> str:
+    """Digest of the kernel sources, to tie counter runs to the code they measured."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2403_11156_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(config: str, kernel: str):
@@ -49,10 +61,9 @@ def measured_traffic(config: str, kernel: str):
     different kernel source than the one built now."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{config}.txt")
-    src = os.path.join(ROOT, "paper_2403_11156_amd", "csrc", "sph_kernels.hip")
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = kernel_sha()
     table, recorded = {}, None
     for line in open(path):
         parts = line.split()
@@ -113,6 +124,7 @@ def main():
     results = {}
     for arm in arms:
         sim = sph.Simulation(sc)
+        sim.set_tiling(args.layout == "tiled")
         net = None
         if arm == "learned":
             import numpy as np
@@ -133,12 +145,13 @@ def main():
         wall = time.perf_counter() - t0
         prof = {k: sim.profile_read(k) for k in PROFILED}
         sim.profile_enable(False)
+        info = sim.info()
         sim.close()
         if net is not None:
             net.close()
         print(f"[bench] {arm}: timed {args.steps} steps in {wall:.3f} s", flush=True)
-        results[arm] = (wall, prof, iters)
-    wall, prof, iters = results[arms[0]]
+        results[arm] = (wall, prof, iters, info)
+    wall, prof, iters, info = results[arms[0]]
 
     ms_step = wall * 1e3 / args.steps
     value = sc.n_fluid * args.steps / wall
@@ -166,7 +179,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc.name, "n_fluid": sc.n_fluid, "n_boundary": sc.n_boundary,
                    "n_rigid": len(sc.rigid), "r": sc.params["r"], "eta": sc.params["eta_density"],
-                   "warm_start": arms[0], "parallelism": "none (1 GPU)"},
+                   "warm_start": arms[0], "layout": args.layout, "parallelism": "none (1 GPU)"},
+        "tiles": {"n": info["n_tiles"], "overfull": info["n_tiles_overfull"]},
         "iters_per_step": {"div": sum(i[0] for i in iters) / n, "dens": sum(i[1] for i in iters) / n,
                            "cg": sum(i[2] for i in iters) / n},
         "max_err_dens": max(i[3] for i in iters), "max_err_div": max(i[4] for i in iters),
@@ -176,7 +190,7 @@ def main():
         "kernels": kernels,
     }
     if "learned" in results:
-        lw, lprof, lit = results["learned"]
+        lw, lprof, lit, _ = results["learned"]
         line["learned"] = {
             "value": sc.n_fluid * args.steps / lw, "ms_per_step": lw * 1e3 / args.steps,
             "iters_per_step": {"div": sum(i[0] for i in lit) / len(lit), "dens": sum(i[1] for i in lit) / len(lit)},

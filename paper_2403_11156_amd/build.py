@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsph.so")
-SOURCES = ["sph_kernels.hip", "sph_mlp.hip", "sph_api.cpp"]
+SOURCES = ["sph_kernels.hip", "sph_tiled.hip", "sph_mlp.hip", "sph_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

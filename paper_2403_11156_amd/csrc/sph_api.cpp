@@ -60,6 +60,14 @@ struct sph_ctx {
     uint32_t *key = nullptr, *slot = nullptr, *src = nullptr, *count = nullptr, *start_f = nullptr;
     uint32_t *scan_part = nullptr;
     uint32_t *nlist = nullptr, *ncnt = nullptr, *blist = nullptr, *bcnt = nullptr;
+    // cell-row tiles and their 16-bit lists
+    bool tiled = false, tile_capable = false;
+    int32_t slab_limit = sph::kSlab;
+    int64_t nrows = 0, max_t = 0, ntiles = 0, n_over = 0;
+    double over_entries = 0.0;
+    sph::TileDesc *tiles = nullptr;
+    uint32_t *tilecnt = nullptr, *tileoff = nullptr;
+    uint16_t *l16 = nullptr, *b16 = nullptr;
     // boundary, sorted order (xb.w = Psi, vb.w = body id)
     float4 *xb = nullptr, *xb2 = nullptr, *vb = nullptr, *vb2 = nullptr;
     int32_t *bid = nullptr, *bid2 = nullptr;
@@ -335,9 +343,20 @@ int sort_boundary(sph_ctx *c) {
     return SPH_OK;
 }
 
-// algorithmic bytes of reading every neighbour-list entry once (4 B each)
-double list_bytes(const sph_ctx *c) { return 4.0 * c->nbr_sum; }
-double fluid_list_bytes(const sph_ctx *c) { return 4.0 * c->nbr_sum_f; }
+// algorithmic bytes of reading every neighbour-list entry once: 4 B per
+// sorted index, 2 B per slot of a tiled list (over-full tiles keep 4 B)
+double list_bytes(const sph_ctx *c) {
+    return c->tiled ? 2.0 * (c->nbr_sum - c->over_entries) + 4.0 * c->over_entries : 4.0 * c->nbr_sum;
+}
+double fluid_list_bytes(const sph_ctx *c) {
+    // over-full entries are not split by set; count them all as fluid
+    const double over = std::min(c->over_entries, c->nbr_sum_f);
+    return c->tiled ? 2.0 * (c->nbr_sum_f - over) + 4.0 * over : 4.0 * c->nbr_sum_f;
+}
+
+sph::Lists tile_lists(const sph_ctx *c) {
+    return sph::Lists{c->tiles, c->ntiles, c->l16, c->nlist, c->ncnt, c->b16, c->blist, c->bcnt};
+}
 
 int build(sph_ctx *c) {
     hipStream_t s = c->stream;
@@ -353,14 +372,28 @@ int build(sph_ctx *c) {
         int rc = sort_fluid(c);
         if (rc) return rc;
     }
-    {
+    if (c->tiled) {
+        {
+            ProfScope ps(c, "tiles", 8.0 * c->nrows + 18.0 * 4.0 * c->nrows + sizeof(sph::TileDesc) * (double)c->ntiles);
+            HIP_TRY(c, sph::launch_tiles_build(c->x, c->start_f, c->start_b, c->g, c->slab_limit, c->tilecnt,
+                                               c->tileoff, c->scan_part, c->tiles, s));
+        }
+        ProfScope ps(c, "nbr_build", 16.0 * c->nf + 8.0 * c->nf + list_bytes(c));
+        HIP_TRY(c, sph::launch_nbr_build_tiled(c->tiles, c->tileoff + c->nrows, c->max_t, c->x, c->nf, c->xb,
+                                               c->start_f, c->start_b, c->g, c->l16, c->nlist, c->ncnt, c->capf,
+                                               c->b16, c->blist, c->bcnt, c->capb, c->flags, c->nstat_part,
+                                               c->nstats, s));
+        HIP_TRY(c, hipMemcpyAsync(c->h_u32 + 1, c->tileoff + c->nrows, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    } else {
         ProfScope ps(c, "nbr_build", 16.0 * c->nf + 8.0 * c->nf + list_bytes(c));
         HIP_TRY(c, sph::launch_nbr_build(c->x, c->nf, c->xb, c->start_f, c->start_b, c->g, c->nlist, c->ncnt, c->capf,
                                          c->blist, c->bcnt, c->capb, c->flags, c->nstat_part, c->nstats, s));
     }
     HIP_TRY(c, hipMemcpyAsync(c->h_u32, c->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipMemcpyAsync(c->h_stats, c->nstats, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(c->h_stats, c->nstats, sph::kNStats * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                              s));
     HIP_TRY(c, hipStreamSynchronize(s));
+    c->ntiles = c->tiled ? (int64_t)c->h_u32[1] : 0;
     c->sorted_once = true;
     if (c->h_u32[0] & 2u) {
         c->nbr_fresh = false;
@@ -372,6 +405,8 @@ int build(sph_ctx *c) {
     }
     c->nbr_sum = (double)c->h_stats[2];
     c->nbr_sum_f = (double)c->h_stats[3];
+    c->over_entries = (double)c->h_stats[4];
+    c->n_over = (int64_t)c->h_stats[5];
     c->nbr_fresh = true;
     return SPH_OK;
 }
@@ -386,17 +421,25 @@ int read_scalar(sph_ctx *c, const double *dev, double *out) {
 
 int pressure_pass(sph_ctx *c, float *Kacc, float *klast, float dt) {
     ProfScope ps(c, "pressure_update", (48.0 + (klast ? 24.0 : 20.0)) * c->nf + list_bytes(c));
-    HIP_TRY(c, sph::launch_pressure_update(c->nf, c->x, c->v, c->kappa, Kacc, klast, c->nlist, c->ncnt, c->xb,
-                                           c->blist, c->bcnt, c->kc, dt, c->stream));
+    if (c->tiled)
+        HIP_TRY(c, sph::launch_pressure_update_t(tile_lists(c), c->nf, c->x, c->v, c->kappa, Kacc, klast, c->xb, c->kc,
+                                                 dt, c->stream));
+    else
+        HIP_TRY(c, sph::launch_pressure_update(c->nf, c->x, c->v, c->kappa, Kacc, klast, c->nlist, c->ncnt, c->xb,
+                                               c->blist, c->bcnt, c->kc, dt, c->stream));
     return SPH_OK;
 }
 
 int predict_pass(sph_ctx *c, int mode, float dt, double *err_sum) {
     {
         ProfScope ps(c, "predict", 56.0 * c->nf + list_bytes(c));
-        HIP_TRY(c, sph::launch_predict(mode, c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->nlist, c->ncnt, c->xb,
-                                       c->vb, c->blist, c->bcnt, c->kc, dt, c->red_part, c->scal,
-                                       c->stream));
+        if (c->tiled)
+            HIP_TRY(c, sph::launch_predict_t(mode, tile_lists(c), c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->xb,
+                                             c->vb, c->kc, dt, c->red_part, c->scal, c->stream));
+        else
+            HIP_TRY(c, sph::launch_predict(mode, c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->nlist, c->ncnt,
+                                           c->xb, c->vb, c->blist, c->bcnt, c->kc, dt, c->red_part, c->scal,
+                                           c->stream));
     }
     return read_scalar(c, c->scal, err_sum);
 }
@@ -427,6 +470,11 @@ int jacobi_solve(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, int3
     return SPH_OK;
 }
 
+hipError_t visc_matvec(sph_ctx *c, const float4 *p, float4 *Mp, float dt, float mu) {
+    if (c->tiled) return sph::launch_visc_matvec_t(tile_lists(c), c->nf, c->x, c->rho, p, Mp, c->kc, dt, mu, c->stream);
+    return sph::launch_visc_matvec(c->nf, c->x, c->rho, p, Mp, c->nlist, c->ncnt, c->kc, dt, mu, c->stream);
+}
+
 // Implicit viscosity (Eqs. 16-19): CG with block-Jacobi preconditioner on
 // (I - dt A) v* = v~, x0 = v~, stop at |r| <= tol |b|.  Dot products FP64.
 int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
@@ -438,11 +486,14 @@ int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
     HIP_TRY(c, hipMemcpyAsync(c->v2, c->cg_b, sizeof(float4) * nf, hipMemcpyDeviceToDevice, s));   // x0 = b
     {
         ProfScope ps(c, "visc", 60.0 * nf + fluid_list_bytes(c));
-        HIP_TRY(c, sph::launch_visc_precond(nf, c->x, c->rho, c->nlist, c->ncnt, c->kc, dt, mu, c->Pinv, s));
+        if (c->tiled)
+            HIP_TRY(c, sph::launch_visc_precond_t(tile_lists(c), nf, c->x, c->rho, c->kc, dt, mu, c->Pinv, s));
+        else
+            HIP_TRY(c, sph::launch_visc_precond(nf, c->x, c->rho, c->nlist, c->ncnt, c->kc, dt, mu, c->Pinv, s));
     }
     {
         ProfScope ps(c, "visc", 44.0 * nf + fluid_list_bytes(c));
-        HIP_TRY(c, sph::launch_visc_matvec(nf, c->x, c->rho, c->v2, c->cg_Ap, c->nlist, c->ncnt, c->kc, dt, mu, s));
+        HIP_TRY(c, visc_matvec(c, c->v2, c->cg_Ap, dt, mu));
     }
     HIP_TRY(c, sph::launch_axpy_residual(nf, c->cg_b, c->cg_Ap, c->cg_r, s));
     HIP_TRY(c, sph::launch_apply_precond(nf, c->Pinv, c->cg_r, c->cg_z, s));
@@ -460,7 +511,7 @@ int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
     while (rnorm > c->P.cg_tol * bnorm && it < c->P.cg_max_iters) {
         {
             ProfScope ps(c, "visc", 44.0 * nf + fluid_list_bytes(c));
-            HIP_TRY(c, sph::launch_visc_matvec(nf, c->x, c->rho, c->cg_p, c->cg_Ap, c->nlist, c->ncnt, c->kc, dt, mu, s));
+            HIP_TRY(c, visc_matvec(c, c->cg_p, c->cg_Ap, dt, mu));
         }
         HIP_TRY(c, sph::launch_dot(nf, c->cg_p, c->cg_Ap, c->red_part, pAp, s));
         HIP_TRY(c, sph::launch_cg_update(nf, c->v2, c->cg_r, c->cg_z, c->cg_p, c->cg_Ap, c->Pinv, rz, pAp,
@@ -511,8 +562,12 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     // 2. density, alpha; divergence warm-start set-up
     {
         ProfScope ps(c, "density_alpha", 80.0 * nf + list_bytes(c));
-        HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, c->nlist, c->ncnt, c->xb, c->blist, c->bcnt, c->kc,
-                                             c->rho, c->alpha, c->v_in, c->Kv, c->kappa, wf, s));
+        if (c->tiled)
+            HIP_TRY(c, sph::launch_density_alpha_t(tile_lists(c), nf, c->x, c->v, c->xb, c->kc, c->rho, c->alpha,
+                                                   c->v_in, c->Kv, c->kappa, wf, s));
+        else
+            HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, c->nlist, c->ncnt, c->xb, c->blist, c->bcnt, c->kc,
+                                                 c->rho, c->alpha, c->v_in, c->Kv, c->kappa, wf, s));
     }
     // 3. divergence-free solve
     if (warm) {
@@ -535,8 +590,14 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         if (setup_in_pass) HIP_TRY(c, sph::launch_warm_setup(nf, c->x, c->rho, c->K, c->kappa, wf, s));
     } else {
         ProfScope ps(c, "xsph", 72.0 * nf + fluid_list_bytes(c));
-        HIP_TRY(c, sph::launch_nonpressure(c->P.visc_model, nf, c->x, c->v, c->v2, c->rho, c->nlist, c->ncnt, c->kc,
-                                           dt, gx, gy, gz, (float)c->P.visc, c->K, c->kappa, wf, setup_in_pass, s));
+        if (c->tiled)
+            HIP_TRY(c, sph::launch_nonpressure_t(c->P.visc_model, tile_lists(c), nf, c->x, c->v, c->v2, c->rho, c->kc,
+                                                 dt, gx, gy, gz, (float)c->P.visc, c->K, c->kappa, wf, setup_in_pass,
+                                                 s));
+        else
+            HIP_TRY(c, sph::launch_nonpressure(c->P.visc_model, nf, c->x, c->v, c->v2, c->rho, c->nlist, c->ncnt,
+                                               c->kc, dt, gx, gy, gz, (float)c->P.visc, c->K, c->kappa, wf,
+                                               setup_in_pass, s));
         std::swap(c->v, c->v2);
     }
     // 5. warm start of the density solve: the previous stiffness, or the MLP's
@@ -547,8 +608,12 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         float *feat = tracing ? c->trace_feat + 5 * c->trace_rows : c->feat;
         {
             ProfScope ps(c, "warm_features", 56.0 * nf + list_bytes(c));
-            HIP_TRY(c, sph::launch_warm_features(nf, c->x, c->v, c->rho, c->alpha, c->K, c->nlist, c->ncnt, c->xb, c->vb,
-                                                 c->blist, c->bcnt, c->kc, dt, alpha_ref, feat, s));
+            if (c->tiled)
+                HIP_TRY(c, sph::launch_warm_features_t(tile_lists(c), nf, c->x, c->v, c->rho, c->alpha, c->K, c->xb,
+                                                       c->vb, c->kc, dt, alpha_ref, feat, s));
+            else
+                HIP_TRY(c, sph::launch_warm_features(nf, c->x, c->v, c->rho, c->alpha, c->K, c->nlist, c->ncnt, c->xb,
+                                                     c->vb, c->blist, c->bcnt, c->kc, dt, alpha_ref, feat, s));
         }
         if (learned) {
             {
@@ -576,8 +641,12 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     }
     // 7. rigid bodies: Eq. 14 reaction, FP64 Newton-Euler, new boundary pose
     if (c->nr > 0) {
-        HIP_TRY(c, sph::launch_rigid_force(nf, c->x, c->rho, c->K, c->Kv, c->blist, c->bcnt, c->xb, c->vb, c->kc,
-                                           c->nr, c->com_dev, c->red_part, c->rigid_out, s));
+        if (c->tiled)
+            HIP_TRY(c, sph::launch_rigid_force_t(tile_lists(c), nf, c->x, c->rho, c->K, c->Kv, c->xb, c->vb, c->kc,
+                                                 c->nr, c->com_dev, c->red_part, c->rigid_out, s));
+        else
+            HIP_TRY(c, sph::launch_rigid_force(nf, c->x, c->rho, c->K, c->Kv, c->blist, c->bcnt, c->xb, c->vb, c->kc,
+                                               c->nr, c->com_dev, c->red_part, c->rigid_out, s));
         std::vector<double> fo(6 * c->nr);
         HIP_TRY(c, hipMemcpyAsync(fo.data(), c->rigid_out, sizeof(double) * 6 * c->nr, hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
@@ -610,7 +679,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         st->converged_dens = ed <= c->P.eta_density;
         st->cg_iters = cg_it;
         st->cg_resid = cg_res;
-        st->nbr_min = (int32_t)(c->h_stats[0] == ~0ull ? 0 : c->h_stats[0]);
+        st->nbr_min = (int32_t)(c->h_stats[0] >= 0xffffffffull ? 0 : c->h_stats[0]);
         st->nbr_max = (int32_t)c->h_stats[1];
         st->nbr_mean = c->nf ? (double)c->h_stats[2] / (double)c->nf : 0.0;
         st->warm_fallback = c->warm_fallback ? 1 : 0;
@@ -724,6 +793,11 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     const int64_t nf = c->nf, nb = c->nb;
     const int64_t tiles = (ncell + 4095) / 4096;
     const int64_t nred = std::max<int64_t>(sph::reduction_blocks(std::max(nf, nb)), 8);
+    c->nrows = (int64_t)c->g.n[1] * c->g.n[2];
+    c->tiled = c->tile_capable = c->capf <= sph::kTileCapF && c->capb <= sph::kTileCapB;
+    c->max_t = c->tiled ? sph::max_tiles(nf, c->nrows) : 0;
+    const int64_t nstat_blocks = std::max<int64_t>(nred, c->tiled ? sph::tile_partials(c->max_t) : 0);
+    const int64_t red_blocks = std::max<int64_t>(nred, c->tiled ? sph::tile_partials(c->max_t) : 0);
     int rc = SPH_OK;
 #define ALLOC(ptr, n)                       \
     if ((rc = dev_alloc(c, &(ptr), (n)))) { \
@@ -742,9 +816,13 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     ALLOC(c->xb, nb); ALLOC(c->xb2, nb); ALLOC(c->vb, nb); ALLOC(c->vb2, nb); ALLOC(c->bid, nb); ALLOC(c->bid2, nb);
     ALLOC(c->bkey, nb); ALLOC(c->bslot, nb); ALLOC(c->bsrc, nb); ALLOC(c->blocal, 3 * nb);
     ALLOC(c->poses, std::max(1, c->nr)); ALLOC(c->com_dev, 3 * std::max(1, c->nr));
-    ALLOC(c->red_part, nred * 6 * std::max(1, c->nr) + 16); ALLOC(c->scal, 16); ALLOC(c->rigid_out, 6 * std::max(1, c->nr));
-    ALLOC(c->flags, 4); ALLOC(c->vmax_bits, 4); ALLOC(c->nstats, 4);
-    ALLOC(c->nstat_part, 4 * nred);
+    ALLOC(c->red_part, red_blocks * 6 * std::max(1, c->nr) + 16); ALLOC(c->scal, 16); ALLOC(c->rigid_out, 6 * std::max(1, c->nr));
+    ALLOC(c->flags, 4); ALLOC(c->vmax_bits, 4); ALLOC(c->nstats, sph::kNStats);
+    ALLOC(c->nstat_part, sph::kNStats * nstat_blocks);
+    if (c->tiled) {
+        ALLOC(c->tiles, c->max_t); ALLOC(c->tilecnt, c->nrows + 1); ALLOC(c->tileoff, c->nrows + 1);
+        ALLOC(c->l16, (int64_t)c->capf * nf); ALLOC(c->b16, (int64_t)c->capb * nf);
+    }
     ALLOC(c->feat, 5 * nf); ALLOC(c->ybuf, nf);
     if (p->visc_model == SPH_VISC_IMPLICIT) {
         ALLOC(c->Pinv, 9 * nf); ALLOC(c->cg_b, nf); ALLOC(c->cg_r, nf); ALLOC(c->cg_z, nf); ALLOC(c->cg_p, nf);
@@ -753,7 +831,7 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
 #undef ALLOC
     if (hipHostMalloc((void **)&c->h_scal, 16 * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->h_u32, 16 * sizeof(uint32_t)) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_stats, 4 * sizeof(unsigned long long)) != hipSuccess) {
+        hipHostMalloc((void **)&c->h_stats, sph::kNStats * sizeof(unsigned long long)) != hipSuccess) {
         free_all(c);
         delete c;
         return fail(nullptr, SPH_ERR_OOM, "pinned host allocation failed");
@@ -858,6 +936,9 @@ int sph_get_info(const sph_ctx *c, sph_info *info) {
     info->max_neighbors = c->capf;
     info->max_boundary_neighbors = c->capb;
     info->device_bytes = c->dev_bytes;
+    info->tiled = c->tiled ? 1 : 0;
+    info->n_tiles = c->ntiles;
+    info->n_tiles_overfull = c->n_over;
     return SPH_OK;
 }
 
@@ -1054,24 +1135,54 @@ int sph_read_neighbors(sph_ctx *c, const sph_nbr_view *d) {
     if (d->start_b)
         HIP_TRY(c, hipMemcpyAsync(d->start_b, c->start_b, sizeof(uint32_t) * (c->ncell + 1), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    auto csr = [&](const uint32_t *dev, int32_t cap, const std::vector<uint32_t> &n, uint32_t *counts, uint32_t *out,
-                   int64_t outcap) -> int {
+    std::vector<sph::TileDesc> tiles((size_t)std::max<int64_t>(c->ntiles, 1));
+    if (c->tiled && c->ntiles > 0) {
+        HIP_TRY(c, hipMemcpyAsync(tiles.data(), c->tiles, sizeof(sph::TileDesc) * c->ntiles, hipMemcpyDeviceToHost,
+                                  c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    // Lists as sorted indices; a tiled list entry is a slot, mapped back
+    // through its tile's ranges (slot - off[r] + first[r] for the range r
+    // holding it), and over-full tiles hold sorted indices already.
+    auto csr = [&](const uint32_t *dev, const uint16_t *dev16, bool fluid, int32_t cap,
+                   const std::vector<uint32_t> &n, uint32_t *counts, uint32_t *out, int64_t outcap) -> int {
         int64_t tot = 0;
         for (int64_t s = 0; s < nf; ++s) tot += std::min<uint32_t>(n[s], (uint32_t)cap);
         if (counts)
             for (int64_t s = 0; s < nf; ++s) counts[s] = n[s];
         if (!out) return SPH_OK;
         if (tot > outcap) return fail(c, SPH_ERR_CAPACITY, "CSR capacity too small");
-        std::vector<uint32_t> L((size_t)std::max<int64_t>((int64_t)cap * nf, 1));
+        const size_t len = (size_t)std::max<int64_t>((int64_t)cap * nf, 1);
+        std::vector<uint32_t> L(len);
         HIP_TRY(c, hipMemcpyAsync(L.data(), dev, sizeof(uint32_t) * (size_t)cap * nf, hipMemcpyDeviceToHost, c->stream));
+        std::vector<uint16_t> L16;
+        if (c->tiled) {
+            L16.resize(len);
+            HIP_TRY(c, hipMemcpyAsync(L16.data(), dev16, sizeof(uint16_t) * (size_t)cap * nf, hipMemcpyDeviceToHost,
+                                      c->stream));
+        }
         HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (c->tiled) {
+            for (int64_t t = 0; t < c->ntiles; ++t) {
+                const sph::TileDesc &T = tiles[t];
+                if (!T.ok) continue;
+                const int32_t *first = fluid ? T.fb : T.bb, *off = fluid ? T.foff : T.boff;
+                for (int64_t s = T.p0; s < T.p1; ++s)
+                    for (uint32_t k = 0; k < std::min<uint32_t>(n[s], (uint32_t)cap); ++k) {
+                        const int32_t q = L16[(size_t)k * nf + s];
+                        int r = 0;
+                        while (r < 8 && q >= off[r + 1]) ++r;
+                        L[(size_t)k * nf + s] = (uint32_t)(first[r] + (q - off[r]));
+                    }
+            }
+        }
         int64_t o = 0;
         for (int64_t s = 0; s < nf; ++s)
             for (uint32_t k = 0; k < std::min<uint32_t>(n[s], (uint32_t)cap); ++k) out[o++] = L[(size_t)k * nf + s];
         return SPH_OK;
     };
-    if ((rc = csr(c->nlist, c->capf, cnt, d->counts_f, d->lists_f, d->cap_f))) return rc;
-    if ((rc = csr(c->blist, c->capb, bcnt, d->counts_b, d->lists_b, d->cap_b))) return rc;
+    if ((rc = csr(c->nlist, c->l16, true, c->capf, cnt, d->counts_f, d->lists_f, d->cap_f))) return rc;
+    if ((rc = csr(c->blist, c->b16, false, c->capb, bcnt, d->counts_b, d->lists_b, d->cap_b))) return rc;
     return SPH_OK;
 }
 
@@ -1221,6 +1332,25 @@ int sph_set_forced_iters(sph_ctx *c, int32_t div, int32_t dens) {
     if (!c) return SPH_ERR_INVALID;
     c->forced_div = div;
     c->forced_dens = dens;
+    return SPH_OK;
+}
+
+int sph_set_tiling(sph_ctx *c, int32_t enable, int32_t slab_limit) {
+    if (!c) return SPH_ERR_INVALID;
+    c->err.clear();
+    if (enable && !c->tile_capable)
+        return fail(c, SPH_ERR_INVALID, "tiled lists need max_neighbors <= 64 and max_boundary_neighbors <= 48");
+    if (slab_limit < 0 || slab_limit > sph::kSlab)
+        return fail(c, SPH_ERR_INVALID, "slab_limit must lie in [0, 640]");
+    const int32_t lim = slab_limit == 0 ? sph::kSlab : slab_limit;
+    if ((enable != 0) != c->tiled || lim != c->slab_limit) {
+        c->tiled = enable != 0;
+        c->slab_limit = lim;
+        c->ntiles = 0;
+        c->n_over = 0;
+        c->over_entries = 0.0;
+        c->nbr_fresh = false;
+    }
     return SPH_OK;
 }
 

@@ -1,0 +1,213 @@
+// sph_device.h -- device helpers shared by the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sph_internal.h"
+
+namespace sph {
+namespace {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ uint32_t logical_block() {
+    const uint32_t b = blockIdx.x, per = gridDim.x >> 3;
+    return (b & 7u) * per + (b >> 3);
+}
+
+__device__ __forceinline__ int64_t particle_index() {
+    return (int64_t)logical_block() * kBlock + threadIdx.x;
+}
+
+inline uint32_t grid_blocks(int64_t n) {
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    return (uint32_t)((b + 7) & ~int64_t(7));   // a multiple of the 8 XCDs
+}
+
+// Cell coordinate: clamp(floor(fl32(fl32(x - o) * inv)), 0, n - 1); NaN -> 0.
+__device__ __forceinline__ int32_t cell_coord(float x, float o, float inv, int32_t n) {
+#pragma clang fp contract(off)
+    const float t = (x - o) * inv;
+    const float f = floorf(t);
+    if (!(f >= 0.0f)) return 0;
+    if (f > (float)(n - 1)) return n - 1;
+    return (int32_t)f;
+}
+
+__device__ __forceinline__ uint32_t cell_key(const Grid& g, float4 p) {
+    const int32_t cx = cell_coord(p.x, g.o[0], g.inv, g.n[0]);
+    const int32_t cy = cell_coord(p.y, g.o[1], g.inv, g.n[1]);
+    const int32_t cz = cell_coord(p.z, g.o[2], g.inv, g.n[2]);
+    return (uint32_t)(cx + g.n[0] * (cy + g.n[1] * cz));
+}
+
+// FP32 squared distance ((dx*dx + dy*dy) + dz*dz), no FMA: the neighbour predicate.
+__device__ __forceinline__ float dist2_exact(float4 a, float4 b) {
+#pragma clang fp contract(off)
+    const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    const float s = xx + yy;
+    return s + zz;
+}
+
+// Cubic spline (support h): grad_i W(x_ij) = grad_factor * x_ij.  Branch-free
+// (coincident particles select 0) so that neighbour loops can issue their
+// gathers ahead of the arithmetic; v_rsq_f32 directly (r^2 is never denormal
+// for distinct particles).
+__device__ __forceinline__ float inv_dist(float r2) { return r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f; }
+
+__device__ __forceinline__ float grad_factor(float r2, const Kern& kc) {
+    const float rinv = inv_dist(r2);
+    const float q = r2 * rinv * kc.inv_h;
+    const float t = fmaxf(1.0f - q, 0.0f);
+    const float fp = q <= 0.5f ? q * (3.0f * q - 2.0f) : -t * t;
+    return kc.kg * fp * rinv;
+}
+
+__device__ __forceinline__ float kernel_W(float r2, const Kern& kc) {
+    const float q = r2 * inv_dist(r2) * kc.inv_h;
+    const float t = fmaxf(1.0f - q, 0.0f);
+    return q <= 0.5f ? kc.k * (6.0f * q * q * (q - 1.0f) + 1.0f) : kc.k * 2.0f * t * t * t;
+}
+
+// Visit the first n entries of particle i's neighbour-major list in chunks of
+// four: the four list loads, then the four gathers done by `f`, are issued
+// before any of the arithmetic, so each wave keeps several gathers in flight.
+template <class F>
+__device__ __forceinline__ void for_each_nbr(const uint32_t* __restrict__ list, int64_t nf, int64_t i, uint32_t n,
+                                             F&& f) {
+    const uint32_t* p = list + i;
+    uint32_t k = 0;
+    for (; k + 4 <= n; k += 4) {
+        const uint32_t j0 = p[0], j1 = p[nf], j2 = p[2 * nf], j3 = p[3 * nf];
+        p += 4 * nf;
+        f(j0);
+        f(j1);
+        f(j2);
+        f(j3);
+    }
+    for (; k < n; ++k) {
+        f(*p);
+        p += nf;
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Block-wide FP64 sum in a fixed order; the result is valid in thread 0.
+__device__ double block_sum(double v) {
+    __shared__ double ws[kBlock / 64];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        r = ws[0];
+        for (int w = 1; w < kBlock / 64; ++w) r += ws[w];
+    }
+    __syncthreads();
+    return r;
+}
+
+// Reductions are two-phase: every workgroup stores its partial with a plain
+// store, and a one-workgroup finishing kernel sums the partials in workgroup
+// order.  The kernel boundary orders the two phases; no device-scope fence or
+// atomic is needed (an agent-scope fence on the multi-XCD part writes back the
+// XCD's L2, which costs far more than one extra launch).
+__global__ void k_finish_f64(const double* __restrict__ partials, int nblk, int nout, double* __restrict__ out) {
+    for (int o = 0; o < nout; ++o) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partials[(size_t)b * nout + o];
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) out[o] = acc;
+    }
+}
+
+// neighbour statistics per workgroup (kNStats fields): min, max, then sums
+__global__ void k_finish_nstats(const unsigned long long* __restrict__ partials, int nblk,
+                                unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long s[kNStats][kBlock];
+    unsigned long long a[kNStats];
+    a[0] = ~0ull;
+    for (int f = 1; f < kNStats; ++f) a[f] = 0ull;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) {
+        const unsigned long long* p = partials + (size_t)kNStats * b;
+        a[0] = min(a[0], p[0]);
+        a[1] = max(a[1], p[1]);
+        for (int f = 2; f < kNStats; ++f) a[f] += p[f];
+    }
+    for (int f = 0; f < kNStats; ++f) s[f][threadIdx.x] = a[f];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s[0][threadIdx.x] = min(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+            s[1][threadIdx.x] = max(s[1][threadIdx.x], s[1][threadIdx.x + w]);
+            for (int f = 2; f < kNStats; ++f) s[f][threadIdx.x] += s[f][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < kNStats) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk, uint32_t* __restrict__ out) {
+    __shared__ uint32_t s[kBlock];
+    uint32_t m = 0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) m = max(m, partials[b]);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+
+// As for_each_nbr over 16-bit LDS slots.
+template <class F>
+__device__ __forceinline__ void for_each_slot(const uint16_t* __restrict__ list, int64_t nf, int64_t i, uint32_t n,
+                                              F&& f) {
+    const uint16_t* p = list + i;
+    uint32_t k = 0;
+    for (; k + 4 <= n; k += 4) {
+        const uint32_t j0 = p[0], j1 = p[nf], j2 = p[2 * nf], j3 = p[3 * nf];
+        p += 4 * nf;
+        f(j0);
+        f(j1);
+        f(j2);
+        f(j3);
+    }
+    for (; k < n; ++k) {
+        f((uint32_t)*p);
+        p += nf;
+    }
+}
+
+// Append the candidates c in [b, e) (ascending) with c != skip and the FP32
+// predicate d^2 < h^2 to row i of the neighbour-major list; candidates are
+// loaded four at a time ahead of the tests.
+__device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, uint32_t b, uint32_t e, float4 xi,
+                                                int64_t i, int64_t skip, float h2, uint32_t* __restrict__ list,
+                                                int64_t nf, int32_t cap, uint32_t& cnt) {
+    auto take = [&](uint32_t c, float4 p) {
+        if ((int64_t)c != skip && dist2_exact(xi, p) < h2) {
+            if (cnt < (uint32_t)cap) list[(int64_t)cnt * nf + i] = c;
+            ++cnt;
+        }
+    };
+    uint32_t c = b;
+    for (; c + 4 <= e; c += 4) {
+        const float4 p0 = pos[c], p1 = pos[c + 1], p2 = pos[c + 2], p3 = pos[c + 3];
+        take(c, p0);
+        take(c + 1, p1);
+        take(c + 2, p2);
+        take(c + 3, p3);
+    }
+    for (; c < e; ++c) take(c, pos[c]);
+}
+
+}  // namespace
+}  // namespace sph
