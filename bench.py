@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--arm", choices=("plain", "learned", "both"), default="both",
                     help="warm start of the density solve: previous-step (plain) and/or the trained MLP")
-    ap.add_argument("--layout", choices=("tiled", "untiled"), default="tiled",
+    ap.add_argument("--layout", choices=("tiled", "untiled"), default="untiled",
                     help="neighbour passes over LDS-staged cell-row tiles or one thread per particle")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")

@@ -250,12 +250,13 @@ int sph_read_neighbors(sph_ctx *ctx, const sph_nbr_view *dst);
 int sph_set_forced_iters(sph_ctx *ctx, int32_t div, int32_t dens);
 
 /* Execution layout of the neighbour passes (no effect on the results beyond
- * the order of the FP64 partial sums).  enable = 1 (the default when
- * max_neighbors <= 64 and max_boundary_neighbors <= 48): fluid particles are
- * processed in tiles of up to 128 consecutive sorted particles of one row of
- * cells; each pass stages the tile's stencil in LDS one z-slab at a time and
- * the lists hold 16-bit slots into that staging.  enable = 0: one thread per
- * particle over 32-bit sorted-index lists, gathers from global memory.
+ * the order of the FP64 partial sums).  enable = 0 (the default): one thread
+ * per particle over 32-bit sorted-index lists, gathers from global memory.
+ * enable = 1 (only when max_neighbors <= 64 and max_boundary_neighbors <=
+ * 48; allocates the tile buffers on first use): fluid particles are processed
+ * in tiles of up to 128 consecutive sorted particles of one row of cells; each
+ * pass stages the tile's stencil in LDS one z-slab at a time and the lists
+ * hold 16-bit slots into that staging.
  * slab_limit (0 = the default 640, at most 640) is the most particles of one
  * set a tile may stage per z-slab; tiles above it keep 32-bit lists and
  * global gathers (sph_info.n_tiles_overfull counts them).  A change

@@ -774,6 +774,10 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     out->err_div = err_v;
     out->S_err_div = S_err_v;
     out->converged_div = err_v <= p->eta_divergence;
+    /* the divergence of the solve's final velocity feeds the learned warm start */
+    double *d_div = malloc(s1), *Sd_div = malloc(s1);
+    memcpy(d_div, d, s1);
+    memcpy(Sd_div, Sd, s1);
 
     /* -- 6. non-pressure accelerations (Algorithm 1, first two lines):
      *    gravity plus XSPH, Eq. (15), or the implicit solve of Eqs. (16)-(19). */
@@ -849,25 +853,27 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     /* -- 7. warm start of the density solve (Algorithm 2, "initialize p^l"):
      *    K0 = 0, warm_factor * K_prev, or the learned prediction
      *    max(0, y alpha rho0 / dt^2) of the step's final stiffness, y = MLP of
-     *    five dimensionless features; the target is K_final dt^2 / (alpha rho0). */
+     *    five dimensionless features; the target is K_final dt^2 / (alpha rho0).
+     *    Features: (rho - rho0)/rho0, dt d/rho0 with d the divergence of the
+     *    divergence-free solve's final velocity (its last predict), (n_f +
+     *    n_b)/26, K_prev dt^2/(alpha rho0), alpha/alpha_ref. */
     const double alpha_ref = 2.35376 * (2.0 * p->r) * (2.0 * p->r) / p->rho0;
     double *feat = NULL, *Sfeat = NULL;
     if (p->warm_start == 2 || out->features) {
         feat = malloc(sizeof(double) * 5 * (nf ? nf : 1));
         Sfeat = malloc(sizeof(double) * 5 * (nf ? nf : 1));
-        divergence(w, w->v, w->Sv, d, Sd);   /* divergence of v* */
         for (int64_t i = 0; i < nf; ++i) {
             int64_t n_i = (w->ff.start[i + 1] - w->ff.start[i]) + (w->fb.start[i + 1] - w->fb.start[i]);
             double a = w->alpha[i];
             feat[5 * i + 0] = (w->rho[i] - p->rho0) / p->rho0;
-            feat[5 * i + 1] = dt * d[i] / p->rho0;
+            feat[5 * i + 1] = dt * d_div[i] / p->rho0;
             feat[5 * i + 2] = (double)n_i / 26.0;
             feat[5 * i + 3] = a > 0.0 ? (double)in->K[i] * dt * dt / (a * p->rho0) : 0.0;
             feat[5 * i + 4] = a / alpha_ref;
             {
                 double *S = Sfeat + 5 * i;
                 S[0] = (w->rho[i] + p->rho0) / p->rho0;
-                S[1] = dt * Sd[i] / p->rho0;
+                S[1] = dt * Sd_div[i] / p->rho0;
                 S[2] = 0.0;
                 S[3] = a > 0.0 ? fabs(feat[5 * i + 3]) * (1.0 + w->Salpha[i] / a) : 0.0;
                 S[4] = w->Salpha[i] / alpha_ref;
@@ -1074,6 +1080,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     free(feat);
     free(Sfeat);
     free(rs); free(Srs); free(vs); free(Svs);
+    free(d_div); free(Sd_div);
     free(v_in); free(d); free(Sd); free(kap); free(Skap); free(Kv); free(SKv); free(K); free(SK);
     free(kappa_last); free(Skappa_last);
     free(w->x); free(w->v); free(w->Sv); free(w->xb); free(w->vb); free(w->psi);

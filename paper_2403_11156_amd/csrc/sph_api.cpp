@@ -66,7 +66,7 @@ struct sph_ctx {
     int64_t nrows = 0, max_t = 0, ntiles = 0, n_over = 0;
     double over_entries = 0.0;
     sph::TileDesc *tiles = nullptr;
-    uint32_t *tilecnt = nullptr, *tileoff = nullptr;
+    uint32_t *tilecnt = nullptr, *tileoff = nullptr, *tilerow = nullptr;
     uint16_t *l16 = nullptr, *b16 = nullptr;
     // boundary, sorted order (xb.w = Psi, vb.w = body id)
     float4 *xb = nullptr, *xb2 = nullptr, *vb = nullptr, *vb2 = nullptr;
@@ -77,6 +77,8 @@ struct sph_ctx {
     double *com_dev = nullptr;
     // reductions and flags
     double *red_part = nullptr, *scal = nullptr, *rigid_out = nullptr;
+    sph::SolveCtl *ctl = nullptr, *h_ctl = nullptr;   // device control block, pinned host copy
+    int32_t last_iters[2] = {0, 0};                   // previous step's iterations (divergence, density)
     uint32_t *flags = nullptr, *vmax_bits = nullptr;
     unsigned long long *nstats = nullptr, *nstat_part = nullptr;
     // implicit viscosity
@@ -106,6 +108,8 @@ struct sph_ctx {
     sph_mlp *mlp = nullptr;
     bool warm_fallback = false;
     float *feat = nullptr, *ybuf = nullptr;
+    float *dbuf = nullptr;   // divergence after the divergence-free solve (learned features)
+    bool want_d = false;
     float *trace_feat = nullptr, *trace_target = nullptr;
     int64_t trace_cap = 0, trace_rows = 0;
 
@@ -156,9 +160,11 @@ void free_all(sph_ctx *c) {
     if (c->h_scal) (void)hipHostFree(c->h_scal);
     if (c->h_u32) (void)hipHostFree(c->h_u32);
     if (c->h_stats) (void)hipHostFree(c->h_stats);
+    if (c->h_ctl) (void)hipHostFree(c->h_ctl);
     c->h_scal = nullptr;
     c->h_u32 = nullptr;
     c->h_stats = nullptr;
+    c->h_ctl = nullptr;
     for (auto &e : c->prof_pending) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
@@ -376,7 +382,7 @@ int build(sph_ctx *c) {
         {
             ProfScope ps(c, "tiles", 8.0 * c->nrows + 18.0 * 4.0 * c->nrows + sizeof(sph::TileDesc) * (double)c->ntiles);
             HIP_TRY(c, sph::launch_tiles_build(c->x, c->start_f, c->start_b, c->g, c->slab_limit, c->tilecnt,
-                                               c->tileoff, c->scan_part, c->tiles, s));
+                                               c->tileoff, c->tilerow, c->max_t, c->scan_part, c->tiles, s));
         }
         ProfScope ps(c, "nbr_build", 16.0 * c->nf + 8.0 * c->nf + list_bytes(c));
         HIP_TRY(c, sph::launch_nbr_build_tiled(c->tiles, c->tileoff + c->nrows, c->max_t, c->x, c->nf, c->xb,
@@ -411,62 +417,76 @@ int build(sph_ctx *c) {
     return SPH_OK;
 }
 
-// read one FP64 scalar of the device scratch after the stream drains
-int read_scalar(sph_ctx *c, const double *dev, double *out) {
-    HIP_TRY(c, hipMemcpyAsync(c->h_scal, dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    *out = c->h_scal[0];
-    return SPH_OK;
-}
-
-int pressure_pass(sph_ctx *c, float *Kacc, float *klast, float dt) {
+// go (nullable): skip the pass on the device once the solve needs no more
+// iterations.
+int pressure_pass(sph_ctx *c, float *Kacc, float *klast, float dt, const int32_t *go) {
     ProfScope ps(c, "pressure_update", (48.0 + (klast ? 24.0 : 20.0)) * c->nf + list_bytes(c));
     if (c->tiled)
         HIP_TRY(c, sph::launch_pressure_update_t(tile_lists(c), c->nf, c->x, c->v, c->kappa, Kacc, klast, c->xb, c->kc,
-                                                 dt, c->stream));
+                                                 dt, go, c->stream));
     else
         HIP_TRY(c, sph::launch_pressure_update(c->nf, c->x, c->v, c->kappa, Kacc, klast, c->nlist, c->ncnt, c->xb,
-                                               c->blist, c->bcnt, c->kc, dt, c->stream));
+                                               c->blist, c->bcnt, c->kc, dt, go, c->stream));
     return SPH_OK;
 }
 
-int predict_pass(sph_ctx *c, int mode, float dt, double *err_sum) {
-    {
-        ProfScope ps(c, "predict", 56.0 * c->nf + list_bytes(c));
-        if (c->tiled)
-            HIP_TRY(c, sph::launch_predict_t(mode, tile_lists(c), c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->xb,
-                                             c->vb, c->kc, dt, c->red_part, c->scal, c->stream));
-        else
-            HIP_TRY(c, sph::launch_predict(mode, c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->nlist, c->ncnt,
-                                           c->xb, c->vb, c->blist, c->bcnt, c->kc, dt, c->red_part, c->scal,
-                                           c->stream));
-    }
-    return read_scalar(c, c->scal, err_sum);
+int predict_pass(sph_ctx *c, int mode, float dt, bool first) {
+    float *dout = (mode == 0 && c->want_d) ? c->dbuf : nullptr;
+    ProfScope ps(c, "predict", (56.0 + (dout ? 4.0 : 0.0)) * c->nf + list_bytes(c));
+    if (c->tiled)
+        HIP_TRY(c, sph::launch_predict_t(mode, tile_lists(c), c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->xb,
+                                         c->vb, c->kc, dt, c->red_part, c->ctl, first, dout, c->stream));
+    else
+        HIP_TRY(c, sph::launch_predict(mode, c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->nlist, c->ncnt, c->xb,
+                                       c->vb, c->blist, c->bcnt, c->kc, dt, c->red_part, c->ctl, first, dout,
+                                       c->stream));
+    return SPH_OK;
 }
 
 // One Jacobi solve (Algorithm 2): stop when err <= eta, or after max_iters,
-// or after exactly `forced` iterations when forced >= 0.
+// or after exactly `forced` iterations when forced >= 0.  The stop rule runs
+// on the device (SolveCtl): the host queues iterations in batches, sized by
+// the previous step's count for this solve, and reads the control block once
+// per batch; passes of iterations past the stop do nothing.
 int jacobi_solve(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, int32_t forced, double eta,
                  int32_t *iters, double *err_out) {
+    hipStream_t s = c->stream;
     const double N = (double)std::max<int64_t>(c->nf, 1);
     const double scale = mode == 0 ? (double)dt / c->P.rho0 / N : 1.0 / (c->P.rho0 * N);
-    double sum = 0.0;
-    int rc = predict_pass(c, mode, dt, &sum);
+    const int32_t cap = forced >= 0 ? forced : std::max(c->P.max_iters, 0);
+    HIP_TRY(c, sph::launch_solve_init(c->ctl, scale, eta, forced, c->P.max_iters, s));
+    int rc = predict_pass(c, mode, dt, true);
     if (rc) return rc;
-    double err = sum * scale;
-    int32_t l = 0;
+    const size_t mark = c->prof_pending.size();
+    int32_t queued = 0;
+    int32_t batch = std::min(c->last_iters[mode], cap);
+    sph::SolveCtl h{};
     for (;;) {
-        const bool go = forced >= 0 ? (l < forced) : (err > eta && l < c->P.max_iters);
-        if (!go) break;
-        rc = pressure_pass(c, Kacc, klast, dt);
-        if (rc) return rc;
-        ++l;
-        rc = predict_pass(c, mode, dt, &sum);
-        if (rc) return rc;
-        err = sum * scale;
+        for (int32_t k = 0; k < batch; ++k) {
+            rc = pressure_pass(c, Kacc, klast, dt, &c->ctl->go);
+            if (rc) return rc;
+            rc = predict_pass(c, mode, dt, false);
+            if (rc) return rc;
+        }
+        queued += batch;
+        HIP_TRY(c, hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(sph::SolveCtl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        h = *c->h_ctl;
+        if (!h.go || queued >= cap) break;
+        batch = std::min<int32_t>(queued < 2 ? 1 : 2, cap - queued);
     }
-    *iters = l;
-    *err_out = err;
+    // drop the timing records of queued passes that did nothing
+    if (c->prof && c->prof_pending.size() > mark) {
+        const size_t keep = mark + 2 * (size_t)h.iters;
+        for (size_t q = keep; q < c->prof_pending.size(); ++q) {
+            c->event_pool.push_back(c->prof_pending[q].a);
+            c->event_pool.push_back(c->prof_pending[q].b);
+        }
+        if (keep < c->prof_pending.size()) c->prof_pending.resize(keep);
+    }
+    c->last_iters[mode] = h.iters;
+    *iters = h.iters;
+    *err_out = h.err;
     return SPH_OK;
 }
 
@@ -558,6 +578,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     const float wf = warm ? (float)c->P.warm_factor : 0.0f;
     const bool learned = c->warm_mode == SPH_WARM_LEARNED && c->mlp != nullptr;
     const bool tracing = c->trace_feat != nullptr && c->trace_rows + nf <= c->trace_cap;
+    c->want_d = learned || tracing;
 
     // 2. density, alpha; divergence warm-start set-up
     {
@@ -571,7 +592,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     }
     // 3. divergence-free solve
     if (warm) {
-        int rc = pressure_pass(c, c->Kv, nullptr, dt);
+        int rc = pressure_pass(c, c->Kv, nullptr, dt, nullptr);
         if (rc) return rc;
     }
     int32_t iv = 0, id = 0;
@@ -601,19 +622,16 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         std::swap(c->v, c->v2);
     }
     // 5. warm start of the density solve: the previous stiffness, or the MLP's
-    //    prediction from per-particle features of v* (features also feed the
-    //    training trace)
+    //    prediction from per-particle features (density, the divergence left
+    //    by the divergence-free solve, neighbour count, previous stiffness,
+    //    alpha); the features also feed the training trace
     if (!setup_in_pass) {
         const float alpha_ref = (float)(2.35376 * 4.0 * c->P.r * c->P.r / c->P.rho0);
         float *feat = tracing ? c->trace_feat + 5 * c->trace_rows : c->feat;
         {
-            ProfScope ps(c, "warm_features", 56.0 * nf + list_bytes(c));
-            if (c->tiled)
-                HIP_TRY(c, sph::launch_warm_features_t(tile_lists(c), nf, c->x, c->v, c->rho, c->alpha, c->K, c->xb,
-                                                       c->vb, c->kc, dt, alpha_ref, feat, s));
-            else
-                HIP_TRY(c, sph::launch_warm_features(nf, c->x, c->v, c->rho, c->alpha, c->K, c->nlist, c->ncnt, c->xb,
-                                                     c->vb, c->blist, c->bcnt, c->kc, dt, alpha_ref, feat, s));
+            ProfScope ps(c, "warm_features", 28.0 * nf + 20.0 * nf);
+            HIP_TRY(c, sph::launch_features(nf, c->rho, c->alpha, c->K, c->ncnt, c->bcnt, c->dbuf, c->kc, dt, alpha_ref,
+                                            feat, s));
         }
         if (learned) {
             {
@@ -627,7 +645,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         }
     }
     if (warm) {
-        rc = pressure_pass(c, c->K, nullptr, dt);
+        rc = pressure_pass(c, c->K, nullptr, dt, nullptr);
         if (rc) return rc;
     }
     HIP_TRY(c, sph::launch_fill_f32(c->kappa_last, nf, 0.0f, s));
@@ -794,10 +812,13 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     const int64_t tiles = (ncell + 4095) / 4096;
     const int64_t nred = std::max<int64_t>(sph::reduction_blocks(std::max(nf, nb)), 8);
     c->nrows = (int64_t)c->g.n[1] * c->g.n[2];
-    c->tiled = c->tile_capable = c->capf <= sph::kTileCapF && c->capb <= sph::kTileCapB;
-    c->max_t = c->tiled ? sph::max_tiles(nf, c->nrows) : 0;
-    const int64_t nstat_blocks = std::max<int64_t>(nred, c->tiled ? sph::tile_partials(c->max_t) : 0);
-    const int64_t red_blocks = std::max<int64_t>(nred, c->tiled ? sph::tile_partials(c->max_t) : 0);
+    // one thread per particle by default; tiles on request (sph_set_tiling),
+    // their buffers allocated then
+    c->tile_capable = c->capf <= sph::kTileCapF && c->capb <= sph::kTileCapB;
+    c->tiled = false;
+    c->max_t = c->tile_capable ? sph::max_tiles(nf, c->nrows) : 0;
+    const int64_t nstat_blocks = std::max<int64_t>(nred, c->tile_capable ? sph::tile_partials(c->max_t) : 0);
+    const int64_t red_blocks = std::max<int64_t>(nred, c->tile_capable ? sph::tile_partials(c->max_t) : 0);
     int rc = SPH_OK;
 #define ALLOC(ptr, n)                       \
     if ((rc = dev_alloc(c, &(ptr), (n)))) { \
@@ -817,13 +838,10 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     ALLOC(c->bkey, nb); ALLOC(c->bslot, nb); ALLOC(c->bsrc, nb); ALLOC(c->blocal, 3 * nb);
     ALLOC(c->poses, std::max(1, c->nr)); ALLOC(c->com_dev, 3 * std::max(1, c->nr));
     ALLOC(c->red_part, red_blocks * 6 * std::max(1, c->nr) + 16); ALLOC(c->scal, 16); ALLOC(c->rigid_out, 6 * std::max(1, c->nr));
+    ALLOC(c->ctl, 1);
     ALLOC(c->flags, 4); ALLOC(c->vmax_bits, 4); ALLOC(c->nstats, sph::kNStats);
     ALLOC(c->nstat_part, sph::kNStats * nstat_blocks);
-    if (c->tiled) {
-        ALLOC(c->tiles, c->max_t); ALLOC(c->tilecnt, c->nrows + 1); ALLOC(c->tileoff, c->nrows + 1);
-        ALLOC(c->l16, (int64_t)c->capf * nf); ALLOC(c->b16, (int64_t)c->capb * nf);
-    }
-    ALLOC(c->feat, 5 * nf); ALLOC(c->ybuf, nf);
+    ALLOC(c->feat, 5 * nf); ALLOC(c->ybuf, nf); ALLOC(c->dbuf, nf);
     if (p->visc_model == SPH_VISC_IMPLICIT) {
         ALLOC(c->Pinv, 9 * nf); ALLOC(c->cg_b, nf); ALLOC(c->cg_r, nf); ALLOC(c->cg_z, nf); ALLOC(c->cg_p, nf);
         ALLOC(c->cg_Ap, nf);
@@ -831,7 +849,8 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
 #undef ALLOC
     if (hipHostMalloc((void **)&c->h_scal, 16 * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->h_u32, 16 * sizeof(uint32_t)) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_stats, sph::kNStats * sizeof(unsigned long long)) != hipSuccess) {
+        hipHostMalloc((void **)&c->h_stats, sph::kNStats * sizeof(unsigned long long)) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_ctl, sizeof(sph::SolveCtl)) != hipSuccess) {
         free_all(c);
         delete c;
         return fail(nullptr, SPH_ERR_OOM, "pinned host allocation failed");
@@ -1343,6 +1362,14 @@ int sph_set_tiling(sph_ctx *c, int32_t enable, int32_t slab_limit) {
     if (slab_limit < 0 || slab_limit > sph::kSlab)
         return fail(c, SPH_ERR_INVALID, "slab_limit must lie in [0, 640]");
     const int32_t lim = slab_limit == 0 ? sph::kSlab : slab_limit;
+    if (enable && !c->tiles) {
+        int rc;
+        if ((rc = dev_alloc(c, &c->tiles, c->max_t)) || (rc = dev_alloc(c, &c->tilecnt, c->nrows + 1)) ||
+            (rc = dev_alloc(c, &c->tileoff, c->nrows + 1)) || (rc = dev_alloc(c, &c->tilerow, c->max_t)) ||
+            (rc = dev_alloc(c, &c->l16, (int64_t)c->capf * c->nf)) ||
+            (rc = dev_alloc(c, &c->b16, (int64_t)c->capb * c->nf)))
+            return rc;
+    }
     if ((enable != 0) != c->tiled || lim != c->slab_limit) {
         c->tiled = enable != 0;
         c->slab_limit = lim;

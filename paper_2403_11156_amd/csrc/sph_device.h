@@ -126,6 +126,36 @@ __global__ void k_finish_f64(const double* __restrict__ partials, int nblk, int 
     }
 }
 
+// Jacobi solve control (Algorithm 2's stop rule on the device).
+__global__ void k_solve_init(SolveCtl* ctl, double scale, double eta, int32_t forced, int32_t max_iters) {
+    ctl->err = 0.0;
+    ctl->scale = scale;
+    ctl->eta = eta;
+    ctl->iters = 0;
+    ctl->go = 1;
+    ctl->forced = forced;
+    ctl->max_iters = max_iters;
+}
+
+// Finish of a predict pass: err = scale * (sum of the partials in workgroup
+// order); after an iteration's predict (not first) count the iteration; then
+// decide whether another one is due: exactly `forced` iterations, else while
+// err > eta and fewer than max_iters.  Nothing happens once go is 0.
+__global__ void k_finish_solve(const double* __restrict__ partials, int nblk, SolveCtl* ctl, bool first) {
+    const int32_t go = ctl->go;
+    if (!first && go == 0) return;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partials[b];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) {
+        const double err = acc * ctl->scale;
+        const int32_t it = ctl->iters + (first ? 0 : 1);
+        ctl->err = err;
+        ctl->iters = it;
+        ctl->go = ctl->forced >= 0 ? (it < ctl->forced ? 1 : 0) : ((err > ctl->eta && it < ctl->max_iters) ? 1 : 0);
+    }
+}
+
 // neighbour statistics per workgroup (kNStats fields): min, max, then sums
 __global__ void k_finish_nstats(const unsigned long long* __restrict__ partials, int nblk,
                                 unsigned long long* __restrict__ out) {

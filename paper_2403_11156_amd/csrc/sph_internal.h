@@ -46,6 +46,19 @@ struct TileDesc {
     int32_t bb[9], boff[10];   // boundary ranges
 };
 
+// Device-side state of one Jacobi solve (Algorithm 2): the host queues
+// iterations ahead and every pass of an iteration that is no longer due
+// returns at once, so the stop rule needs no host round trip per iteration.
+struct SolveCtl {
+    double err;          // error after the last predict pass
+    double scale;        // err = scale * (FP64 sum of the clamped deviations)
+    double eta;
+    int32_t iters;       // iterations done
+    int32_t go;          // 1 while another iteration is due
+    int32_t forced;      // >= 0: exactly this many iterations
+    int32_t max_iters;
+};
+
 // Pose of one rigid body for the boundary update (FP64).
 struct BodyPose {
     double com[3];
@@ -89,17 +102,27 @@ hipError_t launch_density_alpha(int64_t nf, float4* x, const float4* v, const ui
                                 const uint32_t* ncnt, const float4* xb, const uint32_t* blist,
                                 const uint32_t* bcnt, Kern kc, float* rho, float* alpha, float4* v_in,
                                 float* Kv, float* kappa, float warm_factor, hipStream_t s);
+// go (nullable): the pass does nothing when *go == 0 (an iteration the
+// solve no longer needs).
 hipError_t launch_pressure_update(int64_t nf, const float4* x, float4* v, const float* kappa, float* Kacc,
                                   float* kappa_last, const uint32_t* nlist, const uint32_t* ncnt, const float4* xb,
                                   const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt,
-                                  hipStream_t s);
+                                  const int32_t* go, hipStream_t s);
 // mode 0: divergence (kappa = max(d,0) alpha / dt); mode 1: density
 // (kappa = max(rho - rho0 + dt d, 0) alpha / dt^2).  Writes kappa, kappa/rho
 // into x.w, and the FP64 sum of the clamped error into *err_out.
+// first: the solve's initial predict (always runs); otherwise the pass and
+// its finish do nothing once ctl->go == 0.  The finish updates ctl.  dout
+// (nullable, mode 0 only): the unclamped divergence d of every particle.
 hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, const float* rho, const float* alpha,
                           float* kappa, const uint32_t* nlist, const uint32_t* ncnt,
                           const float4* xb, const float4* vb, const uint32_t* blist, const uint32_t* bcnt,
-                          Kern kc, float dt, double* partials, double* err_out, hipStream_t s);
+                          Kern kc, float dt, double* partials, SolveCtl* ctl, bool first, float* dout,
+                          hipStream_t s);
+hipError_t launch_solve_init(SolveCtl* ctl, double scale, double eta, int32_t forced, int32_t max_iters,
+                             hipStream_t s);
+// one-workgroup finish of a predict pass over nblk partials (declared for the tiled launchers)
+hipError_t launch_solve_finish(const double* partials, int nblk, SolveCtl* ctl, bool first, hipStream_t s);
 // non-pressure: v* = v + dt g + viscosity; also sets up the density warm start
 // (kappa = warm_factor K, K = 0, x.w = kappa / rho).
 hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v, float4* vout, const float* rho,
@@ -139,10 +162,12 @@ hipError_t launch_gravity(int64_t nf, const float4* v, float4* out, float dt, fl
                           hipStream_t s);
 
 // learned warm start: the features pass, the learned stiffness, trace targets
-hipError_t launch_warm_features(int64_t nf, const float4* x, const float4* v, const float* rho, const float* alpha,
-                                const float* K, const uint32_t* nlist, const uint32_t* ncnt, const float4* xb,
-                                const float4* vb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt,
-                                float alpha_ref, float* feat, hipStream_t s);
+// learned-warm-start features from per-particle fields (no neighbour pass):
+// (rho - rho0)/rho0, dt d/rho0 (d from the divergence solve's last predict),
+// (n_f + n_b)/26, K_prev dt^2/(alpha rho0), alpha/alpha_ref; feat [nf][5]
+hipError_t launch_features(int64_t nf, const float* rho, const float* alpha, const float* K, const uint32_t* ncnt,
+                           const uint32_t* bcnt, const float* d, Kern kc, float dt, float alpha_ref, float* feat,
+                           hipStream_t s);
 hipError_t launch_warm_learned(int64_t nf, float4* x, const float* rho, const float* alpha, const float* y, float* K,
                                float* kappa, float dt, float rho0, hipStream_t s);
 hipError_t launch_trace_target(int64_t nf, const float* alpha, const float* K, float dt, float rho0, float* target,
@@ -162,9 +187,10 @@ hipError_t launch_mlp_adam(float* P, const float* grad, float* m, float* v, floa
 int64_t max_tiles(int64_t nf, int64_t nrows);
 // slab_limit (<= kSlab): the most particles of one set a tile may stage per
 // z-slab; tiles above it are marked over-full.
+// tilerow and tiles need max_t entries.
 hipError_t launch_tiles_build(const float4* x, const uint32_t* start_f, const uint32_t* start_b, Grid g,
-                              int32_t slab_limit, uint32_t* tilecnt, uint32_t* tileoff, uint32_t* scan_part,
-                              TileDesc* tiles, hipStream_t s);
+                              int32_t slab_limit, uint32_t* tilecnt, uint32_t* tileoff, uint32_t* tilerow,
+                              int64_t max_t, uint32_t* scan_part, TileDesc* tiles, hipStream_t s);
 // The tile count is read on the device (ntiles_dev = tileoff + nrows); the
 // launch covers max_t tiles and workgroups past the count only store neutral
 // statistics.  partials needs tile_partials(max_t) * 4 entries.
@@ -190,16 +216,15 @@ hipError_t launch_density_alpha_t(const Lists& L, int64_t nf, float4* x, const f
                                   float* rho, float* alpha, float4* v_in, float* Kv, float* kappa, float warm_factor,
                                   hipStream_t s);
 hipError_t launch_pressure_update_t(const Lists& L, int64_t nf, const float4* x, float4* v, const float* kappa,
-                                    float* Kacc, float* kappa_last, const float4* xb, Kern kc, float dt, hipStream_t s);
+                                    float* Kacc, float* kappa_last, const float4* xb, Kern kc, float dt,
+                                    const int32_t* go, hipStream_t s);
 hipError_t launch_predict_t(int mode, const Lists& L, int64_t nf, float4* x, const float4* v, const float* rho,
                             const float* alpha, float* kappa, const float4* xb, const float4* vb, Kern kc, float dt,
-                            double* partials, double* err_out, hipStream_t s);
+                            double* partials, SolveCtl* ctl, bool first, float* dout, hipStream_t s);
 hipError_t launch_nonpressure_t(int model, const Lists& L, int64_t nf, float4* x, const float4* v, float4* vout,
                                 const float* rho, Kern kc, float dt, float gx, float gy, float gz, float visc,
                                 float* K, float* kappa, float warm_factor, bool setup_warm, hipStream_t s);
-hipError_t launch_warm_features_t(const Lists& L, int64_t nf, const float4* x, const float4* v, const float* rho,
-                                  const float* alpha, const float* K, const float4* xb, const float4* vb, Kern kc,
-                                  float dt, float alpha_ref, float* feat, hipStream_t s);
+
 hipError_t launch_rigid_force_t(const Lists& L, int64_t nf, const float4* x, const float* rho, const float* K,
                                 const float* Kv, const float4* xb, const float4* vb, Kern kc, int32_t nbody,
                                 const double* com, double* partials, double* out, hipStream_t s);

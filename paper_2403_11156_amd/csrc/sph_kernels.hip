@@ -30,13 +30,34 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
 }
 
 // ------------------------------------------------------------------ counting sort
+// Cell key and a provisional rank within the cell (the rank order is erased by
+// the per-cell id sort).  The lanes of a wave that share a key (consecutive
+// particles are mostly in the same cell, the input being last step's order)
+// take one atomic per distinct key and rank among themselves by lane.
 __global__ void k_keys_hist(const float4* __restrict__ x, int64_t n, Grid g, uint32_t* __restrict__ key,
                             uint32_t* __restrict__ slot, uint32_t* __restrict__ count) {
     const int64_t i = particle_index();
-    if (i >= n) return;
-    const uint32_t k = cell_key(g, x[i]);
-    key[i] = k;
-    slot[i] = atomicAdd(count + k, 1u);
+    const bool valid = i < n;
+    uint32_t k = 0;
+    if (valid) {
+        k = cell_key(g, x[i]);
+        key[i] = k;
+    }
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t pending = __ballot(valid);
+    uint32_t rank = 0;
+    while (pending) {   // wave-uniform
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const uint32_t kl = (uint32_t)__shfl((int)k, leader, 64);
+        const uint64_t same = __ballot(valid && k == kl) & pending;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(count + kl, (uint32_t)__popcll(same));
+        base = (uint32_t)__shfl((int)base, leader, 64);
+        if ((same >> lane) & 1ull) rank = base + (uint32_t)__popcll(same & below);
+        pending &= ~same;
+    }
+    if (valid) slot[i] = rank;
 }
 
 constexpr int kScanItems = 16;
@@ -316,7 +337,8 @@ __global__ void __launch_bounds__(kBlock) k_pressure_update(
     int64_t nf, const float4* __restrict__ x, float4* __restrict__ v, const float* __restrict__ kappa,
     float* __restrict__ Kacc, float* __restrict__ kappa_last, const uint32_t* __restrict__ nlist,
     const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const uint32_t* __restrict__ blist,
-    const uint32_t* __restrict__ bcnt, Kern kc, float dt) {
+    const uint32_t* __restrict__ bcnt, Kern kc, float dt, const int32_t* __restrict__ go) {
+    if (go != nullptr && *go == 0) return;
     const int64_t i = particle_index();
     if (i >= nf) return;
     const float4 xi = x[i];
@@ -354,7 +376,8 @@ __global__ void __launch_bounds__(kBlock) k_predict(
     const float* __restrict__ alpha, float* __restrict__ kappa, const uint32_t* __restrict__ nlist,
     const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const float4* __restrict__ vb,
     const uint32_t* __restrict__ blist, const uint32_t* __restrict__ bcnt, Kern kc, float dt,
-    double* __restrict__ partials) {
+    double* __restrict__ partials, const int32_t* __restrict__ go, float* __restrict__ dout) {
+    if (go != nullptr && *go == 0) return;
     const int64_t i = particle_index();
     double e = 0.0;
     if (i < nf) {
@@ -379,6 +402,7 @@ __global__ void __launch_bounds__(kBlock) k_predict(
         const float ri = rho[i];
         float kap;
         if (MODE == 0) {
+            if (dout) dout[i] = d;
             const float ep = fmaxf(d, 0.0f);
             kap = ep * alpha[i] / dt;
             e = (double)ep;
@@ -445,40 +469,20 @@ __global__ void __launch_bounds__(kBlock) k_nonpressure(
 }
 
 // Learned warm start, features of each particle at the start of the density
-// solve: (rho - rho0)/rho0, dt d*/rho0 with d* the density change rate of v*,
-// (n_f + n_b)/26, K_prev dt^2/(alpha rho0), alpha/alpha_ref.
-__global__ void __launch_bounds__(kBlock) k_warm_features(
-    int64_t nf, const float4* __restrict__ x, const float4* __restrict__ v, const float* __restrict__ rho,
-    const float* __restrict__ alpha, const float* __restrict__ K, const uint32_t* __restrict__ nlist,
-    const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const float4* __restrict__ vb,
-    const uint32_t* __restrict__ blist, const uint32_t* __restrict__ bcnt, Kern kc, float dt, float alpha_ref,
-    float* __restrict__ feat) {
+// solve, from per-particle fields: (rho - rho0)/rho0, dt d/rho0 with d the
+// divergence after the divergence-free solve, (n_f + n_b)/26,
+// K_prev dt^2/(alpha rho0), alpha/alpha_ref.
+__global__ void k_features(int64_t nf, const float* __restrict__ rho, const float* __restrict__ alpha,
+                           const float* __restrict__ K, const uint32_t* __restrict__ ncnt,
+                           const uint32_t* __restrict__ bcnt, const float* __restrict__ d, Kern kc, float dt,
+                           float alpha_ref, float* __restrict__ feat) {
     const int64_t i = particle_index();
     if (i >= nf) return;
-    const float4 xi = x[i];
-    const float4 vi = v[i];
-    float d = 0.f;
-    const uint32_t nfc = ncnt[i], nbc = bcnt[i];
-    for_each_nbr(nlist, nf, i, nfc, [&](uint32_t j) {
-        const float4 xj = x[j];
-        const float4 vj = v[j];
-        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        d += grad_factor(r2, kc) * ((vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz);
-    });
-    d *= kc.m;
-    for_each_nbr(blist, nf, i, nbc, [&](uint32_t kk) {
-        const float4 xk = xb[kk];
-        const float4 vk = vb[kk];
-        const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        d += xk.w * grad_factor(r2, kc) * ((vi.x - vk.x) * dx + (vi.y - vk.y) * dy + (vi.z - vk.z) * dz);
-    });
     const float a = alpha[i];
     float* f = feat + 5 * i;
     f[0] = (rho[i] - kc.rho0) / kc.rho0;
-    f[1] = dt * d / kc.rho0;
-    f[2] = (float)(nfc + nbc) / 26.0f;
+    f[1] = dt * d[i] / kc.rho0;
+    f[2] = (float)(ncnt[i] + bcnt[i]) / 26.0f;
     f[3] = a > 0.0f ? K[i] * dt * dt / (a * kc.rho0) : 0.0f;
     f[4] = a / alpha_ref;
 }
@@ -848,23 +852,35 @@ hipError_t launch_density_alpha(int64_t nf, float4* x, const float4* v, const ui
 
 hipError_t launch_pressure_update(int64_t nf, const float4* x, float4* v, const float* kappa, float* Kacc,
                                   float* kappa_last, const uint32_t* nlist, const uint32_t* ncnt, const float4* xb,
-                                  const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt, hipStream_t s) {
+                                  const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt, const int32_t* go,
+                                  hipStream_t s) {
     if (nf <= 0) return hipSuccess;
-    LAUNCH(k_pressure_update, nf, nf, x, v, kappa, Kacc, kappa_last, nlist, ncnt, xb, blist, bcnt, kc, dt);
+    LAUNCH(k_pressure_update, nf, nf, x, v, kappa, Kacc, kappa_last, nlist, ncnt, xb, blist, bcnt, kc, dt, go);
 }
 
 hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, const float* rho, const float* alpha,
                           float* kappa, const uint32_t* nlist, const uint32_t* ncnt, const float4* xb,
                           const float4* vb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt,
-                          double* partials, double* err_out, hipStream_t s) {
+                          double* partials, SolveCtl* ctl, bool first, float* dout, hipStream_t s) {
     const uint32_t nblk = grid_blocks(nf);
+    const int32_t* go = first ? nullptr : &ctl->go;
     if (mode == 0)
         hipLaunchKernelGGL(k_predict<0>, dim3(nblk), dim3(kBlock), 0, s, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb,
-                           vb, blist, bcnt, kc, dt, partials);
+                           vb, blist, bcnt, kc, dt, partials, go, dout);
     else
         hipLaunchKernelGGL(k_predict<1>, dim3(nblk), dim3(kBlock), 0, s, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb,
-                           vb, blist, bcnt, kc, dt, partials);
-    hipLaunchKernelGGL(k_finish_f64, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, 1, err_out);
+                           vb, blist, bcnt, kc, dt, partials, go, nullptr);
+    return launch_solve_finish(partials, nf > 0 ? (int)nblk : 0, ctl, first, s);
+}
+
+hipError_t launch_solve_init(SolveCtl* ctl, double scale, double eta, int32_t forced, int32_t max_iters,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(1), 0, s, ctl, scale, eta, forced, max_iters);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_finish(const double* partials, int nblk, SolveCtl* ctl, bool first, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish_solve, dim3(1), dim3(kBlock), 0, s, partials, nblk, ctl, first);
     return hipGetLastError();
 }
 
@@ -883,14 +899,12 @@ hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v,
            warm_factor, setup_warm);
 }
 
-hipError_t launch_warm_features(int64_t nf, const float4* x, const float4* v, const float* rho, const float* alpha,
-                                const float* K, const uint32_t* nlist, const uint32_t* ncnt, const float4* xb,
-                                const float4* vb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt,
-                                float alpha_ref, float* feat, hipStream_t s) {
+hipError_t launch_features(int64_t nf, const float* rho, const float* alpha, const float* K, const uint32_t* ncnt,
+                           const uint32_t* bcnt, const float* d, Kern kc, float dt, float alpha_ref, float* feat,
+                           hipStream_t s) {
     if (nf <= 0) return hipSuccess;
-    LAUNCH(k_warm_features, nf, nf, x, v, rho, alpha, K, nlist, ncnt, xb, vb, blist, bcnt, kc, dt, alpha_ref, feat);
+    LAUNCH(k_features, nf, nf, rho, alpha, K, ncnt, bcnt, d, kc, dt, alpha_ref, feat);
 }
-
 hipError_t launch_warm_learned(int64_t nf, float4* x, const float* rho, const float* alpha, const float* y, float* K,
                                float* kappa, float dt, float rho0, hipStream_t s) {
     if (nf <= 0) return hipSuccess;

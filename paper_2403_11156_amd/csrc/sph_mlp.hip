@@ -32,11 +32,8 @@ static_assert(NPARAM == 4620, "parameter layout");
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ uint16_t to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// round to nearest even (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 __device__ __forceinline__ f32x16 mfma(bf16x4 a, bf16x4 b, f32x16 c) {
@@ -52,8 +49,11 @@ __device__ __forceinline__ bf16x4 pack4(const uint16_t* p) {
     return v;
 }
 
+// four consecutive bf16 at an 8-byte aligned LDS address, one 64-bit read
+__device__ __forceinline__ bf16x4 load4(const uint16_t* p) { return *reinterpret_cast<const bf16x4*>(p); }
+
 // Weights as bf16 in LDS: W1b[64][8] (k padded with zeros), W2b[64][64], W2t[64][64] (transposed)
-struct WeightsLDS {
+struct alignas(16) WeightsLDS {
     uint16_t W1b[H * 8];
     uint16_t W2b[H * H];
     uint16_t W2t[H * H];
@@ -88,6 +88,23 @@ __device__ void load_weights(WeightsLDS& W, const float* __restrict__ P, bool tr
     __syncthreads();
 }
 
+// A operands of layers 1 and 2 for this lane (row p of each 32-row tile,
+// k-chunk half h), held in registers across the tiles a wave processes.
+struct AOps {
+    bf16x4 w1[2];
+    bf16x4 w2[2][8];
+};
+
+__device__ __forceinline__ void load_aops(const WeightsLDS& W, AOps& a) {
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        a.w1[t] = load4(&W.W1b[(32 * t + p) * 8 + 4 * h]);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) a.w2[t][b] = load4(&W.W2b[(32 * t + p) * H + 8 * b + 4 * h]);
+    }
+}
+
 // Forward of one 32-sample tile in one wave.  lane = p + 32 h.
 struct Fwd {
     f32x16 z1[2], z2[2];   // pre-activations, transposed tiles (rows = hidden units)
@@ -97,8 +114,8 @@ struct Fwd {
     bf16x4 xb;             // normalised features as the layer-1 B operand
 };
 
-__device__ __forceinline__ void forward_tile(const WeightsLDS& W, const float* __restrict__ feat, int64_t n,
-                                             int64_t base, Fwd& f) {
+__device__ __forceinline__ void forward_tile(const WeightsLDS& W, const AOps& A, const float* __restrict__ feat,
+                                             int64_t n, int64_t base, Fwd& f) {
     const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
     const int64_t s = base + p;
     // features 4h..4h+3 of sample p, normalised in FP32 then rounded to bf16
@@ -120,8 +137,7 @@ __device__ __forceinline__ void forward_tile(const WeightsLDS& W, const float* _
         f32x16 c;
 #pragma unroll
         for (int r = 0; r < 16; ++r) c[r] = W.b1[32 * t + drow(r, h)];
-        const bf16x4 a = pack4(&W.W1b[(32 * t + p) * 8 + 4 * h]);
-        f.z1[t] = mfma(a, f.xb, c);
+        f.z1[t] = mfma(A.w1[t], f.xb, c);
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
             uint16_t q[4];
@@ -138,10 +154,7 @@ __device__ __forceinline__ void forward_tile(const WeightsLDS& W, const float* _
 #pragma unroll
         for (int r = 0; r < 16; ++r) c[r] = W.b2[32 * t + drow(r, h)];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bf16x4 a = pack4(&W.W2b[(32 * t + p) * H + 8 * b + 4 * h]);
-            c = mfma(a, f.h1[b >> 2][b & 3], c);
-        }
+        for (int b = 0; b < 8; ++b) c = mfma(A.w2[t][b], f.h1[b >> 2][b & 3], c);
         f.z2[t] = c;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -160,11 +173,13 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ P
                                                      int64_t n, float* __restrict__ y) {
     __shared__ WeightsLDS W;
     load_weights(W, P, false);
+    AOps A;
+    load_aops(W, A);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t tiles = (n + 31) / 32;
     for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < tiles; t += (int64_t)gridDim.x * 4) {
         Fwd f;
-        forward_tile(W, feat, n, 32 * t, f);
+        forward_tile(W, A, feat, n, 32 * t, f);
         const int64_t s = 32 * t + lane;
         if (lane < 32 && s < n) y[s] = f.z * W.out_scale;
     }
@@ -177,9 +192,13 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ P, co
                                                  const float* __restrict__ target, int64_t n,
                                                  float* __restrict__ part, double* __restrict__ loss_part) {
     __shared__ WeightsLDS W;
-    __shared__ uint16_t dz2t[H][32], dz1t[H][32], h1t[H][32];
+    __shared__ alignas(16) uint16_t dz2t[H][32];
+    __shared__ alignas(16) uint16_t dz1t[H][32];
+    __shared__ alignas(16) uint16_t h1t[H][32];
     __shared__ float h2t[H][32], xf[8][32], dzs[32];
     load_weights(W, P, true);
+    AOps A;
+    load_aops(W, A);
     const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
     const float inv_out = 1.0f / W.out_scale;
     f32x16 gW2[2][2];
@@ -195,7 +214,7 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ P, co
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const int64_t base = 32 * tile, s = base + p;
         Fwd f;
-        forward_tile(W, feat, n, base, f);
+        forward_tile(W, A, feat, n, base, f);
         // dz = 2 (z - t/out_scale) / n for real samples
         float dz = 0.f;
         if (s < n) {
@@ -238,7 +257,7 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ P, co
             for (int r = 0; r < 16; ++r) c[r] = 0.f;
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
-                const bf16x4 a = pack4(&W.W2t[(32 * t + p) * H + 8 * b + 4 * h]);
+                const bf16x4 a = load4(&W.W2t[(32 * t + p) * H + 8 * b + 4 * h]);
                 c = mfma(a, dz2[b >> 2][b & 3], c);
             }
 #pragma unroll
@@ -251,16 +270,16 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ P, co
         // gW2[j2][j1] += sum_p dZ2^T[j2][p] H1^T[j1][p]: K = the tile's 32 samples
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            bf16x4 A[2], B[2];
+            bf16x4 Ag[2], Bg[2];
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-                A[t] = pack4(&dz2t[32 * t + p][8 * b + 4 * h]);
-                B[t] = pack4(&h1t[32 * t + p][8 * b + 4 * h]);
+                Ag[t] = load4(&dz2t[32 * t + p][8 * b + 4 * h]);
+                Bg[t] = load4(&h1t[32 * t + p][8 * b + 4 * h]);
             }
 #pragma unroll
             for (int t = 0; t < 2; ++t)
 #pragma unroll
-                for (int u = 0; u < 2; ++u) gW2[t][u] = mfma(A[t], B[u], gW2[t][u]);
+                for (int u = 0; u < 2; ++u) gW2[t][u] = mfma(Ag[t], Bg[u], gW2[t][u]);
         }
         // row sums: thread j owns hidden unit j
         {

@@ -13,6 +13,7 @@
 // before boundary), so the sums are the same.  Tiles with a slab of more than
 // kSlab particles keep 32-bit sorted indices and gather from global memory.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 
 #include "sph_device.h"
 #include "sph_internal.h"
@@ -59,63 +60,133 @@ __global__ void k_row_tile_count(const uint32_t* __restrict__ start_f, Grid g, u
     tilecnt[row] = (e - b + kTile - 1) / kTile;
 }
 
-__global__ void k_row_tile_fill(const float4* __restrict__ x, const uint32_t* __restrict__ start_f,
-                                const uint32_t* __restrict__ start_b, Grid g, const uint32_t* __restrict__ tileoff,
-                                int32_t limit, TileDesc* __restrict__ tiles) {
+// tilerow[t] = the row of tile t
+__global__ void k_row_tile_mark(const uint32_t* __restrict__ tileoff, int64_t nrows, uint32_t* __restrict__ tilerow) {
     const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int32_t nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    if (row >= (int64_t)ny * nz) return;
-    const int32_t cy = (int32_t)(row % ny), cz = (int32_t)(row / ny);
-    const uint32_t b = start_f[row * nx], e = start_f[row * nx + nx];
-    uint32_t t = tileoff[row];
-    for (uint32_t p0 = b; p0 < e; p0 += kTile, ++t) {
-        const uint32_t p1 = min(p0 + (uint32_t)kTile, e);
-        // the row's particles are sorted by cx: the first and last bound the tile
-        const int32_t cxa = cell_coord(x[p0].x, g.o[0], g.inv, nx);
-        const int32_t cxb = cell_coord(x[p1 - 1].x, g.o[0], g.inv, nx);
-        TileDesc d;
-        d.p0 = (int32_t)p0;
-        d.p1 = (int32_t)p1;
-        d.pad = 0;
-        int32_t fo = 0, bo = 0, ok = 1;
-        for (int r = 0; r < 9; ++r) {
-            const int32_t z = cz + r / 3 - 1, y = cy + r % 3 - 1;
-            uint32_t fb = 0, fe = 0, bb = 0, be = 0;
-            if (z >= 0 && z < nz && y >= 0 && y < ny) {
-                const int64_t rowp = (int64_t)nx * (y + (int64_t)ny * z);
-                const int64_t lo = rowp + (cxa > 0 ? cxa - 1 : 0), hi = rowp + (cxb < nx - 1 ? cxb + 1 : nx - 1);
-                fb = start_f[lo];
-                fe = start_f[hi + 1];
-                bb = start_b[lo];
-                be = start_b[hi + 1];
-            }
-            d.fb[r] = (int32_t)fb;
-            d.foff[r] = fo;
-            fo += (int32_t)(fe - fb);
-            d.bb[r] = (int32_t)bb;
-            d.boff[r] = bo;
-            bo += (int32_t)(be - bb);
-            if (r % 3 == 2) {
-                if (fo - d.foff[r - 2] > limit || bo - d.boff[r - 2] > limit) ok = 0;
-            }
-        }
-        d.foff[9] = fo;
-        d.boff[9] = bo;
-        d.ok = ok;
-        tiles[t] = d;
-    }
+    if (row >= nrows) return;
+    for (uint32_t t = tileoff[row]; t < tileoff[row + 1]; ++t) tilerow[t] = (uint32_t)row;
 }
 
-// Copy the three ranges of slab s of src into dst (LDS), slab-relative.
-template <class T>
-__device__ __forceinline__ void stage_slab(T* dst, const T* __restrict__ src, const int32_t* fb, const int32_t* off,
-                                           int s) {
-    const int32_t o0 = off[3 * s];
-    for (int r = 3 * s; r < 3 * s + 3; ++r) {
-        const int32_t b = fb[r], o = off[r] - o0, len = off[r + 1] - off[r];
-        for (int q = threadIdx.x; q < len; q += kTile) dst[lds(o + q)] = src[b + q];
+// One thread per tile: its particle range and the nine ranges of its stencil.
+__global__ void k_tile_fill(const float4* __restrict__ x, const uint32_t* __restrict__ start_f,
+                            const uint32_t* __restrict__ start_b, Grid g, const uint32_t* __restrict__ tileoff,
+                            const uint32_t* __restrict__ tilerow, int32_t limit, TileDesc* __restrict__ tiles) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int32_t nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    if (t >= (int64_t)tileoff[(int64_t)ny * nz]) return;
+    const int64_t row = tilerow[t];
+    const int32_t cy = (int32_t)(row % ny), cz = (int32_t)(row / ny);
+    const uint32_t e = start_f[row * nx + nx];
+    const uint32_t p0 = start_f[row * nx] + (uint32_t)(t - tileoff[row]) * (uint32_t)kTile;
+    const uint32_t p1 = min(p0 + (uint32_t)kTile, e);
+    // the row's particles are sorted by cx: the first and last bound the tile
+    const int32_t cxa = cell_coord(x[p0].x, g.o[0], g.inv, nx);
+    const int32_t cxb = cell_coord(x[p1 - 1].x, g.o[0], g.inv, nx);
+    TileDesc d;
+    d.p0 = (int32_t)p0;
+    d.p1 = (int32_t)p1;
+    d.pad = 0;
+    int32_t fo = 0, bo = 0, ok = 1;
+    for (int r = 0; r < 9; ++r) {
+        const int32_t z = cz + r / 3 - 1, y = cy + r % 3 - 1;
+        uint32_t fb = 0, fe = 0, bb = 0, be = 0;
+        if (z >= 0 && z < nz && y >= 0 && y < ny) {
+            const int64_t rowp = (int64_t)nx * (y + (int64_t)ny * z);
+            const int64_t lo = rowp + (cxa > 0 ? cxa - 1 : 0), hi = rowp + (cxb < nx - 1 ? cxb + 1 : nx - 1);
+            fb = start_f[lo];
+            fe = start_f[hi + 1];
+            bb = start_b[lo];
+            be = start_b[hi + 1];
+        }
+        d.fb[r] = (int32_t)fb;
+        d.foff[r] = fo;
+        fo += (int32_t)(fe - fb);
+        d.bb[r] = (int32_t)bb;
+        d.boff[r] = bo;
+        bo += (int32_t)(be - bb);
+        if (r % 3 == 2) {
+            if (fo - d.foff[r - 2] > limit || bo - d.boff[r - 2] > limit) ok = 0;
+        }
     }
+    d.foff[9] = fo;
+    d.boff[9] = bo;
+    d.ok = ok;
+    tiles[t] = d;
 }
+
+// Slab s of a set: its three ranges laid end to end, position q of the slab
+// holding sorted index src(q).
+struct SlabMap {
+    int32_t n, l1, l2, b0, b1, b2;
+};
+
+__device__ __forceinline__ SlabMap slab_map(const int32_t* first, const int32_t* off, int s) {
+    const int32_t o0 = off[3 * s];
+    SlabMap m;
+    m.l1 = off[3 * s + 1] - o0;
+    m.l2 = off[3 * s + 2] - o0;
+    m.n = off[3 * s + 3] - o0;
+    m.b0 = first[3 * s];
+    m.b1 = first[3 * s + 1] - m.l1;
+    m.b2 = first[3 * s + 2] - m.l2;
+    return m;
+}
+
+__device__ __forceinline__ int32_t slab_src(SlabMap m, int32_t q) {
+    return (q < m.l1 ? m.b0 : (q < m.l2 ? m.b1 : m.b2)) + q;
+}
+
+constexpr int kStageIters = (kSlab + kTile - 1) / kTile;
+
+// Copy slab m of one, two or three arrays into LDS: the workgroup's loads
+// (positions past the slab re-read its first element, a valid index whenever
+// the slab is not empty) are all issued before the first LDS store, so the
+// copy costs one memory latency.  An empty slab loads nothing (uniform).
+#define SPH_STAGE_LOADS(u)                                                      \
+    const int32_t q##u = (int32_t)threadIdx.x + (u) * kTile;                    \
+    const int32_t j##u = slab_src(m, q##u < m.n ? q##u : 0);
+#define SPH_STAGE_ALL(X) X(0) X(1) X(2) X(3) X(4)
+static_assert(kStageIters == 5, "SPH_STAGE_ALL unrolls five iterations");
+
+template <class T0>
+__device__ __forceinline__ void stage(SlabMap m, T0* d0, const T0* __restrict__ a0) {
+    if (m.n == 0) return;
+    SPH_STAGE_ALL(SPH_STAGE_LOADS)
+#define L_(u) const T0 v0_##u = a0[j##u];
+    SPH_STAGE_ALL(L_)
+#undef L_
+#define S_(u) if (q##u < m.n) d0[lds(q##u)] = v0_##u;
+    SPH_STAGE_ALL(S_)
+#undef S_
+}
+
+template <class T0, class T1>
+__device__ __forceinline__ void stage(SlabMap m, T0* d0, const T0* __restrict__ a0, T1* d1,
+                                      const T1* __restrict__ a1) {
+    if (m.n == 0) return;
+    SPH_STAGE_ALL(SPH_STAGE_LOADS)
+#define L_(u) const T0 v0_##u = a0[j##u]; const T1 v1_##u = a1[j##u];
+    SPH_STAGE_ALL(L_)
+#undef L_
+#define S_(u) if (q##u < m.n) { d0[lds(q##u)] = v0_##u; d1[lds(q##u)] = v1_##u; }
+    SPH_STAGE_ALL(S_)
+#undef S_
+}
+
+template <class T0, class T1, class T2>
+__device__ __forceinline__ void stage(SlabMap m, T0* d0, const T0* __restrict__ a0, T1* d1,
+                                      const T1* __restrict__ a1, T2* d2, const T2* __restrict__ a2) {
+    if (m.n == 0) return;
+    SPH_STAGE_ALL(SPH_STAGE_LOADS)
+#define L_(u) const T0 v0_##u = a0[j##u]; const T1 v1_##u = a1[j##u]; const T2 v2_##u = a2[j##u];
+    SPH_STAGE_ALL(L_)
+#undef L_
+#define S_(u) if (q##u < m.n) { d0[lds(q##u)] = v0_##u; d1[lds(q##u)] = v1_##u; d2[lds(q##u)] = v2_##u; }
+    SPH_STAGE_ALL(S_)
+#undef S_
+}
+#undef SPH_STAGE_ALL
+#undef SPH_STAGE_LOADS
 
 // Visit the list entries k.. of one particle whose slots lie below `end`
 // (the slots ascend, so they form a prefix), as LDS positions lds(slot - base).
@@ -160,20 +231,21 @@ __device__ __forceinline__ void slab_slots(const uint16_t*& p, int64_t nf, uint3
     }
 }
 
-// One set's neighbours of the tile particle i, slab by slab: stage(s) copies
-// slab s into LDS, fn(index) does one neighbour.  Every thread of the
+// One set's neighbours of the tile particle i, slab by slab: stage_fn(map)
+// copies the slab into LDS, fn(position) does one neighbour.  Every thread of the
 // workgroup calls this (the barriers); threads without a particle pass mine =
 // false.
 template <class Stage, class Fn>
 __device__ __forceinline__ void sweep(const uint16_t* __restrict__ list, const uint32_t* __restrict__ cnt, int64_t nf,
-                                      int64_t i, bool mine, const int32_t* off, Stage&& stage, Fn&& fn) {
+                                      int64_t i, bool mine, const int32_t* first, const int32_t* off,
+                                      Stage&& stage_fn, Fn&& fn) {
     if (off[9] == 0) return;   // no particle of this set near the tile (uniform)
     const uint32_t n = mine ? cnt[i] : 0u;
     uint32_t k = 0;
     const uint16_t* p = list + (mine ? i : 0);
     for (int s = 0; s < 3; ++s) {
         if (off[3 * s + 3] == off[3 * s]) continue;   // empty slab (uniform)
-        stage(s);
+        stage_fn(slab_map(first, off, s));
         __syncthreads();
         slab_slots(p, nf, n, k, (uint32_t)off[3 * s + 3], (uint32_t)off[3 * s], fn);
         __syncthreads();
@@ -212,8 +284,8 @@ __global__ void __launch_bounds__(kTile) k_nbr_build_tiled(
         if (d.ok) {
             for (int s = 0; s < 3; ++s) {
                 if (d.foff[3 * s + 3] == d.foff[3 * s] && d.boff[3 * s + 3] == d.boff[3 * s]) continue;
-                stage_slab(sx, x, d.fb, d.foff, s);
-                stage_slab(sb, xb, d.bb, d.boff, s);
+                stage(slab_map(d.fb, d.foff, s), sx, x);
+                stage(slab_map(d.bb, d.boff, s), sb, xb);
                 __syncthreads();
                 const int32_t z = cz + s - 1;
                 if (mine && z >= 0 && z < g.n[2]) {
@@ -366,9 +438,9 @@ __global__ void __launch_bounds__(kTile) k_density_alpha_t(Lists L, int64_t nf, 
         gx += F * dx; gy += F * dy; gz += F * dz;
     };
     if (d.ok) {
-        sweep(L.l16, L.ncnt, nf, i, mine, d.foff, [&](int s) { stage_slab(s0, (const float4*)x, d.fb, d.foff, s); },
+        sweep(L.l16, L.ncnt, nf, i, mine, d.fb, d.foff, [&](SlabMap m) { stage(m, s0, (const float4*)x); },
               [&](uint32_t q) { fluid(s0[q]); });
-        sweep(L.b16, L.bcnt, nf, i, mine, d.boff, [&](int s) { stage_slab(s0, xb, d.bb, d.boff, s); },
+        sweep(L.b16, L.bcnt, nf, i, mine, d.bb, d.boff, [&](SlabMap m) { stage(m, s0, xb); },
               [&](uint32_t q) { bound(s0[q]); });
     } else if (mine) {
         for_each_nbr(L.l32, nf, i, L.ncnt[i], [&](uint32_t j) { fluid(x[j]); });
@@ -390,8 +462,10 @@ __global__ void __launch_bounds__(kTile) k_pressure_update_t(Lists L, int64_t nf
                                                              const float* __restrict__ kappa,
                                                              float* __restrict__ Kacc,
                                                              float* __restrict__ kappa_last,
-                                                             const float4* __restrict__ xb, Kern kc, float dt) {
+                                                             const float4* __restrict__ xb, Kern kc, float dt,
+                                                             const int32_t* __restrict__ go) {
     __shared__ float4 s0[kSlabPad];
+    if (go != nullptr && *go == 0) return;
     const uint32_t t = logical_block();
     if (t >= L.ntiles) return;
     const TileDesc& d = L.tiles[t];
@@ -413,10 +487,10 @@ __global__ void __launch_bounds__(kTile) k_pressure_update_t(Lists L, int64_t nf
         ax += c * dx; ay += c * dy; az += c * dz;
     };
     if (d.ok) {
-        sweep(L.l16, L.ncnt, nf, i, mine, d.foff, [&](int s) { stage_slab(s0, x, d.fb, d.foff, s); },
+        sweep(L.l16, L.ncnt, nf, i, mine, d.fb, d.foff, [&](SlabMap m) { stage(m, s0, x); },
               [&](uint32_t q) { fluid(s0[q]); });
         ax *= kc.m; ay *= kc.m; az *= kc.m;
-        sweep(L.b16, L.bcnt, nf, i, mine, d.boff, [&](int s) { stage_slab(s0, xb, d.bb, d.boff, s); },
+        sweep(L.b16, L.bcnt, nf, i, mine, d.bb, d.boff, [&](SlabMap m) { stage(m, s0, xb); },
               [&](uint32_t q) { bound(s0[q]); });
     } else if (mine) {
         for_each_nbr(L.l32, nf, i, L.ncnt[i], [&](uint32_t j) { fluid(x[j]); });
@@ -454,18 +528,10 @@ __device__ __forceinline__ void divergence_tile(const Lists& L, int64_t nf, cons
         dd += xk.w * grad_factor(r2, kc) * ((vi.x - vk.x) * dx + (vi.y - vk.y) * dy + (vi.z - vk.z) * dz);
     };
     if (d.ok) {
-        sweep(L.l16, L.ncnt, nf, i, mine, d.foff,
-              [&](int s) {
-                  stage_slab(s0, x, d.fb, d.foff, s);
-                  stage_slab(s1, v, d.fb, d.foff, s);
-              },
+        sweep(L.l16, L.ncnt, nf, i, mine, d.fb, d.foff, [&](SlabMap m) { stage(m, s0, x, s1, v); },
               [&](uint32_t q) { fluid(s0[q], s1[q]); });
         dd *= kc.m;
-        sweep(L.b16, L.bcnt, nf, i, mine, d.boff,
-              [&](int s) {
-                  stage_slab(s0, xb, d.bb, d.boff, s);
-                  stage_slab(s1, vb, d.bb, d.boff, s);
-              },
+        sweep(L.b16, L.bcnt, nf, i, mine, d.bb, d.boff, [&](SlabMap m) { stage(m, s0, xb, s1, vb); },
               [&](uint32_t q) { bound(s0[q], s1[q]); });
     } else if (mine) {
         for_each_nbr(L.l32, nf, i, L.ncnt[i], [&](uint32_t j) { fluid(x[j], v[j]); });
@@ -480,9 +546,11 @@ __global__ void __launch_bounds__(kTile) k_predict_t(Lists L, int64_t nf, float4
                                                      const float4* __restrict__ v, const float* __restrict__ rho,
                                                      const float* __restrict__ alpha, float* __restrict__ kappa,
                                                      const float4* __restrict__ xb, const float4* __restrict__ vb,
-                                                     Kern kc, float dt, double* __restrict__ partials) {
+                                                     Kern kc, float dt, double* __restrict__ partials,
+                                                     const int32_t* __restrict__ go, float* __restrict__ dout) {
     __shared__ float4 s0[kSlabPad];
     __shared__ float4 s1[kSlabPad];
+    if (go != nullptr && *go == 0) return;
     const uint32_t t = logical_block();
     double e = 0.0;
     if (t < L.ntiles) {
@@ -494,6 +562,7 @@ __global__ void __launch_bounds__(kTile) k_predict_t(Lists L, int64_t nf, float4
             const float ri = rho[i];
             float kap;
             if (MODE == 0) {
+                if (dout) dout[i] = dd;
                 const float ep = fmaxf(dd, 0.0f);
                 kap = ep * alpha[i] / dt;
                 e = (double)ep;
@@ -509,34 +578,6 @@ __global__ void __launch_bounds__(kTile) k_predict_t(Lists L, int64_t nf, float4
     }
     const double bs = tile_sum(e);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-}
-
-__global__ void __launch_bounds__(kTile) k_warm_features_t(Lists L, int64_t nf, const float4* __restrict__ x,
-                                                           const float4* __restrict__ v,
-                                                           const float* __restrict__ rho,
-                                                           const float* __restrict__ alpha,
-                                                           const float* __restrict__ K,
-                                                           const float4* __restrict__ xb,
-                                                           const float4* __restrict__ vb, Kern kc, float dt,
-                                                           float alpha_ref, float* __restrict__ feat) {
-    __shared__ float4 s0[kSlabPad];
-    __shared__ float4 s1[kSlabPad];
-    const uint32_t t = logical_block();
-    if (t >= L.ntiles) return;
-    const TileDesc& d = L.tiles[t];
-    const int64_t i = d.p0 + (int64_t)threadIdx.x;
-    const bool mine = i < d.p1;
-    divergence_tile(L, nf, d, i, mine, x, v, xb, vb, kc, s0, s1, [&](float dd) {
-        if (!mine) return;
-        const uint32_t nfc = L.ncnt[i], nbc = L.bcnt[i];
-        const float a = alpha[i];
-        float* f = feat + 5 * i;
-        f[0] = (rho[i] - kc.rho0) / kc.rho0;
-        f[1] = dt * dd / kc.rho0;
-        f[2] = (float)(nfc + nbc) / 26.0f;
-        f[3] = a > 0.0f ? K[i] * dt * dt / (a * kc.rho0) : 0.0f;
-        f[4] = a / alpha_ref;
-    });
 }
 
 template <int MODEL>
@@ -573,12 +614,8 @@ __global__ void __launch_bounds__(kTile) k_nonpressure_t(Lists L, int64_t nf, fl
             }
         };
         if (d.ok)
-            sweep(L.l16, L.ncnt, nf, i, mine, d.foff,
-                  [&](int s) {
-                      stage_slab(s0, (const float4*)x, d.fb, d.foff, s);
-                      stage_slab(s1, v, d.fb, d.foff, s);
-                      stage_slab(s2, rho, d.fb, d.foff, s);
-                  },
+            sweep(L.l16, L.ncnt, nf, i, mine, d.fb, d.foff,
+                  [&](SlabMap m) { stage(m, s0, (const float4*)x, s1, v, s2, rho); },
                   [&](uint32_t q) { fluid(s0[q], s1[q], s2[q]); });
         else if (mine)
             for_each_nbr(L.l32, nf, i, L.ncnt[i], [&](uint32_t j) { fluid(x[j], v[j], rho[j]); });
@@ -690,12 +727,7 @@ __global__ void __launch_bounds__(kTile) k_visc_matvec_t(Lists L, int64_t nf, co
         ax += c * dx; ay += c * dy; az += c * dz;
     };
     if (d.ok)
-        sweep(L.l16, L.ncnt, nf, i, mine, d.foff,
-              [&](int s) {
-                  stage_slab(s0, x, d.fb, d.foff, s);
-                  stage_slab(s1, p, d.fb, d.foff, s);
-                  stage_slab(s2, rho, d.fb, d.foff, s);
-              },
+        sweep(L.l16, L.ncnt, nf, i, mine, d.fb, d.foff, [&](SlabMap m) { stage(m, s0, x, s1, p, s2, rho); },
               [&](uint32_t q) { fluid(s0[q], s1[q], s2[q]); });
     else if (mine)
         for_each_nbr(L.l32, nf, i, L.ncnt[i], [&](uint32_t j) { fluid(x[j], p[j], rho[j]); });
@@ -727,11 +759,7 @@ __global__ void __launch_bounds__(kTile) k_visc_precond_t(Lists L, int64_t nf, c
         b11 += c * dy * dy; b12 += c * dy * dz; b22 += c * dz * dz;
     };
     if (d.ok)
-        sweep(L.l16, L.ncnt, nf, i, mine, d.foff,
-              [&](int s) {
-                  stage_slab(s0, x, d.fb, d.foff, s);
-                  stage_slab(s2, rho, d.fb, d.foff, s);
-              },
+        sweep(L.l16, L.ncnt, nf, i, mine, d.fb, d.foff, [&](SlabMap m) { stage(m, s0, x, s2, rho); },
               [&](uint32_t q) { fluid(s0[q], s2[q]); });
     else if (mine)
         for_each_nbr(L.l32, nf, i, L.ncnt[i], [&](uint32_t j) { fluid(x[j], rho[j]); });
@@ -761,15 +789,17 @@ int64_t max_tiles(int64_t nf, int64_t nrows) { return nf / kTile + nrows + 1; }
 uint32_t tile_partials(int64_t ntiles) { return tile_blocks(ntiles); }
 
 hipError_t launch_tiles_build(const float4* x, const uint32_t* start_f, const uint32_t* start_b, Grid g,
-                              int32_t slab_limit, uint32_t* tilecnt, uint32_t* tileoff, uint32_t* scan_part,
-                              TileDesc* tiles, hipStream_t s) {
+                              int32_t slab_limit, uint32_t* tilecnt, uint32_t* tileoff, uint32_t* tilerow,
+                              int64_t max_t, uint32_t* scan_part, TileDesc* tiles, hipStream_t s) {
     if (slab_limit < 0 || slab_limit > kSlab) return hipErrorInvalidValue;
     const int64_t nrows = (int64_t)g.n[1] * g.n[2];
     const uint32_t blocks = (uint32_t)((nrows + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_row_tile_count, dim3(blocks), dim3(kBlock), 0, s, start_f, g, tilecnt);
     hipError_t e = launch_exclusive_scan(tilecnt, nrows, tileoff, scan_part, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_row_tile_fill, dim3(blocks), dim3(kBlock), 0, s, x, start_f, start_b, g, tileoff,
+    hipLaunchKernelGGL(k_row_tile_mark, dim3(blocks), dim3(kBlock), 0, s, tileoff, nrows, tilerow);
+    const uint32_t tb = (uint32_t)std::max<int64_t>((max_t + kBlock - 1) / kBlock, 1);
+    hipLaunchKernelGGL(k_tile_fill, dim3(tb), dim3(kBlock), 0, s, x, start_f, start_b, g, tileoff, tilerow,
                        slab_limit, tiles);
     return hipGetLastError();
 }
@@ -801,24 +831,25 @@ hipError_t launch_density_alpha_t(const Lists& L, int64_t nf, float4* x, const f
 }
 
 hipError_t launch_pressure_update_t(const Lists& L, int64_t nf, const float4* x, float4* v, const float* kappa,
-                                    float* Kacc, float* kappa_last, const float4* xb, Kern kc, float dt, hipStream_t s) {
-    TLAUNCH(k_pressure_update_t, nf, x, v, kappa, Kacc, kappa_last, xb, kc, dt);
+                                    float* Kacc, float* kappa_last, const float4* xb, Kern kc, float dt,
+                                    const int32_t* go, hipStream_t s) {
+    TLAUNCH(k_pressure_update_t, nf, x, v, kappa, Kacc, kappa_last, xb, kc, dt, go);
 }
 
 hipError_t launch_predict_t(int mode, const Lists& L, int64_t nf, float4* x, const float4* v, const float* rho,
                             const float* alpha, float* kappa, const float4* xb, const float4* vb, Kern kc, float dt,
-                            double* partials, double* err_out, hipStream_t s) {
+                            double* partials, SolveCtl* ctl, bool first, float* dout, hipStream_t s) {
     const uint32_t nblk = tile_blocks(L.ntiles);
+    const int32_t* go = first ? nullptr : &ctl->go;
     if (L.ntiles > 0) {
         if (mode == 0)
             hipLaunchKernelGGL(k_predict_t<0>, dim3(nblk), dim3(kTile), 0, s, L, nf, x, v, rho, alpha, kappa, xb, vb,
-                               kc, dt, partials);
+                               kc, dt, partials, go, dout);
         else
             hipLaunchKernelGGL(k_predict_t<1>, dim3(nblk), dim3(kTile), 0, s, L, nf, x, v, rho, alpha, kappa, xb, vb,
-                               kc, dt, partials);
+                               kc, dt, partials, go, nullptr);
     }
-    hipLaunchKernelGGL(k_finish_f64, dim3(1), dim3(kBlock), 0, s, partials, L.ntiles > 0 ? (int)nblk : 0, 1, err_out);
-    return hipGetLastError();
+    return launch_solve_finish(partials, L.ntiles > 0 ? (int)nblk : 0, ctl, first, s);
 }
 
 hipError_t launch_nonpressure_t(int model, const Lists& L, int64_t nf, float4* x, const float4* v, float4* vout,
@@ -831,11 +862,6 @@ hipError_t launch_nonpressure_t(int model, const Lists& L, int64_t nf, float4* x
     TLAUNCH(k_nonpressure_t<0>, nf, x, v, vout, rho, kc, dt, gx, gy, gz, visc, K, kappa, warm_factor, setup_warm);
 }
 
-hipError_t launch_warm_features_t(const Lists& L, int64_t nf, const float4* x, const float4* v, const float* rho,
-                                  const float* alpha, const float* K, const float4* xb, const float4* vb, Kern kc,
-                                  float dt, float alpha_ref, float* feat, hipStream_t s) {
-    TLAUNCH(k_warm_features_t, nf, x, v, rho, alpha, K, xb, vb, kc, dt, alpha_ref, feat);
-}
 
 hipError_t launch_rigid_force_t(const Lists& L, int64_t nf, const float4* x, const float* rho, const float* K,
                                 const float* Kv, const float4* xb, const float4* vb, Kern kc, int32_t nbody,

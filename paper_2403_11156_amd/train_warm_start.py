@@ -10,7 +10,7 @@
    master weights), shuffled mini-batches.
 3. The FP32 parameters go to weights/warm_start_mlp.f32 with a JSON record.
 
-    python -m paper_2403_11156_amd.train_warm_start [--epochs 12] [--quick]
+    python -m paper_2403_11156_amd.train_warm_start [--epochs 40] [--quick]
 """
 
 from __future__ import annotations
@@ -68,7 +68,7 @@ def collect(runs, torch, sph, scenes, log=print):
     return F, T
 
 
-def train(F, T, torch, sph, epochs=12, batch=65536, lr=2e-3, seed=0, log=print):
+def train(F, T, torch, sph, epochs=40, batch=65536, lr=2e-3, halve_every=10, seed=0, log=print):
     n = F.shape[0]
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
@@ -92,7 +92,7 @@ def train(F, T, torch, sph, epochs=12, batch=65536, lr=2e-3, seed=0, log=print):
     t0 = time.time()
     for ep in range(epochs):
         order = torch.randperm(Ft.shape[0], generator=g, device="cuda")
-        rate = lr * (0.5 ** (ep // 4))
+        rate = lr * (0.5 ** (ep // halve_every))
         for b in range(steps_per_epoch):
             idx = order[b * batch:(b + 1) * batch]
             net.train_step(Ft[idx].contiguous(), Tt[idx].contiguous(), rate)
@@ -103,12 +103,12 @@ def train(F, T, torch, sph, epochs=12, batch=65536, lr=2e-3, seed=0, log=print):
     params = net.params()
     net.close()
     return params, {"validation_loss": hist, "initial_validation_loss": base, "samples": int(n),
-                    "train_steps": step, "batch": batch, "epochs": epochs, "lr": lr}
+                    "train_steps": step, "batch": batch, "epochs": epochs, "lr": lr, "halve_every": halve_every}
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--quick", action="store_true", help="c1 only, 2 epochs (smoke of the driver)")
     ap.add_argument("--out", default=WEIGHTS)
     args = ap.parse_args()

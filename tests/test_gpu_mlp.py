@@ -197,3 +197,35 @@ def test_trace_capture_matches_oracle(env):
         assert fr.max() <= 1.0 and tr.max() <= 1.0
     assert sim.trace_rows() == cap
     sim.close()
+
+
+def test_trained_network_cuts_iterations(env):
+    """The committed trained network against the plain previous-step warm
+    start on the 125k dam break: both converge to the same eta every step,
+    and the learned start needs fewer density iterations on average."""
+    import os
+    torch, sph = env
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2403_11156_amd",
+                        "weights", "warm_start_mlp.f32")
+    assert os.path.exists(path), "trained weights are part of the package"
+    p = np.fromfile(path, dtype=np.float32)
+    sc = scenes.scene("c2")
+    eta = sc.params["eta_density"]
+    means = {}
+    for arm in ("plain", "learned"):
+        sim = sph.Simulation(sc)
+        net = None
+        if arm == "learned":
+            net = sph.MLP(p)
+            sim.set_warm_start(2, net)
+        its = []
+        for k in range(60):
+            st = sim.advance()
+            assert st["err_dens"] <= eta and st["warm_fallback"] == 0, (arm, k, st["err_dens"])
+            its.append(st["iters_dens"])
+        means[arm] = float(np.mean(its))
+        sim.close()
+        if net is not None:
+            net.close()
+    print("mean density iterations over 60 steps of c2:", means, flush=True)
+    assert means["learned"] < means["plain"]
