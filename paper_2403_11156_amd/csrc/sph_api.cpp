@@ -76,18 +76,18 @@ struct sph_ctx {
     BodyPose *poses = nullptr;
     double *com_dev = nullptr;
     // reductions and flags
-    double *red_part = nullptr, *scal = nullptr, *rigid_out = nullptr;
-    sph::SolveCtl *ctl = nullptr, *h_ctl = nullptr;   // device control block, pinned host copy
+    double *red_part = nullptr, *scal = nullptr;
+    sph::SolveCtl *ctl = nullptr;                     // device control block of the running solve
     int32_t last_iters[2] = {0, 0};                   // previous step's iterations (divergence, density)
-    uint32_t *flags = nullptr, *vmax_bits = nullptr;
-    unsigned long long *nstats = nullptr, *nstat_part = nullptr;
+    uint32_t *flags = nullptr;
+    unsigned long long *nstat_part = nullptr;
+    // pinned host memory the finishing kernels write (host view, device address)
+    sph::HostStatus *hs = nullptr, *hs_dev = nullptr;
     // implicit viscosity
     float *Pinv = nullptr;
     float4 *cg_b = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
     // pinned host staging
     double *h_scal = nullptr;
-    uint32_t *h_u32 = nullptr;
-    unsigned long long *h_stats = nullptr;
 
     std::vector<sph_rigid_desc> rigid;
     std::vector<double> force, torque;
@@ -97,6 +97,7 @@ struct sph_ctx {
     int64_t dev_bytes = 0;
 
     bool nbr_fresh = false, boundary_dirty = true, sorted_once = false;
+    unsigned long long nstats[sph::kNStats] = {};   // of the last build
     int64_t step_index = 0;
     float last_dt = 0.f;
     int32_t forced_div = -1, forced_dens = -1;
@@ -158,13 +159,10 @@ void free_all(sph_ctx *c) {
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     if (c->h_scal) (void)hipHostFree(c->h_scal);
-    if (c->h_u32) (void)hipHostFree(c->h_u32);
-    if (c->h_stats) (void)hipHostFree(c->h_stats);
-    if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+    if (c->hs) (void)hipHostFree(c->hs);
     c->h_scal = nullptr;
-    c->h_u32 = nullptr;
-    c->h_stats = nullptr;
-    c->h_ctl = nullptr;
+    c->hs = nullptr;
+    c->hs_dev = nullptr;
     for (auto &e : c->prof_pending) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
@@ -388,31 +386,29 @@ int build(sph_ctx *c) {
         HIP_TRY(c, sph::launch_nbr_build_tiled(c->tiles, c->tileoff + c->nrows, c->max_t, c->x, c->nf, c->xb,
                                                c->start_f, c->start_b, c->g, c->l16, c->nlist, c->ncnt, c->capf,
                                                c->b16, c->blist, c->bcnt, c->capb, c->flags, c->nstat_part,
-                                               c->nstats, s));
-        HIP_TRY(c, hipMemcpyAsync(c->h_u32 + 1, c->tileoff + c->nrows, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+                                               c->hs_dev, s));
     } else {
         ProfScope ps(c, "nbr_build", 16.0 * c->nf + 8.0 * c->nf + list_bytes(c));
         HIP_TRY(c, sph::launch_nbr_build(c->x, c->nf, c->xb, c->start_f, c->start_b, c->g, c->nlist, c->ncnt, c->capf,
-                                         c->blist, c->bcnt, c->capb, c->flags, c->nstat_part, c->nstats, s));
+                                         c->blist, c->bcnt, c->capb, c->flags, c->nstat_part, c->hs_dev, s));
     }
-    HIP_TRY(c, hipMemcpyAsync(c->h_u32, c->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipMemcpyAsync(c->h_stats, c->nstats, sph::kNStats * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                              s));
     HIP_TRY(c, hipStreamSynchronize(s));
-    c->ntiles = c->tiled ? (int64_t)c->h_u32[1] : 0;
+    const sph::HostStatus &hs = *c->hs;
+    c->ntiles = c->tiled ? (int64_t)hs.ntiles : 0;
     c->sorted_once = true;
-    if (c->h_u32[0] & 2u) {
+    if (hs.flags & 2u) {
         c->nbr_fresh = false;
         return fail(c, SPH_ERR_CAPACITY, "more than 4096 particles in one grid cell");
     }
-    if (c->h_u32[0] & 1u) {
+    if (hs.flags & 1u) {
         c->nbr_fresh = false;
         return fail(c, SPH_ERR_CAPACITY, "neighbour list capacity exceeded (max_neighbors / max_boundary_neighbors)");
     }
-    c->nbr_sum = (double)c->h_stats[2];
-    c->nbr_sum_f = (double)c->h_stats[3];
-    c->over_entries = (double)c->h_stats[4];
-    c->n_over = (int64_t)c->h_stats[5];
+    for (int f = 0; f < sph::kNStats; ++f) c->nstats[f] = hs.nstats[f];
+    c->nbr_sum = (double)hs.nstats[2];
+    c->nbr_sum_f = (double)hs.nstats[3];
+    c->over_entries = (double)hs.nstats[4];
+    c->n_over = (int64_t)hs.nstats[5];
     c->nbr_fresh = true;
     return SPH_OK;
 }
@@ -430,16 +426,21 @@ int pressure_pass(sph_ctx *c, float *Kacc, float *klast, float dt, const int32_t
     return SPH_OK;
 }
 
-int predict_pass(sph_ctx *c, int mode, float dt, bool first) {
+// The predict pass and its finish (the timing record covers the pass only).
+int predict_pass(sph_ctx *c, int mode, float dt, bool first, const sph::SolveCtl &init) {
     float *dout = (mode == 0 && c->want_d) ? c->dbuf : nullptr;
-    ProfScope ps(c, "predict", (56.0 + (dout ? 4.0 : 0.0)) * c->nf + list_bytes(c));
-    if (c->tiled)
-        HIP_TRY(c, sph::launch_predict_t(mode, tile_lists(c), c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->xb,
-                                         c->vb, c->kc, dt, c->red_part, c->ctl, first, dout, c->stream));
-    else
-        HIP_TRY(c, sph::launch_predict(mode, c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->nlist, c->ncnt, c->xb,
-                                       c->vb, c->blist, c->bcnt, c->kc, dt, c->red_part, c->ctl, first, dout,
-                                       c->stream));
+    int nparts = 0;
+    {
+        ProfScope ps(c, "predict", (56.0 + (dout ? 4.0 : 0.0)) * c->nf + list_bytes(c));
+        if (c->tiled)
+            HIP_TRY(c, sph::launch_predict_t(mode, tile_lists(c), c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->xb,
+                                             c->vb, c->kc, dt, c->red_part, c->ctl, first, dout, &nparts, c->stream));
+        else
+            HIP_TRY(c, sph::launch_predict(mode, c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->nlist, c->ncnt,
+                                           c->xb, c->vb, c->blist, c->bcnt, c->kc, dt, c->red_part, c->ctl, first,
+                                           dout, &nparts, c->stream));
+    }
+    HIP_TRY(c, sph::launch_solve_finish(c->red_part, nparts, c->ctl, first, init, c->hs_dev, c->stream));
     return SPH_OK;
 }
 
@@ -454,8 +455,13 @@ int jacobi_solve(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, int3
     const double N = (double)std::max<int64_t>(c->nf, 1);
     const double scale = mode == 0 ? (double)dt / c->P.rho0 / N : 1.0 / (c->P.rho0 * N);
     const int32_t cap = forced >= 0 ? forced : std::max(c->P.max_iters, 0);
-    HIP_TRY(c, sph::launch_solve_init(c->ctl, scale, eta, forced, c->P.max_iters, s));
-    int rc = predict_pass(c, mode, dt, true);
+    sph::SolveCtl init{};
+    init.scale = scale;
+    init.eta = eta;
+    init.forced = forced;
+    init.max_iters = c->P.max_iters;
+    init.go = 1;
+    int rc = predict_pass(c, mode, dt, true, init);
     if (rc) return rc;
     const size_t mark = c->prof_pending.size();
     int32_t queued = 0;
@@ -465,13 +471,12 @@ int jacobi_solve(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, int3
         for (int32_t k = 0; k < batch; ++k) {
             rc = pressure_pass(c, Kacc, klast, dt, &c->ctl->go);
             if (rc) return rc;
-            rc = predict_pass(c, mode, dt, false);
+            rc = predict_pass(c, mode, dt, false, init);
             if (rc) return rc;
         }
         queued += batch;
-        HIP_TRY(c, hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(sph::SolveCtl), hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
-        h = *c->h_ctl;
+        h = c->hs->solve;
         if (!h.go || queued >= cap) break;
         batch = std::min<int32_t>(queued < 2 ? 1 : 2, cap - queued);
     }
@@ -560,11 +565,10 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     // 1. time step (fixed, or CFL from the step's input velocities)
     float dt;
     if (c->P.cfl_lambda > 0.0) {
-        HIP_TRY(c, sph::launch_max_v2(c->v, nf, (uint32_t *)c->red_part, c->vmax_bits, s));
-        HIP_TRY(c, hipMemcpyAsync(c->h_u32, c->vmax_bits, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, sph::launch_max_v2(c->v, nf, (uint32_t *)c->red_part, c->hs_dev, s));
         HIP_TRY(c, hipStreamSynchronize(s));
         float vmax2;
-        std::memcpy(&vmax2, c->h_u32, sizeof(float));
+        std::memcpy(&vmax2, &c->hs->vmax_bits, sizeof(float));
         double d = c->P.dt_max;
         if (vmax2 > 0.0f) {
             const double cfl = c->P.cfl_lambda * (2.0 * c->P.r) / std::sqrt((double)vmax2);
@@ -661,13 +665,13 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     if (c->nr > 0) {
         if (c->tiled)
             HIP_TRY(c, sph::launch_rigid_force_t(tile_lists(c), nf, c->x, c->rho, c->K, c->Kv, c->xb, c->vb, c->kc,
-                                                 c->nr, c->com_dev, c->red_part, c->rigid_out, s));
+                                                 c->nr, c->com_dev, c->red_part, c->hs_dev, s));
         else
             HIP_TRY(c, sph::launch_rigid_force(nf, c->x, c->rho, c->K, c->Kv, c->blist, c->bcnt, c->xb, c->vb, c->kc,
-                                               c->nr, c->com_dev, c->red_part, c->rigid_out, s));
+                                               c->nr, c->com_dev, c->red_part, c->hs_dev, s));
         std::vector<double> fo(6 * c->nr);
-        HIP_TRY(c, hipMemcpyAsync(fo.data(), c->rigid_out, sizeof(double) * 6 * c->nr, hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
+        std::memcpy(fo.data(), c->hs->rigid, sizeof(double) * 6 * c->nr);
         for (int b = 0; b < c->nr; ++b)
             for (int a = 0; a < 3; ++a) {
                 c->force[3 * b + a] = fo[6 * b + a];
@@ -697,9 +701,9 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         st->converged_dens = ed <= c->P.eta_density;
         st->cg_iters = cg_it;
         st->cg_resid = cg_res;
-        st->nbr_min = (int32_t)(c->h_stats[0] >= 0xffffffffull ? 0 : c->h_stats[0]);
-        st->nbr_max = (int32_t)c->h_stats[1];
-        st->nbr_mean = c->nf ? (double)c->h_stats[2] / (double)c->nf : 0.0;
+        st->nbr_min = (int32_t)(c->nstats[0] >= 0xffffffffull ? 0 : c->nstats[0]);
+        st->nbr_max = (int32_t)c->nstats[1];
+        st->nbr_mean = c->nf ? (double)c->nstats[2] / (double)c->nf : 0.0;
         st->warm_fallback = c->warm_fallback ? 1 : 0;
         st->step_index = c->step_index;
     }
@@ -837,9 +841,9 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     ALLOC(c->xb, nb); ALLOC(c->xb2, nb); ALLOC(c->vb, nb); ALLOC(c->vb2, nb); ALLOC(c->bid, nb); ALLOC(c->bid2, nb);
     ALLOC(c->bkey, nb); ALLOC(c->bslot, nb); ALLOC(c->bsrc, nb); ALLOC(c->blocal, 3 * nb);
     ALLOC(c->poses, std::max(1, c->nr)); ALLOC(c->com_dev, 3 * std::max(1, c->nr));
-    ALLOC(c->red_part, red_blocks * 6 * std::max(1, c->nr) + 16); ALLOC(c->scal, 16); ALLOC(c->rigid_out, 6 * std::max(1, c->nr));
+    ALLOC(c->red_part, red_blocks * 6 * std::max(1, c->nr) + 16); ALLOC(c->scal, 16);
     ALLOC(c->ctl, 1);
-    ALLOC(c->flags, 4); ALLOC(c->vmax_bits, 4); ALLOC(c->nstats, sph::kNStats);
+    ALLOC(c->flags, 4);
     ALLOC(c->nstat_part, sph::kNStats * nstat_blocks);
     ALLOC(c->feat, 5 * nf); ALLOC(c->ybuf, nf); ALLOC(c->dbuf, nf);
     if (p->visc_model == SPH_VISC_IMPLICIT) {
@@ -848,9 +852,9 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     }
 #undef ALLOC
     if (hipHostMalloc((void **)&c->h_scal, 16 * sizeof(double)) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_u32, 16 * sizeof(uint32_t)) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_stats, sph::kNStats * sizeof(unsigned long long)) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_ctl, sizeof(sph::SolveCtl)) != hipSuccess) {
+        hipHostMalloc((void **)&c->hs, sizeof(sph::HostStatus), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->hs_dev, c->hs, 0) != hipSuccess) {
         free_all(c);
         delete c;
         return fail(nullptr, SPH_ERR_OOM, "pinned host allocation failed");

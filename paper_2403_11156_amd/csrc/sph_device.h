@@ -126,39 +126,43 @@ __global__ void k_finish_f64(const double* __restrict__ partials, int nblk, int 
     }
 }
 
-// Jacobi solve control (Algorithm 2's stop rule on the device).
-__global__ void k_solve_init(SolveCtl* ctl, double scale, double eta, int32_t forced, int32_t max_iters) {
-    ctl->err = 0.0;
-    ctl->scale = scale;
-    ctl->eta = eta;
-    ctl->iters = 0;
-    ctl->go = 1;
-    ctl->forced = forced;
-    ctl->max_iters = max_iters;
+// as k_finish_f64 into the host status (rigid force and torque)
+__global__ void k_finish_rigid(const double* __restrict__ partials, int nblk, int nout, HostStatus* host) {
+    for (int o = 0; o < nout; ++o) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partials[(size_t)b * nout + o];
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) host->rigid[o] = acc;
+    }
 }
 
 // Finish of a predict pass: err = scale * (sum of the partials in workgroup
-// order); after an iteration's predict (not first) count the iteration; then
-// decide whether another one is due: exactly `forced` iterations, else while
-// err > eta and fewer than max_iters.  Nothing happens once go is 0.
-__global__ void k_finish_solve(const double* __restrict__ partials, int nblk, SolveCtl* ctl, bool first) {
-    const int32_t go = ctl->go;
-    if (!first && go == 0) return;
+// order); the solve's first finish starts the control block from init, a
+// later one counts the iteration; then decide whether another one is due:
+// exactly `forced` iterations, else while err > eta and fewer than
+// max_iters.  Nothing happens once go is 0.  The block is mirrored to host.
+__global__ void k_finish_solve(const double* __restrict__ partials, int nblk, SolveCtl* ctl, bool first,
+                               SolveCtl init, HostStatus* host) {
+    if (!first && ctl->go == 0) return;
     double acc = 0.0;
     for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partials[b];
     acc = block_sum(acc);
     if (threadIdx.x == 0) {
-        const double err = acc * ctl->scale;
-        const int32_t it = ctl->iters + (first ? 0 : 1);
-        ctl->err = err;
-        ctl->iters = it;
-        ctl->go = ctl->forced >= 0 ? (it < ctl->forced ? 1 : 0) : ((err > ctl->eta && it < ctl->max_iters) ? 1 : 0);
+        SolveCtl c = first ? init : *ctl;
+        if (first) c.iters = 0;
+        else c.iters += 1;
+        c.err = acc * c.scale;
+        c.go = c.forced >= 0 ? (c.iters < c.forced ? 1 : 0) : ((c.err > c.eta && c.iters < c.max_iters) ? 1 : 0);
+        *ctl = c;
+        host->solve = c;
     }
 }
 
 // neighbour statistics per workgroup (kNStats fields): min, max, then sums
+// Also mirrors the build flags and (tiled builds) the tile count to host.
 __global__ void k_finish_nstats(const unsigned long long* __restrict__ partials, int nblk,
-                                unsigned long long* __restrict__ out) {
+                                const uint32_t* __restrict__ flags, const uint32_t* __restrict__ ntiles,
+                                HostStatus* host) {
     __shared__ unsigned long long s[kNStats][kBlock];
     unsigned long long a[kNStats];
     a[0] = ~0ull;
@@ -179,10 +183,14 @@ __global__ void k_finish_nstats(const unsigned long long* __restrict__ partials,
         }
         __syncthreads();
     }
-    if (threadIdx.x < kNStats) out[threadIdx.x] = s[threadIdx.x][0];
+    if (threadIdx.x < kNStats) host->nstats[threadIdx.x] = s[threadIdx.x][0];
+    if (threadIdx.x == 0) {
+        host->flags = *flags;
+        host->ntiles = ntiles ? *ntiles : 0u;
+    }
 }
 
-__global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk, uint32_t* __restrict__ out) {
+__global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk, HostStatus* host) {
     __shared__ uint32_t s[kBlock];
     uint32_t m = 0;
     for (int b = threadIdx.x; b < nblk; b += kBlock) m = max(m, partials[b]);
@@ -192,7 +200,7 @@ __global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk
         if ((int)threadIdx.x < w) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = s[0];
+    if (threadIdx.x == 0) host->vmax_bits = s[0];
 }
 
 

@@ -59,6 +59,18 @@ struct SolveCtl {
     int32_t max_iters;
 };
 
+// What the host reads after a stream synchronisation: the finishing kernels
+// store it straight into pinned host memory, so no copy is queued for it.
+struct HostStatus {
+    SolveCtl solve;                        // the control block after the last finish
+    uint32_t flags;                        // build flags (bit 0 capacity, bit 1 cell > 4096)
+    uint32_t ntiles;                       // tiles of the last tiled build
+    uint32_t vmax_bits;                    // max |v|^2 (FP32 bits) of the CFL pass
+    uint32_t pad;
+    unsigned long long nstats[kNStats];    // neighbour statistics of the last build
+    double rigid[6 * kMaxBodies];          // force and torque per body
+};
+
 // Pose of one rigid body for the boundary update (FP64).
 struct BodyPose {
     double com[3];
@@ -93,11 +105,11 @@ hipError_t launch_gather_boundary(const uint32_t* src, int64_t n, const float4* 
 hipError_t launch_nbr_build(const float4* x, int64_t nf, const float4* xb, const uint32_t* start_f,
                             const uint32_t* start_b, Grid g, uint32_t* nlist, uint32_t* ncnt, int32_t capf,
                             uint32_t* blist, uint32_t* bcnt, int32_t capb, uint32_t* flags,
-                            unsigned long long* partials, unsigned long long* stats, hipStream_t s);
+                            unsigned long long* partials, HostStatus* host, hipStream_t s);
 hipError_t launch_boundary_psi(float4* xb, int64_t nb, const uint32_t* start_b, Grid g, Kern kc, hipStream_t s);
 
 // the step
-hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, uint32_t* out_bits, hipStream_t s);
+hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, HostStatus* host, hipStream_t s);
 hipError_t launch_density_alpha(int64_t nf, float4* x, const float4* v, const uint32_t* nlist,
                                 const uint32_t* ncnt, const float4* xb, const uint32_t* blist,
                                 const uint32_t* bcnt, Kern kc, float* rho, float* alpha, float4* v_in,
@@ -118,11 +130,11 @@ hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, cons
                           float* kappa, const uint32_t* nlist, const uint32_t* ncnt,
                           const float4* xb, const float4* vb, const uint32_t* blist, const uint32_t* bcnt,
                           Kern kc, float dt, double* partials, SolveCtl* ctl, bool first, float* dout,
-                          hipStream_t s);
-hipError_t launch_solve_init(SolveCtl* ctl, double scale, double eta, int32_t forced, int32_t max_iters,
-                             hipStream_t s);
-// one-workgroup finish of a predict pass over nblk partials (declared for the tiled launchers)
-hipError_t launch_solve_finish(const double* partials, int nblk, SolveCtl* ctl, bool first, hipStream_t s);
+                          int* nparts, hipStream_t s);   // the pass only; nparts partials for the finish
+// One-workgroup finish of a predict pass over nblk partials: the first finish
+// of a solve initialises ctl from init; every finish copies ctl to host->solve.
+hipError_t launch_solve_finish(const double* partials, int nblk, SolveCtl* ctl, bool first, const SolveCtl& init,
+                               HostStatus* host, hipStream_t s);
 // non-pressure: v* = v + dt g + viscosity; also sets up the density warm start
 // (kappa = warm_factor K, K = 0, x.w = kappa / rho).
 hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v, float4* vout, const float* rho,
@@ -134,7 +146,7 @@ hipError_t launch_warm_setup(int64_t nf, float4* x, const float* rho, float* K, 
 hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, hipStream_t s);
 hipError_t launch_rigid_force(int64_t nf, const float4* x, const float* rho, const float* K, const float* Kv,
                               const uint32_t* blist, const uint32_t* bcnt, const float4* xb, const float4* vb,
-                              Kern kc, int32_t nbody, const double* com, double* partials, double* out,
+                              Kern kc, int32_t nbody, const double* com, double* partials, HostStatus* host,
                               hipStream_t s);
 hipError_t launch_rigid_boundary(int64_t nb, float4* xb, float4* vb, const int32_t* bid, const double* local,
                                  const BodyPose* poses, hipStream_t s);
@@ -198,7 +210,7 @@ hipError_t launch_nbr_build_tiled(const TileDesc* tiles, const uint32_t* ntiles_
                                   int64_t nf, const float4* xb, const uint32_t* start_f, const uint32_t* start_b,
                                   Grid g, uint16_t* l16, uint32_t* l32, uint32_t* ncnt, int32_t capf, uint16_t* b16,
                                   uint32_t* b32, uint32_t* bcnt, int32_t capb, uint32_t* flags,
-                                  unsigned long long* partials, unsigned long long* stats, hipStream_t s);
+                                  unsigned long long* partials, HostStatus* host, hipStream_t s);
 // workgroups of a per-tile launch over n tiles (a multiple of 8)
 uint32_t tile_partials(int64_t ntiles);
 // Neighbour lists of the tiled passes.
@@ -220,14 +232,14 @@ hipError_t launch_pressure_update_t(const Lists& L, int64_t nf, const float4* x,
                                     const int32_t* go, hipStream_t s);
 hipError_t launch_predict_t(int mode, const Lists& L, int64_t nf, float4* x, const float4* v, const float* rho,
                             const float* alpha, float* kappa, const float4* xb, const float4* vb, Kern kc, float dt,
-                            double* partials, SolveCtl* ctl, bool first, float* dout, hipStream_t s);
+                            double* partials, SolveCtl* ctl, bool first, float* dout, int* nparts, hipStream_t s);
 hipError_t launch_nonpressure_t(int model, const Lists& L, int64_t nf, float4* x, const float4* v, float4* vout,
                                 const float* rho, Kern kc, float dt, float gx, float gy, float gz, float visc,
                                 float* K, float* kappa, float warm_factor, bool setup_warm, hipStream_t s);
 
 hipError_t launch_rigid_force_t(const Lists& L, int64_t nf, const float4* x, const float* rho, const float* K,
                                 const float* Kv, const float4* xb, const float4* vb, Kern kc, int32_t nbody,
-                                const double* com, double* partials, double* out, hipStream_t s);
+                                const double* com, double* partials, HostStatus* host, hipStream_t s);
 hipError_t launch_visc_precond_t(const Lists& L, int64_t nf, const float4* x, const float* rho, Kern kc, float dt,
                                  float mu, float* Pinv, hipStream_t s);
 hipError_t launch_visc_matvec_t(const Lists& L, int64_t nf, const float4* x, const float* rho, const float4* p,

@@ -821,11 +821,12 @@ hipError_t launch_gather_boundary(const uint32_t* src, int64_t n, const float4* 
 hipError_t launch_nbr_build(const float4* x, int64_t nf, const float4* xb, const uint32_t* start_f,
                             const uint32_t* start_b, Grid g, uint32_t* nlist, uint32_t* ncnt, int32_t capf,
                             uint32_t* blist, uint32_t* bcnt, int32_t capb, uint32_t* flags,
-                            unsigned long long* partials, unsigned long long* stats, hipStream_t s) {
+                            unsigned long long* partials, HostStatus* host, hipStream_t s) {
     const uint32_t nblk = grid_blocks(nf);
     hipLaunchKernelGGL(k_nbr_build, dim3(nblk), dim3(kBlock), 0, s, x, nf, xb, start_f, start_b, g, nlist, ncnt,
                        capf, blist, bcnt, capb, flags, partials);
-    hipLaunchKernelGGL(k_finish_nstats, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, stats);
+    hipLaunchKernelGGL(k_finish_nstats, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, (const uint32_t*)flags,
+                       (const uint32_t*)nullptr, host);
     return hipGetLastError();
 }
 
@@ -834,10 +835,10 @@ hipError_t launch_boundary_psi(float4* xb, int64_t nb, const uint32_t* start_b, 
     LAUNCH(k_boundary_psi, nb, xb, nb, start_b, g, kc);
 }
 
-hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, uint32_t* out_bits, hipStream_t s) {
+hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, HostStatus* host, hipStream_t s) {
     const uint32_t nblk = grid_blocks(n);
     hipLaunchKernelGGL(k_max_v2, dim3(nblk), dim3(kBlock), 0, s, v, n, partials);
-    hipLaunchKernelGGL(k_finish_max_u32, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, out_bits);
+    hipLaunchKernelGGL(k_finish_max_u32, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, host);
     return hipGetLastError();
 }
 
@@ -861,8 +862,11 @@ hipError_t launch_pressure_update(int64_t nf, const float4* x, float4* v, const 
 hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, const float* rho, const float* alpha,
                           float* kappa, const uint32_t* nlist, const uint32_t* ncnt, const float4* xb,
                           const float4* vb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt,
-                          double* partials, SolveCtl* ctl, bool first, float* dout, hipStream_t s) {
+                          double* partials, SolveCtl* ctl, bool first, float* dout, int* nparts,
+                          hipStream_t s) {
     const uint32_t nblk = grid_blocks(nf);
+    *nparts = nf > 0 ? (int)nblk : 0;
+    if (nf <= 0) return hipSuccess;
     const int32_t* go = first ? nullptr : &ctl->go;
     if (mode == 0)
         hipLaunchKernelGGL(k_predict<0>, dim3(nblk), dim3(kBlock), 0, s, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb,
@@ -870,17 +874,12 @@ hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, cons
     else
         hipLaunchKernelGGL(k_predict<1>, dim3(nblk), dim3(kBlock), 0, s, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb,
                            vb, blist, bcnt, kc, dt, partials, go, nullptr);
-    return launch_solve_finish(partials, nf > 0 ? (int)nblk : 0, ctl, first, s);
-}
-
-hipError_t launch_solve_init(SolveCtl* ctl, double scale, double eta, int32_t forced, int32_t max_iters,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(1), 0, s, ctl, scale, eta, forced, max_iters);
     return hipGetLastError();
 }
 
-hipError_t launch_solve_finish(const double* partials, int nblk, SolveCtl* ctl, bool first, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish_solve, dim3(1), dim3(kBlock), 0, s, partials, nblk, ctl, first);
+hipError_t launch_solve_finish(const double* partials, int nblk, SolveCtl* ctl, bool first, const SolveCtl& init,
+                               HostStatus* host, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish_solve, dim3(1), dim3(kBlock), 0, s, partials, nblk, ctl, first, init, host);
     return hipGetLastError();
 }
 
@@ -930,12 +929,12 @@ hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, hi
 
 hipError_t launch_rigid_force(int64_t nf, const float4* x, const float* rho, const float* K, const float* Kv,
                               const uint32_t* blist, const uint32_t* bcnt, const float4* xb, const float4* vb,
-                              Kern kc, int32_t nbody, const double* com, double* partials, double* out,
+                              Kern kc, int32_t nbody, const double* com, double* partials, HostStatus* host,
                               hipStream_t s) {
     const uint32_t nblk = grid_blocks(nf);
     hipLaunchKernelGGL(k_rigid_force, dim3(nblk), dim3(kBlock), 0, s, nf, x, rho, K, Kv, blist, bcnt, xb, vb, kc,
                        nbody, com, partials);
-    hipLaunchKernelGGL(k_finish_f64, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, 6 * nbody, out);
+    hipLaunchKernelGGL(k_finish_rigid, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, 6 * nbody, host);
     return hipGetLastError();
 }
 

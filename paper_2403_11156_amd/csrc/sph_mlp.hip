@@ -169,19 +169,115 @@ __device__ __forceinline__ void forward_tile(const WeightsLDS& W, const AOps& A,
 }
 
 // ---------------------------------------------------------------- inference
+// Inference keeps every weight and bias a lane needs in registers and runs
+// layer 2 on v_mfma_f32_32x32x16_bf16 (K = 16 per instruction, twice the
+// rate of the 32x32x8 form).  A lane contributes eight k values per
+// operand; the contraction does not depend on which eight as long as A and
+// B agree, so lane half h of chunk c takes the hidden units that the
+// layer-1 D registers 8(c&1)..8(c&1)+7 of tile c>>1 already hold:
+// k = 32 (c>>1) + 8 (2 (c&1) + e/4) + 4 h + e%4 for element e.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ int k16(int c, int h, int e) { return 32 * (c >> 1) + 8 * (2 * (c & 1) + (e >> 2)) + 4 * h + (e & 3); }
+
+struct InferRegs {
+    bf16x4 w1[2];
+    bf16x8 w2[2][4];
+    f32x16 b1[2], b2[2], w3[2];
+    float b3, out_scale;
+};
+
+__device__ __forceinline__ void load_infer(const WeightsLDS& W, InferRegs& R) {
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        R.w1[t] = load4(&W.W1b[(32 * t + p) * 8 + 4 * h]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) R.w2[t][c][e] = __builtin_bit_cast(__bf16, W.W2b[(32 * t + p) * H + k16(c, h, e)]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int j = 32 * t + drow(r, h);
+            R.b1[t][r] = W.b1[j];
+            R.b2[t][r] = W.b2[j];
+            R.w3[t][r] = W.w3[j];
+        }
+    }
+    R.b3 = W.b3;
+    R.out_scale = W.out_scale;
+}
+
+// Raw features 4h..4h+3 of sample base + p (0 past the sample or feature count).
+__device__ __forceinline__ void load_features(const float* __restrict__ feat, int64_t n, int64_t base, float fr[4]) {
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+    const int64_t s = base + p;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int k = 4 * h + c;
+        fr[c] = (k < NF && s < n) ? feat[s * NF + k] : 0.f;
+    }
+}
+
+// y of the 32 samples base..base+31 (valid in lanes 0..31 for sample lane)
+// from the raw features fr of load_features
+__device__ __forceinline__ float forward_infer(const WeightsLDS& W, const InferRegs& R, const float fr[4], int64_t n,
+                                               int64_t base) {
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+    const int64_t s = base + p;
+    uint16_t xv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int k = 4 * h + c;
+        float v = 0.f;
+        if (k < NF && s < n) {
+#pragma clang fp contract(off)
+            v = (fr[c] - W.shift[k]) * W.scale[k];
+        }
+        xv[c] = to_bf16(v);
+    }
+    const bf16x4 xb = pack4(xv);
+    f32x16 z1[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) z1[t] = mfma(R.w1[t], xb, R.b1[t]);
+    bf16x8 hb[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) hb[c][e] = (__bf16)fmaxf(z1[c >> 1][8 * (c & 1) + e], 0.f);
+    float part = 0.f;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        f32x16 acc = R.b2[t];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w2[t][c], hb[c], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) part += (float)(__bf16)fmaxf(acc[r], 0.f) * R.w3[t][r];
+    }
+    part += __shfl_xor(part, 32, 64);
+    return (part + R.b3) * R.out_scale;
+}
+
 __global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ P, const float* __restrict__ feat,
                                                      int64_t n, float* __restrict__ y) {
     __shared__ WeightsLDS W;
     load_weights(W, P, false);
-    AOps A;
-    load_aops(W, A);
+    InferRegs R;
+    load_infer(W, R);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t tiles = (n + 31) / 32;
-    for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < tiles; t += (int64_t)gridDim.x * 4) {
-        Fwd f;
-        forward_tile(W, A, feat, n, 32 * t, f);
+    const int64_t tiles = (n + 31) / 32, stride = (int64_t)gridDim.x * 4;
+    // the next tile's features are loaded while this tile is computed
+    float cur[4] = {0.f, 0.f, 0.f, 0.f};
+    int64_t t = (int64_t)blockIdx.x * 4 + wave;
+    if (t < tiles) load_features(feat, n, 32 * t, cur);
+    for (; t < tiles; t += stride) {
+        float nxt[4] = {0.f, 0.f, 0.f, 0.f};
+        if (t + stride < tiles) load_features(feat, n, 32 * (t + stride), nxt);
+        const float out = forward_infer(W, R, cur, n, 32 * t);
         const int64_t s = 32 * t + lane;
-        if (lane < 32 && s < n) y[s] = f.z * W.out_scale;
+        if (lane < 32 && s < n) y[s] = out;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cur[c] = nxt[c];
     }
 }
 
@@ -367,7 +463,7 @@ hipError_t launch_mlp_forward(const float* P, const float* feat, int64_t n, floa
     if (n <= 0) return hipSuccess;
     const int64_t tiles = (n + 31) / 32;
     int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 1024) blocks = 1024;   // about two resident waves per SIMD; weights staged once per block
     hipLaunchKernelGGL(k_mlp_forward, dim3((uint32_t)blocks), dim3(256), 0, s, P, feat, n, y);
     return hipGetLastError();
 }

@@ -808,12 +808,13 @@ hipError_t launch_nbr_build_tiled(const TileDesc* tiles, const uint32_t* ntiles_
                                   int64_t nf, const float4* xb, const uint32_t* start_f, const uint32_t* start_b,
                                   Grid g, uint16_t* l16, uint32_t* l32, uint32_t* ncnt, int32_t capf, uint16_t* b16,
                                   uint32_t* b32, uint32_t* bcnt, int32_t capb, uint32_t* flags,
-                                  unsigned long long* partials, unsigned long long* stats, hipStream_t s) {
+                                  unsigned long long* partials, HostStatus* host, hipStream_t s) {
     if (capf > kCapF || capb > kCapB) return hipErrorInvalidValue;
     const uint32_t nblk = tile_blocks(max_t);
     hipLaunchKernelGGL(k_nbr_build_tiled, dim3(nblk), dim3(kTile), 0, s, tiles, ntiles_dev, x, nf, xb, start_f,
                        start_b, g, l16, l32, ncnt, capf, b16, b32, bcnt, capb, flags, partials);
-    hipLaunchKernelGGL(k_finish_nstats, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, stats);
+    hipLaunchKernelGGL(k_finish_nstats, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, (const uint32_t*)flags,
+                       ntiles_dev, host);
     return hipGetLastError();
 }
 
@@ -838,18 +839,18 @@ hipError_t launch_pressure_update_t(const Lists& L, int64_t nf, const float4* x,
 
 hipError_t launch_predict_t(int mode, const Lists& L, int64_t nf, float4* x, const float4* v, const float* rho,
                             const float* alpha, float* kappa, const float4* xb, const float4* vb, Kern kc, float dt,
-                            double* partials, SolveCtl* ctl, bool first, float* dout, hipStream_t s) {
+                            double* partials, SolveCtl* ctl, bool first, float* dout, int* nparts, hipStream_t s) {
     const uint32_t nblk = tile_blocks(L.ntiles);
+    *nparts = L.ntiles > 0 ? (int)nblk : 0;
+    if (L.ntiles <= 0) return hipSuccess;
     const int32_t* go = first ? nullptr : &ctl->go;
-    if (L.ntiles > 0) {
-        if (mode == 0)
-            hipLaunchKernelGGL(k_predict_t<0>, dim3(nblk), dim3(kTile), 0, s, L, nf, x, v, rho, alpha, kappa, xb, vb,
-                               kc, dt, partials, go, dout);
-        else
-            hipLaunchKernelGGL(k_predict_t<1>, dim3(nblk), dim3(kTile), 0, s, L, nf, x, v, rho, alpha, kappa, xb, vb,
-                               kc, dt, partials, go, nullptr);
-    }
-    return launch_solve_finish(partials, L.ntiles > 0 ? (int)nblk : 0, ctl, first, s);
+    if (mode == 0)
+        hipLaunchKernelGGL(k_predict_t<0>, dim3(nblk), dim3(kTile), 0, s, L, nf, x, v, rho, alpha, kappa, xb, vb, kc,
+                           dt, partials, go, dout);
+    else
+        hipLaunchKernelGGL(k_predict_t<1>, dim3(nblk), dim3(kTile), 0, s, L, nf, x, v, rho, alpha, kappa, xb, vb, kc,
+                           dt, partials, go, nullptr);
+    return hipGetLastError();
 }
 
 hipError_t launch_nonpressure_t(int model, const Lists& L, int64_t nf, float4* x, const float4* v, float4* vout,
@@ -865,13 +866,13 @@ hipError_t launch_nonpressure_t(int model, const Lists& L, int64_t nf, float4* x
 
 hipError_t launch_rigid_force_t(const Lists& L, int64_t nf, const float4* x, const float* rho, const float* K,
                                 const float* Kv, const float4* xb, const float4* vb, Kern kc, int32_t nbody,
-                                const double* com, double* partials, double* out, hipStream_t s) {
+                                const double* com, double* partials, HostStatus* host, hipStream_t s) {
     const uint32_t nblk = tile_blocks(L.ntiles);
     if (L.ntiles > 0)
         hipLaunchKernelGGL(k_rigid_force_t, dim3(nblk), dim3(kTile), 0, s, L, nf, x, rho, K, Kv, xb, vb, kc, nbody,
                            com, partials);
-    hipLaunchKernelGGL(k_finish_f64, dim3(1), dim3(kBlock), 0, s, partials, L.ntiles > 0 ? (int)nblk : 0, 6 * nbody,
-                       out);
+    hipLaunchKernelGGL(k_finish_rigid, dim3(1), dim3(kBlock), 0, s, partials, L.ntiles > 0 ? (int)nblk : 0, 6 * nbody,
+                       host);
     return hipGetLastError();
 }
 
