@@ -836,8 +836,9 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     ALLOC(c->kappa, nf); ALLOC(c->kappa_last, nf); ALLOC(c->id, nf); ALLOC(c->id2, nf);
     ALLOC(c->key, nf); ALLOC(c->slot, nf); ALLOC(c->src, nf);
     ALLOC(c->count, ncell); ALLOC(c->start_f, ncell + 1); ALLOC(c->start_b, ncell + 1); ALLOC(c->scan_part, 2 * tiles + 8);
-    ALLOC(c->nlist, (int64_t)c->capf * nf); ALLOC(c->ncnt, nf);
-    ALLOC(c->blist, (int64_t)c->capb * nf); ALLOC(c->bcnt, nf);
+    // 32-bit lists in chunks of four entries (capacity rounded up to a chunk)
+    ALLOC(c->nlist, (int64_t)(c->capf + 3) / 4 * 4 * nf); ALLOC(c->ncnt, nf);
+    ALLOC(c->blist, (int64_t)(c->capb + 3) / 4 * 4 * nf); ALLOC(c->bcnt, nf);
     ALLOC(c->xb, nb); ALLOC(c->xb2, nb); ALLOC(c->vb, nb); ALLOC(c->vb2, nb); ALLOC(c->bid, nb); ALLOC(c->bid2, nb);
     ALLOC(c->bkey, nb); ALLOC(c->bslot, nb); ALLOC(c->bsrc, nb); ALLOC(c->blocal, 3 * nb);
     ALLOC(c->poses, std::max(1, c->nr)); ALLOC(c->com_dev, 3 * std::max(1, c->nr));
@@ -1175,33 +1176,40 @@ int sph_read_neighbors(sph_ctx *c, const sph_nbr_view *d) {
             for (int64_t s = 0; s < nf; ++s) counts[s] = n[s];
         if (!out) return SPH_OK;
         if (tot > outcap) return fail(c, SPH_ERR_CAPACITY, "CSR capacity too small");
-        const size_t len = (size_t)std::max<int64_t>((int64_t)cap * nf, 1);
-        std::vector<uint32_t> L(len);
-        HIP_TRY(c, hipMemcpyAsync(L.data(), dev, sizeof(uint32_t) * (size_t)cap * nf, hipMemcpyDeviceToHost, c->stream));
+        // 32-bit lists: chunks of four entries, chunk-major (entry k of s at 4 ((k/4) nf + s) + k%4)
+        const int64_t cap4 = ((int64_t)cap + 3) / 4 * 4;
+        std::vector<uint32_t> L((size_t)std::max<int64_t>(cap4 * nf, 1));
+        HIP_TRY(c, hipMemcpyAsync(L.data(), dev, sizeof(uint32_t) * (size_t)(cap4 * nf), hipMemcpyDeviceToHost,
+                                  c->stream));
         std::vector<uint16_t> L16;
+        std::vector<int32_t> tile_of;   // ok tile holding each particle, -1 otherwise
         if (c->tiled) {
-            L16.resize(len);
+            L16.resize((size_t)std::max<int64_t>((int64_t)cap * nf, 1));
             HIP_TRY(c, hipMemcpyAsync(L16.data(), dev16, sizeof(uint16_t) * (size_t)cap * nf, hipMemcpyDeviceToHost,
                                       c->stream));
+            tile_of.assign((size_t)std::max<int64_t>(nf, 1), -1);
+            for (int64_t t = 0; t < c->ntiles; ++t)
+                if (tiles[t].ok)
+                    for (int64_t q = tiles[t].p0; q < tiles[t].p1; ++q) tile_of[q] = (int32_t)t;
         }
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        if (c->tiled) {
-            for (int64_t t = 0; t < c->ntiles; ++t) {
-                const sph::TileDesc &T = tiles[t];
-                if (!T.ok) continue;
-                const int32_t *first = fluid ? T.fb : T.bb, *off = fluid ? T.foff : T.boff;
-                for (int64_t s = T.p0; s < T.p1; ++s)
-                    for (uint32_t k = 0; k < std::min<uint32_t>(n[s], (uint32_t)cap); ++k) {
-                        const int32_t q = L16[(size_t)k * nf + s];
-                        int r = 0;
-                        while (r < 8 && q >= off[r + 1]) ++r;
-                        L[(size_t)k * nf + s] = (uint32_t)(first[r] + (q - off[r]));
-                    }
+        int64_t o = 0;
+        for (int64_t q = 0; q < nf; ++q) {
+            const uint32_t m = std::min<uint32_t>(n[q], (uint32_t)cap);
+            const int32_t t = c->tiled ? tile_of[q] : -1;
+            for (uint32_t k = 0; k < m; ++k) {
+                if (t < 0) {
+                    out[o++] = L[(size_t)(4 * ((int64_t)(k >> 2) * nf + q) + (k & 3))];
+                } else {
+                    const sph::TileDesc &T = tiles[t];
+                    const int32_t *first = fluid ? T.fb : T.bb, *off = fluid ? T.foff : T.boff;
+                    const int32_t slot = L16[(size_t)k * nf + q];
+                    int r = 0;
+                    while (r < 8 && slot >= off[r + 1]) ++r;
+                    out[o++] = (uint32_t)(first[r] + (slot - off[r]));
+                }
             }
         }
-        int64_t o = 0;
-        for (int64_t s = 0; s < nf; ++s)
-            for (uint32_t k = 0; k < std::min<uint32_t>(n[s], (uint32_t)cap); ++k) out[o++] = L[(size_t)k * nf + s];
         return SPH_OK;
     };
     if ((rc = csr(c->nlist, c->l16, true, c->capf, cnt, d->counts_f, d->lists_f, d->cap_f))) return rc;

@@ -70,25 +70,35 @@ __device__ __forceinline__ float kernel_W(float r2, const Kern& kc) {
     return q <= 0.5f ? kc.k * (6.0f * q * q * (q - 1.0f) + 1.0f) : kc.k * 2.0f * t * t * t;
 }
 
-// Visit the first n entries of particle i's neighbour-major list in chunks of
-// four: the four list loads, then the four gathers done by `f`, are issued
-// before any of the arithmetic, so each wave keeps several gathers in flight.
+// Neighbour lists (32-bit sorted indices): entry k of particle i sits in
+// chunk k/4 of four entries, chunks stored chunk-major,
+// list[4 ((k/4) nf + i) + k%4]; a wave reads or writes one chunk of its 64
+// consecutive particles as a single coalesced 1 KB access.
+__device__ __forceinline__ int64_t list_index(int64_t nf, int64_t i, uint32_t k) {
+    return (((int64_t)(k >> 2) * nf + i) << 2) + (k & 3u);
+}
+
+// Visit the first n entries of particle i's list: one 16-byte load brings
+// four entries, and the four gathers done by `f` are issued before any of the
+// arithmetic, so each wave keeps several gathers in flight.
 template <class F>
 __device__ __forceinline__ void for_each_nbr(const uint32_t* __restrict__ list, int64_t nf, int64_t i, uint32_t n,
                                              F&& f) {
-    const uint32_t* p = list + i;
+    const uint4* p = reinterpret_cast<const uint4*>(list) + i;
     uint32_t k = 0;
     for (; k + 4 <= n; k += 4) {
-        const uint32_t j0 = p[0], j1 = p[nf], j2 = p[2 * nf], j3 = p[3 * nf];
-        p += 4 * nf;
-        f(j0);
-        f(j1);
-        f(j2);
-        f(j3);
-    }
-    for (; k < n; ++k) {
-        f(*p);
+        const uint4 q = *p;
         p += nf;
+        f(q.x);
+        f(q.y);
+        f(q.z);
+        f(q.w);
+    }
+    if (k < n) {   // the last chunk is allocated whole; entries past n are not used
+        const uint4 q = *p;
+        f(q.x);
+        if (k + 1 < n) f(q.y);
+        if (k + 2 < n) f(q.z);
     }
 }
 
@@ -225,14 +235,22 @@ __device__ __forceinline__ void for_each_slot(const uint16_t* __restrict__ list,
 }
 
 // Append the candidates c in [b, e) (ascending) with c != skip and the FP32
-// predicate d^2 < h^2 to row i of the neighbour-major list; candidates are
-// loaded four at a time ahead of the tests.
+// predicate d^2 < h^2 to particle i's list: entries gather in buf and go out
+// as whole 16-byte chunks (list_flush stores the last, partial one);
+// candidates are loaded four at a time ahead of the tests.
 __device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, uint32_t b, uint32_t e, float4 xi,
                                                 int64_t i, int64_t skip, float h2, uint32_t* __restrict__ list,
-                                                int64_t nf, int32_t cap, uint32_t& cnt) {
+                                                int64_t nf, int32_t cap, uint32_t& cnt, uint4& buf) {
     auto take = [&](uint32_t c, float4 p) {
         if ((int64_t)c != skip && dist2_exact(xi, p) < h2) {
-            if (cnt < (uint32_t)cap) list[(int64_t)cnt * nf + i] = c;
+            if (cnt < (uint32_t)cap) {
+                const uint32_t s = cnt & 3u;
+                buf.x = s == 0u ? c : buf.x;
+                buf.y = s == 1u ? c : buf.y;
+                buf.z = s == 2u ? c : buf.z;
+                buf.w = s == 3u ? c : buf.w;
+                if (s == 3u) reinterpret_cast<uint4*>(list)[(int64_t)(cnt >> 2) * nf + i] = buf;
+            }
             ++cnt;
         }
     };
@@ -245,6 +263,13 @@ __device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, 
         take(c + 3, p3);
     }
     for (; c < e; ++c) take(c, pos[c]);
+}
+
+// Store the partial last chunk of a list filled by scan_candidates.
+__device__ __forceinline__ void list_flush(uint32_t* __restrict__ list, int64_t nf, int64_t i, int32_t cap,
+                                           uint32_t cnt, uint4 buf) {
+    const uint32_t n = min(cnt, (uint32_t)cap);
+    if (n & 3u) reinterpret_cast<uint4*>(list)[(int64_t)(n >> 2) * nf + i] = buf;
 }
 
 }  // namespace

@@ -181,6 +181,7 @@ __global__ void __launch_bounds__(kBlock) k_nbr_build(
         const int32_t cz = cell_coord(xi.z, g.o[2], g.inv, g.n[2]);
         const int32_t x0 = cx > 0 ? cx - 1 : 0, x1 = cx < g.n[0] - 1 ? cx + 1 : g.n[0] - 1;
         uint32_t nfc = 0, nbc = 0;
+        uint4 fbuf = make_uint4(0u, 0u, 0u, 0u), bbuf = make_uint4(0u, 0u, 0u, 0u);
         for (int32_t dz = -1; dz <= 1; ++dz) {
             const int32_t z = cz + dz;
             if (z < 0 || z >= g.n[2]) continue;
@@ -189,11 +190,13 @@ __global__ void __launch_bounds__(kBlock) k_nbr_build(
                 if (y < 0 || y >= g.n[1]) continue;
                 const int64_t row = (int64_t)g.n[0] * (y + (int64_t)g.n[1] * z);
                 const uint32_t b = start_f[row + x0], e = start_f[row + x1 + 1];
-                scan_candidates(x, b, e, xi, i, i, g.h2, nlist, nf, capf, nfc);
+                scan_candidates(x, b, e, xi, i, i, g.h2, nlist, nf, capf, nfc, fbuf);
                 const uint32_t bb = start_b[row + x0], be = start_b[row + x1 + 1];
-                scan_candidates(xb, bb, be, xi, i, -1, g.h2, blist, nf, capb, nbc);
+                scan_candidates(xb, bb, be, xi, i, -1, g.h2, blist, nf, capb, nbc, bbuf);
             }
         }
+        list_flush(nlist, nf, i, capf, nfc, fbuf);
+        list_flush(blist, nf, i, capb, nbc, bbuf);
         // stored counts never exceed the capacity, so readers stay in bounds
         ncnt[i] = min(nfc, (uint32_t)capf);
         bcnt[i] = min(nbc, (uint32_t)capb);
@@ -539,7 +542,7 @@ __global__ void __launch_bounds__(kBlock) k_rigid_force(
     for (int32_t b = 0; b < nbody; ++b) {
         double f[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0};
         for (uint32_t k = 0; k < nbk; ++k) {
-            const uint32_t kk = blist[(int64_t)k * nf + i];
+            const uint32_t kk = blist[list_index(nf, i, k)];
             const float4 vk = vb[kk];
             if ((int32_t)vk.w != b) continue;
             const float4 xk = xb[kk];

@@ -340,6 +340,7 @@ __global__ void __launch_bounds__(kTile) k_nbr_build_tiled(
             }
         } else if (mine) {
             // over-full tile: 32-bit sorted indices from a global-memory search
+            uint4 fbuf = make_uint4(0u, 0u, 0u, 0u), bbuf = make_uint4(0u, 0u, 0u, 0u);
             for (int32_t dz = -1; dz <= 1; ++dz) {
                 const int32_t z = cz + dz;
                 if (z < 0 || z >= g.n[2]) continue;
@@ -347,11 +348,14 @@ __global__ void __launch_bounds__(kTile) k_nbr_build_tiled(
                     const int32_t y = cy + dy;
                     if (y < 0 || y >= g.n[1]) continue;
                     const int64_t row = (int64_t)g.n[0] * (y + (int64_t)g.n[1] * z);
-                    scan_candidates(x, start_f[row + x0], start_f[row + x1 + 1], xi, i, i, g.h2, l32, nf, capf, nfc);
+                    scan_candidates(x, start_f[row + x0], start_f[row + x1 + 1], xi, i, i, g.h2, l32, nf, capf, nfc,
+                                    fbuf);
                     scan_candidates(xb, start_b[row + x0], start_b[row + x1 + 1], xi, i, -1, g.h2, b32, nf, capb,
-                                    nbc);
+                                    nbc, bbuf);
                 }
             }
+            list_flush(l32, nf, i, capf, nfc, fbuf);
+            list_flush(b32, nf, i, capb, nbc, bbuf);
         }
         if (mine) {
             ncnt[i] = min(nfc, (uint32_t)capf);
@@ -677,7 +681,7 @@ __global__ void __launch_bounds__(kTile) k_rigid_force_t(Lists L, int64_t nf, co
                 while (r < 8 && s >= d->boff[r + 1]) ++r;
                 kk = (uint32_t)(d->bb[r] + (s - d->boff[r]));
             } else {
-                kk = L.b32[(int64_t)k * nf + i];
+                kk = L.b32[list_index(nf, i, k)];
             }
             const float4 vk = vb[kk];
             if ((int32_t)vk.w != b) continue;
