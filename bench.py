@@ -24,9 +24,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 # per-launch algorithmic bytes are computed inside the library (see the
 # design notes: own fields of every particle read/written once plus 4 B per
 # neighbour-list entry)
-PROFILED = ("pressure_update", "predict", "density_alpha", "xsph", "nbr_build", "sort", "tiles", "integrate",
-            "visc", "warm_features", "mlp")
-KERNEL_SOURCES = ("sph_kernels.hip", "sph_tiled.hip", "sph_device.h", "sph_internal.h")
+PROFILED = ("pressure_update", "predict", "density_alpha", "xsph", "nbr_build", "sort", "integrate", "visc",
+            "warm_features", "mlp")
+KERNEL_SOURCES = ("sph_kernels.hip", "sph_device.h", "sph_internal.h")
 
 
 def parse():
@@ -39,8 +39,6 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--arm", choices=("plain", "learned", "both"), default="both",
                     help="warm start of the density solve: previous-step (plain) and/or the trained MLP")
-    ap.add_argument("--layout", choices=("tiled", "untiled"), default="untiled",
-                    help="neighbour passes over LDS-staged cell-row tiles or one thread per particle")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -124,7 +122,6 @@ def main():
     results = {}
     for arm in arms:
         sim = sph.Simulation(sc)
-        sim.set_tiling(args.layout == "tiled")
         net = None
         if arm == "learned":
             import numpy as np
@@ -179,8 +176,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc.name, "n_fluid": sc.n_fluid, "n_boundary": sc.n_boundary,
                    "n_rigid": len(sc.rigid), "r": sc.params["r"], "eta": sc.params["eta_density"],
-                   "warm_start": arms[0], "layout": args.layout, "parallelism": "none (1 GPU)"},
-        "tiles": {"n": info["n_tiles"], "overfull": info["n_tiles_overfull"]},
+                   "warm_start": arms[0], "parallelism": "none (1 GPU)"},
         "iters_per_step": {"div": sum(i[0] for i in iters) / n, "dens": sum(i[1] for i in iters) / n,
                            "cg": sum(i[2] for i in iters) / n},
         "max_err_dens": max(i[3] for i in iters), "max_err_div": max(i[4] for i in iters),

@@ -179,9 +179,6 @@ typedef struct sph_info {
     float h2;                /* fl32(h)^2, the neighbour predicate d^2 < h2 */
     int32_t max_neighbors, max_boundary_neighbors;
     int64_t device_bytes;    /* device memory the context holds */
-    int32_t tiled;           /* 1: cell-row tiles with LDS staging (sph_set_tiling) */
-    int64_t n_tiles;         /* tiles of the last neighbour build */
-    int64_t n_tiles_overfull;/* of those, tiles past the LDS budget (32-bit lists, global gathers) */
 } sph_info;
 
 /* ---- life cycle -------------------------------------------------------- */
@@ -249,28 +246,12 @@ int sph_read_neighbors(sph_ctx *ctx, const sph_nbr_view *dst);
  * whose stop decision falls within rounding of eta. */
 int sph_set_forced_iters(sph_ctx *ctx, int32_t div, int32_t dens);
 
-/* Execution layout of the neighbour passes (no effect on the results beyond
- * the order of the FP64 partial sums).  enable = 0 (the default): one thread
- * per particle over 32-bit sorted-index lists, gathers from global memory.
- * enable = 1 (only when max_neighbors <= 64 and max_boundary_neighbors <=
- * 48; allocates the tile buffers on first use): fluid particles are processed
- * in tiles of up to 128 consecutive sorted particles of one row of cells; each
- * pass stages the tile's stencil in LDS one z-slab at a time and the lists
- * hold 16-bit slots into that staging.
- * slab_limit (0 = the default 640, at most 640) is the most particles of one
- * set a tile may stage per z-slab; tiles above it keep 32-bit lists and
- * global gathers (sph_info.n_tiles_overfull counts them).  A change
- * invalidates the neighbour lists (call sph_build_neighbors).  Returns
- * SPH_ERR_INVALID for enable = 1 when the capacities exceed the tiled limits,
- * or for a slab_limit outside [0, 640]. */
-int sph_set_tiling(sph_ctx *ctx, int32_t enable, int32_t slab_limit);
-
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch of the named kernels while enabled.  sph_profile_read returns
  * the launch count and the summed event time [ms] of one kernel name, and the
  * algorithmic bytes those launches moved by the model stated in the design
  * notes.  Names: "nbr_build", "density_alpha", "pressure_update", "predict",
- * "xsph", "visc", "sort", "tiles", "warm_features", "mlp", "integrate". */
+ * "xsph", "visc", "sort", "warm_features", "mlp", "integrate". */
 int sph_profile_enable(sph_ctx *ctx, int32_t enable);
 int sph_profile_read(sph_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms, double *bytes);
 

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsph.so")
-SOURCES = ["sph_kernels.hip", "sph_tiled.hip", "sph_mlp.hip", "sph_api.cpp"]
+SOURCES = ["sph_kernels.hip", "sph_mlp.hip", "sph_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -27,13 +27,14 @@ def build(verbose: bool = False) -> str:
     os.makedirs(tmpdir, exist_ok=True)
     for src in SOURCES:
         path = os.path.join(CSRC, src)
-        if not os.path.exists(path):
-            continue
         obj = os.path.join(tmpdir, src + ".o")
         cmd = [HIPCC, *FLAGS, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True, stderr=subprocess.PIPE if not verbose else None)
+        r = subprocess.run(cmd, stderr=subprocess.PIPE if not verbose else None, text=True)
+        if r.returncode != 0:
+            errs = [l for l in (r.stderr or "").splitlines() if "error" in l or "note:" in l]
+            raise RuntimeError(f"hipcc failed on {src}:\n" + "\n".join(errs[:40]))
         objs.append(obj)
     tmp = LIB + ".tmp"
     subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs], check=True)

@@ -60,14 +60,6 @@ struct sph_ctx {
     uint32_t *key = nullptr, *slot = nullptr, *src = nullptr, *count = nullptr, *start_f = nullptr;
     uint32_t *scan_part = nullptr;
     uint32_t *nlist = nullptr, *ncnt = nullptr, *blist = nullptr, *bcnt = nullptr;
-    // cell-row tiles and their 16-bit lists
-    bool tiled = false, tile_capable = false;
-    int32_t slab_limit = sph::kSlab;
-    int64_t nrows = 0, max_t = 0, ntiles = 0, n_over = 0;
-    double over_entries = 0.0;
-    sph::TileDesc *tiles = nullptr;
-    uint32_t *tilecnt = nullptr, *tileoff = nullptr, *tilerow = nullptr;
-    uint16_t *l16 = nullptr, *b16 = nullptr;
     // boundary, sorted order (xb.w = Psi, vb.w = body id)
     float4 *xb = nullptr, *xb2 = nullptr, *vb = nullptr, *vb2 = nullptr;
     int32_t *bid = nullptr, *bid2 = nullptr;
@@ -347,20 +339,9 @@ int sort_boundary(sph_ctx *c) {
     return SPH_OK;
 }
 
-// algorithmic bytes of reading every neighbour-list entry once: 4 B per
-// sorted index, 2 B per slot of a tiled list (over-full tiles keep 4 B)
-double list_bytes(const sph_ctx *c) {
-    return c->tiled ? 2.0 * (c->nbr_sum - c->over_entries) + 4.0 * c->over_entries : 4.0 * c->nbr_sum;
-}
-double fluid_list_bytes(const sph_ctx *c) {
-    // over-full entries are not split by set; count them all as fluid
-    const double over = std::min(c->over_entries, c->nbr_sum_f);
-    return c->tiled ? 2.0 * (c->nbr_sum_f - over) + 4.0 * over : 4.0 * c->nbr_sum_f;
-}
-
-sph::Lists tile_lists(const sph_ctx *c) {
-    return sph::Lists{c->tiles, c->ntiles, c->l16, c->nlist, c->ncnt, c->b16, c->blist, c->bcnt};
-}
+// algorithmic bytes of reading every neighbour-list entry once (4 B each)
+double list_bytes(const sph_ctx *c) { return 4.0 * c->nbr_sum; }
+double fluid_list_bytes(const sph_ctx *c) { return 4.0 * c->nbr_sum_f; }
 
 int build(sph_ctx *c) {
     hipStream_t s = c->stream;
@@ -376,25 +357,13 @@ int build(sph_ctx *c) {
         int rc = sort_fluid(c);
         if (rc) return rc;
     }
-    if (c->tiled) {
-        {
-            ProfScope ps(c, "tiles", 8.0 * c->nrows + 18.0 * 4.0 * c->nrows + sizeof(sph::TileDesc) * (double)c->ntiles);
-            HIP_TRY(c, sph::launch_tiles_build(c->x, c->start_f, c->start_b, c->g, c->slab_limit, c->tilecnt,
-                                               c->tileoff, c->tilerow, c->max_t, c->scan_part, c->tiles, s));
-        }
-        ProfScope ps(c, "nbr_build", 16.0 * c->nf + 8.0 * c->nf + list_bytes(c));
-        HIP_TRY(c, sph::launch_nbr_build_tiled(c->tiles, c->tileoff + c->nrows, c->max_t, c->x, c->nf, c->xb,
-                                               c->start_f, c->start_b, c->g, c->l16, c->nlist, c->ncnt, c->capf,
-                                               c->b16, c->blist, c->bcnt, c->capb, c->flags, c->nstat_part,
-                                               c->hs_dev, s));
-    } else {
+    {
         ProfScope ps(c, "nbr_build", 16.0 * c->nf + 8.0 * c->nf + list_bytes(c));
         HIP_TRY(c, sph::launch_nbr_build(c->x, c->nf, c->xb, c->start_f, c->start_b, c->g, c->nlist, c->ncnt, c->capf,
                                          c->blist, c->bcnt, c->capb, c->flags, c->nstat_part, c->hs_dev, s));
     }
     HIP_TRY(c, hipStreamSynchronize(s));
     const sph::HostStatus &hs = *c->hs;
-    c->ntiles = c->tiled ? (int64_t)hs.ntiles : 0;
     c->sorted_once = true;
     if (hs.flags & 2u) {
         c->nbr_fresh = false;
@@ -407,8 +376,6 @@ int build(sph_ctx *c) {
     for (int f = 0; f < sph::kNStats; ++f) c->nstats[f] = hs.nstats[f];
     c->nbr_sum = (double)hs.nstats[2];
     c->nbr_sum_f = (double)hs.nstats[3];
-    c->over_entries = (double)hs.nstats[4];
-    c->n_over = (int64_t)hs.nstats[5];
     c->nbr_fresh = true;
     return SPH_OK;
 }
@@ -417,12 +384,8 @@ int build(sph_ctx *c) {
 // iterations.
 int pressure_pass(sph_ctx *c, float *Kacc, float *klast, float dt, const int32_t *go) {
     ProfScope ps(c, "pressure_update", (48.0 + (klast ? 24.0 : 20.0)) * c->nf + list_bytes(c));
-    if (c->tiled)
-        HIP_TRY(c, sph::launch_pressure_update_t(tile_lists(c), c->nf, c->x, c->v, c->kappa, Kacc, klast, c->xb, c->kc,
-                                                 dt, go, c->stream));
-    else
-        HIP_TRY(c, sph::launch_pressure_update(c->nf, c->x, c->v, c->kappa, Kacc, klast, c->nlist, c->ncnt, c->xb,
-                                               c->blist, c->bcnt, c->kc, dt, go, c->stream));
+    HIP_TRY(c, sph::launch_pressure_update(c->nf, c->x, c->v, c->kappa, Kacc, klast, c->nlist, c->ncnt, c->xb,
+                                           c->blist, c->bcnt, c->kc, dt, go, c->stream));
     return SPH_OK;
 }
 
@@ -432,13 +395,9 @@ int predict_pass(sph_ctx *c, int mode, float dt, bool first, const sph::SolveCtl
     int nparts = 0;
     {
         ProfScope ps(c, "predict", (56.0 + (dout ? 4.0 : 0.0)) * c->nf + list_bytes(c));
-        if (c->tiled)
-            HIP_TRY(c, sph::launch_predict_t(mode, tile_lists(c), c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->xb,
-                                             c->vb, c->kc, dt, c->red_part, c->ctl, first, dout, &nparts, c->stream));
-        else
-            HIP_TRY(c, sph::launch_predict(mode, c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->nlist, c->ncnt,
-                                           c->xb, c->vb, c->blist, c->bcnt, c->kc, dt, c->red_part, c->ctl, first,
-                                           dout, &nparts, c->stream));
+        HIP_TRY(c, sph::launch_predict(mode, c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->nlist, c->ncnt,
+                                       c->xb, c->vb, c->blist, c->bcnt, c->kc, dt, c->red_part, c->ctl, first,
+                                       dout, &nparts, c->stream));
     }
     HIP_TRY(c, sph::launch_solve_finish(c->red_part, nparts, c->ctl, first, init, c->hs_dev, c->stream));
     return SPH_OK;
@@ -496,7 +455,6 @@ int jacobi_solve(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, int3
 }
 
 hipError_t visc_matvec(sph_ctx *c, const float4 *p, float4 *Mp, float dt, float mu) {
-    if (c->tiled) return sph::launch_visc_matvec_t(tile_lists(c), c->nf, c->x, c->rho, p, Mp, c->kc, dt, mu, c->stream);
     return sph::launch_visc_matvec(c->nf, c->x, c->rho, p, Mp, c->nlist, c->ncnt, c->kc, dt, mu, c->stream);
 }
 
@@ -511,10 +469,7 @@ int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
     HIP_TRY(c, hipMemcpyAsync(c->v2, c->cg_b, sizeof(float4) * nf, hipMemcpyDeviceToDevice, s));   // x0 = b
     {
         ProfScope ps(c, "visc", 60.0 * nf + fluid_list_bytes(c));
-        if (c->tiled)
-            HIP_TRY(c, sph::launch_visc_precond_t(tile_lists(c), nf, c->x, c->rho, c->kc, dt, mu, c->Pinv, s));
-        else
-            HIP_TRY(c, sph::launch_visc_precond(nf, c->x, c->rho, c->nlist, c->ncnt, c->kc, dt, mu, c->Pinv, s));
+        HIP_TRY(c, sph::launch_visc_precond(nf, c->x, c->rho, c->nlist, c->ncnt, c->kc, dt, mu, c->Pinv, s));
     }
     {
         ProfScope ps(c, "visc", 44.0 * nf + fluid_list_bytes(c));
@@ -587,12 +542,8 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     // 2. density, alpha; divergence warm-start set-up
     {
         ProfScope ps(c, "density_alpha", 80.0 * nf + list_bytes(c));
-        if (c->tiled)
-            HIP_TRY(c, sph::launch_density_alpha_t(tile_lists(c), nf, c->x, c->v, c->xb, c->kc, c->rho, c->alpha,
-                                                   c->v_in, c->Kv, c->kappa, wf, s));
-        else
-            HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, c->nlist, c->ncnt, c->xb, c->blist, c->bcnt, c->kc,
-                                                 c->rho, c->alpha, c->v_in, c->Kv, c->kappa, wf, s));
+        HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, c->nlist, c->ncnt, c->xb, c->blist, c->bcnt, c->kc,
+                                             c->rho, c->alpha, c->v_in, c->Kv, c->kappa, wf, s));
     }
     // 3. divergence-free solve
     if (warm) {
@@ -615,14 +566,9 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         if (setup_in_pass) HIP_TRY(c, sph::launch_warm_setup(nf, c->x, c->rho, c->K, c->kappa, wf, s));
     } else {
         ProfScope ps(c, "xsph", 72.0 * nf + fluid_list_bytes(c));
-        if (c->tiled)
-            HIP_TRY(c, sph::launch_nonpressure_t(c->P.visc_model, tile_lists(c), nf, c->x, c->v, c->v2, c->rho, c->kc,
-                                                 dt, gx, gy, gz, (float)c->P.visc, c->K, c->kappa, wf, setup_in_pass,
-                                                 s));
-        else
-            HIP_TRY(c, sph::launch_nonpressure(c->P.visc_model, nf, c->x, c->v, c->v2, c->rho, c->nlist, c->ncnt,
-                                               c->kc, dt, gx, gy, gz, (float)c->P.visc, c->K, c->kappa, wf,
-                                               setup_in_pass, s));
+        HIP_TRY(c, sph::launch_nonpressure(c->P.visc_model, nf, c->x, c->v, c->v2, c->rho, c->nlist, c->ncnt,
+                                           c->kc, dt, gx, gy, gz, (float)c->P.visc, c->K, c->kappa, wf,
+                                           setup_in_pass, s));
         std::swap(c->v, c->v2);
     }
     // 5. warm start of the density solve: the previous stiffness, or the MLP's
@@ -663,12 +609,8 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     }
     // 7. rigid bodies: Eq. 14 reaction, FP64 Newton-Euler, new boundary pose
     if (c->nr > 0) {
-        if (c->tiled)
-            HIP_TRY(c, sph::launch_rigid_force_t(tile_lists(c), nf, c->x, c->rho, c->K, c->Kv, c->xb, c->vb, c->kc,
-                                                 c->nr, c->com_dev, c->red_part, c->hs_dev, s));
-        else
-            HIP_TRY(c, sph::launch_rigid_force(nf, c->x, c->rho, c->K, c->Kv, c->blist, c->bcnt, c->xb, c->vb, c->kc,
-                                               c->nr, c->com_dev, c->red_part, c->hs_dev, s));
+        HIP_TRY(c, sph::launch_rigid_force(nf, c->x, c->rho, c->K, c->Kv, c->blist, c->bcnt, c->xb, c->vb, c->kc,
+                                           c->nr, c->com_dev, c->red_part, c->hs_dev, s));
         std::vector<double> fo(6 * c->nr);
         HIP_TRY(c, hipStreamSynchronize(s));
         std::memcpy(fo.data(), c->hs->rigid, sizeof(double) * 6 * c->nr);
@@ -813,16 +755,9 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     c->kc.rho0 = (float)p->rho0;
 
     const int64_t nf = c->nf, nb = c->nb;
-    const int64_t tiles = (ncell + 4095) / 4096;
-    const int64_t nred = std::max<int64_t>(sph::reduction_blocks(std::max(nf, nb)), 8);
-    c->nrows = (int64_t)c->g.n[1] * c->g.n[2];
-    // one thread per particle by default; tiles on request (sph_set_tiling),
-    // their buffers allocated then
-    c->tile_capable = c->capf <= sph::kTileCapF && c->capb <= sph::kTileCapB;
-    c->tiled = false;
-    c->max_t = c->tile_capable ? sph::max_tiles(nf, c->nrows) : 0;
-    const int64_t nstat_blocks = std::max<int64_t>(nred, c->tile_capable ? sph::tile_partials(c->max_t) : 0);
-    const int64_t red_blocks = std::max<int64_t>(nred, c->tile_capable ? sph::tile_partials(c->max_t) : 0);
+    const int64_t scan_chunks = (ncell + 4095) / 4096;
+    // reductions run over up to four lanes per fluid particle
+    const int64_t nred = std::max<int64_t>(sph::reduction_blocks(std::max(4 * nf, nb)), 8);
     int rc = SPH_OK;
 #define ALLOC(ptr, n)                       \
     if ((rc = dev_alloc(c, &(ptr), (n)))) { \
@@ -835,17 +770,17 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     ALLOC(c->rho, nf); ALLOC(c->alpha, nf); ALLOC(c->K, nf); ALLOC(c->K2, nf); ALLOC(c->Kv, nf); ALLOC(c->Kv2, nf);
     ALLOC(c->kappa, nf); ALLOC(c->kappa_last, nf); ALLOC(c->id, nf); ALLOC(c->id2, nf);
     ALLOC(c->key, nf); ALLOC(c->slot, nf); ALLOC(c->src, nf);
-    ALLOC(c->count, ncell); ALLOC(c->start_f, ncell + 1); ALLOC(c->start_b, ncell + 1); ALLOC(c->scan_part, 2 * tiles + 8);
+    ALLOC(c->count, ncell); ALLOC(c->start_f, ncell + 1); ALLOC(c->start_b, ncell + 1); ALLOC(c->scan_part, 2 * scan_chunks + 8);
     // 32-bit lists in chunks of four entries (capacity rounded up to a chunk)
     ALLOC(c->nlist, (int64_t)(c->capf + 3) / 4 * 4 * nf); ALLOC(c->ncnt, nf);
     ALLOC(c->blist, (int64_t)(c->capb + 3) / 4 * 4 * nf); ALLOC(c->bcnt, nf);
     ALLOC(c->xb, nb); ALLOC(c->xb2, nb); ALLOC(c->vb, nb); ALLOC(c->vb2, nb); ALLOC(c->bid, nb); ALLOC(c->bid2, nb);
     ALLOC(c->bkey, nb); ALLOC(c->bslot, nb); ALLOC(c->bsrc, nb); ALLOC(c->blocal, 3 * nb);
     ALLOC(c->poses, std::max(1, c->nr)); ALLOC(c->com_dev, 3 * std::max(1, c->nr));
-    ALLOC(c->red_part, red_blocks * 6 * std::max(1, c->nr) + 16); ALLOC(c->scal, 16);
+    ALLOC(c->red_part, nred * 6 * std::max(1, c->nr) + 16); ALLOC(c->scal, 16);
     ALLOC(c->ctl, 1);
     ALLOC(c->flags, 4);
-    ALLOC(c->nstat_part, sph::kNStats * nstat_blocks);
+    ALLOC(c->nstat_part, sph::kNStats * nred);
     ALLOC(c->feat, 5 * nf); ALLOC(c->ybuf, nf); ALLOC(c->dbuf, nf);
     if (p->visc_model == SPH_VISC_IMPLICIT) {
         ALLOC(c->Pinv, 9 * nf); ALLOC(c->cg_b, nf); ALLOC(c->cg_r, nf); ALLOC(c->cg_z, nf); ALLOC(c->cg_p, nf);
@@ -960,9 +895,6 @@ int sph_get_info(const sph_ctx *c, sph_info *info) {
     info->max_neighbors = c->capf;
     info->max_boundary_neighbors = c->capb;
     info->device_bytes = c->dev_bytes;
-    info->tiled = c->tiled ? 1 : 0;
-    info->n_tiles = c->ntiles;
-    info->n_tiles_overfull = c->n_over;
     return SPH_OK;
 }
 
@@ -1159,61 +1091,30 @@ int sph_read_neighbors(sph_ctx *c, const sph_nbr_view *d) {
     if (d->start_b)
         HIP_TRY(c, hipMemcpyAsync(d->start_b, c->start_b, sizeof(uint32_t) * (c->ncell + 1), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    std::vector<sph::TileDesc> tiles((size_t)std::max<int64_t>(c->ntiles, 1));
-    if (c->tiled && c->ntiles > 0) {
-        HIP_TRY(c, hipMemcpyAsync(tiles.data(), c->tiles, sizeof(sph::TileDesc) * c->ntiles, hipMemcpyDeviceToHost,
-                                  c->stream));
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-    }
-    // Lists as sorted indices; a tiled list entry is a slot, mapped back
-    // through its tile's ranges (slot - off[r] + first[r] for the range r
-    // holding it), and over-full tiles hold sorted indices already.
-    auto csr = [&](const uint32_t *dev, const uint16_t *dev16, bool fluid, int32_t cap,
-                   const std::vector<uint32_t> &n, uint32_t *counts, uint32_t *out, int64_t outcap) -> int {
+    // lists as sorted indices, CSR by particle
+    auto csr = [&](const uint32_t *dev, int32_t cap, const std::vector<uint32_t> &n, uint32_t *counts, uint32_t *out,
+                   int64_t outcap) -> int {
         int64_t tot = 0;
         for (int64_t s = 0; s < nf; ++s) tot += std::min<uint32_t>(n[s], (uint32_t)cap);
         if (counts)
             for (int64_t s = 0; s < nf; ++s) counts[s] = n[s];
         if (!out) return SPH_OK;
         if (tot > outcap) return fail(c, SPH_ERR_CAPACITY, "CSR capacity too small");
-        // 32-bit lists: chunks of four entries, chunk-major (entry k of s at 4 ((k/4) nf + s) + k%4)
+        // chunks of four entries, chunk-major: entry k of s at 4 ((k/4) nf + s) + k%4
         const int64_t cap4 = ((int64_t)cap + 3) / 4 * 4;
         std::vector<uint32_t> L((size_t)std::max<int64_t>(cap4 * nf, 1));
         HIP_TRY(c, hipMemcpyAsync(L.data(), dev, sizeof(uint32_t) * (size_t)(cap4 * nf), hipMemcpyDeviceToHost,
                                   c->stream));
-        std::vector<uint16_t> L16;
-        std::vector<int32_t> tile_of;   // ok tile holding each particle, -1 otherwise
-        if (c->tiled) {
-            L16.resize((size_t)std::max<int64_t>((int64_t)cap * nf, 1));
-            HIP_TRY(c, hipMemcpyAsync(L16.data(), dev16, sizeof(uint16_t) * (size_t)cap * nf, hipMemcpyDeviceToHost,
-                                      c->stream));
-            tile_of.assign((size_t)std::max<int64_t>(nf, 1), -1);
-            for (int64_t t = 0; t < c->ntiles; ++t)
-                if (tiles[t].ok)
-                    for (int64_t q = tiles[t].p0; q < tiles[t].p1; ++q) tile_of[q] = (int32_t)t;
-        }
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         int64_t o = 0;
         for (int64_t q = 0; q < nf; ++q) {
             const uint32_t m = std::min<uint32_t>(n[q], (uint32_t)cap);
-            const int32_t t = c->tiled ? tile_of[q] : -1;
-            for (uint32_t k = 0; k < m; ++k) {
-                if (t < 0) {
-                    out[o++] = L[(size_t)(4 * ((int64_t)(k >> 2) * nf + q) + (k & 3))];
-                } else {
-                    const sph::TileDesc &T = tiles[t];
-                    const int32_t *first = fluid ? T.fb : T.bb, *off = fluid ? T.foff : T.boff;
-                    const int32_t slot = L16[(size_t)k * nf + q];
-                    int r = 0;
-                    while (r < 8 && slot >= off[r + 1]) ++r;
-                    out[o++] = (uint32_t)(first[r] + (slot - off[r]));
-                }
-            }
+            for (uint32_t k = 0; k < m; ++k) out[o++] = L[(size_t)(4 * ((int64_t)(k >> 2) * nf + q) + (k & 3))];
         }
         return SPH_OK;
     };
-    if ((rc = csr(c->nlist, c->l16, true, c->capf, cnt, d->counts_f, d->lists_f, d->cap_f))) return rc;
-    if ((rc = csr(c->blist, c->b16, false, c->capb, bcnt, d->counts_b, d->lists_b, d->cap_b))) return rc;
+    if ((rc = csr(c->nlist, c->capf, cnt, d->counts_f, d->lists_f, d->cap_f))) return rc;
+    if ((rc = csr(c->blist, c->capb, bcnt, d->counts_b, d->lists_b, d->cap_b))) return rc;
     return SPH_OK;
 }
 
@@ -1363,33 +1264,6 @@ int sph_set_forced_iters(sph_ctx *c, int32_t div, int32_t dens) {
     if (!c) return SPH_ERR_INVALID;
     c->forced_div = div;
     c->forced_dens = dens;
-    return SPH_OK;
-}
-
-int sph_set_tiling(sph_ctx *c, int32_t enable, int32_t slab_limit) {
-    if (!c) return SPH_ERR_INVALID;
-    c->err.clear();
-    if (enable && !c->tile_capable)
-        return fail(c, SPH_ERR_INVALID, "tiled lists need max_neighbors <= 64 and max_boundary_neighbors <= 48");
-    if (slab_limit < 0 || slab_limit > sph::kSlab)
-        return fail(c, SPH_ERR_INVALID, "slab_limit must lie in [0, 640]");
-    const int32_t lim = slab_limit == 0 ? sph::kSlab : slab_limit;
-    if (enable && !c->tiles) {
-        int rc;
-        if ((rc = dev_alloc(c, &c->tiles, c->max_t)) || (rc = dev_alloc(c, &c->tilecnt, c->nrows + 1)) ||
-            (rc = dev_alloc(c, &c->tileoff, c->nrows + 1)) || (rc = dev_alloc(c, &c->tilerow, c->max_t)) ||
-            (rc = dev_alloc(c, &c->l16, (int64_t)c->capf * c->nf)) ||
-            (rc = dev_alloc(c, &c->b16, (int64_t)c->capb * c->nf)))
-            return rc;
-    }
-    if ((enable != 0) != c->tiled || lim != c->slab_limit) {
-        c->tiled = enable != 0;
-        c->slab_limit = lim;
-        c->ntiles = 0;
-        c->n_over = 0;
-        c->over_entries = 0.0;
-        c->nbr_fresh = false;
-    }
     return SPH_OK;
 }
 

@@ -169,10 +169,9 @@ __global__ void k_finish_solve(const double* __restrict__ partials, int nblk, So
 }
 
 // neighbour statistics per workgroup (kNStats fields): min, max, then sums
-// Also mirrors the build flags and (tiled builds) the tile count to host.
+// Also mirrors the build flags to host.
 __global__ void k_finish_nstats(const unsigned long long* __restrict__ partials, int nblk,
-                                const uint32_t* __restrict__ flags, const uint32_t* __restrict__ ntiles,
-                                HostStatus* host) {
+                                const uint32_t* __restrict__ flags, HostStatus* host) {
     __shared__ unsigned long long s[kNStats][kBlock];
     unsigned long long a[kNStats];
     a[0] = ~0ull;
@@ -194,10 +193,7 @@ __global__ void k_finish_nstats(const unsigned long long* __restrict__ partials,
         __syncthreads();
     }
     if (threadIdx.x < kNStats) host->nstats[threadIdx.x] = s[threadIdx.x][0];
-    if (threadIdx.x == 0) {
-        host->flags = *flags;
-        host->ntiles = ntiles ? *ntiles : 0u;
-    }
+    if (threadIdx.x == 0) host->flags = *flags;
 }
 
 __global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk, HostStatus* host) {
@@ -213,26 +209,6 @@ __global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk
     if (threadIdx.x == 0) host->vmax_bits = s[0];
 }
 
-
-// As for_each_nbr over 16-bit LDS slots.
-template <class F>
-__device__ __forceinline__ void for_each_slot(const uint16_t* __restrict__ list, int64_t nf, int64_t i, uint32_t n,
-                                              F&& f) {
-    const uint16_t* p = list + i;
-    uint32_t k = 0;
-    for (; k + 4 <= n; k += 4) {
-        const uint32_t j0 = p[0], j1 = p[nf], j2 = p[2 * nf], j3 = p[3 * nf];
-        p += 4 * nf;
-        f(j0);
-        f(j1);
-        f(j2);
-        f(j3);
-    }
-    for (; k < n; ++k) {
-        f((uint32_t)*p);
-        p += nf;
-    }
-}
 
 // Append the candidates c in [b, e) (ascending) with c != skip and the FP32
 // predicate d^2 < h^2 to particle i's list: entries gather in buf and go out
@@ -263,6 +239,55 @@ __device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, 
         take(c + 3, p3);
     }
     for (; c < e; ++c) take(c, pos[c]);
+}
+
+// Neighbour passes run L (1, 2 or 4) lanes per particle: lane q of the group
+// takes list entries k = q, q+L, q+2L, ...  The lanes of a wave instruction
+// that belong to one particle read adjacent entries of one 16-byte chunk of
+// its list, and a gather instruction touches the neighbours of 64/L
+// particles, which share far fewer cache lines than those of 64 (the address
+// unit, not HBM, bounds the gather-heavy passes).  Per-lane partial sums are
+// combined by group_sum in a fixed order.
+template <int L>
+__device__ __forceinline__ float group_sum(float v) {
+    if (L >= 2) v += __shfl_xor(v, 1, 64);
+    if (L >= 4) v += __shfl_xor(v, 2, 64);
+    return v;
+}
+
+// lane position in its particle's group, and the particle
+template <int L>
+__device__ __forceinline__ int64_t group_particle(int& q) {
+    const int64_t g = particle_index();
+    q = (int)(g & (L - 1));
+    return g / L;
+}
+
+template <int L, class F>
+__device__ __forceinline__ void for_each_nbr_l(const uint32_t* __restrict__ list, int64_t nf, int64_t i, int q,
+                                               uint32_t n, F&& f) {
+    if (L == 1) {
+        for_each_nbr(list, nf, i, n, f);
+        return;
+    }
+    // entries 4c + q + L t (t < 4/L) of chunk c sit at list + 4 (c nf + i) + q + L t
+    const uint32_t* p = list + ((i << 2) + q);
+    const int64_t step = nf << 2;   // one chunk row
+    constexpr int T = 4 / L;        // entries per lane per chunk
+    uint32_t k = (uint32_t)q;
+    // four entries of this lane per round, loaded ahead of the work
+    for (; k + 3 * L < n; k += 4 * L) {
+        uint32_t j[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) j[u] = p[(u / T) * step + (u % T) * L];
+        p += (4 / T) * step;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) f(j[u]);
+    }
+    for (; k < n; k += L) {
+        const uint32_t c = k >> 2, r = k & 3u;
+        f(list[(((int64_t)c * nf + i) << 2) + r]);
+    }
 }
 
 // Store the partial last chunk of a list filled by scan_candidates.

@@ -27,24 +27,8 @@ struct Kern {
     float rho0;
 };
 
-// Cell-row tiles: up to kTile consecutive sorted fluid particles of one
-// (cy, cz) row of cells.  The 27-cell stencil of a tile is nine contiguous
-// ranges of sorted indices per particle set (rows dz, dy = -1..1 over cells
-// cxa-1 .. cxb+1), three per dz slab.  When every slab holds at most kSlab
-// particles of each set (ok), passes stage one slab at a time in LDS and the
-// neighbour lists hold 16-bit slots (range offset + position in the range);
-// otherwise the tile uses 32-bit sorted indices and global gathers.
-constexpr int kTile = 128;
-constexpr int kSlab = 640;
-constexpr int kTileCapF = 64;   // list capacities the tiled build supports
-constexpr int kTileCapB = 48;
-// neighbour statistics: [min, max, sum, sum_fluid, entries in over-full tiles, over-full tiles]
-constexpr int kNStats = 6;
-struct TileDesc {
-    int32_t p0, p1, ok, pad;
-    int32_t fb[9], foff[10];   // fluid ranges: start index, LDS offset (foff[9] = staged count)
-    int32_t bb[9], boff[10];   // boundary ranges
-};
+// neighbour statistics: [min, max, sum, sum_fluid]
+constexpr int kNStats = 4;
 
 // Device-side state of one Jacobi solve (Algorithm 2): the host queues
 // iterations ahead and every pass of an iteration that is no longer due
@@ -64,9 +48,7 @@ struct SolveCtl {
 struct HostStatus {
     SolveCtl solve;                        // the control block after the last finish
     uint32_t flags;                        // build flags (bit 0 capacity, bit 1 cell > 4096)
-    uint32_t ntiles;                       // tiles of the last tiled build
     uint32_t vmax_bits;                    // max |v|^2 (FP32 bits) of the CFL pass
-    uint32_t pad;
     unsigned long long nstats[kNStats];    // neighbour statistics of the last build
     double rigid[6 * kMaxBodies];          // force and torque per body
 };
@@ -193,57 +175,6 @@ hipError_t launch_mlp_grad(const float* P, const float* feat, const float* targe
                            double* loss_part, float* grad, double* loss_sum, hipStream_t s);
 hipError_t launch_mlp_adam(float* P, const float* grad, float* m, float* v, float lr, float beta1, float beta2,
                            float eps, float c1, float c2, hipStream_t s);
-
-// cell-row tiles (sph_tiled.hip)
-// tilecnt/tileoff need nrows + 1 entries; tiles needs max_tiles(nf, nrows).
-int64_t max_tiles(int64_t nf, int64_t nrows);
-// slab_limit (<= kSlab): the most particles of one set a tile may stage per
-// z-slab; tiles above it are marked over-full.
-// tilerow and tiles need max_t entries.
-hipError_t launch_tiles_build(const float4* x, const uint32_t* start_f, const uint32_t* start_b, Grid g,
-                              int32_t slab_limit, uint32_t* tilecnt, uint32_t* tileoff, uint32_t* tilerow,
-                              int64_t max_t, uint32_t* scan_part, TileDesc* tiles, hipStream_t s);
-// The tile count is read on the device (ntiles_dev = tileoff + nrows); the
-// launch covers max_t tiles and workgroups past the count only store neutral
-// statistics.  partials needs tile_partials(max_t) * 4 entries.
-hipError_t launch_nbr_build_tiled(const TileDesc* tiles, const uint32_t* ntiles_dev, int64_t max_t, const float4* x,
-                                  int64_t nf, const float4* xb, const uint32_t* start_f, const uint32_t* start_b,
-                                  Grid g, uint16_t* l16, uint32_t* l32, uint32_t* ncnt, int32_t capf, uint16_t* b16,
-                                  uint32_t* b32, uint32_t* bcnt, int32_t capb, uint32_t* flags,
-                                  unsigned long long* partials, HostStatus* host, hipStream_t s);
-// workgroups of a per-tile launch over n tiles (a multiple of 8)
-uint32_t tile_partials(int64_t ntiles);
-// Neighbour lists of the tiled passes.
-struct Lists {
-    const TileDesc* tiles;
-    int64_t ntiles;
-    const uint16_t* l16;
-    const uint32_t* l32;
-    const uint32_t* ncnt;
-    const uint16_t* b16;
-    const uint32_t* b32;
-    const uint32_t* bcnt;
-};
-hipError_t launch_density_alpha_t(const Lists& L, int64_t nf, float4* x, const float4* v, const float4* xb, Kern kc,
-                                  float* rho, float* alpha, float4* v_in, float* Kv, float* kappa, float warm_factor,
-                                  hipStream_t s);
-hipError_t launch_pressure_update_t(const Lists& L, int64_t nf, const float4* x, float4* v, const float* kappa,
-                                    float* Kacc, float* kappa_last, const float4* xb, Kern kc, float dt,
-                                    const int32_t* go, hipStream_t s);
-hipError_t launch_predict_t(int mode, const Lists& L, int64_t nf, float4* x, const float4* v, const float* rho,
-                            const float* alpha, float* kappa, const float4* xb, const float4* vb, Kern kc, float dt,
-                            double* partials, SolveCtl* ctl, bool first, float* dout, int* nparts, hipStream_t s);
-hipError_t launch_nonpressure_t(int model, const Lists& L, int64_t nf, float4* x, const float4* v, float4* vout,
-                                const float* rho, Kern kc, float dt, float gx, float gy, float gz, float visc,
-                                float* K, float* kappa, float warm_factor, bool setup_warm, hipStream_t s);
-
-hipError_t launch_rigid_force_t(const Lists& L, int64_t nf, const float4* x, const float* rho, const float* K,
-                                const float* Kv, const float4* xb, const float4* vb, Kern kc, int32_t nbody,
-                                const double* com, double* partials, HostStatus* host, hipStream_t s);
-hipError_t launch_visc_precond_t(const Lists& L, int64_t nf, const float4* x, const float* rho, Kern kc, float dt,
-                                 float mu, float* Pinv, hipStream_t s);
-hipError_t launch_visc_matvec_t(const Lists& L, int64_t nf, const float4* x, const float* rho, const float4* p,
-                                float4* Mp, Kern kc, float dt, float mu, hipStream_t s);
 
 // workgroups of a per-particle launch over n (a multiple of 8)
 uint32_t reduction_blocks(int64_t n);

@@ -234,8 +234,6 @@ __global__ void __launch_bounds__(kBlock) k_nbr_build(
         o[1] = b;
         o[2] = c;
         o[3] = d;
-        o[4] = 0;
-        o[5] = 0;
     }
 }
 
@@ -293,20 +291,24 @@ __global__ void k_max_v2(const float4* __restrict__ v, int64_t n, uint32_t* out_
     }
 }
 
+// The neighbour sums below run L lanes per particle (group_particle,
+// for_each_nbr_l, group_sum); the launchers pick L per pass.
+
 // Density with the Akinci boundary term, Eq. (12), and the DFSPH factor
 // alpha = rho / (|sum_F m gradW + sum_B Psi gradW|^2 + sum_F |m gradW|^2).
 // Also saves the step's input velocity and sets up the divergence warm start.
+template <int L>
 __global__ void __launch_bounds__(kBlock) k_density_alpha(
     int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, const uint32_t* __restrict__ nlist,
     const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const uint32_t* __restrict__ blist,
     const uint32_t* __restrict__ bcnt, Kern kc, float* __restrict__ rho, float* __restrict__ alpha,
     float4* __restrict__ v_in, float* __restrict__ Kv, float* __restrict__ kappa, float warm_factor) {
-    const int64_t i = particle_index();
-    if (i >= nf) return;
+    int q;
+    const int64_t i = group_particle<L>(q);
+    if (i >= nf) return;   // whole groups leave together
     const float4 xi = x[i];
-    float r = kc.m * kc.k;
-    float gx = 0.f, gy = 0.f, gz = 0.f, sq = 0.f;
-    for_each_nbr(nlist, nf, i, ncnt[i], [&](uint32_t j) {
+    float r = 0.f, gx = 0.f, gy = 0.f, gz = 0.f, sq = 0.f;
+    for_each_nbr_l<L>(nlist, nf, i, q, ncnt[i], [&](uint32_t j) {
         const float4 xj = x[j];
         const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
@@ -316,52 +318,66 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
         gx += ax; gy += ay; gz += az;
         sq += ax * ax + ay * ay + az * az;
     });
-    for_each_nbr(blist, nf, i, bcnt[i], [&](uint32_t kk) {
+    float rb = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+    for_each_nbr_l<L>(blist, nf, i, q, bcnt[i], [&](uint32_t kk) {
         const float4 xk = xb[kk];
         const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
-        r += xk.w * kernel_W(r2, kc);
+        rb += xk.w * kernel_W(r2, kc);
         const float F = xk.w * grad_factor(r2, kc);
-        gx += F * dx; gy += F * dy; gz += F * dz;
+        bx += F * dx; by += F * dy; bz += F * dz;
     });
+    // self term, fluid sum, boundary sum
+    const float rr = (kc.m * kc.k + group_sum<L>(r)) + group_sum<L>(rb);
+    gx = group_sum<L>(gx) + group_sum<L>(bx);
+    gy = group_sum<L>(gy) + group_sum<L>(by);
+    gz = group_sum<L>(gz) + group_sum<L>(bz);
+    sq = group_sum<L>(sq);
+    if (q != 0) return;
     const float D = gx * gx + gy * gy + gz * gz + sq;
-    rho[i] = r;
-    alpha[i] = D > 1e-6f ? r / D : 0.0f;
+    rho[i] = rr;
+    alpha[i] = D > 1e-6f ? rr / D : 0.0f;
     v_in[i] = v[i];
     const float k0 = warm_factor * Kv[i];
     kappa[i] = k0;
     Kv[i] = 0.0f;
-    x[i].w = k0 / r;
+    x[i].w = k0 / rr;
 }
 
 // Pressure velocity update (Eq. 7 with p/rho^2 = kappa/rho, the boundary term
 // of Eq. 13 using the particle's own pressure): kappa/rho comes from x.w.
+template <int L>
 __global__ void __launch_bounds__(kBlock) k_pressure_update(
     int64_t nf, const float4* __restrict__ x, float4* __restrict__ v, const float* __restrict__ kappa,
     float* __restrict__ Kacc, float* __restrict__ kappa_last, const uint32_t* __restrict__ nlist,
     const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const uint32_t* __restrict__ blist,
     const uint32_t* __restrict__ bcnt, Kern kc, float dt, const int32_t* __restrict__ go) {
     if (go != nullptr && *go == 0) return;
-    const int64_t i = particle_index();
+    int q;
+    const int64_t i = group_particle<L>(q);
     if (i >= nf) return;
     const float4 xi = x[i];
     const float kri = xi.w;
     float ax = 0.f, ay = 0.f, az = 0.f;
-    for_each_nbr(nlist, nf, i, ncnt[i], [&](uint32_t j) {
+    for_each_nbr_l<L>(nlist, nf, i, q, ncnt[i], [&](uint32_t j) {
         const float4 xj = x[j];
         const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
         const float c = (kri + xj.w) * grad_factor(r2, kc);
         ax += c * dx; ay += c * dy; az += c * dz;
     });
-    ax *= kc.m; ay *= kc.m; az *= kc.m;
-    for_each_nbr(blist, nf, i, bcnt[i], [&](uint32_t kk) {
+    float bx = 0.f, by = 0.f, bz = 0.f;
+    for_each_nbr_l<L>(blist, nf, i, q, bcnt[i], [&](uint32_t kk) {
         const float4 xk = xb[kk];
         const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
         const float c = xk.w * kri * grad_factor(r2, kc);
-        ax += c * dx; ay += c * dy; az += c * dz;
+        bx += c * dx; by += c * dy; bz += c * dz;
     });
+    ax = group_sum<L>(ax) * kc.m + group_sum<L>(bx);
+    ay = group_sum<L>(ay) * kc.m + group_sum<L>(by);
+    az = group_sum<L>(az) * kc.m + group_sum<L>(bz);
+    if (q != 0) return;
     float4 vi = v[i];
     vi.x -= dt * ax; vi.y -= dt * ay; vi.z -= dt * az;
     v[i] = vi;
@@ -373,7 +389,7 @@ __global__ void __launch_bounds__(kBlock) k_pressure_update(
 // Divergence d_i = sum_F m (v_i - v_j).gradW + sum_B Psi (v_i - v_k).gradW
 // (Eq. 6 in the DFSPH form, Eq. 9 for the predicted density), the next
 // stiffness, and the FP64 sum of the clamped error.
-template <int MODE>
+template <int MODE, int L>
 __global__ void __launch_bounds__(kBlock) k_predict(
     int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, const float* __restrict__ rho,
     const float* __restrict__ alpha, float* __restrict__ kappa, const uint32_t* __restrict__ nlist,
@@ -381,42 +397,46 @@ __global__ void __launch_bounds__(kBlock) k_predict(
     const uint32_t* __restrict__ blist, const uint32_t* __restrict__ bcnt, Kern kc, float dt,
     double* __restrict__ partials, const int32_t* __restrict__ go, float* __restrict__ dout) {
     if (go != nullptr && *go == 0) return;
-    const int64_t i = particle_index();
+    int q;
+    const int64_t i = group_particle<L>(q);
     double e = 0.0;
-    if (i < nf) {
+    if (i < nf) {   // whole groups
         const float4 xi = x[i];
         const float4 vi = v[i];
         float d = 0.f;
-        for_each_nbr(nlist, nf, i, ncnt[i], [&](uint32_t j) {
+        for_each_nbr_l<L>(nlist, nf, i, q, ncnt[i], [&](uint32_t j) {
             const float4 xj = x[j];
             const float4 vj = v[j];
             const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             d += grad_factor(r2, kc) * ((vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz);
         });
-        d *= kc.m;
-        for_each_nbr(blist, nf, i, bcnt[i], [&](uint32_t kk) {
+        float db = 0.f;
+        for_each_nbr_l<L>(blist, nf, i, q, bcnt[i], [&](uint32_t kk) {
             const float4 xk = xb[kk];
             const float4 vk = vb[kk];
             const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
-            d += xk.w * grad_factor(r2, kc) * ((vi.x - vk.x) * dx + (vi.y - vk.y) * dy + (vi.z - vk.z) * dz);
+            db += xk.w * grad_factor(r2, kc) * ((vi.x - vk.x) * dx + (vi.y - vk.y) * dy + (vi.z - vk.z) * dz);
         });
-        const float ri = rho[i];
-        float kap;
-        if (MODE == 0) {
-            if (dout) dout[i] = d;
-            const float ep = fmaxf(d, 0.0f);
-            kap = ep * alpha[i] / dt;
-            e = (double)ep;
-        } else {
-            const float dev = (ri - kc.rho0) + dt * d;
-            const float ep = fmaxf(dev, 0.0f);
-            kap = ep * alpha[i] / (dt * dt);
-            e = (double)ep;
+        d = group_sum<L>(d) * kc.m + group_sum<L>(db);
+        if (q == 0) {
+            const float ri = rho[i];
+            float kap;
+            if (MODE == 0) {
+                if (dout) dout[i] = d;
+                const float ep = fmaxf(d, 0.0f);
+                kap = ep * alpha[i] / dt;
+                e = (double)ep;
+            } else {
+                const float dev = (ri - kc.rho0) + dt * d;
+                const float ep = fmaxf(dev, 0.0f);
+                kap = ep * alpha[i] / (dt * dt);
+                e = (double)ep;
+            }
+            kappa[i] = kap;
+            x[i].w = kap / ri;
         }
-        kappa[i] = kap;
-        x[i].w = kap / ri;
     }
     const double bs = block_sum(e);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
@@ -425,20 +445,21 @@ __global__ void __launch_bounds__(kBlock) k_predict(
 // Non-pressure accelerations (Algorithm 1, first lines): v* = v + dt g plus
 // XSPH (model 1) or the explicit Laplacian of Eq. (15) (model 2); and the
 // set-up of the density warm start (kappa = warm_factor K, K = 0, x.w = kappa/rho).
-template <int MODEL>
+template <int MODEL, int L>
 __global__ void __launch_bounds__(kBlock) k_nonpressure(
     int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, float4* __restrict__ vout,
     const float* __restrict__ rho, const uint32_t* __restrict__ nlist, const uint32_t* __restrict__ ncnt,
     Kern kc, float dt, float gx, float gy, float gz, float visc, float* __restrict__ K, float* __restrict__ kappa,
     float warm_factor, bool setup_warm) {
-    const int64_t i = particle_index();
+    int q;
+    const int64_t i = group_particle<L>(q);
     if (i >= nf) return;
     const float4 xi = x[i];
     const float4 vi = v[i];
     float ax = 0.f, ay = 0.f, az = 0.f;
     if (MODEL == 1 || MODEL == 2) {
         const float eps2 = 0.01f * kc.h * kc.h;
-        for_each_nbr(nlist, nf, i, ncnt[i], [&](uint32_t j) {
+        for_each_nbr_l<L>(nlist, nf, i, q, ncnt[i], [&](uint32_t j) {
             const float4 xj = x[j];
             const float4 vj = v[j];
             const float mj = kc.m / rho[j];
@@ -453,7 +474,9 @@ __global__ void __launch_bounds__(kBlock) k_nonpressure(
                 ax += c * dx; ay += c * dy; az += c * dz;
             }
         });
+        ax = group_sum<L>(ax); ay = group_sum<L>(ay); az = group_sum<L>(az);
     }
+    if (q != 0) return;
     float s = 0.f;
     if (MODEL == 1) s = visc;
     if (MODEL == 2) s = dt * visc * 2.0f * (3 + 2);
@@ -758,6 +781,9 @@ __global__ void k_warm_setup(int64_t nf, float4* __restrict__ x, const float* __
 }  // namespace
 
 // ================================================================== launchers
+// lanes per particle of the neighbour sums (measured at 1.23M particles)
+constexpr int kLanesDensity = 2, kLanesPressure = 2, kLanesPredict = 2, kLanesXsph = 4;
+
 #define LAUNCH(kern, n, ...)                                                        \
     do {                                                                            \
         hipLaunchKernelGGL(kern, dim3(grid_blocks(n)), dim3(kBlock), 0, s, __VA_ARGS__); \
@@ -829,7 +855,7 @@ hipError_t launch_nbr_build(const float4* x, int64_t nf, const float4* xb, const
     hipLaunchKernelGGL(k_nbr_build, dim3(nblk), dim3(kBlock), 0, s, x, nf, xb, start_f, start_b, g, nlist, ncnt,
                        capf, blist, bcnt, capb, flags, partials);
     hipLaunchKernelGGL(k_finish_nstats, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, (const uint32_t*)flags,
-                       (const uint32_t*)nullptr, host);
+                       host);
     return hipGetLastError();
 }
 
@@ -850,7 +876,7 @@ hipError_t launch_density_alpha(int64_t nf, float4* x, const float4* v, const ui
                                 float* alpha, float4* v_in, float* Kv, float* kappa, float warm_factor,
                                 hipStream_t s) {
     if (nf <= 0) return hipSuccess;
-    LAUNCH(k_density_alpha, nf, nf, x, v, nlist, ncnt, xb, blist, bcnt, kc, rho, alpha, v_in, Kv, kappa,
+    LAUNCH(k_density_alpha<kLanesDensity>, kLanesDensity * nf, nf, x, v, nlist, ncnt, xb, blist, bcnt, kc, rho, alpha, v_in, Kv, kappa,
            warm_factor);
 }
 
@@ -859,7 +885,8 @@ hipError_t launch_pressure_update(int64_t nf, const float4* x, float4* v, const 
                                   const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt, const int32_t* go,
                                   hipStream_t s) {
     if (nf <= 0) return hipSuccess;
-    LAUNCH(k_pressure_update, nf, nf, x, v, kappa, Kacc, kappa_last, nlist, ncnt, xb, blist, bcnt, kc, dt, go);
+    LAUNCH(k_pressure_update<kLanesPressure>, kLanesPressure * nf, nf, x, v, kappa, Kacc, kappa_last, nlist, ncnt, xb, blist, bcnt, kc, dt,
+           go);
 }
 
 hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, const float* rho, const float* alpha,
@@ -867,15 +894,15 @@ hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, cons
                           const float4* vb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float dt,
                           double* partials, SolveCtl* ctl, bool first, float* dout, int* nparts,
                           hipStream_t s) {
-    const uint32_t nblk = grid_blocks(nf);
+    const uint32_t nblk = grid_blocks(kLanesPredict * nf);
     *nparts = nf > 0 ? (int)nblk : 0;
     if (nf <= 0) return hipSuccess;
     const int32_t* go = first ? nullptr : &ctl->go;
     if (mode == 0)
-        hipLaunchKernelGGL(k_predict<0>, dim3(nblk), dim3(kBlock), 0, s, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb,
+        hipLaunchKernelGGL((k_predict<0, kLanesPredict>), dim3(nblk), dim3(kBlock), 0, s, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb,
                            vb, blist, bcnt, kc, dt, partials, go, dout);
     else
-        hipLaunchKernelGGL(k_predict<1>, dim3(nblk), dim3(kBlock), 0, s, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb,
+        hipLaunchKernelGGL((k_predict<1, kLanesPredict>), dim3(nblk), dim3(kBlock), 0, s, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb,
                            vb, blist, bcnt, kc, dt, partials, go, nullptr);
     return hipGetLastError();
 }
@@ -892,13 +919,19 @@ hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v,
                               hipStream_t s) {
     if (nf <= 0) return hipSuccess;
     if (model == 1)
-        LAUNCH(k_nonpressure<1>, nf, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa,
-               warm_factor, setup_warm);
+        {
+        hipLaunchKernelGGL((k_nonpressure<1, kLanesXsph>), dim3(grid_blocks(kLanesXsph * nf)), dim3(kBlock), 0, s, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa, warm_factor, setup_warm);
+        return hipGetLastError();
+    }
     if (model == 2)
-        LAUNCH(k_nonpressure<2>, nf, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa,
-               warm_factor, setup_warm);
-    LAUNCH(k_nonpressure<0>, nf, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa,
-           warm_factor, setup_warm);
+        {
+        hipLaunchKernelGGL((k_nonpressure<2, kLanesXsph>), dim3(grid_blocks(kLanesXsph * nf)), dim3(kBlock), 0, s, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa, warm_factor, setup_warm);
+        return hipGetLastError();
+    }
+    {
+        hipLaunchKernelGGL((k_nonpressure<0, 1>), dim3(grid_blocks(nf)), dim3(kBlock), 0, s, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa, warm_factor, setup_warm);
+        return hipGetLastError();
+    }
 }
 
 hipError_t launch_features(int64_t nf, const float* rho, const float* alpha, const float* K, const uint32_t* ncnt,

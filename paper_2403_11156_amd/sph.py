@@ -86,7 +86,6 @@ class sph_info(C.Structure):
         ("origin", C.c_float * 3), ("h2", C.c_float),
         ("max_neighbors", C.c_int32), ("max_boundary_neighbors", C.c_int32),
         ("device_bytes", C.c_int64),
-        ("tiled", C.c_int32), ("n_tiles", C.c_int64), ("n_tiles_overfull", C.c_int64),
     ]
 
 
@@ -116,7 +115,6 @@ def _load():
         "sph_get_info": (C.c_int, [P, C.POINTER(sph_info)]),
         "sph_read_neighbors": (C.c_int, [P, C.POINTER(sph_nbr_view)]),
         "sph_set_forced_iters": (C.c_int, [P, C.c_int32, C.c_int32]),
-        "sph_set_tiling": (C.c_int, [P, C.c_int32, C.c_int32]),
         "sph_profile_enable": (C.c_int, [P, C.c_int32]),
         "sph_profile_read": (C.c_int, [P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double)]),
@@ -152,7 +150,6 @@ sph_write_state = lib.sph_write_state
 sph_get_info = lib.sph_get_info
 sph_read_neighbors = lib.sph_read_neighbors
 sph_set_forced_iters = lib.sph_set_forced_iters
-sph_set_tiling = lib.sph_set_tiling
 sph_profile_enable = lib.sph_profile_enable
 sph_profile_read = lib.sph_profile_read
 sph_last_error = lib.sph_last_error
@@ -291,9 +288,6 @@ class Simulation:
 
     def set_forced_iters(self, div: int, dens: int):
         self._check(sph_set_forced_iters(self.ctx, div, dens))
-
-    def set_tiling(self, enable: bool, slab_limit: int = 0):
-        self._check(sph_set_tiling(self.ctx, 1 if enable else 0, int(slab_limit)))
 
     def read(self, fields=("x", "v", "rho", "alpha", "K", "Kv", "kappa", "accel", "nbr", "psi",
                            "boundary", "rigid")) -> Dict:
