@@ -70,6 +70,8 @@ struct sph_ctx {
     // reductions and flags
     double *red_part = nullptr, *scal = nullptr;
     sph::SolveCtl *ctl = nullptr;                     // device control block of the running solve
+    sph::CgCtl *cgc = nullptr;                        // and of the implicit-viscosity CG
+    int32_t last_cg = 0;                              // previous step's CG iterations
     int32_t last_iters[2] = {0, 0};                   // previous step's iterations (divergence, density)
     uint32_t *flags = nullptr;
     unsigned long long *nstat_part = nullptr;
@@ -78,8 +80,6 @@ struct sph_ctx {
     // implicit viscosity
     float *Pinv = nullptr;
     float4 *cg_b = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
-    // pinned host staging
-    double *h_scal = nullptr;
 
     std::vector<sph_rigid_desc> rigid;
     std::vector<double> force, torque;
@@ -150,9 +150,7 @@ int dev_alloc(sph_ctx *c, T **p, int64_t count) {
 void free_all(sph_ctx *c) {
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
-    if (c->h_scal) (void)hipHostFree(c->h_scal);
     if (c->hs) (void)hipHostFree(c->hs);
-    c->h_scal = nullptr;
     c->hs = nullptr;
     c->hs_dev = nullptr;
     for (auto &e : c->prof_pending) {
@@ -454,12 +452,14 @@ int jacobi_solve(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, int3
     return SPH_OK;
 }
 
-hipError_t visc_matvec(sph_ctx *c, const float4 *p, float4 *Mp, float dt, float mu) {
-    return sph::launch_visc_matvec(c->nf, c->x, c->rho, p, Mp, c->nlist, c->ncnt, c->kc, dt, mu, c->stream);
+hipError_t visc_matvec(sph_ctx *c, const float4 *p, float4 *Mp, float dt, float mu, const int32_t *go) {
+    return sph::launch_visc_matvec(c->nf, c->x, c->rho, p, Mp, c->nlist, c->ncnt, c->kc, dt, mu, go, c->stream);
 }
 
 // Implicit viscosity (Eqs. 16-19): CG with block-Jacobi preconditioner on
 // (I - dt A) v* = v~, x0 = v~, stop at |r| <= tol |b|.  Dot products FP64.
+// The stop rule runs on the device (CgCtl) as in jacobi_solve: iterations are
+// queued in batches and the host reads the control block once per batch.
 int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
     hipStream_t s = c->stream;
     const int64_t nf = c->nf;
@@ -473,37 +473,46 @@ int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
     }
     {
         ProfScope ps(c, "visc", 44.0 * nf + fluid_list_bytes(c));
-        HIP_TRY(c, visc_matvec(c, c->v2, c->cg_Ap, dt, mu));
+        HIP_TRY(c, visc_matvec(c, c->v2, c->cg_Ap, dt, mu, nullptr));
     }
     HIP_TRY(c, sph::launch_axpy_residual(nf, c->cg_b, c->cg_Ap, c->cg_r, s));
     HIP_TRY(c, sph::launch_apply_precond(nf, c->Pinv, c->cg_r, c->cg_z, s));
     HIP_TRY(c, hipMemcpyAsync(c->cg_p, c->cg_z, sizeof(float4) * nf, hipMemcpyDeviceToDevice, s));
-    double *rz = c->scal + 1, *pAp = c->scal + 2, *out2 = c->scal + 3, *bb = c->scal + 5;
-    // out2[0] = rz_new, out2[1] = rr
+    double *rz = c->scal + 1, *bb = c->scal + 2, *rr = c->scal + 3;
     HIP_TRY(c, sph::launch_dot(nf, c->cg_r, c->cg_z, c->red_part, rz, s));
     HIP_TRY(c, sph::launch_dot(nf, c->cg_b, c->cg_b, c->red_part, bb, s));
-    HIP_TRY(c, sph::launch_dot(nf, c->cg_r, c->cg_r, c->red_part, out2 + 1, s));
-    HIP_TRY(c, hipMemcpyAsync(c->h_scal, c->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
-    const double bnorm = std::sqrt(c->h_scal[5]);
-    double rnorm = std::sqrt(c->h_scal[4]);
-    int32_t it = 0;
-    while (rnorm > c->P.cg_tol * bnorm && it < c->P.cg_max_iters) {
-        {
-            ProfScope ps(c, "visc", 44.0 * nf + fluid_list_bytes(c));
-            HIP_TRY(c, visc_matvec(c, c->cg_p, c->cg_Ap, dt, mu));
+    HIP_TRY(c, sph::launch_dot(nf, c->cg_r, c->cg_r, c->red_part, rr, s));
+    HIP_TRY(c, sph::launch_cg_init(c->cgc, rz, bb, rr, c->P.cg_tol, c->P.cg_max_iters, c->hs_dev, s));
+    const int32_t cap = std::max(c->P.cg_max_iters, 0);
+    const size_t mark = c->prof_pending.size();
+    int32_t queued = 0, batch = std::min(std::max(c->last_cg, 1), cap);
+    for (;;) {
+        for (int32_t k = 0; k < batch; ++k) {
+            {
+                ProfScope ps(c, "visc", 44.0 * nf + fluid_list_bytes(c));
+                HIP_TRY(c, visc_matvec(c, c->cg_p, c->cg_Ap, dt, mu, &c->cgc->go));
+            }
+            HIP_TRY(c, sph::launch_cg_iteration(nf, c->v2, c->cg_r, c->cg_z, c->cg_p, c->cg_Ap, c->Pinv, c->cgc,
+                                                c->red_part, c->hs_dev, s));
         }
-        HIP_TRY(c, sph::launch_dot(nf, c->cg_p, c->cg_Ap, c->red_part, pAp, s));
-        HIP_TRY(c, sph::launch_cg_update(nf, c->v2, c->cg_r, c->cg_z, c->cg_p, c->cg_Ap, c->Pinv, rz, pAp,
-                                         c->red_part, out2, s));
-        HIP_TRY(c, sph::launch_cg_direction(nf, c->cg_p, c->cg_z, out2, rz, s));
-        HIP_TRY(c, hipMemcpyAsync(rz, out2, sizeof(double), hipMemcpyDeviceToDevice, s));
-        HIP_TRY(c, hipMemcpyAsync(c->h_scal, out2 + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        queued += batch;
         HIP_TRY(c, hipStreamSynchronize(s));
-        rnorm = std::sqrt(c->h_scal[0]);
-        ++it;
+        if (!c->hs->cg.go || queued >= cap) break;
+        batch = std::min<int32_t>(4, cap - queued);
     }
-    *iters = it;
+    const sph::CgCtl h = c->hs->cg;
+    // drop the timing records of queued mat-vecs that did nothing
+    if (c->prof && c->prof_pending.size() > mark) {
+        const size_t keep = mark + (size_t)h.iters;
+        for (size_t q = keep; q < c->prof_pending.size(); ++q) {
+            c->event_pool.push_back(c->prof_pending[q].a);
+            c->event_pool.push_back(c->prof_pending[q].b);
+        }
+        if (keep < c->prof_pending.size()) c->prof_pending.resize(keep);
+    }
+    c->last_cg = h.iters;
+    const double bnorm = h.bnorm, rnorm = std::sqrt(h.rr);
+    *iters = h.iters;
     *resid = bnorm > 0 ? rnorm / bnorm : rnorm;
     std::swap(c->v, c->v2);
     return SPH_OK;
@@ -778,7 +787,7 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     ALLOC(c->bkey, nb); ALLOC(c->bslot, nb); ALLOC(c->bsrc, nb); ALLOC(c->blocal, 3 * nb);
     ALLOC(c->poses, std::max(1, c->nr)); ALLOC(c->com_dev, 3 * std::max(1, c->nr));
     ALLOC(c->red_part, nred * 6 * std::max(1, c->nr) + 16); ALLOC(c->scal, 16);
-    ALLOC(c->ctl, 1);
+    ALLOC(c->ctl, 1); ALLOC(c->cgc, 1);
     ALLOC(c->flags, 4);
     ALLOC(c->nstat_part, sph::kNStats * nred);
     ALLOC(c->feat, 5 * nf); ALLOC(c->ybuf, nf); ALLOC(c->dbuf, nf);
@@ -787,8 +796,7 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
         ALLOC(c->cg_Ap, nf);
     }
 #undef ALLOC
-    if (hipHostMalloc((void **)&c->h_scal, 16 * sizeof(double)) != hipSuccess ||
-        hipHostMalloc((void **)&c->hs, sizeof(sph::HostStatus), hipHostMallocMapped | hipHostMallocCoherent) !=
+    if (hipHostMalloc((void **)&c->hs, sizeof(sph::HostStatus), hipHostMallocMapped | hipHostMallocCoherent) !=
             hipSuccess ||
         hipHostGetDevicePointer((void **)&c->hs_dev, c->hs, 0) != hipSuccess) {
         free_all(c);

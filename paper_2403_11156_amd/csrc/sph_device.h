@@ -146,17 +146,36 @@ __global__ void k_finish_rigid(const double* __restrict__ partials, int nblk, in
     }
 }
 
-// Finish of a predict pass: err = scale * (sum of the partials in workgroup
+// FP64 sum over a workgroup of NT threads in a fixed order; valid in thread 0.
+template <int NT>
+__device__ double block_sum_n(double v) {
+    __shared__ double ws[NT / 64];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        r = ws[0];
+        for (int w = 1; w < NT / 64; ++w) r += ws[w];
+    }
+    __syncthreads();
+    return r;
+}
+
+constexpr int kFinishThreads = 1024;   // the solve finish sums ~10^4 partials per pass
+
+// Finish of a predict pass: err = scale * (sum of the partials in a fixed
 // order); the solve's first finish starts the control block from init, a
 // later one counts the iteration; then decide whether another one is due:
 // exactly `forced` iterations, else while err > eta and fewer than
 // max_iters.  Nothing happens once go is 0.  The block is mirrored to host.
-__global__ void k_finish_solve(const double* __restrict__ partials, int nblk, SolveCtl* ctl, bool first,
-                               SolveCtl init, HostStatus* host) {
+__global__ void __launch_bounds__(kFinishThreads) k_finish_solve(const double* __restrict__ partials, int nblk,
+                                                                 SolveCtl* ctl, bool first, SolveCtl init,
+                                                                 HostStatus* host) {
     if (!first && ctl->go == 0) return;
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partials[b];
-    acc = block_sum(acc);
+    for (int b = threadIdx.x; b < nblk; b += kFinishThreads) acc += partials[b];
+    acc = block_sum_n<kFinishThreads>(acc);
     if (threadIdx.x == 0) {
         SolveCtl c = first ? init : *ctl;
         if (first) c.iters = 0;

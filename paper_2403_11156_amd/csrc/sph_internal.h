@@ -43,10 +43,27 @@ struct SolveCtl {
     int32_t max_iters;
 };
 
+// Device-side state of the implicit-viscosity CG (Eq. 19): as SolveCtl, the
+// host queues iterations and every kernel of an iteration past the stop does
+// nothing.  alpha and beta are the FP64 step ratios the next kernels use.
+struct CgCtl {
+    double rz;           // r.z of the current residual
+    double alpha;        // rz / p.Ap of the running iteration
+    double beta;         // rz_new / rz_old for the direction update
+    double rr;           // r.r after the last update
+    double bnorm;        // |b|
+    double thresh;       // tol |b|: stop when |r| <= thresh
+    int32_t iters;
+    int32_t go;
+    int32_t max_iters;
+    int32_t pad;
+};
+
 // What the host reads after a stream synchronisation: the finishing kernels
 // store it straight into pinned host memory, so no copy is queued for it.
 struct HostStatus {
     SolveCtl solve;                        // the control block after the last finish
+    CgCtl cg;                              // the CG control block after the last finish
     uint32_t flags;                        // build flags (bit 0 capacity, bit 1 cell > 4096)
     uint32_t vmax_bits;                    // max |v|^2 (FP32 bits) of the CFL pass
     unsigned long long nstats[kNStats];    // neighbour statistics of the last build
@@ -136,20 +153,18 @@ hipError_t launch_rigid_boundary(int64_t nb, float4* xb, float4* vb, const int32
 // implicit viscosity (Eqs. 16-19): M p = p - dt A p and its block-Jacobi preconditioner
 hipError_t launch_visc_precond(int64_t nf, const float4* x, const float* rho, const uint32_t* nlist,
                                const uint32_t* ncnt, Kern kc, float dt, float mu, float* Pinv, hipStream_t s);
+// go (nullable): skip when *go == 0
 hipError_t launch_visc_matvec(int64_t nf, const float4* x, const float* rho, const float4* p, float4* Mp,
                               const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float mu,
-                              hipStream_t s);
-// FP64 dot products of 3-vectors stored as float4 (w ignored): out[0] = a.b
-hipError_t launch_dot(int64_t nf, const float4* a, const float4* b, double* partials, double* out,
-                      hipStream_t s);
-// x += a p; r -= a Ap with a = num/den from device scalars; z = Pinv r;
-// out_rz = r.z (FP64), out_rr = r.r (FP64)
-hipError_t launch_cg_update(int64_t nf, float4* xv, float4* r, float4* z, const float4* p, const float4* Ap,
-                            const float* Pinv, const double* num, const double* den, double* partials,
-                            double* out2, hipStream_t s);
-// p = z + (rz_new / rz_old) p
-hipError_t launch_cg_direction(int64_t nf, float4* p, const float4* z, const double* rz_new, const double* rz_old,
-                               hipStream_t s);
+                              const int32_t* go, hipStream_t s);
+hipError_t launch_dot(int64_t nf, const float4* a, const float4* b, double* partials, double* out, hipStream_t s);
+// CG set-up from the dots r.z, b.b, r.r of the initial residual
+hipError_t launch_cg_init(CgCtl* ctl, const double* rz, const double* bb, const double* rr, double tol,
+                          int32_t max_iters, HostStatus* host, hipStream_t s);
+// one CG iteration after the mat-vec Ap: alpha = rz/p.Ap; x += alpha p,
+// r -= alpha Ap, z = P r, rz and rr, the stop rule; p = z + beta p
+hipError_t launch_cg_iteration(int64_t nf, float4* xv, float4* r, float4* z, float4* p, const float4* Ap,
+                               const float* Pinv, CgCtl* ctl, double* partials, HostStatus* host, hipStream_t s);
 hipError_t launch_apply_precond(int64_t nf, const float* Pinv, const float4* r, float4* z, hipStream_t s);
 hipError_t launch_axpy_residual(int64_t nf, const float4* b, const float4* Mx, float4* r, hipStream_t s);
 hipError_t launch_gravity(int64_t nf, const float4* v, float4* out, float dt, float gx, float gy, float gz,

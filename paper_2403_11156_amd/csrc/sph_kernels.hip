@@ -629,7 +629,8 @@ __global__ void k_rigid_boundary(int64_t nb, float4* __restrict__ xb, float4* __
 __global__ void __launch_bounds__(kBlock) k_visc_matvec(
     int64_t nf, const float4* __restrict__ x, const float* __restrict__ rho, const float4* __restrict__ p,
     float4* __restrict__ Mp, const uint32_t* __restrict__ nlist, const uint32_t* __restrict__ ncnt, Kern kc,
-    float dt, float mu) {
+    float dt, float mu, const int32_t* __restrict__ go) {
+    if (go != nullptr && *go == 0) return;
     const int64_t i = particle_index();
     if (i >= nf) return;
     const float4 xi = x[i];
@@ -722,12 +723,34 @@ __global__ void k_dot(int64_t nf, const float4* __restrict__ a, const float4* __
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
+// CG kernels of one iteration; each does nothing once ctl->go is 0.
+__global__ void k_cg_dot_pap(int64_t nf, const float4* __restrict__ p, const float4* __restrict__ Ap,
+                             const CgCtl* ctl, double* __restrict__ partials) {
+    if (ctl->go == 0) return;
+    const int64_t i = particle_index();
+    double s = 0.0;
+    if (i < nf) {
+        const float4 u = p[i], w = Ap[i];
+        s = (double)u.x * (double)w.x + (double)u.y * (double)w.y + (double)u.z * (double)w.z;
+    }
+    const double bs = block_sum(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
+__global__ void k_cg_finish_pap(const double* __restrict__ partials, int nblk, CgCtl* ctl) {
+    if (ctl->go == 0) return;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partials[b];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) ctl->alpha = ctl->rz / acc;
+}
+
 __global__ void k_cg_update(int64_t nf, float4* __restrict__ xv, float4* __restrict__ r, float4* __restrict__ z,
                             const float4* __restrict__ p, const float4* __restrict__ Ap,
-                            const float* __restrict__ Pinv, const double* num, const double* den,
-                            double* __restrict__ partials) {
+                            const float* __restrict__ Pinv, const CgCtl* ctl, double* __restrict__ partials) {
+    if (ctl->go == 0) return;
     const int64_t i = particle_index();
-    const float a = (float)(*num / *den);
+    const float a = (float)ctl->alpha;
     double rz = 0.0, rr = 0.0;
     if (i < nf) {
         const float4 pp = p[i], ap = Ap[i];
@@ -749,15 +772,54 @@ __global__ void k_cg_update(int64_t nf, float4* __restrict__ xv, float4* __restr
     }
 }
 
-__global__ void k_cg_direction(int64_t nf, float4* __restrict__ p, const float4* __restrict__ z,
-                               const double* rz_new, const double* rz_old) {
+// rz_new, rr; count the iteration; beta = rz_new/rz; continue while
+// |r| > tol |b| and fewer than max_iters
+__global__ void k_cg_finish_update(const double* __restrict__ partials, int nblk, CgCtl* ctl, HostStatus* host) {
+    if (ctl->go == 0) return;
+    double a0 = 0.0, a1 = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) {
+        a0 += partials[2 * (size_t)b];
+        a1 += partials[2 * (size_t)b + 1];
+    }
+    a0 = block_sum(a0);
+    a1 = block_sum(a1);
+    if (threadIdx.x == 0) {
+        CgCtl c = *ctl;
+        c.beta = a0 / c.rz;
+        c.rz = a0;
+        c.rr = a1;
+        c.iters += 1;
+        c.go = (sqrt(a1) > c.thresh && c.iters < c.max_iters) ? 1 : 0;
+        *ctl = c;
+        host->cg = c;
+    }
+}
+
+// p = z + beta p; runs in an iteration whose update left go at 1 (a
+// converged solve needs no new direction)
+__global__ void k_cg_direction(int64_t nf, float4* __restrict__ p, const float4* __restrict__ z, const CgCtl* ctl) {
+    if (ctl->go == 0) return;
     const int64_t i = particle_index();
     if (i >= nf) return;
-    const float beta = (float)(*rz_new / *rz_old);
+    const float beta = (float)ctl->beta;
     const float4 zz = z[i];
     float4 pp = p[i];
     pp.x = zz.x + beta * pp.x; pp.y = zz.y + beta * pp.y; pp.z = zz.z + beta * pp.z;
     p[i] = pp;
+}
+
+__global__ void k_cg_init(CgCtl* ctl, const double* rz, const double* bb, const double* rr, double tol,
+                          int32_t max_iters, HostStatus* host) {
+    CgCtl c{};
+    c.rz = *rz;
+    c.rr = *rr;
+    c.bnorm = sqrt(*bb);
+    c.thresh = tol * c.bnorm;
+    c.iters = 0;
+    c.max_iters = max_iters;
+    c.go = (sqrt(c.rr) > c.thresh && 0 < max_iters) ? 1 : 0;
+    *ctl = c;
+    host->cg = c;
 }
 
 __global__ void k_gravity(int64_t nf, const float4* __restrict__ v, float4* __restrict__ out, float dt, float gx,
@@ -909,7 +971,7 @@ hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, cons
 
 hipError_t launch_solve_finish(const double* partials, int nblk, SolveCtl* ctl, bool first, const SolveCtl& init,
                                HostStatus* host, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish_solve, dim3(1), dim3(kBlock), 0, s, partials, nblk, ctl, first, init, host);
+    hipLaunchKernelGGL(k_finish_solve, dim3(1), dim3(kFinishThreads), 0, s, partials, nblk, ctl, first, init, host);
     return hipGetLastError();
 }
 
@@ -988,9 +1050,9 @@ hipError_t launch_visc_precond(int64_t nf, const float4* x, const float* rho, co
 
 hipError_t launch_visc_matvec(int64_t nf, const float4* x, const float* rho, const float4* p, float4* Mp,
                               const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float mu,
-                              hipStream_t s) {
+                              const int32_t* go, hipStream_t s) {
     if (nf <= 0) return hipSuccess;
-    LAUNCH(k_visc_matvec, nf, nf, x, rho, p, Mp, nlist, ncnt, kc, dt, mu);
+    LAUNCH(k_visc_matvec, nf, nf, x, rho, p, Mp, nlist, ncnt, kc, dt, mu, go);
 }
 
 hipError_t launch_dot(int64_t nf, const float4* a, const float4* b, double* partials, double* out, hipStream_t s) {
@@ -1000,19 +1062,21 @@ hipError_t launch_dot(int64_t nf, const float4* a, const float4* b, double* part
     return hipGetLastError();
 }
 
-hipError_t launch_cg_update(int64_t nf, float4* xv, float4* r, float4* z, const float4* p, const float4* Ap,
-                            const float* Pinv, const double* num, const double* den, double* partials, double* out2,
-                            hipStream_t s) {
-    const uint32_t nblk = grid_blocks(nf);
-    hipLaunchKernelGGL(k_cg_update, dim3(nblk), dim3(kBlock), 0, s, nf, xv, r, z, p, Ap, Pinv, num, den, partials);
-    hipLaunchKernelGGL(k_finish_f64, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, 2, out2);
+hipError_t launch_cg_init(CgCtl* ctl, const double* rz, const double* bb, const double* rr, double tol,
+                          int32_t max_iters, HostStatus* host, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(1), 0, s, ctl, rz, bb, rr, tol, max_iters, host);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_direction(int64_t nf, float4* p, const float4* z, const double* rz_new, const double* rz_old,
-                               hipStream_t s) {
-    if (nf <= 0) return hipSuccess;
-    LAUNCH(k_cg_direction, nf, nf, p, z, rz_new, rz_old);
+hipError_t launch_cg_iteration(int64_t nf, float4* xv, float4* r, float4* z, float4* p, const float4* Ap,
+                               const float* Pinv, CgCtl* ctl, double* partials, HostStatus* host, hipStream_t s) {
+    const uint32_t nblk = grid_blocks(nf);
+    hipLaunchKernelGGL(k_cg_dot_pap, dim3(nblk), dim3(kBlock), 0, s, nf, p, Ap, ctl, partials);
+    hipLaunchKernelGGL(k_cg_finish_pap, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, ctl);
+    hipLaunchKernelGGL(k_cg_update, dim3(nblk), dim3(kBlock), 0, s, nf, xv, r, z, p, Ap, Pinv, ctl, partials);
+    hipLaunchKernelGGL(k_cg_finish_update, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, ctl, host);
+    hipLaunchKernelGGL(k_cg_direction, dim3(nblk), dim3(kBlock), 0, s, nf, p, z, ctl);
+    return hipGetLastError();
 }
 
 hipError_t launch_apply_precond(int64_t nf, const float* Pinv, const float4* r, float4* z, hipStream_t s) {

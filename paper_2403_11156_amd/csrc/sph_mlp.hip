@@ -36,6 +36,11 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 __device__ __forceinline__ uint16_t to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+// ReLU as one integer max on the bit pattern: every float with the sign bit
+// set (negatives, -0) becomes +0, the rest is unchanged (fmaxf costs a second,
+// canonicalising max per value)
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 __device__ __forceinline__ f32x16 mfma(bf16x4 a, bf16x4 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
 }
@@ -142,7 +147,7 @@ __device__ __forceinline__ void forward_tile(const WeightsLDS& W, const AOps& A,
         for (int cc = 0; cc < 4; ++cc) {
             uint16_t q[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) q[u] = to_bf16(fmaxf(f.z1[t][4 * cc + u], 0.f));
+            for (int u = 0; u < 4; ++u) q[u] = to_bf16(relu(f.z1[t][4 * cc + u]));
             f.h1[t][cc] = pack4(q);
         }
     }
@@ -158,7 +163,7 @@ __device__ __forceinline__ void forward_tile(const WeightsLDS& W, const AOps& A,
         f.z2[t] = c;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const float hv = from_bf16(to_bf16(fmaxf(c[r], 0.f)));
+            const float hv = from_bf16(to_bf16(relu(c[r])));
             f.h2[t][r] = hv;
             part += hv * W.w3[32 * t + drow(r, h)];
         }
@@ -244,7 +249,7 @@ __device__ __forceinline__ float forward_infer(const WeightsLDS& W, const InferR
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) hb[c][e] = (__bf16)fmaxf(z1[c >> 1][8 * (c & 1) + e], 0.f);
+        for (int e = 0; e < 8; ++e) hb[c][e] = (__bf16)relu(z1[c >> 1][8 * (c & 1) + e]);
     float part = 0.f;
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
@@ -252,7 +257,7 @@ __device__ __forceinline__ float forward_infer(const WeightsLDS& W, const InferR
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w2[t][c], hb[c], acc, 0, 0, 0);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) part += (float)(__bf16)fmaxf(acc[r], 0.f) * R.w3[t][r];
+        for (int r = 0; r < 16; ++r) part += (float)(__bf16)relu(acc[r]) * R.w3[t][r];
     }
     part += __shfl_xor(part, 32, 64);
     return (part + R.b3) * R.out_scale;
