@@ -260,7 +260,7 @@ __device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, 
     for (; c < e; ++c) take(c, pos[c]);
 }
 
-// Neighbour passes run L (1, 2 or 4) lanes per particle: lane q of the group
+// Neighbour passes run L (1, 2, 4 or 8) lanes per particle: lane q of the group
 // takes list entries k = q, q+L, q+2L, ...  The lanes of a wave instruction
 // that belong to one particle read adjacent entries of one 16-byte chunk of
 // its list, and a gather instruction touches the neighbours of 64/L
@@ -271,6 +271,7 @@ template <int L>
 __device__ __forceinline__ float group_sum(float v) {
     if (L >= 2) v += __shfl_xor(v, 1, 64);
     if (L >= 4) v += __shfl_xor(v, 2, 64);
+    if (L >= 8) v += __shfl_xor(v, 4, 64);
     return v;
 }
 
@@ -285,28 +286,35 @@ __device__ __forceinline__ int64_t group_particle(int& q) {
 template <int L, class F>
 __device__ __forceinline__ void for_each_nbr_l(const uint32_t* __restrict__ list, int64_t nf, int64_t i, int q,
                                                uint32_t n, F&& f) {
+    static_assert(L == 1 || L == 2 || L == 4 || L == 8, "lanes per particle");
     if (L == 1) {
         for_each_nbr(list, nf, i, n, f);
         return;
     }
-    // entries 4c + q + L t (t < 4/L) of chunk c sit at list + 4 (c nf + i) + q + L t
-    const uint32_t* p = list + ((i << 2) + q);
+    // entry k of particle i sits at list + 4 ((k/4) nf + i) + k%4; this lane
+    // takes k = q + L t.  Four of its entries per round, loaded ahead of the
+    // work: for L = 2 two chunks hold them (positions q and q + 2), for
+    // L >= 4 one chunk row each, L/4 rows apart.
     const int64_t step = nf << 2;   // one chunk row
-    constexpr int T = 4 / L;        // entries per lane per chunk
+    const uint32_t* p = list + ((((int64_t)(q >> 2) * nf + i) << 2) + (q & 3));
     uint32_t k = (uint32_t)q;
-    // four entries of this lane per round, loaded ahead of the work
     for (; k + 3 * L < n; k += 4 * L) {
         uint32_t j[4];
+        if (L == 2) {
+            j[0] = p[0];
+            j[1] = p[2];
+            j[2] = p[step];
+            j[3] = p[step + 2];
+            p += 2 * step;
+        } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) j[u] = p[(u / T) * step + (u % T) * L];
-        p += (4 / T) * step;
+            for (int u = 0; u < 4; ++u) j[u] = p[u * (L / 4) * step];
+            p += 4 * (L / 4) * step;
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) f(j[u]);
     }
-    for (; k < n; k += L) {
-        const uint32_t c = k >> 2, r = k & 3u;
-        f(list[(((int64_t)c * nf + i) << 2) + r]);
-    }
+    for (; k < n; k += L) f(list[(((int64_t)(k >> 2) * nf + i) << 2) + (k & 3u)]);
 }
 
 // Store the partial last chunk of a list filled by scan_candidates.

@@ -109,7 +109,7 @@ hipError_t launch_boundary_psi(float4* xb, int64_t nb, const uint32_t* start_b, 
 
 // the step
 hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, HostStatus* host, hipStream_t s);
-hipError_t launch_density_alpha(int64_t nf, float4* x, const float4* v, const uint32_t* nlist,
+hipError_t launch_density_alpha(int64_t nf, float4* x, float4* v, const uint32_t* nlist,
                                 const uint32_t* ncnt, const float4* xb, const uint32_t* blist,
                                 const uint32_t* bcnt, Kern kc, float* rho, float* alpha, float4* v_in,
                                 float* Kv, float* kappa, float warm_factor, hipStream_t s);

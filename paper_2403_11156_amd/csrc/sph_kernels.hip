@@ -296,10 +296,12 @@ __global__ void k_max_v2(const float4* __restrict__ v, int64_t n, uint32_t* out_
 
 // Density with the Akinci boundary term, Eq. (12), and the DFSPH factor
 // alpha = rho / (|sum_F m gradW + sum_B Psi gradW|^2 + sum_F |m gradW|^2).
-// Also saves the step's input velocity and sets up the divergence warm start.
+// Also saves the step's input velocity, copies rho into v.w (the XSPH pass
+// then gathers a neighbour's velocity and density in one load) and sets up
+// the divergence warm start.
 template <int L>
 __global__ void __launch_bounds__(kBlock) k_density_alpha(
-    int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, const uint32_t* __restrict__ nlist,
+    int64_t nf, float4* __restrict__ x, float4* __restrict__ v, const uint32_t* __restrict__ nlist,
     const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const uint32_t* __restrict__ blist,
     const uint32_t* __restrict__ bcnt, Kern kc, float* __restrict__ rho, float* __restrict__ alpha,
     float4* __restrict__ v_in, float* __restrict__ Kv, float* __restrict__ kappa, float warm_factor) {
@@ -337,7 +339,9 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
     const float D = gx * gx + gy * gy + gz * gz + sq;
     rho[i] = rr;
     alpha[i] = D > 1e-6f ? rr / D : 0.0f;
-    v_in[i] = v[i];
+    const float4 vi = v[i];
+    v_in[i] = vi;
+    v[i] = make_float4(vi.x, vi.y, vi.z, rr);
     const float k0 = warm_factor * Kv[i];
     kappa[i] = k0;
     Kv[i] = 0.0f;
@@ -462,7 +466,7 @@ __global__ void __launch_bounds__(kBlock) k_nonpressure(
         for_each_nbr_l<L>(nlist, nf, i, q, ncnt[i], [&](uint32_t j) {
             const float4 xj = x[j];
             const float4 vj = v[j];
-            const float mj = kc.m / rho[j];
+            const float mj = kc.m / vj.w;   // v.w = rho (density pass)
             const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             if (MODEL == 1) {
@@ -933,7 +937,7 @@ hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, HostSta
     return hipGetLastError();
 }
 
-hipError_t launch_density_alpha(int64_t nf, float4* x, const float4* v, const uint32_t* nlist, const uint32_t* ncnt,
+hipError_t launch_density_alpha(int64_t nf, float4* x, float4* v, const uint32_t* nlist, const uint32_t* ncnt,
                                 const float4* xb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float* rho,
                                 float* alpha, float4* v_in, float* Kv, float* kappa, float warm_factor,
                                 hipStream_t s) {
