@@ -89,6 +89,7 @@ struct sph_ctx {
     int64_t dev_bytes = 0;
 
     bool nbr_fresh = false, boundary_dirty = true, sorted_once = false;
+    bool vmax_ready = false;   // hs->vmax_bits holds max |v|^2 of the current v
     unsigned long long nstats[sph::kNStats] = {};   // of the last build
     int64_t step_index = 0;
     float last_dt = 0.f;
@@ -529,8 +530,14 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     // 1. time step (fixed, or CFL from the step's input velocities)
     float dt;
     if (c->P.cfl_lambda > 0.0) {
-        HIP_TRY(c, sph::launch_max_v2(c->v, nf, (uint32_t *)c->red_part, c->hs_dev, s));
-        HIP_TRY(c, hipStreamSynchronize(s));
+        // max |v|^2 of the step's input velocities: queued at the end of the
+        // previous step and complete at the neighbour build's synchronisation,
+        // else computed now
+        if (!c->vmax_ready) {
+            HIP_TRY(c, sph::launch_max_v2(c->v, nf, (uint32_t *)c->red_part, c->hs_dev, s));
+            HIP_TRY(c, hipStreamSynchronize(s));
+        }
+        c->vmax_ready = false;
         float vmax2;
         std::memcpy(&vmax2, &c->hs->vmax_bits, sizeof(float));
         double d = c->P.dt_max;
@@ -638,6 +645,10 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     {
         ProfScope ps(c, "integrate", 44.0 * nf);
         HIP_TRY(c, sph::launch_integrate(nf, c->x, c->v, dt, s));
+    }
+    if (c->P.cfl_lambda > 0.0) {   // the next step's CFL input, read after its neighbour build
+        HIP_TRY(c, sph::launch_max_v2(c->v, nf, (uint32_t *)c->red_part, c->hs_dev, s));
+        c->vmax_ready = true;
     }
     c->nbr_fresh = false;
     c->last_dt = dt;
@@ -1004,6 +1015,7 @@ int sph_read_state(sph_ctx *c, uint32_t mask, const sph_host_view *dst) {
 int sph_write_state(sph_ctx *c, uint32_t mask, const sph_host_view *src) {
     if (!c || !src) return SPH_ERR_INVALID;
     c->err.clear();
+    c->vmax_ready = false;
     const int64_t nf = c->nf, nb = c->nb;
     std::vector<int32_t> id;
     int rc = d2h(c, id, c->id, nf);
