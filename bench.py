@@ -25,7 +25,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 # design notes: own fields of every particle read/written once plus 4 B per
 # neighbour-list entry)
 PROFILED = ("pressure_update", "predict", "density_alpha", "xsph", "nbr_build", "sort", "integrate", "visc",
-            "warm_features", "mlp")
+            "warm_features", "mlp", "eos")
 KERNEL_SOURCES = ("sph_kernels.hip", "sph_device.h", "sph_internal.h")
 
 
@@ -115,7 +115,10 @@ def main():
         del a, b
     sc = scenes.scene(args.config)
     weights = os.path.join(ROOT, "paper_2403_11156_amd", "weights", "warm_start_mlp.f32")
+    wcsph = sc.params.get("solver", 0) == scenes.SOLVER_WCSPH
     arms = ["plain", "learned"] if args.arm == "both" else [args.arm]
+    if wcsph:
+        arms = ["plain"]   # no iterative solve to warm-start
     if "learned" in arms and not os.path.exists(weights):
         print("[bench] no trained warm-start weights; learned arm skipped", flush=True)
         arms = [a for a in arms if a != "learned"] or ["plain"]
@@ -162,7 +165,9 @@ def main():
                    "share": v["ms"] / max(1e-9, wall * 1e3)} for k, v in prof.items() if v["launches"]}
     n = len(iters)
     line = {
-        "metric": "particle-steps/sec at eta=0.1% (DFSPH), plain vs learned warm start",
+        "metric": ("particle-steps/sec (WCSPH, equation of state k=%g Pa, gamma=%g)"
+                   % (sc.params["wcsph_k"], sc.params["wcsph_gamma"]) if wcsph else
+                   "particle-steps/sec at eta=0.1% (DFSPH), plain vs learned warm start"),
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -176,6 +181,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc.name, "n_fluid": sc.n_fluid, "n_boundary": sc.n_boundary,
                    "n_rigid": len(sc.rigid), "r": sc.params["r"], "eta": sc.params["eta_density"],
+                   "solver": "wcsph" if wcsph else "dfsph", "dt": sc.params["dt_max"],
                    "warm_start": arms[0], "parallelism": "none (1 GPU)"},
         "iters_per_step": {"div": sum(i[0] for i in iters) / n, "dens": sum(i[1] for i in iters) / n,
                            "cg": sum(i[2] for i in iters) / n},

@@ -58,6 +58,10 @@ extern "C" {
 #define SPH_WARM_PREVIOUS 1 /* warm_factor * the previous step's accumulated stiffness */
 #define SPH_WARM_LEARNED 2  /* density solve: per-particle MLP prediction (sph_set_warm_start) */
 
+/* pressure solver (Sec. 3.4: the EOS solver of Sec. 3.4.1 or DFSPH, Sec. 3.4.2) */
+#define SPH_SOLVER_DFSPH 0  /* divergence-free and constant-density Jacobi solves (Algorithm 2) */
+#define SPH_SOLVER_WCSPH 1  /* equation of state p = k ((rho/rho0)^gamma - 1), one pressure pass */
+
 typedef struct sph_ctx sph_ctx;
 typedef struct sph_mlp sph_mlp;
 
@@ -84,6 +88,12 @@ typedef struct sph_mlp sph_mlp;
  *   warm_start      SPH_WARM_*; warm_factor scales the previous stiffness.
  *   max_neighbors, max_boundary_neighbors  list capacities per particle.
  *   auto_rebuild    1: sph_step rebuilds stale neighbour lists itself.
+ *   solver          SPH_SOLVER_*.  WCSPH (Sec. 3.4.1): p_i = wcsph_k
+ *                   ((rho_i/rho0)^wcsph_gamma - 1), clamped at zero, applied
+ *                   in one pressure pass after gravity and viscosity; dt_max
+ *                   must respect the acoustic limit ~0.4 h / c with
+ *                   c = sqrt(wcsph_k wcsph_gamma / rho0).  The warm-start and
+ *                   eta settings apply to DFSPH only.
  */
 typedef struct sph_params {
     double r, h, rho0;
@@ -100,6 +110,8 @@ typedef struct sph_params {
     double warm_factor;
     int32_t max_neighbors, max_boundary_neighbors;
     int32_t auto_rebuild;
+    int32_t solver;
+    double wcsph_k, wcsph_gamma;
 } sph_params;
 
 /* A rigid body (Sec. 3.5): mass, principal moments of inertia (body frame,
@@ -251,7 +263,7 @@ int sph_set_forced_iters(sph_ctx *ctx, int32_t div, int32_t dens);
  * the launch count and the summed event time [ms] of one kernel name, and the
  * algorithmic bytes those launches moved by the model stated in the design
  * notes.  Names: "nbr_build", "density_alpha", "pressure_update", "predict",
- * "xsph", "visc", "sort", "warm_features", "mlp", "integrate". */
+ * "xsph", "visc", "sort", "warm_features", "mlp", "integrate", "eos". */
 int sph_profile_enable(sph_ctx *ctx, int32_t enable);
 int sph_profile_read(sph_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms, double *bytes);
 

@@ -44,6 +44,7 @@ class Params(C.Structure):
         ("forced_div", C.c_int32), ("forced_dens", C.c_int32),
         ("n_rigid", C.c_int32),
         ("warm_factor", C.c_double),
+        ("solver", C.c_int32), ("wcsph_k", C.c_double), ("wcsph_gamma", C.c_double),
     ]
 
 
@@ -154,6 +155,9 @@ def make_params(pd: Dict, forced_div: int = -1, forced_dens: int = -1, n_rigid: 
     p.forced_div = forced_div; p.forced_dens = forced_dens
     p.n_rigid = n_rigid
     p.warm_factor = pd["warm_factor"]
+    p.solver = pd.get("solver", 0)
+    p.wcsph_k = pd.get("wcsph_k", 2.8e5)
+    p.wcsph_gamma = pd.get("wcsph_gamma", 7.0)
     return p
 
 

@@ -58,6 +58,8 @@ typedef struct or_params {
     int32_t forced_div, forced_dens; /* >= 0: run exactly that many iterations */
     int32_t n_rigid;
     double warm_factor;   /* PREVIOUS warm start: K0 = warm_factor * K_prev */
+    int32_t solver;       /* 0 DFSPH, 1 WCSPH (equation of state, one pressure pass) */
+    double wcsph_k, wcsph_gamma;  /* WCSPH stiffness [Pa] and exponent */
 } or_params;
 
 typedef struct or_rigid {
@@ -739,36 +741,41 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     double *kappa_last = calloc((size_t)(nf ? nf : 1), sizeof(double));
     double *Skappa_last = calloc((size_t)(nf ? nf : 1), sizeof(double));
 
-    /* -- 5. divergence-free solve (Eq. 10 with Algorithm 2).  Warm start:
-     *    Kv0 = 0 (ZERO) or the previous step's Kv (PREVIOUS, LEARNED). */
-    for (int64_t i = 0; i < nf; ++i) {
-        Kv[i] = p->warm_start == 0 ? 0.0 : p->warm_factor * (double)in->Kv[i];
-        SKv[i] = fabs(Kv[i]);
-    }
-    if (p->warm_start != 0) pressure_update(w, Kv, SKv, w->v, w->Sv);
-    divergence(w, w->v, w->Sv, d, Sd);
-    double err_v = 0.0, S_err_v = 0.0;
-    {
-        err_v = dt / p->rho0 * mean_pos(d, nf);
-        S_err_v = dt / p->rho0 * mean_abs(Sd, nf);
-    }
+    const int dfsph = p->solver == 0;
     int32_t lv = 0;
-    out->err_div_hist[0] = err_v;
-    for (;;) {
-        int go = p->forced_div >= 0 ? (lv < p->forced_div) : (err_v > p->eta_divergence && lv < p->max_iters);
-        if (!go) break;
+    double err_v = 0.0, S_err_v = 0.0;
+    if (dfsph) {
+        /* -- 5. divergence-free solve (Eq. 10 with Algorithm 2).  Warm start:
+         *    Kv0 = 0 (ZERO) or the previous step's Kv (PREVIOUS, LEARNED). */
         for (int64_t i = 0; i < nf; ++i) {
-            double dp = d[i] > 0.0 ? d[i] : 0.0;
-            kap[i] = dp * w->alpha[i] / dt;
-            Skap[i] = (Sd[i] * w->alpha[i] + dp * w->Salpha[i]) / dt;
+            Kv[i] = p->warm_start == 0 ? 0.0 : p->warm_factor * (double)in->Kv[i];
+            SKv[i] = fabs(Kv[i]);
         }
-        pressure_update(w, kap, Skap, w->v, w->Sv);
-        for (int64_t i = 0; i < nf; ++i) { Kv[i] += kap[i]; SKv[i] += Skap[i]; }
-        ++lv;
+        if (p->warm_start != 0) pressure_update(w, Kv, SKv, w->v, w->Sv);
         divergence(w, w->v, w->Sv, d, Sd);
         err_v = dt / p->rho0 * mean_pos(d, nf);
         S_err_v = dt / p->rho0 * mean_abs(Sd, nf);
-        if (lv < 128) out->err_div_hist[lv] = err_v;
+        out->err_div_hist[0] = err_v;
+        for (;;) {
+            int go = p->forced_div >= 0 ? (lv < p->forced_div) : (err_v > p->eta_divergence && lv < p->max_iters);
+            if (!go) break;
+            for (int64_t i = 0; i < nf; ++i) {
+                double dp = d[i] > 0.0 ? d[i] : 0.0;
+                kap[i] = dp * w->alpha[i] / dt;
+                Skap[i] = (Sd[i] * w->alpha[i] + dp * w->Salpha[i]) / dt;
+            }
+            pressure_update(w, kap, Skap, w->v, w->Sv);
+            for (int64_t i = 0; i < nf; ++i) { Kv[i] += kap[i]; SKv[i] += Skap[i]; }
+            ++lv;
+            divergence(w, w->v, w->Sv, d, Sd);
+            err_v = dt / p->rho0 * mean_pos(d, nf);
+            S_err_v = dt / p->rho0 * mean_abs(Sd, nf);
+            if (lv < 128) out->err_div_hist[lv] = err_v;
+        }
+    } else {
+        /* WCSPH has no divergence solve */
+        for (int64_t i = 0; i < nf; ++i) { Kv[i] = 0.0; SKv[i] = 0.0; d[i] = 0.0; Sd[i] = 0.0; }
+        out->err_div_hist[0] = 0.0;
     }
     out->iters_div = lv;
     out->err_div = err_v;
@@ -859,7 +866,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
      *    n_b)/26, K_prev dt^2/(alpha rho0), alpha/alpha_ref. */
     const double alpha_ref = 2.35376 * (2.0 * p->r) * (2.0 * p->r) / p->rho0;
     double *feat = NULL, *Sfeat = NULL;
-    if (p->warm_start == 2 || out->features) {
+    if (dfsph && (p->warm_start == 2 || out->features)) {
         feat = malloc(sizeof(double) * 5 * (nf ? nf : 1));
         Sfeat = malloc(sizeof(double) * 5 * (nf ? nf : 1));
         for (int64_t i = 0; i < nf; ++i) {
@@ -886,7 +893,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
         K[i] = p->warm_start == 0 ? 0.0 : p->warm_factor * (double)in->K[i];
         SK[i] = fabs(K[i]);
     }
-    if (p->warm_start == 2) {
+    if (dfsph && p->warm_start == 2) {
         double *y = malloc(2 * s1);
         in->mlp(feat, Sfeat, nf, y, in->mlp_user);
         for (int64_t i = 0; i < nf; ++i) {
@@ -896,7 +903,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
         }
         free(y);
     }
-    if (p->warm_start != 0) pressure_update(w, K, SK, w->v, w->Sv);
+    if (dfsph && p->warm_start != 0) pressure_update(w, K, SK, w->v, w->Sv);
 
     /* -- 8. constant-density solve (Eqs. 8, 9 with Eq. 7, Algorithm 2):
      *    rho*_i = rho_i + dt d_i(v*), kappa_i = max(rho*_i - rho0, 0) alpha_i / dt^2 */
@@ -912,25 +919,50 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
         err_d = mean_pos(rs, nf) / p->rho0;                                 \
         S_err_d = mean_abs(Srs, nf) / p->rho0;                              \
     } while (0)
-    PREDICT_DENSITY();
     int32_t ld = 0;
-    out->err_dens_hist[0] = err_d;
-    for (;;) {
-        int go = p->forced_dens >= 0 ? (ld < p->forced_dens) : (err_d > p->eta_density && ld < p->max_iters);
-        if (!go) break;
+    if (dfsph) {
+        PREDICT_DENSITY();
+        out->err_dens_hist[0] = err_d;
+        for (;;) {
+            int go = p->forced_dens >= 0 ? (ld < p->forced_dens) : (err_d > p->eta_density && ld < p->max_iters);
+            if (!go) break;
+            for (int64_t i = 0; i < nf; ++i) {
+                double e = rs[i] > 0.0 ? rs[i] : 0.0;
+                kap[i] = e * w->alpha[i] / (dt * dt);
+                Skap[i] = (Srs[i] * w->alpha[i] + e * w->Salpha[i]) / (dt * dt);
+            }
+            pressure_update(w, kap, Skap, w->v, w->Sv);
+            for (int64_t i = 0; i < nf; ++i) {
+                K[i] += kap[i]; SK[i] += Skap[i];
+                kappa_last[i] = kap[i]; Skappa_last[i] = Skap[i];
+            }
+            ++ld;
+            PREDICT_DENSITY();
+            if (ld < 128) out->err_dens_hist[ld] = err_d;
+        }
+    } else {
+        /* -- 8w. WCSPH (Sec. 3.4.1): the equation of state
+         *    p_i = k ((rho_i/rho0)^gamma - 1), clamped at zero (R20), then one
+         *    pressure pass on v* with kappa_i = p_i / rho_i (p/rho^2 = kappa/rho,
+         *    R4).  The reported error is the mean compression of rho itself. */
         for (int64_t i = 0; i < nf; ++i) {
-            double e = rs[i] > 0.0 ? rs[i] : 0.0;
-            kap[i] = e * w->alpha[i] / (dt * dt);
-            Skap[i] = (Srs[i] * w->alpha[i] + e * w->Salpha[i]) / (dt * dt);
+            const double ratio = w->rho[i] / p->rho0;
+            const double pw = pow(ratio, p->wcsph_gamma);
+            double pr = p->wcsph_k * (pw - 1.0);
+            if (pr < 0.0) pr = 0.0;
+            kap[i] = pr / w->rho[i];
+            /* scale: the two terms of the difference, and rho's own rounding
+             * through the exponent */
+            Skap[i] = p->wcsph_k * (pw + 1.0) * (1.0 + p->wcsph_gamma) / w->rho[i];
+            K[i] = kap[i]; SK[i] = Skap[i];
+            kappa_last[i] = kap[i]; Skappa_last[i] = Skap[i];
+            rs[i] = w->rho[i] - p->rho0;
+            Srs[i] = w->rho[i] + p->rho0;
         }
         pressure_update(w, kap, Skap, w->v, w->Sv);
-        for (int64_t i = 0; i < nf; ++i) {
-            K[i] += kap[i]; SK[i] += Skap[i];
-            kappa_last[i] = kap[i]; Skappa_last[i] = Skap[i];
-        }
-        ++ld;
-        PREDICT_DENSITY();
-        if (ld < 128) out->err_dens_hist[ld] = err_d;
+        err_d = mean_pos(rs, nf) / p->rho0;
+        S_err_d = mean_abs(Srs, nf) / p->rho0;
+        out->err_dens_hist[0] = err_d;
     }
 #undef PREDICT_DENSITY
     out->iters_dens = ld;

@@ -457,6 +457,29 @@ hipError_t visc_matvec(sph_ctx *c, const float4 *p, float4 *Mp, float dt, float 
     return sph::launch_visc_matvec(c->nf, c->x, c->rho, p, Mp, c->nlist, c->ncnt, c->kc, dt, mu, go, c->stream);
 }
 
+// WCSPH pressure (Sec. 3.4.1): kappa = p/rho from the equation of state (with
+// the mean compression of rho as the reported error), then one pressure pass
+// that accumulates kappa into K and records it as the last kappa.
+int wcsph_pressure(sph_ctx *c, float dt, double *err) {
+    hipStream_t s = c->stream;
+    int nparts = 0;
+    {
+        ProfScope ps(c, "eos", 16.0 * c->nf);   // rho in; kappa, K, x.w out
+        HIP_TRY(c, sph::launch_eos(c->nf, c->x, c->rho, c->kappa, c->K, c->kc, (float)c->P.wcsph_k,
+                                   (float)c->P.wcsph_gamma, c->red_part, &nparts, s));
+    }
+    sph::SolveCtl init{};
+    init.scale = 1.0 / (c->P.rho0 * (double)std::max<int64_t>(c->nf, 1));
+    init.eta = c->P.eta_density;
+    init.forced = 0;   // no iterations: the finish only records the error
+    HIP_TRY(c, sph::launch_solve_finish(c->red_part, nparts, c->ctl, true, init, c->hs_dev, s));
+    int rc = pressure_pass(c, c->K, c->kappa_last, dt, nullptr);
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(s));
+    *err = c->hs->solve.err;
+    return SPH_OK;
+}
+
 // Implicit viscosity (Eqs. 16-19): CG with block-Jacobi preconditioner on
 // (I - dt A) v* = v~, x0 = v~, stop at |r| <= tol |b|.  Dot products FP64.
 // The stop rule runs on the device (CgCtl) as in jacobi_solve: iterations are
@@ -549,10 +572,11 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     } else {
         dt = (float)c->P.dt_max;
     }
-    const bool warm = c->warm_mode != SPH_WARM_ZERO;
+    const bool dfsph = c->P.solver == SPH_SOLVER_DFSPH;
+    const bool warm = dfsph && c->warm_mode != SPH_WARM_ZERO;
     const float wf = warm ? (float)c->P.warm_factor : 0.0f;
-    const bool learned = c->warm_mode == SPH_WARM_LEARNED && c->mlp != nullptr;
-    const bool tracing = c->trace_feat != nullptr && c->trace_rows + nf <= c->trace_cap;
+    const bool learned = dfsph && c->warm_mode == SPH_WARM_LEARNED && c->mlp != nullptr;
+    const bool tracing = dfsph && c->trace_feat != nullptr && c->trace_rows + nf <= c->trace_cap;
     c->want_d = learned || tracing;
 
     // 2. density, alpha; divergence warm-start set-up
@@ -561,21 +585,24 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, c->nlist, c->ncnt, c->xb, c->blist, c->bcnt, c->kc,
                                              c->rho, c->alpha, c->v_in, c->Kv, c->kappa, wf, s));
     }
-    // 3. divergence-free solve
-    if (warm) {
-        int rc = pressure_pass(c, c->Kv, nullptr, dt, nullptr);
-        if (rc) return rc;
-    }
+    // 3. divergence-free solve (DFSPH)
     int32_t iv = 0, id = 0;
     double ev = 0.0, ed = 0.0;
-    int rc = jacobi_solve(c, 0, dt, c->Kv, nullptr, c->forced_div, c->P.eta_divergence, &iv, &ev);
-    if (rc) return rc;
+    int rc = SPH_OK;
+    if (dfsph) {
+        if (warm) {
+            rc = pressure_pass(c, c->Kv, nullptr, dt, nullptr);
+            if (rc) return rc;
+        }
+        rc = jacobi_solve(c, 0, dt, c->Kv, nullptr, c->forced_div, c->P.eta_divergence, &iv, &ev);
+        if (rc) return rc;
+    }
 
     // 4. non-pressure accelerations; density warm-start set-up
     int32_t cg_it = 0;
     double cg_res = 0.0;
     const float gx = (float)c->P.gravity[0], gy = (float)c->P.gravity[1], gz = (float)c->P.gravity[2];
-    const bool setup_in_pass = !(learned || tracing);
+    const bool setup_in_pass = dfsph && !(learned || tracing);
     if (c->P.visc_model == SPH_VISC_IMPLICIT) {
         rc = implicit_viscosity(c, dt, &cg_it, &cg_res);
         if (rc) return rc;
@@ -591,7 +618,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     //    prediction from per-particle features (density, the divergence left
     //    by the divergence-free solve, neighbour count, previous stiffness,
     //    alpha); the features also feed the training trace
-    if (!setup_in_pass) {
+    if (dfsph && !setup_in_pass) {
         const float alpha_ref = (float)(2.35376 * 4.0 * c->P.r * c->P.r / c->P.rho0);
         float *feat = tracing ? c->trace_feat + 5 * c->trace_rows : c->feat;
         {
@@ -610,14 +637,20 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
             HIP_TRY(c, sph::launch_warm_setup(nf, c->x, c->rho, c->K, c->kappa, wf, s));
         }
     }
-    if (warm) {
-        rc = pressure_pass(c, c->K, nullptr, dt, nullptr);
+    if (dfsph) {
+        if (warm) {
+            rc = pressure_pass(c, c->K, nullptr, dt, nullptr);
+            if (rc) return rc;
+        }
+        HIP_TRY(c, sph::launch_fill_f32(c->kappa_last, nf, 0.0f, s));
+        // 6. constant-density solve
+        rc = jacobi_solve(c, 1, dt, c->K, c->kappa_last, c->forced_dens, c->P.eta_density, &id, &ed);
+        if (rc) return rc;
+    } else {
+        // 6w. WCSPH: equation of state, then one pressure pass on v*
+        rc = wcsph_pressure(c, dt, &ed);
         if (rc) return rc;
     }
-    HIP_TRY(c, sph::launch_fill_f32(c->kappa_last, nf, 0.0f, s));
-    // 6. constant-density solve
-    rc = jacobi_solve(c, 1, dt, c->K, c->kappa_last, c->forced_dens, c->P.eta_density, &id, &ed);
-    if (rc) return rc;
 
     if (tracing) {
         HIP_TRY(c, sph::launch_trace_target(nf, c->alpha, c->K, dt, (float)c->P.rho0, c->trace_target + c->trace_rows, s));
@@ -715,7 +748,8 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     if (!p || !sc) return fail(nullptr, SPH_ERR_INVALID, "params or scene is NULL");
     if (!(p->r > 0) || !(p->h > 0) || !(p->rho0 > 0) || !(p->dt_max > 0) || p->max_iters < 0 ||
         p->max_neighbors <= 0 || p->max_boundary_neighbors <= 0 || p->cfl_lambda < 0 || p->warm_factor < 0 ||
-        p->visc_model < 0 || p->visc_model > 3 || p->warm_start < 0 || p->warm_start > 2 || p->cg_max_iters < 0)
+        p->visc_model < 0 || p->visc_model > 3 || p->warm_start < 0 || p->warm_start > 2 || p->cg_max_iters < 0 ||
+        p->solver < 0 || p->solver > 1 || (p->solver == SPH_SOLVER_WCSPH && !(p->wcsph_k > 0 && p->wcsph_gamma > 0)))
         return fail(nullptr, SPH_ERR_INVALID, "invalid parameter value");
     for (int a = 0; a < 3; ++a)
         if (!(p->domain_max[a] > p->domain_min[a])) return fail(nullptr, SPH_ERR_INVALID, "empty domain");

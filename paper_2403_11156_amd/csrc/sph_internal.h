@@ -130,6 +130,10 @@ hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, cons
                           const float4* xb, const float4* vb, const uint32_t* blist, const uint32_t* bcnt,
                           Kern kc, float dt, double* partials, SolveCtl* ctl, bool first, float* dout,
                           int* nparts, hipStream_t s);   // the pass only; nparts partials for the finish
+// WCSPH equation of state: kappa = max(k ((rho/rho0)^gamma - 1), 0) / rho,
+// x.w = kappa/rho, K = 0; nparts partials of max(rho - rho0, 0) for a finish
+hipError_t launch_eos(int64_t nf, float4* x, const float* rho, float* kappa, float* K, Kern kc, float k, float gamma,
+                      double* partials, int* nparts, hipStream_t s);
 // One-workgroup finish of a predict pass over nblk partials: the first finish
 // of a solve initialises ctl from init; every finish copies ctl to host->solve.
 hipError_t launch_solve_finish(const double* partials, int nblk, SolveCtl* ctl, bool first, const SolveCtl& init,

@@ -517,6 +517,28 @@ __global__ void k_features(int64_t nf, const float* __restrict__ rho, const floa
     f[4] = a / alpha_ref;
 }
 
+// WCSPH equation of state (Sec. 3.4.1): p = k ((rho/rho0)^gamma - 1), clamped
+// at zero; kappa = p/rho (so p/rho^2 = kappa/rho as in the DFSPH passes),
+// x.w = kappa/rho, K = 0 (the pressure pass accumulates kappa into it), and
+// per-workgroup FP64 partials of max(rho - rho0, 0) for the reported error.
+__global__ void k_eos(int64_t nf, float4* __restrict__ x, const float* __restrict__ rho, float* __restrict__ kappa,
+                      float* __restrict__ K, Kern kc, float k, float gamma, double* __restrict__ partials) {
+    const int64_t i = particle_index();
+    double e = 0.0;
+    if (i < nf) {
+        const float r = rho[i];
+        const float pw = powf(r / kc.rho0, gamma);
+        const float p = fmaxf(k * (pw - 1.0f), 0.0f);
+        const float kap = p / r;
+        kappa[i] = kap;
+        K[i] = 0.0f;
+        x[i].w = kap / r;
+        e = (double)fmaxf(r - kc.rho0, 0.0f);
+    }
+    const double bs = block_sum(e);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
 // K0 = max(0, y alpha rho0 / dt^2) from the MLP output y.
 __global__ void k_warm_learned(int64_t nf, float4* __restrict__ x, const float* __restrict__ rho,
                                const float* __restrict__ alpha, const float* __restrict__ y, float* __restrict__ K,
@@ -970,6 +992,15 @@ hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, cons
     else
         hipLaunchKernelGGL((k_predict<1, kLanesPredict>), dim3(nblk), dim3(kBlock), 0, s, nf, x, v, rho, alpha, kappa, nlist, ncnt, xb,
                            vb, blist, bcnt, kc, dt, partials, go, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_eos(int64_t nf, float4* x, const float* rho, float* kappa, float* K, Kern kc, float k, float gamma,
+                      double* partials, int* nparts, hipStream_t s) {
+    const uint32_t nblk = grid_blocks(nf);
+    *nparts = nf > 0 ? (int)nblk : 0;
+    if (nf <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eos, dim3(nblk), dim3(kBlock), 0, s, nf, x, rho, kappa, K, kc, k, gamma, partials);
     return hipGetLastError();
 }
 

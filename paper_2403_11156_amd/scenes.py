@@ -33,6 +33,7 @@ _M2 = np.uint64(0x94D049BB133111EB)
 
 VISC_NONE, VISC_XSPH, VISC_LAPLACIAN, VISC_IMPLICIT = 0, 1, 2, 3
 WARM_ZERO, WARM_PREVIOUS, WARM_LEARNED = 0, 1, 2
+SOLVER_DFSPH, SOLVER_WCSPH = 0, 1
 
 
 def splitmix64(seed: int, count: int, offset: int = 0) -> np.ndarray:
@@ -141,6 +142,9 @@ def default_params(r: float, lo, hi, **kw) -> Dict:
         cg_tol=1e-4, cg_max_iters=1000,
         warm_start=WARM_PREVIOUS, warm_factor=0.5,
         max_neighbors=64, max_boundary_neighbors=48,
+        # WCSPH: gamma = 7, k = rho0 c^2 / gamma with a sound speed c of 44 m/s,
+        # ten times the ~4.4 m/s a 1 m dam break reaches
+        solver=SOLVER_DFSPH, wcsph_k=2.8e5, wcsph_gamma=7.0,
     )
     p.update(kw)
     return p
@@ -238,6 +242,15 @@ def scene(name: str) -> Scene:
     if name == "c5":
         return make_block_scene("c5 dam break 1.23M", 0.005, (0, 0, 0), (2.0, 1.0, 1.0),
                                 (150, 82, 100), (0.005, 0.005, 0.005), seed=5, steps=1000)
+    if name == "c1w":
+        # c1 with the WCSPH solver; dt within the acoustic limit 0.4 h / c
+        return make_block_scene("c1 dam break 8k, WCSPH", 0.01, (0, 0, 0), (0.8, 0.8, 0.8), (20, 20, 20),
+                                (0.01, 0.01, 0.01), seed=1, steps=100, cfl_lambda=0.0, dt_max=2e-4,
+                                solver=SOLVER_WCSPH)
+    if name == "c5w":
+        return make_block_scene("c5 dam break 1.23M, WCSPH", 0.005, (0, 0, 0), (2.0, 1.0, 1.0),
+                                (150, 82, 100), (0.005, 0.005, 0.005), seed=5, steps=1000, dt_max=1.5e-4,
+                                solver=SOLVER_WCSPH)
     if name == "column":
         # hydrostatic fixture: unjittered 10 x 30 x 10 column filling a 0.2 m wide tank
         return make_block_scene("hydrostatic column", 0.01, (0, 0, 0), (0.2, 0.8, 0.2), (10, 30, 10),

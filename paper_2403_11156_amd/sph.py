@@ -37,6 +37,7 @@ class sph_params(C.Structure):
         ("warm_start", C.c_int32), ("warm_factor", C.c_double),
         ("max_neighbors", C.c_int32), ("max_boundary_neighbors", C.c_int32),
         ("auto_rebuild", C.c_int32),
+        ("solver", C.c_int32), ("wcsph_k", C.c_double), ("wcsph_gamma", C.c_double),
     ]
 
 
@@ -194,6 +195,9 @@ def make_params(pd: Dict) -> sph_params:
     p.max_neighbors = pd["max_neighbors"]
     p.max_boundary_neighbors = pd["max_boundary_neighbors"]
     p.auto_rebuild = pd.get("auto_rebuild", 0)
+    p.solver = pd.get("solver", 0)
+    p.wcsph_k = pd.get("wcsph_k", 2.8e5)
+    p.wcsph_gamma = pd.get("wcsph_gamma", 7.0)
     return p
 
 
