@@ -115,10 +115,11 @@ def main():
         del a, b
     sc = scenes.scene(args.config)
     weights = os.path.join(ROOT, "paper_2403_11156_amd", "weights", "warm_start_mlp.f32")
-    wcsph = sc.params.get("solver", 0) == scenes.SOLVER_WCSPH
+    solver = sc.params.get("solver", scenes.SOLVER_DFSPH)
+    wcsph = solver == scenes.SOLVER_WCSPH
     arms = ["plain", "learned"] if args.arm == "both" else [args.arm]
-    if wcsph:
-        arms = ["plain"]   # no iterative solve to warm-start
+    if solver != scenes.SOLVER_DFSPH:
+        arms = ["plain"]   # the learned warm start is DFSPH's
     if "learned" in arms and not os.path.exists(weights):
         print("[bench] no trained warm-start weights; learned arm skipped", flush=True)
         arms = [a for a in arms if a != "learned"] or ["plain"]
@@ -140,7 +141,7 @@ def main():
         t0 = time.perf_counter()
         for _ in range(args.steps):
             st = sim.advance()
-            iters.append((st["iters_div"], st["iters_dens"], st["cg_iters"], st["err_dens"], st["err_div"]))
+            iters.append((st["iters_div"], st["iters_dens"], st["cg_iters"], st["err_dens"], st["err_div"], st["dt"]))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         prof = {k: sim.profile_read(k) for k in PROFILED}
@@ -167,6 +168,7 @@ def main():
     line = {
         "metric": ("particle-steps/sec (WCSPH, equation of state k=%g Pa, gamma=%g)"
                    % (sc.params["wcsph_k"], sc.params["wcsph_gamma"]) if wcsph else
+                   "particle-steps/sec at eta=0.1% (PCISPH)" if solver == scenes.SOLVER_PCISPH else
                    "particle-steps/sec at eta=0.1% (DFSPH), plain vs learned warm start"),
         "value": value,
         "unit": "particle-steps/s",
@@ -181,11 +183,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc.name, "n_fluid": sc.n_fluid, "n_boundary": sc.n_boundary,
                    "n_rigid": len(sc.rigid), "r": sc.params["r"], "eta": sc.params["eta_density"],
-                   "solver": "wcsph" if wcsph else "dfsph", "dt": sc.params["dt_max"],
+                   "solver": ("dfsph", "wcsph", "pcisph")[solver], "dt_max": sc.params["dt_max"],
                    "warm_start": arms[0], "parallelism": "none (1 GPU)"},
         "iters_per_step": {"div": sum(i[0] for i in iters) / n, "dens": sum(i[1] for i in iters) / n,
                            "cg": sum(i[2] for i in iters) / n},
         "max_err_dens": max(i[3] for i in iters), "max_err_div": max(i[4] for i in iters),
+        "mean_dt": sum(i[5] for i in iters) / n, "simulated_s_per_wall_s": sum(i[5] for i in iters) / wall,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config, dom),
                      "bytes_per_launch": d["bytes"] / max(d["launches"], 1)},

@@ -58,9 +58,11 @@ extern "C" {
 #define SPH_WARM_PREVIOUS 1 /* warm_factor * the previous step's accumulated stiffness */
 #define SPH_WARM_LEARNED 2  /* density solve: per-particle MLP prediction (sph_set_warm_start) */
 
-/* pressure solver (Sec. 3.4: the EOS solver of Sec. 3.4.1 or DFSPH, Sec. 3.4.2) */
+/* pressure solver (Sec. 3.4: the EOS solver of Sec. 3.4.1, or the PPE solvers
+ * of Sec. 3.4.2) */
 #define SPH_SOLVER_DFSPH 0  /* divergence-free and constant-density Jacobi solves (Algorithm 2) */
 #define SPH_SOLVER_WCSPH 1  /* equation of state p = k ((rho/rho0)^gamma - 1), one pressure pass */
+#define SPH_SOLVER_PCISPH 2 /* constant-density solve with PCISPH's prototype stiffness factor */
 
 typedef struct sph_ctx sph_ctx;
 typedef struct sph_mlp sph_mlp;
@@ -92,8 +94,15 @@ typedef struct sph_mlp sph_mlp;
  *                   ((rho_i/rho0)^wcsph_gamma - 1), clamped at zero, applied
  *                   in one pressure pass after gravity and viscosity; dt_max
  *                   must respect the acoustic limit ~0.4 h / c with
- *                   c = sqrt(wcsph_k wcsph_gamma / rho0).  The warm-start and
- *                   eta settings apply to DFSPH only.
+ *                   c = sqrt(wcsph_k wcsph_gamma / rho0).  PCISPH (Sec. 3.4.2,
+ *                   Algorithm 2): no divergence-free solve; the
+ *                   constant-density solve runs with kappa_i = (rho*_i -
+ *                   rho0) c / (rho_i dt^2), c = rho0^2 / (2 sum_j |m gradW_j|^2)
+ *                   over a prototype particle in a filled lattice of spacing
+ *                   2r (PCISPH's delta), and reports c / rho_i as alpha.
+ *                   eta_divergence applies to DFSPH only, eta_density and
+ *                   warm_start to DFSPH and PCISPH; SPH_WARM_LEARNED needs
+ *                   DFSPH (SPH_ERR_INVALID otherwise).
  */
 typedef struct sph_params {
     double r, h, rho0;

@@ -121,6 +121,8 @@ def lib():
                                         C.c_int32, C.c_void_p, C.c_void_p, C.c_int64]
         L.or_rigid_local.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         L.or_boundary_psi.argtypes = [C.POINTER(Params), C.c_void_p, C.c_int64, C.c_void_p]
+        L.or_pcisph_factor.restype = C.c_double
+        L.or_pcisph_factor.argtypes = [C.POINTER(Params)]
         L.or_step.restype = C.c_int
         L.or_step.argtypes = [C.POINTER(Params), C.POINTER(In), C.POINTER(Out)]
         L.or_visc_dense.argtypes = [C.POINTER(Params), C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p]
@@ -307,6 +309,12 @@ class State:
         self.rigid = [dict(r) for r in scene.rigid]
         self.local = rigid_local(self.xb, self.body, self.rigid) if local is None else local
         self.vb = np.zeros_like(self.xb)
+
+
+def pcisph_factor(pd: Dict) -> float:
+    """PCISPH stiffness factor c of kappa_i = (rho*_i - rho0) c / (rho_i dt^2)."""
+    p = make_params(pd)
+    return float(lib().or_pcisph_factor(C.byref(p)))
 
 
 def step(state: State, forced_div: int = -1, forced_dens: int = -1, brute: Optional[bool] = None,

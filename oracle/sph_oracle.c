@@ -58,7 +58,8 @@ typedef struct or_params {
     int32_t forced_div, forced_dens; /* >= 0: run exactly that many iterations */
     int32_t n_rigid;
     double warm_factor;   /* PREVIOUS warm start: K0 = warm_factor * K_prev */
-    int32_t solver;       /* 0 DFSPH, 1 WCSPH (equation of state, one pressure pass) */
+    int32_t solver;       /* 0 DFSPH, 1 WCSPH (equation of state, one pressure pass),
+                             2 PCISPH (density solve with the prototype stiffness factor) */
     double wcsph_k, wcsph_gamma;  /* WCSPH stiffness [Pa] and exponent */
 } or_params;
 
@@ -676,7 +677,32 @@ static void visc_cg(world *w, double mu, const double *b, double *x, int32_t *it
 }
 
 /* ---- the whole step ------------------------------------------------------ */
+/* PCISPH stiffness factor (Sec. 3.4.2 names PCISPH; its delta is taken from
+ * the predictive-corrective method, reading R21).  delta = 1 / (beta sum_j
+ * |gradW_j|^2) with beta = 2 (dt m / rho0)^2, summed once over a prototype
+ * particle inside a filled lattice of spacing 2r (its sum_j gradW_j vanishes
+ * by symmetry).  In the stiffness form of the density solve, kappa_i = p_i /
+ * rho_i = (rho*_i - rho0) c / (rho_i dt^2) with
+ *     c = rho0^2 / (2 sum_j |m gradW_j|^2).                                  */
+double or_pcisph_factor(const or_params *p) {
+    const double s = 2.0 * p->r, h = p->h;
+    const double m = p->rho0 * s * s * s;
+    const int n = (int)ceil(h / s);
+    double sum = 0.0;
+    for (int a = -n; a <= n; ++a)
+        for (int b = -n; b <= n; ++b)
+            for (int c = -n; c <= n; ++c) {
+                const double d = s * sqrt((double)(a * a + b * b + c * c));
+                if (d == 0.0 || d >= h) continue;
+                const double g = m * or_dWdr(d, h);
+                sum += g * g;
+            }
+    return p->rho0 * p->rho0 / (2.0 * sum);
+}
+
 int or_step(const or_params *p, const or_in *in, or_out *out) {
+    if (p->solver == 2 && p->warm_start == 2) return -2;   /* the learned start is DFSPH's */
+    if (in->nf < 0 || in->nb < 0) return -3;
     world W_, *w = &W_;
     memset(w, 0, sizeof(*w));
     const int64_t nf = in->nf, nb = in->nb, n3 = 3 * nf;
@@ -733,6 +759,16 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     /* -- 4. density (Eq. 12) and alpha */
     w->rho = malloc(s1); w->alpha = malloc(s1); w->Salpha = malloc(s1);
     density_alpha(w);
+    const int dfsph = p->solver == 0, pcisph = p->solver == 2;
+    if (pcisph) {
+        /* PCISPH: the density solve's factor is c / rho_i (R21) instead of
+         * the DFSPH alpha; it is reported in its place */
+        const double c = or_pcisph_factor(p);
+        for (int64_t i = 0; i < nf; ++i) {
+            w->alpha[i] = c / w->rho[i];
+            w->Salpha[i] = w->alpha[i];
+        }
+    }
 
     double *v_in = malloc(s3);
     memcpy(v_in, w->v, s3);
@@ -741,7 +777,6 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     double *kappa_last = calloc((size_t)(nf ? nf : 1), sizeof(double));
     double *Skappa_last = calloc((size_t)(nf ? nf : 1), sizeof(double));
 
-    const int dfsph = p->solver == 0;
     int32_t lv = 0;
     double err_v = 0.0, S_err_v = 0.0;
     if (dfsph) {
@@ -773,7 +808,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
             if (lv < 128) out->err_div_hist[lv] = err_v;
         }
     } else {
-        /* WCSPH has no divergence solve */
+        /* WCSPH and PCISPH have no divergence solve */
         for (int64_t i = 0; i < nf; ++i) { Kv[i] = 0.0; SKv[i] = 0.0; d[i] = 0.0; Sd[i] = 0.0; }
         out->err_div_hist[0] = 0.0;
     }
@@ -903,10 +938,11 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
         }
         free(y);
     }
-    if (dfsph && p->warm_start != 0) pressure_update(w, K, SK, w->v, w->Sv);
+    if ((dfsph || pcisph) && p->warm_start != 0) pressure_update(w, K, SK, w->v, w->Sv);
 
     /* -- 8. constant-density solve (Eqs. 8, 9 with Eq. 7, Algorithm 2):
-     *    rho*_i = rho_i + dt d_i(v*), kappa_i = max(rho*_i - rho0, 0) alpha_i / dt^2 */
+     *    rho*_i = rho_i + dt d_i(v*), kappa_i = max(rho*_i - rho0, 0) alpha_i / dt^2,
+     *    with PCISPH's c / rho_i in place of alpha_i (R21) */
     double *rs = malloc(s1), *Srs = malloc(s1);
     double err_d, S_err_d;
 #define PREDICT_DENSITY()                                                   \
@@ -920,7 +956,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
         S_err_d = mean_abs(Srs, nf) / p->rho0;                              \
     } while (0)
     int32_t ld = 0;
-    if (dfsph) {
+    if (dfsph || pcisph) {
         PREDICT_DENSITY();
         out->err_dens_hist[0] = err_d;
         for (;;) {

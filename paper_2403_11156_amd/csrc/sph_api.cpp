@@ -49,6 +49,7 @@ struct sph_ctx {
     Grid g{};
     Kern kc{};
     float cell = 0.f;
+    float pci_c = 0.f;   // PCISPH stiffness factor (0 for the other solvers)
     int64_t ncell = 0;
     int32_t capf = 0, capb = 0;
 
@@ -573,7 +574,9 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         dt = (float)c->P.dt_max;
     }
     const bool dfsph = c->P.solver == SPH_SOLVER_DFSPH;
-    const bool warm = dfsph && c->warm_mode != SPH_WARM_ZERO;
+    const bool pcisph = c->P.solver == SPH_SOLVER_PCISPH;
+    const bool ppe = dfsph || pcisph;   // iterative density solve
+    const bool warm = ppe && c->warm_mode != SPH_WARM_ZERO;
     const float wf = warm ? (float)c->P.warm_factor : 0.0f;
     const bool learned = dfsph && c->warm_mode == SPH_WARM_LEARNED && c->mlp != nullptr;
     const bool tracing = dfsph && c->trace_feat != nullptr && c->trace_rows + nf <= c->trace_cap;
@@ -583,7 +586,8 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     {
         ProfScope ps(c, "density_alpha", 80.0 * nf + list_bytes(c));
         HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, c->nlist, c->ncnt, c->xb, c->blist, c->bcnt, c->kc,
-                                             c->rho, c->alpha, c->v_in, c->Kv, c->kappa, wf, s));
+                                             c->rho, c->alpha, c->v_in, c->Kv, c->kappa, dfsph ? wf : 0.0f,
+                                             c->pci_c, s));
     }
     // 3. divergence-free solve (DFSPH)
     int32_t iv = 0, id = 0;
@@ -602,7 +606,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     int32_t cg_it = 0;
     double cg_res = 0.0;
     const float gx = (float)c->P.gravity[0], gy = (float)c->P.gravity[1], gz = (float)c->P.gravity[2];
-    const bool setup_in_pass = dfsph && !(learned || tracing);
+    const bool setup_in_pass = ppe && !(learned || tracing);
     if (c->P.visc_model == SPH_VISC_IMPLICIT) {
         rc = implicit_viscosity(c, dt, &cg_it, &cg_res);
         if (rc) return rc;
@@ -637,7 +641,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
             HIP_TRY(c, sph::launch_warm_setup(nf, c->x, c->rho, c->K, c->kappa, wf, s));
         }
     }
-    if (dfsph) {
+    if (ppe) {
         if (warm) {
             rc = pressure_pass(c, c->K, nullptr, dt, nullptr);
             if (rc) return rc;
@@ -706,6 +710,27 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     return SPH_OK;
 }
 
+// PCISPH's delta = 1 / (2 (dt m / rho0)^2 sum_j |gradW_j|^2), summed over the
+// neighbours of a particle inside a filled lattice of spacing 2r (where
+// sum_j gradW_j = 0), written as the factor c of the density solve's
+// kappa_i = (rho*_i - rho0) c / (rho_i dt^2):  c = rho0^2 / (2 m^2 sum_j |gradW_j|^2).
+// Host FP64, once per context.
+double pcisph_factor(const sph_params &p) {
+    const double s = 2.0 * p.r, h = p.h, m = p.rho0 * s * s * s;
+    const double k6 = 48.0 / (M_PI * h * h * h * h);   // 6 * 8 / (pi h^3) / h
+    const int reach = (int)std::ceil(h / s);
+    double g2 = 0.0;
+    for (int i = -reach; i <= reach; ++i)
+        for (int j = -reach; j <= reach; ++j)
+            for (int k = -reach; k <= reach; ++k) {
+                const double q = s * std::sqrt((double)(i * i + j * j + k * k)) / h;
+                if (q <= 0.0 || q >= 1.0) continue;
+                const double slope = q <= 0.5 ? q * (3.0 * q - 2.0) : -(1.0 - q) * (1.0 - q);   // dW/dr / k6
+                g2 += (k6 * slope) * (k6 * slope);
+            }
+    return p.rho0 * p.rho0 / (2.0 * m * m * g2);
+}
+
 bool finite3(const float *p, int64_t n) {
     for (int64_t i = 0; i < 3 * n; ++i)
         if (!std::isfinite(p[i])) return false;
@@ -749,8 +774,10 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     if (!(p->r > 0) || !(p->h > 0) || !(p->rho0 > 0) || !(p->dt_max > 0) || p->max_iters < 0 ||
         p->max_neighbors <= 0 || p->max_boundary_neighbors <= 0 || p->cfl_lambda < 0 || p->warm_factor < 0 ||
         p->visc_model < 0 || p->visc_model > 3 || p->warm_start < 0 || p->warm_start > 2 || p->cg_max_iters < 0 ||
-        p->solver < 0 || p->solver > 1 || (p->solver == SPH_SOLVER_WCSPH && !(p->wcsph_k > 0 && p->wcsph_gamma > 0)))
+        p->solver < 0 || p->solver > 2 || (p->solver == SPH_SOLVER_WCSPH && !(p->wcsph_k > 0 && p->wcsph_gamma > 0)))
         return fail(nullptr, SPH_ERR_INVALID, "invalid parameter value");
+    if (p->solver != SPH_SOLVER_DFSPH && p->warm_start == SPH_WARM_LEARNED)
+        return fail(nullptr, SPH_ERR_INVALID, "the learned warm start needs the DFSPH solver");
     for (int a = 0; a < 3; ++a)
         if (!(p->domain_max[a] > p->domain_min[a])) return fail(nullptr, SPH_ERR_INVALID, "empty domain");
     if (sc->n_fluid < 0 || sc->n_boundary < 0 || sc->n_rigid < 0 || sc->n_rigid > sph::kMaxBodies)
@@ -807,6 +834,7 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     c->kc.kg = (float)(6.0 * kk / p->h);
     c->kc.m = (float)(p->rho0 * 8.0 * p->r * p->r * p->r);
     c->kc.rho0 = (float)p->rho0;
+    if (p->solver == SPH_SOLVER_PCISPH) c->pci_c = (float)pcisph_factor(*p);
 
     const int64_t nf = c->nf, nb = c->nb;
     const int64_t scan_chunks = (ncell + 4095) / 4096;
@@ -1285,6 +1313,8 @@ int sph_set_warm_start(sph_ctx *c, int32_t mode, sph_mlp *mlp) {
     c->warm_fallback = false;
     if (mode == SPH_WARM_LEARNED) {
         if (!mlp) return fail(c, SPH_ERR_INVALID, "learned warm start needs an MLP");
+        if (c->P.solver != SPH_SOLVER_DFSPH)
+            return fail(c, SPH_ERR_INVALID, "the learned warm start needs the DFSPH solver");
         if (!mlp->finite) {
             c->warm_fallback = true;
             c->warm_mode = SPH_WARM_PREVIOUS;

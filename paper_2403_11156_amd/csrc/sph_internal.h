@@ -112,7 +112,7 @@ hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, HostSta
 hipError_t launch_density_alpha(int64_t nf, float4* x, float4* v, const uint32_t* nlist,
                                 const uint32_t* ncnt, const float4* xb, const uint32_t* blist,
                                 const uint32_t* bcnt, Kern kc, float* rho, float* alpha, float4* v_in,
-                                float* Kv, float* kappa, float warm_factor, hipStream_t s);
+                                float* Kv, float* kappa, float warm_factor, float pci_c, hipStream_t s);
 // go (nullable): the pass does nothing when *go == 0 (an iteration the
 // solve no longer needs).
 hipError_t launch_pressure_update(int64_t nf, const float4* x, float4* v, const float* kappa, float* Kacc,

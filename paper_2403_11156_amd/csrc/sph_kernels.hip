@@ -304,7 +304,8 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
     int64_t nf, float4* __restrict__ x, float4* __restrict__ v, const uint32_t* __restrict__ nlist,
     const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const uint32_t* __restrict__ blist,
     const uint32_t* __restrict__ bcnt, Kern kc, float* __restrict__ rho, float* __restrict__ alpha,
-    float4* __restrict__ v_in, float* __restrict__ Kv, float* __restrict__ kappa, float warm_factor) {
+    float4* __restrict__ v_in, float* __restrict__ Kv, float* __restrict__ kappa, float warm_factor,
+    float pci_c) {
     int q;
     const int64_t i = group_particle<L>(q);
     if (i >= nf) return;   // whole groups leave together
@@ -338,7 +339,8 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
     if (q != 0) return;
     const float D = gx * gx + gy * gy + gz * gz + sq;
     rho[i] = rr;
-    alpha[i] = D > 1e-6f ? rr / D : 0.0f;
+    // PCISPH (pci_c > 0): the prototype factor c / rho replaces alpha
+    alpha[i] = pci_c > 0.0f ? pci_c / rr : (D > 1e-6f ? rr / D : 0.0f);
     const float4 vi = v[i];
     v_in[i] = vi;
     v[i] = make_float4(vi.x, vi.y, vi.z, rr);
@@ -962,10 +964,10 @@ hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, HostSta
 hipError_t launch_density_alpha(int64_t nf, float4* x, float4* v, const uint32_t* nlist, const uint32_t* ncnt,
                                 const float4* xb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float* rho,
                                 float* alpha, float4* v_in, float* Kv, float* kappa, float warm_factor,
-                                hipStream_t s) {
+                                float pci_c, hipStream_t s) {
     if (nf <= 0) return hipSuccess;
     LAUNCH(k_density_alpha<kLanesDensity>, kLanesDensity * nf, nf, x, v, nlist, ncnt, xb, blist, bcnt, kc, rho, alpha, v_in, Kv, kappa,
-           warm_factor);
+           warm_factor, pci_c);
 }
 
 hipError_t launch_pressure_update(int64_t nf, const float4* x, float4* v, const float* kappa, float* Kacc,

@@ -33,7 +33,7 @@ _M2 = np.uint64(0x94D049BB133111EB)
 
 VISC_NONE, VISC_XSPH, VISC_LAPLACIAN, VISC_IMPLICIT = 0, 1, 2, 3
 WARM_ZERO, WARM_PREVIOUS, WARM_LEARNED = 0, 1, 2
-SOLVER_DFSPH, SOLVER_WCSPH = 0, 1
+SOLVER_DFSPH, SOLVER_WCSPH, SOLVER_PCISPH = 0, 1, 2
 
 
 def splitmix64(seed: int, count: int, offset: int = 0) -> np.ndarray:
@@ -251,6 +251,15 @@ def scene(name: str) -> Scene:
         return make_block_scene("c5 dam break 1.23M, WCSPH", 0.005, (0, 0, 0), (2.0, 1.0, 1.0),
                                 (150, 82, 100), (0.005, 0.005, 0.005), seed=5, steps=1000, dt_max=1.5e-4,
                                 solver=SOLVER_WCSPH)
+    if name == "c1p":
+        # c1 with the PCISPH solver (density solve only, pressure from zero each step)
+        return make_block_scene("c1 dam break 8k, PCISPH", 0.01, (0, 0, 0), (0.8, 0.8, 0.8), (20, 20, 20),
+                                (0.01, 0.01, 0.01), seed=1, steps=100, cfl_lambda=0.0, dt_max=4e-4,
+                                solver=SOLVER_PCISPH, warm_start=WARM_ZERO)
+    if name == "c5p":
+        return make_block_scene("c5 dam break 1.23M, PCISPH", 0.005, (0, 0, 0), (2.0, 1.0, 1.0),
+                                (150, 82, 100), (0.005, 0.005, 0.005), seed=5, steps=1000,
+                                solver=SOLVER_PCISPH, warm_start=WARM_ZERO)
     if name == "column":
         # hydrostatic fixture: unjittered 10 x 30 x 10 column filling a 0.2 m wide tank
         return make_block_scene("hydrostatic column", 0.01, (0, 0, 0), (0.2, 0.8, 0.2), (10, 30, 10),

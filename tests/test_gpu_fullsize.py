@@ -23,7 +23,7 @@ def sph():
     return mod
 
 
-@pytest.mark.parametrize("name", ["c5", "c3", "c5w"])
+@pytest.mark.parametrize("name", ["c5", "c3", "c5w", "c5p"])
 def test_full_size_step(sph, name):
     sc = scenes.scene(name)
     print(f"[fullsize] {sc.name}: nf={sc.n_fluid} nb={sc.n_boundary} bodies={len(sc.rigid)}", flush=True)

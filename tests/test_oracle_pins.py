@@ -463,3 +463,81 @@ def test_wcsph_fluid_pressure_momentum_is_zero():
     dv = out["v"] - st.v
     assert out["nb_count"].max() == 0 and out["K"].max() > 0
     assert np.abs(m * dv.sum(axis=0)).max() < 1e-10 * m * np.abs(dv).sum()
+
+
+# --------------------------------------------------------------- PCISPH (Sec. 3.4.2)
+def _lattice_grad_sum(s):
+    # sum over the rest-lattice neighbours of f'(q)^2 in units where m k / h = rho0/(2 pi s):
+    # 6 at q = 1/2 (f' = -3/2), 12 at q = 1/sqrt2, 8 at q = sqrt3/2
+    return 13.5 + 12 * 36 * (1 - 1 / math.sqrt(2)) ** 4 + 8 * 36 * (1 - math.sqrt(3) / 2) ** 4
+
+
+@pytest.mark.parametrize("r", [0.01, 0.005, 2.0 ** -7])
+def test_pcisph_factor_closed_form(r):
+    # c = rho0^2 / (2 m^2 sum |gradW|^2) with m |gradW_j| = rho0/(2 pi s) |f'(q_j)|,
+    # so c = (2 pi s)^2 / (2 sum f'^2); equivalently rho0^2 alpha_bulk / (2 rho_bulk)
+    # with the pinned bulk DFSPH factor and lattice density
+    s = 2 * r
+    pd = scenes.default_params(r, (0, 0, 0), (1, 1, 1))
+    c = O.pcisph_factor(pd)
+    expect = (2 * math.pi * s) ** 2 / (2 * _lattice_grad_sum(s))
+    assert abs(c - expect) < 1e-12 * expect
+    assert abs(c / (s * s) - 2.35376 / (2 * 0.99997246609)) < 1e-4
+
+
+def test_pcisph_compressed_lattice_first_iteration():
+    # a compressed lattice moving uniformly: XSPH and the velocity divergence
+    # vanish, so rho* = rho and one forced iteration gives exactly
+    # K = max(rho - rho0, 0) c / (rho dt^2); no divergence solve runs, and the
+    # reported alpha is c / rho
+    r = 2.0 ** -7
+    s = 2 * r
+    sc = _lattice_scene(9, 0.9 * s, r, (0.5, 0.5, 0.5), solver=scenes.SOLVER_PCISPH, cfl_lambda=0.0,
+                        dt_max=2e-4, warm_start=scenes.WARM_ZERO)
+    sc.v_fluid[:] = np.array([0.1, -0.3, 0.2], np.float32)
+    st = O.State(sc)
+    out = O.step(st, forced_dens=1)
+    c = (2 * math.pi * s) ** 2 / (2 * _lattice_grad_sum(s))
+    rho_c, _, _ = O.density_alpha(sc.params, sc.x_fluid, np.zeros((0, 3), np.float32))
+    dt = out["dt"]
+    expect = np.maximum(rho_c - 1000.0, 0.0) * c / (rho_c * dt * dt)
+    assert out["iters_div"] == 0 and out["iters_dens"] == 1
+    assert np.all(out["Kv"] == 0.0)
+    assert expect.max() > 0 and (expect == 0).any()   # compressed inside, not at the corners
+    np.testing.assert_allclose(out["K"], expect, rtol=1e-12, atol=1e-12 * expect.max())
+    np.testing.assert_allclose(out["alpha"], c / rho_c, rtol=1e-12)
+
+
+def test_pcisph_solver_stops_at_eta_and_conserves_momentum():
+    # Algorithm 2's stop rule on a dam break, and antisymmetric fluid-fluid
+    # pressure terms on a free block (no walls, gravity and viscosity off)
+    sc = scenes.scene("c1p")
+    st = O.State(sc)
+    p = st.params
+    for _ in range(4):
+        out = O.step(st)
+        assert out["iters_div"] == 0
+        assert out["err_dens"] <= p["eta_density"] or out["iters_dens"] == p["max_iters"]
+        assert (out["err_dens_hist"][:-1] > p["eta_density"]).all()
+        st = O.advance(st, out)
+    r = 0.01
+    sc = scenes.make_block_scene("momp", r, (0, 0, 0), (0.4, 0.4, 0.4), (6, 6, 6), (0.1, 0.1, 0.1),
+                                 seed=10, steps=1, gravity=(0.0, 0.0, 0.0), visc_model=0, jitter=0.3,
+                                 cfl_lambda=0.0, dt_max=1e-3, solver=scenes.SOLVER_PCISPH, warm_start=0)
+    sc.x_fluid = (0.9 * (sc.x_fluid - 0.2) + 0.2).astype(np.float32)
+    sc.v_fluid[:] = np.random.default_rng(4).normal(0, 0.3, sc.v_fluid.shape).astype(np.float32)
+    st = O.State(sc)
+    out = O.step(st, forced_dens=4)
+    m = 1000.0 * (2 * r) ** 3
+    dv = out["v"] - st.v
+    assert out["nb_count"].max() == 0 and out["K"].max() > 0
+    assert np.abs(m * dv.sum(axis=0)).max() < 1e-10 * m * np.abs(dv).sum()
+    h = out["err_dens_hist"]
+    assert (np.diff(h) < 0).all()   # the sweeps reduce the compression
+
+
+def test_pcisph_rejects_learned_warm_start():
+    sc = scenes.scene("c1p")
+    sc.params = dict(sc.params, warm_start=scenes.WARM_LEARNED)
+    with pytest.raises(RuntimeError):
+        O.step(O.State(sc))
