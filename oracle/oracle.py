@@ -45,6 +45,7 @@ class Params(C.Structure):
         ("n_rigid", C.c_int32),
         ("warm_factor", C.c_double),
         ("solver", C.c_int32), ("wcsph_k", C.c_double), ("wcsph_gamma", C.c_double),
+        ("cg_warm_factor", C.c_double),
     ]
 
 
@@ -64,6 +65,7 @@ class In(C.Structure):
         ("xb", C.c_void_p), ("vb", C.c_void_p), ("body", C.c_void_p), ("local", C.c_void_p),
         ("rigid", C.c_void_p), ("mlp", MLP_FN), ("mlp_user", C.c_void_p),
         ("brute_force", C.c_int32),
+        ("dvisc", C.c_void_p),
     ]
 
 
@@ -86,6 +88,7 @@ class Out(C.Structure):
         ("err_div", C.c_double), ("err_dens", C.c_double),
         ("S_err_div", C.c_double), ("S_err_dens", C.c_double), ("cg_resid", C.c_double),
         ("err_div_hist", C.c_double * 128), ("err_dens_hist", C.c_double * 128),
+        ("dvisc", C.c_void_p),
     ]
 
 
@@ -160,6 +163,7 @@ def make_params(pd: Dict, forced_div: int = -1, forced_dens: int = -1, n_rigid: 
     p.solver = pd.get("solver", 0)
     p.wcsph_k = pd.get("wcsph_k", 2.8e5)
     p.wcsph_gamma = pd.get("wcsph_gamma", 7.0)
+    p.cg_warm_factor = pd.get("cg_warm_factor", 0.0)
     return p
 
 
@@ -309,6 +313,7 @@ class State:
         self.rigid = [dict(r) for r in scene.rigid]
         self.local = rigid_local(self.xb, self.body, self.rigid) if local is None else local
         self.vb = np.zeros_like(self.xb)
+        self.dvisc = np.zeros((n, 3), np.float32)   # previous implicit-viscosity correction
 
 
 def pcisph_factor(pd: Dict) -> float:
@@ -345,6 +350,8 @@ def step(state: State, forced_div: int = -1, forced_dens: int = -1, brute: Optio
     ci.xb, ci.vb, ci.body, ci.local = _p(xb), _p(vb), _p(body), _p(local)
     ci.rigid = C.cast(rb, C.c_void_p)
     ci.brute_force = int(bool(brute))
+    dv = np.ascontiguousarray(getattr(state, "dvisc", np.zeros((nf, 3))), np.float32).reshape(nf, 3)
+    ci.dvisc = _p(dv)
     keep = []
     if mlp is not None:
         def _cb(fp, sp, n, yp, user):
@@ -361,7 +368,7 @@ def step(state: State, forced_div: int = -1, forced_dens: int = -1, brute: Optio
     else:
         ci.mlp = MLP_FN()
 
-    o = {k: np.zeros((nf, 3)) for k in ("x", "v", "accel", "S_x", "S_v", "S_accel")}
+    o = {k: np.zeros((nf, 3)) for k in ("x", "v", "accel", "S_x", "S_v", "S_accel", "dvisc")}
     for k in ("rho", "alpha", "K", "Kv", "kappa", "S_K", "S_Kv", "S_kappa", "S_alpha"):
         o[k] = np.zeros(nf)
     o["psi"] = np.zeros(max(1, nb))
@@ -421,6 +428,7 @@ def advance(state: State, out: Dict) -> State:
     s.body = state.body
     s.local = state.local
     s.rigid = out["rigid_new"]
+    s.dvisc = out["dvisc"].astype(np.float32)
     return s
 
 

@@ -61,6 +61,7 @@ typedef struct or_params {
     int32_t solver;       /* 0 DFSPH, 1 WCSPH (equation of state, one pressure pass),
                              2 PCISPH (density solve with the prototype stiffness factor) */
     double wcsph_k, wcsph_gamma;  /* WCSPH stiffness [Pa] and exponent */
+    double cg_warm_factor;        /* implicit-viscosity CG start: x0 = b + cg_warm_factor dvisc_prev */
 } or_params;
 
 typedef struct or_rigid {
@@ -83,6 +84,7 @@ typedef struct or_in {
     or_mlp_fn mlp;
     void *mlp_user;
     int32_t brute_force;       /* 1: O(N^2) neighbour sets, 0: oracle grid */
+    const float *dvisc;        /* [nf][3] previous implicit-viscosity correction v* - b (NULL: zero) */
 } or_in;
 
 typedef struct or_out {
@@ -102,6 +104,7 @@ typedef struct or_out {
     int32_t iters_div, iters_dens, converged_div, converged_dens, cg_iters;
     double err_div, err_dens, S_err_div, S_err_dens, cg_resid;
     double err_div_hist[128], err_dens_hist[128];
+    double *dvisc;             /* [nf][3] this step's implicit-viscosity correction v* - b (may be NULL) */
 } or_out;
 
 /* ------------------------------------------------------------------------ */
@@ -638,14 +641,14 @@ static double dot(const double *a, const double *b, int64_t n) {
     return s;
 }
 
-/* Preconditioned CG (block Jacobi), x0 = b, stop at |r| <= tol |b| */
+/* Preconditioned CG (block Jacobi) from the start value x (on entry), stop at
+ * |r| <= tol |b| */
 static void visc_cg(world *w, double mu, const double *b, double *x, int32_t *iters, double *resid) {
     int64_t n3 = 3 * w->nf;
     size_t sz = sizeof(double) * (n3 ? n3 : 1);
     double *r = malloc(sz), *z = malloc(sz), *pp = malloc(sz), *Ap = malloc(sz);
     double *Pinv = malloc(sizeof(double) * 9 * (w->nf ? w->nf : 1));
     visc_block_inverse(w, mu, Pinv);
-    memcpy(x, b, sz);
     visc_M(w, mu, x, Ap);
     for (int64_t i = 0; i < n3; ++i) r[i] = b[i] - Ap[i];
     for (int64_t i = 0; i < w->nf; ++i)
@@ -878,7 +881,13 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
         double *b = malloc(s3);
         for (int64_t i = 0; i < nf; ++i)
             for (int a = 0; a < 3; ++a) b[3 * i + a] = w->v[3 * i + a] + dt * gr[a];
+        /* start value (R22): x0 = b + cg_warm_factor times the previous
+         * step's correction v* - b */
+        for (int64_t i = 0; i < n3; ++i)
+            vs[i] = b[i] + (in->dvisc ? p->cg_warm_factor * (double)in->dvisc[i] : 0.0);
         visc_cg(w, p->visc * p->rho0, b, vs, &out->cg_iters, &out->cg_resid);
+        if (out->dvisc)
+            for (int64_t i = 0; i < n3; ++i) out->dvisc[i] = vs[i] - b[i];
         /* the CG result is compared by its residual, so its scale is its size */
         for (int64_t i = 0; i < n3; ++i) Svs[i] = w->Sv[i] + fabs(vs[i]);
         free(b);
@@ -1221,6 +1230,7 @@ int or_visc_solve(const or_params *p, const float *xf, int64_t nf, double dt, co
     for (int64_t i = 0; i < 3 * nf; ++i) w->x[i] = xf[i];
     w->rho = malloc(sizeof(double) * nf); w->alpha = malloc(sizeof(double) * nf); w->Salpha = malloc(sizeof(double) * nf);
     density_alpha(w);
+    memcpy(x, b, sizeof(double) * 3 * nf);
     visc_cg(w, p->visc * p->rho0, b, x, iters, resid);
     free(w->x); free(w->rho); free(w->alpha); free(w->Salpha);
     csr_free(&w->ff); csr_free(&w->fb);

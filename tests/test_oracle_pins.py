@@ -541,3 +541,62 @@ def test_pcisph_rejects_learned_warm_start():
     sc.params = dict(sc.params, warm_start=scenes.WARM_LEARNED)
     with pytest.raises(RuntimeError):
         O.step(O.State(sc))
+
+
+# ------------------------------------------- implicit-viscosity CG start value
+def _visc_column(**kw):
+    return scenes.make_block_scene("visc column", 0.008, (0, 0, 0), (0.4, 0.5, 0.2), (8, 20, 8),
+                                   (0.008, 0.008, 0.008), seed=4, steps=1, visc_model=scenes.VISC_IMPLICIT,
+                                   visc=10.0, **kw)
+
+
+def test_cg_start_from_the_exact_solution_takes_no_iteration():
+    # with pressure off, the step's velocity is the CG solution v*; giving the
+    # exact dense solution as the start (factor 1, dvisc = v* - b) needs no
+    # iteration and returns it; the reported correction is v* - b
+    sc = _visc_scene(7)   # a free block: no wall neighbours, so visc_dense is the step's matrix
+    sc.params = dict(sc.params, cg_warm_factor=1.0, warm_start=0)
+    st = O.State(sc)
+    st.v = np.random.default_rng(6).normal(0, 0.5, st.v.shape).astype(np.float32)
+    out = O.step(st, forced_div=0, forced_dens=0)
+    assert out["nb_count"].max() == 0
+    dt = out["dt"]
+    b = st.v.astype(np.float64) + dt * np.array(sc.params["gravity"])
+    np.testing.assert_allclose(out["dvisc"], out["v"] - b, rtol=0, atol=1e-15)
+    M, _ = O.visc_dense(sc.params, st.x, dt)
+    xs = np.linalg.solve(M, b.reshape(-1)).reshape(-1, 3)
+    st.dvisc = (xs - b).astype(np.float32)
+    out2 = O.step(st, forced_div=0, forced_dens=0)
+    assert out2["cg_iters"] == 0 and out["cg_iters"] > 5
+    start = b + st.dvisc.astype(np.float64)
+    np.testing.assert_array_equal(out2["v"], start)
+    # the same solution from x0 = b and from the warm start, within cond x tol
+    assert np.abs(out2["v"] - out["v"]).max() <= 4 * np.linalg.cond(M) * 1e-4 * np.abs(b).max()
+
+
+def test_cg_start_factor_zero_is_x0_b():
+    sc = _visc_column(cg_warm_factor=0.0)
+    st = O.State(sc)
+    st.dvisc = np.random.default_rng(5).normal(0, 1.0, st.v.shape).astype(np.float32)
+    a = O.step(st)
+    st.dvisc[:] = 0.0
+    b = O.step(st)
+    assert a["cg_iters"] == b["cg_iters"]
+    np.testing.assert_array_equal(a["v"], b["v"])
+
+
+def test_cg_start_half_previous_correction_saves_iterations():
+    # the start of R22 on the viscous column: over 12 steps the half previous
+    # correction needs clearly fewer CG iterations than x0 = b (the same
+    # trajectory: the step is re-run with factor 0 from each state)
+    sc = _visc_column(cg_warm_factor=0.5)
+    st = O.State(sc)
+    cold_pd = dict(sc.params, cg_warm_factor=0.0)
+    warm_it = cold_it = 0
+    for k in range(16):
+        out = O.step(st)
+        if k >= 4:
+            warm_it += out["cg_iters"]
+            cold_it += O.step(st, params=cold_pd)["cg_iters"]
+        st = O.advance(st, out)
+    assert warm_it < 0.85 * cold_it, (warm_it, cold_it)
