@@ -87,6 +87,9 @@ typedef struct sph_mlp sph_mlp;
  *   visc_model/visc SPH_VISC_*; visc is the XSPH epsilon or the kinematic
  *                   viscosity nu [m^2/s] (mu = nu rho0).
  *   cg_tol/cg_max_iters  implicit viscosity: relative residual and cap.
+ *   cg_warm_factor  implicit viscosity: the CG starts from x0 = v~ + cg_warm_factor
+ *                   times the previous step's correction v* - v~ (0: x0 = v~;
+ *                   [0, 4]; the correction is SPH_FIELD_DVISC).
  *   warm_start      SPH_WARM_*; warm_factor scales the previous stiffness.
  *   max_neighbors, max_boundary_neighbors  list capacities per particle.
  *   auto_rebuild    1: sph_step rebuilds stale neighbour lists itself.
@@ -121,6 +124,7 @@ typedef struct sph_params {
     int32_t auto_rebuild;
     int32_t solver;
     double wcsph_k, wcsph_gamma;
+    double cg_warm_factor;
 } sph_params;
 
 /* A rigid body (Sec. 3.5): mass, principal moments of inertia (body frame,
@@ -176,6 +180,7 @@ typedef struct sph_step_stats {
 #define SPH_FIELD_PSI (1u << 9)      /* Akinci boundary mass Psi, Eq. (11) */
 #define SPH_FIELD_BOUNDARY (1u << 10)/* boundary positions and velocities (read, write) */
 #define SPH_FIELD_RIGID (1u << 11)   /* rigid states (read, write), force and torque (read) */
+#define SPH_FIELD_DVISC (1u << 12)   /* implicit-viscosity correction v* - v~ of the last step (read, write) */
 
 /* Host buffers for sph_read_state / sph_write_state; NULL members are
  * skipped.  Fluid arrays have n_fluid entries, boundary arrays n_boundary,
@@ -188,6 +193,7 @@ typedef struct sph_host_view {
     float *x_boundary, *v_boundary;
     sph_rigid_desc *rigid;
     double *rigid_force, *rigid_torque; /* [n_rigid][3], Eq. (14) summed per body */
+    float *dvisc;                       /* [n_fluid][3] */
 } sph_host_view;
 
 /* Static facts about a context. */

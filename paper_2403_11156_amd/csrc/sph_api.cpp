@@ -81,6 +81,8 @@ struct sph_ctx {
     // implicit viscosity
     float *Pinv = nullptr;
     float4 *cg_b = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
+    float4 *dvisc = nullptr, *dvisc2 = nullptr;   // previous correction v* - b, sorted order
+    double *cg_part = nullptr;                    // CG partial sums (mat-vec, then update)
 
     std::vector<sph_rigid_desc> rigid;
     std::vector<double> force, torque;
@@ -314,8 +316,9 @@ int sort_fluid(sph_ctx *c) {
     HIP_TRY(c, sph::launch_exclusive_scan(c->count, c->ncell, c->start_f, c->scan_part, s));
     HIP_TRY(c, sph::launch_scatter(c->key, c->slot, c->start_f, c->nf, c->src, s));
     HIP_TRY(c, sph::launch_cell_sort(c->start_f, c->ncell, c->src, c->id, c->flags, s));
-    HIP_TRY(c, sph::launch_gather_fluid(c->src, c->nf, c->x, c->v, c->K, c->Kv, c->id, c->x2, c->v2, c->K2, c->Kv2,
-                                        c->id2, s));
+    HIP_TRY(c, sph::launch_gather_fluid(c->src, c->nf, c->x, c->v, c->K, c->Kv, c->id, c->dvisc, c->x2, c->v2, c->K2,
+                                        c->Kv2, c->id2, c->dvisc2, s));
+    std::swap(c->dvisc, c->dvisc2);
     std::swap(c->x, c->x2);
     std::swap(c->v, c->v2);
     std::swap(c->K, c->K2);
@@ -454,8 +457,9 @@ int jacobi_solve(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, int3
     return SPH_OK;
 }
 
-hipError_t visc_matvec(sph_ctx *c, const float4 *p, float4 *Mp, float dt, float mu, const int32_t *go) {
-    return sph::launch_visc_matvec(c->nf, c->x, c->rho, p, Mp, c->nlist, c->ncnt, c->kc, dt, mu, go, c->stream);
+hipError_t visc_matvec(sph_ctx *c, const float4 *p, float4 *Mp, float dt, float mu, const int32_t *go,
+                       double *partials) {
+    return sph::launch_visc_matvec(c->nf, c->x, p, Mp, c->nlist, c->ncnt, c->kc, dt, mu, go, partials, c->stream);
 }
 
 // WCSPH pressure (Sec. 3.4.1): kappa = p/rho from the equation of state (with
@@ -482,43 +486,45 @@ int wcsph_pressure(sph_ctx *c, float dt, double *err) {
 }
 
 // Implicit viscosity (Eqs. 16-19): CG with block-Jacobi preconditioner on
-// (I - dt A) v* = v~, x0 = v~, stop at |r| <= tol |b|.  Dot products FP64.
-// The stop rule runs on the device (CgCtl) as in jacobi_solve: iterations are
-// queued in batches and the host reads the control block once per batch.
+// (I - dt A) v* = v~ from x0 = v~ + cg_warm_factor (the previous step's
+// correction v* - v~), stop at |r| <= tol |b|.  Dot products FP64.  The stop
+// rule runs on the device as in jacobi_solve: iterations are queued in
+// batches and the host reads the control block once per batch.  An iteration
+// is three kernels (mat-vec with the p.Ap sums, update, direction) whose
+// control blocks alternate between two slots.
 int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
     hipStream_t s = c->stream;
     const int64_t nf = c->nf;
+    *iters = 0;
+    *resid = 0.0;
+    if (nf == 0) return SPH_OK;
     const float mu = (float)(c->P.visc * c->P.rho0);
-    HIP_TRY(c, sph::launch_gravity(nf, c->v, c->cg_b, dt, (float)c->P.gravity[0], (float)c->P.gravity[1],
-                                   (float)c->P.gravity[2], s));
-    HIP_TRY(c, hipMemcpyAsync(c->v2, c->cg_b, sizeof(float4) * nf, hipMemcpyDeviceToDevice, s));   // x0 = b
+    HIP_TRY(c, sph::launch_cg_start(nf, c->v, c->dvisc, c->cg_b, c->v2, dt, (float)c->P.gravity[0],
+                                    (float)c->P.gravity[1], (float)c->P.gravity[2], (float)c->P.cg_warm_factor, s));
     {
         ProfScope ps(c, "visc", 60.0 * nf + fluid_list_bytes(c));
         HIP_TRY(c, sph::launch_visc_precond(nf, c->x, c->rho, c->nlist, c->ncnt, c->kc, dt, mu, c->Pinv, s));
     }
     {
-        ProfScope ps(c, "visc", 44.0 * nf + fluid_list_bytes(c));
-        HIP_TRY(c, visc_matvec(c, c->v2, c->cg_Ap, dt, mu, nullptr));
+        ProfScope ps(c, "visc", 48.0 * nf + fluid_list_bytes(c));
+        HIP_TRY(c, visc_matvec(c, c->v2, c->cg_Ap, dt, mu, nullptr, nullptr));
     }
-    HIP_TRY(c, sph::launch_axpy_residual(nf, c->cg_b, c->cg_Ap, c->cg_r, s));
-    HIP_TRY(c, sph::launch_apply_precond(nf, c->Pinv, c->cg_r, c->cg_z, s));
-    HIP_TRY(c, hipMemcpyAsync(c->cg_p, c->cg_z, sizeof(float4) * nf, hipMemcpyDeviceToDevice, s));
-    double *rz = c->scal + 1, *bb = c->scal + 2, *rr = c->scal + 3;
-    HIP_TRY(c, sph::launch_dot(nf, c->cg_r, c->cg_z, c->red_part, rz, s));
-    HIP_TRY(c, sph::launch_dot(nf, c->cg_b, c->cg_b, c->red_part, bb, s));
-    HIP_TRY(c, sph::launch_dot(nf, c->cg_r, c->cg_r, c->red_part, rr, s));
-    HIP_TRY(c, sph::launch_cg_init(c->cgc, rz, bb, rr, c->P.cg_tol, c->P.cg_max_iters, c->hs_dev, s));
+    HIP_TRY(c, sph::launch_cg_setup(nf, c->cg_b, c->cg_Ap, c->Pinv, c->cg_r, c->cg_z, c->cg_p, c->cg_part, &c->cgc[0],
+                                    c->P.cg_tol, c->P.cg_max_iters, c->hs_dev, s));
+    const int npap = sph::visc_matvec_parts(nf);
+    double *pap = c->cg_part, *upd = c->cg_part + npap;
     const int32_t cap = std::max(c->P.cg_max_iters, 0);
     const size_t mark = c->prof_pending.size();
     int32_t queued = 0, batch = std::min(std::max(c->last_cg, 1), cap);
     for (;;) {
         for (int32_t k = 0; k < batch; ++k) {
+            const int par = (queued + k) & 1;
             {
-                ProfScope ps(c, "visc", 44.0 * nf + fluid_list_bytes(c));
-                HIP_TRY(c, visc_matvec(c, c->cg_p, c->cg_Ap, dt, mu, &c->cgc->go));
+                ProfScope ps(c, "visc", 48.0 * nf + fluid_list_bytes(c));
+                HIP_TRY(c, visc_matvec(c, c->cg_p, c->cg_Ap, dt, mu, &c->cgc[par].go, pap));
             }
-            HIP_TRY(c, sph::launch_cg_iteration(nf, c->v2, c->cg_r, c->cg_z, c->cg_p, c->cg_Ap, c->Pinv, c->cgc,
-                                                c->red_part, c->hs_dev, s));
+            HIP_TRY(c, sph::launch_cg_iteration(nf, c->v2, c->cg_r, c->cg_z, c->cg_p, c->cg_Ap, c->Pinv, &c->cgc[par],
+                                                &c->cgc[par ^ 1], pap, npap, upd, c->hs_dev, s));
         }
         queued += batch;
         HIP_TRY(c, hipStreamSynchronize(s));
@@ -539,6 +545,7 @@ int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
     const double bnorm = h.bnorm, rnorm = std::sqrt(h.rr);
     *iters = h.iters;
     *resid = bnorm > 0 ? rnorm / bnorm : rnorm;
+    HIP_TRY(c, sph::launch_visc_correction(nf, c->v2, c->cg_b, c->dvisc, s));
     std::swap(c->v, c->v2);
     return SPH_OK;
 }
@@ -776,6 +783,8 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
         p->visc_model < 0 || p->visc_model > 3 || p->warm_start < 0 || p->warm_start > 2 || p->cg_max_iters < 0 ||
         p->solver < 0 || p->solver > 2 || (p->solver == SPH_SOLVER_WCSPH && !(p->wcsph_k > 0 && p->wcsph_gamma > 0)))
         return fail(nullptr, SPH_ERR_INVALID, "invalid parameter value");
+    if (!(p->cg_warm_factor >= 0.0 && p->cg_warm_factor <= 4.0))
+        return fail(nullptr, SPH_ERR_INVALID, "cg_warm_factor outside [0, 4]");
     if (p->solver != SPH_SOLVER_DFSPH && p->warm_start == SPH_WARM_LEARNED)
         return fail(nullptr, SPH_ERR_INVALID, "the learned warm start needs the DFSPH solver");
     for (int a = 0; a < 3; ++a)
@@ -860,13 +869,14 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     ALLOC(c->bkey, nb); ALLOC(c->bslot, nb); ALLOC(c->bsrc, nb); ALLOC(c->blocal, 3 * nb);
     ALLOC(c->poses, std::max(1, c->nr)); ALLOC(c->com_dev, 3 * std::max(1, c->nr));
     ALLOC(c->red_part, nred * 6 * std::max(1, c->nr) + 16); ALLOC(c->scal, 16);
-    ALLOC(c->ctl, 1); ALLOC(c->cgc, 1);
+    ALLOC(c->ctl, 1); ALLOC(c->cgc, 2);
     ALLOC(c->flags, 4);
     ALLOC(c->nstat_part, sph::kNStats * nred);
     ALLOC(c->feat, 5 * nf); ALLOC(c->ybuf, nf); ALLOC(c->dbuf, nf);
     if (p->visc_model == SPH_VISC_IMPLICIT) {
         ALLOC(c->Pinv, 9 * nf); ALLOC(c->cg_b, nf); ALLOC(c->cg_r, nf); ALLOC(c->cg_z, nf); ALLOC(c->cg_p, nf);
-        ALLOC(c->cg_Ap, nf);
+        ALLOC(c->cg_Ap, nf); ALLOC(c->dvisc, nf); ALLOC(c->dvisc2, nf);
+        ALLOC(c->cg_part, sph::visc_matvec_parts(nf) + 3 * (int64_t)sph::reduction_blocks(nf) + 16);
     }
 #undef ALLOC
     if (hipHostMalloc((void **)&c->hs, sizeof(sph::HostStatus), hipHostMallocMapped | hipHostMallocCoherent) !=
@@ -892,7 +902,8 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
                   hipMemcpyAsync(c->v, hv.data(), sizeof(float4) * nf, hipMemcpyHostToDevice, s) == hipSuccess &&
                   hipMemcpyAsync(c->id, hid.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, s) == hipSuccess &&
                   hipMemcpyAsync(c->K, zero.data(), sizeof(float) * nf, hipMemcpyHostToDevice, s) == hipSuccess &&
-                  hipMemcpyAsync(c->Kv, zero.data(), sizeof(float) * nf, hipMemcpyHostToDevice, s) == hipSuccess;
+                  hipMemcpyAsync(c->Kv, zero.data(), sizeof(float) * nf, hipMemcpyHostToDevice, s) == hipSuccess &&
+                  (!c->dvisc || hipMemsetAsync(c->dvisc, 0, sizeof(float4) * nf, s) == hipSuccess);
         // boundary: positions, velocities from the body state, body ids, local offsets
         c->rigid.assign(sc->rigid, sc->rigid + c->nr);
         c->force.assign(3 * std::max(1, c->nr), 0.0);
@@ -1025,6 +1036,16 @@ int sph_read_state(sph_ctx *c, uint32_t mask, const sph_host_view *dst) {
             }
         }
     }
+    if ((mask & SPH_FIELD_DVISC) && dst->dvisc) {
+        if (c->dvisc) {
+            std::vector<float4> d4;
+            if ((rc = d2h(c, d4, c->dvisc, nf))) return rc;
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            scatter3(d4, dst->dvisc);
+        } else {
+            std::fill(dst->dvisc, dst->dvisc + 3 * nf, 0.0f);
+        }
+    }
     if ((mask & SPH_FIELD_RHO) && dst->rho && (rc = read1(c->rho, dst->rho))) return rc;
     if ((mask & SPH_FIELD_ALPHA) && dst->alpha && (rc = read1(c->alpha, dst->alpha))) return rc;
     if ((mask & SPH_FIELD_K) && dst->K && (rc = read1(c->K, dst->K))) return rc;
@@ -1114,6 +1135,11 @@ int sph_write_state(sph_ctx *c, uint32_t mask, const sph_host_view *src) {
     if ((mask & SPH_FIELD_V) && src->v && (rc = write3(src->v, c->v, false))) return rc;
     if ((mask & SPH_FIELD_K) && src->K && (rc = write1(src->K, c->K))) return rc;
     if ((mask & SPH_FIELD_KV) && src->Kv && (rc = write1(src->Kv, c->Kv))) return rc;
+    if ((mask & SPH_FIELD_DVISC) && src->dvisc) {
+        if (!c->dvisc) return fail(c, SPH_ERR_INVALID, "dvisc needs the implicit viscosity model");
+        if (!finite3(src->dvisc, nf)) return fail(c, SPH_ERR_INVALID, "non-finite dvisc");
+        if ((rc = write3(src->dvisc, c->dvisc, false))) return rc;
+    }
     if ((mask & SPH_FIELD_RIGID) && src->rigid) {
         for (int b = 0; b < c->nr; ++b) c->rigid[b] = src->rigid[b];
         if ((rc = upload_poses(c))) return rc;

@@ -94,9 +94,10 @@ hipError_t launch_scatter(const uint32_t* key, const uint32_t* slot, const uint3
                           uint32_t* src, hipStream_t s);
 hipError_t launch_cell_sort(const uint32_t* start, int64_t ncell, uint32_t* src, const int32_t* id,
                             uint32_t* flags, hipStream_t s);
+// dv/dvo (nullable): the implicit-viscosity correction, carried along
 hipError_t launch_gather_fluid(const uint32_t* src, int64_t n, const float4* x, const float4* v, const float* K,
-                               const float* Kv, const int32_t* id, float4* xo, float4* vo, float* Ko, float* Kvo,
-                               int32_t* ido, hipStream_t s);
+                               const float* Kv, const int32_t* id, const float4* dv, float4* xo, float4* vo,
+                               float* Ko, float* Kvo, int32_t* ido, float4* dvo, hipStream_t s);
 hipError_t launch_gather_boundary(const uint32_t* src, int64_t n, const float4* x, const float4* v,
                                   const int32_t* id, float4* xo, float4* vo, int32_t* ido, hipStream_t s);
 
@@ -157,22 +158,29 @@ hipError_t launch_rigid_boundary(int64_t nb, float4* xb, float4* vb, const int32
 // implicit viscosity (Eqs. 16-19): M p = p - dt A p and its block-Jacobi preconditioner
 hipError_t launch_visc_precond(int64_t nf, const float4* x, const float* rho, const uint32_t* nlist,
                                const uint32_t* ncnt, Kern kc, float dt, float mu, float* Pinv, hipStream_t s);
-// go (nullable): skip when *go == 0
-hipError_t launch_visc_matvec(int64_t nf, const float4* x, const float* rho, const float4* p, float4* Mp,
-                              const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float mu,
-                              const int32_t* go, hipStream_t s);
-hipError_t launch_dot(int64_t nf, const float4* a, const float4* b, double* partials, double* out, hipStream_t s);
-// CG set-up from the dots r.z, b.b, r.r of the initial residual
-hipError_t launch_cg_init(CgCtl* ctl, const double* rz, const double* bb, const double* rr, double tol,
-                          int32_t max_iters, HostStatus* host, hipStream_t s);
-// one CG iteration after the mat-vec Ap: alpha = rz/p.Ap; x += alpha p,
-// r -= alpha Ap, z = P r, rz and rr, the stop rule; p = z + beta p
+// M p with rho taken from p.w; go (nullable): skip when *go == 0;
+// partials (nullable): per-workgroup sums of p.(M p), visc_matvec_parts(nf) of them
+int visc_matvec_parts(int64_t nf);
+hipError_t launch_visc_matvec(int64_t nf, const float4* x, const float4* p, float4* Mp, const uint32_t* nlist,
+                              const uint32_t* ncnt, Kern kc, float dt, float mu, const int32_t* go,
+                              double* partials, hipStream_t s);
+// b = v + dt g, x0 = b + w dvisc (w = rho from v.w in both)
+hipError_t launch_cg_start(int64_t nf, const float4* v, const float4* dvisc, float4* b, float4* x0, float dt,
+                           float gx, float gy, float gz, float w, hipStream_t s);
+// dvisc = v* - b
+hipError_t launch_visc_correction(int64_t nf, const float4* vs, const float4* b, float4* dvisc, hipStream_t s);
+// r = b - M x0, z = P r, p = z, and the control block of iteration 0 in *ctl
+// (partials: 3 per workgroup of nf)
+hipError_t launch_cg_setup(int64_t nf, const float4* b, const float4* Mx, const float* Pinv, float4* r, float4* z,
+                           float4* p, double* partials, CgCtl* ctl, double tol, int32_t max_iters,
+                           HostStatus* host, hipStream_t s);
+// one CG iteration after its mat-vec Ap (with the npap partial sums p.Ap):
+// alpha = rz/p.Ap; x += alpha p, r -= alpha Ap, z = P r; the stop rule;
+// p = z + beta p.  Reads *ctl, writes the next control block *next
+// (partials: 2 per workgroup of nf, apart from pap_part)
 hipError_t launch_cg_iteration(int64_t nf, float4* xv, float4* r, float4* z, float4* p, const float4* Ap,
-                               const float* Pinv, CgCtl* ctl, double* partials, HostStatus* host, hipStream_t s);
-hipError_t launch_apply_precond(int64_t nf, const float* Pinv, const float4* r, float4* z, hipStream_t s);
-hipError_t launch_axpy_residual(int64_t nf, const float4* b, const float4* Mx, float4* r, hipStream_t s);
-hipError_t launch_gravity(int64_t nf, const float4* v, float4* out, float dt, float gx, float gy, float gz,
-                          hipStream_t s);
+                               const float* Pinv, const CgCtl* ctl, CgCtl* next, const double* pap_part, int npap,
+                               double* partials, HostStatus* host, hipStream_t s);
 
 // learned warm start: the features pass, the learned stiffness, trace targets
 // learned-warm-start features from per-particle fields (no neighbour pass):

@@ -141,8 +141,9 @@ __global__ void k_cell_sort(const uint32_t* __restrict__ start, int64_t ncell, u
 __global__ void k_gather_fluid(const uint32_t* __restrict__ src, int64_t n, const float4* __restrict__ x,
                                const float4* __restrict__ v, const float* __restrict__ K,
                                const float* __restrict__ Kv, const int32_t* __restrict__ id,
-                               float4* __restrict__ xo, float4* __restrict__ vo, float* __restrict__ Ko,
-                               float* __restrict__ Kvo, int32_t* __restrict__ ido) {
+                               const float4* __restrict__ dv, float4* __restrict__ xo, float4* __restrict__ vo,
+                               float* __restrict__ Ko, float* __restrict__ Kvo, int32_t* __restrict__ ido,
+                               float4* __restrict__ dvo) {
     const int64_t i = particle_index();
     if (i >= n) return;
     const uint32_t s = src[i];
@@ -151,6 +152,7 @@ __global__ void k_gather_fluid(const uint32_t* __restrict__ src, int64_t n, cons
     Ko[i] = K[s];
     Kvo[i] = Kv[s];
     ido[i] = id[s];
+    if (dv != nullptr) dvo[i] = dv[s];
 }
 
 __global__ void k_gather_boundary(const uint32_t* __restrict__ src, int64_t n, const float4* __restrict__ x,
@@ -654,30 +656,46 @@ __global__ void k_rigid_boundary(int64_t nb, float4* __restrict__ xb, float4* __
 
 // ------------------------------------------------------------------ implicit viscosity
 // (A v)_i = sum_j 10 mu m / (rho_i rho_j) (x_ij.(v_i - v_j)) / (|x_ij|^2 + 0.01 h^2) gradW_ij
+// Every CG vector carries rho in its w component (k_cg_start copies it from
+// v.w), so a neighbour costs two gathers, x_j and p_j.  With `partials` the
+// pass also stores the per-workgroup FP64 sums of p.(M p) for the CG step.
+template <int L>
 __global__ void __launch_bounds__(kBlock) k_visc_matvec(
-    int64_t nf, const float4* __restrict__ x, const float* __restrict__ rho, const float4* __restrict__ p,
-    float4* __restrict__ Mp, const uint32_t* __restrict__ nlist, const uint32_t* __restrict__ ncnt, Kern kc,
-    float dt, float mu, const int32_t* __restrict__ go) {
+    int64_t nf, const float4* __restrict__ x, const float4* __restrict__ p, float4* __restrict__ Mp,
+    const uint32_t* __restrict__ nlist, const uint32_t* __restrict__ ncnt, Kern kc, float dt, float mu,
+    const int32_t* __restrict__ go, double* __restrict__ partials) {
     if (go != nullptr && *go == 0) return;
-    const int64_t i = particle_index();
-    if (i >= nf) return;
-    const float4 xi = x[i];
-    const float4 pi = p[i];
-    const float eps2 = 0.01f * kc.h * kc.h;
-    float ax = 0.f, ay = 0.f, az = 0.f;
-    for_each_nbr(nlist, nf, i, ncnt[i], [&](uint32_t j) {
-        const float4 xj = x[j];
-        const float4 pj = p[j];
-        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const float xv = (pi.x - pj.x) * dx + (pi.y - pj.y) * dy + (pi.z - pj.z) * dz;
-        const float c = xv / (rho[j] * (r2 + eps2)) * grad_factor(r2, kc);
-        ax += c * dx; ay += c * dy; az += c * dz;
-    });
-    const float s = dt * 10.0f * mu * kc.m / rho[i];
-    float4 o;
-    o.x = pi.x - s * ax; o.y = pi.y - s * ay; o.z = pi.z - s * az; o.w = 0.f;
-    Mp[i] = o;
+    int q;
+    const int64_t i = group_particle<L>(q);
+    double e = 0.0;
+    if (i < nf) {   // whole groups
+        const float4 xi = x[i];
+        const float4 pi = p[i];
+        const float eps2 = 0.01f * kc.h * kc.h;
+        float ax = 0.f, ay = 0.f, az = 0.f;
+        for_each_nbr_l<L>(nlist, nf, i, q, ncnt[i], [&](uint32_t j) {
+            const float4 xj = x[j];
+            const float4 pj = p[j];
+            const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float xv = (pi.x - pj.x) * dx + (pi.y - pj.y) * dy + (pi.z - pj.z) * dz;
+            const float c = xv / (pj.w * (r2 + eps2)) * grad_factor(r2, kc);
+            ax += c * dx; ay += c * dy; az += c * dz;
+        });
+        ax = group_sum<L>(ax);
+        ay = group_sum<L>(ay);
+        az = group_sum<L>(az);
+        if (q == 0) {
+            const float s = dt * 10.0f * mu * kc.m / pi.w;
+            const float4 o = make_float4(pi.x - s * ax, pi.y - s * ay, pi.z - s * az, pi.w);
+            Mp[i] = o;
+            e = (double)pi.x * o.x + (double)pi.y * o.y + (double)pi.z * o.z;
+        }
+    }
+    if (partials != nullptr) {
+        const double bs = block_sum(e);
+        if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+    }
 }
 
 // Inverse of the 3x3 diagonal block I - dt A_ii = I + dt sum_j c_ij (-F_ij) x_ij x_ij^T.
@@ -724,61 +742,107 @@ __device__ __forceinline__ float4 apply3(const float* P, float4 r) {
     return z;
 }
 
-__global__ void k_apply_precond(int64_t nf, const float* __restrict__ Pinv, const float4* __restrict__ r,
-                                float4* __restrict__ z) {
-    const int64_t i = particle_index();
-    if (i >= nf) return;
-    z[i] = apply3(Pinv + 9 * i, r[i]);
-}
-
-__global__ void k_axpy_residual(int64_t nf, const float4* __restrict__ b, const float4* __restrict__ Mx,
-                                float4* __restrict__ r) {
-    const int64_t i = particle_index();
-    if (i >= nf) return;
-    const float4 bb = b[i], m = Mx[i];
-    r[i] = make_float4(bb.x - m.x, bb.y - m.y, bb.z - m.z, 0.f);
-}
-
-__global__ void k_dot(int64_t nf, const float4* __restrict__ a, const float4* __restrict__ b,
-                      double* __restrict__ partials) {
-    const int64_t i = particle_index();
-    double s = 0.0;
-    if (i < nf) {
-        const float4 u = a[i], w = b[i];
-        s = (double)u.x * (double)w.x + (double)u.y * (double)w.y + (double)u.z * (double)w.z;
-    }
-    const double bs = block_sum(s);
-    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-}
-
-// CG kernels of one iteration; each does nothing once ctl->go is 0.
-__global__ void k_cg_dot_pap(int64_t nf, const float4* __restrict__ p, const float4* __restrict__ Ap,
-                             const CgCtl* ctl, double* __restrict__ partials) {
-    if (ctl->go == 0) return;
-    const int64_t i = particle_index();
-    double s = 0.0;
-    if (i < nf) {
-        const float4 u = p[i], w = Ap[i];
-        s = (double)u.x * (double)w.x + (double)u.y * (double)w.y + (double)u.z * (double)w.z;
-    }
-    const double bs = block_sum(s);
-    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-}
-
-__global__ void k_cg_finish_pap(const double* __restrict__ partials, int nblk, CgCtl* ctl) {
-    if (ctl->go == 0) return;
+// FP64 sum of n partials part[k stride + off] in a fixed order, the same in
+// every workgroup that calls it, returned to every thread of the workgroup.
+__device__ double block_total(const double* __restrict__ part, int n, int stride, int off) {
+    __shared__ double total;
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partials[b];
+    for (int b = threadIdx.x; b < n; b += kBlock) acc += part[(size_t)b * stride + off];
     acc = block_sum(acc);
-    if (threadIdx.x == 0) ctl->alpha = ctl->rz / acc;
+    if (threadIdx.x == 0) total = acc;
+    __syncthreads();
+    const double t = total;
+    __syncthreads();
+    return t;
 }
 
+// CG start value: b = v + dt g and x0 = b + w dvisc, with dvisc the previous
+// step's correction v* - b; both carry rho (v.w) in w.
+__global__ void k_cg_start(int64_t nf, const float4* __restrict__ v, const float4* __restrict__ dvisc,
+                           float4* __restrict__ b, float4* __restrict__ x0, float dt, float gx, float gy, float gz,
+                           float w) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float4 a = v[i];
+    const float4 bb = make_float4(a.x + dt * gx, a.y + dt * gy, a.z + dt * gz, a.w);
+    const float4 d = dvisc[i];
+    b[i] = bb;
+    x0[i] = make_float4(bb.x + w * d.x, bb.y + w * d.y, bb.z + w * d.z, a.w);
+}
+
+// The correction v* - b of the solve just finished (the next step's start).
+__global__ void k_visc_correction(int64_t nf, const float4* __restrict__ vs, const float4* __restrict__ b,
+                                  float4* __restrict__ dvisc) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float4 u = vs[i], bb = b[i];
+    dvisc[i] = make_float4(u.x - bb.x, u.y - bb.y, u.z - bb.z, 0.f);
+}
+
+// Initial residual r = b - M x0, z = P r, p = z (w = rho), and the
+// per-workgroup FP64 sums r.z, b.b, r.r (three per workgroup).
+__global__ void k_cg_setup(int64_t nf, const float4* __restrict__ b, const float4* __restrict__ Mx,
+                           const float* __restrict__ Pinv, float4* __restrict__ r, float4* __restrict__ z,
+                           float4* __restrict__ p, double* __restrict__ partials) {
+    const int64_t i = particle_index();
+    double rz = 0.0, bb2 = 0.0, rr = 0.0;
+    if (i < nf) {
+        const float4 bb = b[i], m = Mx[i];
+        const float4 rv = make_float4(bb.x - m.x, bb.y - m.y, bb.z - m.z, bb.w);
+        float4 zz = apply3(Pinv + 9 * i, rv);
+        zz.w = bb.w;
+        r[i] = rv;
+        z[i] = zz;
+        p[i] = zz;
+        rz = (double)rv.x * zz.x + (double)rv.y * zz.y + (double)rv.z * zz.z;
+        bb2 = (double)bb.x * bb.x + (double)bb.y * bb.y + (double)bb.z * bb.z;
+        rr = (double)rv.x * rv.x + (double)rv.y * rv.y + (double)rv.z * rv.z;
+    }
+    const double s0 = block_sum(rz);
+    const double s1 = block_sum(bb2);
+    const double s2 = block_sum(rr);
+    if (threadIdx.x == 0) {
+        partials[3 * (size_t)blockIdx.x] = s0;
+        partials[3 * (size_t)blockIdx.x + 1] = s1;
+        partials[3 * (size_t)blockIdx.x + 2] = s2;
+    }
+}
+
+// The control block of iteration 0 from the set-up's sums (one workgroup).
+__global__ void k_cg_init(const double* __restrict__ partials, int nblk, CgCtl* ctl, double tol, int32_t max_iters,
+                          HostStatus* host) {
+    const double rz = block_total(partials, nblk, 3, 0);
+    const double bb = block_total(partials, nblk, 3, 1);
+    const double rr = block_total(partials, nblk, 3, 2);
+    if (threadIdx.x == 0) {
+        CgCtl c{};
+        c.rz = rz;
+        c.rr = rr;
+        c.bnorm = sqrt(bb);
+        c.thresh = tol * c.bnorm;
+        c.iters = 0;
+        c.max_iters = max_iters;
+        c.go = (sqrt(c.rr) > c.thresh && 0 < max_iters) ? 1 : 0;
+        *ctl = c;
+        host->cg = c;
+    }
+}
+
+// The kernels of one CG iteration read the control block `ctl` of that
+// iteration; the direction kernel's workgroup 0 writes the next one into the
+// other slot of a pair, so no launch writes a block it reads.  Each does
+// nothing once ctl->go is 0.
+//
+// Update: alpha = rz / p.Ap from the mat-vec's partial sums; x += alpha p,
+// r -= alpha Ap, z = P r (w = rho kept); per-workgroup sums r.z and r.r.
 __global__ void k_cg_update(int64_t nf, float4* __restrict__ xv, float4* __restrict__ r, float4* __restrict__ z,
                             const float4* __restrict__ p, const float4* __restrict__ Ap,
-                            const float* __restrict__ Pinv, const CgCtl* ctl, double* __restrict__ partials) {
+                            const float* __restrict__ Pinv, const CgCtl* ctl, const double* __restrict__ pap_part,
+                            int npap, double* __restrict__ partials) {
     if (ctl->go == 0) return;
+    const double pap = block_total(pap_part, npap, 1, 0);
+    const float a = (float)(ctl->rz / pap);
     const int64_t i = particle_index();
-    const float a = (float)ctl->alpha;
     double rz = 0.0, rr = 0.0;
     if (i < nf) {
         const float4 pp = p[i], ap = Ap[i];
@@ -787,7 +851,8 @@ __global__ void k_cg_update(int64_t nf, float4* __restrict__ xv, float4* __restr
         rv.x -= a * ap.x; rv.y -= a * ap.y; rv.z -= a * ap.z;
         xv[i] = xx;
         r[i] = rv;
-        const float4 zz = apply3(Pinv + 9 * i, rv);
+        float4 zz = apply3(Pinv + 9 * i, rv);
+        zz.w = rv.w;
         z[i] = zz;
         rz = (double)rv.x * zz.x + (double)rv.y * zz.y + (double)rv.z * zz.z;
         rr = (double)rv.x * rv.x + (double)rv.y * rv.y + (double)rv.z * rv.z;
@@ -795,67 +860,39 @@ __global__ void k_cg_update(int64_t nf, float4* __restrict__ xv, float4* __restr
     const double s0 = block_sum(rz);
     const double s1 = block_sum(rr);
     if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = s0;
-        partials[2 * blockIdx.x + 1] = s1;
+        partials[2 * (size_t)blockIdx.x] = s0;
+        partials[2 * (size_t)blockIdx.x + 1] = s1;
     }
 }
 
-// rz_new, rr; count the iteration; beta = rz_new/rz; continue while
-// |r| > tol |b| and fewer than max_iters
-__global__ void k_cg_finish_update(const double* __restrict__ partials, int nblk, CgCtl* ctl, HostStatus* host) {
-    if (ctl->go == 0) return;
-    double a0 = 0.0, a1 = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kBlock) {
-        a0 += partials[2 * (size_t)b];
-        a1 += partials[2 * (size_t)b + 1];
-    }
-    a0 = block_sum(a0);
-    a1 = block_sum(a1);
-    if (threadIdx.x == 0) {
-        CgCtl c = *ctl;
-        c.beta = a0 / c.rz;
-        c.rz = a0;
-        c.rr = a1;
+// Direction: rz_new, rr from the update's sums; count the iteration; go on
+// while |r| > tol |b| and fewer than max_iters; beta = rz_new / rz and
+// p = z + beta p while going on.  Workgroup 0 stores the next control block
+// (a stopped one is carried forward unchanged) and the host status.
+__global__ void k_cg_direction(int64_t nf, float4* __restrict__ p, const float4* __restrict__ z, const CgCtl* ctl,
+                               CgCtl* next, const double* __restrict__ partials, int nblk, HostStatus* host) {
+    CgCtl c = *ctl;
+    if (c.go) {
+        const double rz = block_total(partials, nblk, 2, 0);
+        const double rr = block_total(partials, nblk, 2, 1);
+        c.beta = rz / c.rz;
+        c.rz = rz;
+        c.rr = rr;
         c.iters += 1;
-        c.go = (sqrt(a1) > c.thresh && c.iters < c.max_iters) ? 1 : 0;
-        *ctl = c;
+        c.go = (sqrt(rr) > c.thresh && c.iters < c.max_iters) ? 1 : 0;
+        const int64_t i = particle_index();
+        if (c.go && i < nf) {
+            const float beta = (float)c.beta;
+            const float4 zz = z[i];
+            float4 pp = p[i];
+            pp.x = zz.x + beta * pp.x; pp.y = zz.y + beta * pp.y; pp.z = zz.z + beta * pp.z;
+            p[i] = pp;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *next = c;
         host->cg = c;
     }
-}
-
-// p = z + beta p; runs in an iteration whose update left go at 1 (a
-// converged solve needs no new direction)
-__global__ void k_cg_direction(int64_t nf, float4* __restrict__ p, const float4* __restrict__ z, const CgCtl* ctl) {
-    if (ctl->go == 0) return;
-    const int64_t i = particle_index();
-    if (i >= nf) return;
-    const float beta = (float)ctl->beta;
-    const float4 zz = z[i];
-    float4 pp = p[i];
-    pp.x = zz.x + beta * pp.x; pp.y = zz.y + beta * pp.y; pp.z = zz.z + beta * pp.z;
-    p[i] = pp;
-}
-
-__global__ void k_cg_init(CgCtl* ctl, const double* rz, const double* bb, const double* rr, double tol,
-                          int32_t max_iters, HostStatus* host) {
-    CgCtl c{};
-    c.rz = *rz;
-    c.rr = *rr;
-    c.bnorm = sqrt(*bb);
-    c.thresh = tol * c.bnorm;
-    c.iters = 0;
-    c.max_iters = max_iters;
-    c.go = (sqrt(c.rr) > c.thresh && 0 < max_iters) ? 1 : 0;
-    *ctl = c;
-    host->cg = c;
-}
-
-__global__ void k_gravity(int64_t nf, const float4* __restrict__ v, float4* __restrict__ out, float dt, float gx,
-                          float gy, float gz) {
-    const int64_t i = particle_index();
-    if (i >= nf) return;
-    const float4 a = v[i];
-    out[i] = make_float4(a.x + dt * gx, a.y + dt * gy, a.z + dt * gz, 0.f);
 }
 
 __global__ void k_warm_setup(int64_t nf, float4* __restrict__ x, const float* __restrict__ rho,
@@ -925,10 +962,10 @@ hipError_t launch_cell_sort(const uint32_t* start, int64_t ncell, uint32_t* src,
 }
 
 hipError_t launch_gather_fluid(const uint32_t* src, int64_t n, const float4* x, const float4* v, const float* K,
-                               const float* Kv, const int32_t* id, float4* xo, float4* vo, float* Ko, float* Kvo,
-                               int32_t* ido, hipStream_t s) {
+                               const float* Kv, const int32_t* id, const float4* dv, float4* xo, float4* vo,
+                               float* Ko, float* Kvo, int32_t* ido, float4* dvo, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    LAUNCH(k_gather_fluid, n, src, n, x, v, K, Kv, id, xo, vo, Ko, Kvo, ido);
+    LAUNCH(k_gather_fluid, n, src, n, x, v, K, Kv, id, dv, xo, vo, Ko, Kvo, ido, dvo);
 }
 
 hipError_t launch_gather_boundary(const uint32_t* src, int64_t n, const float4* x, const float4* v, const int32_t* id,
@@ -1085,51 +1122,49 @@ hipError_t launch_visc_precond(int64_t nf, const float4* x, const float* rho, co
     LAUNCH(k_visc_precond, nf, nf, x, rho, nlist, ncnt, kc, dt, mu, Pinv);
 }
 
-hipError_t launch_visc_matvec(int64_t nf, const float4* x, const float* rho, const float4* p, float4* Mp,
-                              const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float mu,
-                              const int32_t* go, hipStream_t s) {
+constexpr int kLanesVisc = 2;
+
+int visc_matvec_parts(int64_t nf) { return (int)grid_blocks(kLanesVisc * nf); }
+
+hipError_t launch_visc_matvec(int64_t nf, const float4* x, const float4* p, float4* Mp, const uint32_t* nlist,
+                              const uint32_t* ncnt, Kern kc, float dt, float mu, const int32_t* go,
+                              double* partials, hipStream_t s) {
     if (nf <= 0) return hipSuccess;
-    LAUNCH(k_visc_matvec, nf, nf, x, rho, p, Mp, nlist, ncnt, kc, dt, mu, go);
+    LAUNCH(k_visc_matvec<kLanesVisc>, kLanesVisc * nf, nf, x, p, Mp, nlist, ncnt, kc, dt, mu, go, partials);
 }
 
-hipError_t launch_dot(int64_t nf, const float4* a, const float4* b, double* partials, double* out, hipStream_t s) {
+hipError_t launch_cg_start(int64_t nf, const float4* v, const float4* dvisc, float4* b, float4* x0, float dt,
+                           float gx, float gy, float gz, float w, hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_cg_start, nf, nf, v, dvisc, b, x0, dt, gx, gy, gz, w);
+}
+
+hipError_t launch_visc_correction(int64_t nf, const float4* vs, const float4* b, float4* dvisc, hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_visc_correction, nf, nf, vs, b, dvisc);
+}
+
+hipError_t launch_cg_setup(int64_t nf, const float4* b, const float4* Mx, const float* Pinv, float4* r, float4* z,
+                           float4* p, double* partials, CgCtl* ctl, double tol, int32_t max_iters,
+                           HostStatus* host, hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
     const uint32_t nblk = grid_blocks(nf);
-    hipLaunchKernelGGL(k_dot, dim3(nblk), dim3(kBlock), 0, s, nf, a, b, partials);
-    hipLaunchKernelGGL(k_finish_f64, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, 1, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_init(CgCtl* ctl, const double* rz, const double* bb, const double* rr, double tol,
-                          int32_t max_iters, HostStatus* host, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(1), 0, s, ctl, rz, bb, rr, tol, max_iters, host);
+    hipLaunchKernelGGL(k_cg_setup, dim3(nblk), dim3(kBlock), 0, s, nf, b, Mx, Pinv, r, z, p, partials);
+    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kBlock), 0, s, (const double*)partials, (int)nblk, ctl, tol,
+                       max_iters, host);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_iteration(int64_t nf, float4* xv, float4* r, float4* z, float4* p, const float4* Ap,
-                               const float* Pinv, CgCtl* ctl, double* partials, HostStatus* host, hipStream_t s) {
+                               const float* Pinv, const CgCtl* ctl, CgCtl* next, const double* pap_part, int npap,
+                               double* partials, HostStatus* host, hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
     const uint32_t nblk = grid_blocks(nf);
-    hipLaunchKernelGGL(k_cg_dot_pap, dim3(nblk), dim3(kBlock), 0, s, nf, p, Ap, ctl, partials);
-    hipLaunchKernelGGL(k_cg_finish_pap, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, ctl);
-    hipLaunchKernelGGL(k_cg_update, dim3(nblk), dim3(kBlock), 0, s, nf, xv, r, z, p, Ap, Pinv, ctl, partials);
-    hipLaunchKernelGGL(k_cg_finish_update, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, ctl, host);
-    hipLaunchKernelGGL(k_cg_direction, dim3(nblk), dim3(kBlock), 0, s, nf, p, z, ctl);
+    hipLaunchKernelGGL(k_cg_update, dim3(nblk), dim3(kBlock), 0, s, nf, xv, r, z, p, Ap, Pinv, ctl, pap_part, npap,
+                       partials);
+    hipLaunchKernelGGL(k_cg_direction, dim3(nblk), dim3(kBlock), 0, s, nf, p, (const float4*)z, ctl, next,
+                       (const double*)partials, (int)nblk, host);
     return hipGetLastError();
-}
-
-hipError_t launch_apply_precond(int64_t nf, const float* Pinv, const float4* r, float4* z, hipStream_t s) {
-    if (nf <= 0) return hipSuccess;
-    LAUNCH(k_apply_precond, nf, nf, Pinv, r, z);
-}
-
-hipError_t launch_axpy_residual(int64_t nf, const float4* b, const float4* Mx, float4* r, hipStream_t s) {
-    if (nf <= 0) return hipSuccess;
-    LAUNCH(k_axpy_residual, nf, nf, b, Mx, r);
-}
-
-hipError_t launch_gravity(int64_t nf, const float4* v, float4* out, float dt, float gx, float gy, float gz,
-                          hipStream_t s) {
-    if (nf <= 0) return hipSuccess;
-    LAUNCH(k_gravity, nf, nf, v, out, dt, gx, gy, gz);
 }
 
 uint32_t reduction_blocks(int64_t n) { return grid_blocks(n); }

@@ -145,6 +145,8 @@ def default_params(r: float, lo, hi, **kw) -> Dict:
         # WCSPH: gamma = 7, k = rho0 c^2 / gamma with a sound speed c of 44 m/s,
         # ten times the ~4.4 m/s a 1 m dam break reaches
         solver=SOLVER_DFSPH, wcsph_k=2.8e5, wcsph_gamma=7.0,
+        # implicit viscosity: start the CG from v~ + 0.5 (v* - v~) of the previous step
+        cg_warm_factor=0.5,
     )
     p.update(kw)
     return p

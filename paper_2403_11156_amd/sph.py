@@ -22,6 +22,7 @@ SPH_ERR_INVALID, SPH_ERR_OOM, SPH_ERR_DEVICE, SPH_ERR_CAPACITY, SPH_ERR_STATE, S
 FIELD_X, FIELD_V, FIELD_RHO, FIELD_ALPHA = 1 << 0, 1 << 1, 1 << 2, 1 << 3
 FIELD_K, FIELD_KV, FIELD_KAPPA, FIELD_ACCEL = 1 << 4, 1 << 5, 1 << 6, 1 << 7
 FIELD_NBR, FIELD_PSI, FIELD_BOUNDARY, FIELD_RIGID = 1 << 8, 1 << 9, 1 << 10, 1 << 11
+FIELD_DVISC = 1 << 12
 
 
 class sph_params(C.Structure):
@@ -38,6 +39,7 @@ class sph_params(C.Structure):
         ("max_neighbors", C.c_int32), ("max_boundary_neighbors", C.c_int32),
         ("auto_rebuild", C.c_int32),
         ("solver", C.c_int32), ("wcsph_k", C.c_double), ("wcsph_gamma", C.c_double),
+        ("cg_warm_factor", C.c_double),
     ]
 
 
@@ -77,6 +79,7 @@ class sph_host_view(C.Structure):
         ("n_fluid_nbrs", C.c_void_p), ("n_boundary_nbrs", C.c_void_p),
         ("psi", C.c_void_p), ("x_boundary", C.c_void_p), ("v_boundary", C.c_void_p),
         ("rigid", C.c_void_p), ("rigid_force", C.c_void_p), ("rigid_torque", C.c_void_p),
+        ("dvisc", C.c_void_p),
     ]
 
 
@@ -198,6 +201,7 @@ def make_params(pd: Dict) -> sph_params:
     p.solver = pd.get("solver", 0)
     p.wcsph_k = pd.get("wcsph_k", 2.8e5)
     p.wcsph_gamma = pd.get("wcsph_gamma", 7.0)
+    p.cg_warm_factor = pd.get("cg_warm_factor", 0.0)
     return p
 
 
@@ -299,7 +303,7 @@ class Simulation:
         out: Dict = {}
         hv = sph_host_view()
         mask = 0
-        spec3 = {"x": FIELD_X, "v": FIELD_V, "accel": FIELD_ACCEL}
+        spec3 = {"x": FIELD_X, "v": FIELD_V, "accel": FIELD_ACCEL, "dvisc": FIELD_DVISC}
         spec1 = {"rho": FIELD_RHO, "alpha": FIELD_ALPHA, "K": FIELD_K, "Kv": FIELD_KV, "kappa": FIELD_KAPPA}
         for f, bit in spec3.items():
             if f in fields:
@@ -338,7 +342,7 @@ class Simulation:
             out["rigid"] = _rigid_dicts(rig, nr)
         return out
 
-    def write(self, x=None, v=None, K=None, Kv=None, xb=None, vb=None, rigid=None):
+    def write(self, x=None, v=None, K=None, Kv=None, xb=None, vb=None, rigid=None, dvisc=None):
         hv = sph_host_view()
         keep = []
         mask = 0
@@ -356,6 +360,7 @@ class Simulation:
         put("v", v, FIELD_V, (self.nf, 3))
         put("K", K, FIELD_K, (self.nf,))
         put("Kv", Kv, FIELD_KV, (self.nf,))
+        put("dvisc", dvisc, FIELD_DVISC, (self.nf, 3))
         put("x_boundary", xb, FIELD_BOUNDARY, (self.nb, 3))
         put("v_boundary", vb, FIELD_BOUNDARY, (self.nb, 3))
         if rigid is not None:

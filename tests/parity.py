@@ -22,7 +22,7 @@ def ratio(gpu, ref, scale=None):
 
 def oracle_state_from_gpu(sim, scene, local):
     """Re-anchor: the oracle's FP32 input state is exactly the GPU's state."""
-    g = sim.read(("x", "v", "K", "Kv", "boundary", "rigid"))
+    g = sim.read(("x", "v", "K", "Kv", "boundary", "rigid", "dvisc"))
     st = O.State.__new__(O.State)
     st.params = dict(sim.params)
     st.x, st.v = g["x"], g["v"]
@@ -31,6 +31,7 @@ def oracle_state_from_gpu(sim, scene, local):
     st.body = np.ascontiguousarray(scene.body_of_boundary, np.int32)
     st.local = local
     st.rigid = g.get("rigid", [])
+    st.dvisc = g["dvisc"]
     return st
 
 

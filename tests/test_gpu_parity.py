@@ -238,3 +238,42 @@ def test_implicit_viscosity_solution_property(sph):
     cond = np.linalg.cond(M)
     err = np.linalg.norm(g["v"].astype(np.float64).ravel() - x_ref.ravel()) / np.linalg.norm(x_ref)
     assert err <= 4 * cond * sc.params["cg_tol"]
+
+
+def test_implicit_viscosity_cg_start_value(sph):
+    # the CG start x0 = v~ + cg_warm_factor (v* - v~ of the previous step):
+    # every step's v is still the solution (pressure off), the carried
+    # correction is v* - v~ of the device's own step, the oracle run from the
+    # re-anchored state (correction included) needs about as many iterations,
+    # and the start saves iterations against x0 = v~ on the same scene
+    def run(factor, steps=10):
+        sc = scenes.small_scene(8, 10, 6, visc_model=scenes.VISC_IMPLICIT, visc=10.0, warm_start=0,
+                                cfl_lambda=0.0, dt_max=1e-3, cg_warm_factor=factor)
+        sc.v_fluid[:] = np.random.default_rng(7).normal(0, 0.2, sc.v_fluid.shape).astype(np.float32)
+        sim = sph.Simulation(sc)
+        sim.set_forced_iters(0, 0)
+        local = O.rigid_local(sc.x_boundary, sc.body_of_boundary, sc.rigid)
+        total = 0
+        for k in range(steps):
+            sim.build_neighbors()
+            state = oracle_state_from_gpu(sim, sc, local)
+            st = sim.step()
+            g = sim.read(("v", "rho", "dvisc"))
+            dt = st["dt"]
+            b = state.v.astype(np.float64) + dt * np.array(sc.params["gravity"])
+            res = O.visc_residual(sc.params, state.x, g["rho"].astype(np.float64), dt, b, g["v"].astype(np.float64))
+            assert res <= 2 * sc.params["cg_tol"], (factor, k, res)
+            assert np.abs(g["dvisc"] - (g["v"] - b)).max() <= 1e-6 * (np.abs(b).max() + 1.0)
+            if factor > 0 and k in (1, 5, 9):
+                ref = O.step(state, forced_div=0, forced_dens=0)
+                print("[cg start] step", k, "gpu", st["cg_iters"], "oracle", ref["cg_iters"], flush=True)
+                assert abs(st["cg_iters"] - ref["cg_iters"]) <= 2 + ref["cg_iters"] // 5
+            if k > 0:
+                total += st["cg_iters"]
+        sim.close()
+        return total
+
+    warm = run(0.5)
+    cold = run(0.0)
+    print("[cg start] iterations over 9 steps: start 0.5", warm, "x0 = v~", cold, flush=True)
+    assert warm < cold
