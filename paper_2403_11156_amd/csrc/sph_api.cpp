@@ -462,10 +462,11 @@ hipError_t visc_matvec(sph_ctx *c, const float4 *p, float4 *Mp, float dt, float 
     return sph::launch_visc_matvec(c->nf, c->x, p, Mp, c->nlist, c->ncnt, c->kc, dt, mu, go, partials, c->stream);
 }
 
-// WCSPH pressure (Sec. 3.4.1): kappa = p/rho from the equation of state (with
-// the mean compression of rho as the reported error), then one pressure pass
-// that accumulates kappa into K and records it as the last kappa.
-int wcsph_pressure(sph_ctx *c, float dt, double *err) {
+// WCSPH equation of state (Sec. 3.4.1): kappa = p/rho, x.w = kappa/rho, K = 0,
+// and the mean compression of rho as the reported error (read by the host
+// after its next synchronisation); the pressure pass follows, on its own or
+// inside the non-pressure pass.
+int wcsph_eos(sph_ctx *c) {
     hipStream_t s = c->stream;
     int nparts = 0;
     {
@@ -478,10 +479,6 @@ int wcsph_pressure(sph_ctx *c, float dt, double *err) {
     init.eta = c->P.eta_density;
     init.forced = 0;   // no iterations: the finish only records the error
     HIP_TRY(c, sph::launch_solve_finish(c->red_part, nparts, c->ctl, true, init, c->hs_dev, s));
-    int rc = pressure_pass(c, c->K, c->kappa_last, dt, nullptr);
-    if (rc) return rc;
-    HIP_TRY(c, hipStreamSynchronize(s));
-    *err = c->hs->solve.err;
     return SPH_OK;
 }
 
@@ -609,58 +606,71 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         if (rc) return rc;
     }
 
-    // 4. non-pressure accelerations; density warm-start set-up
+    // 4. non-pressure accelerations and the density warm start (or WCSPH's
+    //    equation of state).  The warm start's stiffness is set up first: the
+    //    previous stiffness, or the MLP's prediction from per-particle
+    //    features (density, the divergence left by the divergence-free solve,
+    //    neighbour count, previous stiffness, alpha), which also feed the
+    //    training trace.  With explicit viscosity one neighbour pass then
+    //    applies both v* and that stiffness's pressure.
     int32_t cg_it = 0;
     double cg_res = 0.0;
     const float gx = (float)c->P.gravity[0], gy = (float)c->P.gravity[1], gz = (float)c->P.gravity[2];
-    const bool setup_in_pass = ppe && !(learned || tracing);
-    if (c->P.visc_model == SPH_VISC_IMPLICIT) {
+    const bool implicit = c->P.visc_model == SPH_VISC_IMPLICIT;
+    const bool wcsph = c->P.solver == SPH_SOLVER_WCSPH;
+    auto warm_setup = [&]() -> int {   // kappa = K0, K = 0, x.w = K0 / rho
+        if (learned || tracing) {
+            const float alpha_ref = (float)(2.35376 * 4.0 * c->P.r * c->P.r / c->P.rho0);
+            float *feat = tracing ? c->trace_feat + 5 * c->trace_rows : c->feat;
+            {
+                ProfScope ps(c, "warm_features", 28.0 * nf + 20.0 * nf);
+                HIP_TRY(c, sph::launch_features(nf, c->rho, c->alpha, c->K, c->ncnt, c->bcnt, c->dbuf, c->kc, dt,
+                                                alpha_ref, feat, s));
+            }
+            if (learned) {
+                {
+                    ProfScope ps(c, "mlp", 24.0 * nf);
+                    HIP_TRY(c, sph::launch_mlp_forward(c->mlp->P, feat, nf, c->ybuf, s));
+                }
+                HIP_TRY(c, sph::launch_warm_learned(nf, c->x, c->rho, c->alpha, c->ybuf, c->K, c->kappa, dt,
+                                                    (float)c->P.rho0, s));
+                return SPH_OK;
+            }
+        }
+        HIP_TRY(c, sph::launch_warm_setup(nf, c->x, c->rho, c->K, c->kappa, wf, s));
+        return SPH_OK;
+    };
+    if (implicit) {
         rc = implicit_viscosity(c, dt, &cg_it, &cg_res);
         if (rc) return rc;
-        if (setup_in_pass) HIP_TRY(c, sph::launch_warm_setup(nf, c->x, c->rho, c->K, c->kappa, wf, s));
+        if (ppe && (rc = warm_setup())) return rc;
+        if (ppe && warm && (rc = pressure_pass(c, c->K, nullptr, dt, nullptr))) return rc;
+        if (wcsph) {
+            if ((rc = wcsph_eos(c))) return rc;
+            if ((rc = pressure_pass(c, c->K, c->kappa_last, dt, nullptr))) return rc;
+        }
     } else {
-        ProfScope ps(c, "xsph", 72.0 * nf + fluid_list_bytes(c));
+        // the ZERO start only clears K and kappa, inside the pass
+        const bool setup_in_pass = ppe && !warm && !(learned || tracing);
+        if (ppe && !setup_in_pass && (rc = warm_setup())) return rc;
+        if (wcsph && (rc = wcsph_eos(c))) return rc;
+        const bool press = (ppe && warm) || wcsph;
+        ProfScope ps(c, "xsph", 72.0 * nf + (press ? 16.0 * nf + list_bytes(c) : fluid_list_bytes(c)));
         HIP_TRY(c, sph::launch_nonpressure(c->P.visc_model, nf, c->x, c->v, c->v2, c->rho, c->nlist, c->ncnt,
                                            c->kc, dt, gx, gy, gz, (float)c->P.visc, c->K, c->kappa, wf,
-                                           setup_in_pass, s));
+                                           setup_in_pass, press, c->xb, c->blist, c->bcnt,
+                                           wcsph ? c->kappa_last : nullptr, s));
         std::swap(c->v, c->v2);
     }
-    // 5. warm start of the density solve: the previous stiffness, or the MLP's
-    //    prediction from per-particle features (density, the divergence left
-    //    by the divergence-free solve, neighbour count, previous stiffness,
-    //    alpha); the features also feed the training trace
-    if (dfsph && !setup_in_pass) {
-        const float alpha_ref = (float)(2.35376 * 4.0 * c->P.r * c->P.r / c->P.rho0);
-        float *feat = tracing ? c->trace_feat + 5 * c->trace_rows : c->feat;
-        {
-            ProfScope ps(c, "warm_features", 28.0 * nf + 20.0 * nf);
-            HIP_TRY(c, sph::launch_features(nf, c->rho, c->alpha, c->K, c->ncnt, c->bcnt, c->dbuf, c->kc, dt, alpha_ref,
-                                            feat, s));
-        }
-        if (learned) {
-            {
-                ProfScope ps(c, "mlp", 24.0 * nf);
-                HIP_TRY(c, sph::launch_mlp_forward(c->mlp->P, feat, nf, c->ybuf, s));
-            }
-            HIP_TRY(c, sph::launch_warm_learned(nf, c->x, c->rho, c->alpha, c->ybuf, c->K, c->kappa, dt,
-                                                (float)c->P.rho0, s));
-        } else {
-            HIP_TRY(c, sph::launch_warm_setup(nf, c->x, c->rho, c->K, c->kappa, wf, s));
-        }
-    }
     if (ppe) {
-        if (warm) {
-            rc = pressure_pass(c, c->K, nullptr, dt, nullptr);
-            if (rc) return rc;
-        }
         HIP_TRY(c, sph::launch_fill_f32(c->kappa_last, nf, 0.0f, s));
         // 6. constant-density solve
         rc = jacobi_solve(c, 1, dt, c->K, c->kappa_last, c->forced_dens, c->P.eta_density, &id, &ed);
         if (rc) return rc;
     } else {
-        // 6w. WCSPH: equation of state, then one pressure pass on v*
-        rc = wcsph_pressure(c, dt, &ed);
-        if (rc) return rc;
+        // 6w. WCSPH: the error the equation-of-state pass recorded
+        HIP_TRY(c, hipStreamSynchronize(s));
+        ed = c->hs->solve.err;
     }
 
     if (tracing) {

@@ -140,11 +140,14 @@ hipError_t launch_eos(int64_t nf, float4* x, const float* rho, float* kappa, flo
 hipError_t launch_solve_finish(const double* partials, int nblk, SolveCtl* ctl, bool first, const SolveCtl& init,
                                HostStatus* host, hipStream_t s);
 // non-pressure: v* = v + dt g + viscosity; also sets up the density warm start
-// (kappa = warm_factor K, K = 0, x.w = kappa / rho).
+// (kappa = warm_factor K, K = 0, x.w = kappa / rho) when setup_warm and not press.
+// press: also the pressure pass of the stiffness already in x.w / kappa
+// (v* -= dt a_p, K += kappa, kappa_last = kappa when non-null).
 hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v, float4* vout, const float* rho,
                               const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float gx, float gy,
                               float gz, float visc, float* K, float* kappa, float warm_factor, bool setup_warm,
-                              hipStream_t s);
+                              bool press, const float4* xb, const uint32_t* blist, const uint32_t* bcnt,
+                              float* kappa_last, hipStream_t s);
 hipError_t launch_warm_setup(int64_t nf, float4* x, const float* rho, float* K, float* kappa, float warm_factor,
                              hipStream_t s);
 hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, hipStream_t s);

@@ -453,36 +453,65 @@ __global__ void __launch_bounds__(kBlock) k_predict(
 // Non-pressure accelerations (Algorithm 1, first lines): v* = v + dt g plus
 // XSPH (model 1) or the explicit Laplacian of Eq. (15) (model 2); and the
 // set-up of the density warm start (kappa = warm_factor K, K = 0, x.w = kappa/rho).
-template <int MODEL, int L>
+// PRESS: the same pass also applies the pressure of the stiffness kappa/rho
+// already in x.w (the density solve's warm start, or WCSPH's equation of
+// state), as k_pressure_update would right after it: v* -= dt (Eq. 7 with the
+// Eq. 13 boundary term), K += kappa, kappa_last = kappa.  Both sums read the
+// step's v and x, so one neighbour walk serves them.
+template <int MODEL, int L, bool PRESS>
 __global__ void __launch_bounds__(kBlock) k_nonpressure(
     int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, float4* __restrict__ vout,
     const float* __restrict__ rho, const uint32_t* __restrict__ nlist, const uint32_t* __restrict__ ncnt,
     Kern kc, float dt, float gx, float gy, float gz, float visc, float* __restrict__ K, float* __restrict__ kappa,
-    float warm_factor, bool setup_warm) {
+    float warm_factor, bool setup_warm, const float4* __restrict__ xb, const uint32_t* __restrict__ blist,
+    const uint32_t* __restrict__ bcnt, float* __restrict__ kappa_last) {
     int q;
     const int64_t i = group_particle<L>(q);
     if (i >= nf) return;
     const float4 xi = x[i];
     const float4 vi = v[i];
+    const float kri = xi.w;   // kappa/rho (PRESS)
     float ax = 0.f, ay = 0.f, az = 0.f;
-    if (MODEL == 1 || MODEL == 2) {
+    float px = 0.f, py = 0.f, pz = 0.f;
+    if (MODEL == 1 || MODEL == 2 || PRESS) {
         const float eps2 = 0.01f * kc.h * kc.h;
         for_each_nbr_l<L>(nlist, nf, i, q, ncnt[i], [&](uint32_t j) {
             const float4 xj = x[j];
-            const float4 vj = v[j];
-            const float mj = kc.m / vj.w;   // v.w = rho (density pass)
             const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
-            if (MODEL == 1) {
-                const float c = mj * kernel_W(r2, kc);
-                ax += c * (vj.x - vi.x); ay += c * (vj.y - vi.y); az += c * (vj.z - vi.z);
-            } else {
-                const float vx = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
-                const float c = mj * vx / (r2 + eps2) * grad_factor(r2, kc);
-                ax += c * dx; ay += c * dy; az += c * dz;
+            if (MODEL == 1 || MODEL == 2) {
+                const float4 vj = v[j];
+                const float mj = kc.m / vj.w;   // v.w = rho (density pass)
+                if (MODEL == 1) {
+                    const float c = mj * kernel_W(r2, kc);
+                    ax += c * (vj.x - vi.x); ay += c * (vj.y - vi.y); az += c * (vj.z - vi.z);
+                } else {
+                    const float vx = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
+                    const float c = mj * vx / (r2 + eps2) * grad_factor(r2, kc);
+                    ax += c * dx; ay += c * dy; az += c * dz;
+                }
+            }
+            if (PRESS) {
+                const float c = (kri + xj.w) * grad_factor(r2, kc);
+                px += c * dx; py += c * dy; pz += c * dz;
             }
         });
-        ax = group_sum<L>(ax); ay = group_sum<L>(ay); az = group_sum<L>(az);
+        if (MODEL == 1 || MODEL == 2) {
+            ax = group_sum<L>(ax); ay = group_sum<L>(ay); az = group_sum<L>(az);
+        }
+    }
+    if (PRESS) {
+        float bx = 0.f, by = 0.f, bz = 0.f;
+        for_each_nbr_l<L>(blist, nf, i, q, bcnt[i], [&](uint32_t kk) {
+            const float4 xk = xb[kk];
+            const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float c = xk.w * kri * grad_factor(r2, kc);
+            bx += c * dx; by += c * dy; bz += c * dz;
+        });
+        px = group_sum<L>(px) * kc.m + group_sum<L>(bx);
+        py = group_sum<L>(py) * kc.m + group_sum<L>(by);
+        pz = group_sum<L>(pz) * kc.m + group_sum<L>(bz);
     }
     if (q != 0) return;
     float s = 0.f;
@@ -493,8 +522,14 @@ __global__ void __launch_bounds__(kBlock) k_nonpressure(
     o.y = vi.y + dt * gy + s * ay;
     o.z = vi.z + dt * gz + s * az;
     o.w = 0.f;
+    if (PRESS) {
+        o.x -= dt * px; o.y -= dt * py; o.z -= dt * pz;
+        const float ki = kappa[i];
+        K[i] += ki;
+        if (kappa_last) kappa_last[i] = ki;
+    }
     vout[i] = o;
-    if (setup_warm) {
+    if (!PRESS && setup_warm) {
         const float k0 = warm_factor * K[i];
         kappa[i] = k0;
         K[i] = 0.0f;
@@ -1052,22 +1087,26 @@ hipError_t launch_solve_finish(const double* partials, int nblk, SolveCtl* ctl, 
 hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v, float4* vout, const float* rho,
                               const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float gx, float gy,
                               float gz, float visc, float* K, float* kappa, float warm_factor, bool setup_warm,
-                              hipStream_t s) {
+                              bool press, const float4* xb, const uint32_t* blist, const uint32_t* bcnt,
+                              float* kappa_last, hipStream_t s) {
     if (nf <= 0) return hipSuccess;
-    if (model == 1)
-        {
-        hipLaunchKernelGGL((k_nonpressure<1, kLanesXsph>), dim3(grid_blocks(kLanesXsph * nf)), dim3(kBlock), 0, s, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa, warm_factor, setup_warm);
-        return hipGetLastError();
+    const dim3 grid(grid_blocks(kLanesXsph * nf)), block(kBlock);
+#define NONPRESSURE(M, P)                                                                                       \
+    hipLaunchKernelGGL((k_nonpressure<M, kLanesXsph, P>), grid, block, 0, s, nf, x, v, vout, rho, nlist, ncnt, kc, \
+                       dt, gx, gy, gz, visc, K, kappa, warm_factor, setup_warm, xb, blist, bcnt, kappa_last)
+    if (model == 1) {
+        if (press) NONPRESSURE(1, true); else NONPRESSURE(1, false);
+    } else if (model == 2) {
+        if (press) NONPRESSURE(2, true); else NONPRESSURE(2, false);
+    } else if (press) {
+        NONPRESSURE(0, true);
+    } else {   // gravity only: no neighbour walk, one lane per particle
+        hipLaunchKernelGGL((k_nonpressure<0, 1, false>), dim3(grid_blocks(nf)), block, 0, s, nf, x, v, vout, rho,
+                           nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa, warm_factor, setup_warm, xb, blist, bcnt,
+                           kappa_last);
     }
-    if (model == 2)
-        {
-        hipLaunchKernelGGL((k_nonpressure<2, kLanesXsph>), dim3(grid_blocks(kLanesXsph * nf)), dim3(kBlock), 0, s, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa, warm_factor, setup_warm);
-        return hipGetLastError();
-    }
-    {
-        hipLaunchKernelGGL((k_nonpressure<0, 1>), dim3(grid_blocks(nf)), dim3(kBlock), 0, s, nf, x, v, vout, rho, nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa, warm_factor, setup_warm);
-        return hipGetLastError();
-    }
+#undef NONPRESSURE
+    return hipGetLastError();
 }
 
 hipError_t launch_features(int64_t nf, const float* rho, const float* alpha, const float* K, const uint32_t* ncnt,
