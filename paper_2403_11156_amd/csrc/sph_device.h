@@ -230,34 +230,39 @@ __global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk
 
 
 // Append the candidates c in [b, e) (ascending) with c != skip and the FP32
-// predicate d^2 < h^2 to particle i's list: entries gather in buf and go out
-// as whole 16-byte chunks (list_flush stores the last, partial one);
-// candidates are loaded four at a time ahead of the tests.
+// predicate d^2 < h^2 to particle i's list.  Accepted entries shift into buf
+// (oldest in buf.x) and go out as whole 16-byte chunks; list_flush stores the
+// last, partial one.  The body has no branch but the chunk store, so the four
+// candidates' loads issue ahead of the tests.  chunk points at the particle's
+// next chunk (list chunk (cnt/4) of particle i) and steps by nf chunks per
+// store.  cnt counts every neighbour, entries past cap are dropped (the
+// caller flags the overflow).
 __device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, uint32_t b, uint32_t e, float4 xi,
-                                                int64_t i, int64_t skip, float h2, uint32_t* __restrict__ list,
-                                                int64_t nf, int32_t cap, uint32_t& cnt, uint4& buf) {
+                                                uint32_t skip, float h2, uint4*& chunk, int64_t nf, int32_t cap,
+                                                uint32_t& cnt, uint4& buf) {
     auto take = [&](uint32_t c, float4 p) {
-        if ((int64_t)c != skip && dist2_exact(xi, p) < h2) {
-            if (cnt < (uint32_t)cap) {
-                const uint32_t s = cnt & 3u;
-                buf.x = s == 0u ? c : buf.x;
-                buf.y = s == 1u ? c : buf.y;
-                buf.z = s == 2u ? c : buf.z;
-                buf.w = s == 3u ? c : buf.w;
-                if (s == 3u) reinterpret_cast<uint4*>(list)[(int64_t)(cnt >> 2) * nf + i] = buf;
-            }
-            ++cnt;
+        const bool nb = (c != skip) & (dist2_exact(xi, p) < h2);
+        const bool t = nb & (cnt < (uint32_t)cap);
+        buf.x = t ? buf.y : buf.x;
+        buf.y = t ? buf.z : buf.y;
+        buf.z = t ? buf.w : buf.z;
+        buf.w = t ? c : buf.w;
+        if (t & ((cnt & 3u) == 3u)) {
+            *chunk = buf;
+            chunk += nf;
         }
+        cnt += nb ? 1u : 0u;
     };
     uint32_t c = b;
-    for (; c + 4 <= e; c += 4) {
-        const float4 p0 = pos[c], p1 = pos[c + 1], p2 = pos[c + 2], p3 = pos[c + 3];
+    const float4* q = pos + b;
+    for (; c + 4 <= e; c += 4, q += 4) {
+        const float4 p0 = q[0], p1 = q[1], p2 = q[2], p3 = q[3];
         take(c, p0);
         take(c + 1, p1);
         take(c + 2, p2);
         take(c + 3, p3);
     }
-    for (; c < e; ++c) take(c, pos[c]);
+    for (; c < e; ++c, ++q) take(c, *q);
 }
 
 // Neighbour passes run L (1, 2, 4 or 8) lanes per particle: lane q of the group
@@ -317,11 +322,16 @@ __device__ __forceinline__ void for_each_nbr_l(const uint32_t* __restrict__ list
     for (; k < n; k += L) f(list[(((int64_t)(k >> 2) * nf + i) << 2) + (k & 3u)]);
 }
 
-// Store the partial last chunk of a list filled by scan_candidates.
-__device__ __forceinline__ void list_flush(uint32_t* __restrict__ list, int64_t nf, int64_t i, int32_t cap,
-                                           uint32_t cnt, uint4 buf) {
-    const uint32_t n = min(cnt, (uint32_t)cap);
-    if (n & 3u) reinterpret_cast<uint4*>(list)[(int64_t)(n >> 2) * nf + i] = buf;
+// Store the partial last chunk of a list filled by scan_candidates: its k
+// entries sit in the last k slots of buf.
+__device__ __forceinline__ void list_flush(uint4* chunk, int32_t cap, uint32_t cnt, uint4 buf) {
+    const uint32_t k = min(cnt, (uint32_t)cap) & 3u;
+    if (k == 0u) return;
+    uint4 o = buf;
+    if (k == 1u) o = make_uint4(buf.w, 0u, 0u, 0u);
+    if (k == 2u) o = make_uint4(buf.z, buf.w, 0u, 0u);
+    if (k == 3u) o = make_uint4(buf.y, buf.z, buf.w, 0u);
+    *chunk = o;
 }
 
 }  // namespace

@@ -168,7 +168,8 @@ __global__ void k_gather_boundary(const uint32_t* __restrict__ src, int64_t n, c
 
 // ------------------------------------------------------------------ neighbour lists
 // Walk the 27-cell stencil (dz, dy outer; the contiguous cx-1..cx+1 run of
-// sorted particles inner), which yields ascending sorted indices.
+// sorted particles inner), which yields ascending sorted indices; fluid
+// rows first, then boundary rows.
 __global__ void __launch_bounds__(kBlock) k_nbr_build(
     const float4* __restrict__ x, int64_t nf, const float4* __restrict__ xb, const uint32_t* __restrict__ start_f,
     const uint32_t* __restrict__ start_b, Grid g, uint32_t* __restrict__ nlist, uint32_t* __restrict__ ncnt,
@@ -184,21 +185,29 @@ __global__ void __launch_bounds__(kBlock) k_nbr_build(
         const int32_t x0 = cx > 0 ? cx - 1 : 0, x1 = cx < g.n[0] - 1 ? cx + 1 : g.n[0] - 1;
         uint32_t nfc = 0, nbc = 0;
         uint4 fbuf = make_uint4(0u, 0u, 0u, 0u), bbuf = make_uint4(0u, 0u, 0u, 0u);
-        for (int32_t dz = -1; dz <= 1; ++dz) {
-            const int32_t z = cz + dz;
-            if (z < 0 || z >= g.n[2]) continue;
-            for (int32_t dy = -1; dy <= 1; ++dy) {
-                const int32_t y = cy + dy;
-                if (y < 0 || y >= g.n[1]) continue;
-                const int64_t row = (int64_t)g.n[0] * (y + (int64_t)g.n[1] * z);
-                const uint32_t b = start_f[row + x0], e = start_f[row + x1 + 1];
-                scan_candidates(x, b, e, xi, i, i, g.h2, nlist, nf, capf, nfc, fbuf);
-                const uint32_t bb = start_b[row + x0], be = start_b[row + x1 + 1];
-                scan_candidates(xb, bb, be, xi, i, -1, g.h2, blist, nf, capb, nbc, bbuf);
-            }
+        uint4* fchunk = reinterpret_cast<uint4*>(nlist) + i;   // chunk 0 of particle i
+        uint4* bchunk = reinterpret_cast<uint4*>(blist) + i;
+        // the nine rows' candidate ranges, all loads issued before the scans
+        // (a row outside the grid reads row 0 and is made empty)
+        uint32_t fb[9], fe[9], bb[9], be[9];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            const int32_t z = cz + r / 3 - 1, y = cy + r % 3 - 1;
+            const bool ok = z >= 0 && z < g.n[2] && y >= 0 && y < g.n[1];
+            const int64_t row = ok ? (int64_t)g.n[0] * (y + (int64_t)g.n[1] * z) : 0;
+            fb[r] = start_f[row + x0];
+            fe[r] = start_f[row + x1 + 1];
+            bb[r] = start_b[row + x0];
+            be[r] = start_b[row + x1 + 1];
+            if (!ok) fe[r] = fb[r], be[r] = bb[r];
         }
-        list_flush(nlist, nf, i, capf, nfc, fbuf);
-        list_flush(blist, nf, i, capb, nbc, bbuf);
+#pragma unroll
+        for (int r = 0; r < 9; ++r) scan_candidates(x, fb[r], fe[r], xi, (uint32_t)i, g.h2, fchunk, nf, capf, nfc, fbuf);
+#pragma unroll
+        for (int r = 0; r < 9; ++r)
+            scan_candidates(xb, bb[r], be[r], xi, 0xffffffffu, g.h2, bchunk, nf, capb, nbc, bbuf);
+        list_flush(fchunk, capf, nfc, fbuf);
+        list_flush(bchunk, capb, nbc, bbuf);
         // stored counts never exceed the capacity, so readers stay in bounds
         ncnt[i] = min(nfc, (uint32_t)capf);
         bcnt[i] = min(nbc, (uint32_t)capb);
