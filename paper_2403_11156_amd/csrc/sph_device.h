@@ -232,16 +232,18 @@ __global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk
 // Append the candidates c in [b, e) (ascending) with c != skip and the FP32
 // predicate d^2 < h^2 to particle i's list.  Accepted entries shift into buf
 // (oldest in buf.x) and go out as whole 16-byte chunks; list_flush stores the
-// last, partial one.  The body has no branch but the chunk store, so the four
-// candidates' loads issue ahead of the tests.  chunk points at the particle's
-// next chunk (list chunk (cnt/4) of particle i) and steps by nf chunks per
-// store.  cnt counts every neighbour, entries past cap are dropped (the
-// caller flags the overflow).
+// last, partial one.  The body has no branch but the chunk store, so four
+// candidates' loads (one to three for the tail) issue ahead of the tests.
+// chunk points at the particle's next chunk (list chunk cnt/4 of particle i)
+// and steps by nf chunks per store.  cnt counts every neighbour, entries past
+// cap are dropped (the caller flags the overflow).  SKIP: the range may hold
+// the particle itself.
+template <bool SKIP>
 __device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, uint32_t b, uint32_t e, float4 xi,
                                                 uint32_t skip, float h2, uint4*& chunk, int64_t nf, int32_t cap,
                                                 uint32_t& cnt, uint4& buf) {
-    auto take = [&](uint32_t c, float4 p) {
-        const bool nb = (c != skip) & (dist2_exact(xi, p) < h2);
+    auto take = [&](uint32_t c, float4 p, bool valid = true) {
+        const bool nb = valid & (!SKIP || c != skip) & (dist2_exact(xi, p) < h2);
         const bool t = nb & (cnt < (uint32_t)cap);
         buf.x = t ? buf.y : buf.x;
         buf.y = t ? buf.z : buf.y;
@@ -262,7 +264,13 @@ __device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, 
         take(c + 2, p2);
         take(c + 3, p3);
     }
-    for (; c < e; ++c, ++q) take(c, *q);
+    if (c < e) {   // one to three left: load them together (repeats of the last one stay in range)
+        const uint32_t n = e - c;
+        const float4 p0 = q[0], p1 = q[n > 1u ? 1 : 0], p2 = q[n > 2u ? 2 : 0];
+        take(c, p0);
+        take(c + 1, p1, n > 1u);
+        take(c + 2, p2, n > 2u);
+    }
 }
 
 // Neighbour passes run L (1, 2, 4 or 8) lanes per particle: lane q of the group

@@ -201,11 +201,17 @@ __global__ void __launch_bounds__(kBlock) k_nbr_build(
             be[r] = start_b[row + x1 + 1];
             if (!ok) fe[r] = fb[r], be[r] = bb[r];
         }
+        // only the middle row (dy = dz = 0) holds the particle itself
 #pragma unroll
-        for (int r = 0; r < 9; ++r) scan_candidates(x, fb[r], fe[r], xi, (uint32_t)i, g.h2, fchunk, nf, capf, nfc, fbuf);
+        for (int r = 0; r < 9; ++r) {
+            if (r == 4)
+                scan_candidates<true>(x, fb[r], fe[r], xi, (uint32_t)i, g.h2, fchunk, nf, capf, nfc, fbuf);
+            else
+                scan_candidates<false>(x, fb[r], fe[r], xi, 0u, g.h2, fchunk, nf, capf, nfc, fbuf);
+        }
 #pragma unroll
         for (int r = 0; r < 9; ++r)
-            scan_candidates(xb, bb[r], be[r], xi, 0xffffffffu, g.h2, bchunk, nf, capb, nbc, bbuf);
+            scan_candidates<false>(xb, bb[r], be[r], xi, 0u, g.h2, bchunk, nf, capb, nbc, bbuf);
         list_flush(fchunk, capf, nfc, fbuf);
         list_flush(bchunk, capb, nbc, bbuf);
         // stored counts never exceed the capacity, so readers stay in bounds
@@ -954,6 +960,7 @@ __global__ void k_warm_setup(int64_t nf, float4* __restrict__ x, const float* __
 // ================================================================== launchers
 // lanes per particle of the neighbour sums (measured at 1.23M particles)
 constexpr int kLanesDensity = 2, kLanesPressure = 2, kLanesPredict = 2, kLanesXsph = 4;
+constexpr int kLanesXsphPress = 2;   // the non-pressure pass that also applies a pressure
 
 #define LAUNCH(kern, n, ...)                                                        \
     do {                                                                            \
@@ -1099,10 +1106,12 @@ hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v,
                               bool press, const float4* xb, const uint32_t* blist, const uint32_t* bcnt,
                               float* kappa_last, hipStream_t s) {
     if (nf <= 0) return hipSuccess;
-    const dim3 grid(grid_blocks(kLanesXsph * nf)), block(kBlock);
-#define NONPRESSURE(M, P)                                                                                       \
-    hipLaunchKernelGGL((k_nonpressure<M, kLanesXsph, P>), grid, block, 0, s, nf, x, v, vout, rho, nlist, ncnt, kc, \
-                       dt, gx, gy, gz, visc, K, kappa, warm_factor, setup_warm, xb, blist, bcnt, kappa_last)
+    const dim3 block(kBlock);
+#define NONPRESSURE(M, P)                                                                                         \
+    hipLaunchKernelGGL((k_nonpressure<M, P ? kLanesXsphPress : kLanesXsph, P>),                                   \
+                       dim3(grid_blocks((P ? kLanesXsphPress : kLanesXsph) * nf)), block, 0, s, nf, x, v, vout, rho, \
+                       nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa, warm_factor, setup_warm, xb, blist, bcnt,    \
+                       kappa_last)
     if (model == 1) {
         if (press) NONPRESSURE(1, true); else NONPRESSURE(1, false);
     } else if (model == 2) {
