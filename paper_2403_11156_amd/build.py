@@ -18,6 +18,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]
+# per source: the MLP keeps its matrix-core accumulators in ordinary VGPRs
+# (gfx950 MFMA reads and writes them directly), sparing the copies out of AGPRs
+EXTRA = {"sph_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def build(verbose: bool = False) -> str:
@@ -28,7 +31,7 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(tmpdir, src + ".o")
-        cmd = [HIPCC, *FLAGS, "-c", path, "-o", obj]
+        cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, stderr=subprocess.PIPE if not verbose else None, text=True)

@@ -119,6 +119,7 @@ struct sph_ctx {
 struct sph_mlp {
     hipStream_t stream = nullptr;
     float *P = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *part = nullptr;
+    uint32_t *packed = nullptr;   // inference operands prepared from P (after every change of P)
     double *loss_part = nullptr, *loss = nullptr;
     int64_t step = 0;
     bool finite = true;
@@ -630,7 +631,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
             if (learned) {
                 {
                     ProfScope ps(c, "mlp", 24.0 * nf);
-                    HIP_TRY(c, sph::launch_mlp_forward(c->mlp->P, feat, nf, c->ybuf, s));
+                    HIP_TRY(c, sph::launch_mlp_forward(c->mlp->packed, feat, nf, c->ybuf, s));
                 }
                 HIP_TRY(c, sph::launch_warm_learned(nf, c->x, c->rho, c->alpha, c->ybuf, c->K, c->kappa, dt,
                                                     (float)c->P.rho0, s));
@@ -1248,7 +1249,8 @@ int sph_mlp_create(const float *params, void *hip_stream, sph_mlp **out) {
               hipMalloc(&m->v, sizeof(float) * np) == hipSuccess && hipMalloc(&m->grad, sizeof(float) * np) == hipSuccess &&
               hipMalloc(&m->part, sizeof(float) * (size_t)np * nb) == hipSuccess &&
               hipMalloc(&m->loss_part, sizeof(double) * nb) == hipSuccess &&
-              hipMalloc(&m->loss, sizeof(double) * 2) == hipSuccess;
+              hipMalloc(&m->loss, sizeof(double) * 2) == hipSuccess &&
+              hipMalloc(&m->packed, sizeof(uint32_t) * sph::mlp_packed_words()) == hipSuccess;
     if (!ok) {
         sph_mlp_destroy(m);
         return fail(nullptr, SPH_ERR_OOM, "MLP device allocation failed");
@@ -1269,7 +1271,7 @@ void sph_mlp_destroy(sph_mlp *m) {
     if (!m) return;
     (void)hipStreamSynchronize(m->stream);
     for (void *p : {(void *)m->P, (void *)m->m, (void *)m->v, (void *)m->grad, (void *)m->part, (void *)m->loss_part,
-                    (void *)m->loss})
+                    (void *)m->loss, (void *)m->packed})
         if (p) (void)hipFree(p);
     delete m;
 }
@@ -1281,6 +1283,7 @@ int sph_mlp_set_params(sph_mlp *m, const float *params) {
     for (int i = 0; i < np; ++i)
         if (!std::isfinite(params[i])) m->finite = false;
     if (hipMemcpyAsync(m->P, params, sizeof(float) * np, hipMemcpyHostToDevice, m->stream) != hipSuccess ||
+        sph::launch_mlp_pack(m->P, m->packed, m->stream) != hipSuccess ||
         hipStreamSynchronize(m->stream) != hipSuccess)
         return SPH_ERR_DEVICE;
     return SPH_OK;
@@ -1297,7 +1300,7 @@ int sph_mlp_get_params(sph_mlp *m, float *params) {
 
 int sph_mlp_forward(sph_mlp *m, const float *features, float *y, int64_t n) {
     if (!m || n < 0 || (n > 0 && (!features || !y))) return SPH_ERR_INVALID;
-    if (sph::launch_mlp_forward(m->P, features, n, y, m->stream) != hipSuccess) return SPH_ERR_DEVICE;
+    if (sph::launch_mlp_forward(m->packed, features, n, y, m->stream) != hipSuccess) return SPH_ERR_DEVICE;
     return hipStreamSynchronize(m->stream) == hipSuccess ? SPH_OK : SPH_ERR_DEVICE;
 }
 
@@ -1332,7 +1335,8 @@ int sph_mlp_train_step(sph_mlp *m, const float *features, const float *targets, 
     const double b1 = 0.9, b2 = 0.999;
     const float c1 = (float)(1.0 - std::pow(b1, (double)m->step)), c2 = (float)(1.0 - std::pow(b2, (double)m->step));
     if (sph::launch_mlp_adam(m->P, m->grad, m->m, m->v, lr, (float)b1, (float)b2, 1e-8f, c1, c2, m->stream) !=
-        hipSuccess)
+            hipSuccess ||
+        sph::launch_mlp_pack(m->P, m->packed, m->stream) != hipSuccess)
         return SPH_ERR_DEVICE;
     if (loss) {
         double l = 0.0;

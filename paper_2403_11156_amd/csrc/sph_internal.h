@@ -200,7 +200,11 @@ hipError_t launch_trace_target(int64_t nf, const float* alpha, const float* K, f
 // the MLP (sph_mlp.hip)
 int mlp_param_count();
 int mlp_grad_blocks();
-hipError_t launch_mlp_forward(const float* P, const float* feat, int64_t n, float* y, hipStream_t s);
+// inference reads operands that launch_mlp_pack prepares from P (mlp_packed_words() words);
+// pack again after every change of P
+int mlp_packed_words();
+hipError_t launch_mlp_pack(const float* P, uint32_t* packed, hipStream_t s);
+hipError_t launch_mlp_forward(const uint32_t* packed, const float* feat, int64_t n, float* y, hipStream_t s);
 hipError_t launch_mlp_grad(const float* P, const float* feat, const float* target, int64_t n, float* part,
                            double* loss_part, float* grad, double* loss_sum, hipStream_t s);
 hipError_t launch_mlp_adam(float* P, const float* grad, float* m, float* v, float lr, float beta1, float beta2,

@@ -185,32 +185,86 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ int k16(int c, int h, int e) { return 32 * (c >> 1) + 8 * (2 * (c & 1) + (e >> 2)) + 4 * h + (e & 3); }
 
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// bf16(relu(x)) of z[r0..r0+7]: round pairs to bf16 (one v_cvt_pk_bf16_f32
+// each), then clamp at zero as 16-bit integers (one v_pk_max_i16 per pair: a
+// bf16 with the sign bit set is a negative int16, and rounding keeps the
+// sign, so this equals rounding relu(x))
+__device__ __forceinline__ bf16x8 relu_bf16x8(const f32x16& z, int r0) {
+    u32x4 w;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const f32x2 f = {z[r0 + 2 * k], z[r0 + 2 * k + 1]};
+        w[k] = __builtin_bit_cast(unsigned int, __builtin_convertvector(f, bf16x2));
+    }
+    i16x8 q = __builtin_bit_cast(i16x8, w);
+    q = __builtin_elementwise_max(q, (i16x8)0);
+    return __builtin_bit_cast(bf16x8, q);
+}
+
 struct InferRegs {
     bf16x4 w1[2];
     bf16x8 w2[2][4];
-    f32x16 b1[2], b2[2], w3[2];
-    float b3, out_scale;
+    bf16x8 w3[4];          // layer 3 as row 0 of an A operand (rows 1..31 zero)
 };
 
-__device__ __forceinline__ void load_infer(const WeightsLDS& W, InferRegs& R) {
-    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+// Inference operands, prepared once per parameter change by k_mlp_pack: the
+// InferRegs image of every lane, dword d of lane l at word d * 64 + l (so a
+// wave reads each dword with one coalesced load), then InferConst.
+constexpr int kImageWords = 52;
+static_assert(sizeof(InferRegs) == 4 * kImageWords, "register image");
+
+// constants every lane needs: b1 and b2 in D-register order,
+// [layer][tile t][lane half h][register r] = b[32 t + drow(r, h)], read by all
+// lanes of a half at one address; the input normalisation; b3, out_scale
+struct alignas(16) InferConst {
+    float bperm[2][2][2][16];
+    float shift[8], scale[8];
+    float b3, out_scale, pad[2];
+};
+constexpr int kConstWords = sizeof(InferConst) / 4;
+constexpr int kPackedWords = 64 * kImageWords + kConstWords;
+
+__global__ void __launch_bounds__(64) k_mlp_pack(const float* __restrict__ P, uint32_t* __restrict__ packed) {
+    const int lane = threadIdx.x, p = lane & 31, h = lane >> 5;
+    InferRegs R;
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-        R.w1[t] = load4(&W.W1b[(32 * t + p) * 8 + 4 * h]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * h + e;
+            R.w1[t][e] = k < NF ? (short)to_bf16(P[OFF_W1 + (32 * t + p) * NF + k]) : (short)0;
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) R.w2[t][c][e] = __builtin_bit_cast(__bf16, W.W2b[(32 * t + p) * H + k16(c, h, e)]);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int j = 32 * t + drow(r, h);
-            R.b1[t][r] = W.b1[j];
-            R.b2[t][r] = W.b2[j];
-            R.w3[t][r] = W.w3[j];
-        }
+            for (int e = 0; e < 8; ++e) R.w2[t][c][e] = (__bf16)P[OFF_W2 + (32 * t + p) * H + k16(c, h, e)];
     }
-    R.b3 = W.b3;
-    R.out_scale = W.out_scale;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) R.w3[c][e] = p == 0 ? (__bf16)P[OFF_W3 + k16(c, h, e)] : (__bf16)0.0f;
+    const uint32_t* img = reinterpret_cast<const uint32_t*>(&R);
+#pragma unroll
+    for (int d = 0; d < kImageWords; ++d) packed[d * 64 + lane] = img[d];
+    InferConst* C = reinterpret_cast<InferConst*>(packed + 64 * kImageWords);
+    for (int q = lane; q < 128; q += 64) {
+        const int l = q >> 6, t = (q >> 5) & 1, hh = (q >> 4) & 1, r = q & 15;
+        C->bperm[l][t][hh][r] = P[(l == 0 ? OFF_B1 : OFF_B2) + 32 * t + 8 * (r >> 2) + 4 * hh + (r & 3)];
+    }
+    if (lane < 8) {
+        C->shift[lane] = lane < NF ? P[OFF_SHIFT + lane] : 0.f;
+        C->scale[lane] = lane < NF ? P[OFF_SCALE + lane] : 0.f;
+    }
+    if (lane == 0) {
+        C->b3 = P[OFF_B3];
+        C->out_scale = P[OFF_OUT];
+        C->pad[0] = C->pad[1] = 0.f;
+    }
 }
 
 // Raw features 4h..4h+3 of sample base + p (0 past the sample or feature count).
@@ -226,7 +280,7 @@ __device__ __forceinline__ void load_features(const float* __restrict__ feat, in
 
 // y of the 32 samples base..base+31 (valid in lanes 0..31 for sample lane)
 // from the raw features fr of load_features
-__device__ __forceinline__ float forward_infer(const WeightsLDS& W, const InferRegs& R, const float fr[4], int64_t n,
+__device__ __forceinline__ float forward_infer(const InferConst& W, const InferRegs& R, const float fr[4], int64_t n,
                                                int64_t base) {
     const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
     const int64_t s = base + p;
@@ -242,34 +296,45 @@ __device__ __forceinline__ float forward_infer(const WeightsLDS& W, const InferR
         xv[c] = to_bf16(v);
     }
     const bf16x4 xb = pack4(xv);
+    // the bias rows are re-read from LDS every tile (an opaque offset keeps
+    // the compiler from holding them in 64 registers across the tile loop)
+    int boff = 0;
+    asm volatile("" : "+v"(boff));
+    const float* bp = &W.bperm[0][0][h][0] + boff;
     f32x16 z1[2];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) z1[t] = mfma(R.w1[t], xb, R.b1[t]);
+    for (int t = 0; t < 2; ++t) z1[t] = mfma(R.w1[t], xb, *reinterpret_cast<const f32x16*>(bp + 32 * t));
     bf16x8 hb[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) hb[c][e] = (__bf16)relu(z1[c >> 1][8 * (c & 1) + e]);
-    float part = 0.f;
+    for (int c = 0; c < 4; ++c) hb[c] = relu_bf16x8(z1[c >> 1], 8 * (c & 1));
+    // layer 2 one 32-row tile at a time, each followed by its two layer-3
+    // chunks (row 0 of the product holds h2 . w3 for the tile's 32 samples,
+    // register 0 of lanes 0..31)
+    f32x16 d = {};
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-        f32x16 acc = R.b2[t];
+        f32x16 acc = *reinterpret_cast<const f32x16*>(bp + 64 + 32 * t);
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w2[t][c], hb[c], acc, 0, 0, 0);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) part += (float)(__bf16)relu(acc[r]) * R.w3[t][r];
+        for (int u = 0; u < 2; ++u)
+            d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w3[2 * t + u], relu_bf16x8(acc, 8 * u), d, 0, 0, 0);
     }
-    part += __shfl_xor(part, 32, 64);
-    return (part + R.b3) * R.out_scale;
+    return (d[0] + W.b3) * W.out_scale;
 }
 
-__global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ P, const float* __restrict__ feat,
-                                                     int64_t n, float* __restrict__ y) {
-    __shared__ WeightsLDS W;
-    load_weights(W, P, false);
-    InferRegs R;
-    load_infer(W, R);
+__global__ void __launch_bounds__(256) k_mlp_forward(const uint32_t* __restrict__ packed,
+                                                     const float* __restrict__ feat, int64_t n,
+                                                     float* __restrict__ y) {
+    __shared__ InferConst W;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int q = threadIdx.x; q < kConstWords; q += blockDim.x)
+        reinterpret_cast<uint32_t*>(&W)[q] = packed[64 * kImageWords + q];
+    InferRegs R;
+    uint32_t* img = reinterpret_cast<uint32_t*>(&R);
+#pragma unroll
+    for (int d = 0; d < kImageWords; ++d) img[d] = packed[d * 64 + lane];
+    __syncthreads();
     const int64_t tiles = (n + 31) / 32, stride = (int64_t)gridDim.x * 4;
     // the next tile's features are loaded while this tile is computed
     float cur[4] = {0.f, 0.f, 0.f, 0.f};
@@ -464,12 +529,19 @@ constexpr int kMlpGradBlocks = 256;
 int mlp_param_count() { return NPARAM; }
 int mlp_grad_blocks() { return kMlpGradBlocks; }
 
-hipError_t launch_mlp_forward(const float* P, const float* feat, int64_t n, float* y, hipStream_t s) {
+int mlp_packed_words() { return kPackedWords; }
+
+hipError_t launch_mlp_pack(const float* P, uint32_t* packed, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_pack, dim3(1), dim3(64), 0, s, P, packed);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const uint32_t* packed, const float* feat, int64_t n, float* y, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t tiles = (n + 31) / 32;
     int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 1024) blocks = 1024;   // about two resident waves per SIMD; weights staged once per block
-    hipLaunchKernelGGL(k_mlp_forward, dim3((uint32_t)blocks), dim3(256), 0, s, P, feat, n, y);
+    if (blocks > 1024) blocks = 1024;   // four resident blocks per CU (at most 128 VGPRs); weights staged once per block
+    hipLaunchKernelGGL(k_mlp_forward, dim3((uint32_t)blocks), dim3(256), 0, s, packed, feat, n, y);
     return hipGetLastError();
 }
 
