@@ -620,8 +620,14 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     const bool implicit = c->P.visc_model == SPH_VISC_IMPLICIT;
     const bool wcsph = c->P.solver == SPH_SOLVER_WCSPH;
     auto warm_setup = [&]() -> int {   // kappa = K0, K = 0, x.w = K0 / rho
+        const float alpha_ref = (float)(2.35376 * 4.0 * c->P.r * c->P.r / c->P.rho0);
+        if (learned && !tracing) {   // features, network and start in one pass
+            ProfScope ps(c, "mlp", 36.0 * nf);
+            HIP_TRY(c, sph::launch_mlp_warm_start(c->mlp->packed, nf, c->x, c->rho, c->alpha, c->K, c->kappa, c->ncnt,
+                                                  c->bcnt, c->dbuf, c->kc, dt, alpha_ref, s));
+            return SPH_OK;
+        }
         if (learned || tracing) {
-            const float alpha_ref = (float)(2.35376 * 4.0 * c->P.r * c->P.r / c->P.rho0);
             float *feat = tracing ? c->trace_feat + 5 * c->trace_rows : c->feat;
             {
                 ProfScope ps(c, "warm_features", 28.0 * nf + 20.0 * nf);

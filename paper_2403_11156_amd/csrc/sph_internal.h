@@ -205,6 +205,11 @@ int mlp_grad_blocks();
 int mlp_packed_words();
 hipError_t launch_mlp_pack(const float* P, uint32_t* packed, hipStream_t s);
 hipError_t launch_mlp_forward(const uint32_t* packed, const float* feat, int64_t n, float* y, hipStream_t s);
+// features, network and start stiffness in one pass (as launch_features,
+// launch_mlp_forward and launch_warm_learned in sequence)
+hipError_t launch_mlp_warm_start(const uint32_t* packed, int64_t n, float4* x, const float* rho, const float* alpha,
+                                 float* K, float* kappa, const uint32_t* ncnt, const uint32_t* bcnt, const float* d,
+                                 Kern kc, float dt, float alpha_ref, hipStream_t s);
 hipError_t launch_mlp_grad(const float* P, const float* feat, const float* target, int64_t n, float* part,
                            double* loss_part, float* grad, double* loss_sum, hipStream_t s);
 hipError_t launch_mlp_adam(float* P, const float* grad, float* m, float* v, float lr, float beta1, float beta2,

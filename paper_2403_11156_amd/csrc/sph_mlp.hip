@@ -351,6 +351,66 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const uint32_t* __restrict_
     }
 }
 
+// The learned warm start in one pass (when no training trace is recorded):
+// each particle's features computed from its fields exactly as k_features
+// does, the network, and the start stiffness exactly as k_warm_learned sets
+// it: kappa = K0 = max(0, y alpha rho0 / dt^2), K = 0, x.w = K0 / rho.
+// Lane half 0 holds features 0..3 of its sample, half 1 feature 4.
+__device__ __forceinline__ void load_fields(int64_t n, int64_t base, const float* __restrict__ rho,
+                                            const float* __restrict__ alpha, const float* __restrict__ K,
+                                            const uint32_t* __restrict__ ncnt, const uint32_t* __restrict__ bcnt,
+                                            const float* __restrict__ d, const Kern& kc, float dt, float alpha_ref,
+                                            float fr[4]) {
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+    const int64_t i = base + p;
+    fr[0] = fr[1] = fr[2] = fr[3] = 0.f;
+    if (i >= n) return;
+    const float a = alpha[i];
+    if (h == 0) {
+        fr[0] = (rho[i] - kc.rho0) / kc.rho0;
+        fr[1] = dt * d[i] / kc.rho0;
+        fr[2] = (float)(ncnt[i] + bcnt[i]) / 26.0f;
+        fr[3] = a > 0.0f ? K[i] * dt * dt / (a * kc.rho0) : 0.0f;
+    } else {
+        fr[0] = a / alpha_ref;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_mlp_warm_start(const uint32_t* __restrict__ packed, int64_t n,
+                                                        float4* __restrict__ x, const float* __restrict__ rho,
+                                                        const float* __restrict__ alpha, float* __restrict__ K,
+                                                        float* __restrict__ kappa, const uint32_t* __restrict__ ncnt,
+                                                        const uint32_t* __restrict__ bcnt, const float* __restrict__ d,
+                                                        Kern kc, float dt, float alpha_ref) {
+    __shared__ InferConst W;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int q = threadIdx.x; q < kConstWords; q += blockDim.x)
+        reinterpret_cast<uint32_t*>(&W)[q] = packed[64 * kImageWords + q];
+    InferRegs R;
+    uint32_t* img = reinterpret_cast<uint32_t*>(&R);
+#pragma unroll
+    for (int q = 0; q < kImageWords; ++q) img[q] = packed[q * 64 + lane];
+    __syncthreads();
+    const int64_t tiles = (n + 31) / 32, stride = (int64_t)gridDim.x * 4;
+    float cur[4] = {0.f, 0.f, 0.f, 0.f};
+    int64_t t = (int64_t)blockIdx.x * 4 + wave;
+    if (t < tiles) load_fields(n, 32 * t, rho, alpha, K, ncnt, bcnt, d, kc, dt, alpha_ref, cur);
+    for (; t < tiles; t += stride) {
+        float nxt[4] = {0.f, 0.f, 0.f, 0.f};
+        if (t + stride < tiles) load_fields(n, 32 * (t + stride), rho, alpha, K, ncnt, bcnt, d, kc, dt, alpha_ref, nxt);
+        const float yv = forward_infer(W, R, cur, n, 32 * t);
+        const int64_t i = 32 * t + lane;
+        if (lane < 32 && i < n) {
+            const float k0 = fmaxf(yv * alpha[i] * kc.rho0 / (dt * dt), 0.0f);
+            kappa[i] = k0;
+            K[i] = 0.0f;
+            x[i].w = k0 / rho[i];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cur[c] = nxt[c];
+    }
+}
+
 // ---------------------------------------------------------------- training
 // One wave per workgroup.  Partial gradient (packed like the parameters) and
 // FP64 loss sum of this workgroup's tiles go to part[blockIdx.x].
@@ -533,6 +593,18 @@ int mlp_packed_words() { return kPackedWords; }
 
 hipError_t launch_mlp_pack(const float* P, uint32_t* packed, hipStream_t s) {
     hipLaunchKernelGGL(k_mlp_pack, dim3(1), dim3(64), 0, s, P, packed);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_warm_start(const uint32_t* packed, int64_t n, float4* x, const float* rho, const float* alpha,
+                                 float* K, float* kappa, const uint32_t* ncnt, const uint32_t* bcnt, const float* d,
+                                 Kern kc, float dt, float alpha_ref, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t tiles = (n + 31) / 32;
+    int64_t blocks = (tiles + 3) / 4;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_mlp_warm_start, dim3((uint32_t)blocks), dim3(256), 0, s, packed, n, x, rho, alpha, K, kappa,
+                       ncnt, bcnt, d, kc, dt, alpha_ref);
     return hipGetLastError();
 }
 
