@@ -88,6 +88,7 @@ struct sph_ctx {
     std::vector<double> force, torque;
     std::vector<double> local_host;   // [nb][3] body-frame offsets, original order
     std::vector<int32_t> body_host;   // [nb]
+    std::vector<std::vector<double>> body_points;   // per body: its particles' body-frame offsets
     std::vector<void *> allocs;
     int64_t dev_bytes = 0;
 
@@ -251,8 +252,7 @@ int upload_poses(sph_ctx *c) {
 // Newton-Euler in FP64 with the world inertia R diag(I) R^T, then the
 // tank-contact stand-in: push the body back inside [min + r, max - r] along
 // each axis and drop the velocity component into the wall.
-void rigid_integrate(sph_ctx *c, double dt, const std::vector<double> &local_host,
-                     const std::vector<int32_t> &body_host) {
+void rigid_integrate(sph_ctx *c, double dt) {
     const double *gr = c->P.gravity;
     for (int b = 0; b < c->nr; ++b) {
         sph_rigid_desc s = c->rigid[b];
@@ -287,11 +287,11 @@ void rigid_integrate(sph_ctx *c, double dt, const std::vector<double> &local_hos
             s.quat[0] = qw / nq; s.quat[1] = qx / nq; s.quat[2] = qy / nq; s.quat[3] = qz / nq;
         }
         quat_to_R(s.quat, R);
+        const std::vector<double> &pts = c->body_points[b];
         for (int a = 0; a < 3; ++a) {
             double lo = 1e300, hi = -1e300;
-            for (int64_t k = 0; k < c->nb; ++k) {
-                if (body_host[k] != b) continue;
-                const double *l = &local_host[3 * k];
+            for (size_t k = 0; k + 2 < pts.size(); k += 3) {
+                const double *l = &pts[k];
                 const double xa = s.com[a] + (R[3 * a] * l[0] + R[3 * a + 1] * l[1] + R[3 * a + 2] * l[2]);
                 lo = std::min(lo, xa);
                 hi = std::max(hi, xa);
@@ -696,7 +696,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
                 c->force[3 * b + a] = fo[6 * b + a];
                 c->torque[3 * b + a] = fo[6 * b + 3 + a];
             }
-        rigid_integrate(c, (double)dt, c->local_host, c->body_host);
+        rigid_integrate(c, (double)dt);
         rc = upload_poses(c);
         if (rc) return rc;
         HIP_TRY(c, sph::launch_rigid_boundary(c->nb, c->xb, c->vb, c->bid, c->blocal, c->poses, s));
@@ -949,6 +949,11 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
                 hvb[k].z = (float)(s.vel[2] + wx[2]);
             }
         }
+        c->body_points.assign(std::max(1, c->nr), {});
+        for (int64_t k = 0; k < nb; ++k)
+            if (c->body_host[k] >= 0)
+                c->body_points[c->body_host[k]].insert(c->body_points[c->body_host[k]].end(), &local[3 * k],
+                                                       &local[3 * k] + 3);
         ok = ok && hipMemcpyAsync(c->xb, hxb.data(), sizeof(float4) * nb, hipMemcpyHostToDevice, s) == hipSuccess &&
              hipMemcpyAsync(c->vb, hvb.data(), sizeof(float4) * nb, hipMemcpyHostToDevice, s) == hipSuccess &&
              hipMemcpyAsync(c->bid, hbid.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s) == hipSuccess &&

@@ -136,14 +136,14 @@ __global__ void k_finish_f64(const double* __restrict__ partials, int nblk, int 
     }
 }
 
-// as k_finish_f64 into the host status (rigid force and torque)
-__global__ void k_finish_rigid(const double* __restrict__ partials, int nblk, int nout, HostStatus* host) {
-    for (int o = 0; o < nout; ++o) {
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partials[(size_t)b * nout + o];
-        acc = block_sum(acc);
-        if (threadIdx.x == 0) host->rigid[o] = acc;
-    }
+// as k_finish_f64 into the host status (rigid force and torque): workgroup o
+// sums output o's partials, stored output-major (partials[o nblk + b])
+__global__ void k_finish_rigid(const double* __restrict__ partials, int nblk, HostStatus* host) {
+    const int o = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partials[(size_t)o * nblk + b];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) host->rigid[o] = acc;
 }
 
 // FP64 sum over a workgroup of NT threads in a fixed order; valid in thread 0.

@@ -635,37 +635,57 @@ __global__ void __launch_bounds__(kBlock) k_rigid_force(
     uint32_t nbk = 0;
     float4 xi = make_float4(0.f, 0.f, 0.f, 0.f);
     float base = 0.f;
+    uint32_t mine = 0;   // bit b: a boundary neighbour of this particle belongs to body b
     if (i < nf) {
         nbk = bcnt[i];
         if (nbk) {
             xi = x[i];
             base = kc.m * (K[i] + Kv[i]) / rho[i];
         }
-    }
-    for (int32_t b = 0; b < nbody; ++b) {
-        double f[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0};
         for (uint32_t k = 0; k < nbk; ++k) {
-            const uint32_t kk = blist[list_index(nf, i, k)];
-            const float4 vk = vb[kk];
-            if ((int32_t)vk.w != b) continue;
-            const float4 xk = xb[kk];
-            const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float c = base * xk.w * grad_factor(r2, kc);
-            const double Fx = (double)(c * dx), Fy = (double)(c * dy), Fz = (double)(c * dz);
-            const double rx = (double)xk.x - com[3 * b], ry = (double)xk.y - com[3 * b + 1],
-                         rz = (double)xk.z - com[3 * b + 2];
-            f[0] += Fx; f[1] += Fy; f[2] += Fz;
-            t[0] += ry * Fz - rz * Fy;
-            t[1] += rz * Fx - rx * Fz;
-            t[2] += rx * Fy - ry * Fx;
+            const int32_t b = (int32_t)vb[blist[list_index(nf, i, k)]].w;
+            if (b >= 0) mine |= 1u << b;
+        }
+    }
+    // the bodies the workgroup touches (integer OR: exact); most workgroups
+    // touch none and only store zeros
+    for (int off = 32; off > 0; off >>= 1) mine |= (uint32_t)__shfl_xor((int)mine, off, 64);
+    __shared__ uint32_t wmask[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) wmask[threadIdx.x >> 6] = mine;
+    __syncthreads();
+    uint32_t touched = 0;
+    for (int w = 0; w < kBlock / 64; ++w) touched |= wmask[w];
+    const size_t nblk = gridDim.x;
+    for (int32_t b = 0; b < nbody; ++b) {
+        if (!((touched >> b) & 1u)) {
+            if (threadIdx.x < 6) partials[(size_t)(6 * b + threadIdx.x) * nblk + blockIdx.x] = 0.0;
+            continue;
+        }
+        double f[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0};
+        if ((mine >> b) & 1u) {
+            for (uint32_t k = 0; k < nbk; ++k) {
+                const uint32_t kk = blist[list_index(nf, i, k)];
+                const float4 vk = vb[kk];
+                if ((int32_t)vk.w != b) continue;
+                const float4 xk = xb[kk];
+                const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float c = base * xk.w * grad_factor(r2, kc);
+                const double Fx = (double)(c * dx), Fy = (double)(c * dy), Fz = (double)(c * dz);
+                const double rx = (double)xk.x - com[3 * b], ry = (double)xk.y - com[3 * b + 1],
+                             rz = (double)xk.z - com[3 * b + 2];
+                f[0] += Fx; f[1] += Fy; f[2] += Fz;
+                t[0] += ry * Fz - rz * Fy;
+                t[1] += rz * Fx - rx * Fz;
+                t[2] += rx * Fy - ry * Fx;
+            }
         }
         for (int c = 0; c < 3; ++c) {
             const double s0 = block_sum(f[c]);
             const double s1 = block_sum(t[c]);
             if (threadIdx.x == 0) {
-                partials[((size_t)blockIdx.x * nbody + b) * 6 + c] = s0;
-                partials[((size_t)blockIdx.x * nbody + b) * 6 + 3 + c] = s1;
+                partials[(size_t)(6 * b + c) * nblk + blockIdx.x] = s0;
+                partials[(size_t)(6 * b + 3 + c) * nblk + blockIdx.x] = s1;
             }
         }
     }
@@ -1163,7 +1183,7 @@ hipError_t launch_rigid_force(int64_t nf, const float4* x, const float* rho, con
     const uint32_t nblk = grid_blocks(nf);
     hipLaunchKernelGGL(k_rigid_force, dim3(nblk), dim3(kBlock), 0, s, nf, x, rho, K, Kv, blist, bcnt, xb, vb, kc,
                        nbody, com, partials);
-    hipLaunchKernelGGL(k_finish_rigid, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, 6 * nbody, host);
+    hipLaunchKernelGGL(k_finish_rigid, dim3(6 * nbody), dim3(kBlock), 0, s, partials, (int)nblk, host);
     return hipGetLastError();
 }
 
