@@ -29,6 +29,11 @@ def _scene(name):
     if name == "previous":
         return scenes.small_scene(9, 7, 6, dt_max=1e-3, solver=scenes.SOLVER_PCISPH,
                                   warm_start=scenes.WARM_PREVIOUS)
+    if name == "implicit":
+        sc = scenes.small_scene(9, 7, 6, dt_max=1e-3, visc_model=scenes.VISC_IMPLICIT, visc=0.05, cg_tol=1e-6,
+                                **kw)
+        sc.v_fluid[:] = np.random.default_rng(9).normal(0, 0.2, sc.v_fluid.shape).astype(np.float32)
+        return sc
     if name == "bodies":
         r = 0.01
         bodies = scenes.small_bodies(r, 4, [(0.22, 0.12, 0.2)])
@@ -38,7 +43,7 @@ def _scene(name):
     return scenes.scene(name)
 
 
-@pytest.mark.parametrize("name", ["small", "previous", "bodies"])
+@pytest.mark.parametrize("name", ["small", "previous", "bodies", "implicit"])
 def test_pcisph_single_step_fields(sph, name):
     sc = _scene(name)
     print(f"[pcisph] {name}: nf={sc.n_fluid} nb={sc.n_boundary}", flush=True)

@@ -30,6 +30,12 @@ def _scene(name):
         c = sc.x_fluid.mean(axis=0)
         sc.x_fluid = (0.92 * (sc.x_fluid - c) + c).astype(np.float32)
         return sc
+    if name == "implicit":
+        sc = scenes.small_scene(9, 7, 6, solver=scenes.SOLVER_WCSPH, dt_max=2e-4,
+                                visc_model=scenes.VISC_IMPLICIT, visc=0.05,
+                                cg_tol=1e-6)
+        sc.v_fluid[:] = np.random.default_rng(8).normal(0, 0.2, sc.v_fluid.shape).astype(np.float32)
+        return sc
     if name == "bodies":
         r = 0.01
         bodies = scenes.small_bodies(r, 4, [(0.22, 0.12, 0.2)])
@@ -39,7 +45,7 @@ def _scene(name):
     return scenes.scene(name)
 
 
-@pytest.mark.parametrize("name", ["small", "compressed", "bodies"])
+@pytest.mark.parametrize("name", ["small", "compressed", "bodies", "implicit"])
 def test_wcsph_single_step_fields(sph, name):
     sc = _scene(name)
     print(f"[wcsph] {name}: nf={sc.n_fluid} nb={sc.n_boundary}", flush=True)
