@@ -125,7 +125,7 @@ def main():
         arms = [a for a in arms if a != "learned"] or ["plain"]
     results = {}
     for arm in arms:
-        sim = sph.Simulation(sc)
+        sim = sph.Simulation(sc, params=dict(sc.params, auto_rebuild=1))   # the step queues its own build
         net = None
         if arm == "learned":
             import numpy as np

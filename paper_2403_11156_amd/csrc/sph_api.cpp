@@ -111,6 +111,8 @@ struct sph_ctx {
     float *trace_feat = nullptr, *trace_target = nullptr;
     int64_t trace_cap = 0, trace_rows = 0;
 
+    hipEvent_t build_done = nullptr;   // recorded after a build queued by sph_step
+
     bool prof = false;
     std::vector<ProfEvent> prof_pending;
     std::vector<hipEvent_t> event_pool;
@@ -166,6 +168,8 @@ void free_all(sph_ctx *c) {
     c->prof_pending.clear();
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     c->event_pool.clear();
+    if (c->build_done) (void)hipEventDestroy(c->build_done);
+    c->build_done = nullptr;
 }
 
 hipEvent_t take_event(sph_ctx *c) {
@@ -347,7 +351,10 @@ int sort_boundary(sph_ctx *c) {
 double list_bytes(const sph_ctx *c) { return 4.0 * c->nbr_sum; }
 double fluid_list_bytes(const sph_ctx *c) { return 4.0 * c->nbr_sum_f; }
 
-int build(sph_ctx *c) {
+// The neighbour pipeline in two halves: build_queue launches the sorts and
+// the list build, build_check reads their status (capacity flags, neighbour
+// statistics) once the stream has passed them.
+int build_queue(sph_ctx *c) {
     hipStream_t s = c->stream;
     HIP_TRY(c, sph::launch_fill_u32(c->flags, 1, 0u, s));
     if (c->boundary_dirty) {
@@ -366,7 +373,10 @@ int build(sph_ctx *c) {
         HIP_TRY(c, sph::launch_nbr_build(c->x, c->nf, c->xb, c->start_f, c->start_b, c->g, c->nlist, c->ncnt, c->capf,
                                          c->blist, c->bcnt, c->capb, c->flags, c->nstat_part, c->hs_dev, s));
     }
-    HIP_TRY(c, hipStreamSynchronize(s));
+    return SPH_OK;
+}
+
+int build_check(sph_ctx *c) {
     const sph::HostStatus &hs = *c->hs;
     c->sorted_once = true;
     if (hs.flags & 2u) {
@@ -382,6 +392,13 @@ int build(sph_ctx *c) {
     c->nbr_sum_f = (double)hs.nstats[3];
     c->nbr_fresh = true;
     return SPH_OK;
+}
+
+int build(sph_ctx *c) {
+    int rc = build_queue(c);
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return build_check(c);
 }
 
 // go (nullable): skip the pass on the device once the solve needs no more
@@ -550,12 +567,38 @@ int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
 
 int step_impl(sph_ctx *c, sph_step_stats *st) {
     hipStream_t s = c->stream;
-    if (!c->nbr_fresh) {
+    // 0. neighbours: with auto_rebuild the build is queued here and its status
+    //    read only after the density pass (which needs no dt) is queued too,
+    //    so the device runs that pass while the host waits
+    const bool rebuild = !c->nbr_fresh;
+    if (rebuild) {
         if (!c->P.auto_rebuild) return fail(c, SPH_ERR_STATE, "sph_step needs fresh neighbours (sph_build_neighbors)");
-        int rc = build(c);
+        int rc = build_queue(c);
         if (rc) return rc;
+        HIP_TRY(c, hipEventRecord(c->build_done, s));
     }
     const int64_t nf = c->nf;
+    const bool dfsph = c->P.solver == SPH_SOLVER_DFSPH;
+    const bool pcisph = c->P.solver == SPH_SOLVER_PCISPH;
+    const bool ppe = dfsph || pcisph;   // iterative density solve
+    const bool warm = ppe && c->warm_mode != SPH_WARM_ZERO;
+    const float wf = warm ? (float)c->P.warm_factor : 0.0f;
+    const bool learned = dfsph && c->warm_mode == SPH_WARM_LEARNED && c->mlp != nullptr;
+    const bool tracing = dfsph && c->trace_feat != nullptr && c->trace_rows + nf <= c->trace_cap;
+    c->want_d = learned || tracing;
+
+    // 2. density, alpha; divergence warm-start set-up
+    {
+        ProfScope ps(c, "density_alpha", 80.0 * nf + list_bytes(c));
+        HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, c->nlist, c->ncnt, c->xb, c->blist, c->bcnt, c->kc,
+                                             c->rho, c->alpha, c->v_in, c->Kv, c->kappa, dfsph ? wf : 0.0f,
+                                             c->pci_c, s));
+    }
+    if (rebuild) {
+        HIP_TRY(c, hipEventSynchronize(c->build_done));
+        int rc = build_check(c);   // a capacity error leaves clamped, in-bounds lists behind
+        if (rc) return rc;
+    }
     // 1. time step (fixed, or CFL from the step's input velocities)
     float dt;
     if (c->P.cfl_lambda > 0.0) {
@@ -577,22 +620,6 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         dt = (float)d;
     } else {
         dt = (float)c->P.dt_max;
-    }
-    const bool dfsph = c->P.solver == SPH_SOLVER_DFSPH;
-    const bool pcisph = c->P.solver == SPH_SOLVER_PCISPH;
-    const bool ppe = dfsph || pcisph;   // iterative density solve
-    const bool warm = ppe && c->warm_mode != SPH_WARM_ZERO;
-    const float wf = warm ? (float)c->P.warm_factor : 0.0f;
-    const bool learned = dfsph && c->warm_mode == SPH_WARM_LEARNED && c->mlp != nullptr;
-    const bool tracing = dfsph && c->trace_feat != nullptr && c->trace_rows + nf <= c->trace_cap;
-    c->want_d = learned || tracing;
-
-    // 2. density, alpha; divergence warm-start set-up
-    {
-        ProfScope ps(c, "density_alpha", 80.0 * nf + list_bytes(c));
-        HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, c->nlist, c->ncnt, c->xb, c->blist, c->bcnt, c->kc,
-                                             c->rho, c->alpha, c->v_in, c->Kv, c->kappa, dfsph ? wf : 0.0f,
-                                             c->pci_c, s));
     }
     // 3. divergence-free solve (DFSPH)
     int32_t iv = 0, id = 0;
@@ -902,6 +929,11 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
         free_all(c);
         delete c;
         return fail(nullptr, SPH_ERR_OOM, "pinned host allocation failed");
+    }
+    if (hipEventCreateWithFlags(&c->build_done, hipEventDisableTiming) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return fail(nullptr, SPH_ERR_DEVICE, "event creation failed");
     }
     // upload the scene (original order; the first build sorts it)
     {

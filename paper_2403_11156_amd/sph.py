@@ -286,7 +286,11 @@ class Simulation:
         return self.last_stats
 
     def advance(self) -> Dict:
-        self.build_neighbors()
+        """One whole step: the neighbour build and the step (with auto_rebuild
+        the step queues the build itself and overlaps its status read with
+        the density pass)."""
+        if not self.params.get("auto_rebuild", 0):
+            self.build_neighbors()
         return self.step()
 
     def info(self) -> Dict:

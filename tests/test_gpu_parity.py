@@ -177,6 +177,33 @@ def test_deterministic(sph):
         assert np.array_equal(outs[0][f], outs[1][f]), f
 
 
+@pytest.mark.parametrize("name", ["c1", "bodies"])
+def test_auto_rebuild_matches_explicit_build(sph, name):
+    # with auto_rebuild the step queues the build itself and reads its status
+    # after the density pass: the same state, bit for bit, as build + step
+    outs = []
+    for auto in (0, 1):
+        sc = scenes.scene("c1") if name == "c1" else _small_with_bodies()
+        sim = sph.Simulation(sc, params=dict(sc.params, auto_rebuild=auto))
+        stats = [sim.advance() for _ in range(4)]
+        outs.append((sim.read(("x", "v", "K", "Kv", "rigid")), stats))
+        sim.close()
+    for f in ("x", "v", "K", "Kv"):
+        assert np.array_equal(outs[0][0][f], outs[1][0][f]), f
+    for a, b in zip(outs[0][1], outs[1][1]):
+        for k in ("dt", "iters_div", "iters_dens", "nbr_min", "nbr_max", "nbr_mean"):
+            assert a[k] == b[k], k
+
+
+def test_auto_rebuild_capacity_error(sph):
+    sc = scenes.small_scene(6, 5, 4)
+    sim = sph.Simulation(sc, params=dict(sc.params, max_neighbors=4, auto_rebuild=1))
+    with pytest.raises(sph.SphError) as e:
+        sim.step()
+    assert e.value.code == sph.SPH_ERR_CAPACITY
+    sim.close()
+
+
 def test_free_fall_closed_form(sph):
     sc = scenes.small_scene(1, 1, 1, jitter=0.0, cfl_lambda=0.0, dt_max=1e-3)
     sc.x_fluid[:] = [[0.15, 0.2, 0.15]]
