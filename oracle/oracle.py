@@ -65,7 +65,7 @@ class In(C.Structure):
         ("xb", C.c_void_p), ("vb", C.c_void_p), ("body", C.c_void_p), ("local", C.c_void_p),
         ("rigid", C.c_void_p), ("mlp", MLP_FN), ("mlp_user", C.c_void_p),
         ("brute_force", C.c_int32),
-        ("dvisc", C.c_void_p),
+        ("dvisc", C.c_void_p), ("rho_prev", C.c_void_p),
     ]
 
 
@@ -314,6 +314,7 @@ class State:
         self.local = rigid_local(self.xb, self.body, self.rigid) if local is None else local
         self.vb = np.zeros_like(self.xb)
         self.dvisc = np.zeros((n, 3), np.float32)   # previous implicit-viscosity correction
+        self.rho_prev = np.full(n, np.float32(self.params["rho0"]), np.float32)   # previous step's density
 
 
 def pcisph_factor(pd: Dict) -> float:
@@ -352,6 +353,8 @@ def step(state: State, forced_div: int = -1, forced_dens: int = -1, brute: Optio
     ci.brute_force = int(bool(brute))
     dv = np.ascontiguousarray(getattr(state, "dvisc", np.zeros((nf, 3))), np.float32).reshape(nf, 3)
     ci.dvisc = _p(dv)
+    rp = np.ascontiguousarray(getattr(state, "rho_prev", np.full(nf, pd["rho0"])), np.float32).reshape(nf)
+    ci.rho_prev = _p(rp)
     keep = []
     if mlp is not None:
         def _cb(fp, sp, n, yp, user):
@@ -429,6 +432,7 @@ def advance(state: State, out: Dict) -> State:
     s.local = state.local
     s.rigid = out["rigid_new"]
     s.dvisc = out["dvisc"].astype(np.float32)
+    s.rho_prev = out["rho"].astype(np.float32)
     return s
 
 

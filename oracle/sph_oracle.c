@@ -85,6 +85,7 @@ typedef struct or_in {
     void *mlp_user;
     int32_t brute_force;       /* 1: O(N^2) neighbour sets, 0: oracle grid */
     const float *dvisc;        /* [nf][3] previous implicit-viscosity correction v* - b (NULL: zero) */
+    const float *rho_prev;     /* [nf] previous step's density (NULL: rho0), for the divergence warm start */
 } or_in;
 
 typedef struct or_out {
@@ -529,16 +530,18 @@ static void divergence(const world *w, const double *v, const double *Sv, double
  * kr = kappa / rho.  impulse (optional, [n_rigid][6]) collects the Eq. 14
  * reaction on the bodies (force and torque about the body centre).
  */
-static void pressure_update(const world *w, const double *kappa, const double *Skappa, double *v, double *Sv) {
+/* pressure velocity update with kappa_j / den_j in place of kappa_j / rho_j */
+static void pressure_update_den(const world *w, const double *kappa, const double *Skappa, const double *den,
+                                double *v, double *Sv) {
     const double m = w->m, h = w->h, dt = w->dt;
     double *dv = malloc(sizeof(double) * 3 * (w->nf ? w->nf : 1));
     double *Sdv = malloc(sizeof(double) * 3 * (w->nf ? w->nf : 1));
     for (int64_t i = 0; i < w->nf; ++i) {
-        double kri = kappa[i] / w->rho[i], Skri = (Skappa[i] + fabs(kappa[i])) / w->rho[i];
+        double kri = kappa[i] / den[i], Skri = (Skappa[i] + fabs(kappa[i])) / den[i];
         double acc[3] = {0, 0, 0}, Sacc[3] = {0, 0, 0};
         FOR_F(i, e) {
             int64_t j = w->ff.idx[e];
-            double krj = kappa[j] / w->rho[j], Skrj = (Skappa[j] + fabs(kappa[j])) / w->rho[j];
+            double krj = kappa[j] / den[j], Skrj = (Skappa[j] + fabs(kappa[j])) / den[j];
             double x[3], gw[3], sg[3];
             xij_f(w, i, j, x);
             or_gradW(x, h, gw);
@@ -563,6 +566,10 @@ static void pressure_update(const world *w, const double *kappa, const double *S
     }
     for (int64_t i = 0; i < 3 * w->nf; ++i) { v[i] -= dv[i]; Sv[i] += Sdv[i]; }
     free(dv); free(Sdv);
+}
+
+static void pressure_update(const world *w, const double *kappa, const double *Skappa, double *v, double *Sv) {
+    pressure_update_den(w, kappa, Skappa, w->rho, v, Sv);
 }
 
 /* mean over fluid particles of a clamped (compression-only) deviation */
@@ -783,13 +790,22 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     int32_t lv = 0;
     double err_v = 0.0, S_err_v = 0.0;
     if (dfsph) {
-        /* -- 5. divergence-free solve (Eq. 10 with Algorithm 2).  Warm start:
-         *    Kv0 = 0 (ZERO) or the previous step's Kv (PREVIOUS, LEARNED). */
+        /* -- 5. divergence-free solve (Eq. 10 with Algorithm 2).  Warm start
+         *    (R15): zero (ZERO), or kappa/rho = warm_factor Kv_prev / rho_prev,
+         *    the previous step's stiffness over its own density (PREVIOUS,
+         *    LEARNED); it accumulates as Kv0 = that times the current rho. */
+        double *rp = malloc(s1);
         for (int64_t i = 0; i < nf; ++i) {
+            rp[i] = in->rho_prev ? (double)in->rho_prev[i] : p->rho0;
             Kv[i] = p->warm_start == 0 ? 0.0 : p->warm_factor * (double)in->Kv[i];
             SKv[i] = fabs(Kv[i]);
         }
-        if (p->warm_start != 0) pressure_update(w, Kv, SKv, w->v, w->Sv);
+        if (p->warm_start != 0) pressure_update_den(w, Kv, SKv, rp, w->v, w->Sv);
+        for (int64_t i = 0; i < nf; ++i) {
+            Kv[i] = Kv[i] / rp[i] * w->rho[i];
+            SKv[i] = fabs(Kv[i]);
+        }
+        free(rp);
         divergence(w, w->v, w->Sv, d, Sd);
         err_v = dt / p->rho0 * mean_pos(d, nf);
         S_err_v = dt / p->rho0 * mean_abs(Sd, nf);

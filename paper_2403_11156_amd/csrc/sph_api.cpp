@@ -82,6 +82,7 @@ struct sph_ctx {
     float *Pinv = nullptr;
     float4 *cg_b = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
     float4 *dvisc = nullptr, *dvisc2 = nullptr;   // previous correction v* - b, sorted order
+    float *rho2 = nullptr, *kvr = nullptr;         // density ping-pong; Kv / rho of the previous step
     double *cg_part = nullptr;                    // CG partial sums (mat-vec, then update)
 
     std::vector<sph_rigid_desc> rigid;
@@ -112,6 +113,7 @@ struct sph_ctx {
     int64_t trace_cap = 0, trace_rows = 0;
 
     hipEvent_t build_done = nullptr;   // recorded after a build queued by sph_step
+    hipEvent_t vmax_done = nullptr;    // recorded after the CFL reduction at the end of a step
 
     bool prof = false;
     std::vector<ProfEvent> prof_pending;
@@ -169,7 +171,8 @@ void free_all(sph_ctx *c) {
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     c->event_pool.clear();
     if (c->build_done) (void)hipEventDestroy(c->build_done);
-    c->build_done = nullptr;
+    if (c->vmax_done) (void)hipEventDestroy(c->vmax_done);
+    c->build_done = c->vmax_done = nullptr;
 }
 
 hipEvent_t take_event(sph_ctx *c) {
@@ -321,9 +324,10 @@ int sort_fluid(sph_ctx *c) {
     HIP_TRY(c, sph::launch_exclusive_scan(c->count, c->ncell, c->start_f, c->scan_part, s));
     HIP_TRY(c, sph::launch_scatter(c->key, c->slot, c->start_f, c->nf, c->src, s));
     HIP_TRY(c, sph::launch_cell_sort(c->start_f, c->ncell, c->src, c->id, c->flags, s));
-    HIP_TRY(c, sph::launch_gather_fluid(c->src, c->nf, c->x, c->v, c->K, c->Kv, c->id, c->dvisc, c->x2, c->v2, c->K2,
-                                        c->Kv2, c->id2, c->dvisc2, s));
+    HIP_TRY(c, sph::launch_gather_fluid(c->src, c->nf, c->x, c->v, c->K, c->Kv, c->rho, c->id, c->dvisc, c->x2, c->v2,
+                                        c->K2, c->Kv2, c->rho2, c->kvr, c->id2, c->dvisc2, s));
     std::swap(c->dvisc, c->dvisc2);
+    std::swap(c->rho, c->rho2);
     std::swap(c->x, c->x2);
     std::swap(c->v, c->v2);
     std::swap(c->K, c->K2);
@@ -568,8 +572,8 @@ int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
 int step_impl(sph_ctx *c, sph_step_stats *st) {
     hipStream_t s = c->stream;
     // 0. neighbours: with auto_rebuild the build is queued here and its status
-    //    read only after the density pass (which needs no dt) is queued too,
-    //    so the device runs that pass while the host waits
+    //    read only after the density pass is queued too, so the device runs
+    //    that pass while the host waits
     const bool rebuild = !c->nbr_fresh;
     if (rebuild) {
         if (!c->P.auto_rebuild) return fail(c, SPH_ERR_STATE, "sph_step needs fresh neighbours (sph_build_neighbors)");
@@ -587,25 +591,14 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     const bool tracing = dfsph && c->trace_feat != nullptr && c->trace_rows + nf <= c->trace_cap;
     c->want_d = learned || tracing;
 
-    // 2. density, alpha; divergence warm-start set-up
-    {
-        ProfScope ps(c, "density_alpha", 80.0 * nf + list_bytes(c));
-        HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, c->nlist, c->ncnt, c->xb, c->blist, c->bcnt, c->kc,
-                                             c->rho, c->alpha, c->v_in, c->Kv, c->kappa, dfsph ? wf : 0.0f,
-                                             c->pci_c, s));
-    }
-    if (rebuild) {
-        HIP_TRY(c, hipEventSynchronize(c->build_done));
-        int rc = build_check(c);   // a capacity error leaves clamped, in-bounds lists behind
-        if (rc) return rc;
-    }
     // 1. time step (fixed, or CFL from the step's input velocities)
     float dt;
     if (c->P.cfl_lambda > 0.0) {
         // max |v|^2 of the step's input velocities: queued at the end of the
-        // previous step and complete at the neighbour build's synchronisation,
-        // else computed now
-        if (!c->vmax_ready) {
+        // previous step (vmax_done), else computed now
+        if (c->vmax_ready) {
+            HIP_TRY(c, hipEventSynchronize(c->vmax_done));
+        } else {
             HIP_TRY(c, sph::launch_max_v2(c->v, nf, (uint32_t *)c->red_part, c->hs_dev, s));
             HIP_TRY(c, hipStreamSynchronize(s));
         }
@@ -621,15 +614,24 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     } else {
         dt = (float)c->P.dt_max;
     }
+
+    // 2. density, alpha, and (DFSPH) the divergence solve's warm start
+    {
+        ProfScope ps(c, "density_alpha", 80.0 * nf + list_bytes(c) + (dfsph && warm ? 12.0 * nf : 0.0));
+        HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, c->nlist, c->ncnt, c->xb, c->blist, c->bcnt, c->kc,
+                                             c->rho, c->alpha, c->v_in, c->Kv, c->kvr, dt, dfsph ? wf : 0.0f,
+                                             c->pci_c, s));
+    }
+    if (rebuild) {
+        HIP_TRY(c, hipEventSynchronize(c->build_done));
+        int rc = build_check(c);   // a capacity error leaves clamped, in-bounds lists behind
+        if (rc) return rc;
+    }
     // 3. divergence-free solve (DFSPH)
     int32_t iv = 0, id = 0;
     double ev = 0.0, ed = 0.0;
     int rc = SPH_OK;
     if (dfsph) {
-        if (warm) {
-            rc = pressure_pass(c, c->Kv, nullptr, dt, nullptr);
-            if (rc) return rc;
-        }
         rc = jacobi_solve(c, 0, dt, c->Kv, nullptr, c->forced_div, c->P.eta_divergence, &iv, &ev);
         if (rc) return rc;
     }
@@ -736,6 +738,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     }
     if (c->P.cfl_lambda > 0.0) {   // the next step's CFL input, read after its neighbour build
         HIP_TRY(c, sph::launch_max_v2(c->v, nf, (uint32_t *)c->red_part, c->hs_dev, s));
+        HIP_TRY(c, hipEventRecord(c->vmax_done, s));
         c->vmax_ready = true;
     }
     c->nbr_fresh = false;
@@ -902,7 +905,7 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
         return fail(nullptr, rc, m_);       \
     }
     ALLOC(c->x, nf); ALLOC(c->x2, nf); ALLOC(c->v, nf); ALLOC(c->v2, nf); ALLOC(c->v_in, nf);
-    ALLOC(c->rho, nf); ALLOC(c->alpha, nf); ALLOC(c->K, nf); ALLOC(c->K2, nf); ALLOC(c->Kv, nf); ALLOC(c->Kv2, nf);
+    ALLOC(c->rho, nf); ALLOC(c->rho2, nf); ALLOC(c->kvr, nf); ALLOC(c->alpha, nf); ALLOC(c->K, nf); ALLOC(c->K2, nf); ALLOC(c->Kv, nf); ALLOC(c->Kv2, nf);
     ALLOC(c->kappa, nf); ALLOC(c->kappa_last, nf); ALLOC(c->id, nf); ALLOC(c->id2, nf);
     ALLOC(c->key, nf); ALLOC(c->slot, nf); ALLOC(c->src, nf);
     ALLOC(c->count, ncell); ALLOC(c->start_f, ncell + 1); ALLOC(c->start_b, ncell + 1); ALLOC(c->scan_part, 2 * scan_chunks + 8);
@@ -930,7 +933,8 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
         delete c;
         return fail(nullptr, SPH_ERR_OOM, "pinned host allocation failed");
     }
-    if (hipEventCreateWithFlags(&c->build_done, hipEventDisableTiming) != hipSuccess) {
+    if (hipEventCreateWithFlags(&c->build_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->vmax_done, hipEventDisableTiming) != hipSuccess) {
         free_all(c);
         delete c;
         return fail(nullptr, SPH_ERR_DEVICE, "event creation failed");
@@ -946,12 +950,15 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
             hid[i] = (int32_t)i;
         }
         std::vector<float> zero(std::max<int64_t>(nf, 1), 0.0f);
+        // the "previous" density of the first step (its divergence warm start is zero)
+        std::vector<float> rho0v(std::max<int64_t>(nf, 1), (float)p->rho0);
         hipStream_t s = c->stream;
         bool ok = hipMemcpyAsync(c->x, hx.data(), sizeof(float4) * nf, hipMemcpyHostToDevice, s) == hipSuccess &&
                   hipMemcpyAsync(c->v, hv.data(), sizeof(float4) * nf, hipMemcpyHostToDevice, s) == hipSuccess &&
                   hipMemcpyAsync(c->id, hid.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, s) == hipSuccess &&
                   hipMemcpyAsync(c->K, zero.data(), sizeof(float) * nf, hipMemcpyHostToDevice, s) == hipSuccess &&
                   hipMemcpyAsync(c->Kv, zero.data(), sizeof(float) * nf, hipMemcpyHostToDevice, s) == hipSuccess &&
+                  hipMemcpyAsync(c->rho, rho0v.data(), sizeof(float) * nf, hipMemcpyHostToDevice, s) == hipSuccess &&
                   (!c->dvisc || hipMemsetAsync(c->dvisc, 0, sizeof(float4) * nf, s) == hipSuccess);
         // boundary: positions, velocities from the body state, body ids, local offsets
         c->rigid.assign(sc->rigid, sc->rigid + c->nr);

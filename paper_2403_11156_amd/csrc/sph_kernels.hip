@@ -138,11 +138,14 @@ __global__ void k_cell_sort(const uint32_t* __restrict__ start, int64_t ncell, u
     }
 }
 
+// Reorder the per-particle state by the permutation; kvro = Kv / rho, the
+// previous step's divergence stiffness over its density (the next warm start).
 __global__ void k_gather_fluid(const uint32_t* __restrict__ src, int64_t n, const float4* __restrict__ x,
                                const float4* __restrict__ v, const float* __restrict__ K,
-                               const float* __restrict__ Kv, const int32_t* __restrict__ id,
-                               const float4* __restrict__ dv, float4* __restrict__ xo, float4* __restrict__ vo,
-                               float* __restrict__ Ko, float* __restrict__ Kvo, int32_t* __restrict__ ido,
+                               const float* __restrict__ Kv, const float* __restrict__ rho,
+                               const int32_t* __restrict__ id, const float4* __restrict__ dv, float4* __restrict__ xo,
+                               float4* __restrict__ vo, float* __restrict__ Ko, float* __restrict__ Kvo,
+                               float* __restrict__ rhoo, float* __restrict__ kvro, int32_t* __restrict__ ido,
                                float4* __restrict__ dvo) {
     const int64_t i = particle_index();
     if (i >= n) return;
@@ -150,7 +153,10 @@ __global__ void k_gather_fluid(const uint32_t* __restrict__ src, int64_t n, cons
     xo[i] = x[s];
     vo[i] = v[s];
     Ko[i] = K[s];
-    Kvo[i] = Kv[s];
+    const float kv = Kv[s], r = rho[s];
+    Kvo[i] = kv;
+    rhoo[i] = r;
+    kvro[i] = kv / r;
     ido[i] = id[s];
     if (dv != nullptr) dvo[i] = dv[s];
 }
@@ -313,39 +319,55 @@ __global__ void k_max_v2(const float4* __restrict__ v, int64_t n, uint32_t* out_
 
 // Density with the Akinci boundary term, Eq. (12), and the DFSPH factor
 // alpha = rho / (|sum_F m gradW + sum_B Psi gradW|^2 + sum_F |m gradW|^2).
-// Also saves the step's input velocity, copies rho into v.w (the XSPH pass
-// then gathers a neighbour's velocity and density in one load) and sets up
-// the divergence warm start.
-template <int L>
+// Also saves the step's input velocity and copies rho into v.w (the XSPH
+// pass then gathers a neighbour's velocity and density in one load).  WARM:
+// the divergence solve's warm start in the same neighbour walk: its
+// stiffness over density, warm_factor Kv_prev / rho_prev (kvr, from the sort),
+// does not depend on this step's density, so its pressure (Eq. 7 with the
+// Eq. 13 boundary term) is applied here, and Kv starts at that times rho.
+template <int L, bool WARM>
 __global__ void __launch_bounds__(kBlock) k_density_alpha(
     int64_t nf, float4* __restrict__ x, float4* __restrict__ v, const uint32_t* __restrict__ nlist,
     const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const uint32_t* __restrict__ blist,
     const uint32_t* __restrict__ bcnt, Kern kc, float* __restrict__ rho, float* __restrict__ alpha,
-    float4* __restrict__ v_in, float* __restrict__ Kv, float* __restrict__ kappa, float warm_factor,
+    float4* __restrict__ v_in, float* __restrict__ Kv, const float* __restrict__ kvr, float dt, float warm_factor,
     float pci_c) {
     int q;
     const int64_t i = group_particle<L>(q);
     if (i >= nf) return;   // whole groups leave together
     const float4 xi = x[i];
+    const float kri = WARM ? warm_factor * kvr[i] : 0.0f;
     float r = 0.f, gx = 0.f, gy = 0.f, gz = 0.f, sq = 0.f;
+    float px = 0.f, py = 0.f, pz = 0.f;
     for_each_nbr_l<L>(nlist, nf, i, q, ncnt[i], [&](uint32_t j) {
         const float4 xj = x[j];
         const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
         r += kc.m * kernel_W(r2, kc);
-        const float F = kc.m * grad_factor(r2, kc);
+        const float g = grad_factor(r2, kc);
+        const float F = kc.m * g;
         const float ax = F * dx, ay = F * dy, az = F * dz;
         gx += ax; gy += ay; gz += az;
         sq += ax * ax + ay * ay + az * az;
+        if (WARM) {
+            const float c = (kri + warm_factor * kvr[j]) * g;
+            px += c * dx; py += c * dy; pz += c * dz;
+        }
     });
     float rb = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+    float pbx = 0.f, pby = 0.f, pbz = 0.f;
     for_each_nbr_l<L>(blist, nf, i, q, bcnt[i], [&](uint32_t kk) {
         const float4 xk = xb[kk];
         const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
         rb += xk.w * kernel_W(r2, kc);
-        const float F = xk.w * grad_factor(r2, kc);
+        const float g = grad_factor(r2, kc);
+        const float F = xk.w * g;
         bx += F * dx; by += F * dy; bz += F * dz;
+        if (WARM) {
+            const float c = xk.w * kri * g;
+            pbx += c * dx; pby += c * dy; pbz += c * dz;
+        }
     });
     // self term, fluid sum, boundary sum
     const float rr = (kc.m * kc.k + group_sum<L>(r)) + group_sum<L>(rb);
@@ -353,18 +375,23 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
     gy = group_sum<L>(gy) + group_sum<L>(by);
     gz = group_sum<L>(gz) + group_sum<L>(bz);
     sq = group_sum<L>(sq);
+    if (WARM) {
+        px = group_sum<L>(px) * kc.m + group_sum<L>(pbx);
+        py = group_sum<L>(py) * kc.m + group_sum<L>(pby);
+        pz = group_sum<L>(pz) * kc.m + group_sum<L>(pbz);
+    }
     if (q != 0) return;
     const float D = gx * gx + gy * gy + gz * gz + sq;
     rho[i] = rr;
     // PCISPH (pci_c > 0): the prototype factor c / rho replaces alpha
     alpha[i] = pci_c > 0.0f ? pci_c / rr : (D > 1e-6f ? rr / D : 0.0f);
-    const float4 vi = v[i];
+    float4 vi = v[i];
     v_in[i] = vi;
+    if (WARM) {
+        vi.x -= dt * px; vi.y -= dt * py; vi.z -= dt * pz;
+    }
     v[i] = make_float4(vi.x, vi.y, vi.z, rr);
-    const float k0 = warm_factor * Kv[i];
-    kappa[i] = k0;
-    Kv[i] = 0.0f;
-    x[i].w = k0 / rr;
+    Kv[i] = WARM ? kri * rr : 0.0f;
 }
 
 // Pressure velocity update (Eq. 7 with p/rho^2 = kappa/rho, the boundary term
@@ -1033,10 +1060,11 @@ hipError_t launch_cell_sort(const uint32_t* start, int64_t ncell, uint32_t* src,
 }
 
 hipError_t launch_gather_fluid(const uint32_t* src, int64_t n, const float4* x, const float4* v, const float* K,
-                               const float* Kv, const int32_t* id, const float4* dv, float4* xo, float4* vo,
-                               float* Ko, float* Kvo, int32_t* ido, float4* dvo, hipStream_t s) {
+                               const float* Kv, const float* rho, const int32_t* id, const float4* dv, float4* xo,
+                               float4* vo, float* Ko, float* Kvo, float* rhoo, float* kvro, int32_t* ido, float4* dvo,
+                               hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    LAUNCH(k_gather_fluid, n, src, n, x, v, K, Kv, id, dv, xo, vo, Ko, Kvo, ido, dvo);
+    LAUNCH(k_gather_fluid, n, src, n, x, v, K, Kv, rho, id, dv, xo, vo, Ko, Kvo, rhoo, kvro, ido, dvo);
 }
 
 hipError_t launch_gather_boundary(const uint32_t* src, int64_t n, const float4* x, const float4* v, const int32_t* id,
@@ -1071,11 +1099,17 @@ hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, HostSta
 
 hipError_t launch_density_alpha(int64_t nf, float4* x, float4* v, const uint32_t* nlist, const uint32_t* ncnt,
                                 const float4* xb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float* rho,
-                                float* alpha, float4* v_in, float* Kv, float* kappa, float warm_factor,
+                                float* alpha, float4* v_in, float* Kv, const float* kvr, float dt, float warm_factor,
                                 float pci_c, hipStream_t s) {
     if (nf <= 0) return hipSuccess;
-    LAUNCH(k_density_alpha<kLanesDensity>, kLanesDensity * nf, nf, x, v, nlist, ncnt, xb, blist, bcnt, kc, rho, alpha, v_in, Kv, kappa,
-           warm_factor, pci_c);
+    const dim3 grid(grid_blocks(kLanesDensity * nf)), block(kBlock);
+    if (warm_factor > 0.0f)
+        hipLaunchKernelGGL((k_density_alpha<kLanesDensity, true>), grid, block, 0, s, nf, x, v, nlist, ncnt, xb, blist,
+                           bcnt, kc, rho, alpha, v_in, Kv, kvr, dt, warm_factor, pci_c);
+    else
+        hipLaunchKernelGGL((k_density_alpha<kLanesDensity, false>), grid, block, 0, s, nf, x, v, nlist, ncnt, xb,
+                           blist, bcnt, kc, rho, alpha, v_in, Kv, kvr, dt, warm_factor, pci_c);
+    return hipGetLastError();
 }
 
 hipError_t launch_pressure_update(int64_t nf, const float4* x, float4* v, const float* kappa, float* Kacc,

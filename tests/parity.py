@@ -22,7 +22,7 @@ def ratio(gpu, ref, scale=None):
 
 def oracle_state_from_gpu(sim, scene, local):
     """Re-anchor: the oracle's FP32 input state is exactly the GPU's state."""
-    g = sim.read(("x", "v", "K", "Kv", "boundary", "rigid", "dvisc"))
+    g = sim.read(("x", "v", "K", "Kv", "rho", "boundary", "rigid", "dvisc"))
     st = O.State.__new__(O.State)
     st.params = dict(sim.params)
     st.x, st.v = g["x"], g["v"]
@@ -32,6 +32,7 @@ def oracle_state_from_gpu(sim, scene, local):
     st.local = local
     st.rigid = g.get("rigid", [])
     st.dvisc = g["dvisc"]
+    st.rho_prev = g["rho"]   # the previous step's density (the divergence warm start's)
     return st
 
 

@@ -600,3 +600,32 @@ def test_cg_start_half_previous_correction_saves_iterations():
             cold_it += O.step(st, params=cold_pd)["cg_iters"]
         st = O.advance(st, out)
     assert warm_it < 0.85 * cold_it, (warm_it, cold_it)
+
+
+def test_divergence_warm_start_uses_previous_stiffness_over_previous_density():
+    # R15: the divergence solve starts from kappa/rho = warm_factor Kv_prev /
+    # rho_prev; it accumulates as Kv0 = that times the step's density, and the
+    # fluid-only pressure impulse of the start sums to zero
+    r = 0.01
+    sc = scenes.make_block_scene("warm", r, (0, 0, 0), (0.4, 0.4, 0.4), (6, 6, 6), (0.1, 0.1, 0.1),
+                                 seed=12, steps=1, gravity=(0.0, 0.0, 0.0), visc_model=0,
+                                 cfl_lambda=0.0, dt_max=1e-3, warm_start=scenes.WARM_PREVIOUS)
+    st = O.State(sc)
+    rng = np.random.default_rng(13)
+    st.Kv = rng.uniform(0.0, 50.0, len(st.x)).astype(np.float32)
+    st.rho_prev = rng.uniform(980.0, 1020.0, len(st.x)).astype(np.float32)
+    st.v = rng.normal(0, 0.1, st.v.shape).astype(np.float32)
+    out = O.step(st, forced_div=0, forced_dens=0)
+    wf = sc.params["warm_factor"]
+    expect = wf * st.Kv.astype(np.float64) / st.rho_prev.astype(np.float64) * out["rho"]
+    np.testing.assert_allclose(out["Kv"], expect, rtol=1e-12)
+    m = 1000.0 * (2 * r) ** 3
+    dv = out["v"] - st.v
+    assert out["nb_count"].max() == 0 and np.abs(dv).max() > 0
+    assert np.abs(m * dv.sum(axis=0)).max() < 1e-10 * m * np.abs(dv).sum()
+    # a uniform rho_prev scales the applied start: rho_prev -> 2 rho_prev halves the velocity change
+    st2 = O.State(sc)
+    st2.Kv, st2.v = st.Kv, st.v
+    st2.rho_prev = 2.0 * st.rho_prev
+    out2 = O.step(st2, forced_div=0, forced_dens=0)
+    np.testing.assert_allclose(out2["v"] - st.v, 0.5 * dv, rtol=1e-9, atol=1e-15)
