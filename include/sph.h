@@ -90,7 +90,11 @@ typedef struct sph_mlp sph_mlp;
  *   cg_warm_factor  implicit viscosity: the CG starts from x0 = v~ + cg_warm_factor
  *                   times the previous step's correction v* - v~ (0: x0 = v~;
  *                   [0, 4]; the correction is SPH_FIELD_DVISC).
- *   warm_start      SPH_WARM_*; warm_factor scales the previous stiffness.
+ *   warm_start      SPH_WARM_*; warm_factor scales the previous stiffness
+ *                   (the density solve starts from warm_factor K_prev; the
+ *                   divergence solve from stiffness over density
+ *                   warm_factor Kv_prev / rho_prev, i.e. Kv0 = that times the
+ *                   step's density).
  *   max_neighbors, max_boundary_neighbors  list capacities per particle.
  *   auto_rebuild    1: sph_step rebuilds stale neighbour lists itself.
  *   solver          SPH_SOLVER_*.  WCSPH (Sec. 3.4.1): p_i = wcsph_k
