@@ -230,46 +230,58 @@ __global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk
 
 
 // Append the candidates c in [b, e) (ascending) with c != skip and the FP32
-// predicate d^2 < h^2 to particle i's list.  Accepted entries shift into buf
-// (oldest in buf.x) and go out as whole 16-byte chunks; list_flush stores the
-// last, partial one.  The body has no branch but the chunk store, so four
-// candidates' loads (one to three for the tail) issue ahead of the tests.
-// chunk points at the particle's next chunk (list chunk cnt/4 of particle i)
-// and steps by nf chunks per store.  cnt counts every neighbour, entries past
-// cap are dropped (the caller flags the overflow).  SKIP: the range may hold
-// the particle itself.
+// predicate d^2 < h^2 to particle i's list.  A range is tested 32 candidates
+// at a time into a bit mask (four candidates' loads issued ahead of the
+// tests; one to three for the tail), then the set bits are appended in
+// ascending order: the per-candidate work is the distance and one bit, the
+// list bookkeeping runs once per accepted neighbour.  Accepted entries shift
+// into buf (oldest in buf.x) and go out as whole 16-byte chunks; list_flush
+// stores the last, partial one.  chunk points at the particle's next chunk
+// (list chunk cnt/4 of particle i) and steps by nf chunks per store.  cnt
+// counts every neighbour, entries past cap are dropped (the caller flags the
+// overflow).  SKIP: the range may hold the particle itself.
 template <bool SKIP>
 __device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, uint32_t b, uint32_t e, float4 xi,
                                                 uint32_t skip, float h2, uint4*& chunk, int64_t nf, int32_t cap,
                                                 uint32_t& cnt, uint4& buf) {
-    auto take = [&](uint32_t c, float4 p, bool valid = true) {
-        const bool nb = valid & (!SKIP || c != skip) & (dist2_exact(xi, p) < h2);
-        const bool t = nb & (cnt < (uint32_t)cap);
-        buf.x = t ? buf.y : buf.x;
-        buf.y = t ? buf.z : buf.y;
-        buf.z = t ? buf.w : buf.z;
-        buf.w = t ? c : buf.w;
-        if (t & ((cnt & 3u) == 3u)) {
-            *chunk = buf;
-            chunk += nf;
+    for (uint32_t base = b; base < e; base += 32u) {
+        const uint32_t n = min(e - base, 32u);
+        const float4* q = pos + base;
+        uint32_t mask = 0u;
+        auto test = [&](uint32_t k, float4 p, bool valid) {
+            const bool nb = valid & (!SKIP || base + k != skip) & (dist2_exact(xi, p) < h2);
+            mask |= (nb ? 1u : 0u) << k;
+        };
+        uint32_t k = 0;
+        for (; k + 4 <= n; k += 4) {
+            const float4 p0 = q[k], p1 = q[k + 1], p2 = q[k + 2], p3 = q[k + 3];
+            test(k, p0, true);
+            test(k + 1, p1, true);
+            test(k + 2, p2, true);
+            test(k + 3, p3, true);
         }
-        cnt += nb ? 1u : 0u;
-    };
-    uint32_t c = b;
-    const float4* q = pos + b;
-    for (; c + 4 <= e; c += 4, q += 4) {
-        const float4 p0 = q[0], p1 = q[1], p2 = q[2], p3 = q[3];
-        take(c, p0);
-        take(c + 1, p1);
-        take(c + 2, p2);
-        take(c + 3, p3);
-    }
-    if (c < e) {   // one to three left: load them together (repeats of the last one stay in range)
-        const uint32_t n = e - c;
-        const float4 p0 = q[0], p1 = q[n > 1u ? 1 : 0], p2 = q[n > 2u ? 2 : 0];
-        take(c, p0);
-        take(c + 1, p1, n > 1u);
-        take(c + 2, p2, n > 2u);
+        if (k < n) {   // one to three left: load them together (repeats of the last one stay in range)
+            const uint32_t r = n - k;
+            const float4 p0 = q[k], p1 = q[k + (r > 1u ? 1 : 0)], p2 = q[k + (r > 2u ? 2 : 0)];
+            test(k, p0, true);
+            test(k + 1, p1, r > 1u);
+            test(k + 2, p2, r > 2u);
+        }
+        while (mask) {
+            const uint32_t j = (uint32_t)__builtin_ctz(mask);
+            mask &= mask - 1u;
+            if (cnt < (uint32_t)cap) {
+                buf.x = buf.y;
+                buf.y = buf.z;
+                buf.z = buf.w;
+                buf.w = base + j;
+                if ((cnt & 3u) == 3u) {
+                    *chunk = buf;
+                    chunk += nf;
+                }
+            }
+            ++cnt;
+        }
     }
 }
 
