@@ -240,13 +240,12 @@ __global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk
 // (list chunk cnt/4 of particle i) and steps by nf chunks per store.  cnt
 // counts every neighbour, entries past cap are dropped (the caller flags the
 // overflow).  SKIP: the range may hold the particle itself.
-template <bool SKIP>
-__device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, uint32_t b, uint32_t e, float4 xi,
-                                                uint32_t skip, float h2, uint4*& chunk, int64_t nf, int32_t cap,
-                                                uint32_t& cnt, uint4& buf) {
+template <bool SKIP, typename Load>
+__device__ __forceinline__ void scan_with(Load load, uint32_t b, uint32_t e, float4 xi, uint32_t skip, float h2,
+                                          uint4*& chunk, int64_t nf, int32_t cap, uint32_t& cnt, uint4& buf) {
     for (uint32_t base = b; base < e; base += 32u) {
         const uint32_t n = min(e - base, 32u);
-        const float4* q = pos + base;
+        auto q = [&](uint32_t k) { return load(base + k); };
         uint32_t mask = 0u;
         auto test = [&](uint32_t k, float4 p, bool valid) {
             const bool nb = valid & (!SKIP || base + k != skip) & (dist2_exact(xi, p) < h2);
@@ -254,7 +253,7 @@ __device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, 
         };
         uint32_t k = 0;
         for (; k + 4 <= n; k += 4) {
-            const float4 p0 = q[k], p1 = q[k + 1], p2 = q[k + 2], p3 = q[k + 3];
+            const float4 p0 = q(k), p1 = q(k + 1), p2 = q(k + 2), p3 = q(k + 3);
             test(k, p0, true);
             test(k + 1, p1, true);
             test(k + 2, p2, true);
@@ -262,7 +261,7 @@ __device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, 
         }
         if (k < n) {   // one to three left: load them together (repeats of the last one stay in range)
             const uint32_t r = n - k;
-            const float4 p0 = q[k], p1 = q[k + (r > 1u ? 1 : 0)], p2 = q[k + (r > 2u ? 2 : 0)];
+            const float4 p0 = q(k), p1 = q(k + (r > 1u ? 1 : 0)), p2 = q(k + (r > 2u ? 2 : 0));
             test(k, p0, true);
             test(k + 1, p1, r > 1u);
             test(k + 2, p2, r > 2u);
@@ -340,6 +339,30 @@ __device__ __forceinline__ void for_each_nbr_l(const uint32_t* __restrict__ list
         for (int u = 0; u < 4; ++u) f(j[u]);
     }
     for (; k < n; k += L) f(list[(((int64_t)(k >> 2) * nf + i) << 2) + (k & 3u)]);
+}
+
+// scan_with on candidates read from global memory
+template <bool SKIP>
+__device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, uint32_t b, uint32_t e, float4 xi,
+                                                uint32_t skip, float h2, uint4*& chunk, int64_t nf, int32_t cap,
+                                                uint32_t& cnt, uint4& buf) {
+    scan_with<SKIP>([&](uint32_t c) { return pos[c]; }, b, e, xi, skip, h2, chunk, nf, cap, cnt, buf);
+}
+
+// A wave's window of candidates staged in LDS: entry t of the window sits at
+// slot t + t/8 (one pad slot per eight spreads the lanes' reads of
+// neighbouring cells over the banks).
+constexpr uint32_t kWinCand = 192;
+constexpr uint32_t kWinSlots = kWinCand + kWinCand / 8;
+__device__ __forceinline__ uint32_t win_slot(uint32_t t) { return t + (t >> 3); }
+
+// LDS written by some lanes of a wave and read by others: order the two
+// (the LDS executes one wave's instructions in order; this keeps the
+// compiler from moving them across each other)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Store the partial last chunk of a list filled by scan_candidates: its k

@@ -181,43 +181,80 @@ __global__ void __launch_bounds__(kBlock) k_nbr_build(
     const uint32_t* __restrict__ start_b, Grid g, uint32_t* __restrict__ nlist, uint32_t* __restrict__ ncnt,
     int32_t capf, uint32_t* __restrict__ blist, uint32_t* __restrict__ bcnt, int32_t capb, uint32_t* flags,
     unsigned long long* __restrict__ stats) {
+    __shared__ float4 win_all[kBlock / 64][kWinSlots];
+    float4* win = win_all[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
     const int64_t i = particle_index();
+    const bool valid = i < nf;
     uint32_t total = 0xffffffffu, fl = 0;
-    if (i < nf) {
-        const float4 xi = x[i];
-        const int32_t cx = cell_coord(xi.x, g.o[0], g.inv, g.n[0]);
-        const int32_t cy = cell_coord(xi.y, g.o[1], g.inv, g.n[1]);
-        const int32_t cz = cell_coord(xi.z, g.o[2], g.inv, g.n[2]);
-        const int32_t x0 = cx > 0 ? cx - 1 : 0, x1 = cx < g.n[0] - 1 ? cx + 1 : g.n[0] - 1;
-        uint32_t nfc = 0, nbc = 0;
-        uint4 fbuf = make_uint4(0u, 0u, 0u, 0u), bbuf = make_uint4(0u, 0u, 0u, 0u);
-        uint4* fchunk = reinterpret_cast<uint4*>(nlist) + i;   // chunk 0 of particle i
-        uint4* bchunk = reinterpret_cast<uint4*>(blist) + i;
-        // the nine rows' candidate ranges, all loads issued before the scans
-        // (a row outside the grid reads row 0 and is made empty)
-        uint32_t fb[9], fe[9], bb[9], be[9];
+    // the wave's particles usually lie in consecutive cells of one row of the
+    // grid (sorted order, x fastest): then each of the nine stencil rows is
+    // one contiguous window of sorted particles for the whole wave, staged in
+    // LDS with coalesced loads, and the lanes test their candidates there
+    const float4 xi = valid ? x[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int32_t cx = cell_coord(xi.x, g.o[0], g.inv, g.n[0]);
+    const int32_t cy = cell_coord(xi.y, g.o[1], g.inv, g.n[1]);
+    const int32_t cz = cell_coord(xi.z, g.o[2], g.inv, g.n[2]);
+    const int32_t x0 = cx > 0 ? cx - 1 : 0, x1 = cx < g.n[0] - 1 ? cx + 1 : g.n[0] - 1;
+    const unsigned long long vmask = __ballot(valid);
+    const int src = vmask ? __ffsll((long long)vmask) - 1 : 0;
+    const int32_t cy0 = __shfl(cy, src, 64), cz0 = __shfl(cz, src, 64);
+    const bool one_row = vmask != 0ull && __all(!valid || (cy == cy0 && cz == cz0));
+    int32_t xlo = valid ? x0 : 0x7fffffff, xhi = valid ? x1 : -1;
+    for (int off = 32; off > 0; off >>= 1) {
+        xlo = min(xlo, __shfl_xor(xlo, off, 64));
+        xhi = max(xhi, __shfl_xor(xhi, off, 64));
+    }
+    uint32_t nfc = 0, nbc = 0;
+    uint4 fbuf = make_uint4(0u, 0u, 0u, 0u), bbuf = make_uint4(0u, 0u, 0u, 0u);
+    uint4* fchunk = reinterpret_cast<uint4*>(nlist) + i;   // chunk 0 of particle i
+    uint4* bchunk = reinterpret_cast<uint4*>(blist) + i;
+    // the nine rows' candidate ranges, all loads issued before the scans
+    // (a row outside the grid reads row 0 and is made empty)
+    uint32_t fb[9], fe[9], bb[9], be[9];
 #pragma unroll
-        for (int r = 0; r < 9; ++r) {
-            const int32_t z = cz + r / 3 - 1, y = cy + r % 3 - 1;
+    for (int r = 0; r < 9; ++r) {
+        const int32_t z = cz + r / 3 - 1, y = cy + r % 3 - 1;
+        const bool ok = valid && z >= 0 && z < g.n[2] && y >= 0 && y < g.n[1];
+        const int64_t row = ok ? (int64_t)g.n[0] * (y + (int64_t)g.n[1] * z) : 0;
+        fb[r] = start_f[row + x0];
+        fe[r] = start_f[row + x1 + 1];
+        bb[r] = start_b[row + x0];
+        be[r] = start_b[row + x1 + 1];
+        if (!ok) fe[r] = fb[r], be[r] = bb[r];
+    }
+    // only the middle row (dy = dz = 0) holds the particle itself
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        bool staged = false;
+        if (one_row) {   // wave-uniform
+            const int32_t z = cz0 + r / 3 - 1, y = cy0 + r % 3 - 1;
             const bool ok = z >= 0 && z < g.n[2] && y >= 0 && y < g.n[1];
             const int64_t row = ok ? (int64_t)g.n[0] * (y + (int64_t)g.n[1] * z) : 0;
-            fb[r] = start_f[row + x0];
-            fe[r] = start_f[row + x1 + 1];
-            bb[r] = start_b[row + x0];
-            be[r] = start_b[row + x1 + 1];
-            if (!ok) fe[r] = fb[r], be[r] = bb[r];
+            const uint32_t wb = ok ? start_f[row + xlo] : 0u, we = ok ? start_f[row + xhi + 1] : 0u;
+            if (we - wb <= kWinCand) {   // the window holds every lane's range [fb, fe)
+                wave_lds_sync();   // the previous row's reads are done
+                for (uint32_t t = lane; t < we - wb; t += 64) win[win_slot(t)] = x[wb + t];
+                wave_lds_sync();
+                auto ld = [&](uint32_t c) { return win[win_slot(c - wb)]; };
+                if (r == 4)
+                    scan_with<true>(ld, fb[r], fe[r], xi, (uint32_t)i, g.h2, fchunk, nf, capf, nfc, fbuf);
+                else
+                    scan_with<false>(ld, fb[r], fe[r], xi, 0u, g.h2, fchunk, nf, capf, nfc, fbuf);
+                staged = true;
+            }
         }
-        // only the middle row (dy = dz = 0) holds the particle itself
-#pragma unroll
-        for (int r = 0; r < 9; ++r) {
+        if (!staged) {
             if (r == 4)
                 scan_candidates<true>(x, fb[r], fe[r], xi, (uint32_t)i, g.h2, fchunk, nf, capf, nfc, fbuf);
             else
                 scan_candidates<false>(x, fb[r], fe[r], xi, 0u, g.h2, fchunk, nf, capf, nfc, fbuf);
         }
+    }
 #pragma unroll
-        for (int r = 0; r < 9; ++r)
-            scan_candidates<false>(xb, bb[r], be[r], xi, 0u, g.h2, bchunk, nf, capb, nbc, bbuf);
+    for (int r = 0; r < 9; ++r)
+        scan_candidates<false>(xb, bb[r], be[r], xi, 0u, g.h2, bchunk, nf, capb, nbc, bbuf);
+    if (valid) {
         list_flush(fchunk, capf, nfc, fbuf);
         list_flush(bchunk, capb, nbc, bbuf);
         // stored counts never exceed the capacity, so readers stay in bounds
