@@ -110,6 +110,14 @@ typedef struct sph_mlp sph_mlp;
  *                   eta_divergence applies to DFSPH only, eta_density and
  *                   warm_start to DFSPH and PCISPH; SPH_WARM_LEARNED needs
  *                   DFSPH (SPH_ERR_INVALID otherwise).
+ *   separate_div_check  0 (default): with explicit viscosity, when the
+ *                   previous step's divergence-free solve needed no
+ *                   iteration, the non-pressure pass also computes that
+ *                   solve's first error (both read the same velocities);
+ *                   if the error then calls for iterations they run and the
+ *                   non-pressure pass is repeated, so the step computes the
+ *                   same thing either way.  1: always run the check as a
+ *                   pass of its own.
  */
 typedef struct sph_params {
     double r, h, rho0;
@@ -129,6 +137,7 @@ typedef struct sph_params {
     int32_t solver;
     double wcsph_k, wcsph_gamma;
     double cg_warm_factor;
+    int32_t separate_div_check;
 } sph_params;
 
 /* A rigid body (Sec. 3.5): mass, principal moments of inertia (body frame,

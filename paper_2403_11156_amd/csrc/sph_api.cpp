@@ -83,6 +83,8 @@ struct sph_ctx {
     float4 *cg_b = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
     float4 *dvisc = nullptr, *dvisc2 = nullptr;   // previous correction v* - b, sorted order
     float *rho2 = nullptr, *kvr = nullptr;         // density ping-pong; Kv / rho of the previous step
+    float2 *div_kvs = nullptr;   // divergence check folded into the non-pressure pass: kappa_v, kappa_v / rho
+    float *K_saved = nullptr;    // and K as it was before the warm start's set-up
     double *cg_part = nullptr;                    // CG partial sums (mat-vec, then update)
 
     std::vector<sph_rigid_desc> rigid;
@@ -428,32 +430,36 @@ int predict_pass(sph_ctx *c, int mode, float dt, bool first, const sph::SolveCtl
     return SPH_OK;
 }
 
-// One Jacobi solve (Algorithm 2): stop when err <= eta, or after max_iters,
-// or after exactly `forced` iterations when forced >= 0.  The stop rule runs
-// on the device (SolveCtl): the host queues iterations in batches, sized by
-// the previous step's count for this solve, and reads the control block once
-// per batch; passes of iterations past the stop do nothing.
-int jacobi_solve(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, int32_t forced, double eta,
-                 int32_t *iters, double *err_out) {
-    hipStream_t s = c->stream;
+// Control block a solve starts from: err = scale * (sum of the clamped
+// deviations), the mean of Algorithm 2 (dt/rho0 for the divergence).
+sph::SolveCtl solve_init(const sph_ctx *c, int mode, float dt, int32_t forced, double eta) {
     const double N = (double)std::max<int64_t>(c->nf, 1);
-    const double scale = mode == 0 ? (double)dt / c->P.rho0 / N : 1.0 / (c->P.rho0 * N);
-    const int32_t cap = forced >= 0 ? forced : std::max(c->P.max_iters, 0);
     sph::SolveCtl init{};
-    init.scale = scale;
+    init.scale = mode == 0 ? (double)dt / c->P.rho0 / N : 1.0 / (c->P.rho0 * N);
     init.eta = eta;
     init.forced = forced;
     init.max_iters = c->P.max_iters;
     init.go = 1;
-    int rc = predict_pass(c, mode, dt, true, init);
-    if (rc) return rc;
+    return init;
+}
+
+// The iterations of a Jacobi solve whose first predict pass and finish are
+// queued: stop when err <= eta, or after max_iters, or after exactly
+// `forced` iterations when forced >= 0.  The stop rule runs on the device
+// (SolveCtl): the host queues iterations in batches (the first of
+// first_batch) and reads the control block once per batch; passes of
+// iterations past the stop do nothing.
+int jacobi_iterate(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, const sph::SolveCtl &init,
+                   int32_t first_batch, int32_t *iters, double *err_out) {
+    hipStream_t s = c->stream;
+    const int32_t cap = init.forced >= 0 ? init.forced : std::max(init.max_iters, 0);
     const size_t mark = c->prof_pending.size();
     int32_t queued = 0;
-    int32_t batch = std::min(c->last_iters[mode], cap);
+    int32_t batch = std::min(first_batch, cap);
     sph::SolveCtl h{};
     for (;;) {
         for (int32_t k = 0; k < batch; ++k) {
-            rc = pressure_pass(c, Kacc, klast, dt, &c->ctl->go);
+            int rc = pressure_pass(c, Kacc, klast, dt, &c->ctl->go);
             if (rc) return rc;
             rc = predict_pass(c, mode, dt, false, init);
             if (rc) return rc;
@@ -477,6 +483,17 @@ int jacobi_solve(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, int3
     *iters = h.iters;
     *err_out = h.err;
     return SPH_OK;
+}
+
+// One Jacobi solve (Algorithm 2): the first predict pass (the error of the
+// starting state), then the iterations, the first batch sized by the
+// previous step's count for this solve.
+int jacobi_solve(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, int32_t forced, double eta,
+                 int32_t *iters, double *err_out) {
+    const sph::SolveCtl init = solve_init(c, mode, dt, forced, eta);
+    int rc = predict_pass(c, mode, dt, true, init);
+    if (rc) return rc;
+    return jacobi_iterate(c, mode, dt, Kacc, klast, init, c->last_iters[mode], iters, err_out);
 }
 
 hipError_t visc_matvec(sph_ctx *c, const float4 *p, float4 *Mp, float dt, float mu, const int32_t *go,
@@ -627,11 +644,18 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         int rc = build_check(c);   // a capacity error leaves clamped, in-bounds lists behind
         if (rc) return rc;
     }
-    // 3. divergence-free solve (DFSPH)
+    // 3. divergence-free solve (DFSPH).  Its first predict pass reads the v
+    //    the explicit non-pressure pass reads too.  When the previous step's
+    //    solve needed no iteration, that pass takes the check over (fold);
+    //    should the error call for iterations after all, they run after it
+    //    and the non-pressure pass is queued again.
+    const bool implicit = c->P.visc_model == SPH_VISC_IMPLICIT;
+    const bool fold = dfsph && !implicit && !tracing && !c->P.separate_div_check && c->forced_div < 0 &&
+                      c->last_iters[0] == 0;
     int32_t iv = 0, id = 0;
     double ev = 0.0, ed = 0.0;
     int rc = SPH_OK;
-    if (dfsph) {
+    if (dfsph && !fold) {
         rc = jacobi_solve(c, 0, dt, c->Kv, nullptr, c->forced_div, c->P.eta_divergence, &iv, &ev);
         if (rc) return rc;
     }
@@ -646,9 +670,8 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     int32_t cg_it = 0;
     double cg_res = 0.0;
     const float gx = (float)c->P.gravity[0], gy = (float)c->P.gravity[1], gz = (float)c->P.gravity[2];
-    const bool implicit = c->P.visc_model == SPH_VISC_IMPLICIT;
     const bool wcsph = c->P.solver == SPH_SOLVER_WCSPH;
-    auto warm_setup = [&]() -> int {   // kappa = K0, K = 0, x.w = K0 / rho
+    auto warm_setup = [&](float *Ksave) -> int {   // kappa = K0, K = 0, x.w = K0 / rho
         const float alpha_ref = (float)(2.35376 * 4.0 * c->P.r * c->P.r / c->P.rho0);
         if (learned && !tracing) {   // features, network and start in one pass
             ProfScope ps(c, "mlp", 36.0 * nf);
@@ -673,13 +696,13 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
                 return SPH_OK;
             }
         }
-        HIP_TRY(c, sph::launch_warm_setup(nf, c->x, c->rho, c->K, c->kappa, wf, s));
+        HIP_TRY(c, sph::launch_warm_setup(nf, c->x, c->rho, c->K, c->kappa, wf, Ksave, s));
         return SPH_OK;
     };
     if (implicit) {
         rc = implicit_viscosity(c, dt, &cg_it, &cg_res);
         if (rc) return rc;
-        if (ppe && (rc = warm_setup())) return rc;
+        if (ppe && (rc = warm_setup(nullptr))) return rc;
         if (ppe && warm && (rc = pressure_pass(c, c->K, nullptr, dt, nullptr))) return rc;
         if (wcsph) {
             if ((rc = wcsph_eos(c))) return rc;
@@ -688,15 +711,53 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     } else {
         // the ZERO start only clears K and kappa, inside the pass
         const bool setup_in_pass = ppe && !warm && !(learned || tracing);
-        if (ppe && !setup_in_pass && (rc = warm_setup())) return rc;
-        if (wcsph && (rc = wcsph_eos(c))) return rc;
         const bool press = (ppe && warm) || wcsph;
-        ProfScope ps(c, "xsph", 72.0 * nf + (press ? 16.0 * nf + list_bytes(c) : fluid_list_bytes(c)));
-        HIP_TRY(c, sph::launch_nonpressure(c->P.visc_model, nf, c->x, c->v, c->v2, c->rho, c->nlist, c->ncnt,
-                                           c->kc, dt, gx, gy, gz, (float)c->P.visc, c->K, c->kappa, wf,
-                                           setup_in_pass, press, c->xb, c->blist, c->bcnt,
-                                           wcsph ? c->kappa_last : nullptr, s));
-        std::swap(c->v, c->v2);
+        auto nonpressure = [&](bool with_press, const sph::DivCheck *dc, int *nparts) -> int {
+            const double walk = (with_press || dc) ? list_bytes(c) : fluid_list_bytes(c);
+            ProfScope ps(c, "xsph", 72.0 * nf + (with_press ? 16.0 * nf : 0.0) + (dc ? 12.0 * nf : 0.0) + walk);
+            HIP_TRY(c, sph::launch_nonpressure(c->P.visc_model, nf, c->x, c->v, c->v2, c->rho, c->nlist, c->ncnt,
+                                               c->kc, dt, gx, gy, gz, (float)c->P.visc, c->K, c->kappa, wf,
+                                               setup_in_pass, with_press, c->xb, c->blist, c->bcnt,
+                                               wcsph ? c->kappa_last : nullptr, dc, nparts, s));
+            return SPH_OK;
+        };
+        if (!fold) {
+            if (ppe && !setup_in_pass && (rc = warm_setup(nullptr))) return rc;
+            if (wcsph && (rc = wcsph_eos(c))) return rc;
+            if ((rc = nonpressure(press, nullptr, nullptr))) return rc;
+            std::swap(c->v, c->v2);
+        } else {
+            // The learned start reads the check's D rho/Dt, so with it the
+            // pass applies no pressure: the network and the start's pressure
+            // pass follow.  Otherwise the start is set up first (K kept) and
+            // the pass applies its pressure as well.
+            const bool fold_press = press && !learned;
+            if (fold_press && (rc = warm_setup(c->K_saved))) return rc;
+            const sph::DivCheck dc{c->vb, c->alpha, c->div_kvs, c->want_d ? c->dbuf : nullptr, c->red_part};
+            int nparts = 0;
+            if ((rc = nonpressure(fold_press, &dc, &nparts))) return rc;
+            const sph::SolveCtl init = solve_init(c, 0, dt, c->forced_div, c->P.eta_divergence);
+            HIP_TRY(c, sph::launch_solve_finish(c->red_part, nparts, c->ctl, true, init, c->hs_dev, s));
+            HIP_TRY(c, hipStreamSynchronize(s));
+            const sph::SolveCtl h = c->hs->solve;
+            if (h.go) {   // iterations due: the state the separate check leaves, the solve, the pass again
+                if (fold_press)
+                    HIP_TRY(c, sph::launch_div_resume(nf, c->x, c->kappa, c->K, c->div_kvs, c->K_saved, s));
+                if ((rc = jacobi_iterate(c, 0, dt, c->Kv, nullptr, init, 1, &iv, &ev))) return rc;
+                if (ppe && !setup_in_pass && (rc = warm_setup(nullptr))) return rc;
+                if ((rc = nonpressure(press, nullptr, nullptr))) return rc;
+                std::swap(c->v, c->v2);
+            } else {
+                c->last_iters[0] = 0;
+                iv = 0;
+                ev = h.err;
+                std::swap(c->v, c->v2);
+                if (learned) {
+                    if ((rc = warm_setup(nullptr))) return rc;
+                    if ((rc = pressure_pass(c, c->K, nullptr, dt, nullptr))) return rc;
+                }
+            }
+        }
     }
     if (ppe) {
         HIP_TRY(c, sph::launch_fill_f32(c->kappa_last, nf, 0.0f, s));
@@ -832,6 +893,8 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
         return fail(nullptr, SPH_ERR_INVALID, "invalid parameter value");
     if (!(p->cg_warm_factor >= 0.0 && p->cg_warm_factor <= 4.0))
         return fail(nullptr, SPH_ERR_INVALID, "cg_warm_factor outside [0, 4]");
+    if (p->separate_div_check != 0 && p->separate_div_check != 1)
+        return fail(nullptr, SPH_ERR_INVALID, "separate_div_check must be 0 or 1");
     if (p->solver != SPH_SOLVER_DFSPH && p->warm_start == SPH_WARM_LEARNED)
         return fail(nullptr, SPH_ERR_INVALID, "the learned warm start needs the DFSPH solver");
     for (int a = 0; a < 3; ++a)
@@ -907,6 +970,7 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     ALLOC(c->x, nf); ALLOC(c->x2, nf); ALLOC(c->v, nf); ALLOC(c->v2, nf); ALLOC(c->v_in, nf);
     ALLOC(c->rho, nf); ALLOC(c->rho2, nf); ALLOC(c->kvr, nf); ALLOC(c->alpha, nf); ALLOC(c->K, nf); ALLOC(c->K2, nf); ALLOC(c->Kv, nf); ALLOC(c->Kv2, nf);
     ALLOC(c->kappa, nf); ALLOC(c->kappa_last, nf); ALLOC(c->id, nf); ALLOC(c->id2, nf);
+    ALLOC(c->div_kvs, nf); ALLOC(c->K_saved, nf);
     ALLOC(c->key, nf); ALLOC(c->slot, nf); ALLOC(c->src, nf);
     ALLOC(c->count, ncell); ALLOC(c->start_f, ncell + 1); ALLOC(c->start_b, ncell + 1); ALLOC(c->scan_part, 2 * scan_chunks + 8);
     // 32-bit lists in chunks of four entries (capacity rounded up to a chunk)

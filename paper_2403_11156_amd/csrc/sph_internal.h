@@ -147,13 +147,29 @@ hipError_t launch_solve_finish(const double* partials, int nblk, SolveCtl* ctl, 
 // (kappa = warm_factor K, K = 0, x.w = kappa / rho) when setup_warm and not press.
 // press: also the pressure pass of the stiffness already in x.w / kappa
 // (v* -= dt a_p, K += kappa, kappa_last = kappa when non-null).
+// Outputs of the divergence-free solve's first error pass when the
+// non-pressure pass takes it over (see k_nonpressure): boundary velocities
+// and alpha in; kappa_v and kappa_v/rho (kvs, with a pressure in the same
+// pass), D rho/Dt (dout, nullable) and the error partials out.
+struct DivCheck {
+    const float4* vb;
+    const float* alpha;
+    float2* kvs;
+    float* dout;
+    double* partials;
+};
+
+// div (nullable): also take the divergence check; *nparts = its partials.
 hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v, float4* vout, const float* rho,
                               const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float gx, float gy,
                               float gz, float visc, float* K, float* kappa, float warm_factor, bool setup_warm,
                               bool press, const float4* xb, const uint32_t* blist, const uint32_t* bcnt,
-                              float* kappa_last, hipStream_t s);
-hipError_t launch_warm_setup(int64_t nf, float4* x, const float* rho, float* K, float* kappa, float warm_factor,
+                              float* kappa_last, const DivCheck* div, int* nparts, hipStream_t s);
+hipError_t launch_div_resume(int64_t nf, float4* x, float* kappa, float* K, const float2* kvs, const float* Ksaved,
                              hipStream_t s);
+// Ksave (nullable): keep a copy of K before it is cleared.
+hipError_t launch_warm_setup(int64_t nf, float4* x, const float* rho, float* K, float* kappa, float warm_factor,
+                             float* Ksave, hipStream_t s);
 hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, hipStream_t s);
 hipError_t launch_rigid_force(int64_t nf, const float4* x, const float* rho, const float* K, const float* Kv,
                               const uint32_t* blist, const uint32_t* bcnt, const float4* xb, const float4* vb,

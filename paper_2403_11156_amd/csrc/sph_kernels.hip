@@ -537,83 +537,136 @@ __global__ void __launch_bounds__(kBlock) k_predict(
 // state), as k_pressure_update would right after it: v* -= dt (Eq. 7 with the
 // Eq. 13 boundary term), K += kappa, kappa_last = kappa.  Both sums read the
 // step's v and x, so one neighbour walk serves them.
-template <int MODEL, int L, bool PRESS>
+// DIV: the walk also takes the divergence-free solve's first error pass
+// (k_predict, mode 0) on the same v: D rho/Dt (Eq. 4 with the boundary
+// term), its stiffness kappa_v = max(D rho/Dt, 0) alpha / dt and the FP64
+// per-workgroup partials of the error.  kappa_v and kappa_v/rho go to
+// dc.kvs when PRESS (x.w is being read as the warm start's kappa/rho), else
+// to kappa and x.w as k_predict writes them; D rho/Dt to dc.dout if given.
+template <int MODEL, int L, bool PRESS, bool DIV>
 __global__ void __launch_bounds__(kBlock) k_nonpressure(
     int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, float4* __restrict__ vout,
     const float* __restrict__ rho, const uint32_t* __restrict__ nlist, const uint32_t* __restrict__ ncnt,
     Kern kc, float dt, float gx, float gy, float gz, float visc, float* __restrict__ K, float* __restrict__ kappa,
     float warm_factor, bool setup_warm, const float4* __restrict__ xb, const uint32_t* __restrict__ blist,
-    const uint32_t* __restrict__ bcnt, float* __restrict__ kappa_last) {
+    const uint32_t* __restrict__ bcnt, float* __restrict__ kappa_last, DivCheck dc) {
     int q;
     const int64_t i = group_particle<L>(q);
-    if (i >= nf) return;
-    const float4 xi = x[i];
-    const float4 vi = v[i];
-    const float kri = xi.w;   // kappa/rho (PRESS)
-    float ax = 0.f, ay = 0.f, az = 0.f;
-    float px = 0.f, py = 0.f, pz = 0.f;
-    if (MODEL == 1 || MODEL == 2 || PRESS) {
-        const float eps2 = 0.01f * kc.h * kc.h;
-        for_each_nbr_l<L>(nlist, nf, i, q, ncnt[i], [&](uint32_t j) {
-            const float4 xj = x[j];
-            const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-            const float r2 = dx * dx + dy * dy + dz * dz;
+    double e = 0.0;
+    if (i < nf) {   // whole groups
+        const float4 xi = x[i];
+        const float4 vi = v[i];
+        const float kri = xi.w;   // kappa/rho (PRESS)
+        float ax = 0.f, ay = 0.f, az = 0.f;
+        float px = 0.f, py = 0.f, pz = 0.f;
+        float dd = 0.f, db = 0.f;
+        if (MODEL == 1 || MODEL == 2 || PRESS || DIV) {
+            const float eps2 = 0.01f * kc.h * kc.h;
+            for_each_nbr_l<L>(nlist, nf, i, q, ncnt[i], [&](uint32_t j) {
+                const float4 xj = x[j];
+                const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                float4 vj;
+                if (MODEL == 1 || MODEL == 2 || DIV) vj = v[j];
+                if (MODEL == 1 || MODEL == 2) {
+                    const float mj = kc.m / vj.w;   // v.w = rho (density pass)
+                    if (MODEL == 1) {
+                        const float c = mj * kernel_W(r2, kc);
+                        ax += c * (vj.x - vi.x); ay += c * (vj.y - vi.y); az += c * (vj.z - vi.z);
+                    } else {
+                        const float vx = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
+                        const float c = mj * vx / (r2 + eps2) * grad_factor(r2, kc);
+                        ax += c * dx; ay += c * dy; az += c * dz;
+                    }
+                }
+                if (PRESS) {
+                    const float c = (kri + xj.w) * grad_factor(r2, kc);
+                    px += c * dx; py += c * dy; pz += c * dz;
+                }
+                if (DIV)
+                    dd += grad_factor(r2, kc) * ((vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz);
+            });
             if (MODEL == 1 || MODEL == 2) {
-                const float4 vj = v[j];
-                const float mj = kc.m / vj.w;   // v.w = rho (density pass)
-                if (MODEL == 1) {
-                    const float c = mj * kernel_W(r2, kc);
-                    ax += c * (vj.x - vi.x); ay += c * (vj.y - vi.y); az += c * (vj.z - vi.z);
+                ax = group_sum<L>(ax); ay = group_sum<L>(ay); az = group_sum<L>(az);
+            }
+        }
+        if (PRESS || DIV) {
+            float bx = 0.f, by = 0.f, bz = 0.f;
+            for_each_nbr_l<L>(blist, nf, i, q, bcnt[i], [&](uint32_t kk) {
+                const float4 xk = xb[kk];
+                const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                if (PRESS) {
+                    const float c = xk.w * kri * grad_factor(r2, kc);
+                    bx += c * dx; by += c * dy; bz += c * dz;
+                }
+                if (DIV) {
+                    const float4 vk = dc.vb[kk];
+                    db += xk.w * grad_factor(r2, kc) * ((vi.x - vk.x) * dx + (vi.y - vk.y) * dy + (vi.z - vk.z) * dz);
+                }
+            });
+            if (PRESS) {
+                px = group_sum<L>(px) * kc.m + group_sum<L>(bx);
+                py = group_sum<L>(py) * kc.m + group_sum<L>(by);
+                pz = group_sum<L>(pz) * kc.m + group_sum<L>(bz);
+            }
+            if (DIV) dd = group_sum<L>(dd) * kc.m + group_sum<L>(db);
+        }
+        if (q == 0) {
+            float s = 0.f;
+            if (MODEL == 1) s = visc;
+            if (MODEL == 2) s = dt * visc * 2.0f * (3 + 2);
+            float4 o;
+            o.x = vi.x + dt * gx + s * ax;
+            o.y = vi.y + dt * gy + s * ay;
+            o.z = vi.z + dt * gz + s * az;
+            o.w = 0.f;
+            if (PRESS) {
+                o.x -= dt * px; o.y -= dt * py; o.z -= dt * pz;
+                const float ki = kappa[i];
+                K[i] += ki;
+                if (kappa_last) kappa_last[i] = ki;
+            }
+            vout[i] = o;
+            if (!PRESS && setup_warm) {
+                const float k0 = warm_factor * K[i];
+                kappa[i] = k0;
+                K[i] = 0.0f;
+                x[i].w = k0 / rho[i];
+            }
+            if (DIV) {
+                const float ri = rho[i];
+                if (dc.dout) dc.dout[i] = dd;
+                const float ep = fmaxf(dd, 0.0f);
+                const float kap = ep * dc.alpha[i] / dt;
+                e = (double)ep;
+                if (PRESS) {
+                    dc.kvs[i] = make_float2(kap, kap / ri);
                 } else {
-                    const float vx = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
-                    const float c = mj * vx / (r2 + eps2) * grad_factor(r2, kc);
-                    ax += c * dx; ay += c * dy; az += c * dz;
+                    kappa[i] = kap;
+                    x[i].w = kap / ri;
                 }
             }
-            if (PRESS) {
-                const float c = (kri + xj.w) * grad_factor(r2, kc);
-                px += c * dx; py += c * dy; pz += c * dz;
-            }
-        });
-        if (MODEL == 1 || MODEL == 2) {
-            ax = group_sum<L>(ax); ay = group_sum<L>(ay); az = group_sum<L>(az);
         }
     }
-    if (PRESS) {
-        float bx = 0.f, by = 0.f, bz = 0.f;
-        for_each_nbr_l<L>(blist, nf, i, q, bcnt[i], [&](uint32_t kk) {
-            const float4 xk = xb[kk];
-            const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float c = xk.w * kri * grad_factor(r2, kc);
-            bx += c * dx; by += c * dy; bz += c * dz;
-        });
-        px = group_sum<L>(px) * kc.m + group_sum<L>(bx);
-        py = group_sum<L>(py) * kc.m + group_sum<L>(by);
-        pz = group_sum<L>(pz) * kc.m + group_sum<L>(bz);
+    if (DIV) {
+        const double bs = block_sum(e);
+        if (threadIdx.x == 0) dc.partials[blockIdx.x] = bs;
     }
-    if (q != 0) return;
-    float s = 0.f;
-    if (MODEL == 1) s = visc;
-    if (MODEL == 2) s = dt * visc * 2.0f * (3 + 2);
-    float4 o;
-    o.x = vi.x + dt * gx + s * ax;
-    o.y = vi.y + dt * gy + s * ay;
-    o.z = vi.z + dt * gz + s * az;
-    o.w = 0.f;
-    if (PRESS) {
-        o.x -= dt * px; o.y -= dt * py; o.z -= dt * pz;
-        const float ki = kappa[i];
-        K[i] += ki;
-        if (kappa_last) kappa_last[i] = ki;
-    }
-    vout[i] = o;
-    if (!PRESS && setup_warm) {
-        const float k0 = warm_factor * K[i];
-        kappa[i] = k0;
-        K[i] = 0.0f;
-        x[i].w = k0 / rho[i];
-    }
+}
+
+// After a folded divergence check (k_nonpressure with PRESS and DIV) whose
+// error calls for iterations: the state the separate check would have left
+// for them (kappa = kappa_v, x.w = kappa_v/rho) and the K the warm start's
+// set-up had saved.
+__global__ void k_div_resume(int64_t nf, float4* __restrict__ x, float* __restrict__ kappa, float* __restrict__ K,
+                             const float2* __restrict__ kvs, const float* __restrict__ Ksaved) {
+    const int64_t i = particle_index();
+    if (i >= nf) return;
+    const float2 kv = kvs[i];
+    kappa[i] = kv.x;
+    x[i].w = kv.y;
+    K[i] = Ksaved[i];
 }
 
 // Learned warm start, features of each particle at the start of the density
@@ -1030,10 +1083,13 @@ __global__ void k_cg_direction(int64_t nf, float4* __restrict__ p, const float4*
 }
 
 __global__ void k_warm_setup(int64_t nf, float4* __restrict__ x, const float* __restrict__ rho,
-                             float* __restrict__ K, float* __restrict__ kappa, float warm_factor) {
+                             float* __restrict__ K, float* __restrict__ kappa, float warm_factor,
+                             float* __restrict__ Ksave) {
     const int64_t i = particle_index();
     if (i >= nf) return;
-    const float k0 = warm_factor * K[i];
+    const float Ki = K[i];
+    if (Ksave) Ksave[i] = Ki;
+    const float k0 = warm_factor * Ki;
     kappa[i] = k0;
     K[i] = 0.0f;
     x[i].w = k0 / rho[i];
@@ -1195,27 +1251,43 @@ hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v,
                               const uint32_t* nlist, const uint32_t* ncnt, Kern kc, float dt, float gx, float gy,
                               float gz, float visc, float* K, float* kappa, float warm_factor, bool setup_warm,
                               bool press, const float4* xb, const uint32_t* blist, const uint32_t* bcnt,
-                              float* kappa_last, hipStream_t s) {
+                              float* kappa_last, const DivCheck* div, int* nparts, hipStream_t s) {
+    if (nparts) *nparts = 0;
     if (nf <= 0) return hipSuccess;
     const dim3 block(kBlock);
-#define NONPRESSURE(M, P)                                                                                         \
-    hipLaunchKernelGGL((k_nonpressure<M, P ? kLanesXsphPress : kLanesXsph, P>),                                   \
-                       dim3(grid_blocks((P ? kLanesXsphPress : kLanesXsph) * nf)), block, 0, s, nf, x, v, vout, rho, \
-                       nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa, warm_factor, setup_warm, xb, blist, bcnt,    \
-                       kappa_last)
-    if (model == 1) {
-        if (press) NONPRESSURE(1, true); else NONPRESSURE(1, false);
-    } else if (model == 2) {
-        if (press) NONPRESSURE(2, true); else NONPRESSURE(2, false);
-    } else if (press) {
-        NONPRESSURE(0, true);
-    } else {   // gravity only: no neighbour walk, one lane per particle
-        hipLaunchKernelGGL((k_nonpressure<0, 1, false>), dim3(grid_blocks(nf)), block, 0, s, nf, x, v, vout, rho,
-                           nlist, ncnt, kc, dt, gx, gy, gz, visc, K, kappa, warm_factor, setup_warm, xb, blist, bcnt,
-                           kappa_last);
-    }
+    const DivCheck dc = div ? *div : DivCheck{};
+#define NONPRESSURE(M, P, D)                                                                                      \
+    do {                                                                                                          \
+        constexpr int lanes = (M == 0 && !P && !D) ? 1 : (P ? kLanesXsphPress : kLanesXsph);                      \
+        const uint32_t nblk = grid_blocks(lanes * nf);                                                            \
+        if (nparts) *nparts = (int)nblk;                                                                          \
+        hipLaunchKernelGGL((k_nonpressure<M, lanes, P, D>), dim3(nblk), block, 0, s, nf, x, v, vout, rho, nlist,  \
+                           ncnt, kc, dt, gx, gy, gz, visc, K, kappa, warm_factor, setup_warm, xb, blist, bcnt,    \
+                           kappa_last, dc);                                                                       \
+    } while (0)
+#define NONPRESSURE_M(M)                                       \
+    do {                                                       \
+        if (press) {                                           \
+            if (div) NONPRESSURE(M, true, true);               \
+            else NONPRESSURE(M, true, false);                  \
+        } else {                                               \
+            if (div) NONPRESSURE(M, false, true);              \
+            else NONPRESSURE(M, false, false);                 \
+        }                                                      \
+    } while (0)
+    // model 0 without pressure or check: gravity only, one lane per particle
+    if (model == 1) NONPRESSURE_M(1);
+    else if (model == 2) NONPRESSURE_M(2);
+    else NONPRESSURE_M(0);
+#undef NONPRESSURE_M
 #undef NONPRESSURE
     return hipGetLastError();
+}
+
+hipError_t launch_div_resume(int64_t nf, float4* x, float* kappa, float* K, const float2* kvs, const float* Ksaved,
+                             hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    LAUNCH(k_div_resume, nf, nf, x, kappa, K, kvs, Ksaved);
 }
 
 hipError_t launch_features(int64_t nf, const float* rho, const float* alpha, const float* K, const uint32_t* ncnt,
@@ -1237,9 +1309,9 @@ hipError_t launch_trace_target(int64_t nf, const float* alpha, const float* K, f
 }
 
 hipError_t launch_warm_setup(int64_t nf, float4* x, const float* rho, float* K, float* kappa, float warm_factor,
-                             hipStream_t s) {
+                             float* Ksave, hipStream_t s) {
     if (nf <= 0) return hipSuccess;
-    LAUNCH(k_warm_setup, nf, nf, x, rho, K, kappa, warm_factor);
+    LAUNCH(k_warm_setup, nf, nf, x, rho, K, kappa, warm_factor, Ksave);
 }
 
 hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, hipStream_t s) {

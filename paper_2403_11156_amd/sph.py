@@ -40,6 +40,7 @@ class sph_params(C.Structure):
         ("auto_rebuild", C.c_int32),
         ("solver", C.c_int32), ("wcsph_k", C.c_double), ("wcsph_gamma", C.c_double),
         ("cg_warm_factor", C.c_double),
+        ("separate_div_check", C.c_int32),
     ]
 
 
@@ -202,6 +203,7 @@ def make_params(pd: Dict) -> sph_params:
     p.wcsph_k = pd.get("wcsph_k", 2.8e5)
     p.wcsph_gamma = pd.get("wcsph_gamma", 7.0)
     p.cg_warm_factor = pd.get("cg_warm_factor", 0.0)
+    p.separate_div_check = pd.get("separate_div_check", 0)
     return p
 
 

@@ -1,0 +1,120 @@
+"""The divergence-free solve's first error pass folded into the explicit
+non-pressure pass (separate_div_check = 0): both outcomes of the fold -- the
+error allows no iteration, or it calls for iterations, which then run before
+the non-pressure pass is queued again -- against the FP64 oracle step by step
+(re-anchored), for the three warm starts; and the same sequence with the
+check as a pass of its own."""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from oracle import oracle as O
+from paper_2403_11156_amd import scenes
+
+from tests.parity import compare_step, oracle_state_from_gpu
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2403_11156_amd",
+                       "weights", "warm_start_mlp.f32")
+
+
+@pytest.fixture(scope="module")
+def sph():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2403_11156_amd import sph as mod
+    O.build(force=False)
+    return mod
+
+
+def _compress(sim, rate):
+    """v += rate (c - x): a uniform compression, D rho/Dt = 3 rate rho."""
+    g = sim.read(("x", "v"))
+    c = g["x"].mean(axis=0)
+    v = (g["v"] + np.float32(rate) * (c - g["x"])).astype(np.float32)
+    sim.write(v=v)
+
+
+@pytest.mark.parametrize("separate", [0, 1])
+@pytest.mark.parametrize("arm", ["previous", "zero", "learned"])
+def test_fold_outcomes_match_oracle(sph, arm, separate):
+    sc = scenes.scene("c1")
+    warm = {"previous": 1, "zero": 0, "learned": 2}[arm]
+    params = dict(sc.params, warm_start=warm if warm != 2 else 1, separate_div_check=separate)
+    sim = sph.Simulation(sc, params=params)
+    net, cb = None, None
+    if arm == "learned":
+        w = np.fromfile(WEIGHTS, dtype=np.float32)
+        net = sph.MLP(w)
+        cb = M.step_callback(w)
+    local = O.rigid_local(sc.x_boundary, sc.body_of_boundary, sc.rigid)
+    prev_div = 0
+    perturbed = False
+    outcomes = set()
+    worst = {}
+    for k in range(7):
+        # compress once a step follows one whose divergence solve did not
+        # iterate, so the fold is taken and its error calls for iterations
+        if k >= 3 and not perturbed and prev_div == 0:
+            _compress(sim, 5.0)
+            perturbed = True
+        sim.build_neighbors()
+        if arm == "learned" and k == 1:
+            sim.set_warm_start(2, net)
+        state = oracle_state_from_gpu(sim, sc, local)
+        folded = separate == 0 and prev_div == 0
+        print(f"[fold] arm={arm} separate={separate} step={k} folded={folded}", flush=True)
+        st = sim.step()
+        g = sim.read()
+        pd = dict(state.params, warm_start=2 if (arm == "learned" and k >= 1) else params["warm_start"])
+        ref = O.step(state, forced_div=st["iters_div"], forced_dens=st["iters_dens"], params=pd,
+                     mlp=cb if pd["warm_start"] == 2 else None)
+        r = compare_step(g, ref, st)
+        for f, v in r.items():
+            worst[f] = max(worst.get(f, 0.0), v)
+        assert st["err_div"] <= params["eta_divergence"] or st["iters_div"] == params["max_iters"]
+        if folded:
+            outcomes.add("iterate" if st["iters_div"] > 0 else "done")
+        prev_div = st["iters_div"]
+    print(arm, separate, "outcomes", sorted(outcomes), "worst", worst, flush=True)
+    for f, v in worst.items():
+        assert v <= 1.0, (f, v)
+    assert perturbed
+    if separate == 0:
+        assert outcomes == {"iterate", "done"}, outcomes
+    sim.close()
+    if net is not None:
+        net.close()
+
+
+def test_fold_same_decisions_as_separate(sph):
+    """Both forms take the same stop decisions and reach the same state up to
+    FP32 rounding: over four steps of c1 (the fused pass contracts its sums
+    differently; 2e-5 of each field's largest magnitude, twice the per-step
+    parity tolerance), and, in decisions, over four more after a strong
+    compression (its pressure response amplifies rounding differences)."""
+    runs = []
+    for separate in (0, 1):
+        sc = scenes.scene("c1")
+        sim = sph.Simulation(sc, params=dict(sc.params, separate_div_check=separate))
+        stats = []
+        before = None
+        for k in range(8):
+            if k == 4:
+                before = sim.read(("x", "v", "K", "Kv"))
+                _compress(sim, 5.0)
+            sim.build_neighbors()
+            stats.append(sim.step())
+        runs.append((before, stats))
+        sim.close()
+    for a, b in zip(runs[0][1], runs[1][1]):
+        for key in ("iters_div", "iters_dens"):
+            assert a[key] == b[key], (key, a[key], b[key])
+    for f in ("x", "v", "K", "Kv"):
+        x0, x1 = runs[0][0][f].astype(np.float64), runs[1][0][f].astype(np.float64)
+        scale = np.abs(x1).max() + 1e-30
+        assert np.abs(x0 - x1).max() <= 2e-5 * scale, (f, np.abs(x0 - x1).max(), scale)
