@@ -183,8 +183,10 @@ hipEvent_t take_event(sph_ctx *c) {
         c->event_pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fence (an L2 write-back and invalidate
+    // around every timed kernel would slow the kernels that follow)
     hipEvent_t e = nullptr;
-    (void)hipEventCreate(&e);
+    (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     return e;
 }
 
