@@ -82,7 +82,7 @@ struct sph_ctx {
     float *Pinv = nullptr;
     float4 *cg_b = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
     float4 *dvisc = nullptr, *dvisc2 = nullptr;   // previous correction v* - b, sorted order
-    float *rho2 = nullptr, *kvr = nullptr;         // density ping-pong; Kv / rho of the previous step
+    float *rho2 = nullptr;                        // density ping-pong
     float2 *div_kvs = nullptr;   // divergence check folded into the non-pressure pass: kappa_v, kappa_v / rho
     float *K_saved = nullptr;    // and K as it was before the warm start's set-up
     double *cg_part = nullptr;                    // CG partial sums (mat-vec, then update)
@@ -329,7 +329,7 @@ int sort_fluid(sph_ctx *c) {
     HIP_TRY(c, sph::launch_scatter(c->key, c->slot, c->start_f, c->nf, c->src, s));
     HIP_TRY(c, sph::launch_cell_sort(c->start_f, c->ncell, c->src, c->id, c->flags, s));
     HIP_TRY(c, sph::launch_gather_fluid(c->src, c->nf, c->x, c->v, c->K, c->Kv, c->rho, c->id, c->dvisc, c->x2, c->v2,
-                                        c->K2, c->Kv2, c->rho2, c->kvr, c->id2, c->dvisc2, s));
+                                        c->K2, c->Kv2, c->rho2, c->id2, c->dvisc2, s));
     std::swap(c->dvisc, c->dvisc2);
     std::swap(c->rho, c->rho2);
     std::swap(c->x, c->x2);
@@ -638,7 +638,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     {
         ProfScope ps(c, "density_alpha", 80.0 * nf + list_bytes(c) + (dfsph && warm ? 12.0 * nf : 0.0));
         HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, c->nlist, c->ncnt, c->xb, c->blist, c->bcnt, c->kc,
-                                             c->rho, c->alpha, c->v_in, c->Kv, c->kvr, dt, dfsph ? wf : 0.0f,
+                                             c->rho, c->alpha, c->v_in, c->Kv, dt, dfsph ? wf : 0.0f,
                                              c->pci_c, s));
     }
     if (rebuild) {
@@ -970,7 +970,7 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
         return fail(nullptr, rc, m_);       \
     }
     ALLOC(c->x, nf); ALLOC(c->x2, nf); ALLOC(c->v, nf); ALLOC(c->v2, nf); ALLOC(c->v_in, nf);
-    ALLOC(c->rho, nf); ALLOC(c->rho2, nf); ALLOC(c->kvr, nf); ALLOC(c->alpha, nf); ALLOC(c->K, nf); ALLOC(c->K2, nf); ALLOC(c->Kv, nf); ALLOC(c->Kv2, nf);
+    ALLOC(c->rho, nf); ALLOC(c->rho2, nf); ALLOC(c->alpha, nf); ALLOC(c->K, nf); ALLOC(c->K2, nf); ALLOC(c->Kv, nf); ALLOC(c->Kv2, nf);
     ALLOC(c->kappa, nf); ALLOC(c->kappa_last, nf); ALLOC(c->id, nf); ALLOC(c->id2, nf);
     ALLOC(c->div_kvs, nf); ALLOC(c->K_saved, nf);
     ALLOC(c->key, nf); ALLOC(c->slot, nf); ALLOC(c->src, nf);

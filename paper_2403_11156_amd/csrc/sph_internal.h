@@ -95,10 +95,10 @@ hipError_t launch_scatter(const uint32_t* key, const uint32_t* slot, const uint3
 hipError_t launch_cell_sort(const uint32_t* start, int64_t ncell, uint32_t* src, const int32_t* id,
                             uint32_t* flags, hipStream_t s);
 // dv/dvo (nullable): the implicit-viscosity correction, carried along;
-// kvro = Kv / rho (the next divergence warm start)
+// xo.w = Kv / rho (the next divergence warm start)
 hipError_t launch_gather_fluid(const uint32_t* src, int64_t n, const float4* x, const float4* v, const float* K,
                                const float* Kv, const float* rho, const int32_t* id, const float4* dv, float4* xo,
-                               float4* vo, float* Ko, float* Kvo, float* rhoo, float* kvro, int32_t* ido, float4* dvo,
+                               float4* vo, float* Ko, float* Kvo, float* rhoo, int32_t* ido, float4* dvo,
                                hipStream_t s);
 hipError_t launch_gather_boundary(const uint32_t* src, int64_t n, const float4* x, const float4* v,
                                   const int32_t* id, float4* xo, float4* vo, int32_t* ido, hipStream_t s);
@@ -113,11 +113,11 @@ hipError_t launch_boundary_psi(float4* xb, int64_t nb, const uint32_t* start_b, 
 // the step
 hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, HostStatus* host, hipStream_t s);
 // density, alpha; with warm_factor > 0 also the divergence warm start's
-// pressure from kvr (Kv_prev / rho_prev) and Kv = warm_factor kvr rho
+// pressure from x.w (Kv_prev / rho_prev) and Kv = warm_factor x.w rho
 hipError_t launch_density_alpha(int64_t nf, float4* x, float4* v, const uint32_t* nlist,
                                 const uint32_t* ncnt, const float4* xb, const uint32_t* blist,
                                 const uint32_t* bcnt, Kern kc, float* rho, float* alpha, float4* v_in,
-                                float* Kv, const float* kvr, float dt, float warm_factor, float pci_c, hipStream_t s);
+                                float* Kv, float dt, float warm_factor, float pci_c, hipStream_t s);
 // go (nullable): the pass does nothing when *go == 0 (an iteration the
 // solve no longer needs).
 hipError_t launch_pressure_update(int64_t nf, const float4* x, float4* v, const float* kappa, float* Kacc,

@@ -138,25 +138,24 @@ __global__ void k_cell_sort(const uint32_t* __restrict__ start, int64_t ncell, u
     }
 }
 
-// Reorder the per-particle state by the permutation; kvro = Kv / rho, the
+// Reorder the per-particle state by the permutation; x.w = Kv / rho, the
 // previous step's divergence stiffness over its density (the next warm start).
 __global__ void k_gather_fluid(const uint32_t* __restrict__ src, int64_t n, const float4* __restrict__ x,
                                const float4* __restrict__ v, const float* __restrict__ K,
                                const float* __restrict__ Kv, const float* __restrict__ rho,
                                const int32_t* __restrict__ id, const float4* __restrict__ dv, float4* __restrict__ xo,
                                float4* __restrict__ vo, float* __restrict__ Ko, float* __restrict__ Kvo,
-                               float* __restrict__ rhoo, float* __restrict__ kvro, int32_t* __restrict__ ido,
-                               float4* __restrict__ dvo) {
+                               float* __restrict__ rhoo, int32_t* __restrict__ ido, float4* __restrict__ dvo) {
     const int64_t i = particle_index();
     if (i >= n) return;
     const uint32_t s = src[i];
-    xo[i] = x[s];
+    const float kv = Kv[s], r = rho[s];
+    const float4 xs = x[s];
+    xo[i] = make_float4(xs.x, xs.y, xs.z, kv / r);
     vo[i] = v[s];
     Ko[i] = K[s];
-    const float kv = Kv[s], r = rho[s];
     Kvo[i] = kv;
     rhoo[i] = r;
-    kvro[i] = kv / r;
     ido[i] = id[s];
     if (dv != nullptr) dvo[i] = dv[s];
 }
@@ -359,7 +358,7 @@ __global__ void k_max_v2(const float4* __restrict__ v, int64_t n, uint32_t* out_
 // Also saves the step's input velocity and copies rho into v.w (the XSPH
 // pass then gathers a neighbour's velocity and density in one load).  WARM:
 // the divergence solve's warm start in the same neighbour walk: its
-// stiffness over density, warm_factor Kv_prev / rho_prev (kvr, from the sort),
+// stiffness over density, warm_factor Kv_prev / rho_prev (x.w, from the sort),
 // does not depend on this step's density, so its pressure (Eq. 7 with the
 // Eq. 13 boundary term) is applied here, and Kv starts at that times rho.
 template <int L, bool WARM>
@@ -367,13 +366,13 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
     int64_t nf, float4* __restrict__ x, float4* __restrict__ v, const uint32_t* __restrict__ nlist,
     const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const uint32_t* __restrict__ blist,
     const uint32_t* __restrict__ bcnt, Kern kc, float* __restrict__ rho, float* __restrict__ alpha,
-    float4* __restrict__ v_in, float* __restrict__ Kv, const float* __restrict__ kvr, float dt, float warm_factor,
+    float4* __restrict__ v_in, float* __restrict__ Kv, float dt, float warm_factor,
     float pci_c) {
     int q;
     const int64_t i = group_particle<L>(q);
     if (i >= nf) return;   // whole groups leave together
     const float4 xi = x[i];
-    const float kri = WARM ? warm_factor * kvr[i] : 0.0f;
+    const float kri = WARM ? warm_factor * xi.w : 0.0f;   // x.w = Kv_prev / rho_prev (from the sort)
     float r = 0.f, gx = 0.f, gy = 0.f, gz = 0.f, sq = 0.f;
     float px = 0.f, py = 0.f, pz = 0.f;
     for_each_nbr_l<L>(nlist, nf, i, q, ncnt[i], [&](uint32_t j) {
@@ -387,7 +386,7 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
         gx += ax; gy += ay; gz += az;
         sq += ax * ax + ay * ay + az * az;
         if (WARM) {
-            const float c = (kri + warm_factor * kvr[j]) * g;
+            const float c = (kri + warm_factor * xj.w) * g;
             px += c * dx; py += c * dy; pz += c * dz;
         }
     });
@@ -1100,7 +1099,7 @@ __global__ void k_warm_setup(int64_t nf, float4* __restrict__ x, const float* __
 // ================================================================== launchers
 // lanes per particle of the neighbour sums (measured at 1.23M particles)
 constexpr int kLanesDensity = 2, kLanesPressure = 2, kLanesPredict = 2, kLanesXsph = 4;
-constexpr int kLanesXsphPress = 2;   // the non-pressure pass that also applies a pressure
+constexpr int kLanesXsphPress = 2;   // the non-pressure pass that also applies a pressure or takes the check
 
 #define LAUNCH(kern, n, ...)                                                        \
     do {                                                                            \
@@ -1154,10 +1153,10 @@ hipError_t launch_cell_sort(const uint32_t* start, int64_t ncell, uint32_t* src,
 
 hipError_t launch_gather_fluid(const uint32_t* src, int64_t n, const float4* x, const float4* v, const float* K,
                                const float* Kv, const float* rho, const int32_t* id, const float4* dv, float4* xo,
-                               float4* vo, float* Ko, float* Kvo, float* rhoo, float* kvro, int32_t* ido, float4* dvo,
+                               float4* vo, float* Ko, float* Kvo, float* rhoo, int32_t* ido, float4* dvo,
                                hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    LAUNCH(k_gather_fluid, n, src, n, x, v, K, Kv, rho, id, dv, xo, vo, Ko, Kvo, rhoo, kvro, ido, dvo);
+    LAUNCH(k_gather_fluid, n, src, n, x, v, K, Kv, rho, id, dv, xo, vo, Ko, Kvo, rhoo, ido, dvo);
 }
 
 hipError_t launch_gather_boundary(const uint32_t* src, int64_t n, const float4* x, const float4* v, const int32_t* id,
@@ -1192,16 +1191,16 @@ hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, HostSta
 
 hipError_t launch_density_alpha(int64_t nf, float4* x, float4* v, const uint32_t* nlist, const uint32_t* ncnt,
                                 const float4* xb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float* rho,
-                                float* alpha, float4* v_in, float* Kv, const float* kvr, float dt, float warm_factor,
+                                float* alpha, float4* v_in, float* Kv, float dt, float warm_factor,
                                 float pci_c, hipStream_t s) {
     if (nf <= 0) return hipSuccess;
     const dim3 grid(grid_blocks(kLanesDensity * nf)), block(kBlock);
     if (warm_factor > 0.0f)
         hipLaunchKernelGGL((k_density_alpha<kLanesDensity, true>), grid, block, 0, s, nf, x, v, nlist, ncnt, xb, blist,
-                           bcnt, kc, rho, alpha, v_in, Kv, kvr, dt, warm_factor, pci_c);
+                           bcnt, kc, rho, alpha, v_in, Kv, dt, warm_factor, pci_c);
     else
         hipLaunchKernelGGL((k_density_alpha<kLanesDensity, false>), grid, block, 0, s, nf, x, v, nlist, ncnt, xb,
-                           blist, bcnt, kc, rho, alpha, v_in, Kv, kvr, dt, warm_factor, pci_c);
+                           blist, bcnt, kc, rho, alpha, v_in, Kv, dt, warm_factor, pci_c);
     return hipGetLastError();
 }
 
@@ -1258,7 +1257,7 @@ hipError_t launch_nonpressure(int model, int64_t nf, float4* x, const float4* v,
     const DivCheck dc = div ? *div : DivCheck{};
 #define NONPRESSURE(M, P, D)                                                                                      \
     do {                                                                                                          \
-        constexpr int lanes = (M == 0 && !P && !D) ? 1 : (P ? kLanesXsphPress : kLanesXsph);                      \
+        constexpr int lanes = (M == 0 && !P && !D) ? 1 : ((P || D) ? kLanesXsphPress : kLanesXsph);               \
         const uint32_t nblk = grid_blocks(lanes * nf);                                                            \
         if (nparts) *nparts = (int)nblk;                                                                          \
         hipLaunchKernelGGL((k_nonpressure<M, lanes, P, D>), dim3(nblk), block, 0, s, nf, x, v, vout, rho, nlist,  \
