@@ -321,15 +321,17 @@ __device__ __forceinline__ void for_each_nbr_l(const uint32_t* __restrict__ list
     // L >= 4 one chunk row each, L/4 rows apart.
     const int64_t step = nf << 2;   // one chunk row
     const uint32_t* p = list + ((((int64_t)(q >> 2) * nf + i) << 2) + (q & 3));
+    const uint4* p4 = reinterpret_cast<const uint4*>(list) + i;   // L = 2: whole chunks
     uint32_t k = (uint32_t)q;
     for (; k + 3 * L < n; k += 4 * L) {
         uint32_t j[4];
-        if (L == 2) {
-            j[0] = p[0];
-            j[1] = p[2];
-            j[2] = p[step];
-            j[3] = p[step + 2];
-            p += 2 * step;
+        if (L == 2) {   // both lanes load the two chunks (one load each instead of two) and pick their entries
+            const uint4 a = p4[0], b = p4[nf];
+            j[0] = q ? a.y : a.x;
+            j[1] = q ? a.w : a.z;
+            j[2] = q ? b.y : b.x;
+            j[3] = q ? b.w : b.z;
+            p4 += 2 * nf;
         } else {
 #pragma unroll
             for (int u = 0; u < 4; ++u) j[u] = p[u * (L / 4) * step];
