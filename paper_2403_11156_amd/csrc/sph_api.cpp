@@ -96,6 +96,7 @@ struct sph_ctx {
     int64_t dev_bytes = 0;
 
     bool nbr_fresh = false, boundary_dirty = true, sorted_once = false;
+    bool vb_moving = false;   // some boundary velocity may be non-zero (rigid bodies, or written)
     bool vmax_ready = false;   // hs->vmax_bits holds max |v|^2 of the current v
     unsigned long long nstats[sph::kNStats] = {};   // of the last build
     int64_t step_index = 0;
@@ -425,7 +426,8 @@ int predict_pass(sph_ctx *c, int mode, float dt, bool first, const sph::SolveCtl
     {
         ProfScope ps(c, "predict", (56.0 + (dout ? 4.0 : 0.0)) * c->nf + list_bytes(c));
         HIP_TRY(c, sph::launch_predict(mode, c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->nlist, c->ncnt,
-                                       c->xb, c->vb, c->blist, c->bcnt, c->kc, dt, c->red_part, c->ctl, first,
+                                       c->xb, c->vb_moving ? c->vb : nullptr, c->blist, c->bcnt, c->kc, dt,
+                                       c->red_part, c->ctl, first,
                                        dout, &nparts, c->stream));
     }
     HIP_TRY(c, sph::launch_solve_finish(c->red_part, nparts, c->ctl, first, init, c->hs_dev, c->stream));
@@ -735,7 +737,8 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
             // the pass applies its pressure as well.
             const bool fold_press = press && !learned;
             if (fold_press && (rc = warm_setup(c->K_saved))) return rc;
-            const sph::DivCheck dc{c->vb, c->alpha, c->div_kvs, c->want_d ? c->dbuf : nullptr, c->red_part};
+            const sph::DivCheck dc{c->vb_moving ? c->vb : nullptr, c->alpha, c->div_kvs, c->want_d ? c->dbuf : nullptr,
+                                   c->red_part};
             int nparts = 0;
             if ((rc = nonpressure(fold_press, &dc, &nparts))) return rc;
             const sph::SolveCtl init = solve_init(c, 0, dt, c->forced_div, c->P.eta_divergence);
@@ -927,6 +930,7 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     c->nf = sc->n_fluid;
     c->nb = sc->n_boundary;
     c->nr = sc->n_rigid;
+    c->vb_moving = c->nr > 0;
     c->capf = p->max_neighbors;
     c->capb = p->max_boundary_neighbors;
     (void)hipGetDevice(&c->device);
@@ -1289,6 +1293,7 @@ int sph_write_state(sph_ctx *c, uint32_t mask, const sph_host_view *src) {
                 vb4[s].x = src->v_boundary[3 * k];
                 vb4[s].y = src->v_boundary[3 * k + 1];
                 vb4[s].z = src->v_boundary[3 * k + 2];
+                if (vb4[s].x != 0.0f || vb4[s].y != 0.0f || vb4[s].z != 0.0f) c->vb_moving = true;
             }
         }
         HIP_TRY(c, hipMemcpyAsync(c->xb, xb4.data(), sizeof(float4) * nb, hipMemcpyHostToDevice, c->stream));

@@ -340,6 +340,18 @@ __device__ __forceinline__ void for_each_nbr_l(const uint32_t* __restrict__ list
 #pragma unroll
         for (int u = 0; u < 4; ++u) f(j[u]);
     }
+    if (L == 2) {   // up to three left, k, k+2 (this chunk row) and k+4 (the next)
+        if (k < n) {
+            const uint4 a = p4[0];
+            f(q ? a.y : a.x);
+            if (k + 2 < n) f(q ? a.w : a.z);
+            if (k + 4 < n) {
+                const uint4 b = p4[nf];
+                f(q ? b.y : b.x);
+            }
+        }
+        return;
+    }
     for (; k < n; k += L) f(list[(((int64_t)(k >> 2) * nf + i) << 2) + (k & 3u)]);
 }
 

@@ -130,6 +130,7 @@ hipError_t launch_pressure_update(int64_t nf, const float4* x, float4* v, const 
 // first: the solve's initial predict (always runs); otherwise the pass and
 // its finish do nothing once ctl->go == 0.  The finish updates ctl.  dout
 // (nullable, mode 0 only): the unclamped divergence d of every particle.
+// vb null: every boundary particle is at rest.
 hipError_t launch_predict(int mode, int64_t nf, float4* x, const float4* v, const float* rho, const float* alpha,
                           float* kappa, const uint32_t* nlist, const uint32_t* ncnt,
                           const float4* xb, const float4* vb, const uint32_t* blist, const uint32_t* bcnt,
@@ -149,8 +150,9 @@ hipError_t launch_solve_finish(const double* partials, int nblk, SolveCtl* ctl, 
 // (v* -= dt a_p, K += kappa, kappa_last = kappa when non-null).
 // Outputs of the divergence-free solve's first error pass when the
 // non-pressure pass takes it over (see k_nonpressure): boundary velocities
-// and alpha in; kappa_v and kappa_v/rho (kvs, with a pressure in the same
-// pass), D rho/Dt (dout, nullable) and the error partials out.
+// (null: all at rest) and alpha in; kappa_v and kappa_v/rho (kvs, with a
+// pressure in the same pass), D rho/Dt (dout, nullable) and the error
+// partials out.
 struct DivCheck {
     const float4* vb;
     const float* alpha;

@@ -500,7 +500,7 @@ __global__ void __launch_bounds__(kBlock) k_predict(
         float db = 0.f;
         for_each_nbr_l<L>(blist, nf, i, q, bcnt[i], [&](uint32_t kk) {
             const float4 xk = xb[kk];
-            const float4 vk = vb[kk];
+            const float4 vk = vb ? vb[kk] : make_float4(0.f, 0.f, 0.f, 0.f);   // null: all boundaries at rest
             const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             db += xk.w * grad_factor(r2, kc) * ((vi.x - vk.x) * dx + (vi.y - vk.y) * dy + (vi.z - vk.z) * dz);
@@ -600,7 +600,7 @@ __global__ void __launch_bounds__(kBlock) k_nonpressure(
                     bx += c * dx; by += c * dy; bz += c * dz;
                 }
                 if (DIV) {
-                    const float4 vk = dc.vb[kk];
+                    const float4 vk = dc.vb ? dc.vb[kk] : make_float4(0.f, 0.f, 0.f, 0.f);
                     db += xk.w * grad_factor(r2, kc) * ((vi.x - vk.x) * dx + (vi.y - vk.y) * dy + (vi.z - vk.z) * dz);
                 }
             });
