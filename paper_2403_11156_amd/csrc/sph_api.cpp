@@ -800,10 +800,11 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     // 8. symplectic Euler: v = v*, x += dt v
     {
         ProfScope ps(c, "integrate", 44.0 * nf);
-        HIP_TRY(c, sph::launch_integrate(nf, c->x, c->v, dt, s));
+        // with a CFL step the pass also reduces the next step's input max |v|^2
+        const bool cfl = c->P.cfl_lambda > 0.0;
+        HIP_TRY(c, sph::launch_integrate(nf, c->x, c->v, dt, cfl ? (uint32_t *)c->red_part : nullptr, c->hs_dev, s));
     }
-    if (c->P.cfl_lambda > 0.0) {   // the next step's CFL input, read after its neighbour build
-        HIP_TRY(c, sph::launch_max_v2(c->v, nf, (uint32_t *)c->red_part, c->hs_dev, s));
+    if (c->P.cfl_lambda > 0.0) {   // read after the next step's neighbour build is queued
         HIP_TRY(c, hipEventRecord(c->vmax_done, s));
         c->vmax_ready = true;
     }

@@ -43,21 +43,28 @@ __global__ void k_keys_hist(const float4* __restrict__ x, int64_t n, Grid g, uin
         k = cell_key(g, x[i]);
         key[i] = k;
     }
+    // group the wave's lanes by key (the first lane of a group leads it),
+    // then every leader adds its group's size with one atomic, all at once
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1ull;
     uint64_t pending = __ballot(valid);
-    uint32_t rank = 0;
+    uint32_t rank = 0, group = 0;
+    int leader_of = lane;
     while (pending) {   // wave-uniform
         const int leader = __ffsll((unsigned long long)pending) - 1;
         const uint32_t kl = (uint32_t)__shfl((int)k, leader, 64);
         const uint64_t same = __ballot(valid && k == kl) & pending;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(count + kl, (uint32_t)__popcll(same));
-        base = (uint32_t)__shfl((int)base, leader, 64);
-        if ((same >> lane) & 1ull) rank = base + (uint32_t)__popcll(same & below);
+        if ((same >> lane) & 1ull) {
+            rank = (uint32_t)__popcll(same & below);
+            leader_of = leader;
+        }
+        if (lane == leader) group = (uint32_t)__popcll(same);
         pending &= ~same;
     }
-    if (valid) slot[i] = rank;
+    uint32_t base = 0;
+    if (valid && leader_of == lane) base = atomicAdd(count + k, group);
+    base = (uint32_t)__shfl((int)base, leader_of, 64);
+    if (valid) slot[i] = base + rank;
 }
 
 constexpr int kScanItems = 16;
@@ -328,16 +335,16 @@ __global__ void k_boundary_psi(float4* __restrict__ xb, int64_t nb, const uint32
 }
 
 // ------------------------------------------------------------------ the step
-__global__ void k_max_v2(const float4* __restrict__ v, int64_t n, uint32_t* out_bits) {
-    const int64_t i = particle_index();
-    float m = 0.0f;
-    if (i < n) {
+// |v|^2 as fl32((vx^2 + vy^2) + vz^2), every product and sum rounded
+__device__ __forceinline__ float speed2(float4 a) {
 #pragma clang fp contract(off)
-        const float4 a = v[i];
-        const float xx = a.x * a.x, yy = a.y * a.y, zz = a.z * a.z;
-        const float s = xx + yy;
-        m = s + zz;
-    }
+    const float xx = a.x * a.x, yy = a.y * a.y, zz = a.z * a.z;
+    const float s = xx + yy;
+    return s + zz;
+}
+
+// the workgroup's maximum of m >= 0 into out_bits[blockIdx.x]
+__device__ __forceinline__ void block_max_bits(float m, uint32_t* out_bits) {
     uint32_t bits = __float_as_uint(m);   // non-negative floats order as integers
     for (int off = 32; off > 0; off >>= 1) bits = max(bits, (uint32_t)__shfl_down((int)bits, off, 64));
     __shared__ uint32_t ws[kBlock / 64];
@@ -348,6 +355,11 @@ __global__ void k_max_v2(const float4* __restrict__ v, int64_t n, uint32_t* out_
         for (int w = 1; w < kBlock / 64; ++w) m = max(m, ws[w]);
         out_bits[blockIdx.x] = m;
     }
+}
+
+__global__ void k_max_v2(const float4* __restrict__ v, int64_t n, uint32_t* out_bits) {
+    const int64_t i = particle_index();
+    block_max_bits(i < n ? speed2(v[i]) : 0.0f, out_bits);
 }
 
 // The neighbour sums below run L lanes per particle (group_particle,
@@ -730,13 +742,20 @@ __global__ void k_trace_target(int64_t nf, const float* __restrict__ alpha, cons
     target[i] = a > 0.0f ? K[i] * dt * dt / (a * rho0) : 0.0f;
 }
 
-__global__ void k_integrate(int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, float dt) {
+// x += dt v; out_bits (nullable): per-workgroup max |v|^2 of the new v, the
+// next step's CFL input (as k_max_v2)
+__global__ void k_integrate(int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, float dt,
+                            uint32_t* out_bits) {
     const int64_t i = particle_index();
-    if (i >= nf) return;
-    float4 xi = x[i];
-    const float4 vi = v[i];
-    xi.x += dt * vi.x; xi.y += dt * vi.y; xi.z += dt * vi.z;
-    x[i] = xi;
+    float m = 0.0f;
+    if (i < nf) {
+        float4 xi = x[i];
+        const float4 vi = v[i];
+        xi.x += dt * vi.x; xi.y += dt * vi.y; xi.z += dt * vi.z;
+        x[i] = xi;
+        m = speed2(vi);
+    }
+    if (out_bits) block_max_bits(m, out_bits);
 }
 
 // Reaction on the rigid bodies (Eq. 14) from the step's total stiffness
@@ -1313,9 +1332,14 @@ hipError_t launch_warm_setup(int64_t nf, float4* x, const float* rho, float* K, 
     LAUNCH(k_warm_setup, nf, nf, x, rho, K, kappa, warm_factor, Ksave);
 }
 
-hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, hipStream_t s) {
+hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, uint32_t* partials, HostStatus* host,
+                            hipStream_t s) {
     if (nf <= 0) return hipSuccess;
-    LAUNCH(k_integrate, nf, nf, x, v, dt);
+    const uint32_t nblk = grid_blocks(nf);
+    hipLaunchKernelGGL(k_integrate, dim3(nblk), dim3(kBlock), 0, s, nf, x, v, dt, partials);
+    if (partials)
+        hipLaunchKernelGGL(k_finish_max_u32, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, host);
+    return hipGetLastError();
 }
 
 hipError_t launch_rigid_force(int64_t nf, const float4* x, const float* rho, const float* K, const float* Kv,
