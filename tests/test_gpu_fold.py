@@ -118,3 +118,34 @@ def test_fold_same_decisions_as_separate(sph):
         x0, x1 = runs[0][0][f].astype(np.float64), runs[1][0][f].astype(np.float64)
         scale = np.abs(x1).max() + 1e-30
         assert np.abs(x0 - x1).max() <= 2e-5 * scale, (f, np.abs(x0 - x1).max(), scale)
+
+
+@pytest.mark.parametrize("separate", [0, 1])
+def test_written_boundary_velocity(sph, separate):
+    """Boundary velocities written through the state interface (no rigid
+    body) enter the divergence and density errors (Eqs. 6, 9 with the
+    boundary term): a wall moving into the fluid, against the oracle."""
+    sc = scenes.small_scene(6, 5, 4)
+    sim = sph.Simulation(sc, params=dict(sc.params, separate_div_check=separate))
+    local = O.rigid_local(sc.x_boundary, sc.body_of_boundary, sc.rigid)
+    sim.build_neighbors()
+    sim.step()
+    xb = sim.read(("boundary",))["xb"]
+    vb = np.zeros_like(xb)
+    vb[xb[:, 2] < xb[:, 2].min() + 0.015, 2] = 0.5   # the floor pushes up
+    sim.write(vb=vb)
+    worst = {}
+    for k in range(2):
+        sim.build_neighbors()
+        state = oracle_state_from_gpu(sim, sc, local)
+        assert np.abs(state.vb).max() > 0.0
+        st = sim.step()
+        g = sim.read()
+        ref = O.step(state, forced_div=st["iters_div"], forced_dens=st["iters_dens"])
+        r = compare_step(g, ref, st)
+        for f, v in r.items():
+            worst[f] = max(worst.get(f, 0.0), v)
+    print("moving floor", separate, worst, flush=True)
+    for f, v in worst.items():
+        assert v <= 1.0, (f, v)
+    sim.close()
