@@ -111,7 +111,7 @@ typedef struct sph_mlp sph_mlp;
  *                   warm_start to DFSPH and PCISPH; SPH_WARM_LEARNED needs
  *                   DFSPH (SPH_ERR_INVALID otherwise).
  *   separate_div_check  0 (default): with explicit viscosity, when the
- *                   previous step's divergence-free solve needed no
+ *                   last two steps' divergence-free solves needed no
  *                   iteration, the non-pressure pass also computes that
  *                   solve's first error (both read the same velocities);
  *                   if the error then calls for iterations they run and the

@@ -74,6 +74,7 @@ struct sph_ctx {
     sph::CgCtl *cgc = nullptr;                        // and of the implicit-viscosity CG
     int32_t last_cg = 0;                              // previous step's CG iterations
     int32_t last_iters[2] = {0, 0};                   // previous step's iterations (divergence, density)
+    int32_t div_calm = 2;                             // steps in a row whose divergence solve did not iterate
     uint32_t *flags = nullptr;
     unsigned long long *nstat_part = nullptr;
     // pinned host memory the finishing kernels write (host view, device address)
@@ -649,13 +650,15 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         if (rc) return rc;
     }
     // 3. divergence-free solve (DFSPH).  Its first predict pass reads the v
-    //    the explicit non-pressure pass reads too.  When the previous step's
-    //    solve needed no iteration, that pass takes the check over (fold);
-    //    should the error call for iterations after all, they run after it
-    //    and the non-pressure pass is queued again.
+    //    the explicit non-pressure pass reads too.  When the last two steps'
+    //    solves needed no iteration (a settled flow, whose next step rarely
+    //    does), that pass takes the check over (fold); should the error call
+    //    for iterations after all, they run after it and the non-pressure
+    //    pass is queued again.  A flow whose solve alternates between none
+    //    and one iteration keeps the check separate.
     const bool implicit = c->P.visc_model == SPH_VISC_IMPLICIT;
     const bool fold = dfsph && !implicit && !tracing && !c->P.separate_div_check && c->forced_div < 0 &&
-                      c->last_iters[0] == 0;
+                      c->div_calm >= 2;
     int32_t iv = 0, id = 0;
     double ev = 0.0, ed = 0.0;
     int rc = SPH_OK;
@@ -808,6 +811,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         HIP_TRY(c, hipEventRecord(c->vmax_done, s));
         c->vmax_ready = true;
     }
+    if (dfsph) c->div_calm = iv == 0 ? std::min(c->div_calm + 1, 2) : 0;
     c->nbr_fresh = false;
     c->last_dt = dt;
     c->step_index += 1;

@@ -52,21 +52,19 @@ def test_fold_outcomes_match_oracle(sph, arm, separate):
         net = sph.MLP(w)
         cb = M.step_callback(w)
     local = O.rigid_local(sc.x_boundary, sc.body_of_boundary, sc.rigid)
-    prev_div = 0
-    perturbed = False
+    calm = 2   # steps in a row without divergence iterations (a fresh context counts as settled)
     outcomes = set()
     worst = {}
     for k in range(7):
-        # compress once a step follows one whose divergence solve did not
-        # iterate, so the fold is taken and its error calls for iterations
-        if k >= 3 and not perturbed and prev_div == 0:
+        folded = separate == 0 and calm >= 2
+        # once a folded step has gone without iterations, compress before the
+        # next folded one, so that its error calls for iterations
+        if k >= 1 and folded and "done" in outcomes and "iterate" not in outcomes:
             _compress(sim, 5.0)
-            perturbed = True
         sim.build_neighbors()
         if arm == "learned" and k == 1:
             sim.set_warm_start(2, net)
         state = oracle_state_from_gpu(sim, sc, local)
-        folded = separate == 0 and prev_div == 0
         print(f"[fold] arm={arm} separate={separate} step={k} folded={folded}", flush=True)
         st = sim.step()
         g = sim.read()
@@ -79,11 +77,10 @@ def test_fold_outcomes_match_oracle(sph, arm, separate):
         assert st["err_div"] <= params["eta_divergence"] or st["iters_div"] == params["max_iters"]
         if folded:
             outcomes.add("iterate" if st["iters_div"] > 0 else "done")
-        prev_div = st["iters_div"]
+        calm = min(calm + 1, 2) if st["iters_div"] == 0 else 0
     print(arm, separate, "outcomes", sorted(outcomes), "worst", worst, flush=True)
     for f, v in worst.items():
         assert v <= 1.0, (f, v)
-    assert perturbed
     if separate == 0:
         assert outcomes == {"iterate", "done"}, outcomes
     sim.close()
