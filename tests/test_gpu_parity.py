@@ -304,3 +304,40 @@ def test_implicit_viscosity_cg_start_value(sph):
     cold = run(0.0)
     print("[cg start] iterations over 9 steps: start 0.5", warm, "x0 = v~", cold, flush=True)
     assert warm < cold
+
+
+def test_c1_hundred_steps_statistics(sph):
+    """Whole-run comparison on c1 (SPH is chaotic, so pointwise parity over
+    many steps is unpinned): the GPU run and the oracle's own run from the
+    same input, 100 steps each, every step within eta, iteration counts
+    within one of each other step by step, and the fluid's centre of mass,
+    kinetic energy and front (largest x) within 1% at steps 10, 50 and 100."""
+    sc = scenes.scene("c1")
+    p = sc.params
+    m = p["rho0"] * (2.0 * p["r"]) ** 3
+    sim = sph.Simulation(sc)
+    state = O.State(sc, O.rigid_local(sc.x_boundary, sc.body_of_boundary, sc.rigid))
+
+    def stats(x, v):
+        x = np.asarray(x, np.float64)
+        v = np.asarray(v, np.float64)
+        return x.mean(axis=0), 0.5 * m * float((v * v).sum()), float(x[:, 0].max())
+
+    for k in range(100):
+        st = sim.advance()
+        out = O.step(state)
+        state = O.advance(state, out)
+        for which, eta in (("div", p["eta_divergence"]), ("dens", p["eta_density"])):
+            assert st["err_" + which] <= eta or st["iters_" + which] == p["max_iters"], (k, which)
+            assert out["err_" + which] <= eta or out["iters_" + which] == p["max_iters"], (k, which)
+            assert abs(st["iters_" + which] - out["iters_" + which]) <= 1, (k, which, st, out["iters_" + which])
+        if k in (9, 49, 99):
+            g = sim.read(("x", "v"))
+            cg, kg, fg = stats(g["x"], g["v"])
+            cr, kr, fr = stats(state.x, state.v)
+            print(f"step {k + 1}: com {cg} vs {cr}, ke {kg:.4f} vs {kr:.4f}, front {fg:.5f} vs {fr:.5f}", flush=True)
+            assert np.all(np.abs(cg - cr) <= 0.01 * np.abs(cr)), (k, cg, cr)
+            assert abs(kg - kr) <= 0.01 * kr, (k, kg, kr)
+            assert abs(fg - fr) <= 0.01 * fr, (k, fg, fr)
+            assert np.all(np.isfinite(g["x"])) and len(g["x"]) == sc.n_fluid
+    sim.close()
