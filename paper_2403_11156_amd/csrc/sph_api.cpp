@@ -81,12 +81,12 @@ struct sph_ctx {
     sph::HostStatus *hs = nullptr, *hs_dev = nullptr;
     // implicit viscosity
     float *Pinv = nullptr;
-    float4 *cg_b = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
+    float4 *cg_b = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr, *cg_s = nullptr;
     float4 *dvisc = nullptr, *dvisc2 = nullptr;   // previous correction v* - b, sorted order
     float *rho2 = nullptr;                        // density ping-pong
     float2 *div_kvs = nullptr;   // divergence check folded into the non-pressure pass: kappa_v, kappa_v / rho
     float *K_saved = nullptr;    // and K as it was before the warm start's set-up
-    double *cg_part = nullptr;                    // CG partial sums (mat-vec, then update)
+    double *cg_part = nullptr;                    // CG partial sums (mat-vec, then two update slots)
 
     std::vector<sph_rigid_desc> rigid;
     std::vector<double> force, torque;
@@ -531,8 +531,9 @@ int wcsph_eos(sph_ctx *c) {
 // correction v* - v~), stop at |r| <= tol |b|.  Dot products FP64.  The stop
 // rule runs on the device as in jacobi_solve: iterations are queued in
 // batches and the host reads the control block once per batch.  An iteration
-// is three kernels (mat-vec with the p.Ap sums, update, direction) whose
-// control blocks alternate between two slots.
+// is two kernels, the mat-vec of the preconditioned residual (with the u.w
+// sums) and the single-reduction update (k_cg_update), whose control blocks
+// and update sums alternate between two slots by iteration parity.
 int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
     hipStream_t s = c->stream;
     const int64_t nf = c->nf;
@@ -550,27 +551,34 @@ int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
         ProfScope ps(c, "visc", 48.0 * nf + fluid_list_bytes(c));
         HIP_TRY(c, visc_matvec(c, c->v2, c->cg_Ap, dt, mu, nullptr, nullptr));
     }
-    HIP_TRY(c, sph::launch_cg_setup(nf, c->cg_b, c->cg_Ap, c->Pinv, c->cg_r, c->cg_z, c->cg_p, c->cg_part, &c->cgc[0],
-                                    c->P.cg_tol, c->P.cg_max_iters, c->hs_dev, s));
     const int npap = sph::visc_matvec_parts(nf);
-    double *pap = c->cg_part, *upd = c->cg_part + npap;
+    const int64_t nred = (int64_t)sph::reduction_blocks(nf);
+    double *uw = c->cg_part, *upd[2] = {c->cg_part + npap, c->cg_part + npap + 2 * nred};
+    // the set-up's three sums per workgroup fit the two update slots, read
+    // by its own finish before the first update writes there
+    HIP_TRY(c, sph::launch_cg_setup(nf, c->cg_b, c->cg_Ap, c->Pinv, c->cg_r, c->cg_z, c->cg_p, upd[0], &c->cgc[0],
+                                    c->P.cg_tol, c->P.cg_max_iters, c->hs_dev, s));
     const int32_t cap = std::max(c->P.cg_max_iters, 0);
     const size_t mark = c->prof_pending.size();
-    int32_t queued = 0, batch = std::min(std::max(c->last_cg, 1), cap);
+    // one mat-vec more than updates: the update after the last one finds the
+    // residual converged and stops
+    int32_t queued = 0, batch = std::min(std::max(c->last_cg, 1) + 1, cap + 1);
     for (;;) {
         for (int32_t k = 0; k < batch; ++k) {
-            const int par = (queued + k) & 1;
+            const int32_t it = queued + k;
+            const int par = it & 1;
             {
                 ProfScope ps(c, "visc", 48.0 * nf + fluid_list_bytes(c));
-                HIP_TRY(c, visc_matvec(c, c->cg_p, c->cg_Ap, dt, mu, &c->cgc[par].go, pap));
+                HIP_TRY(c, visc_matvec(c, c->cg_z, c->cg_Ap, dt, mu, &c->cgc[par].go, uw));
             }
-            HIP_TRY(c, sph::launch_cg_iteration(nf, c->v2, c->cg_r, c->cg_z, c->cg_p, c->cg_Ap, c->Pinv, &c->cgc[par],
-                                                &c->cgc[par ^ 1], pap, npap, upd, c->hs_dev, s));
+            HIP_TRY(c, sph::launch_cg_iteration(nf, c->v2, c->cg_r, c->cg_z, c->cg_p, c->cg_s, c->cg_Ap, c->Pinv,
+                                                &c->cgc[par], &c->cgc[par ^ 1], upd[par ^ 1], uw, npap, upd[par],
+                                                c->hs_dev, it == 0, s));
         }
         queued += batch;
         HIP_TRY(c, hipStreamSynchronize(s));
-        if (!c->hs->cg.go || queued >= cap) break;
-        batch = std::min<int32_t>(4, cap - queued);
+        if (!c->hs->cg.go || queued > cap) break;
+        batch = std::min<int32_t>(4, cap + 1 - queued);
     }
     const sph::CgCtl h = c->hs->cg;
     // drop the timing records of queued mat-vecs that did nothing
@@ -998,7 +1006,8 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     if (p->visc_model == SPH_VISC_IMPLICIT) {
         ALLOC(c->Pinv, 9 * nf); ALLOC(c->cg_b, nf); ALLOC(c->cg_r, nf); ALLOC(c->cg_z, nf); ALLOC(c->cg_p, nf);
         ALLOC(c->cg_Ap, nf); ALLOC(c->dvisc, nf); ALLOC(c->dvisc2, nf);
-        ALLOC(c->cg_part, sph::visc_matvec_parts(nf) + 3 * (int64_t)sph::reduction_blocks(nf) + 16);
+        ALLOC(c->cg_s, nf);
+        ALLOC(c->cg_part, sph::visc_matvec_parts(nf) + 4 * (int64_t)sph::reduction_blocks(nf) + 16);
     }
 #undef ALLOC
     if (hipHostMalloc((void **)&c->hs, sizeof(sph::HostStatus), hipHostMallocMapped | hipHostMallocCoherent) !=

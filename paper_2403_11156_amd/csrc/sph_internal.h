@@ -48,8 +48,8 @@ struct SolveCtl {
 // nothing.  alpha and beta are the FP64 step ratios the next kernels use.
 struct CgCtl {
     double rz;           // r.z of the current residual
-    double alpha;        // rz / p.Ap of the running iteration
-    double beta;         // rz_new / rz_old for the direction update
+    double alpha;        // step length of the last iteration
+    double beta;         // direction weight of the last iteration
     double rr;           // r.r after the last update
     double bnorm;        // |b|
     double thresh;       // tol |b|: stop when |r| <= thresh
@@ -201,13 +201,15 @@ hipError_t launch_visc_correction(int64_t nf, const float4* vs, const float4* b,
 hipError_t launch_cg_setup(int64_t nf, const float4* b, const float4* Mx, const float* Pinv, float4* r, float4* z,
                            float4* p, double* partials, CgCtl* ctl, double tol, int32_t max_iters,
                            HostStatus* host, hipStream_t s);
-// one CG iteration after its mat-vec Ap (with the npap partial sums p.Ap):
-// alpha = rz/p.Ap; x += alpha p, r -= alpha Ap, z = P r; the stop rule;
-// p = z + beta p.  Reads *ctl, writes the next control block *next
-// (partials: 2 per workgroup of nf, apart from pap_part)
-hipError_t launch_cg_iteration(int64_t nf, float4* xv, float4* r, float4* z, float4* p, const float4* Ap,
-                               const float* Pinv, const CgCtl* ctl, CgCtl* next, const double* pap_part, int npap,
-                               double* partials, HostStatus* host, hipStream_t s);
+// The update of one CG iteration after its mat-vec w = M u (with nuw partial
+// sums u.w), in the single-reduction form (see k_cg_update): the stop rule
+// from the previous update's sums prev_part (not read when first), then
+// p, s = M p, x, r, u = P r and the sums r.u, r.r into partials (2 per
+// workgroup of nf).  Reads *ctl, writes the next control block *next.
+hipError_t launch_cg_iteration(int64_t nf, float4* xv, float4* r, float4* u, float4* p, float4* sv, const float4* w,
+                               const float* Pinv, const CgCtl* ctl, CgCtl* next, const double* prev_part,
+                               const double* uw_part, int nuw, double* partials, HostStatus* host, bool first,
+                               hipStream_t s);
 
 // learned warm start: the features pass, the learned stiffness, trace targets
 // learned-warm-start features from per-particle fields (no neighbour pass):

@@ -1033,68 +1033,133 @@ __global__ void k_cg_init(const double* __restrict__ partials, int nblk, CgCtl* 
     }
 }
 
-// The kernels of one CG iteration read the control block `ctl` of that
-// iteration; the direction kernel's workgroup 0 writes the next one into the
-// other slot of a pair, so no launch writes a block it reads.  Each does
-// nothing once ctl->go is 0.
-//
-// Update: alpha = rz / p.Ap from the mat-vec's partial sums; x += alpha p,
-// r -= alpha Ap, z = P r (w = rho kept); per-workgroup sums r.z and r.r.
-__global__ void k_cg_update(int64_t nf, float4* __restrict__ xv, float4* __restrict__ r, float4* __restrict__ z,
-                            const float4* __restrict__ p, const float4* __restrict__ Ap,
-                            const float* __restrict__ Pinv, const CgCtl* ctl, const double* __restrict__ pap_part,
-                            int npap, double* __restrict__ partials) {
-    if (ctl->go == 0) return;
-    const double pap = block_total(pap_part, npap, 1, 0);
-    const float a = (float)(ctl->rz / pap);
+// One CG iteration is the mat-vec w = M u of the preconditioned residual u
+// (with the per-workgroup sums of u.w) and this update, in the
+// single-reduction form of preconditioned CG (Chronopoulos and Gear): with
+// gamma = r.u and delta = u.w,
+//   beta = gamma / gamma_prev,  alpha = gamma / (delta - beta gamma / alpha_prev)
+//   (first iteration: beta = 0, alpha = gamma / delta),
+//   p = u + beta p,  s = w + beta s  (s = M p),  x += alpha p,  r -= alpha s,
+//   u = P r,  and the per-workgroup sums r.u, r.r for the next iteration.
+// The iteration reads the control block `ctl` and workgroup 0 writes the
+// next one into the other slot of a pair, so no launch writes a block it
+// reads.  The stop rule (|r| <= tol |b|, or max_iters) is evaluated at the
+// start of the next update from its predecessor's sums (the first update
+// takes the set-up's decision); a stopped block is carried forward.
+__global__ void k_cg_update(int64_t nf, float4* __restrict__ xv, float4* __restrict__ r, float4* __restrict__ u,
+                            float4* __restrict__ p, float4* __restrict__ sv, const float4* __restrict__ w,
+                            const float* __restrict__ Pinv, const CgCtl* ctl, CgCtl* next,
+                            const double* __restrict__ prev_part, int nprev, const double* __restrict__ uw_part,
+                            int nuw, double* __restrict__ partials, HostStatus* host, bool first) {
+    CgCtl c = *ctl;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (!c.go) {
+        if (lead) {
+            *next = c;
+            host->cg = c;
+        }
+        return;
+    }
+    // the particle's vectors are loaded first, the three sums (gamma and r.r
+    // of the previous update, delta of the mat-vec) then formed in one pass
+    // and one workgroup reduction, in the same order in every workgroup
     const int64_t i = particle_index();
-    double rz = 0.0, rr = 0.0;
-    if (i < nf) {
-        const float4 pp = p[i], ap = Ap[i];
-        float4 xx = xv[i], rv = r[i];
+    const bool live = i < nf;
+    float4 uu{}, ww{}, pp{}, ss{}, xx{}, rv{};
+    float P[9];
+    if (live) {
+        uu = u[i];
+        ww = w[i];
+        if (!first) {
+            pp = p[i];
+            ss = sv[i];
+        }
+        xx = xv[i];
+        rv = r[i];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) P[k] = Pinv[9 * i + k];
+    }
+    double sg = 0.0, sr = 0.0, sd = 0.0;
+    if (!first)
+        for (int b = threadIdx.x; b < nprev; b += kBlock) {
+            sg += prev_part[2 * (size_t)b];
+            sr += prev_part[2 * (size_t)b + 1];
+        }
+    for (int b = threadIdx.x; b < nuw; b += kBlock) sd += uw_part[b];
+    {
+        __shared__ double ws[3][kBlock / 64];
+        __shared__ double tot[3];
+        sg = wave_sum(sg);
+        sr = wave_sum(sr);
+        sd = wave_sum(sd);
+        if ((threadIdx.x & 63) == 0) {
+            ws[0][threadIdx.x >> 6] = sg;
+            ws[1][threadIdx.x >> 6] = sr;
+            ws[2][threadIdx.x >> 6] = sd;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            double t = ws[threadIdx.x][0];
+            for (int k = 1; k < kBlock / 64; ++k) t += ws[threadIdx.x][k];
+            tot[threadIdx.x] = t;
+        }
+        __syncthreads();
+        sg = tot[0];
+        sr = tot[1];
+        sd = tot[2];
+    }
+    double gamma = c.rz, rr = c.rr;
+    if (!first) {
+        gamma = sg;
+        rr = sr;
+        if (!(sqrt(rr) > c.thresh && c.iters < c.max_iters)) {
+            c.go = 0;
+            c.rr = rr;
+            c.rz = gamma;
+            if (lead) {
+                *next = c;
+                host->cg = c;
+            }
+            return;
+        }
+    }
+    const double delta = sd;
+    const double beta = first ? 0.0 : gamma / c.rz;
+    const double alpha = first ? gamma / delta : gamma / (delta - beta * gamma / c.alpha);
+    const float a = (float)alpha, bt = (float)beta;
+    double ru = 0.0, r2 = 0.0;
+    if (live) {
+        if (first) {
+            pp = uu;
+            ss = ww;
+        } else {
+            pp.x = uu.x + bt * pp.x; pp.y = uu.y + bt * pp.y; pp.z = uu.z + bt * pp.z;
+            ss.x = ww.x + bt * ss.x; ss.y = ww.y + bt * ss.y; ss.z = ww.z + bt * ss.z;
+        }
+        p[i] = pp;
+        sv[i] = ss;
         xx.x += a * pp.x; xx.y += a * pp.y; xx.z += a * pp.z;
-        rv.x -= a * ap.x; rv.y -= a * ap.y; rv.z -= a * ap.z;
+        rv.x -= a * ss.x; rv.y -= a * ss.y; rv.z -= a * ss.z;
         xv[i] = xx;
         r[i] = rv;
-        float4 zz = apply3(Pinv + 9 * i, rv);
+        float4 zz = apply3(P, rv);
         zz.w = rv.w;
-        z[i] = zz;
-        rz = (double)rv.x * zz.x + (double)rv.y * zz.y + (double)rv.z * zz.z;
-        rr = (double)rv.x * rv.x + (double)rv.y * rv.y + (double)rv.z * rv.z;
+        u[i] = zz;
+        ru = (double)rv.x * zz.x + (double)rv.y * zz.y + (double)rv.z * zz.z;
+        r2 = (double)rv.x * rv.x + (double)rv.y * rv.y + (double)rv.z * rv.z;
     }
-    const double s0 = block_sum(rz);
-    const double s1 = block_sum(rr);
+    const double s0 = block_sum(ru);
+    const double s1 = block_sum(r2);
     if (threadIdx.x == 0) {
         partials[2 * (size_t)blockIdx.x] = s0;
         partials[2 * (size_t)blockIdx.x + 1] = s1;
     }
-}
-
-// Direction: rz_new, rr from the update's sums; count the iteration; go on
-// while |r| > tol |b| and fewer than max_iters; beta = rz_new / rz and
-// p = z + beta p while going on.  Workgroup 0 stores the next control block
-// (a stopped one is carried forward unchanged) and the host status.
-__global__ void k_cg_direction(int64_t nf, float4* __restrict__ p, const float4* __restrict__ z, const CgCtl* ctl,
-                               CgCtl* next, const double* __restrict__ partials, int nblk, HostStatus* host) {
-    CgCtl c = *ctl;
-    if (c.go) {
-        const double rz = block_total(partials, nblk, 2, 0);
-        const double rr = block_total(partials, nblk, 2, 1);
-        c.beta = rz / c.rz;
-        c.rz = rz;
+    if (lead) {
+        c.rz = gamma;
         c.rr = rr;
+        c.alpha = alpha;
+        c.beta = beta;
         c.iters += 1;
-        c.go = (sqrt(rr) > c.thresh && c.iters < c.max_iters) ? 1 : 0;
-        const int64_t i = particle_index();
-        if (c.go && i < nf) {
-            const float beta = (float)c.beta;
-            const float4 zz = z[i];
-            float4 pp = p[i];
-            pp.x = zz.x + beta * pp.x; pp.y = zz.y + beta * pp.y; pp.z = zz.z + beta * pp.z;
-            p[i] = pp;
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
         *next = c;
         host->cg = c;
     }
@@ -1398,15 +1463,14 @@ hipError_t launch_cg_setup(int64_t nf, const float4* b, const float4* Mx, const 
     return hipGetLastError();
 }
 
-hipError_t launch_cg_iteration(int64_t nf, float4* xv, float4* r, float4* z, float4* p, const float4* Ap,
-                               const float* Pinv, const CgCtl* ctl, CgCtl* next, const double* pap_part, int npap,
-                               double* partials, HostStatus* host, hipStream_t s) {
+hipError_t launch_cg_iteration(int64_t nf, float4* xv, float4* r, float4* u, float4* p, float4* sv, const float4* w,
+                               const float* Pinv, const CgCtl* ctl, CgCtl* next, const double* prev_part,
+                               const double* uw_part, int nuw, double* partials, HostStatus* host, bool first,
+                               hipStream_t s) {
     if (nf <= 0) return hipSuccess;
     const uint32_t nblk = grid_blocks(nf);
-    hipLaunchKernelGGL(k_cg_update, dim3(nblk), dim3(kBlock), 0, s, nf, xv, r, z, p, Ap, Pinv, ctl, pap_part, npap,
-                       partials);
-    hipLaunchKernelGGL(k_cg_direction, dim3(nblk), dim3(kBlock), 0, s, nf, p, (const float4*)z, ctl, next,
-                       (const double*)partials, (int)nblk, host);
+    hipLaunchKernelGGL(k_cg_update, dim3(nblk), dim3(kBlock), 0, s, nf, xv, r, u, p, sv, w, Pinv, ctl, next, prev_part,
+                       (int)nblk, uw_part, nuw, partials, host, first);
     return hipGetLastError();
 }
 
