@@ -80,7 +80,7 @@ struct sph_ctx {
     // pinned host memory the finishing kernels write (host view, device address)
     sph::HostStatus *hs = nullptr, *hs_dev = nullptr;
     // implicit viscosity
-    float *Pinv = nullptr;
+    float2 *Pinv = nullptr;   // per particle the upper triangle of its inverse diagonal block
     float4 *cg_b = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr, *cg_s = nullptr;
     float4 *dvisc = nullptr, *dvisc2 = nullptr;   // previous correction v* - b, sorted order
     float *rho2 = nullptr;                        // density ping-pong
@@ -1004,7 +1004,7 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     ALLOC(c->nstat_part, sph::kNStats * nred);
     ALLOC(c->feat, 5 * nf); ALLOC(c->ybuf, nf); ALLOC(c->dbuf, nf);
     if (p->visc_model == SPH_VISC_IMPLICIT) {
-        ALLOC(c->Pinv, 9 * nf); ALLOC(c->cg_b, nf); ALLOC(c->cg_r, nf); ALLOC(c->cg_z, nf); ALLOC(c->cg_p, nf);
+        ALLOC(c->Pinv, 3 * nf); ALLOC(c->cg_b, nf); ALLOC(c->cg_r, nf); ALLOC(c->cg_z, nf); ALLOC(c->cg_p, nf);
         ALLOC(c->cg_Ap, nf); ALLOC(c->dvisc, nf); ALLOC(c->dvisc2, nf);
         ALLOC(c->cg_s, nf);
         ALLOC(c->cg_part, sph::visc_matvec_parts(nf) + 4 * (int64_t)sph::reduction_blocks(nf) + 16);

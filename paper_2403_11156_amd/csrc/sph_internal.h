@@ -182,9 +182,11 @@ hipError_t launch_rigid_force(int64_t nf, const float4* x, const float* rho, con
 hipError_t launch_rigid_boundary(int64_t nb, float4* xb, float4* vb, const int32_t* bid, const double* local,
                                  const BodyPose* poses, hipStream_t s);
 
-// implicit viscosity (Eqs. 16-19): M p = p - dt A p and its block-Jacobi preconditioner
+// implicit viscosity (Eqs. 16-19): M p = p - dt A p and its block-Jacobi
+// preconditioner (per particle the upper triangle of the inverse 3x3 block:
+// 00, 01, 02, 11, 12, 22 as three float2)
 hipError_t launch_visc_precond(int64_t nf, const float4* x, const float* rho, const uint32_t* nlist,
-                               const uint32_t* ncnt, Kern kc, float dt, float mu, float* Pinv, hipStream_t s);
+                               const uint32_t* ncnt, Kern kc, float dt, float mu, float2* Pinv, hipStream_t s);
 // M p with rho taken from p.w; go (nullable): skip when *go == 0;
 // partials (nullable): per-workgroup sums of p.(M p), visc_matvec_parts(nf) of them
 int visc_matvec_parts(int64_t nf);
@@ -198,7 +200,7 @@ hipError_t launch_cg_start(int64_t nf, const float4* v, const float4* dvisc, flo
 hipError_t launch_visc_correction(int64_t nf, const float4* vs, const float4* b, float4* dvisc, hipStream_t s);
 // r = b - M x0, z = P r, p = z, and the control block of iteration 0 in *ctl
 // (partials: 3 per workgroup of nf)
-hipError_t launch_cg_setup(int64_t nf, const float4* b, const float4* Mx, const float* Pinv, float4* r, float4* z,
+hipError_t launch_cg_setup(int64_t nf, const float4* b, const float4* Mx, const float2* Pinv, float4* r, float4* z,
                            float4* p, double* partials, CgCtl* ctl, double tol, int32_t max_iters,
                            HostStatus* host, hipStream_t s);
 // The update of one CG iteration after its mat-vec w = M u (with nuw partial
@@ -207,7 +209,7 @@ hipError_t launch_cg_setup(int64_t nf, const float4* b, const float4* Mx, const 
 // p, s = M p, x, r, u = P r and the sums r.u, r.r into partials (2 per
 // workgroup of nf).  Reads *ctl, writes the next control block *next.
 hipError_t launch_cg_iteration(int64_t nf, float4* xv, float4* r, float4* u, float4* p, float4* sv, const float4* w,
-                               const float* Pinv, const CgCtl* ctl, CgCtl* next, const double* prev_part,
+                               const float2* Pinv, const CgCtl* ctl, CgCtl* next, const double* prev_part,
                                const double* uw_part, int nuw, double* partials, HostStatus* host, bool first,
                                hipStream_t s);
 

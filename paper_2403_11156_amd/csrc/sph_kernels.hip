@@ -906,7 +906,7 @@ __global__ void __launch_bounds__(kBlock) k_visc_matvec(
 // Inverse of the 3x3 diagonal block I - dt A_ii = I + dt sum_j c_ij (-F_ij) x_ij x_ij^T.
 __global__ void __launch_bounds__(kBlock) k_visc_precond(
     int64_t nf, const float4* __restrict__ x, const float* __restrict__ rho, const uint32_t* __restrict__ nlist,
-    const uint32_t* __restrict__ ncnt, Kern kc, float dt, float mu, float* __restrict__ Pinv) {
+    const uint32_t* __restrict__ ncnt, Kern kc, float dt, float mu, float2* __restrict__ Pinv) {
     const int64_t i = particle_index();
     if (i >= nf) return;
     const float4 xi = x[i];
@@ -926,23 +926,21 @@ __global__ void __launch_bounds__(kBlock) k_visc_precond(
     const double A = e * k2 - f * f, B = -(bq * k2 - f * cq), C = bq * f - e * cq;
     const double det = a * A + bq * B + cq * C;
     const double id = 1.0 / det;
-    float* o = Pinv + 9 * i;
-    o[0] = (float)(A * id);
-    o[1] = (float)(-(bq * k2 - cq * f) * id);
-    o[2] = (float)((bq * f - cq * e) * id);
-    o[3] = (float)(B * id);
-    o[4] = (float)((a * k2 - cq * cq) * id);
-    o[5] = (float)(-(a * f - cq * bq) * id);
-    o[6] = (float)(C * id);
-    o[7] = (float)(-(a * f - bq * cq) * id);
-    o[8] = (float)((a * e - bq * bq) * id);
+    // the block is symmetric, so is its inverse: its upper triangle
+    // (00, 01, 02, 11, 12, 22) as three float2
+    float2* o = Pinv + 3 * i;
+    o[0] = make_float2((float)(A * id), (float)(B * id));
+    o[1] = make_float2((float)(C * id), (float)((a * k2 - cq * cq) * id));
+    o[2] = make_float2((float)(-(a * f - cq * bq) * id), (float)((a * e - bq * bq) * id));
 }
 
-__device__ __forceinline__ float4 apply3(const float* P, float4 r) {
+// z = P r with P the symmetric inverse block stored as its upper triangle
+__device__ __forceinline__ float4 apply3(const float2* P, float4 r) {
+    const float2 p0 = P[0], p1 = P[1], p2 = P[2];   // (00, 01), (02, 11), (12, 22)
     float4 z;
-    z.x = P[0] * r.x + P[1] * r.y + P[2] * r.z;
-    z.y = P[3] * r.x + P[4] * r.y + P[5] * r.z;
-    z.z = P[6] * r.x + P[7] * r.y + P[8] * r.z;
+    z.x = p0.x * r.x + p0.y * r.y + p1.x * r.z;
+    z.y = p0.y * r.x + p1.y * r.y + p2.x * r.z;
+    z.z = p1.x * r.x + p2.x * r.y + p2.y * r.z;
     z.w = 0.f;
     return z;
 }
@@ -987,14 +985,14 @@ __global__ void k_visc_correction(int64_t nf, const float4* __restrict__ vs, con
 // Initial residual r = b - M x0, z = P r, p = z (w = rho), and the
 // per-workgroup FP64 sums r.z, b.b, r.r (three per workgroup).
 __global__ void k_cg_setup(int64_t nf, const float4* __restrict__ b, const float4* __restrict__ Mx,
-                           const float* __restrict__ Pinv, float4* __restrict__ r, float4* __restrict__ z,
+                           const float2* __restrict__ Pinv, float4* __restrict__ r, float4* __restrict__ z,
                            float4* __restrict__ p, double* __restrict__ partials) {
     const int64_t i = particle_index();
     double rz = 0.0, bb2 = 0.0, rr = 0.0;
     if (i < nf) {
         const float4 bb = b[i], m = Mx[i];
         const float4 rv = make_float4(bb.x - m.x, bb.y - m.y, bb.z - m.z, bb.w);
-        float4 zz = apply3(Pinv + 9 * i, rv);
+        float4 zz = apply3(Pinv + 3 * i, rv);
         zz.w = bb.w;
         r[i] = rv;
         z[i] = zz;
@@ -1048,7 +1046,7 @@ __global__ void k_cg_init(const double* __restrict__ partials, int nblk, CgCtl* 
 // takes the set-up's decision); a stopped block is carried forward.
 __global__ void k_cg_update(int64_t nf, float4* __restrict__ xv, float4* __restrict__ r, float4* __restrict__ u,
                             float4* __restrict__ p, float4* __restrict__ sv, const float4* __restrict__ w,
-                            const float* __restrict__ Pinv, const CgCtl* ctl, CgCtl* next,
+                            const float2* __restrict__ Pinv, const CgCtl* ctl, CgCtl* next,
                             const double* __restrict__ prev_part, int nprev, const double* __restrict__ uw_part,
                             int nuw, double* __restrict__ partials, HostStatus* host, bool first) {
     CgCtl c = *ctl;
@@ -1066,7 +1064,7 @@ __global__ void k_cg_update(int64_t nf, float4* __restrict__ xv, float4* __restr
     const int64_t i = particle_index();
     const bool live = i < nf;
     float4 uu{}, ww{}, pp{}, ss{}, xx{}, rv{};
-    float P[9];
+    float2 P[3];
     if (live) {
         uu = u[i];
         ww = w[i];
@@ -1077,7 +1075,7 @@ __global__ void k_cg_update(int64_t nf, float4* __restrict__ xv, float4* __restr
         xx = xv[i];
         rv = r[i];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) P[k] = Pinv[9 * i + k];
+        for (int k = 0; k < 3; ++k) P[k] = Pinv[3 * i + k];
     }
     double sg = 0.0, sr = 0.0, sd = 0.0;
     if (!first)
@@ -1425,7 +1423,7 @@ hipError_t launch_rigid_boundary(int64_t nb, float4* xb, float4* vb, const int32
 }
 
 hipError_t launch_visc_precond(int64_t nf, const float4* x, const float* rho, const uint32_t* nlist,
-                               const uint32_t* ncnt, Kern kc, float dt, float mu, float* Pinv, hipStream_t s) {
+                               const uint32_t* ncnt, Kern kc, float dt, float mu, float2* Pinv, hipStream_t s) {
     if (nf <= 0) return hipSuccess;
     LAUNCH(k_visc_precond, nf, nf, x, rho, nlist, ncnt, kc, dt, mu, Pinv);
 }
@@ -1452,7 +1450,7 @@ hipError_t launch_visc_correction(int64_t nf, const float4* vs, const float4* b,
     LAUNCH(k_visc_correction, nf, nf, vs, b, dvisc);
 }
 
-hipError_t launch_cg_setup(int64_t nf, const float4* b, const float4* Mx, const float* Pinv, float4* r, float4* z,
+hipError_t launch_cg_setup(int64_t nf, const float4* b, const float4* Mx, const float2* Pinv, float4* r, float4* z,
                            float4* p, double* partials, CgCtl* ctl, double tol, int32_t max_iters,
                            HostStatus* host, hipStream_t s) {
     if (nf <= 0) return hipSuccess;
@@ -1464,7 +1462,7 @@ hipError_t launch_cg_setup(int64_t nf, const float4* b, const float4* Mx, const 
 }
 
 hipError_t launch_cg_iteration(int64_t nf, float4* xv, float4* r, float4* u, float4* p, float4* sv, const float4* w,
-                               const float* Pinv, const CgCtl* ctl, CgCtl* next, const double* prev_part,
+                               const float2* Pinv, const CgCtl* ctl, CgCtl* next, const double* prev_part,
                                const double* uw_part, int nuw, double* partials, HostStatus* host, bool first,
                                hipStream_t s) {
     if (nf <= 0) return hipSuccess;
