@@ -96,7 +96,7 @@ def cpu_baseline(scene_name: str, steps: int):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
+        print(json.dumps({"error": "bench.py runs the step on one GPU only (--gpus 1)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
