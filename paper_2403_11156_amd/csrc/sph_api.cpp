@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <new>
 #include <string>
@@ -453,9 +454,12 @@ sph::SolveCtl solve_init(const sph_ctx *c, int mode, float dt, int32_t forced, d
 // `forced` iterations when forced >= 0.  The stop rule runs on the device
 // (SolveCtl): the host queues iterations in batches (the first of
 // first_batch) and reads the control block once per batch; passes of
-// iterations past the stop do nothing.
+// iterations past the stop do nothing.  tail (nullable) is queued after
+// every batch, before the host waits: work that runs only once the solve
+// has stopped (it reads the control block's go flag on the device).
 int jacobi_iterate(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, const sph::SolveCtl &init,
-                   int32_t first_batch, int32_t *iters, double *err_out) {
+                   int32_t first_batch, int32_t *iters, double *err_out,
+                   const std::function<int()> *tail = nullptr) {
     hipStream_t s = c->stream;
     const int32_t cap = init.forced >= 0 ? init.forced : std::max(init.max_iters, 0);
     const size_t mark = c->prof_pending.size();
@@ -470,6 +474,10 @@ int jacobi_iterate(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, co
             if (rc) return rc;
         }
         queued += batch;
+        if (tail) {
+            const int rc = (*tail)();
+            if (rc) return rc;
+        }
         HIP_TRY(c, hipStreamSynchronize(s));
         h = c->hs->solve;
         if (!h.go || queued >= cap) break;
@@ -494,11 +502,11 @@ int jacobi_iterate(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, co
 // starting state), then the iterations, the first batch sized by the
 // previous step's count for this solve.
 int jacobi_solve(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, int32_t forced, double eta,
-                 int32_t *iters, double *err_out) {
+                 int32_t *iters, double *err_out, const std::function<int()> *tail = nullptr) {
     const sph::SolveCtl init = solve_init(c, mode, dt, forced, eta);
     int rc = predict_pass(c, mode, dt, true, init);
     if (rc) return rc;
-    return jacobi_iterate(c, mode, dt, Kacc, klast, init, c->last_iters[mode], iters, err_out);
+    return jacobi_iterate(c, mode, dt, Kacc, klast, init, c->last_iters[mode], iters, err_out, tail);
 }
 
 hipError_t visc_matvec(sph_ctx *c, const float4 *p, float4 *Mp, float dt, float mu, const int32_t *go,
@@ -775,10 +783,22 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
             }
         }
     }
+    // 8 (below) queued behind every batch of the density solve, gated on its
+    // stop, so that the device integrates as soon as the solve has stopped
+    // instead of after the host has seen it; not with rigid bodies or a
+    // trace, whose host work comes in between
+    const bool cfl = c->P.cfl_lambda > 0.0;
+    const bool early_integrate = ppe && c->nr == 0 && !tracing;
+    const std::function<int()> integrate_tail = [&]() -> int {
+        HIP_TRY(c, sph::launch_integrate(nf, c->x, c->v, dt, cfl ? (uint32_t *)c->red_part : nullptr, c->hs_dev,
+                                         &c->ctl->go, s));
+        return SPH_OK;
+    };
     if (ppe) {
         HIP_TRY(c, sph::launch_fill_f32(c->kappa_last, nf, 0.0f, s));
         // 6. constant-density solve
-        rc = jacobi_solve(c, 1, dt, c->K, c->kappa_last, c->forced_dens, c->P.eta_density, &id, &ed);
+        rc = jacobi_solve(c, 1, dt, c->K, c->kappa_last, c->forced_dens, c->P.eta_density, &id, &ed,
+                          early_integrate ? &integrate_tail : nullptr);
         if (rc) return rc;
     } else {
         // 6w. WCSPH: the error the equation-of-state pass recorded
@@ -808,14 +828,15 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         HIP_TRY(c, sph::launch_rigid_boundary(c->nb, c->xb, c->vb, c->bid, c->blocal, c->poses, s));
         c->boundary_dirty = true;
     }
-    // 8. symplectic Euler: v = v*, x += dt v
-    {
+    // 8. symplectic Euler: v = v*, x += dt v (already done after the density
+    //    solve's last batch when early_integrate)
+    if (!early_integrate) {
         ProfScope ps(c, "integrate", 44.0 * nf);
         // with a CFL step the pass also reduces the next step's input max |v|^2
-        const bool cfl = c->P.cfl_lambda > 0.0;
-        HIP_TRY(c, sph::launch_integrate(nf, c->x, c->v, dt, cfl ? (uint32_t *)c->red_part : nullptr, c->hs_dev, s));
+        HIP_TRY(c, sph::launch_integrate(nf, c->x, c->v, dt, cfl ? (uint32_t *)c->red_part : nullptr, c->hs_dev,
+                                         nullptr, s));
     }
-    if (c->P.cfl_lambda > 0.0) {   // read after the next step's neighbour build is queued
+    if (cfl) {   // read after the next step's neighbour build is queued
         HIP_TRY(c, hipEventRecord(c->vmax_done, s));
         c->vmax_ready = true;
     }

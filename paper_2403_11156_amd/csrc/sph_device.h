@@ -215,7 +215,10 @@ __global__ void k_finish_nstats(const unsigned long long* __restrict__ partials,
     if (threadIdx.x == 0) host->flags = *flags;
 }
 
-__global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk, HostStatus* host) {
+// gate (nullable): nothing happens while *gate != 0
+__global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk, HostStatus* host,
+                                 const int32_t* __restrict__ gate) {
+    if (gate != nullptr && *gate != 0) return;
     __shared__ uint32_t s[kBlock];
     uint32_t m = 0;
     for (int b = threadIdx.x; b < nblk; b += kBlock) m = max(m, partials[b]);

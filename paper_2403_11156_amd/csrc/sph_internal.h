@@ -172,9 +172,10 @@ hipError_t launch_div_resume(int64_t nf, float4* x, float* kappa, float* K, cons
 // Ksave (nullable): keep a copy of K before it is cleared.
 hipError_t launch_warm_setup(int64_t nf, float4* x, const float* rho, float* K, float* kappa, float warm_factor,
                              float* Ksave, hipStream_t s);
-// x += dt v; partials (nullable): also max |v|^2 of the new v to host->vmax_bits
+// x += dt v; partials (nullable): also max |v|^2 of the new v to host->vmax_bits;
+// gate (nullable): both kernels do nothing while *gate != 0
 hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, uint32_t* partials, HostStatus* host,
-                            hipStream_t s);
+                            const int32_t* gate, hipStream_t s);
 hipError_t launch_rigid_force(int64_t nf, const float4* x, const float* rho, const float* K, const float* Kv,
                               const uint32_t* blist, const uint32_t* bcnt, const float4* xb, const float4* vb,
                               Kern kc, int32_t nbody, const double* com, double* partials, HostStatus* host,

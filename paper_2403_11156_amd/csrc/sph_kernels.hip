@@ -743,9 +743,11 @@ __global__ void k_trace_target(int64_t nf, const float* __restrict__ alpha, cons
 }
 
 // x += dt v; out_bits (nullable): per-workgroup max |v|^2 of the new v, the
-// next step's CFL input (as k_max_v2)
+// next step's CFL input (as k_max_v2).  gate (nullable): nothing happens
+// while *gate != 0 (queued behind a solve that may still be iterating).
 __global__ void k_integrate(int64_t nf, float4* __restrict__ x, const float4* __restrict__ v, float dt,
-                            uint32_t* out_bits) {
+                            uint32_t* out_bits, const int32_t* __restrict__ gate) {
+    if (gate != nullptr && *gate != 0) return;
     const int64_t i = particle_index();
     float m = 0.0f;
     if (i < nf) {
@@ -1267,7 +1269,8 @@ hipError_t launch_boundary_psi(float4* xb, int64_t nb, const uint32_t* start_b, 
 hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, HostStatus* host, hipStream_t s) {
     const uint32_t nblk = grid_blocks(n);
     hipLaunchKernelGGL(k_max_v2, dim3(nblk), dim3(kBlock), 0, s, v, n, partials);
-    hipLaunchKernelGGL(k_finish_max_u32, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, host);
+    hipLaunchKernelGGL(k_finish_max_u32, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, host,
+                       (const int32_t*)nullptr);
     return hipGetLastError();
 }
 
@@ -1396,12 +1399,12 @@ hipError_t launch_warm_setup(int64_t nf, float4* x, const float* rho, float* K, 
 }
 
 hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, uint32_t* partials, HostStatus* host,
-                            hipStream_t s) {
+                            const int32_t* gate, hipStream_t s) {
     if (nf <= 0) return hipSuccess;
     const uint32_t nblk = grid_blocks(nf);
-    hipLaunchKernelGGL(k_integrate, dim3(nblk), dim3(kBlock), 0, s, nf, x, v, dt, partials);
+    hipLaunchKernelGGL(k_integrate, dim3(nblk), dim3(kBlock), 0, s, nf, x, v, dt, partials, gate);
     if (partials)
-        hipLaunchKernelGGL(k_finish_max_u32, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, host);
+        hipLaunchKernelGGL(k_finish_max_u32, dim3(1), dim3(kBlock), 0, s, partials, (int)nblk, host, gate);
     return hipGetLastError();
 }
 
