@@ -795,11 +795,12 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         return SPH_OK;
     };
     if (ppe) {
-        HIP_TRY(c, sph::launch_fill_f32(c->kappa_last, nf, 0.0f, s));
-        // 6. constant-density solve
+        // 6. constant-density solve; every pressure pass of it writes the
+        //    stiffness it applied to kappa_last, which is zero without one
         rc = jacobi_solve(c, 1, dt, c->K, c->kappa_last, c->forced_dens, c->P.eta_density, &id, &ed,
                           early_integrate ? &integrate_tail : nullptr);
         if (rc) return rc;
+        if (id == 0) HIP_TRY(c, sph::launch_fill_f32(c->kappa_last, nf, 0.0f, s));
     } else {
         // 6w. WCSPH: the error the equation-of-state pass recorded
         HIP_TRY(c, hipStreamSynchronize(s));
