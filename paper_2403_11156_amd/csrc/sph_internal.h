@@ -188,13 +188,13 @@ hipError_t launch_rigid_boundary(int64_t nb, float4* xb, float4* vb, const int32
 // 00, 01, 02, 11, 12, 22 as three float2)
 hipError_t launch_visc_precond(int64_t nf, const float4* x, const float* rho, const uint32_t* nlist,
                                const uint32_t* ncnt, Kern kc, float dt, float mu, float2* Pinv, hipStream_t s);
-// M p with rho taken from p.w; go (nullable): skip when *go == 0;
+// M p with the volume m/rho taken from p.w; go (nullable): skip when *go == 0;
 // partials (nullable): per-workgroup sums of p.(M p), visc_matvec_parts(nf) of them
 int visc_matvec_parts(int64_t nf);
 hipError_t launch_visc_matvec(int64_t nf, const float4* x, const float4* p, float4* Mp, const uint32_t* nlist,
                               const uint32_t* ncnt, Kern kc, float dt, float mu, const int32_t* go,
                               double* partials, hipStream_t s);
-// b = v + dt g, x0 = b + w dvisc (w = rho from v.w in both)
+// b = v + dt g, x0 = b + w dvisc (w = m/rho from v.w in both)
 hipError_t launch_cg_start(int64_t nf, const float4* v, const float4* dvisc, float4* b, float4* x0, float dt,
                            float gx, float gy, float gz, float w, hipStream_t s);
 // dvisc = v* - b

@@ -367,8 +367,9 @@ __global__ void k_max_v2(const float4* __restrict__ v, int64_t n, uint32_t* out_
 
 // Density with the Akinci boundary term, Eq. (12), and the DFSPH factor
 // alpha = rho / (|sum_F m gradW + sum_B Psi gradW|^2 + sum_F |m gradW|^2).
-// Also saves the step's input velocity and copies rho into v.w (the XSPH
-// pass then gathers a neighbour's velocity and density in one load).  WARM:
+// Also saves the step's input velocity and stores the particle volume m/rho
+// in v.w (the XSPH pass then gathers a neighbour's velocity and volume in
+// one load, with no division per neighbour).  WARM:
 // the divergence solve's warm start in the same neighbour walk: its
 // stiffness over density, warm_factor Kv_prev / rho_prev (x.w, from the sort),
 // does not depend on this step's density, so its pressure (Eq. 7 with the
@@ -438,7 +439,7 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
     if (WARM) {
         vi.x -= dt * px; vi.y -= dt * py; vi.z -= dt * pz;
     }
-    v[i] = make_float4(vi.x, vi.y, vi.z, rr);
+    v[i] = make_float4(vi.x, vi.y, vi.z, kc.m / rr);
     Kv[i] = WARM ? kri * rr : 0.0f;
 }
 
@@ -580,7 +581,7 @@ __global__ void __launch_bounds__(kBlock) k_nonpressure(
                 float4 vj;
                 if (MODEL == 1 || MODEL == 2 || DIV) vj = v[j];
                 if (MODEL == 1 || MODEL == 2) {
-                    const float mj = kc.m / vj.w;   // v.w = rho (density pass)
+                    const float mj = vj.w;   // v.w = m / rho (density pass)
                     if (MODEL == 1) {
                         const float c = mj * kernel_W(r2, kc);
                         ax += c * (vj.x - vi.x); ay += c * (vj.y - vi.y); az += c * (vj.z - vi.z);
@@ -863,8 +864,9 @@ __global__ void k_rigid_boundary(int64_t nb, float4* __restrict__ xb, float4* __
 
 // ------------------------------------------------------------------ implicit viscosity
 // (A v)_i = sum_j 10 mu m / (rho_i rho_j) (x_ij.(v_i - v_j)) / (|x_ij|^2 + 0.01 h^2) gradW_ij
-// Every CG vector carries rho in its w component (k_cg_start copies it from
-// v.w), so a neighbour costs two gathers, x_j and p_j.  With `partials` the
+// Every CG vector carries the particle volume m/rho in its w component
+// (k_cg_start copies it from v.w), so a neighbour costs two gathers, x_j and
+// p_j.  With `partials` the
 // pass also stores the per-workgroup FP64 sums of p.(M p) for the CG step.
 template <int L>
 __global__ void __launch_bounds__(kBlock) k_visc_matvec(
@@ -886,14 +888,14 @@ __global__ void __launch_bounds__(kBlock) k_visc_matvec(
             const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             const float xv = (pi.x - pj.x) * dx + (pi.y - pj.y) * dy + (pi.z - pj.z) * dz;
-            const float c = xv / (pj.w * (r2 + eps2)) * grad_factor(r2, kc);
+            const float c = xv * pj.w / (kc.m * (r2 + eps2)) * grad_factor(r2, kc);
             ax += c * dx; ay += c * dy; az += c * dz;
         });
         ax = group_sum<L>(ax);
         ay = group_sum<L>(ay);
         az = group_sum<L>(az);
         if (q == 0) {
-            const float s = dt * 10.0f * mu * kc.m / pi.w;
+            const float s = dt * 10.0f * mu * pi.w;
             const float4 o = make_float4(pi.x - s * ax, pi.y - s * ay, pi.z - s * az, pi.w);
             Mp[i] = o;
             e = (double)pi.x * o.x + (double)pi.y * o.y + (double)pi.z * o.z;
@@ -962,7 +964,7 @@ __device__ double block_total(const double* __restrict__ part, int n, int stride
 }
 
 // CG start value: b = v + dt g and x0 = b + w dvisc, with dvisc the previous
-// step's correction v* - b; both carry rho (v.w) in w.
+// step's correction v* - b; both carry the volume m/rho (v.w) in w.
 __global__ void k_cg_start(int64_t nf, const float4* __restrict__ v, const float4* __restrict__ dvisc,
                            float4* __restrict__ b, float4* __restrict__ x0, float dt, float gx, float gy, float gz,
                            float w) {
@@ -984,7 +986,7 @@ __global__ void k_visc_correction(int64_t nf, const float4* __restrict__ vs, con
     dvisc[i] = make_float4(u.x - bb.x, u.y - bb.y, u.z - bb.z, 0.f);
 }
 
-// Initial residual r = b - M x0, z = P r, p = z (w = rho), and the
+// Initial residual r = b - M x0, z = P r, p = z (w = m/rho), and the
 // per-workgroup FP64 sums r.z, b.b, r.r (three per workgroup).
 __global__ void k_cg_setup(int64_t nf, const float4* __restrict__ b, const float4* __restrict__ Mx,
                            const float2* __restrict__ Pinv, float4* __restrict__ r, float4* __restrict__ z,
