@@ -191,7 +191,8 @@ __global__ void __launch_bounds__(kFinishThreads) k_finish_solve(const double* _
 // Also mirrors the build flags to host.
 __global__ void k_finish_nstats(const unsigned long long* __restrict__ partials, int nblk,
                                 const uint32_t* __restrict__ flags, HostStatus* host) {
-    __shared__ unsigned long long s[kNStats][kBlock];
+    // per lane over the partials, then across the wave with shuffles, then
+    // across the workgroup's waves (integers: the order does not matter)
     unsigned long long a[kNStats];
     a[0] = ~0ull;
     for (int f = 1; f < kNStats; ++f) a[f] = 0ull;
@@ -201,34 +202,40 @@ __global__ void k_finish_nstats(const unsigned long long* __restrict__ partials,
         a[1] = max(a[1], p[1]);
         for (int f = 2; f < kNStats; ++f) a[f] += p[f];
     }
-    for (int f = 0; f < kNStats; ++f) s[f][threadIdx.x] = a[f];
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            s[0][threadIdx.x] = min(s[0][threadIdx.x], s[0][threadIdx.x + w]);
-            s[1][threadIdx.x] = max(s[1][threadIdx.x], s[1][threadIdx.x + w]);
-            for (int f = 2; f < kNStats; ++f) s[f][threadIdx.x] += s[f][threadIdx.x + w];
-        }
-        __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) {
+        a[0] = min(a[0], (unsigned long long)__shfl_xor(a[0], off, 64));
+        a[1] = max(a[1], (unsigned long long)__shfl_xor(a[1], off, 64));
+        for (int f = 2; f < kNStats; ++f) a[f] += __shfl_xor(a[f], off, 64);
     }
-    if (threadIdx.x < kNStats) host->nstats[threadIdx.x] = s[threadIdx.x][0];
-    if (threadIdx.x == 0) host->flags = *flags;
+    __shared__ unsigned long long s[kNStats][kBlock / 64];
+    if ((threadIdx.x & 63) == 0)
+        for (int f = 0; f < kNStats; ++f) s[f][threadIdx.x >> 6] = a[f];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) {
+            a[0] = min(a[0], s[0][w]);
+            a[1] = max(a[1], s[1][w]);
+            for (int f = 2; f < kNStats; ++f) a[f] += s[f][w];
+        }
+        for (int f = 0; f < kNStats; ++f) host->nstats[f] = a[f];
+        host->flags = *flags;
+    }
 }
 
 // gate (nullable): nothing happens while *gate != 0
 __global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk, HostStatus* host,
                                  const int32_t* __restrict__ gate) {
     if (gate != nullptr && *gate != 0) return;
-    __shared__ uint32_t s[kBlock];
     uint32_t m = 0;
     for (int b = threadIdx.x; b < nblk; b += kBlock) m = max(m, partials[b]);
-    s[threadIdx.x] = m;
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
+    __shared__ uint32_t s[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = m;
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + w]);
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) m = max(m, s[w]);
+        host->vmax_bits = m;
     }
-    if (threadIdx.x == 0) host->vmax_bits = s[0];
 }
 
 
