@@ -121,39 +121,15 @@ __global__ void k_scatter(const uint32_t* __restrict__ key, const uint32_t* __re
     src[start[key[i]] + slot[i]] = (uint32_t)i;
 }
 
-// Sort of each cell's entries by particle id (cells hold ~8).  A group of
-// kCellLanes lanes per cell: with at most that many entries every lane loads
-// one entry and its id, counts the smaller ids in the group (ids are
-// unique, so the counts are a permutation) and stores the entry at that
-// rank; the group's loads all precede its stores (one wave, in lockstep).
-// Larger cells: insertion sort by the group's first lane.  Cells above 4096
-// entries are left unsorted and flagged (bit 1).
-constexpr int kCellLanes = 16;
+// Insertion sort of each cell's entries by particle id (cells hold ~8).
+// Cells above 4096 entries are left unsorted and flagged (bit 1).
 __global__ void k_cell_sort(const uint32_t* __restrict__ start, int64_t ncell, uint32_t* __restrict__ src,
                             const int32_t* __restrict__ id, uint32_t* flags) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t c = t / kCellLanes;
-    const int k = (int)(threadIdx.x % kCellLanes);
-    const int lane0 = (int)(threadIdx.x & 63) - k;   // the group's first lane in the wave
-    uint32_t b = 0, e = 0;
-    if (c < ncell) {
-        b = start[c];
-        e = start[c + 1];
-    }
-    const uint32_t n = e - b;
-    const bool small = n >= 2 && n <= (uint32_t)kCellLanes;
-    uint32_t sk = 0;
-    int32_t key = INT32_MAX;
-    if (small && (uint32_t)k < n) {
-        sk = src[b + k];
-        key = id[sk];
-    }
-    uint32_t rank = 0;
-#pragma unroll
-    for (int j = 0; j < kCellLanes; ++j) rank += __shfl(key, lane0 + j, 64) < key ? 1u : 0u;
-    if (small && (uint32_t)k < n) src[b + rank] = sk;
-    if (c >= ncell || n <= (uint32_t)kCellLanes || k != 0) return;
-    if (n > 4096) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncell) return;
+    const uint32_t b = start[c], e = start[c + 1];
+    if (e - b < 2) return;
+    if (e - b > 4096) {
         atomicOr(flags, 2u);
         return;
     }
@@ -1257,8 +1233,7 @@ hipError_t launch_scatter(const uint32_t* key, const uint32_t* slot, const uint3
 
 hipError_t launch_cell_sort(const uint32_t* start, int64_t ncell, uint32_t* src, const int32_t* id, uint32_t* flags,
                             hipStream_t s) {
-    hipLaunchKernelGGL(k_cell_sort, dim3(plain_blocks(ncell * kCellLanes)), dim3(kBlock), 0, s, start, ncell, src, id,
-                       flags);
+    hipLaunchKernelGGL(k_cell_sort, dim3(plain_blocks(ncell)), dim3(kBlock), 0, s, start, ncell, src, id, flags);
     return hipGetLastError();
 }
 
