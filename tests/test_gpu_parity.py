@@ -341,3 +341,33 @@ def test_c1_hundred_steps_statistics(sph):
             assert abs(fg - fr) <= 0.01 * fr, (k, fg, fr)
             assert np.all(np.isfinite(g["x"])) and len(g["x"]) == sc.n_fluid
     sim.close()
+
+
+@pytest.mark.parametrize("max_iters", [0, 1])
+def test_iteration_cap(sph, max_iters):
+    """The solves' cap (Alg. 2 with a limit): with no iteration allowed the
+    step still integrates once with the warm start's pressure only; with one,
+    every solve stops at one.  Both against the oracle run with the same cap."""
+    sc = scenes.scene("c1")
+    params = dict(sc.params, max_iters=max_iters)
+    sim = sph.Simulation(sc, params=params)
+    local = O.rigid_local(sc.x_boundary, sc.body_of_boundary, sc.rigid)
+    worst = {}
+    for k in range(3):
+        sim.build_neighbors()
+        state = oracle_state_from_gpu(sim, sc, local)
+        st = sim.step()
+        assert st["iters_div"] <= max_iters and st["iters_dens"] <= max_iters
+        g = sim.read()
+        for which in ("div", "dens"):
+            eta = params["eta_divergence" if which == "div" else "eta_density"]
+            assert st["iters_" + which] == max_iters or st["err_" + which] <= eta, (k, which, st)
+        ref = O.step(state, forced_div=st["iters_div"], forced_dens=st["iters_dens"],
+                     params=dict(state.params, max_iters=max_iters))
+        r = compare_step(g, ref, st)
+        for f, v in r.items():
+            worst[f] = max(worst.get(f, 0.0), v)
+    print("cap", max_iters, worst, flush=True)
+    for f, v in worst.items():
+        assert v <= 1.0, (f, v)
+    sim.close()
