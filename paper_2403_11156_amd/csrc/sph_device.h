@@ -250,6 +250,25 @@ __global__ void k_finish_max_u32(const uint32_t* __restrict__ partials, int nblk
 // (list chunk cnt/4 of particle i) and steps by nf chunks per store.  cnt
 // counts every neighbour, entries past cap are dropped (the caller flags the
 // overflow).  SKIP: the range may hold the particle itself.
+__device__ __forceinline__ void append_mask(uint32_t mask, uint32_t base, uint4*& chunk, int64_t nf, int32_t cap,
+                                            uint32_t& cnt, uint4& buf) {
+    while (mask) {
+        const uint32_t j = (uint32_t)__builtin_ctz(mask);
+        mask &= mask - 1u;
+        if (cnt < (uint32_t)cap) {
+            buf.x = buf.y;
+            buf.y = buf.z;
+            buf.z = buf.w;
+            buf.w = base + j;
+            if ((cnt & 3u) == 3u) {
+                *chunk = buf;
+                chunk += nf;
+            }
+        }
+        ++cnt;
+    }
+}
+
 template <bool SKIP, typename Load>
 __device__ __forceinline__ void scan_with(Load load, uint32_t b, uint32_t e, float4 xi, uint32_t skip, float h2,
                                           uint4*& chunk, int64_t nf, int32_t cap, uint32_t& cnt, uint4& buf) {
@@ -276,21 +295,7 @@ __device__ __forceinline__ void scan_with(Load load, uint32_t b, uint32_t e, flo
             test(k + 1, p1, r > 1u);
             test(k + 2, p2, r > 2u);
         }
-        while (mask) {
-            const uint32_t j = (uint32_t)__builtin_ctz(mask);
-            mask &= mask - 1u;
-            if (cnt < (uint32_t)cap) {
-                buf.x = buf.y;
-                buf.y = buf.z;
-                buf.z = buf.w;
-                buf.w = base + j;
-                if ((cnt & 3u) == 3u) {
-                    *chunk = buf;
-                    chunk += nf;
-                }
-            }
-            ++cnt;
-        }
+        append_mask(mask, base, chunk, nf, cap, cnt, buf);
     }
 }
 
@@ -377,8 +382,36 @@ __device__ __forceinline__ void scan_candidates(const float4* __restrict__ pos, 
 // slot t + t/8 (one pad slot per eight spreads the lanes' reads of
 // neighbouring cells over the banks).
 constexpr uint32_t kWinCand = 192;
-constexpr uint32_t kWinSlots = kWinCand + kWinCand / 8;
+constexpr uint32_t kWinSlots = kWinCand + kWinCand / 8 + 4;   // + a group's overhang past the last entry
 __device__ __forceinline__ uint32_t win_slot(uint32_t t) { return t + (t >> 3); }
+
+// scan_with over the candidates [b, e) of a window staged from wb on: the
+// groups of four start at multiples of four in the window, so a group's
+// slots are contiguous (its four entries never straddle a pad) and load at
+// fixed offsets from one address.  The group holding b may start before it
+// and the last may run past e (at most three slots past the window's last
+// entry, inside kWinSlots): those candidates are loaded but never accepted.
+template <bool SKIP>
+__device__ __forceinline__ void scan_window(const float4* __restrict__ win, uint32_t wb, uint32_t b, uint32_t e,
+                                            float4 xi, uint32_t skip, float h2, uint4*& chunk, int64_t nf,
+                                            int32_t cap, uint32_t& cnt, uint4& buf) {
+    if (b >= e) return;
+    for (uint32_t base = wb + ((b - wb) & ~3u); base < e; base += 32u) {
+        const uint32_t n = min(e - base, 32u);
+        uint32_t mask = 0u;
+        for (uint32_t k = 0; k < n; k += 4) {
+            const float4* g = win + win_slot(base - wb + k);
+            const float4 p[4] = {g[0], g[1], g[2], g[3]};
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) mask |= (dist2_exact(xi, p[j]) < h2 ? 1u : 0u) << (k + j);
+        }
+        // keep the bits of [b, e), without the particle itself
+        const uint32_t lo = b > base ? b - base : 0u, hi = e - base;
+        uint32_t keep = (hi >= 32u ? ~0u : (1u << hi) - 1u) & ~((1u << lo) - 1u);
+        if (SKIP && skip - base < 32u) keep &= ~(1u << (skip - base));
+        append_mask(mask & keep, base, chunk, nf, cap, cnt, buf);
+    }
+}
 
 // LDS written by some lanes of a wave and read by others: order the two
 // (the LDS executes one wave's instructions in order; this keeps the

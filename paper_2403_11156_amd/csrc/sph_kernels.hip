@@ -242,11 +242,10 @@ __global__ void __launch_bounds__(kBlock) k_nbr_build(
                 wave_lds_sync();   // the previous row's reads are done
                 for (uint32_t t = lane; t < we - wb; t += 64) win[win_slot(t)] = x[wb + t];
                 wave_lds_sync();
-                auto ld = [&](uint32_t c) { return win[win_slot(c - wb)]; };
                 if (r == 4)
-                    scan_with<true>(ld, fb[r], fe[r], xi, (uint32_t)i, g.h2, fchunk, nf, capf, nfc, fbuf);
+                    scan_window<true>(win, wb, fb[r], fe[r], xi, (uint32_t)i, g.h2, fchunk, nf, capf, nfc, fbuf);
                 else
-                    scan_with<false>(ld, fb[r], fe[r], xi, 0u, g.h2, fchunk, nf, capf, nfc, fbuf);
+                    scan_window<false>(win, wb, fb[r], fe[r], xi, 0u, g.h2, fchunk, nf, capf, nfc, fbuf);
                 staged = true;
             }
         }
