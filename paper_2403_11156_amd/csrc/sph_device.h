@@ -127,17 +127,9 @@ __device__ double block_sum(double v) {
 // order.  The kernel boundary orders the two phases; no device-scope fence or
 // atomic is needed (an agent-scope fence on the multi-XCD part writes back the
 // XCD's L2, which costs far more than one extra launch).
-__global__ void k_finish_f64(const double* __restrict__ partials, int nblk, int nout, double* __restrict__ out) {
-    for (int o = 0; o < nout; ++o) {
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partials[(size_t)b * nout + o];
-        acc = block_sum(acc);
-        if (threadIdx.x == 0) out[o] = acc;
-    }
-}
-
-// as k_finish_f64 into the host status (rigid force and torque): workgroup o
-// sums output o's partials, stored output-major (partials[o nblk + b])
+//
+// The rigid force and torque into the host status: workgroup o sums output
+// o's partials in workgroup order, stored output-major (partials[o nblk + b])
 __global__ void k_finish_rigid(const double* __restrict__ partials, int nblk, HostStatus* host) {
     const int o = blockIdx.x;
     double acc = 0.0;
