@@ -66,7 +66,9 @@ def test_create_rejects_bad_solver_settings_without_device():
     for bad in (dict(sc.params, solver=3), dict(sc.params, solver=-1),
                 dict(sc.params, solver=scenes.SOLVER_WCSPH, wcsph_k=0.0),
                 dict(sc.params, solver=scenes.SOLVER_PCISPH, warm_start=scenes.WARM_LEARNED),
-                dict(sc.params, solver=scenes.SOLVER_WCSPH, warm_start=scenes.WARM_LEARNED)):
+                dict(sc.params, solver=scenes.SOLVER_WCSPH, warm_start=scenes.WARM_LEARNED),
+                dict(sc.params, separate_div_check=2), dict(sc.params, separate_div_check=-1),
+                dict(sc.params, cg_warm_factor=5.0)):
         try:
             sph.Simulation(sc, params=bad)
             raise AssertionError(f"accepted {bad}")
