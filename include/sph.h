@@ -96,7 +96,13 @@ typedef struct sph_mlp sph_mlp;
  *                   warm_factor Kv_prev / rho_prev, i.e. Kv0 = that times the
  *                   step's density).
  *   max_neighbors, max_boundary_neighbors  list capacities per particle.
- *   auto_rebuild    1: sph_step rebuilds stale neighbour lists itself.
+ *   auto_rebuild    1: sph_step rebuilds stale neighbour lists itself: it
+ *                   queues the next step's sort and neighbour build at its
+ *                   end (the device runs them while the host is away) and
+ *                   reads their status during the next step.  Read-back
+ *                   between steps is unaffected (every field of the step
+ *                   just taken, in original particle order); a
+ *                   sph_write_state makes the next step sort again.
  *   solver          SPH_SOLVER_*.  WCSPH (Sec. 3.4.1): p_i = wcsph_k
  *                   ((rho_i/rho0)^wcsph_gamma - 1), clamped at zero, applied
  *                   in one pressure pass after gravity and viscosity; dt_max

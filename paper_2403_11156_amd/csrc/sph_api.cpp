@@ -62,6 +62,7 @@ struct sph_ctx {
     uint32_t *key = nullptr, *slot = nullptr, *src = nullptr, *count = nullptr, *start_f = nullptr;
     uint32_t *scan_part = nullptr;
     uint32_t *nlist = nullptr, *ncnt = nullptr, *blist = nullptr, *bcnt = nullptr;
+    uint32_t *ncnt2 = nullptr, *bcnt2 = nullptr;   // the previous build's counts (read-back after a build ahead)
     // boundary, sorted order (xb.w = Psi, vb.w = body id)
     float4 *xb = nullptr, *xb2 = nullptr, *vb = nullptr, *vb2 = nullptr;
     int32_t *bid = nullptr, *bid2 = nullptr;
@@ -99,6 +100,10 @@ struct sph_ctx {
 
     bool nbr_fresh = false, boundary_dirty = true, sorted_once = false;
     bool vb_moving = false;   // some boundary velocity may be non-zero (rigid bodies, or written)
+    // auto_rebuild: the next step's sort and neighbour build were queued at
+    // the end of the last step (the per-particle fields the sort does not
+    // reorder, and the previous counts, are then read back through id2)
+    bool build_ahead = false;
     bool vmax_ready = false;   // hs->vmax_bits holds max |v|^2 of the current v
     unsigned long long nstats[sph::kNStats] = {};   // of the last build
     int64_t step_index = 0;
@@ -379,6 +384,8 @@ int build_queue(sph_ctx *c) {
         int rc = sort_fluid(c);
         if (rc) return rc;
     }
+    std::swap(c->ncnt, c->ncnt2);   // keep the previous build's counts
+    std::swap(c->bcnt, c->bcnt2);
     {
         ProfScope ps(c, "nbr_build", 16.0 * c->nf + 8.0 * c->nf + list_bytes(c));
         HIP_TRY(c, sph::launch_nbr_build(c->x, c->nf, c->xb, c->start_f, c->start_b, c->g, c->nlist, c->ncnt, c->capf,
@@ -406,6 +413,7 @@ int build_check(sph_ctx *c) {
 }
 
 int build(sph_ctx *c) {
+    c->build_ahead = false;   // an explicit build replaces one queued ahead
     int rc = build_queue(c);
     if (rc) return rc;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -613,12 +621,13 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     //    read only after the density pass is queued too, so the device runs
     //    that pass while the host waits
     const bool rebuild = !c->nbr_fresh;
-    if (rebuild) {
+    if (rebuild && !c->build_ahead) {
         if (!c->P.auto_rebuild) return fail(c, SPH_ERR_STATE, "sph_step needs fresh neighbours (sph_build_neighbors)");
         int rc = build_queue(c);
         if (rc) return rc;
         HIP_TRY(c, hipEventRecord(c->build_done, s));
     }
+    c->build_ahead = false;
     const int64_t nf = c->nf;
     const bool dfsph = c->P.solver == SPH_SOLVER_DFSPH;
     const bool pcisph = c->P.solver == SPH_SOLVER_PCISPH;
@@ -841,6 +850,15 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         HIP_TRY(c, hipEventRecord(c->vmax_done, s));
         c->vmax_ready = true;
     }
+    // auto_rebuild: the next step's sort and neighbour build go on the stream
+    // now, so the device runs them while the host returns and comes back;
+    // the next step reads their status after its density pass
+    if (c->P.auto_rebuild) {
+        int brc = build_queue(c);
+        if (brc) return brc;
+        HIP_TRY(c, hipEventRecord(c->build_done, s));
+        c->build_ahead = true;
+    }
     if (dfsph) c->div_calm = iv == 0 ? std::min(c->div_calm + 1, 2) : 0;
     c->nbr_fresh = false;
     c->last_dt = dt;
@@ -1015,8 +1033,8 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     ALLOC(c->key, nf); ALLOC(c->slot, nf); ALLOC(c->src, nf);
     ALLOC(c->count, ncell); ALLOC(c->start_f, ncell + 1); ALLOC(c->start_b, ncell + 1); ALLOC(c->scan_part, 2 * scan_chunks + 8);
     // 32-bit lists in chunks of four entries (capacity rounded up to a chunk)
-    ALLOC(c->nlist, (int64_t)(c->capf + 3) / 4 * 4 * nf); ALLOC(c->ncnt, nf);
-    ALLOC(c->blist, (int64_t)(c->capb + 3) / 4 * 4 * nf); ALLOC(c->bcnt, nf);
+    ALLOC(c->nlist, (int64_t)(c->capf + 3) / 4 * 4 * nf); ALLOC(c->ncnt, nf); ALLOC(c->ncnt2, nf);
+    ALLOC(c->blist, (int64_t)(c->capb + 3) / 4 * 4 * nf); ALLOC(c->bcnt, nf); ALLOC(c->bcnt2, nf);
     ALLOC(c->xb, nb); ALLOC(c->xb2, nb); ALLOC(c->vb, nb); ALLOC(c->vb2, nb); ALLOC(c->bid, nb); ALLOC(c->bid2, nb);
     ALLOC(c->bkey, nb); ALLOC(c->bslot, nb); ALLOC(c->bsrc, nb); ALLOC(c->blocal, 3 * nb);
     ALLOC(c->poses, std::max(1, c->nr)); ALLOC(c->com_dev, 3 * std::max(1, c->nr));
@@ -1162,12 +1180,18 @@ int sph_read_state(sph_ctx *c, uint32_t mask, const sph_host_view *dst) {
     if (!c || !dst) return SPH_ERR_INVALID;
     c->err.clear();
     const int64_t nf = c->nf, nb = c->nb;
-    std::vector<int32_t> id;
+    std::vector<int32_t> id, id_prev;
     std::vector<float4> x4, v4, vin4;
     std::vector<float> f1;
     int rc = d2h(c, id, c->id, nf);
     if (rc) return rc;
+    // after a build queued ahead (auto_rebuild), x, v, rho, K, Kv and the
+    // correction are in the new sorted order, the step's other outputs (alpha,
+    // kappa, the input velocity, the counts) still in the step's order
+    const bool ahead = c->build_ahead;
+    if (ahead && (rc = d2h(c, id_prev, c->id2, nf))) return rc;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const std::vector<int32_t> &idp = ahead ? id_prev : id;
     auto scatter3 = [&](const std::vector<float4> &src, float *out) {
         for (int64_t s = 0; s < nf; ++s) {
             const int64_t i = id[s];
@@ -1176,11 +1200,11 @@ int sph_read_state(sph_ctx *c, uint32_t mask, const sph_host_view *dst) {
             out[3 * i + 2] = src[s].z;
         }
     };
-    auto read1 = [&](const float *d, float *out) -> int {
+    auto read1 = [&](const float *d, float *out, const std::vector<int32_t> &ids) -> int {
         int r = d2h(c, f1, d, nf);
         if (r) return r;
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        for (int64_t s = 0; s < nf; ++s) out[id[s]] = f1[s];
+        for (int64_t s = 0; s < nf; ++s) out[ids[s]] = f1[s];
         return SPH_OK;
     };
     if ((mask & SPH_FIELD_X) && dst->x) {
@@ -1195,11 +1219,13 @@ int sph_read_state(sph_ctx *c, uint32_t mask, const sph_host_view *dst) {
         if ((mask & SPH_FIELD_V) && dst->v) scatter3(v4, dst->v);
         if ((mask & SPH_FIELD_ACCEL) && dst->accel) {
             const float idt = c->last_dt > 0 ? 1.0f / c->last_dt : 0.0f;
+            std::vector<float4> vin_by_id(std::max<int64_t>(nf, 1));
+            for (int64_t s = 0; s < nf; ++s) vin_by_id[idp[s]] = vin4[s];
             for (int64_t s = 0; s < nf; ++s) {
                 const int64_t i = id[s];
-                dst->accel[3 * i] = (v4[s].x - vin4[s].x) * idt;
-                dst->accel[3 * i + 1] = (v4[s].y - vin4[s].y) * idt;
-                dst->accel[3 * i + 2] = (v4[s].z - vin4[s].z) * idt;
+                dst->accel[3 * i] = (v4[s].x - vin_by_id[i].x) * idt;
+                dst->accel[3 * i + 1] = (v4[s].y - vin_by_id[i].y) * idt;
+                dst->accel[3 * i + 2] = (v4[s].z - vin_by_id[i].z) * idt;
             }
         }
     }
@@ -1213,19 +1239,19 @@ int sph_read_state(sph_ctx *c, uint32_t mask, const sph_host_view *dst) {
             std::fill(dst->dvisc, dst->dvisc + 3 * nf, 0.0f);
         }
     }
-    if ((mask & SPH_FIELD_RHO) && dst->rho && (rc = read1(c->rho, dst->rho))) return rc;
-    if ((mask & SPH_FIELD_ALPHA) && dst->alpha && (rc = read1(c->alpha, dst->alpha))) return rc;
-    if ((mask & SPH_FIELD_K) && dst->K && (rc = read1(c->K, dst->K))) return rc;
-    if ((mask & SPH_FIELD_KV) && dst->Kv && (rc = read1(c->Kv, dst->Kv))) return rc;
-    if ((mask & SPH_FIELD_KAPPA) && dst->kappa && (rc = read1(c->kappa_last, dst->kappa))) return rc;
+    if ((mask & SPH_FIELD_RHO) && dst->rho && (rc = read1(c->rho, dst->rho, id))) return rc;
+    if ((mask & SPH_FIELD_ALPHA) && dst->alpha && (rc = read1(c->alpha, dst->alpha, idp))) return rc;
+    if ((mask & SPH_FIELD_K) && dst->K && (rc = read1(c->K, dst->K, id))) return rc;
+    if ((mask & SPH_FIELD_KV) && dst->Kv && (rc = read1(c->Kv, dst->Kv, id))) return rc;
+    if ((mask & SPH_FIELD_KAPPA) && dst->kappa && (rc = read1(c->kappa_last, dst->kappa, idp))) return rc;
     if ((mask & SPH_FIELD_NBR) && (dst->n_fluid_nbrs || dst->n_boundary_nbrs)) {
         std::vector<uint32_t> a, b;
-        if ((rc = d2h(c, a, c->ncnt, nf))) return rc;
-        if ((rc = d2h(c, b, c->bcnt, nf))) return rc;
+        if ((rc = d2h(c, a, ahead ? c->ncnt2 : c->ncnt, nf))) return rc;
+        if ((rc = d2h(c, b, ahead ? c->bcnt2 : c->bcnt, nf))) return rc;
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         for (int64_t s = 0; s < nf; ++s) {
-            if (dst->n_fluid_nbrs) dst->n_fluid_nbrs[id[s]] = (int32_t)a[s];
-            if (dst->n_boundary_nbrs) dst->n_boundary_nbrs[id[s]] = (int32_t)b[s];
+            if (dst->n_fluid_nbrs) dst->n_fluid_nbrs[idp[s]] = (int32_t)a[s];
+            if (dst->n_boundary_nbrs) dst->n_boundary_nbrs[idp[s]] = (int32_t)b[s];
         }
     }
     if ((mask & (SPH_FIELD_PSI | SPH_FIELD_BOUNDARY)) && (dst->psi || dst->x_boundary || dst->v_boundary)) {
@@ -1266,6 +1292,7 @@ int sph_write_state(sph_ctx *c, uint32_t mask, const sph_host_view *src) {
     if (!c || !src) return SPH_ERR_INVALID;
     c->err.clear();
     c->vmax_ready = false;
+    c->build_ahead = false;   // a build queued ahead is stale now: the next step sorts again
     const int64_t nf = c->nf, nb = c->nb;
     std::vector<int32_t> id;
     int rc = d2h(c, id, c->id, nf);

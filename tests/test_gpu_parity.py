@@ -179,17 +179,24 @@ def test_deterministic(sph):
 
 @pytest.mark.parametrize("name", ["c1", "bodies"])
 def test_auto_rebuild_matches_explicit_build(sph, name):
-    # with auto_rebuild the step queues the build itself and reads its status
-    # after the density pass: the same state, bit for bit, as build + step
+    # with auto_rebuild the step queues the next step's sort and build at its
+    # end and reads their status after the next density pass: the same
+    # computation, bit for bit, as build + step, and every field read back
+    # after every step (also those the queued sort has not reordered) agrees
+    fields = ("x", "v", "rho", "alpha", "K", "Kv", "kappa", "accel", "nbr", "rigid")
     outs = []
     for auto in (0, 1):
         sc = scenes.scene("c1") if name == "c1" else _small_with_bodies()
         sim = sph.Simulation(sc, params=dict(sc.params, auto_rebuild=auto))
-        stats = [sim.advance() for _ in range(4)]
-        outs.append((sim.read(("x", "v", "K", "Kv", "rigid")), stats))
+        stats, reads = [], []
+        for _ in range(4):
+            stats.append(sim.advance())
+            reads.append(sim.read(fields))
+        outs.append((reads, stats))
         sim.close()
-    for f in ("x", "v", "K", "Kv"):
-        assert np.array_equal(outs[0][0][f], outs[1][0][f]), f
+    for k, (ra, rb) in enumerate(zip(outs[0][0], outs[1][0])):
+        for f in ("x", "v", "rho", "alpha", "K", "Kv", "kappa", "accel", "nf_count", "nb_count"):
+            assert np.array_equal(ra[f], rb[f]), (k, f)
     for a, b in zip(outs[0][1], outs[1][1]):
         for k in ("dt", "iters_div", "iters_dens", "nbr_min", "nbr_max", "nbr_mean"):
             assert a[k] == b[k], k
