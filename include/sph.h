@@ -295,10 +295,15 @@ int sph_set_forced_iters(sph_ctx *ctx, int32_t div, int32_t dens);
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch of the named kernels while enabled.  sph_profile_read returns
  * the launch count and the summed event time [ms] of one kernel name, and the
- * algorithmic bytes those launches moved by the model stated in the design
- * notes.  Names: "nbr_build", "density_alpha", "pressure_update", "predict",
- * "xsph", "visc", "sort", "warm_features", "mlp", "integrate", "eos". */
+ * algorithmic bytes those launches moved (each particle's own fields read and
+ * written once, plus 4 bytes per neighbour-list entry walked).  Names:
+ * "nbr_build", "density_alpha", "pressure_update", "predict", "xsph", "visc",
+ * "sort", "warm_features", "mlp", "integrate", "eos".  sph_profile_only
+ * restricts the recording to one name (NULL: all), so that a timed run pays
+ * for the events of that kernel only; it applies from the next
+ * sph_profile_enable on. */
 int sph_profile_enable(sph_ctx *ctx, int32_t enable);
+int sph_profile_only(sph_ctx *ctx, const char *kernel);
 int sph_profile_read(sph_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms, double *bytes);
 
 /* ---- learned warm start ---------------------------------------------------- */

@@ -126,6 +126,7 @@ struct sph_ctx {
     hipEvent_t vmax_done = nullptr;    // recorded after the CFL reduction at the end of a step
 
     bool prof = false;
+    std::string prof_only;   // empty: every name
     std::vector<ProfEvent> prof_pending;
     std::vector<hipEvent_t> event_pool;
     std::map<std::string, ProfTotal> prof_total;
@@ -203,7 +204,8 @@ struct ProfScope {
     sph_ctx *c;
     ProfEvent ev{};
     bool on;
-    ProfScope(sph_ctx *ctx, const char *name, double bytes) : c(ctx), on(ctx->prof) {
+    ProfScope(sph_ctx *ctx, const char *name, double bytes)
+        : c(ctx), on(ctx->prof && (ctx->prof_only.empty() || ctx->prof_only == name)) {
         if (!on) return;
         ev.name = name;
         ev.bytes = bytes;
@@ -493,7 +495,11 @@ int jacobi_iterate(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, co
     }
     // drop the timing records of queued passes that did nothing
     if (c->prof && c->prof_pending.size() > mark) {
-        const size_t keep = mark + 2 * (size_t)h.iters;
+        // records per iteration: its pressure and predict passes, as far as
+        // the profile records them
+        const size_t per_iter = (c->prof_only.empty() || c->prof_only == "pressure_update" ? 1 : 0) +
+                                (c->prof_only.empty() || c->prof_only == "predict" ? 1 : 0);
+        const size_t keep = mark + per_iter * (size_t)h.iters;
         for (size_t q = keep; q < c->prof_pending.size(); ++q) {
             c->event_pool.push_back(c->prof_pending[q].a);
             c->event_pool.push_back(c->prof_pending[q].b);
@@ -599,7 +605,7 @@ int implicit_viscosity(sph_ctx *c, float dt, int32_t *iters, double *resid) {
     const sph::CgCtl h = c->hs->cg;
     // drop the timing records of queued mat-vecs that did nothing
     if (c->prof && c->prof_pending.size() > mark) {
-        const size_t keep = mark + (size_t)h.iters;
+        const size_t keep = mark + (c->prof_only.empty() || c->prof_only == "visc" ? (size_t)h.iters : 0);
         for (size_t q = keep; q < c->prof_pending.size(); ++q) {
             c->event_pool.push_back(c->prof_pending[q].a);
             c->event_pool.push_back(c->prof_pending[q].b);
@@ -1580,6 +1586,12 @@ int sph_profile_enable(sph_ctx *c, int32_t enable) {
     prof_resolve(c);
     c->prof = enable != 0;
     if (enable) c->prof_total.clear();
+    return SPH_OK;
+}
+
+int sph_profile_only(sph_ctx *c, const char *kernel) {
+    if (!c) return SPH_ERR_INVALID;
+    c->prof_only = kernel ? kernel : "";
     return SPH_OK;
 }
 

@@ -121,6 +121,7 @@ def _load():
         "sph_read_neighbors": (C.c_int, [P, C.POINTER(sph_nbr_view)]),
         "sph_set_forced_iters": (C.c_int, [P, C.c_int32, C.c_int32]),
         "sph_profile_enable": (C.c_int, [P, C.c_int32]),
+        "sph_profile_only": (C.c_int, [P, C.c_char_p]),
         "sph_profile_read": (C.c_int, [P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double)]),
         "sph_last_error": (C.c_char_p, [P]),
@@ -156,6 +157,7 @@ sph_get_info = lib.sph_get_info
 sph_read_neighbors = lib.sph_read_neighbors
 sph_set_forced_iters = lib.sph_set_forced_iters
 sph_profile_enable = lib.sph_profile_enable
+sph_profile_only = lib.sph_profile_only
 sph_profile_read = lib.sph_profile_read
 sph_last_error = lib.sph_last_error
 sph_strerror = lib.sph_strerror
@@ -413,7 +415,9 @@ class Simulation:
         self._check(sph_trace_rows(self.ctx, C.byref(n)))
         return n.value
 
-    def profile_enable(self, on: bool = True):
+    def profile_enable(self, on: bool = True, only: Optional[str] = None):
+        """only: record the events of that kernel name alone (None: all)."""
+        self._check(sph_profile_only(self.ctx, only.encode() if only else None))
         self._check(sph_profile_enable(self.ctx, 1 if on else 0))
 
     def profile_read(self, kernel: str) -> Dict:
