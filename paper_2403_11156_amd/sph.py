@@ -108,6 +108,10 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                           "(the HIP library is required, there is no fallback)")
+    # torch first: it ships its own HIP runtime, and the library must bind to
+    # that same runtime (loaded first, the library would pull in the system's
+    # copy, and torch's streams and memory would then be foreign to it)
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     sig = {
