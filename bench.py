@@ -5,6 +5,11 @@ and alpha, divergence-free solve, non-pressure forces, warm start,
 constant-density solve, rigid coupling, integration) on a synthetic scene
 already resident in HBM.  Prints one JSON line.
 
+Each arm runs --prerun untimed steps from the scene's start, then --warmup
+steps (the last five time every kernel with HIP events), then --reps
+repetitions of exactly --steps timed steps, each bracketed by a device
+synchronisation; the reported throughput is the median repetition's.
+
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c5|c2|c3|c4|c1]
 """
 
@@ -36,7 +41,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="c5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=2,
+                    help="steps of the benchmark workload the all-cores oracle runs for the CPU baseline")
+    ap.add_argument("--prerun", type=int, default=100,
+                    help="untimed steps before the warmup, so that the timed window is past the start-up transient")
+    ap.add_argument("--reps", type=int, default=3,
+                    help="repetitions of the timed window; the reported figure is their median")
     ap.add_argument("--arm", choices=("plain", "learned", "both"), default="both",
                     help="warm start of the density solve: previous-step (plain) and/or the trained MLP")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -76,21 +86,62 @@ def measured_traffic(config: str, kernel: str):
     return table.get(kernel)
 
 
+def host_cpu():
+    """The host's CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, usable, os.cpu_count() or usable
+
+
+def _oracle_rate(O, scene, steps, openmp):
+    O.use_openmp(openmp)
+    try:
+        st = O.State(scene)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = O.step(st)
+            st = O.advance(st, out)
+        dt = time.perf_counter() - t0
+    finally:
+        O.use_openmp(False)
+    return scene.n_fluid * steps / dt, dt
+
+
 def cpu_baseline(scene_name: str, steps: int):
-    """The FP64 oracle, as it stands, on the host: `steps` steps of the same
-    workload from its initial state (single-threaded)."""
+    """The FP64 oracle, as it stands, on the host's cores: `steps` steps of
+    the benchmark workload from its initial state on all usable cores
+    (OpenMP over the independent per-particle loops, reductions in a fixed
+    order, the same results as one thread), one step of it on one thread,
+    and the small dam break (c1) over all its 100 steps both ways."""
     from oracle import oracle as O
     from paper_2403_11156_amd import scenes
     O.build(force=False)
+    O.build(force=False, openmp=True)
+    model, usable, total = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", usable))
     sc = scenes.scene(scene_name)
-    st = O.State(sc)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        out = O.step(st)
-        st = O.advance(st, out)
-    dt = time.perf_counter() - t0
-    return {"value": sc.n_fluid * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} step(s) of {sc.name} from its initial state, FP64, 1 thread, {dt:.1f} s"}
+    v_all, t_all = _oracle_rate(O, sc, steps, True)
+    v_one, t_one = _oracle_rate(O, sc, 1, False)
+    c1 = scenes.scene("c1")
+    c1_all, c1_t_all = _oracle_rate(O, c1, 100, True)
+    c1_one, c1_t_one = _oracle_rate(O, c1, 100, False)
+    return {"value": v_all, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} step(s) of {sc.name} from its initial state, FP64, {threads} OpenMP threads, "
+                      f"{t_all:.1f} s",
+            "host": {"cpu_model": model, "usable_cores": usable, "logical_cpus": total},
+            "one_thread": {"value": v_one, "sample": f"1 step of {sc.name}, FP64, 1 thread, {t_one:.1f} s"},
+            "c1_100_steps": {"all_cores": c1_all, "one_thread": c1_one,
+                             "seconds": {"all_cores": round(c1_t_all, 2), "one_thread": round(c1_t_one, 2)}}}
 
 
 def main():
@@ -137,6 +188,11 @@ def main():
         # the choice of the dominant one); the timed steps then record the
         # events of the dominant kernel only, so that the throughput pays for
         # no other instrumentation
+        # untimed steps past the start-up transient (the jitter's first
+        # corrections, the first contact with the floor), so that the timed
+        # window sees the flow the scene then keeps
+        for _ in range(args.prerun):
+            sim.advance()
         n_prof = min(5, args.warmup)
         for k in range(args.warmup):
             if k == args.warmup - n_prof:
@@ -147,22 +203,27 @@ def main():
         prof_warm = {k: sim.profile_read(k) for k in PROFILED} if n_prof else {}
         dom = max(prof_warm, key=lambda k: prof_warm[k]["ms"]) if n_prof else None
         sim.profile_enable(True, only=dom)
-        iters = []
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            st = sim.advance()
-            iters.append((st["iters_div"], st["iters_dens"], st["cg_iters"], st["err_dens"], st["err_div"], st["dt"]))
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        iters, walls = [], []
+        for rep in range(max(1, args.reps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                st = sim.advance()
+                iters.append((st["iters_div"], st["iters_dens"], st["cg_iters"], st["err_dens"], st["err_div"],
+                              st["dt"]))
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
         prof = {k: sim.profile_read(k) for k in PROFILED}
         sim.profile_enable(False)
         info = sim.info()
         sim.close()
         if net is not None:
             net.close()
-        print(f"[bench] {arm}: timed {args.steps} steps in {wall:.3f} s", flush=True)
-        results[arm] = (wall, prof, iters, info, prof_warm if n_prof else prof)
-    wall, prof, iters, info, prof_table = results[arms[0]]
+        wall = sorted(walls)[len(walls) // 2]   # the median repetition
+        print(f"[bench] {arm}: {len(walls)} x {args.steps} timed steps after {args.prerun} + {args.warmup}: "
+              + ", ".join(f"{w:.4f}" for w in walls) + " s", flush=True)
+        results[arm] = (wall, prof, iters, info, prof_warm if n_prof else prof, walls)
+    wall, prof, iters, info, prof_table, walls = results[arms[0]]
 
     ms_step = wall * 1e3 / args.steps
     value = sc.n_fluid * args.steps / wall
@@ -189,6 +250,8 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "prerun": args.prerun,
+        "repetitions_s": walls,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -211,9 +274,9 @@ def main():
         "kernels_window": f"every kernel timed over the last {n_table} warmup steps",
     }
     if "learned" in results:
-        lw, _, lit, _, lprof = results["learned"]
+        lw, _, lit, _, lprof, lwalls = results["learned"]
         line["learned"] = {
-            "value": sc.n_fluid * args.steps / lw, "ms_per_step": lw * 1e3 / args.steps,
+            "value": sc.n_fluid * args.steps / lw, "ms_per_step": lw * 1e3 / args.steps, "repetitions_s": lwalls,
             "iters_per_step": {"div": sum(i[0] for i in lit) / len(lit), "dens": sum(i[1] for i in lit) / len(lit)},
             "max_err_dens": max(i[3] for i in lit),
             "warm_start_overhead_us": {k: (1e3 * lprof[k]["ms"] / max(1, lprof[k]["launches"]))

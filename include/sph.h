@@ -124,6 +124,19 @@ typedef struct sph_mlp sph_mlp;
  *                   non-pressure pass is repeated, so the step computes the
  *                   same thing either way.  1: always run the check as a
  *                   pass of its own.
+ *   alpha_max_factor  > 0: the DFSPH factor alpha_i = rho_i / D_i (Eq. 12's
+ *                   density over the squared neighbour-gradient sums) is
+ *                   capped at alpha_max_factor times the bulk-lattice factor
+ *                   alpha_ref = 2.35376 (2r)^2 / rho0; a particle whose few
+ *                   neighbours sit at the edge of the support otherwise gets
+ *                   an unbounded factor, and the stiffness it accumulates is
+ *                   carried into the next step.  0: no cap.  alpha = 0 when
+ *                   D_i = 0.  [0, 1e6].
+ *   eta_density_max > 0: the density solve also iterates while the largest
+ *                   predicted compression max_i max(rho*_i - rho0, 0) / rho0
+ *                   exceeds it (the mean of eta_density alone lets a few
+ *                   hundred particles of a million stay compressed by 10%
+ *                   where a wave hits a wall).  0: the mean only.
  */
 typedef struct sph_params {
     double r, h, rho0;
@@ -144,6 +157,8 @@ typedef struct sph_params {
     double wcsph_k, wcsph_gamma;
     double cg_warm_factor;
     int32_t separate_div_check;
+    double alpha_max_factor;
+    double eta_density_max;
 } sph_params;
 
 /* A rigid body (Sec. 3.5): mass, principal moments of inertia (body frame,
@@ -184,12 +199,15 @@ typedef struct sph_step_stats {
     double nbr_mean;
     int32_t warm_fallback;                 /* learned warm start fell back to PREVIOUS */
     int64_t step_index;                    /* steps completed, including this one */
+    double err_dens_max;                   /* largest predicted compression / rho0 after the
+                                              density solve (0 unless eta_density_max > 0) */
 } sph_step_stats;
 
 /* field mask for sph_read_state / sph_write_state */
 #define SPH_FIELD_X (1u << 0)        /* fluid positions (read, write) */
 #define SPH_FIELD_V (1u << 1)        /* fluid velocities (read, write) */
-#define SPH_FIELD_RHO (1u << 2)      /* density of the last step, Eq. (12) */
+#define SPH_FIELD_RHO (1u << 2)      /* density of the last step, Eq. (12) (read, write: the next
+                                        step's divergence warm start divides by it) */
 #define SPH_FIELD_ALPHA (1u << 3)    /* DFSPH factor of the last step */
 #define SPH_FIELD_K (1u << 4)        /* accumulated density stiffness (read, write) */
 #define SPH_FIELD_KV (1u << 5)       /* accumulated divergence stiffness (read, write) */
@@ -262,9 +280,15 @@ int sph_step(sph_ctx *ctx, sph_step_stats *stats);
 /* Blocking copy of the fields in field_mask into dst (original order). */
 int sph_read_state(sph_ctx *ctx, uint32_t field_mask, const sph_host_view *dst);
 
-/* Overwrite x, v, K, Kv, boundary and rigid state from host buffers
- * (original order); marks the neighbour lists stale.  Used to resume from a
- * checkpoint or to re-anchor a test on given inputs. */
+/* Overwrite x, v, rho, K, Kv, the implicit-viscosity correction, boundary and
+ * rigid state from host buffers (original order); marks the neighbour lists
+ * stale.  Used to resume from a checkpoint or to re-anchor a test on given
+ * inputs: a fresh context given the fields read from a running one (x, v,
+ * rho, K, Kv, dvisc, boundary, rigid) continues it bit for bit when
+ * separate_div_check = 1 (with 0, whether the next divergence check runs
+ * inside the non-pressure pass depends on the solves of the last two steps,
+ * which a fresh context has not seen; both give the same result up to
+ * rounding).  SPH_ERR_INVALID on non-finite positions or a density <= 0. */
 int sph_write_state(sph_ctx *ctx, uint32_t field_mask, const sph_host_view *src);
 
 int sph_get_info(const sph_ctx *ctx, sph_info *info);
@@ -295,8 +319,14 @@ int sph_set_forced_iters(sph_ctx *ctx, int32_t div, int32_t dens);
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch of the named kernels while enabled.  sph_profile_read returns
  * the launch count and the summed event time [ms] of one kernel name, and the
- * algorithmic bytes those launches moved (each particle's own fields read and
- * written once, plus 4 bytes per neighbour-list entry walked).  Names:
+ * algorithmic bytes those launches moved: each fluid particle's own fields
+ * read and written once, as 3-vectors and scalars without padding (per
+ * particle: integrate and cell key 44 B, sort and reorder 88, neighbour
+ * build 16, density and alpha 36 (+16 with the divergence warm start),
+ * divergence predict 32, density predict 36, pressure update 52,
+ * non-pressure 40 (+44 with the warm start's pressure, +32 with the folded
+ * divergence check)), plus 4 bytes per neighbour-list entry walked or
+ * written.  Names:
  * "nbr_build", "density_alpha", "pressure_update", "predict", "xsph", "visc",
  * "sort", "warm_features", "mlp", "integrate", "eos".  sph_profile_only
  * restricts the recording to one name (NULL: all), so that a timed run pays
@@ -340,6 +370,26 @@ int sph_mlp_grad(sph_mlp *mlp, const float *features, const float *targets, int6
  * step counter lives in the MLP object.  *loss (may be NULL) gets the loss
  * before the update. */
 int sph_mlp_train_step(sph_mlp *mlp, const float *features, const float *targets, int64_t n, float lr, double *loss);
+
+/* Allocation-free variant of sph_mlp_grad, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight training loops, hosts
+ * that forbid hipMalloc).  No sph_mlp object is needed: params (device,
+ * SPH_MLP_PARAMS FP32 masters, layout above), features (device [n][5]) and
+ * targets (device [n]) are read; grad (device, SPH_MLP_PARAMS floats) gets the
+ * same gradient as sph_mlp_grad, and loss_sum (device, one double) the SUM of
+ * the n squared residuals (sph_mlp_grad reports that sum over n).  Queued on
+ * hip_stream (NULL = the legacy default stream) and returns without
+ * synchronising; it calls no allocating routine.  The per-workgroup partial
+ * sums live in a library-owned device array of 4,732,928 bytes (256 partial
+ * gradients of 4620 floats and 256 FP64 loss partials), one copy per device,
+ * held until the process ends; every call rewrites all of it, so its contents
+ * never need clearing.  Calls that overlap on one device (two streams, two
+ * threads) share that array and race.  SPH_ERR_INVALID: a NULL pointer, n < 1,
+ * or n > SPH_MLP_NOALLOC_MAX_ROWS (the kernel scales each residual by 2/n with
+ * n in FP32, exact up to 2^24 rows). */
+#define SPH_MLP_NOALLOC_MAX_ROWS (1LL << 24)
+int sph_mlp_grad_noalloc(const float *params, const float *features, const float *targets, int64_t n, float *grad,
+                         double *loss_sum, void *hip_stream);
 
 /* Select the warm start of the density solve: SPH_WARM_ZERO, _PREVIOUS, or
  * _LEARNED with mlp (borrowed; must outlive its use).  Non-finite MLP

@@ -17,17 +17,23 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "sph_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+# the same source with its independent per-particle loops split over the
+# host's cores (OpenMP); every reduction stays sequential in a fixed order, so
+# its results equal the single-threaded library's bit for bit
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no FMA contraction; OpenMP off: the
-    oracle's loops are plain and sequential)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
+def build(force: bool = True, openmp: bool = False) -> str:
+    """Compile the oracle with gcc (no FMA contraction).  openmp=False: one
+    thread, the loops run in order (the library the tests use); True: the
+    per-particle loops marked in the source run on all cores."""
+    out = LIB_OMP if openmp else LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+        tmp = out + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC",
-                               "-shared", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+                               *(["-fopenmp"] if openmp else []), "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class Params(C.Structure):
@@ -46,6 +52,8 @@ class Params(C.Structure):
         ("warm_factor", C.c_double),
         ("solver", C.c_int32), ("wcsph_k", C.c_double), ("wcsph_gamma", C.c_double),
         ("cg_warm_factor", C.c_double),
+        ("alpha_max_factor", C.c_double),
+        ("eta_density_max", C.c_double),
     ]
 
 
@@ -89,6 +97,7 @@ class Out(C.Structure):
         ("S_err_div", C.c_double), ("S_err_dens", C.c_double), ("cg_resid", C.c_double),
         ("err_div_hist", C.c_double * 128), ("err_dens_hist", C.c_double * 128),
         ("dvisc", C.c_void_p),
+        ("err_dens_max", C.c_double), ("err_dens_max_hist", C.c_double * 128),
     ]
 
 
@@ -97,15 +106,24 @@ class Grid(C.Structure):
                 ("n", C.c_int32 * 3)]
 
 
-_lib = None
+_libs = {}
+_use_openmp = False
+
+
+def use_openmp(on: bool) -> None:
+    """Route the following calls to the all-cores build (True) or the
+    single-threaded one (False, the default)."""
+    global _use_openmp
+    _use_openmp = bool(on)
 
 
 def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build(force=True)
-        L = C.CDLL(LIB)
+    key = _use_openmp
+    if key not in _libs:
+        path = LIB_OMP if key else LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
+            build(force=True, openmp=key)
+        L = C.CDLL(path)
         L.or_W.restype = C.c_double
         L.or_W.argtypes = [C.c_double, C.c_double]
         L.or_dWdr.restype = C.c_double
@@ -136,8 +154,8 @@ def lib():
                                        C.c_void_p, C.c_void_p]
         L.or_density_alpha.argtypes = [C.POINTER(Params), C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                                        C.c_void_p, C.c_void_p, C.c_void_p]
-        _lib = L
-    return _lib
+        _libs[key] = L
+    return _libs[key]
 
 
 def _p(a: np.ndarray):
@@ -164,6 +182,8 @@ def make_params(pd: Dict, forced_div: int = -1, forced_dens: int = -1, n_rigid: 
     p.wcsph_k = pd.get("wcsph_k", 2.8e5)
     p.wcsph_gamma = pd.get("wcsph_gamma", 7.0)
     p.cg_warm_factor = pd.get("cg_warm_factor", 0.0)
+    p.alpha_max_factor = pd.get("alpha_max_factor", 0.0)
+    p.eta_density_max = pd.get("eta_density_max", 0.0)
     return p
 
 
@@ -410,10 +430,11 @@ def step(state: State, forced_div: int = -1, forced_dens: int = -1, brute: Optio
         o[k] = o[k][:nr]
     o["rigid_new"] = [_rigid_dict(rnew[i]) for i in range(nr)]
     for k in ("dt", "iters_div", "iters_dens", "converged_div", "converged_dens", "cg_iters", "err_div",
-              "err_dens", "S_err_div", "S_err_dens", "cg_resid"):
+              "err_dens", "S_err_div", "S_err_dens", "cg_resid", "err_dens_max"):
         o[k] = getattr(co, k)
     o["err_div_hist"] = np.array(co.err_div_hist[:min(128, o["iters_div"] + 1)])
     o["err_dens_hist"] = np.array(co.err_dens_hist[:min(128, o["iters_dens"] + 1)])
+    o["err_dens_max_hist"] = np.array(co.err_dens_max_hist[:min(128, o["iters_dens"] + 1)])
     return o
 
 

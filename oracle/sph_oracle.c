@@ -62,6 +62,8 @@ typedef struct or_params {
                              2 PCISPH (density solve with the prototype stiffness factor) */
     double wcsph_k, wcsph_gamma;  /* WCSPH stiffness [Pa] and exponent */
     double cg_warm_factor;        /* implicit-viscosity CG start: x0 = b + cg_warm_factor dvisc_prev */
+    double alpha_max_factor;      /* DFSPH factor capped at alpha_max_factor * alpha_ref (0: no cap) */
+    double eta_density_max;       /* > 0: the density solve also bounds the largest compression */
 } or_params;
 
 typedef struct or_rigid {
@@ -106,6 +108,8 @@ typedef struct or_out {
     double err_div, err_dens, S_err_div, S_err_dens, cg_resid;
     double err_div_hist[128], err_dens_hist[128];
     double *dvisc;             /* [nf][3] this step's implicit-viscosity correction v* - b (may be NULL) */
+    double err_dens_max;       /* largest predicted compression / rho0 after the density solve */
+    double err_dens_max_hist[128];
 } or_out;
 
 /* ------------------------------------------------------------------------ */
@@ -263,38 +267,51 @@ int64_t or_neighbors_brute(const float *xq, int64_t nq, const float *xc, int64_t
  * the contiguous cx-1..cx+1 run inner, which yields ascending sorted indices.
  * xq/xc are in their sorted orders; start is the candidate set's cell table.
  */
-int64_t or_neighbors_grid(const or_grid *g, const float *xq, int64_t nq, const float *xc,
-                          const uint32_t *start, int32_t same_set, uint32_t *counts, uint32_t *out,
-                          int64_t out_cap) {
-    int64_t tot = 0;
-    for (int64_t i = 0; i < nq; ++i) {
-        const float *xi = xq + 3 * i;
-        int32_t cx = cell_coord(xi[0], g->o[0], g->inv, g->n[0]);
-        int32_t cy = cell_coord(xi[1], g->o[1], g->inv, g->n[1]);
-        int32_t cz = cell_coord(xi[2], g->o[2], g->inv, g->n[2]);
-        uint32_t cnt = 0;
-        for (int32_t dz = -1; dz <= 1; ++dz) {
-            int32_t z = cz + dz;
-            if (z < 0 || z >= g->n[2]) continue;
-            for (int32_t dy = -1; dy <= 1; ++dy) {
-                int32_t y = cy + dy;
-                if (y < 0 || y >= g->n[1]) continue;
-                int32_t x0 = cx > 0 ? cx - 1 : 0;
-                int32_t x1 = cx < g->n[0] - 1 ? cx + 1 : g->n[0] - 1;
-                int64_t row = (int64_t)g->n[0] * (y + (int64_t)g->n[1] * z);
-                uint32_t b = start[row + x0], e = start[row + x1 + 1];
-                for (uint32_t j = b; j < e; ++j) {
-                    if (same_set && (int64_t)j == i) continue;
-                    if (dist2_f32(xi, xc + 3 * (int64_t)j) < g->h2) {
-                        if (tot >= out_cap) return -1;
-                        out[tot++] = j;
-                        ++cnt;
-                    }
+/* the neighbours of one query in stencil order; writes them to out (if not
+ * NULL) and returns their number */
+static uint32_t grid_query(const or_grid *g, const float *xi, int64_t i, const float *xc, const uint32_t *start,
+                           int32_t same_set, uint32_t *out) {
+    int32_t cx = cell_coord(xi[0], g->o[0], g->inv, g->n[0]);
+    int32_t cy = cell_coord(xi[1], g->o[1], g->inv, g->n[1]);
+    int32_t cz = cell_coord(xi[2], g->o[2], g->inv, g->n[2]);
+    uint32_t cnt = 0;
+    for (int32_t dz = -1; dz <= 1; ++dz) {
+        int32_t z = cz + dz;
+        if (z < 0 || z >= g->n[2]) continue;
+        for (int32_t dy = -1; dy <= 1; ++dy) {
+            int32_t y = cy + dy;
+            if (y < 0 || y >= g->n[1]) continue;
+            int32_t x0 = cx > 0 ? cx - 1 : 0;
+            int32_t x1 = cx < g->n[0] - 1 ? cx + 1 : g->n[0] - 1;
+            int64_t row = (int64_t)g->n[0] * (y + (int64_t)g->n[1] * z);
+            uint32_t b = start[row + x0], e = start[row + x1 + 1];
+            for (uint32_t j = b; j < e; ++j) {
+                if (same_set && (int64_t)j == i) continue;
+                if (dist2_f32(xi, xc + 3 * (int64_t)j) < g->h2) {
+                    if (out) out[cnt] = j;
+                    ++cnt;
                 }
             }
         }
-        counts[i] = cnt;
     }
+    return cnt;
+}
+
+/* counts first, then each query's list at its offset (independent queries) */
+int64_t or_neighbors_grid(const or_grid *g, const float *xq, int64_t nq, const float *xc,
+                          const uint32_t *start, int32_t same_set, uint32_t *counts, uint32_t *out,
+                          int64_t out_cap) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nq; ++i) counts[i] = grid_query(g, xq + 3 * i, i, xc, start, same_set, NULL);
+    int64_t tot = 0;
+    for (int64_t i = 0; i < nq; ++i) tot += counts[i];
+    if (tot > out_cap) return -1;
+    int64_t *off = malloc(sizeof(int64_t) * (nq + 1));
+    off[0] = 0;
+    for (int64_t i = 0; i < nq; ++i) off[i + 1] = off[i] + counts[i];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nq; ++i) grid_query(g, xq + 3 * i, i, xc, start, same_set, out + off[i]);
+    free(off);
     return tot;
 }
 
@@ -400,6 +417,7 @@ void or_rigid_local(const float *xb, const int32_t *body, int64_t nb, const or_r
 /* ------------------------------------------------------------------------ */
 static void boundary_psi(const or_params *p, const double *xb, int64_t nb, const csr *bb, double *psi) {
     double k0 = or_W(0.0, p->h);
+    #pragma omp parallel for schedule(static)
     for (int64_t b = 0; b < nb; ++b) {
         double s = k0;
         for (int64_t e = bb->start[b]; e < bb->start[b + 1]; ++e) {
@@ -451,9 +469,20 @@ static void xij_b(const world *w, int64_t i, int64_t k, double d[3]) {
 
 /* Eq. (12) density, and the DFSPH factor alpha (reading: alpha = rho / D,
  * D = |sum_F m gradW + sum_B Psi gradW|^2 + sum_F |m gradW|^2, alpha = 0 when
- * D <= 1e-6). */
+ * D = 0 (no neighbour gradient), and alpha capped at alpha_max_factor times
+ * the bulk-lattice factor alpha_ref = 2.35376 (2r)^2 / rho0: a particle that
+ * sees a few neighbours at the edge of the support has a vanishing gradient
+ * and an unbounded factor, and the stiffness it accumulates would be carried
+ * into the next step, where the same pair may sit much closer). */
+static double alpha_cap(const or_params *p) {
+    const double s = 2.0 * p->r;
+    return p->alpha_max_factor > 0.0 ? p->alpha_max_factor * 2.35376 * s * s / p->rho0 : 0.0;
+}
+
 static void density_alpha(world *w) {
     const double m = w->m, h = w->h;
+    const double amax = alpha_cap(w->p);
+    #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < w->nf; ++i) {
         double rho = m * w->k0, g[3] = {0, 0, 0}, Sg[3] = {0, 0, 0}, sq = 0.0;
         FOR_F(i, e) {
@@ -478,9 +507,11 @@ static void density_alpha(world *w) {
         double D = g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + sq;
         double SD = Sg[0] * Sg[0] + Sg[1] * Sg[1] + Sg[2] * Sg[2] + sq;
         w->rho[i] = rho;
-        if (D > 1e-6) {
+        if (D > 0.0) {
+            /* the cap is 1-Lipschitz, so the uncapped scale still bounds the error */
             w->alpha[i] = rho / D;
             w->Salpha[i] = rho / D + rho * SD / (D * D);
+            if (amax > 0.0 && w->alpha[i] > amax) w->alpha[i] = amax;
         } else {
             w->alpha[i] = 0.0;
             w->Salpha[i] = 0.0;
@@ -494,6 +525,7 @@ static void density_alpha(world *w) {
  */
 static void divergence(const world *w, const double *v, const double *Sv, double *d, double *Sd) {
     const double m = w->m, h = w->h;
+    #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < w->nf; ++i) {
         double s = 0.0, S = 0.0;
         FOR_F(i, e) {
@@ -536,6 +568,7 @@ static void pressure_update_den(const world *w, const double *kappa, const doubl
     const double m = w->m, h = w->h, dt = w->dt;
     double *dv = malloc(sizeof(double) * 3 * (w->nf ? w->nf : 1));
     double *Sdv = malloc(sizeof(double) * 3 * (w->nf ? w->nf : 1));
+    #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < w->nf; ++i) {
         double kri = kappa[i] / den[i], Skri = (Skappa[i] + fabs(kappa[i])) / den[i];
         double acc[3] = {0, 0, 0}, Sacc[3] = {0, 0, 0};
@@ -572,6 +605,14 @@ static void pressure_update(const world *w, const double *kappa, const double *S
     pressure_update_den(w, kappa, Skappa, w->rho, v, Sv);
 }
 
+/* largest clamped (compression-only) deviation */
+static double max_pos(const double *a, int64_t n) {
+    double m = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        if (a[i] > m) m = a[i];
+    return m;
+}
+
 /* mean over fluid particles of a clamped (compression-only) deviation */
 static double mean_pos(const double *a, int64_t n) {
     double s = 0.0;
@@ -589,6 +630,7 @@ static double mean_abs(const double *a, int64_t n) {
  *           (|x_ij|^2 + 0.01 h^2),  mbar = m, mu = nu rho0 (reading of Eq. 19) */
 static void visc_A(const world *w, double mu, const double *v, double *Av) {
     const double m = w->m, h = w->h;
+    #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < w->nf; ++i) {
         double acc[3] = {0, 0, 0};
         FOR_F(i, e) {
@@ -626,6 +668,7 @@ static void inv3(const double M[9], double I[9]) {
 /* 3x3 diagonal blocks of M: I + dt sum_j c_ij (-gradW_ij) x_ij^T */
 static void visc_block_inverse(const world *w, double mu, double *Pinv) {
     const double m = w->m, h = w->h;
+    #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < w->nf; ++i) {
         double B[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
         FOR_F(i, e) {
@@ -848,6 +891,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     out->cg_resid = 0.0;
     if (p->visc_model == 1) {
         /* XSPH: v*_i = v_i + dt g + eps sum_F (m/rho_j)(v_j - v_i) W_ij */
+        #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < nf; ++i) {
             double acc[3] = {0, 0, 0}, Sacc[3] = {0, 0, 0};
             FOR_F(i, e) {
@@ -868,6 +912,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
         }
     } else if (p->visc_model == 2) {
         /* Eq. (15): lap v_i = 2(d+2) sum_F (m/rho_j) (v_ij.x_ij)/(|x_ij|^2+0.01h^2) gradW_ij */
+        #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < nf; ++i) {
             double acc[3] = {0, 0, 0}, Sacc[3] = {0, 0, 0};
             FOR_F(i, e) {
@@ -967,9 +1012,11 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
 
     /* -- 8. constant-density solve (Eqs. 8, 9 with Eq. 7, Algorithm 2):
      *    rho*_i = rho_i + dt d_i(v*), kappa_i = max(rho*_i - rho0, 0) alpha_i / dt^2,
-     *    with PCISPH's c / rho_i in place of alpha_i (R21) */
+     *    with PCISPH's c / rho_i in place of alpha_i (R21).  The error of
+     *    Algorithm 2 is the mean compression; with eta_density_max > 0 the
+     *    solve also iterates while the largest compression exceeds it. */
     double *rs = malloc(s1), *Srs = malloc(s1);
-    double err_d, S_err_d;
+    double err_d, S_err_d, err_dmax = 0.0;
 #define PREDICT_DENSITY()                                                   \
     do {                                                                    \
         divergence(w, w->v, w->Sv, d, Sd);                                  \
@@ -979,13 +1026,16 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
         }                                                                   \
         err_d = mean_pos(rs, nf) / p->rho0;                                 \
         S_err_d = mean_abs(Srs, nf) / p->rho0;                              \
+        err_dmax = max_pos(rs, nf) / p->rho0;                               \
     } while (0)
     int32_t ld = 0;
     if (dfsph || pcisph) {
         PREDICT_DENSITY();
         out->err_dens_hist[0] = err_d;
+        out->err_dens_max_hist[0] = err_dmax;
         for (;;) {
-            int go = p->forced_dens >= 0 ? (ld < p->forced_dens) : (err_d > p->eta_density && ld < p->max_iters);
+            const int above = err_d > p->eta_density || (p->eta_density_max > 0.0 && err_dmax > p->eta_density_max);
+            int go = p->forced_dens >= 0 ? (ld < p->forced_dens) : (above && ld < p->max_iters);
             if (!go) break;
             for (int64_t i = 0; i < nf; ++i) {
                 double e = rs[i] > 0.0 ? rs[i] : 0.0;
@@ -999,7 +1049,10 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
             }
             ++ld;
             PREDICT_DENSITY();
-            if (ld < 128) out->err_dens_hist[ld] = err_d;
+            if (ld < 128) {
+                out->err_dens_hist[ld] = err_d;
+                out->err_dens_max_hist[ld] = err_dmax;
+            }
         }
     } else {
         /* -- 8w. WCSPH (Sec. 3.4.1): the equation of state
@@ -1029,7 +1082,9 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     out->iters_dens = ld;
     out->err_dens = err_d;
     out->S_err_dens = S_err_d;
-    out->converged_dens = err_d <= p->eta_density;
+    out->err_dens_max = (dfsph || pcisph) && p->eta_density_max > 0.0 ? err_dmax : 0.0;
+    out->converged_dens = err_d <= p->eta_density && (p->eta_density_max <= 0.0 || !(dfsph || pcisph) ||
+                                                      err_dmax <= p->eta_density_max);
 
     /* -- 9. reaction on the rigid bodies (Eq. 14): the pressure impulses of
      *    every pass of this step divided by dt, i.e. with K_tot = Kv + K:

@@ -63,6 +63,15 @@ struct sph_ctx {
     uint32_t *scan_part = nullptr;
     uint32_t *nlist = nullptr, *ncnt = nullptr, *blist = nullptr, *bcnt = nullptr;
     uint32_t *ncnt2 = nullptr, *bcnt2 = nullptr;   // the previous build's counts (read-back after a build ahead)
+    // The step's outputs that the sort does not reorder (alpha, kappa_last,
+    // v_in, the neighbour counts) stay in the order of the step that wrote
+    // them.  out_order says where that order's ids and counts are now: the
+    // current id/ncnt/bcnt (no sort since the step), id2/ncnt2/bcnt2 (one
+    // sort), or a copy in id_out/ncnt_out/bcnt_out, taken before a second sort
+    // overwrites id2.
+    enum class OutOrder { Cur, Prev, Saved } out_order = OutOrder::Cur;
+    int32_t *id_out = nullptr;
+    uint32_t *ncnt_out = nullptr, *bcnt_out = nullptr;
     // boundary, sorted order (xb.w = Psi, vb.w = body id)
     float4 *xb = nullptr, *xb2 = nullptr, *vb = nullptr, *vb2 = nullptr;
     int32_t *bid = nullptr, *bid2 = nullptr;
@@ -76,6 +85,7 @@ struct sph_ctx {
     sph::CgCtl *cgc = nullptr;                        // and of the implicit-viscosity CG
     int32_t last_cg = 0;                              // previous step's CG iterations
     int32_t last_iters[2] = {0, 0};                   // previous step's iterations (divergence, density)
+    double last_err_max = 0.0;                        // largest predicted compression after the density solve
     int32_t div_calm = 2;                             // steps in a row whose divergence solve did not iterate
     uint32_t *flags = nullptr;
     unsigned long long *nstat_part = nullptr;
@@ -374,6 +384,17 @@ double fluid_list_bytes(const sph_ctx *c) { return 4.0 * c->nbr_sum_f; }
 // statistics) once the stream has passed them.
 int build_queue(sph_ctx *c) {
     hipStream_t s = c->stream;
+    // the sort below replaces id2 and the previous counts: the last step's
+    // output order moves there, or, if it is there already, is saved first
+    if (c->out_order == sph_ctx::OutOrder::Prev) {
+        const size_t n4 = sizeof(int32_t) * (size_t)c->nf;
+        HIP_TRY(c, hipMemcpyAsync(c->id_out, c->id2, n4, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(c, hipMemcpyAsync(c->ncnt_out, c->ncnt2, n4, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(c, hipMemcpyAsync(c->bcnt_out, c->bcnt2, n4, hipMemcpyDeviceToDevice, s));
+        c->out_order = sph_ctx::OutOrder::Saved;
+    } else if (c->out_order == sph_ctx::OutOrder::Cur) {
+        c->out_order = sph_ctx::OutOrder::Prev;
+    }
     HIP_TRY(c, sph::launch_fill_u32(c->flags, 1, 0u, s));
     if (c->boundary_dirty) {
         ProfScope ps(c, "sort", 0.0);
@@ -382,14 +403,14 @@ int build_queue(sph_ctx *c) {
         c->boundary_dirty = false;
     }
     {
-        ProfScope ps(c, "sort", 56.0 * c->nf);
+        ProfScope ps(c, "sort", (16.0 + 72.0) * c->nf);   // histogram, scan and scatter ~16 B, reorder 36 + 36
         int rc = sort_fluid(c);
         if (rc) return rc;
     }
     std::swap(c->ncnt, c->ncnt2);   // keep the previous build's counts
     std::swap(c->bcnt, c->bcnt2);
     {
-        ProfScope ps(c, "nbr_build", 16.0 * c->nf + 8.0 * c->nf + list_bytes(c));
+        ProfScope ps(c, "nbr_build", 16.0 * c->nf + list_bytes(c));   // x in, count out, lists written
         HIP_TRY(c, sph::launch_nbr_build(c->x, c->nf, c->xb, c->start_f, c->start_b, c->g, c->nlist, c->ncnt, c->capf,
                                          c->blist, c->bcnt, c->capb, c->flags, c->nstat_part, c->hs_dev, s));
     }
@@ -425,7 +446,7 @@ int build(sph_ctx *c) {
 // go (nullable): skip the pass on the device once the solve needs no more
 // iterations.
 int pressure_pass(sph_ctx *c, float *Kacc, float *klast, float dt, const int32_t *go) {
-    ProfScope ps(c, "pressure_update", (48.0 + (klast ? 24.0 : 20.0)) * c->nf + list_bytes(c));
+    ProfScope ps(c, "pressure_update", 52.0 * c->nf + list_bytes(c));   // x, v, kappa in; v, K out
     HIP_TRY(c, sph::launch_pressure_update(c->nf, c->x, c->v, c->kappa, Kacc, klast, c->nlist, c->ncnt, c->xb,
                                            c->blist, c->bcnt, c->kc, dt, go, c->stream));
     return SPH_OK;
@@ -436,7 +457,8 @@ int predict_pass(sph_ctx *c, int mode, float dt, bool first, const sph::SolveCtl
     float *dout = (mode == 0 && c->want_d) ? c->dbuf : nullptr;
     int nparts = 0;
     {
-        ProfScope ps(c, "predict", (56.0 + (dout ? 4.0 : 0.0)) * c->nf + list_bytes(c));
+        // x and v (plus rho in the density solve) in, kappa out
+        ProfScope ps(c, "predict", (mode == 0 ? 32.0 : 36.0) * c->nf + list_bytes(c));
         HIP_TRY(c, sph::launch_predict(mode, c->nf, c->x, c->v, c->rho, c->alpha, c->kappa, c->nlist, c->ncnt,
                                        c->xb, c->vb_moving ? c->vb : nullptr, c->blist, c->bcnt, c->kc, dt,
                                        c->red_part, c->ctl, first,
@@ -456,6 +478,10 @@ sph::SolveCtl solve_init(const sph_ctx *c, int mode, float dt, int32_t forced, d
     init.forced = forced;
     init.max_iters = c->P.max_iters;
     init.go = 1;
+    if (mode == 1 && c->P.eta_density_max > 0.0) {   // the density solve may bound the largest deviation too
+        init.eta_max = c->P.eta_density_max;
+        init.max_scale = 1.0 / c->P.rho0;
+    }
     return init;
 }
 
@@ -507,6 +533,7 @@ int jacobi_iterate(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, co
         if (keep < c->prof_pending.size()) c->prof_pending.resize(keep);
     }
     c->last_iters[mode] = h.iters;
+    if (mode == 1) c->last_err_max = h.err_max;
     *iters = h.iters;
     *err_out = h.err;
     return SPH_OK;
@@ -670,7 +697,8 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
 
     // 2. density, alpha, and (DFSPH) the divergence solve's warm start
     {
-        ProfScope ps(c, "density_alpha", 80.0 * nf + list_bytes(c) + (dfsph && warm ? 12.0 * nf : 0.0));
+        // x in; rho, alpha, the volume out; with the divergence warm start also v in and out
+        ProfScope ps(c, "density_alpha", 36.0 * nf + list_bytes(c) + (dfsph && warm ? 16.0 * nf : 0.0));
         HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, c->nlist, c->ncnt, c->xb, c->blist, c->bcnt, c->kc,
                                              c->rho, c->alpha, c->v_in, c->Kv, dt, dfsph ? wf : 0.0f,
                                              c->pci_c, s));
@@ -752,7 +780,8 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         const bool press = (ppe && warm) || wcsph;
         auto nonpressure = [&](bool with_press, const sph::DivCheck *dc, int *nparts) -> int {
             const double walk = (with_press || dc) ? list_bytes(c) : fluid_list_bytes(c);
-            ProfScope ps(c, "xsph", 72.0 * nf + (with_press ? 16.0 * nf : 0.0) + (dc ? 12.0 * nf : 0.0) + walk);
+            // x, v in, v* out; the warm start's pressure adds its 32/12, the folded check the predict's 32
+            ProfScope ps(c, "xsph", 40.0 * nf + (with_press ? 44.0 * nf : 0.0) + (dc ? 32.0 * nf : 0.0) + walk);
             HIP_TRY(c, sph::launch_nonpressure(c->P.visc_model, nf, c->x, c->v, c->v2, c->rho, c->nlist, c->ncnt,
                                                c->kc, dt, gx, gy, gz, (float)c->P.visc, c->K, c->kappa, wf,
                                                setup_in_pass, with_press, c->xb, c->blist, c->bcnt,
@@ -856,6 +885,8 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         HIP_TRY(c, hipEventRecord(c->vmax_done, s));
         c->vmax_ready = true;
     }
+    // this step's outputs are in the current order until the next sort
+    c->out_order = sph_ctx::OutOrder::Cur;
     // auto_rebuild: the next step's sort and neighbour build go on the stream
     // now, so the device runs them while the host returns and comes back;
     // the next step reads their status after its density pass
@@ -875,8 +906,10 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         st->iters_dens = id;
         st->err_div = ev;
         st->err_dens = ed;
+        st->err_dens_max = c->P.eta_density_max > 0.0 ? c->last_err_max : 0.0;
         st->converged_div = ev <= c->P.eta_divergence;
-        st->converged_dens = ed <= c->P.eta_density;
+        st->converged_dens = ed <= c->P.eta_density &&
+                             (c->P.eta_density_max <= 0.0 || c->last_err_max <= c->P.eta_density_max);
         st->cg_iters = cg_it;
         st->cg_resid = cg_res;
         st->nbr_min = (int32_t)(c->nstats[0] >= 0xffffffffull ? 0 : c->nstats[0]);
@@ -957,6 +990,10 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
         return fail(nullptr, SPH_ERR_INVALID, "invalid parameter value");
     if (!(p->cg_warm_factor >= 0.0 && p->cg_warm_factor <= 4.0))
         return fail(nullptr, SPH_ERR_INVALID, "cg_warm_factor outside [0, 4]");
+    if (!(p->eta_density_max >= 0.0))
+        return fail(nullptr, SPH_ERR_INVALID, "eta_density_max must be >= 0");
+    if (!(p->alpha_max_factor >= 0.0 && p->alpha_max_factor <= 1e6))
+        return fail(nullptr, SPH_ERR_INVALID, "alpha_max_factor outside [0, 1e6]");
     if (p->separate_div_check != 0 && p->separate_div_check != 1)
         return fail(nullptr, SPH_ERR_INVALID, "separate_div_check must be 0 or 1");
     if (p->solver != SPH_SOLVER_DFSPH && p->warm_start == SPH_WARM_LEARNED)
@@ -1018,6 +1055,9 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     c->kc.kg = (float)(6.0 * kk / p->h);
     c->kc.m = (float)(p->rho0 * 8.0 * p->r * p->r * p->r);
     c->kc.rho0 = (float)p->rho0;
+    c->kc.alpha_max = p->alpha_max_factor > 0.0
+                          ? (float)(p->alpha_max_factor * 2.35376 * 4.0 * p->r * p->r / p->rho0)
+                          : 0.0f;
     if (p->solver == SPH_SOLVER_PCISPH) c->pci_c = (float)pcisph_factor(*p);
 
     const int64_t nf = c->nf, nb = c->nb;
@@ -1040,6 +1080,7 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     ALLOC(c->count, ncell); ALLOC(c->start_f, ncell + 1); ALLOC(c->start_b, ncell + 1); ALLOC(c->scan_part, 2 * scan_chunks + 8);
     // 32-bit lists in chunks of four entries (capacity rounded up to a chunk)
     ALLOC(c->nlist, (int64_t)(c->capf + 3) / 4 * 4 * nf); ALLOC(c->ncnt, nf); ALLOC(c->ncnt2, nf);
+    ALLOC(c->id_out, nf); ALLOC(c->ncnt_out, nf); ALLOC(c->bcnt_out, nf);
     ALLOC(c->blist, (int64_t)(c->capb + 3) / 4 * 4 * nf); ALLOC(c->bcnt, nf); ALLOC(c->bcnt2, nf);
     ALLOC(c->xb, nb); ALLOC(c->xb2, nb); ALLOC(c->vb, nb); ALLOC(c->vb2, nb); ALLOC(c->bid, nb); ALLOC(c->bid2, nb);
     ALLOC(c->bkey, nb); ALLOC(c->bslot, nb); ALLOC(c->bsrc, nb); ALLOC(c->blocal, 3 * nb);
@@ -1191,13 +1232,18 @@ int sph_read_state(sph_ctx *c, uint32_t mask, const sph_host_view *dst) {
     std::vector<float> f1;
     int rc = d2h(c, id, c->id, nf);
     if (rc) return rc;
-    // after a build queued ahead (auto_rebuild), x, v, rho, K, Kv and the
-    // correction are in the new sorted order, the step's other outputs (alpha,
-    // kappa, the input velocity, the counts) still in the step's order
-    const bool ahead = c->build_ahead;
-    if (ahead && (rc = d2h(c, id_prev, c->id2, nf))) return rc;
+    // x, v, rho, K, Kv and the correction are in the current sorted order;
+    // the step's other outputs (alpha, kappa, the input velocity, the counts)
+    // in the order of the step that wrote them (out_order)
+    const sph_ctx::OutOrder oo = c->out_order;
+    const int32_t *id_of_out = oo == sph_ctx::OutOrder::Cur ? c->id : oo == sph_ctx::OutOrder::Prev ? c->id2 : c->id_out;
+    const uint32_t *ncnt_of_out = oo == sph_ctx::OutOrder::Cur ? c->ncnt
+                                  : oo == sph_ctx::OutOrder::Prev ? c->ncnt2 : c->ncnt_out;
+    const uint32_t *bcnt_of_out = oo == sph_ctx::OutOrder::Cur ? c->bcnt
+                                  : oo == sph_ctx::OutOrder::Prev ? c->bcnt2 : c->bcnt_out;
+    if (oo != sph_ctx::OutOrder::Cur && (rc = d2h(c, id_prev, id_of_out, nf))) return rc;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    const std::vector<int32_t> &idp = ahead ? id_prev : id;
+    const std::vector<int32_t> &idp = oo != sph_ctx::OutOrder::Cur ? id_prev : id;
     auto scatter3 = [&](const std::vector<float4> &src, float *out) {
         for (int64_t s = 0; s < nf; ++s) {
             const int64_t i = id[s];
@@ -1252,8 +1298,8 @@ int sph_read_state(sph_ctx *c, uint32_t mask, const sph_host_view *dst) {
     if ((mask & SPH_FIELD_KAPPA) && dst->kappa && (rc = read1(c->kappa_last, dst->kappa, idp))) return rc;
     if ((mask & SPH_FIELD_NBR) && (dst->n_fluid_nbrs || dst->n_boundary_nbrs)) {
         std::vector<uint32_t> a, b;
-        if ((rc = d2h(c, a, ahead ? c->ncnt2 : c->ncnt, nf))) return rc;
-        if ((rc = d2h(c, b, ahead ? c->bcnt2 : c->bcnt, nf))) return rc;
+        if ((rc = d2h(c, a, ncnt_of_out, nf))) return rc;
+        if ((rc = d2h(c, b, bcnt_of_out, nf))) return rc;
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         for (int64_t s = 0; s < nf; ++s) {
             if (dst->n_fluid_nbrs) dst->n_fluid_nbrs[idp[s]] = (int32_t)a[s];
@@ -1335,6 +1381,12 @@ int sph_write_state(sph_ctx *c, uint32_t mask, const sph_host_view *src) {
     if ((mask & SPH_FIELD_V) && src->v && (rc = write3(src->v, c->v, false))) return rc;
     if ((mask & SPH_FIELD_K) && src->K && (rc = write1(src->K, c->K))) return rc;
     if ((mask & SPH_FIELD_KV) && src->Kv && (rc = write1(src->Kv, c->Kv))) return rc;
+    if ((mask & SPH_FIELD_RHO) && src->rho) {
+        for (int64_t i = 0; i < nf; ++i)
+            if (!(src->rho[i] > 0.0f) || !std::isfinite(src->rho[i]))
+                return fail(c, SPH_ERR_INVALID, "density must be positive and finite");
+        if ((rc = write1(src->rho, c->rho))) return rc;
+    }
     if ((mask & SPH_FIELD_DVISC) && src->dvisc) {
         if (!c->dvisc) return fail(c, SPH_ERR_INVALID, "dvisc needs the implicit viscosity model");
         if (!finite3(src->dvisc, nf)) return fail(c, SPH_ERR_INVALID, "non-finite dvisc");

@@ -102,6 +102,14 @@ __device__ __forceinline__ void for_each_nbr(const uint32_t* __restrict__ list, 
     }
 }
 
+// A particle's term of a solver error: its clamped (compression-only)
+// deviation, except that a non-finite deviation passes through unclamped
+// (fmaxf would turn NaN into 0), so that a non-finite state makes the
+// error non-finite and the host reports it instead of declaring convergence.
+__device__ __forceinline__ double err_term(float dev, float clamped) {
+    return (double)(__builtin_isfinite(dev) ? clamped : dev);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     return v;
@@ -154,26 +162,65 @@ __device__ double block_sum_n(double v) {
     return r;
 }
 
+// Workgroup maximum of kBlock threads (exact in any order); valid in thread 0.
+__device__ float block_max(float v) {
+    __shared__ float wm[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_down(v, off, 64));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float r = 0.0f;
+    if (threadIdx.x == 0) {
+        r = wm[0];
+        for (int w = 1; w < kBlock / 64; ++w) r = fmaxf(r, wm[w]);
+    }
+    __syncthreads();
+    return r;
+}
+
+template <int NT>
+__device__ double block_max_n(double v) {
+    __shared__ double wm[NT / 64];
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        r = wm[0];
+        for (int w = 1; w < NT / 64; ++w) r = fmax(r, wm[w]);
+    }
+    __syncthreads();
+    return r;
+}
+
 constexpr int kFinishThreads = 1024;   // the solve finish sums ~10^4 partials per pass
 
 // Finish of a predict pass: err = scale * (sum of the partials in a fixed
 // order); the solve's first finish starts the control block from init, a
 // later one counts the iteration; then decide whether another one is due:
-// exactly `forced` iterations, else while err > eta and fewer than
-// max_iters.  Nothing happens once go is 0.  The block is mirrored to host.
+// exactly `forced` iterations, else while err > eta (or, with eta_max > 0,
+// err_max > eta_max, err_max from the per-workgroup maxima stored after the
+// sums) and fewer than max_iters.  Nothing happens once go is 0.  The block
+// is mirrored to host.
 __global__ void __launch_bounds__(kFinishThreads) k_finish_solve(const double* __restrict__ partials, int nblk,
                                                                  SolveCtl* ctl, bool first, SolveCtl init,
                                                                  HostStatus* host) {
     if (!first && ctl->go == 0) return;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kFinishThreads) acc += partials[b];
+    const bool with_max = (first ? init.eta_max : ctl->eta_max) > 0.0;
+    double acc = 0.0, mx = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kFinishThreads) {
+        acc += partials[b];
+        if (with_max) mx = fmax(mx, partials[nblk + b]);
+    }
     acc = block_sum_n<kFinishThreads>(acc);
+    if (with_max) mx = block_max_n<kFinishThreads>(mx);
     if (threadIdx.x == 0) {
         SolveCtl c = first ? init : *ctl;
         if (first) c.iters = 0;
         else c.iters += 1;
         c.err = acc * c.scale;
-        c.go = c.forced >= 0 ? (c.iters < c.forced ? 1 : 0) : ((c.err > c.eta && c.iters < c.max_iters) ? 1 : 0);
+        c.err_max = with_max ? mx * c.max_scale : 0.0;
+        const bool above = c.err > c.eta || (with_max && c.err_max > c.eta_max);
+        c.go = c.forced >= 0 ? (c.iters < c.forced ? 1 : 0) : ((above && c.iters < c.max_iters) ? 1 : 0);
         *ctl = c;
         host->solve = c;
     }

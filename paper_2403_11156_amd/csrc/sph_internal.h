@@ -25,6 +25,7 @@ struct Kern {
     float kg;        // 6 k / h: dW/dr = kg f'(q) / 6 with f' the polynomial slope
     float m;         // fluid particle mass rho0 (2r)^3
     float rho0;
+    float alpha_max;  // cap of the DFSPH factor alpha (0: none)
 };
 
 // neighbour statistics: [min, max, sum, sum_fluid]
@@ -41,6 +42,9 @@ struct SolveCtl {
     int32_t go;          // 1 while another iteration is due
     int32_t forced;      // >= 0: exactly this many iterations
     int32_t max_iters;
+    double eta_max;      // > 0: also iterate while err_max > eta_max
+    double max_scale;    // err_max = max_scale * (largest clamped deviation)
+    double err_max;
 };
 
 // Device-side state of the implicit-viscosity CG (Eq. 19): as SolveCtl, the

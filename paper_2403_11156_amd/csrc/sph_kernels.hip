@@ -432,7 +432,9 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
     const float D = gx * gx + gy * gy + gz * gz + sq;
     rho[i] = rr;
     // PCISPH (pci_c > 0): the prototype factor c / rho replaces alpha
-    alpha[i] = pci_c > 0.0f ? pci_c / rr : (D > 1e-6f ? rr / D : 0.0f);
+    float a = D > 0.0f ? rr / D : 0.0f;
+    if (kc.alpha_max > 0.0f) a = fminf(a, kc.alpha_max);
+    alpha[i] = pci_c > 0.0f ? pci_c / rr : a;
     float4 vi = v[i];
     v_in[i] = vi;
     if (WARM) {
@@ -498,6 +500,7 @@ __global__ void __launch_bounds__(kBlock) k_predict(
     int q;
     const int64_t i = group_particle<L>(q);
     double e = 0.0;
+    float em = 0.0f;   // the density solve's largest clamped deviation (MODE 1)
     if (i < nf) {   // whole groups
         const float4 xi = x[i];
         const float4 vi = v[i];
@@ -525,12 +528,13 @@ __global__ void __launch_bounds__(kBlock) k_predict(
                 if (dout) dout[i] = d;
                 const float ep = fmaxf(d, 0.0f);
                 kap = ep * alpha[i] / dt;
-                e = (double)ep;
+                e = err_term(d, ep);
             } else {
                 const float dev = (ri - kc.rho0) + dt * d;
                 const float ep = fmaxf(dev, 0.0f);
                 kap = ep * alpha[i] / (dt * dt);
-                e = (double)ep;
+                e = err_term(dev, ep);
+                em = ep;
             }
             kappa[i] = kap;
             x[i].w = kap / ri;
@@ -538,6 +542,10 @@ __global__ void __launch_bounds__(kBlock) k_predict(
     }
     const double bs = block_sum(e);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+    if (MODE == 1) {   // the workgroup maxima follow the sums (read when the solve bounds the maximum)
+        const float bm = block_max(em);
+        if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = (double)bm;
+    }
 }
 
 // Non-pressure accelerations (Algorithm 1, first lines): v* = v + dt g plus
@@ -650,7 +658,7 @@ __global__ void __launch_bounds__(kBlock) k_nonpressure(
                 if (dc.dout) dc.dout[i] = dd;
                 const float ep = fmaxf(dd, 0.0f);
                 const float kap = ep * dc.alpha[i] / dt;
-                e = (double)ep;
+                e = err_term(dd, ep);
                 if (PRESS) {
                     dc.kvs[i] = make_float2(kap, kap / ri);
                 } else {
@@ -715,7 +723,7 @@ __global__ void k_eos(int64_t nf, float4* __restrict__ x, const float* __restric
         kappa[i] = kap;
         K[i] = 0.0f;
         x[i].w = kap / r;
-        e = (double)fmaxf(r - kc.rho0, 0.0f);
+        e = err_term(r - kc.rho0, fmaxf(r - kc.rho0, 0.0f));
     }
     const double bs = block_sum(e);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;

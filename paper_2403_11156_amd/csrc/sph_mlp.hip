@@ -585,6 +585,7 @@ __global__ void k_mlp_adam(float* __restrict__ P, const float* __restrict__ grad
 }  // namespace
 
 constexpr int kMlpGradBlocks = 256;
+constexpr int NPARAM_PUBLIC = NPARAM;
 
 int mlp_param_count() { return NPARAM; }
 int mlp_grad_blocks() { return kMlpGradBlocks; }
@@ -634,3 +635,54 @@ hipError_t launch_mlp_adam(float* P, const float* grad, float* m, float* v, floa
 }
 
 }  // namespace sph
+
+// ---------------------------------------------------------------------------
+// Allocation-free MLP gradient.  The per-workgroup partial gradients and FP64
+// loss partials live in a file-scope device array instead of buffers that
+// sph_mlp_create allocates.  Every launch writes all kMlpGradBlocks partial
+// slots before the finishing kernel reads them, so nothing in it has to start
+// at zero.  Each device holds its own copy of the array; host code reaches it
+// only through the address hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+#include <mutex>
+
+#include "sph.h"
+
+namespace {
+constexpr size_t kNoAllocPartBytes = sizeof(float) * (size_t)sph::kMlpGradBlocks * sph::NPARAM_PUBLIC;
+constexpr size_t kNoAllocBytes = kNoAllocPartBytes + sizeof(double) * sph::kMlpGradBlocks;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];   // device address of `scratch` on each device (null until first use)
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// The address of `scratch` on the current device, looked up once per device.
+static int scratch_address(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SPH_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SPH_ERR_DEVICE;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return SPH_OK;
+}
+
+extern "C" int sph_mlp_grad_noalloc(const float* params, const float* features, const float* targets, int64_t n,
+                                    float* grad, double* loss_sum, void* hip_stream) {
+    if (!params || !features || !targets || !grad || !loss_sum || n <= 0) return SPH_ERR_INVALID;
+    if (n > SPH_MLP_NOALLOC_MAX_ROWS) return SPH_ERR_INVALID;
+    void* base = nullptr;
+    const int rc = scratch_address(&base);
+    if (rc != SPH_OK) return rc;
+    float* part = static_cast<float*>(base);
+    double* loss_part = reinterpret_cast<double*>(static_cast<unsigned char*>(base) + kNoAllocPartBytes);
+    return sph::launch_mlp_grad(params, features, targets, n, part, loss_part, grad, loss_sum,
+                                (hipStream_t)hip_stream) == hipSuccess
+               ? SPH_OK
+               : SPH_ERR_DEVICE;
+}

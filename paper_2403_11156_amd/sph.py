@@ -41,6 +41,8 @@ class sph_params(C.Structure):
         ("solver", C.c_int32), ("wcsph_k", C.c_double), ("wcsph_gamma", C.c_double),
         ("cg_warm_factor", C.c_double),
         ("separate_div_check", C.c_int32),
+        ("alpha_max_factor", C.c_double),
+        ("eta_density_max", C.c_double),
     ]
 
 
@@ -66,6 +68,7 @@ class sph_step_stats(C.Structure):
         ("cg_iters", C.c_int32), ("cg_resid", C.c_double),
         ("nbr_min", C.c_int32), ("nbr_max", C.c_int32), ("nbr_mean", C.c_double),
         ("warm_fallback", C.c_int32), ("step_index", C.c_int64),
+        ("err_dens_max", C.c_double),
     ]
 
     def as_dict(self) -> Dict:
@@ -136,6 +139,7 @@ def _load():
         "sph_mlp_forward": (C.c_int, [P, P, P, C.c_int64]),
         "sph_mlp_grad": (C.c_int, [P, P, P, C.c_int64, P, C.POINTER(C.c_double)]),
         "sph_mlp_train_step": (C.c_int, [P, P, P, C.c_int64, C.c_float, C.POINTER(C.c_double)]),
+        "sph_mlp_grad_noalloc": (C.c_int, [P, P, P, C.c_int64, P, P, P]),
         "sph_set_warm_start": (C.c_int, [P, C.c_int32, P]),
         "sph_enable_trace": (C.c_int, [P, P, P, C.c_int64]),
         "sph_trace_rows": (C.c_int, [P, C.POINTER(C.c_int64)]),
@@ -172,6 +176,7 @@ sph_mlp_set_params = lib.sph_mlp_set_params
 sph_mlp_forward = lib.sph_mlp_forward
 sph_mlp_grad = lib.sph_mlp_grad
 sph_mlp_train_step = lib.sph_mlp_train_step
+sph_mlp_grad_noalloc = lib.sph_mlp_grad_noalloc
 sph_set_warm_start = lib.sph_set_warm_start
 sph_enable_trace = lib.sph_enable_trace
 sph_trace_rows = lib.sph_trace_rows
@@ -210,6 +215,8 @@ def make_params(pd: Dict) -> sph_params:
     p.wcsph_gamma = pd.get("wcsph_gamma", 7.0)
     p.cg_warm_factor = pd.get("cg_warm_factor", 0.0)
     p.separate_div_check = pd.get("separate_div_check", 0)
+    p.alpha_max_factor = pd.get("alpha_max_factor", 0.0)
+    p.eta_density_max = pd.get("eta_density_max", 0.0)
     return p
 
 
@@ -354,7 +361,7 @@ class Simulation:
             out["rigid"] = _rigid_dicts(rig, nr)
         return out
 
-    def write(self, x=None, v=None, K=None, Kv=None, xb=None, vb=None, rigid=None, dvisc=None):
+    def write(self, x=None, v=None, K=None, Kv=None, xb=None, vb=None, rigid=None, dvisc=None, rho=None):
         hv = sph_host_view()
         keep = []
         mask = 0
@@ -372,6 +379,7 @@ class Simulation:
         put("v", v, FIELD_V, (self.nf, 3))
         put("K", K, FIELD_K, (self.nf,))
         put("Kv", Kv, FIELD_KV, (self.nf,))
+        put("rho", rho, FIELD_RHO, (self.nf,))
         put("dvisc", dvisc, FIELD_DVISC, (self.nf, 3))
         put("x_boundary", xb, FIELD_BOUNDARY, (self.nb, 3))
         put("v_boundary", vb, FIELD_BOUNDARY, (self.nb, 3))

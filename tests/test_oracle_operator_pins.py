@@ -327,3 +327,61 @@ def test_alpha_of_the_first_fluid_layer_over_a_wall_closed_form():
         PSI_WALL * KN * sum(n * f(q) for q, n, _ in WALL9)
     assert abs(rho[pick] - r_expect) < 1e-9 * r_expect
     assert abs(alpha[pick] - r_expect / (g * g + sq)) < 1e-9 * alpha[pick]
+
+
+# ------------------------------------------------------ the factor's cap (R3)
+def test_alpha_cap_on_a_lone_pair_near_the_support_edge():
+    # two particles at distance 0.95 h: D = |m gradW|^2 + |m gradW|^2 (gradient
+    # sum and sum of squares hold the one neighbour), rho = m k (1 + f(q)), so
+    # alpha = rho / (2 (m k f'(q)/h)^2), ~4e3 times the bulk factor alpha_ref =
+    # 2.35376 s^2/rho0; with alpha_max_factor = C the factor is C alpha_ref
+    # exactly, and a bulk particle (alpha = 0.99997 alpha_ref) is unaffected
+    q = 0.95
+    xf = np.array([[0.5, 0.5, 0.5], [0.5 + q * H, 0.5, 0.5]], np.float32)
+    assert abs(float(xf[1, 0]) - 0.5 - q * H) < 1e-7
+    qf = (float(xf[1, 0]) - 0.5) / H
+    rho_e = M * KN * (1.0 + f(qf))
+    alpha_e = rho_e / (2.0 * (M * KN * fp(qf) / H) ** 2)
+    aref = 2.35376 * S * S / RHO0
+    pd = _scene(xf).params
+    rho, alpha, _ = O.density_alpha(pd, xf, np.zeros((0, 3), np.float32))
+    np.testing.assert_allclose(rho, rho_e, rtol=1e-12)
+    np.testing.assert_allclose(alpha, alpha_e, rtol=1e-9)
+    assert alpha_e > 1e3 * aref
+    for C in (10.0, 4.0):
+        _, a_c, _ = O.density_alpha(dict(pd, alpha_max_factor=C), xf, np.zeros((0, 3), np.float32))
+        np.testing.assert_allclose(a_c, C * aref, rtol=1e-15)
+    x, c = _lattice()
+    _, a_bulk, _ = O.density_alpha(dict(pd, alpha_max_factor=4.0), x, np.zeros((0, 3), np.float32))
+    sf2 = sum(n * fp(q) ** 2 for q, n in SHELLS)
+    assert abs(a_bulk[c] - RHO_LAT * (2.0 * math.pi * S) ** 2 / (RHO0 ** 2 * sf2)) < 1e-10 * a_bulk[c]
+    # an isolated particle has no gradient at all: alpha = 0, cap or not
+    _, a_iso, _ = O.density_alpha(dict(pd, alpha_max_factor=4.0), xf[:1], np.zeros((0, 3), np.float32))
+    assert a_iso[0] == 0.0
+
+
+# ------------------------------------- the density solve's bound on the maximum
+def test_density_solve_bounds_the_largest_compression():
+    # one particle of a resting bulk lattice pushed 0.3 s toward a neighbour:
+    # a few particles are compressed by several percent while the mean over
+    # the 729 stays below eta.  With zero velocities rho* = rho, so the
+    # solve's first maximum is max_i (rho_i - rho0)/rho0 of the (pinned)
+    # density sum; the mean rule alone does not iterate, the bound on the
+    # maximum iterates until the largest compression is below it
+    x, c = _lattice()
+    x = x.copy()
+    x[c, 0] += np.float32(0.3 * S)
+    sc = _scene(x)
+    rho, _, _ = O.density_alpha(sc.params, x, np.zeros((0, 3), np.float32))
+    top = (rho.max() - RHO0) / RHO0
+    mean = np.maximum(rho - RHO0, 0.0).mean() / RHO0
+    assert top > 0.02 and mean < 1e-3
+    free = O.step(O.State(sc))
+    assert free["iters_dens"] == 0 and free["err_dens_max"] == 0.0
+    eta_max = 0.005
+    sc.params = dict(sc.params, eta_density_max=eta_max)
+    out = O.step(O.State(sc))
+    h, hm = out["err_dens_hist"], out["err_dens_max_hist"]
+    assert abs(hm[0] - top) < 1e-12 and abs(h[0] - mean) < 1e-12
+    assert out["iters_dens"] >= 1 and out["converged_dens"]
+    assert hm[-1] <= eta_max and (hm[:-1] > eta_max).all() and out["err_dens_max"] == hm[-1]

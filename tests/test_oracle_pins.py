@@ -629,3 +629,28 @@ def test_divergence_warm_start_uses_previous_stiffness_over_previous_density():
     st2.rho_prev = 2.0 * st.rho_prev
     out2 = O.step(st2, forced_div=0, forced_dens=0)
     np.testing.assert_allclose(out2["v"] - st.v, 0.5 * dv, rtol=1e-9, atol=1e-15)
+
+
+def test_openmp_oracle_equals_the_single_threaded_one():
+    # the all-cores build (used only to time the CPU baseline) splits the
+    # independent per-particle loops and keeps every reduction in order, so
+    # it computes the same bits as the single-threaded oracle
+    sc = scenes.scene("c1")
+    outs = []
+    for omp in (False, True):
+        O.build(force=False, openmp=omp)
+        O.use_openmp(omp)
+        try:
+            st = O.State(sc)
+            res = []
+            for _ in range(2):
+                out = O.step(st)
+                res.append(out)
+                st = O.advance(st, out)
+            outs.append(res)
+        finally:
+            O.use_openmp(False)
+    for a, b in zip(*outs):
+        for k in ("x", "v", "rho", "alpha", "K", "Kv", "kappa", "nf_count", "nb_count"):
+            assert np.array_equal(a[k], b[k]), k
+        assert a["iters_dens"] == b["iters_dens"] and a["err_dens"] == b["err_dens"]
