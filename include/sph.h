@@ -347,8 +347,9 @@ int sph_profile_read(sph_ctx *ctx, const char *kernel, int64_t *launches, double
  * in_shift[5] in_scale[5] out_scale; output y = out_scale * z with
  * z = h2 . w3 + b3 and inputs normalised as (f - in_shift) * in_scale.
  * Features of particle i, all dimensionless: (rho_i - rho0)/rho0,
- * dt d*_i/rho0 (d* the density change rate of v*, after the non-pressure
- * forces), n_i/26 (fluid + boundary neighbours), K_prev dt^2/(alpha_i rho0),
+ * dt d_i/rho0 (d the density change rate, Eq. 9 in the DFSPH form, of the
+ * step's input velocity, before any pressure of the step), n_i/26 (fluid +
+ * boundary neighbours), K_prev dt^2/(alpha_i rho0),
  * alpha_i/alpha_ref (alpha_ref = 2.35376 (2r)^2/rho0).  Prediction y is the
  * step's final density stiffness in the same units: K0 = max(0, y alpha rho0
  * / dt^2).

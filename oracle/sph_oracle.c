@@ -826,6 +826,10 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     double *v_in = malloc(s3);
     memcpy(v_in, w->v, s3);
     double *d = malloc(s1), *Sd = malloc(s1), *kap = malloc(s1), *Skap = malloc(s1);
+    /* the density change rate of the step's input velocity (before any
+     * pressure of this step), a feature of the learned warm start */
+    double *d_in = malloc(s1), *Sd_in = malloc(s1);
+    divergence(w, w->v, w->Sv, d_in, Sd_in);
     double *Kv = malloc(s1), *SKv = malloc(s1), *K = malloc(s1), *SK = malloc(s1);
     double *kappa_last = calloc((size_t)(nf ? nf : 1), sizeof(double));
     double *Skappa_last = calloc((size_t)(nf ? nf : 1), sizeof(double));
@@ -878,10 +882,6 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     out->err_div = err_v;
     out->S_err_div = S_err_v;
     out->converged_div = err_v <= p->eta_divergence;
-    /* the divergence of the solve's final velocity feeds the learned warm start */
-    double *d_div = malloc(s1), *Sd_div = malloc(s1);
-    memcpy(d_div, d, s1);
-    memcpy(Sd_div, Sd, s1);
 
     /* -- 6. non-pressure accelerations (Algorithm 1, first two lines):
      *    gravity plus XSPH, Eq. (15), or the implicit solve of Eqs. (16)-(19). */
@@ -966,9 +966,10 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
      *    K0 = 0, warm_factor * K_prev, or the learned prediction
      *    max(0, y alpha rho0 / dt^2) of the step's final stiffness, y = MLP of
      *    five dimensionless features; the target is K_final dt^2 / (alpha rho0).
-     *    Features: (rho - rho0)/rho0, dt d/rho0 with d the divergence of the
-     *    divergence-free solve's final velocity (its last predict), (n_f +
-     *    n_b)/26, K_prev dt^2/(alpha rho0), alpha/alpha_ref. */
+     *    Features: (rho - rho0)/rho0, dt d/rho0 with d the density change
+     *    rate (Eq. 9, DFSPH form) of the step's input velocity, before any
+     *    pressure of this step, (n_f + n_b)/26, K_prev dt^2/(alpha rho0),
+     *    alpha/alpha_ref. */
     const double alpha_ref = 2.35376 * (2.0 * p->r) * (2.0 * p->r) / p->rho0;
     double *feat = NULL, *Sfeat = NULL;
     if (dfsph && (p->warm_start == 2 || out->features)) {
@@ -978,14 +979,14 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
             int64_t n_i = (w->ff.start[i + 1] - w->ff.start[i]) + (w->fb.start[i + 1] - w->fb.start[i]);
             double a = w->alpha[i];
             feat[5 * i + 0] = (w->rho[i] - p->rho0) / p->rho0;
-            feat[5 * i + 1] = dt * d_div[i] / p->rho0;
+            feat[5 * i + 1] = dt * d_in[i] / p->rho0;
             feat[5 * i + 2] = (double)n_i / 26.0;
             feat[5 * i + 3] = a > 0.0 ? (double)in->K[i] * dt * dt / (a * p->rho0) : 0.0;
             feat[5 * i + 4] = a / alpha_ref;
             {
                 double *S = Sfeat + 5 * i;
                 S[0] = (w->rho[i] + p->rho0) / p->rho0;
-                S[1] = dt * Sd_div[i] / p->rho0;
+                S[1] = dt * Sd_in[i] / p->rho0;
                 S[2] = 0.0;
                 S[3] = a > 0.0 ? fabs(feat[5 * i + 3]) * (1.0 + w->Salpha[i] / a) : 0.0;
                 S[4] = w->Salpha[i] / alpha_ref;
@@ -1228,7 +1229,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     free(feat);
     free(Sfeat);
     free(rs); free(Srs); free(vs); free(Svs);
-    free(d_div); free(Sd_div);
+    free(d_in); free(Sd_in);
     free(v_in); free(d); free(Sd); free(kap); free(Skap); free(Kv); free(SKv); free(K); free(SK);
     free(kappa_last); free(Skappa_last);
     free(w->x); free(w->v); free(w->Sv); free(w->xb); free(w->vb); free(w->psi);

@@ -127,7 +127,7 @@ struct sph_ctx {
     sph_mlp *mlp = nullptr;
     bool warm_fallback = false;
     float *feat = nullptr, *ybuf = nullptr;
-    float *dbuf = nullptr;   // divergence after the divergence-free solve (learned features)
+    float *dbuf = nullptr;   // density change rate of the step's input velocity (learned features)
     bool want_d = false;
     float *trace_feat = nullptr, *trace_target = nullptr;
     int64_t trace_cap = 0, trace_rows = 0;
@@ -454,7 +454,7 @@ int pressure_pass(sph_ctx *c, float *Kacc, float *klast, float dt, const int32_t
 
 // The predict pass and its finish (the timing record covers the pass only).
 int predict_pass(sph_ctx *c, int mode, float dt, bool first, const sph::SolveCtl &init) {
-    float *dout = (mode == 0 && c->want_d) ? c->dbuf : nullptr;
+    float *dout = nullptr;   // the learned start's divergence feature comes from the density pass
     int nparts = 0;
     {
         // x and v (plus rho in the density solve) in, kappa out
@@ -695,13 +695,19 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         dt = (float)c->P.dt_max;
     }
 
-    // 2. density, alpha, and (DFSPH) the divergence solve's warm start
+    // 2. density, alpha, and (DFSPH) the divergence solve's warm start; for
+    //    the learned start (and its trace) also the density change rate of
+    //    the input velocity, one of the network's features
     {
+        const bool din = dfsph && c->want_d;
         // x in; rho, alpha, the volume out; with the divergence warm start also v in and out
-        ProfScope ps(c, "density_alpha", 36.0 * nf + list_bytes(c) + (dfsph && warm ? 16.0 * nf : 0.0));
-        HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, c->nlist, c->ncnt, c->xb, c->blist, c->bcnt, c->kc,
-                                             c->rho, c->alpha, c->v_in, c->Kv, dt, dfsph ? wf : 0.0f,
-                                             c->pci_c, s));
+        ProfScope ps(c, "density_alpha",
+                     36.0 * nf + list_bytes(c) + (dfsph && warm ? 16.0 * nf : 0.0) + (din ? 20.0 * nf : 0.0));
+        HIP_TRY(c, sph::launch_density_alpha(nf, c->x, c->v, din ? c->v2 : c->v, c->nlist, c->ncnt, c->xb,
+                                             c->vb_moving ? c->vb : nullptr, c->blist, c->bcnt, c->kc, c->rho,
+                                             c->alpha, c->v_in, c->Kv, dt, dfsph ? wf : 0.0f, c->pci_c,
+                                             din ? c->dbuf : nullptr, s));
+        if (din) std::swap(c->v, c->v2);
     }
     if (rebuild) {
         HIP_TRY(c, hipEventSynchronize(c->build_done));
@@ -742,7 +748,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         if (learned && !tracing) {   // features, network and start in one pass
             ProfScope ps(c, "mlp", 36.0 * nf);
             HIP_TRY(c, sph::launch_mlp_warm_start(c->mlp->packed, nf, c->x, c->rho, c->alpha, c->K, c->kappa, c->ncnt,
-                                                  c->bcnt, c->dbuf, c->kc, dt, alpha_ref, s));
+                                                  c->bcnt, c->dbuf, c->kc, dt, alpha_ref, Ksave, s));
             return SPH_OK;
         }
         if (learned || tracing) {
@@ -794,13 +800,11 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
             if ((rc = nonpressure(press, nullptr, nullptr))) return rc;
             std::swap(c->v, c->v2);
         } else {
-            // The learned start reads the check's D rho/Dt, so with it the
-            // pass applies no pressure: the network and the start's pressure
-            // pass follow.  Otherwise the start is set up first (K kept) and
+            // The start (previous or learned) is set up first (K kept) and
             // the pass applies its pressure as well.
-            const bool fold_press = press && !learned;
+            const bool fold_press = press;
             if (fold_press && (rc = warm_setup(c->K_saved))) return rc;
-            const sph::DivCheck dc{c->vb_moving ? c->vb : nullptr, c->alpha, c->div_kvs, c->want_d ? c->dbuf : nullptr,
+            const sph::DivCheck dc{c->vb_moving ? c->vb : nullptr, c->alpha, c->div_kvs, nullptr,
                                    c->red_part};
             int nparts = 0;
             if ((rc = nonpressure(fold_press, &dc, &nparts))) return rc;
@@ -820,10 +824,6 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
                 iv = 0;
                 ev = h.err;
                 std::swap(c->v, c->v2);
-                if (learned) {
-                    if ((rc = warm_setup(nullptr))) return rc;
-                    if ((rc = pressure_pass(c, c->K, nullptr, dt, nullptr))) return rc;
-                }
             }
         }
     }

@@ -118,10 +118,12 @@ hipError_t launch_boundary_psi(float4* xb, int64_t nb, const uint32_t* start_b, 
 hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, HostStatus* host, hipStream_t s);
 // density, alpha; with warm_factor > 0 also the divergence warm start's
 // pressure from x.w (Kv_prev / rho_prev) and Kv = warm_factor x.w rho
-hipError_t launch_density_alpha(int64_t nf, float4* x, float4* v, const uint32_t* nlist,
-                                const uint32_t* ncnt, const float4* xb, const uint32_t* blist,
-                                const uint32_t* bcnt, Kern kc, float* rho, float* alpha, float4* v_in,
-                                float* Kv, float dt, float warm_factor, float pci_c, hipStream_t s);
+// din (nullable): also the density change rate of the input velocity v
+// (boundary velocities vb, nullable = at rest); then vout must differ from v.
+hipError_t launch_density_alpha(int64_t nf, float4* x, const float4* v, float4* vout, const uint32_t* nlist,
+                                const uint32_t* ncnt, const float4* xb, const float4* vb, const uint32_t* blist,
+                                const uint32_t* bcnt, Kern kc, float* rho, float* alpha, float4* v_in, float* Kv,
+                                float dt, float warm_factor, float pci_c, float* din, hipStream_t s);
 // go (nullable): the pass does nothing when *go == 0 (an iteration the
 // solve no longer needs).
 hipError_t launch_pressure_update(int64_t nf, const float4* x, float4* v, const float* kappa, float* Kacc,
@@ -220,7 +222,7 @@ hipError_t launch_cg_iteration(int64_t nf, float4* xv, float4* r, float4* u, flo
 
 // learned warm start: the features pass, the learned stiffness, trace targets
 // learned-warm-start features from per-particle fields (no neighbour pass):
-// (rho - rho0)/rho0, dt d/rho0 (d from the divergence solve's last predict),
+// (rho - rho0)/rho0, dt d/rho0 (d of the input velocity, from the density pass),
 // (n_f + n_b)/26, K_prev dt^2/(alpha rho0), alpha/alpha_ref; feat [nf][5]
 hipError_t launch_features(int64_t nf, const float* rho, const float* alpha, const float* K, const uint32_t* ncnt,
                            const uint32_t* bcnt, const float* d, Kern kc, float dt, float alpha_ref, float* feat,
@@ -242,7 +244,7 @@ hipError_t launch_mlp_forward(const uint32_t* packed, const float* feat, int64_t
 // launch_mlp_forward and launch_warm_learned in sequence)
 hipError_t launch_mlp_warm_start(const uint32_t* packed, int64_t n, float4* x, const float* rho, const float* alpha,
                                  float* K, float* kappa, const uint32_t* ncnt, const uint32_t* bcnt, const float* d,
-                                 Kern kc, float dt, float alpha_ref, hipStream_t s);
+                                 Kern kc, float dt, float alpha_ref, float* Ksave, hipStream_t s);
 hipError_t launch_mlp_grad(const float* P, const float* feat, const float* target, int64_t n, float* part,
                            double* loss_part, float* grad, double* loss_sum, hipStream_t s);
 hipError_t launch_mlp_adam(float* P, const float* grad, float* m, float* v, float lr, float beta1, float beta2,

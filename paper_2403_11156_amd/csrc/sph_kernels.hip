@@ -373,20 +373,26 @@ __global__ void k_max_v2(const float4* __restrict__ v, int64_t n, uint32_t* out_
 // stiffness over density, warm_factor Kv_prev / rho_prev (x.w, from the sort),
 // does not depend on this step's density, so its pressure (Eq. 7 with the
 // Eq. 13 boundary term) is applied here, and Kv starts at that times rho.
-template <int L, bool WARM>
+// DIN: the walk also sums the density change rate of the step's input
+// velocity (Eq. 9 in the DFSPH form, with the boundary velocities vb when
+// given) into din, a feature of the learned warm start; neighbours then read
+// v during the pass, so the updated velocities go to vout (a different
+// buffer), else vout == v.
+template <int L, bool WARM, bool DIN>
 __global__ void __launch_bounds__(kBlock) k_density_alpha(
-    int64_t nf, float4* __restrict__ x, float4* __restrict__ v, const uint32_t* __restrict__ nlist,
-    const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const uint32_t* __restrict__ blist,
-    const uint32_t* __restrict__ bcnt, Kern kc, float* __restrict__ rho, float* __restrict__ alpha,
-    float4* __restrict__ v_in, float* __restrict__ Kv, float dt, float warm_factor,
-    float pci_c) {
+    int64_t nf, float4* __restrict__ x, const float4* v, float4* vout, const uint32_t* __restrict__ nlist,
+    const uint32_t* __restrict__ ncnt, const float4* __restrict__ xb, const float4* __restrict__ vb,
+    const uint32_t* __restrict__ blist, const uint32_t* __restrict__ bcnt, Kern kc, float* __restrict__ rho,
+    float* __restrict__ alpha, float4* __restrict__ v_in, float* __restrict__ Kv, float dt, float warm_factor,
+    float pci_c, float* __restrict__ din) {
     int q;
     const int64_t i = group_particle<L>(q);
     if (i >= nf) return;   // whole groups leave together
     const float4 xi = x[i];
+    const float4 vi0 = DIN ? v[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float kri = WARM ? warm_factor * xi.w : 0.0f;   // x.w = Kv_prev / rho_prev (from the sort)
     float r = 0.f, gx = 0.f, gy = 0.f, gz = 0.f, sq = 0.f;
-    float px = 0.f, py = 0.f, pz = 0.f;
+    float px = 0.f, py = 0.f, pz = 0.f, dv = 0.f;
     for_each_nbr_l<L>(nlist, nf, i, q, ncnt[i], [&](uint32_t j) {
         const float4 xj = x[j];
         const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
@@ -401,9 +407,13 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
             const float c = (kri + warm_factor * xj.w) * g;
             px += c * dx; py += c * dy; pz += c * dz;
         }
+        if (DIN) {
+            const float4 vj = v[j];
+            dv += g * ((vi0.x - vj.x) * dx + (vi0.y - vj.y) * dy + (vi0.z - vj.z) * dz);
+        }
     });
     float rb = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
-    float pbx = 0.f, pby = 0.f, pbz = 0.f;
+    float pbx = 0.f, pby = 0.f, pbz = 0.f, dvb = 0.f;
     for_each_nbr_l<L>(blist, nf, i, q, bcnt[i], [&](uint32_t kk) {
         const float4 xk = xb[kk];
         const float dx = xi.x - xk.x, dy = xi.y - xk.y, dz = xi.z - xk.z;
@@ -415,6 +425,10 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
         if (WARM) {
             const float c = xk.w * kri * g;
             pbx += c * dx; pby += c * dy; pbz += c * dz;
+        }
+        if (DIN) {
+            const float4 vk = vb ? vb[kk] : make_float4(0.f, 0.f, 0.f, 0.f);
+            dvb += F * ((vi0.x - vk.x) * dx + (vi0.y - vk.y) * dy + (vi0.z - vk.z) * dz);
         }
     });
     // self term, fluid sum, boundary sum
@@ -428,7 +442,9 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
         py = group_sum<L>(py) * kc.m + group_sum<L>(pby);
         pz = group_sum<L>(pz) * kc.m + group_sum<L>(pbz);
     }
+    if (DIN) dv = group_sum<L>(dv) * kc.m + group_sum<L>(dvb);
     if (q != 0) return;
+    if (DIN) din[i] = dv;
     const float D = gx * gx + gy * gy + gz * gz + sq;
     rho[i] = rr;
     // PCISPH (pci_c > 0): the prototype factor c / rho replaces alpha
@@ -440,7 +456,7 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
     if (WARM) {
         vi.x -= dt * px; vi.y -= dt * py; vi.z -= dt * pz;
     }
-    v[i] = make_float4(vi.x, vi.y, vi.z, kc.m / rr);
+    vout[i] = make_float4(vi.x, vi.y, vi.z, kc.m / rr);
     Kv[i] = WARM ? kri * rr : 0.0f;
 }
 
@@ -690,8 +706,8 @@ __global__ void k_div_resume(int64_t nf, float4* __restrict__ x, float* __restri
 
 // Learned warm start, features of each particle at the start of the density
 // solve, from per-particle fields: (rho - rho0)/rho0, dt d/rho0 with d the
-// divergence after the divergence-free solve, (n_f + n_b)/26,
-// K_prev dt^2/(alpha rho0), alpha/alpha_ref.
+// density change rate of the step's input velocity (from the density pass),
+// (n_f + n_b)/26, K_prev dt^2/(alpha rho0), alpha/alpha_ref.
 __global__ void k_features(int64_t nf, const float* __restrict__ rho, const float* __restrict__ alpha,
                            const float* __restrict__ K, const uint32_t* __restrict__ ncnt,
                            const uint32_t* __restrict__ bcnt, const float* __restrict__ d, Kern kc, float dt,
@@ -1283,18 +1299,24 @@ hipError_t launch_max_v2(const float4* v, int64_t n, uint32_t* partials, HostSta
     return hipGetLastError();
 }
 
-hipError_t launch_density_alpha(int64_t nf, float4* x, float4* v, const uint32_t* nlist, const uint32_t* ncnt,
-                                const float4* xb, const uint32_t* blist, const uint32_t* bcnt, Kern kc, float* rho,
-                                float* alpha, float4* v_in, float* Kv, float dt, float warm_factor,
-                                float pci_c, hipStream_t s) {
+hipError_t launch_density_alpha(int64_t nf, float4* x, const float4* v, float4* vout, const uint32_t* nlist,
+                                const uint32_t* ncnt, const float4* xb, const float4* vb, const uint32_t* blist,
+                                const uint32_t* bcnt, Kern kc, float* rho, float* alpha, float4* v_in, float* Kv,
+                                float dt, float warm_factor, float pci_c, float* din, hipStream_t s) {
     if (nf <= 0) return hipSuccess;
+    if (din && vout == v) return hipErrorInvalidValue;   // neighbours read v while the pass writes
     const dim3 grid(grid_blocks(kLanesDensity * nf)), block(kBlock);
-    if (warm_factor > 0.0f)
-        hipLaunchKernelGGL((k_density_alpha<kLanesDensity, true>), grid, block, 0, s, nf, x, v, nlist, ncnt, xb, blist,
-                           bcnt, kc, rho, alpha, v_in, Kv, dt, warm_factor, pci_c);
-    else
-        hipLaunchKernelGGL((k_density_alpha<kLanesDensity, false>), grid, block, 0, s, nf, x, v, nlist, ncnt, xb,
-                           blist, bcnt, kc, rho, alpha, v_in, Kv, dt, warm_factor, pci_c);
+#define DENSITY_LAUNCH(W, D)                                                                                      \
+    hipLaunchKernelGGL((k_density_alpha<kLanesDensity, W, D>), grid, block, 0, s, nf, x, v, vout, nlist, ncnt, xb, \
+                       vb, blist, bcnt, kc, rho, alpha, v_in, Kv, dt, warm_factor, pci_c, din)
+    if (warm_factor > 0.0f) {
+        if (din) DENSITY_LAUNCH(true, true);
+        else DENSITY_LAUNCH(true, false);
+    } else {
+        if (din) DENSITY_LAUNCH(false, true);
+        else DENSITY_LAUNCH(false, false);
+    }
+#undef DENSITY_LAUNCH
     return hipGetLastError();
 }
 

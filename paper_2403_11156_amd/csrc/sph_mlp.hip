@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(256) k_mlp_warm_start(const uint32_t* __restri
                                                         const float* __restrict__ alpha, float* __restrict__ K,
                                                         float* __restrict__ kappa, const uint32_t* __restrict__ ncnt,
                                                         const uint32_t* __restrict__ bcnt, const float* __restrict__ d,
-                                                        Kern kc, float dt, float alpha_ref) {
+                                                        Kern kc, float dt, float alpha_ref, float* __restrict__ Ksave) {
     __shared__ InferConst W;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int q = threadIdx.x; q < kConstWords; q += blockDim.x)
@@ -403,6 +403,7 @@ __global__ void __launch_bounds__(256) k_mlp_warm_start(const uint32_t* __restri
         if (lane < 32 && i < n) {
             const float k0 = fmaxf(yv * alpha[i] * kc.rho0 / (dt * dt), 0.0f);
             kappa[i] = k0;
+            if (Ksave) Ksave[i] = K[i];
             K[i] = 0.0f;
             x[i].w = k0 / rho[i];
         }
@@ -599,13 +600,13 @@ hipError_t launch_mlp_pack(const float* P, uint32_t* packed, hipStream_t s) {
 
 hipError_t launch_mlp_warm_start(const uint32_t* packed, int64_t n, float4* x, const float* rho, const float* alpha,
                                  float* K, float* kappa, const uint32_t* ncnt, const uint32_t* bcnt, const float* d,
-                                 Kern kc, float dt, float alpha_ref, hipStream_t s) {
+                                 Kern kc, float dt, float alpha_ref, float* Ksave, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t tiles = (n + 31) / 32;
     int64_t blocks = (tiles + 3) / 4;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_mlp_warm_start, dim3((uint32_t)blocks), dim3(256), 0, s, packed, n, x, rho, alpha, K, kappa,
-                       ncnt, bcnt, d, kc, dt, alpha_ref);
+                       ncnt, bcnt, d, kc, dt, alpha_ref, Ksave);
     return hipGetLastError();
 }
 

@@ -147,6 +147,12 @@ def default_params(r: float, lo, hi, **kw) -> Dict:
         solver=SOLVER_DFSPH, wcsph_k=2.8e5, wcsph_gamma=7.0,
         # implicit viscosity: start the CG from v~ + 0.5 (v* - v~) of the previous step
         cg_warm_factor=0.5,
+        # the DFSPH factor at most ten times its bulk-lattice value, and the
+        # density solve also bounds the largest compression at 2%: without
+        # them the dam breaks at 125k to 1.23M particles break down within
+        # their configured lengths (a pair meeting at the support's edge, and
+        # pockets of compression the mean error over a million particles hides)
+        alpha_max_factor=10.0, eta_density_max=0.02,
     )
     p.update(kw)
     return p

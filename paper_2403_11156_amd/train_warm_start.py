@@ -106,11 +106,25 @@ def train(F, T, torch, sph, epochs=40, batch=65536, lr=2e-3, halve_every=10, see
                     "train_steps": step, "batch": batch, "epochs": epochs, "lr": lr, "halve_every": halve_every}
 
 
+def source_digest() -> str:
+    """SHA-256 prefix of the sources the traces depend on (the HIP library and
+    the scene generator), recorded with the weights."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "csrc")
+    for name in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    h.update(open(os.path.join(HERE, "scenes.py"), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--quick", action="store_true", help="c1 only, 2 epochs (smoke of the driver)")
     ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--commit", default=os.environ.get("TRACE_COMMIT", ""),
+                    help="the repository commit whose solver produced the traces (recorded)")
     args = ap.parse_args()
     import torch
     from paper_2403_11156_amd import scenes, sph
@@ -121,6 +135,12 @@ def main():
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     params.astype(np.float32).tofile(args.out)
     rec["runs"] = runs
+    rec["trace_windows"] = [f"{name}: steps 0..{steps - 1}, every {every}" for name, steps, every in runs]
+    rec["source_digest"] = source_digest()
+    rec["commit"] = args.commit
+    keys = ("warm_start", "warm_factor", "alpha_max_factor", "eta_density", "eta_density_max", "eta_divergence",
+            "cfl_lambda", "dt_max", "visc_model", "visc")
+    rec["solver_readings"] = {name: {k: scenes.scene(name).params.get(k) for k in keys} for name, _, _ in runs}
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps({"weights": args.out, **{k: rec[k] for k in ("samples", "train_steps")},

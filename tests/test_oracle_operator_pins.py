@@ -67,10 +67,11 @@ def setup_module(_):
 
 def _scene(xf, xb=None, vf=None, **kw):
     """A scene with the given fluid (and optional static boundary) in a unit
-    domain; no gravity, no viscosity, zero warm start, fixed dt unless kw
-    says otherwise."""
+    domain; no gravity, no viscosity, zero warm start, fixed dt, no cap on
+    the factor and no bound on the largest compression unless kw says
+    otherwise."""
     kw = dict(dict(gravity=(0.0, 0.0, 0.0), visc_model=scenes.VISC_NONE, warm_start=scenes.WARM_ZERO,
-                   cfl_lambda=0.0, dt_max=1e-4), **kw)
+                   cfl_lambda=0.0, dt_max=1e-4, alpha_max_factor=0.0, eta_density_max=0.0), **kw)
     sc = scenes.make_block_scene("pin", R, (0, 0, 0), (1, 1, 1), (1, 1, 1), (0.5, 0.5, 0.5), seed=1,
                                  steps=1, jitter=0.0, **kw)
     sc.x_fluid = np.ascontiguousarray(xf, np.float32)

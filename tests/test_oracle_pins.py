@@ -279,12 +279,15 @@ def test_stop_rule_holds_after_every_solve():
     for _ in range(6):
         out = O.step(st)
         p = st.params
+        emax = p["eta_density_max"]
         assert out["err_div"] <= p["eta_divergence"] or out["iters_div"] == p["max_iters"]
-        assert out["err_dens"] <= p["eta_density"] or out["iters_dens"] == p["max_iters"]
-        # Algorithm 2: no iteration once err <= eta, so every recorded
-        # pre-iteration error but the last one is above eta
-        hd = out["err_dens_hist"]
-        assert (hd[:-1] > p["eta_density"]).all()
+        assert (out["err_dens"] <= p["eta_density"] and out["err_dens_max"] <= emax) or \
+            out["iters_dens"] == p["max_iters"]
+        # Algorithm 2: no iteration once err <= eta (and, with the bound, the
+        # largest compression <= eta_density_max), so every recorded
+        # pre-iteration state but the last one is above one of them
+        hd, hm = out["err_dens_hist"], out["err_dens_max_hist"]
+        assert ((hd[:-1] > p["eta_density"]) | (hm[:-1] > emax)).all()
         hv = out["err_div_hist"]
         assert (hv[:-1] > p["eta_divergence"]).all()
         st = O.advance(st, out)
