@@ -200,14 +200,17 @@ def _random_quat(u1, u2, u3) -> tuple:
             a * math.cos(2 * math.pi * u2), b * math.sin(2 * math.pi * u3))
 
 
-def rigid_bodies_c3(r: float, seed: int) -> List[Dict]:
+def rigid_bodies_c3(r: float, seed: int, centres=None) -> List[Dict]:
     """Two boxes (0.2 m, 500 and 600 kg/m^3) and two spheres (R 0.15 m,
-    700 and 800 kg/m^3) at x = 1.75, centres jittered by +-0.01 m."""
+    700 and 800 kg/m^3) at x = 1.75 (or at the four given centres),
+    centres jittered by +-0.01 m."""
     s = 2.0 * r
     u = uniform01(seed, 16, offset=10_000_000)
     out = []
-    specs = [("box", 0.2, 500.0, (1.75, 0.5, 0.25)), ("box", 0.2, 600.0, (1.75, 0.5, 0.75)),
-             ("sphere", 0.15, 700.0, (1.75, 0.8, 0.25)), ("sphere", 0.15, 800.0, (1.75, 0.8, 0.75))]
+    if centres is None:
+        centres = [(1.75, 0.5, 0.25), (1.75, 0.5, 0.75), (1.75, 0.8, 0.25), (1.75, 0.8, 0.75)]
+    specs = [("box", 0.2, 500.0, centres[0]), ("box", 0.2, 600.0, centres[1]),
+             ("sphere", 0.15, 700.0, centres[2]), ("sphere", 0.15, 800.0, centres[3])]
     for bi, (kind, size, dens, c) in enumerate(specs):
         com = tuple(c[a] + (2.0 * u[4 * bi + a] - 1.0) * 0.01 for a in range(3))
         if kind == "box":
@@ -224,8 +227,23 @@ def rigid_bodies_c3(r: float, seed: int) -> List[Dict]:
             inertia = (0.4 * mass * size * size,) * 3
             uu = uniform01(seed, 3, offset=20_000_000 + 3 * bi)
             quat = _random_quat(*uu)
-        out.append(dict(local_points=pts, mass=mass, inertia=inertia, com=com, quat=quat))
+        out.append(dict(local_points=pts, mass=mass, inertia=inertia, com=com, quat=quat, kind=kind, size=size))
     return out
+
+
+def carve(x: np.ndarray, bodies: List[Dict], gap: float) -> np.ndarray:
+    """The fluid points that lie at least `gap` outside every body (boxes:
+    in the body frame, |q_a| >= size/2 + gap on some axis; spheres:
+    distance >= R + gap from the centre)."""
+    keep = np.ones(len(x), bool)
+    for b in bodies:
+        d = x.astype(np.float64) - np.asarray(b["com"], np.float64)
+        if b["kind"] == "box":
+            q = d @ quat_to_matrix(b["quat"])   # R^T d, row-wise
+            keep &= (np.abs(q) >= 0.5 * b["size"] + gap).any(axis=1)
+        else:
+            keep &= np.linalg.norm(d, axis=1) >= b["size"] + gap
+    return x[keep]
 
 
 def scene(name: str) -> Scene:
@@ -243,6 +261,18 @@ def scene(name: str) -> Scene:
         return make_block_scene("c3 rigid coupling 1.23M", 0.005, (0, 0, 0), (2.0, 1.0, 1.0),
                                 (150, 82, 100), (0.005, 0.175, 0.005), seed=3, steps=500,
                                 bodies=rigid_bodies_c3(0.005, 3))
+    if name == "c3i":
+        # c3 with the four bodies inside the block (boxes low, spheres above
+        # them), the fluid carved away within 1.1 s of their surfaces, as the
+        # tank walls stand 1.1 s from the fluid: the coupling under load
+        r = 0.005
+        bodies = rigid_bodies_c3(r, 3, centres=[(0.45, 0.45, 0.3), (0.45, 0.45, 0.7), (1.05, 0.6, 0.3),
+                                                (1.05, 0.6, 0.7)])
+        sc = make_block_scene("c3 rigid coupling 1.23M, bodies immersed", r, (0, 0, 0), (2.0, 1.0, 1.0),
+                              (150, 82, 100), (0.005, 0.175, 0.005), seed=3, steps=500, bodies=bodies)
+        sc.x_fluid = np.ascontiguousarray(carve(sc.x_fluid, bodies, 2.2 * r))
+        sc.v_fluid = np.zeros_like(sc.x_fluid)
+        return sc
     if name == "c4":
         return make_block_scene("c4 viscous column 250k", 0.008, (0, 0, 0), (3.2, 2.0, 0.8),
                                 (50, 100, 50), (0.008, 0.008, 0.008), seed=4, steps=500,

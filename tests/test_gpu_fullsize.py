@@ -1,17 +1,24 @@
-"""Parity at the benchmark's full sizes (1.23 M fluid particles), in the
-launch configuration bench.py times: the whole neighbour structure bit-exact
-and one complete step within the field tolerance, against the FP64 oracle
-(grid search; about 25 s of oracle time per step)."""
+"""Parity at the benchmark's full sizes (1.23 M fluid particles; 250 k for
+the viscous column), in the launch configuration bench.py times: the whole
+neighbour structure bit-exact and one complete step within the field
+tolerance, against the FP64 oracle (grid search, on all host cores: the
+OpenMP build computes the same bits as one thread)."""
+
+import os
 
 import numpy as np
 import pytest
 
+from oracle import mlp as M
 from oracle import oracle as O
 from paper_2403_11156_amd import scenes
 
-from tests.parity import compare_step, ratio
+from tests.parity import compare_step, oracle_state_from_gpu, ratio
 
 pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2403_11156_amd",
+                       "weights", "warm_start_mlp.f32")
 
 
 @pytest.fixture(scope="module")
@@ -20,10 +27,13 @@ def sph():
     assert torch.cuda.is_available()
     from paper_2403_11156_amd import sph as mod
     O.build(force=False)
-    return mod
+    O.build(force=False, openmp=True)
+    O.use_openmp(True)
+    yield mod
+    O.use_openmp(False)
 
 
-@pytest.mark.parametrize("name", ["c5", "c3", "c5w", "c5p"])
+@pytest.mark.parametrize("name", ["c5", "c3", "c3i", "c5w", "c5p"])
 def test_full_size_step(sph, name):
     sc = scenes.scene(name)
     print(f"[fullsize] {sc.name}: nf={sc.n_fluid} nb={sc.n_boundary} bodies={len(sc.rigid)}", flush=True)
@@ -51,4 +61,63 @@ def test_full_size_step(sph, name):
     if sc.rigid:
         assert ratio(g["force"], ref["force"], ref["S_force"]) <= 1.0
         assert ratio(g["torque"], ref["torque"], ref["S_torque"]) <= 1.0
+        if name == "c3i":   # the bodies sit in the fluid: every one is pushed
+            print("[fullsize] c3i force", g["force"].tolist(), flush=True)
+            assert (np.abs(ref["force"]).max(axis=1) > 1.0).all()
+    sim.close()
+
+
+def test_full_size_learned_step(sph):
+    # the trained warm start at 1.23 M: the step re-anchored after a plain
+    # first step (so K_prev is not zero), against the oracle with the
+    # bf16-emulating network
+    sc = scenes.scene("c5")
+    p = np.fromfile(WEIGHTS, dtype=np.float32)
+    sim = sph.Simulation(sc)
+    net = sph.MLP(p)
+    local = O.rigid_local(sc.x_boundary, sc.body_of_boundary, sc.rigid)
+    sim.build_neighbors()
+    sim.step()
+    sim.build_neighbors()
+    state = oracle_state_from_gpu(sim, sc, local)
+    sim.set_warm_start(2, net)
+    st = sim.step()
+    assert st["warm_fallback"] == 0
+    g = sim.read()
+    ref = O.step(state, forced_div=st["iters_div"], forced_dens=st["iters_dens"], brute=False,
+                 params=dict(state.params, warm_start=2), mlp=M.step_callback(p))
+    r = compare_step(g, ref, st)
+    print("[fullsize] c5 learned", st["iters_div"], st["iters_dens"], {k: f"{v:.3g}" for k, v in r.items()},
+          flush=True)
+    for k, v in r.items():
+        assert v <= 1.0, (k, v)
+    sim.close()
+    net.close()
+
+
+def test_full_size_implicit_viscosity(sph):
+    # the 250k viscous column (Eqs. 16-19): neighbour structure bit-exact,
+    # density within the field tolerance, and with the pressure solves off the
+    # step's velocity is the CG solution: its FP64 residual in the oracle is
+    # within twice the tolerance
+    sc = scenes.scene("c4")
+    sc.v_fluid[:] = np.random.default_rng(8).normal(0, 0.2, sc.v_fluid.shape).astype(np.float32)
+    sim = sph.Simulation(sc)
+    sim.set_forced_iters(0, 0)
+    sim.build_neighbors()
+    g_nbr = sim.read_neighbors()
+    ref_nbr = O.sorted_neighbor_structure(sc.params, sc.x_fluid, sc.x_boundary, brute=False)
+    np.testing.assert_array_equal(g_nbr["perm_f"], ref_nbr["perm_f"])
+    np.testing.assert_array_equal(g_nbr["counts_f"], ref_nbr["nf"][0])
+    np.testing.assert_array_equal(g_nbr["lists_f"], ref_nbr["nf"][1])
+    st = sim.step()
+    g = sim.read(("v", "rho"))
+    rho_ref, _, _ = O.density_alpha(sc.params, sc.x_fluid, sc.x_boundary)
+    assert ratio(g["rho"], rho_ref) <= 1.0
+    dt = st["dt"]
+    b = sc.v_fluid.astype(np.float64) + dt * np.array(sc.params["gravity"])
+    res = O.visc_residual(sc.params, sc.x_fluid, g["rho"].astype(np.float64), dt, b, g["v"].astype(np.float64))
+    print("[fullsize] c4 cg iterations", st["cg_iters"], "device residual", st["cg_resid"], "oracle residual", res,
+          flush=True)
+    assert st["cg_iters"] > 0 and res <= 2 * sc.params["cg_tol"]
     sim.close()
