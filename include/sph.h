@@ -137,6 +137,17 @@ typedef struct sph_mlp sph_mlp;
  *                   exceeds it (the mean of eta_density alone lets a few
  *                   hundred particles of a million stay compressed by 10%
  *                   where a wave hits a wall).  0: the mean only.
+ *   rigid_coupling  0 (weak, Sec. 3.5): the bodies keep their velocity during
+ *                   the fluid solve and take the step's total reaction
+ *                   (Eq. 14) afterwards.  1 (strong, the interlinked
+ *                   coupling of the paper's outlook, Sec. 6): every pressure
+ *                   pass of both solves (warm starts included) advances the
+ *                   bodies' velocities by its own reaction at once (FP64 on
+ *                   the device), so the next pass sees their new boundary
+ *                   velocities; gravity and the gyroscopic term reach the
+ *                   bodies between the two solves; the pose moves at the
+ *                   step's end.  The reported force and torque are the
+ *                   step's summed reaction either way.
  */
 typedef struct sph_params {
     double r, h, rho0;
@@ -159,6 +170,7 @@ typedef struct sph_params {
     int32_t separate_div_check;
     double alpha_max_factor;
     double eta_density_max;
+    int32_t rigid_coupling;
 } sph_params;
 
 /* A rigid body (Sec. 3.5): mass, principal moments of inertia (body frame,

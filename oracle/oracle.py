@@ -54,6 +54,7 @@ class Params(C.Structure):
         ("cg_warm_factor", C.c_double),
         ("alpha_max_factor", C.c_double),
         ("eta_density_max", C.c_double),
+        ("rigid_coupling", C.c_int32),
     ]
 
 
@@ -184,6 +185,7 @@ def make_params(pd: Dict, forced_div: int = -1, forced_dens: int = -1, n_rigid: 
     p.cg_warm_factor = pd.get("cg_warm_factor", 0.0)
     p.alpha_max_factor = pd.get("alpha_max_factor", 0.0)
     p.eta_density_max = pd.get("eta_density_max", 0.0)
+    p.rigid_coupling = pd.get("rigid_coupling", 0)
     return p
 
 

@@ -64,6 +64,8 @@ typedef struct or_params {
     double cg_warm_factor;        /* implicit-viscosity CG start: x0 = b + cg_warm_factor dvisc_prev */
     double alpha_max_factor;      /* DFSPH factor capped at alpha_max_factor * alpha_ref (0: no cap) */
     double eta_density_max;       /* > 0: the density solve also bounds the largest compression */
+    int32_t rigid_coupling;       /* 0 weak (bodies move after the fluid solve), 1 strong (every
+                                     pressure pass moves them, reading R24) */
 } or_params;
 
 typedef struct or_rigid {
@@ -455,6 +457,14 @@ typedef struct world {
     double *xb, *vb, *psi;         /* boundary */
     csr ff, fb;
     double *rho, *alpha, *Salpha;
+    /* strong coupling: the bodies' velocities during the step, their world
+     * inverse inertia, and the reactions summed over the step's passes */
+    int32_t nr, strong;
+    const int32_t *body;           /* [nb] body of each boundary particle, -1 static */
+    const float *xb32;             /* [nb][3] boundary positions as stored (FP32) */
+    or_rigid *bs;                  /* [nr] state during the step */
+    double *Iwinv, *Iw;            /* [nr][9] */
+    double *F, *T, *SF, *ST;       /* [nr][3] */
 } world;
 
 #define FOR_F(i, e) for (int64_t e = w->ff.start[i]; e < w->ff.start[(i) + 1]; ++e)
@@ -601,8 +611,80 @@ static void pressure_update_den(const world *w, const double *kappa, const doubl
     free(dv); free(Sdv);
 }
 
+/* Boundary velocities of the bodies' particles from the bodies' state:
+ * v_k = fl32(V + w x (x_k - c)) with x_k the stored FP32 position. */
+static void body_boundary_velocities(world *w) {
+    for (int64_t k = 0; k < w->nb; ++k) {
+        const int32_t b = w->body[k];
+        if (b < 0) continue;
+        const or_rigid *s = &w->bs[b];
+        double r[3], wx[3];
+        for (int a = 0; a < 3; ++a) r[a] = (double)w->xb32[3 * k + a] - s->com[a];
+        wx[0] = s->omega[1] * r[2] - s->omega[2] * r[1];
+        wx[1] = s->omega[2] * r[0] - s->omega[0] * r[2];
+        wx[2] = s->omega[0] * r[1] - s->omega[1] * r[0];
+        for (int a = 0; a < 3; ++a) w->vb[3 * k + a] = (double)(float)(s->vel[a] + wx[a]);
+    }
+}
+
+/* Strong coupling (reading R24): the reaction of one pressure pass on each
+ * body, Eq. (14) with the pass's stiffness over density,
+ *   F_b = sum_i sum_{k in b} m Psi_k (kappa_i / den_i) gradW_ik,
+ *   tau_b = sum (x_k - c_b) x F_ik,
+ * applied to the body at once (V += dt F/M, w += dt I_w^-1 tau), summed into
+ * the step's reaction, and the body's boundary velocities refreshed for the
+ * next pass. */
+static void couple_pass(world *w, const double *kappa, const double *Skappa, const double *den) {
+    if (!w->strong || w->nr == 0) return;
+    double *F = calloc((size_t)(6 * w->nr), sizeof(double)), *SF = calloc((size_t)(6 * w->nr), sizeof(double));
+    for (int64_t i = 0; i < w->nf; ++i) {
+        FOR_B(i, e) {
+            const int64_t k = w->fb.idx[e];
+            const int32_t b = w->body[k];
+            if (b < 0) continue;
+            double x[3], gw[3], sg[3], f[3], r[3], t[3];
+            xij_b(w, i, k, x);
+            or_gradW(x, w->h, gw);
+            gradW_scale(x, w->h, sg);
+            const double c = w->m * w->psi[k] * kappa[i] / den[i];
+            const double Sc = w->m * w->psi[k] * (Skappa[i] + fabs(kappa[i])) / den[i];
+            for (int a = 0; a < 3; ++a) {
+                f[a] = c * gw[a];
+                r[a] = w->xb[3 * k + a] - w->bs[b].com[a];
+            }
+            t[0] = r[1] * f[2] - r[2] * f[1];
+            t[1] = r[2] * f[0] - r[0] * f[2];
+            t[2] = r[0] * f[1] - r[1] * f[0];
+            for (int a = 0; a < 3; ++a) {
+                F[6 * b + a] += f[a];
+                F[6 * b + 3 + a] += t[a];
+                SF[6 * b + a] += Sc * sg[a];
+            }
+            SF[6 * b + 3] += fabs(r[1]) * Sc * sg[2] + fabs(r[2]) * Sc * sg[1];
+            SF[6 * b + 4] += fabs(r[2]) * Sc * sg[0] + fabs(r[0]) * Sc * sg[2];
+            SF[6 * b + 5] += fabs(r[0]) * Sc * sg[1] + fabs(r[1]) * Sc * sg[0];
+        }
+    }
+    for (int32_t b = 0; b < w->nr; ++b) {
+        or_rigid *s = &w->bs[b];
+        const double *Iv = w->Iwinv + 9 * b, *tq = F + 6 * b + 3;
+        for (int a = 0; a < 3; ++a) {
+            s->vel[a] += w->dt * F[6 * b + a] / s->mass;
+            s->omega[a] += w->dt * (Iv[3 * a] * tq[0] + Iv[3 * a + 1] * tq[1] + Iv[3 * a + 2] * tq[2]);
+            w->F[3 * b + a] += F[6 * b + a];
+            w->T[3 * b + a] += F[6 * b + 3 + a];
+            w->SF[3 * b + a] += SF[6 * b + a];
+            w->ST[3 * b + a] += SF[6 * b + 3 + a];
+        }
+    }
+    body_boundary_velocities(w);
+    free(F);
+    free(SF);
+}
+
 static void pressure_update(const world *w, const double *kappa, const double *Skappa, double *v, double *Sv) {
     pressure_update_den(w, kappa, Skappa, w->rho, v, Sv);
+    couple_pass((world *)w, kappa, Skappa, w->rho);
 }
 
 /* largest clamped (compression-only) deviation */
@@ -809,6 +891,30 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     /* -- 3. Psi, Eq. (11) */
     boundary_psi(p, w->xb, nb, &bb, w->psi);
 
+    /* bodies during the step (strong coupling, R24): their velocities change
+     * with every pressure pass; the pose (and so the world inertia) stays */
+    w->nr = p->n_rigid;
+    w->strong = p->rigid_coupling == 1 && p->n_rigid > 0;
+    w->body = in->body;
+    w->xb32 = in->xb;
+    const size_t snr = (size_t)(p->n_rigid > 0 ? p->n_rigid : 1);
+    w->bs = malloc(sizeof(or_rigid) * snr);
+    w->Iw = calloc(9 * snr, sizeof(double));
+    w->Iwinv = calloc(9 * snr, sizeof(double));
+    w->F = calloc(3 * snr, sizeof(double)); w->T = calloc(3 * snr, sizeof(double));
+    w->SF = calloc(3 * snr, sizeof(double)); w->ST = calloc(3 * snr, sizeof(double));
+    for (int32_t b = 0; b < p->n_rigid; ++b) {
+        w->bs[b] = in->rigid[b];
+        double R[9];
+        quat_to_R(in->rigid[b].quat, R);
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c)
+                for (int q = 0; q < 3; ++q) {
+                    w->Iw[9 * b + 3 * a + c] += R[3 * a + q] * in->rigid[b].inertia[q] * R[3 * c + q];
+                    w->Iwinv[9 * b + 3 * a + c] += R[3 * a + q] / in->rigid[b].inertia[q] * R[3 * c + q];
+                }
+    }
+
     /* -- 4. density (Eq. 12) and alpha */
     w->rho = malloc(s1); w->alpha = malloc(s1); w->Salpha = malloc(s1);
     density_alpha(w);
@@ -847,7 +953,10 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
             Kv[i] = p->warm_start == 0 ? 0.0 : p->warm_factor * (double)in->Kv[i];
             SKv[i] = fabs(Kv[i]);
         }
-        if (p->warm_start != 0) pressure_update_den(w, Kv, SKv, rp, w->v, w->Sv);
+        if (p->warm_start != 0) {
+            pressure_update_den(w, Kv, SKv, rp, w->v, w->Sv);
+            couple_pass(w, Kv, SKv, rp);
+        }
         for (int64_t i = 0; i < nf; ++i) {
             Kv[i] = Kv[i] / rp[i] * w->rho[i];
             SKv[i] = fabs(Kv[i]);
@@ -882,6 +991,23 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     out->err_div = err_v;
     out->S_err_div = S_err_v;
     out->converged_div = err_v <= p->eta_divergence;
+
+    /* the bodies' own non-pressure accelerations (strong coupling): gravity
+     * and the gyroscopic term, between the two solves as for the fluid */
+    if (w->strong) {
+        for (int32_t b = 0; b < p->n_rigid; ++b) {
+            or_rigid *s = &w->bs[b];
+            const double *Iw = w->Iw + 9 * b, *Iv = w->Iwinv + 9 * b;
+            double L[3], gy[3];
+            for (int a = 0; a < 3; ++a) L[a] = Iw[3 * a] * s->omega[0] + Iw[3 * a + 1] * s->omega[1] + Iw[3 * a + 2] * s->omega[2];
+            cross(s->omega, L, gy);
+            for (int a = 0; a < 3; ++a) {
+                s->vel[a] += dt * p->gravity[a];
+                s->omega[a] -= dt * (Iv[3 * a] * gy[0] + Iv[3 * a + 1] * gy[1] + Iv[3 * a + 2] * gy[2]);
+            }
+        }
+        body_boundary_velocities(w);
+    }
 
     /* -- 6. non-pressure accelerations (Algorithm 1, first two lines):
      *    gravity plus XSPH, Eq. (15), or the implicit solve of Eqs. (16)-(19). */
@@ -1096,7 +1222,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
             out->force[3 * b + a] = 0.0; out->torque[3 * b + a] = 0.0;
             if (out->S_force) { out->S_force[3 * b + a] = 0.0; out->S_torque[3 * b + a] = 0.0; }
         }
-    for (int64_t i = 0; i < nf; ++i) {
+    for (int64_t i = 0; i < nf && !w->strong; ++i) {
         FOR_B(i, e) {
             int64_t k = w->fb.idx[e];
             int32_t b = in->body[k];
@@ -1122,6 +1248,17 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
             }
         }
     }
+
+    if (w->strong)   /* the reactions were summed pass by pass */
+        for (int32_t b = 0; b < p->n_rigid; ++b)
+            for (int a = 0; a < 3; ++a) {
+                out->force[3 * b + a] = w->F[3 * b + a];
+                out->torque[3 * b + a] = w->T[3 * b + a];
+                if (out->S_force) {
+                    out->S_force[3 * b + a] = w->SF[3 * b + a];
+                    out->S_torque[3 * b + a] = w->ST[3 * b + a];
+                }
+            }
 
     /* -- 10. symplectic Euler (Algorithm 1, last two lines): v = v*, x += dt v */
     for (int64_t i = 0; i < nf; ++i) {
@@ -1168,13 +1305,19 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
                 }
             }
         (void)tmp;
-        for (int a = 0; a < 3; ++a) s.vel[a] += dt * (out->force[3 * b + a] / s.mass + gr[a]);
-        double Lw[3], gyro[3], rhs[3];
-        for (int a = 0; a < 3; ++a) Lw[a] = Iw[3 * a] * s.omega[0] + Iw[3 * a + 1] * s.omega[1] + Iw[3 * a + 2] * s.omega[2];
-        cross(s.omega, Lw, gyro);
-        for (int a = 0; a < 3; ++a) rhs[a] = out->torque[3 * b + a] - gyro[a];
-        for (int a = 0; a < 3; ++a)
-            s.omega[a] += dt * (Iwinv[3 * a] * rhs[0] + Iwinv[3 * a + 1] * rhs[1] + Iwinv[3 * a + 2] * rhs[2]);
+        if (w->strong) {
+            /* the velocities were advanced by every pressure pass, gravity
+             * and the gyroscopic term during the step */
+            for (int a = 0; a < 3; ++a) { s.vel[a] = w->bs[b].vel[a]; s.omega[a] = w->bs[b].omega[a]; }
+        } else {
+            for (int a = 0; a < 3; ++a) s.vel[a] += dt * (out->force[3 * b + a] / s.mass + gr[a]);
+            double Lw[3], gyro[3], rhs[3];
+            for (int a = 0; a < 3; ++a) Lw[a] = Iw[3 * a] * s.omega[0] + Iw[3 * a + 1] * s.omega[1] + Iw[3 * a + 2] * s.omega[2];
+            cross(s.omega, Lw, gyro);
+            for (int a = 0; a < 3; ++a) rhs[a] = out->torque[3 * b + a] - gyro[a];
+            for (int a = 0; a < 3; ++a)
+                s.omega[a] += dt * (Iwinv[3 * a] * rhs[0] + Iwinv[3 * a + 1] * rhs[1] + Iwinv[3 * a + 2] * rhs[2]);
+        }
         for (int a = 0; a < 3; ++a) s.com[a] += dt * s.vel[a];
         {
             double qw = s.quat[0], qx = s.quat[1], qy = s.quat[2], qz = s.quat[3];
@@ -1234,6 +1377,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     free(kappa_last); free(Skappa_last);
     free(w->x); free(w->v); free(w->Sv); free(w->xb); free(w->vb); free(w->psi);
     free(w->rho); free(w->alpha); free(w->Salpha);
+    free(w->bs); free(w->Iw); free(w->Iwinv); free(w->F); free(w->T); free(w->SF); free(w->ST);
     csr_free(&w->ff); csr_free(&w->fb); csr_free(&bb);
     free(perm_f); free(start_f); free(xs_f); free(perm_b); free(start_b); free(xs_b);
     return 0;

@@ -78,6 +78,9 @@ struct sph_ctx {
     uint32_t *bkey = nullptr, *bslot = nullptr, *bsrc = nullptr, *start_b = nullptr;
     double *blocal = nullptr;   // [nb][3] body-frame offsets, original order
     BodyPose *poses = nullptr;
+    sph::BodyDyn *dyn = nullptr;   // strong coupling: mass and world inertia per body for the step
+    double *ft = nullptr;          // strong coupling: the step's summed reaction, then one pass's [2][6 kMaxBodies]
+    bool strong = false;           // strong (interlinked) rigid-fluid coupling
     double *com_dev = nullptr;
     // reductions and flags
     double *red_part = nullptr, *scal = nullptr;
@@ -283,7 +286,9 @@ int upload_poses(sph_ctx *c) {
 // Newton-Euler in FP64 with the world inertia R diag(I) R^T, then the
 // tank-contact stand-in: push the body back inside [min + r, max - r] along
 // each axis and drop the velocity component into the wall.
-void rigid_integrate(sph_ctx *c, double dt) {
+// advance_velocity false (strong coupling): the velocities were advanced
+// during the step, only the pose moves.
+void rigid_integrate(sph_ctx *c, double dt, bool advance_velocity) {
     const double *gr = c->P.gravity;
     for (int b = 0; b < c->nr; ++b) {
         sph_rigid_desc s = c->rigid[b];
@@ -298,13 +303,16 @@ void rigid_integrate(sph_ctx *c, double dt) {
                     Iwinv[3 * a + q] += R[3 * a + k] / s.inertia[k] * R[3 * q + k];
                 }
             }
-        for (int a = 0; a < 3; ++a) s.vel[a] += dt * (c->force[3 * b + a] / s.mass + gr[a]);
-        double Lw[3], gyro[3], rhs[3];
-        for (int a = 0; a < 3; ++a) Lw[a] = Iw[3 * a] * s.omega[0] + Iw[3 * a + 1] * s.omega[1] + Iw[3 * a + 2] * s.omega[2];
-        cross3(s.omega, Lw, gyro);
-        for (int a = 0; a < 3; ++a) rhs[a] = c->torque[3 * b + a] - gyro[a];
-        for (int a = 0; a < 3; ++a)
-            s.omega[a] += dt * (Iwinv[3 * a] * rhs[0] + Iwinv[3 * a + 1] * rhs[1] + Iwinv[3 * a + 2] * rhs[2]);
+        if (advance_velocity) {
+            for (int a = 0; a < 3; ++a) s.vel[a] += dt * (c->force[3 * b + a] / s.mass + gr[a]);
+            double Lw[3], gyro[3], rhs[3];
+            for (int a = 0; a < 3; ++a)
+                Lw[a] = Iw[3 * a] * s.omega[0] + Iw[3 * a + 1] * s.omega[1] + Iw[3 * a + 2] * s.omega[2];
+            cross3(s.omega, Lw, gyro);
+            for (int a = 0; a < 3; ++a) rhs[a] = c->torque[3 * b + a] - gyro[a];
+            for (int a = 0; a < 3; ++a)
+                s.omega[a] += dt * (Iwinv[3 * a] * rhs[0] + Iwinv[3 * a + 1] * rhs[1] + Iwinv[3 * a + 2] * rhs[2]);
+        }
         for (int a = 0; a < 3; ++a) s.com[a] += dt * s.vel[a];
         {
             double qw = s.quat[0], qx = s.quat[1], qy = s.quat[2], qz = s.quat[3];
@@ -452,6 +460,17 @@ int pressure_pass(sph_ctx *c, float *Kacc, float *klast, float dt, const int32_t
     return SPH_OK;
 }
 
+// Strong coupling: the reaction of the pressure pass just queued (kappa/rho =
+// scale x.w) moves the bodies at once and refreshes their boundary
+// velocities (go: the solve's control block, or null).
+int couple_pass(sph_ctx *c, float dt, float scale, const int32_t *go) {
+    if (!c->strong) return SPH_OK;
+    HIP_TRY(c, sph::launch_rigid_couple(c->nf, c->x, c->blist, c->bcnt, c->xb, c->vb, c->bid, c->blocal, c->kc, c->nr,
+                                        c->com_dev, c->nb, c->red_part, scale, dt, go, c->dyn, c->poses, c->ft,
+                                        c->hs_dev, c->stream));
+    return SPH_OK;
+}
+
 // The predict pass and its finish (the timing record covers the pass only).
 int predict_pass(sph_ctx *c, int mode, float dt, bool first, const sph::SolveCtl &init) {
     float *dout = nullptr;   // the learned start's divergence feature comes from the density pass
@@ -506,6 +525,7 @@ int jacobi_iterate(sph_ctx *c, int mode, float dt, float *Kacc, float *klast, co
         for (int32_t k = 0; k < batch; ++k) {
             int rc = pressure_pass(c, Kacc, klast, dt, &c->ctl->go);
             if (rc) return rc;
+            if ((rc = couple_pass(c, dt, 1.0f, &c->ctl->go))) return rc;
             rc = predict_pass(c, mode, dt, false, init);
             if (rc) return rc;
         }
@@ -670,6 +690,31 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     const bool learned = dfsph && c->warm_mode == SPH_WARM_LEARNED && c->mlp != nullptr;
     const bool tracing = dfsph && c->trace_feat != nullptr && c->trace_rows + nf <= c->trace_cap;
     c->want_d = learned || tracing;
+    // strong coupling: the bodies' mass and world inertia for this step (the
+    // pose stays until the step's end), the summed reaction cleared
+    c->strong = c->P.rigid_coupling == 1 && c->nr > 0;
+    if (c->strong) {
+        std::vector<sph::BodyDyn> dyn(c->nr);
+        for (int b = 0; b < c->nr; ++b) {
+            const sph_rigid_desc &r = c->rigid[b];
+            double R[9];
+            quat_to_R(r.quat, R);
+            dyn[b].mass = r.mass;
+            for (int a = 0; a < 3; ++a)
+                for (int q = 0; q < 3; ++q) {
+                    dyn[b].Iw[3 * a + q] = 0.0;
+                    dyn[b].Iwinv[3 * a + q] = 0.0;
+                    for (int k = 0; k < 3; ++k) {
+                        dyn[b].Iw[3 * a + q] += R[3 * a + k] * r.inertia[k] * R[3 * q + k];
+                        dyn[b].Iwinv[3 * a + q] += R[3 * a + k] / r.inertia[k] * R[3 * q + k];
+                    }
+                }
+        }
+        HIP_TRY(c, hipMemcpyAsync(c->dyn, dyn.data(), sizeof(sph::BodyDyn) * c->nr, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, sph::launch_fill_u32(reinterpret_cast<uint32_t *>(c->ft), 2 * 6 * sph::kMaxBodies, 0u, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));   // the host copy of dyn is released below
+        std::memset(c->hs->rigid, 0, sizeof(c->hs->rigid));
+    }
 
     // 1. time step (fixed, or CFL from the step's input velocities)
     float dt;
@@ -709,6 +754,11 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
                                              din ? c->dbuf : nullptr, s));
         if (din) std::swap(c->v, c->v2);
     }
+    // the divergence warm start's pressure (applied in the density pass) moves the bodies
+    if (dfsph && warm) {
+        int rc = couple_pass(c, dt, wf, nullptr);
+        if (rc) return rc;
+    }
     if (rebuild) {
         HIP_TRY(c, hipEventSynchronize(c->build_done));
         int rc = build_check(c);   // a capacity error leaves clamped, in-bounds lists behind
@@ -722,8 +772,8 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     //    pass is queued again.  A flow whose solve alternates between none
     //    and one iteration keeps the check separate.
     const bool implicit = c->P.visc_model == SPH_VISC_IMPLICIT;
-    const bool fold = dfsph && !implicit && !tracing && !c->P.separate_div_check && c->forced_div < 0 &&
-                      c->div_calm >= 2;
+    const bool fold = dfsph && !implicit && !tracing && !c->strong && !c->P.separate_div_check &&
+                      c->forced_div < 0 && c->div_calm >= 2;
     int32_t iv = 0, id = 0;
     double ev = 0.0, ed = 0.0;
     int rc = SPH_OK;
@@ -731,6 +781,11 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         rc = jacobi_solve(c, 0, dt, c->Kv, nullptr, c->forced_div, c->P.eta_divergence, &iv, &ev);
         if (rc) return rc;
     }
+    // strong coupling: the bodies' gravity and gyroscopic term, between the
+    // solves as the fluid's non-pressure accelerations
+    if (c->strong)
+        HIP_TRY(c, sph::launch_rigid_gravity(c->nr, c->nb, c->xb, c->vb, c->bid, c->blocal, c->dyn, c->poses,
+                                             c->P.gravity[0], c->P.gravity[1], c->P.gravity[2], dt, s));
 
     // 4. non-pressure accelerations and the density warm start (or WCSPH's
     //    equation of state).  The warm start's stiffness is set up first: the
@@ -776,9 +831,11 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
         if (rc) return rc;
         if (ppe && (rc = warm_setup(nullptr))) return rc;
         if (ppe && warm && (rc = pressure_pass(c, c->K, nullptr, dt, nullptr))) return rc;
+        if (ppe && warm && (rc = couple_pass(c, dt, 1.0f, nullptr))) return rc;
         if (wcsph) {
             if ((rc = wcsph_eos(c))) return rc;
             if ((rc = pressure_pass(c, c->K, c->kappa_last, dt, nullptr))) return rc;
+            if ((rc = couple_pass(c, dt, 1.0f, nullptr))) return rc;
         }
     } else {
         // the ZERO start only clears K and kappa, inside the pass
@@ -799,6 +856,7 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
             if (wcsph && (rc = wcsph_eos(c))) return rc;
             if ((rc = nonpressure(press, nullptr, nullptr))) return rc;
             std::swap(c->v, c->v2);
+            if (press && (rc = couple_pass(c, dt, 1.0f, nullptr))) return rc;
         } else {
             // The start (previous or learned) is set up first (K kept) and
             // the pass applies its pressure as well.
@@ -857,17 +915,27 @@ int step_impl(sph_ctx *c, sph_step_stats *st) {
     }
     // 7. rigid bodies: Eq. 14 reaction, FP64 Newton-Euler, new boundary pose
     if (c->nr > 0) {
-        HIP_TRY(c, sph::launch_rigid_force(nf, c->x, c->rho, c->K, c->Kv, c->blist, c->bcnt, c->xb, c->vb, c->kc,
-                                           c->nr, c->com_dev, c->red_part, c->hs_dev, s));
+        // weak coupling: the step's total reaction now; strong: summed pass
+        // by pass, the velocities already advanced on the device
+        if (!c->strong)
+            HIP_TRY(c, sph::launch_rigid_force(nf, c->x, c->rho, c->K, c->Kv, c->blist, c->bcnt, c->xb, c->vb, c->kc,
+                                               c->nr, c->com_dev, c->red_part, c->hs_dev, s));
         std::vector<double> fo(6 * c->nr);
+        std::vector<sph::BodyPose> pz(c->strong ? c->nr : 0);
+        if (c->strong)
+            HIP_TRY(c, hipMemcpyAsync(pz.data(), c->poses, sizeof(sph::BodyPose) * c->nr, hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
         std::memcpy(fo.data(), c->hs->rigid, sizeof(double) * 6 * c->nr);
         for (int b = 0; b < c->nr; ++b)
             for (int a = 0; a < 3; ++a) {
                 c->force[3 * b + a] = fo[6 * b + a];
                 c->torque[3 * b + a] = fo[6 * b + 3 + a];
+                if (c->strong) {
+                    c->rigid[b].vel[a] = pz[b].vel[a];
+                    c->rigid[b].omega[a] = pz[b].omega[a];
+                }
             }
-        rigid_integrate(c, (double)dt);
+        rigid_integrate(c, (double)dt, !c->strong);
         rc = upload_poses(c);
         if (rc) return rc;
         HIP_TRY(c, sph::launch_rigid_boundary(c->nb, c->xb, c->vb, c->bid, c->blocal, c->poses, s));
@@ -990,6 +1058,8 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
         return fail(nullptr, SPH_ERR_INVALID, "invalid parameter value");
     if (!(p->cg_warm_factor >= 0.0 && p->cg_warm_factor <= 4.0))
         return fail(nullptr, SPH_ERR_INVALID, "cg_warm_factor outside [0, 4]");
+    if (p->rigid_coupling != 0 && p->rigid_coupling != 1)
+        return fail(nullptr, SPH_ERR_INVALID, "rigid_coupling must be 0 (weak) or 1 (strong)");
     if (!(p->eta_density_max >= 0.0))
         return fail(nullptr, SPH_ERR_INVALID, "eta_density_max must be >= 0");
     if (!(p->alpha_max_factor >= 0.0 && p->alpha_max_factor <= 1e6))
@@ -1085,6 +1155,7 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     ALLOC(c->xb, nb); ALLOC(c->xb2, nb); ALLOC(c->vb, nb); ALLOC(c->vb2, nb); ALLOC(c->bid, nb); ALLOC(c->bid2, nb);
     ALLOC(c->bkey, nb); ALLOC(c->bslot, nb); ALLOC(c->bsrc, nb); ALLOC(c->blocal, 3 * nb);
     ALLOC(c->poses, std::max(1, c->nr)); ALLOC(c->com_dev, 3 * std::max(1, c->nr));
+    ALLOC(c->dyn, std::max(1, c->nr)); ALLOC(c->ft, 12 * sph::kMaxBodies);
     ALLOC(c->red_part, nred * 6 * std::max(1, c->nr) + 16); ALLOC(c->scal, 16);
     ALLOC(c->ctl, 1); ALLOC(c->cgc, 2);
     ALLOC(c->flags, 4);

@@ -82,6 +82,14 @@ struct BodyPose {
     double omega[3];
 };
 
+// A body's mass and world inertia during a step of the strong coupling
+// (the pose, and so the inertia, stays fixed until the step's end).
+struct BodyDyn {
+    double mass;
+    double Iw[9];
+    double Iwinv[9];
+};
+
 // ---------------------------------------------------------------- launchers
 // Every launcher queues on `s` and returns hipGetLastError().  Reductions
 // store one partial per workgroup in `partials` (reduction_blocks(n) entries
@@ -182,6 +190,21 @@ hipError_t launch_warm_setup(int64_t nf, float4* x, const float* rho, float* K, 
 // gate (nullable): both kernels do nothing while *gate != 0
 hipError_t launch_integrate(int64_t nf, float4* x, const float4* v, float dt, uint32_t* partials, HostStatus* host,
                             const int32_t* gate, hipStream_t s);
+// Strong coupling (one pressure pass): the reaction of the pass on every body
+// from each fluid particle's kappa/rho = xw_scale * x.w (Eq. 14), summed into
+// ft (force and torque per body) and the step's totals, the bodies'
+// velocities advanced by it (FP64, in poses), and their boundary velocities
+// refreshed.  Nothing happens when go (nullable) reads 0.
+hipError_t launch_rigid_couple(int64_t nf, const float4* x, const uint32_t* blist, const uint32_t* bcnt,
+                               float4* xb, float4* vb, const int32_t* bid, const double* local, Kern kc,
+                               int32_t nbody, const double* com, int64_t nb, double* partials, float xw_scale,
+                               float dt, const int32_t* go, const BodyDyn* dyn, BodyPose* poses, double* ft_total,
+                               HostStatus* host, hipStream_t s);
+// The bodies' own accelerations in the strong coupling: V += dt g and the
+// gyroscopic term w += dt Iw^-1 (-(w x Iw w)), then their boundary velocities.
+hipError_t launch_rigid_gravity(int32_t nbody, int64_t nb, float4* xb, float4* vb, const int32_t* bid,
+                                const double* local, const BodyDyn* dyn, BodyPose* poses, double gx, double gy,
+                                double gz, float dt, hipStream_t s);
 hipError_t launch_rigid_force(int64_t nf, const float4* x, const float* rho, const float* K, const float* Kv,
                               const uint32_t* blist, const uint32_t* bcnt, const float4* xb, const float4* vb,
                               Kern kc, int32_t nbody, const double* com, double* partials, HostStatus* host,

@@ -787,11 +787,15 @@ __global__ void k_integrate(int64_t nf, float4* __restrict__ x, const float4* __
 // Reaction on the rigid bodies (Eq. 14) from the step's total stiffness
 // K + Kv: F_ik = m Psi_k ((K_i + Kv_i) / rho_i) gradW_ik, torque (x_k - c_b) x F.
 // Pair terms in FP32, accumulation in FP64, fixed order.
+// xw_scale > 0: the stiffness of one pressure pass, kappa/rho = xw_scale x.w
+// (strong coupling), instead of the step's total (K + Kv)/rho; go (nullable):
+// nothing happens when it reads 0.
 __global__ void __launch_bounds__(kBlock) k_rigid_force(
     int64_t nf, const float4* __restrict__ x, const float* __restrict__ rho, const float* __restrict__ K,
     const float* __restrict__ Kv, const uint32_t* __restrict__ blist, const uint32_t* __restrict__ bcnt,
     const float4* __restrict__ xb, const float4* __restrict__ vb, Kern kc, int32_t nbody,
-    const double* __restrict__ com, double* __restrict__ partials) {
+    const double* __restrict__ com, double* __restrict__ partials, float xw_scale, const int32_t* __restrict__ go) {
+    if (go != nullptr && *go == 0) return;
     const int64_t i = particle_index();
     uint32_t nbk = 0;
     float4 xi = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -801,7 +805,7 @@ __global__ void __launch_bounds__(kBlock) k_rigid_force(
         nbk = bcnt[i];
         if (nbk) {
             xi = x[i];
-            base = kc.m * (K[i] + Kv[i]) / rho[i];
+            base = xw_scale > 0.0f ? kc.m * (xw_scale * xi.w) : kc.m * (K[i] + Kv[i]) / rho[i];
         }
         for (uint32_t k = 0; k < nbk; ++k) {
             const int32_t b = (int32_t)vb[blist[list_index(nf, i, k)]].w;
@@ -856,8 +860,9 @@ __global__ void __launch_bounds__(kBlock) k_rigid_force(
 // v_k = fl32(V + w x (x_k - c)), FP64 with no contraction.
 __global__ void k_rigid_boundary(int64_t nb, float4* __restrict__ xb, float4* __restrict__ vb,
                                  const int32_t* __restrict__ bid, const double* __restrict__ local,
-                                 const BodyPose* __restrict__ poses) {
+                                 const BodyPose* __restrict__ poses, const int32_t* __restrict__ go) {
 #pragma clang fp contract(off)
+    if (go != nullptr && *go == 0) return;
     const int64_t i = particle_index();
     if (i >= nb) return;
     float4 vk = vb[i];
@@ -1445,7 +1450,7 @@ hipError_t launch_rigid_force(int64_t nf, const float4* x, const float* rho, con
                               hipStream_t s) {
     const uint32_t nblk = grid_blocks(nf);
     hipLaunchKernelGGL(k_rigid_force, dim3(nblk), dim3(kBlock), 0, s, nf, x, rho, K, Kv, blist, bcnt, xb, vb, kc,
-                       nbody, com, partials);
+                       nbody, com, partials, 0.0f, nullptr);
     hipLaunchKernelGGL(k_finish_rigid, dim3(6 * nbody), dim3(kBlock), 0, s, partials, (int)nblk, host);
     return hipGetLastError();
 }
@@ -1453,7 +1458,91 @@ hipError_t launch_rigid_force(int64_t nf, const float4* x, const float* rho, con
 hipError_t launch_rigid_boundary(int64_t nb, float4* xb, float4* vb, const int32_t* bid, const double* local,
                                  const BodyPose* poses, hipStream_t s) {
     if (nb <= 0) return hipSuccess;
-    LAUNCH(k_rigid_boundary, nb, nb, xb, vb, bid, local, poses);
+    LAUNCH(k_rigid_boundary, nb, nb, xb, vb, bid, local, poses, nullptr);
+}
+
+// Strong coupling: the pass's reaction per body (fixed-order sums of the
+// workgroup partials, one workgroup per output), then one thread per body
+// advances its velocity and the step's totals.
+__global__ void k_rigid_pass_finish(const double* __restrict__ partials, int nblk, double* __restrict__ ft,
+                                    const int32_t* __restrict__ go) {
+    if (go != nullptr && *go == 0) return;
+    const int o = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partials[(size_t)o * nblk + b];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) ft[o] = acc;
+}
+
+__global__ void k_rigid_pass_update(int32_t nbody, const double* __restrict__ ft, const BodyDyn* __restrict__ dyn,
+                                    BodyPose* __restrict__ poses, double* __restrict__ total, float dt,
+                                    const int32_t* __restrict__ go, HostStatus* host) {
+#pragma clang fp contract(off)
+    if (go != nullptr && *go == 0) return;
+    const int b = threadIdx.x;
+    if (b >= nbody) return;
+    const double* F = ft + 6 * b;
+    const BodyDyn& D = dyn[b];
+    BodyPose& P = poses[b];
+    const double h = (double)dt;
+    for (int a = 0; a < 3; ++a) {
+        P.vel[a] += h * F[a] / D.mass;
+        P.omega[a] += h * (D.Iwinv[3 * a] * F[3] + D.Iwinv[3 * a + 1] * F[4] + D.Iwinv[3 * a + 2] * F[5]);
+    }
+    for (int a = 0; a < 6; ++a) {
+        total[6 * b + a] += F[a];
+        host->rigid[6 * b + a] = total[6 * b + a];
+    }
+}
+
+__global__ void k_rigid_gravity(int32_t nbody, const BodyDyn* __restrict__ dyn, BodyPose* __restrict__ poses,
+                                double gx, double gy, double gz, float dt) {
+#pragma clang fp contract(off)
+    const int b = threadIdx.x;
+    if (b >= nbody) return;
+    const BodyDyn& D = dyn[b];
+    BodyPose& P = poses[b];
+    const double h = (double)dt, g[3] = {gx, gy, gz};
+    double L[3], gy3[3];
+    for (int a = 0; a < 3; ++a) L[a] = D.Iw[3 * a] * P.omega[0] + D.Iw[3 * a + 1] * P.omega[1] + D.Iw[3 * a + 2] * P.omega[2];
+    gy3[0] = P.omega[1] * L[2] - P.omega[2] * L[1];
+    gy3[1] = P.omega[2] * L[0] - P.omega[0] * L[2];
+    gy3[2] = P.omega[0] * L[1] - P.omega[1] * L[0];
+    double dw[3];
+    for (int a = 0; a < 3; ++a) dw[a] = D.Iwinv[3 * a] * gy3[0] + D.Iwinv[3 * a + 1] * gy3[1] + D.Iwinv[3 * a + 2] * gy3[2];
+    for (int a = 0; a < 3; ++a) {
+        P.vel[a] += h * g[a];
+        P.omega[a] -= h * dw[a];
+    }
+}
+
+hipError_t launch_rigid_couple(int64_t nf, const float4* x, const uint32_t* blist, const uint32_t* bcnt,
+                               float4* xb, float4* vb, const int32_t* bid, const double* local, Kern kc,
+                               int32_t nbody, const double* com, int64_t nb, double* partials, float xw_scale,
+                               float dt, const int32_t* go, const BodyDyn* dyn, BodyPose* poses, double* ft_total,
+                               HostStatus* host, hipStream_t s) {
+    if (nbody <= 0) return hipSuccess;
+    const uint32_t nblk = grid_blocks(nf);
+    double* ft = ft_total + 6 * kMaxBodies;   // this pass's reaction, after the totals
+    hipLaunchKernelGGL(k_rigid_force, dim3(nblk), dim3(kBlock), 0, s, nf, x, nullptr, nullptr, nullptr, blist, bcnt,
+                       xb, vb, kc, nbody, com, partials, xw_scale, go);
+    hipLaunchKernelGGL(k_rigid_pass_finish, dim3(6 * nbody), dim3(kBlock), 0, s, partials, (int)nblk, ft, go);
+    hipLaunchKernelGGL(k_rigid_pass_update, dim3(1), dim3(64), 0, s, nbody, ft, dyn, poses, ft_total, dt, go, host);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_rigid_boundary, dim3(grid_blocks(nb)), dim3(kBlock), 0, s, nb, xb, vb, bid, local,
+                           poses, go);
+    return hipGetLastError();
+}
+
+hipError_t launch_rigid_gravity(int32_t nbody, int64_t nb, float4* xb, float4* vb, const int32_t* bid,
+                                const double* local, const BodyDyn* dyn, BodyPose* poses, double gx, double gy,
+                                double gz, float dt, hipStream_t s) {
+    if (nbody <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rigid_gravity, dim3(1), dim3(64), 0, s, nbody, dyn, poses, gx, gy, gz, dt);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_rigid_boundary, dim3(grid_blocks(nb)), dim3(kBlock), 0, s, nb, xb, vb, bid, local,
+                           poses, nullptr);
+    return hipGetLastError();
 }
 
 hipError_t launch_visc_precond(int64_t nf, const float4* x, const float* rho, const uint32_t* nlist,

@@ -325,5 +325,6 @@ def small_bodies(r: float, seed: int, centres) -> List[Dict]:
         pts = shell((7, 7, 7), (-size / 2,) * 3, s)
         mass = 500.0 * size ** 3
         out.append(dict(local_points=pts, mass=mass, inertia=(mass * size * size / 6.0,) * 3,
-                        com=tuple(c), quat=_random_quat(u[4 * bi], u[4 * bi + 1], u[4 * bi + 2])))
+                        com=tuple(c), quat=_random_quat(u[4 * bi], u[4 * bi + 1], u[4 * bi + 2]), kind="box",
+                        size=size))
     return out

@@ -43,6 +43,7 @@ class sph_params(C.Structure):
         ("separate_div_check", C.c_int32),
         ("alpha_max_factor", C.c_double),
         ("eta_density_max", C.c_double),
+        ("rigid_coupling", C.c_int32),
     ]
 
 
@@ -217,6 +218,7 @@ def make_params(pd: Dict) -> sph_params:
     p.separate_div_check = pd.get("separate_div_check", 0)
     p.alpha_max_factor = pd.get("alpha_max_factor", 0.0)
     p.eta_density_max = pd.get("eta_density_max", 0.0)
+    p.rigid_coupling = pd.get("rigid_coupling", 0)
     return p
 
 

@@ -1,0 +1,102 @@
+"""Strong (interlinked) rigid-fluid coupling on the device against the oracle:
+every pressure pass moves the bodies at once (reading R24)."""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2403_11156_amd import scenes
+
+from tests.parity import compare_step, oracle_state_from_gpu, ratio
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sph():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2403_11156_amd import sph as mod
+    O.build(force=False)
+    return mod
+
+
+def _scene(mass_scale=1.0, **kw):
+    # a light box (250 kg/m^3 by default) half immersed in a resting block,
+    # driven into the fluid at 0.5 m/s
+    r = 0.01
+    bodies = scenes.small_bodies(r, 4, [(0.2, 0.14, 0.2)])
+    for b in bodies:
+        b["mass"] *= 0.5 * mass_scale
+        b["inertia"] = tuple(0.5 * mass_scale * i for i in b["inertia"])
+    sc = scenes.make_block_scene("strong coupling", r, (0, 0, 0), (0.4, 0.4, 0.4), (18, 9, 18), (0.02, 0.01, 0.02),
+                                 seed=13, steps=4, bodies=bodies, rigid_coupling=1, **kw)
+    sc.x_fluid = np.ascontiguousarray(scenes.carve(sc.x_fluid, bodies, 2.2 * r))
+    sc.v_fluid = np.random.default_rng(14).normal(0, 0.2, sc.x_fluid.shape).astype(np.float32)
+    sc.rigid[0] = dict(sc.rigid[0], vel=(0.0, -0.5, 0.0))
+    return sc
+
+
+def _compare_bodies(g, ref):
+    assert ratio(g["force"], ref["force"], ref["S_force"]) <= 1.0
+    assert ratio(g["torque"], ref["torque"], ref["S_torque"]) <= 1.0
+    for a, b in zip(g["rigid"], ref["rigid_new"]):
+        # the velocity is the pass-by-pass sum of reactions: FP64 on both
+        # sides, from FP32 fields, so the force tolerance carries over
+        dv = np.asarray(a["vel"]) - np.asarray(b["vel"])
+        assert np.abs(dv).max() <= 1e-5 * (np.abs(np.asarray(b["vel"])).max() + 1e-3), (a["vel"], b["vel"])
+        np.testing.assert_allclose(a["com"], b["com"], rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("warm", [0, 1])
+def test_strong_coupling_single_step(sph, warm):
+    # three passes in each solve, so that every later pass sees the body
+    # moved by the earlier ones
+    sc = _scene(warm_start=warm)
+    print(f"[strong] nf={sc.n_fluid} nb={sc.n_boundary} warm={warm}", flush=True)
+    sim = sph.Simulation(sc)
+    local = O.rigid_local(sc.x_boundary, sc.body_of_boundary, sc.rigid)
+    sim.set_forced_iters(3, 3)
+    sim.build_neighbors()
+    state = oracle_state_from_gpu(sim, sc, local)   # the body's boundary velocities as the device holds them
+    st = sim.step()
+    g = sim.read()
+    ref = O.step(state, forced_div=3, forced_dens=3)
+    r = compare_step(g, ref, st)
+    print("[strong] step", {k: f"{v:.3g}" for k, v in r.items()}, "force", g["force"].tolist(), flush=True)
+    for k, v in r.items():
+        assert v <= 1.0, (k, v)
+    assert np.abs(ref["force"]).max() > 1.0
+    _compare_bodies(g, ref)
+    sim.close()
+
+
+def test_strong_coupling_reanchored_steps_and_differs_from_weak(sph):
+    sc = _scene()
+    local = O.rigid_local(sc.x_boundary, sc.body_of_boundary, sc.rigid)
+    sim = sph.Simulation(sc)
+    worst = {}
+    for k in range(4):
+        sim.build_neighbors()
+        state = oracle_state_from_gpu(sim, sc, local)
+        st = sim.step()
+        g = sim.read()
+        ref = O.step(state, forced_div=st["iters_div"], forced_dens=st["iters_dens"])
+        for f, v in compare_step(g, ref, st).items():
+            worst[f] = max(worst.get(f, 0.0), v)
+        _compare_bodies(g, ref)
+    print("[strong] re-anchored worst", worst, flush=True)
+    for f, v in worst.items():
+        assert v <= 1.0, (f, v)
+    sim.close()
+    # the weak coupling from the same state gives a different reaction
+    runs = {}
+    for coupling in (0, 1):
+        s2 = sph.Simulation(sc, params=dict(sc.params, rigid_coupling=coupling))
+        s2.set_forced_iters(3, 3)
+        s2.build_neighbors()
+        s2.step()
+        runs[coupling] = s2.read(("rigid", "v"))
+        s2.close()
+    print("[strong] weak vs strong force", runs[0]["force"].tolist(), runs[1]["force"].tolist(), flush=True)
+    assert np.abs(runs[0]["force"] - runs[1]["force"]).max() > 1e-2 * np.abs(runs[0]["force"]).max()

@@ -33,9 +33,11 @@ def sph():
     O.use_openmp(False)
 
 
-@pytest.mark.parametrize("name", ["c5", "c3", "c3i", "c5w", "c5p"])
+@pytest.mark.parametrize("name", ["c5", "c3", "c3i", "c3i_strong", "c5w", "c5p"])
 def test_full_size_step(sph, name):
-    sc = scenes.scene(name)
+    sc = scenes.scene(name.replace("_strong", ""))
+    if name.endswith("_strong"):   # the bodies move with every pressure pass (strong coupling)
+        sc.params = dict(sc.params, rigid_coupling=1)
     print(f"[fullsize] {sc.name}: nf={sc.n_fluid} nb={sc.n_boundary} bodies={len(sc.rigid)}", flush=True)
     sim = sph.Simulation(sc)
     sim.build_neighbors()
@@ -61,9 +63,38 @@ def test_full_size_step(sph, name):
     if sc.rigid:
         assert ratio(g["force"], ref["force"], ref["S_force"]) <= 1.0
         assert ratio(g["torque"], ref["torque"], ref["S_torque"]) <= 1.0
-        if name == "c3i":   # the bodies sit in the fluid: every one is pushed
+        if name.startswith("c3i"):   # the bodies sit in the fluid: every one is pushed
             print("[fullsize] c3i force", g["force"].tolist(), flush=True)
-            assert (np.abs(ref["force"]).max(axis=1) > 1.0).all()
+            assert (np.abs(ref["force"]).max(axis=1) > 1e-5).all()
+    sim.close()
+
+
+@pytest.mark.parametrize("coupling", [0, 1])
+def test_full_size_bodies_under_load(sph, coupling):
+    # c3i after the falling block and its bodies have hit the floor (200
+    # steps on the device, past t = 0.19 s): a step re-anchored on the
+    # device's state, bodies pushed by newtons of fluid pressure
+    sc = scenes.scene("c3i")
+    sc.params = dict(sc.params, rigid_coupling=coupling)
+    local = O.rigid_local(sc.x_boundary, sc.body_of_boundary, sc.rigid)
+    sim = sph.Simulation(sc, params=dict(sc.params, auto_rebuild=1))
+    t = 0.0
+    for _ in range(200):
+        t += sim.advance()["dt"]
+    print(f"[fullsize] c3i coupling {coupling}: t = {t:.4f} s after 200 steps", flush=True)
+    sim.build_neighbors()
+    state = oracle_state_from_gpu(sim, sc, local)
+    st = sim.step()
+    g = sim.read()
+    ref = O.step(state, forced_div=st["iters_div"], forced_dens=st["iters_dens"], brute=False)
+    r = compare_step(g, ref, st)
+    print(f"[fullsize] c3i loaded, coupling {coupling}:", st["iters_div"], st["iters_dens"],
+          {k: f"{v:.3g}" for k, v in r.items()}, "force", g["force"].tolist(), flush=True)
+    for k, v in r.items():
+        assert v <= 1.0, (k, v)
+    assert ratio(g["force"], ref["force"], ref["S_force"]) <= 1.0
+    assert ratio(g["torque"], ref["torque"], ref["S_torque"]) <= 1.0
+    assert (np.abs(ref["force"]).max(axis=1) > 1.0).all()
     sim.close()
 
 
