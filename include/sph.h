@@ -131,7 +131,9 @@ typedef struct sph_mlp sph_mlp;
  *                   neighbours sit at the edge of the support otherwise gets
  *                   an unbounded factor, and the stiffness it accumulates is
  *                   carried into the next step.  0: no cap.  alpha = 0 when
- *                   D_i = 0.  [0, 1e6].
+ *                   D_i <= 1e-12 of a bulk particle's D (a vanishing
+ *                   gradient, e.g. a neighbour within rounding of the
+ *                   support's edge).  [0, 1e6].
  *   eta_density_max > 0: the density solve also iterates while the largest
  *                   predicted compression max_i max(rho*_i - rho0, 0) / rho0
  *                   exceeds it (the mean of eta_density alone lets a few

@@ -479,7 +479,8 @@ static void xij_b(const world *w, int64_t i, int64_t k, double d[3]) {
 
 /* Eq. (12) density, and the DFSPH factor alpha (reading: alpha = rho / D,
  * D = |sum_F m gradW + sum_B Psi gradW|^2 + sum_F |m gradW|^2, alpha = 0 when
- * D = 0 (no neighbour gradient), and alpha capped at alpha_max_factor times
+ * D <= 1e-12 of a bulk particle's D (no neighbour gradient), and alpha capped
+ * at alpha_max_factor times
  * the bulk-lattice factor alpha_ref = 2.35376 (2r)^2 / rho0: a particle that
  * sees a few neighbours at the edge of the support has a vanishing gradient
  * and an unbounded factor, and the stiffness it accumulates would be carried
@@ -489,9 +490,31 @@ static double alpha_cap(const or_params *p) {
     return p->alpha_max_factor > 0.0 ? p->alpha_max_factor * 2.35376 * s * s / p->rho0 : 0.0;
 }
 
+/* D of a bulk lattice point: sum over its neighbours (spacing 2r, inside the
+ * support) of |m gradW|^2 (the gradient sum itself vanishes by symmetry) */
+static double bulk_D(const or_params *p) {
+    const double s = 2.0 * p->r, h = p->h, m = p->rho0 * s * s * s;
+    const int n = (int)ceil(h / s);
+    double sum = 0.0;
+    for (int a = -n; a <= n; ++a)
+        for (int b = -n; b <= n; ++b)
+            for (int c = -n; c <= n; ++c) {
+                const double d = s * sqrt((double)(a * a + b * b + c * c));
+                if (d == 0.0 || d >= h) continue;
+                const double g = m * or_dWdr(d, h);
+                sum += g * g;
+            }
+    return sum;
+}
+
 static void density_alpha(world *w) {
     const double m = w->m, h = w->h;
     const double amax = alpha_cap(w->p);
+    /* no factor below 1e-12 of the bulk D: a neighbour sitting within
+     * rounding of the support's edge gives a vanishing gradient, zero in
+     * FP32 where FP64 still sees ~1e-30 of the bulk, so both precisions
+     * decide alike (the bulk is ~1e9 in SI units) */
+    const double Dmin = 1e-12 * bulk_D(w->p);
     #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < w->nf; ++i) {
         double rho = m * w->k0, g[3] = {0, 0, 0}, Sg[3] = {0, 0, 0}, sq = 0.0;
@@ -517,7 +540,7 @@ static void density_alpha(world *w) {
         double D = g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + sq;
         double SD = Sg[0] * Sg[0] + Sg[1] * Sg[1] + Sg[2] * Sg[2] + sq;
         w->rho[i] = rho;
-        if (D > 0.0) {
+        if (D > Dmin) {
             /* the cap is 1-Lipschitz, so the uncapped scale still bounds the error */
             w->alpha[i] = rho / D;
             w->Salpha[i] = rho / D + rho * SD / (D * D);

@@ -1128,6 +1128,21 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     c->kc.alpha_max = p->alpha_max_factor > 0.0
                           ? (float)(p->alpha_max_factor * 2.35376 * 4.0 * p->r * p->r / p->rho0)
                           : 0.0f;
+    {   // 1e-12 of a bulk lattice particle's sum of |m gradW|^2 (the gradient sum vanishes there)
+        const double s = 2.0 * p->r, m = p->rho0 * s * s * s, k6 = 48.0 / (M_PI * p->h * p->h * p->h * p->h);
+        const int reach = (int)std::ceil(p->h / s);
+        double dsum = 0.0;
+        for (int a = -reach; a <= reach; ++a)
+            for (int b = -reach; b <= reach; ++b)
+                for (int e = -reach; e <= reach; ++e) {
+                    const double q = s * std::sqrt((double)(a * a + b * b + e * e)) / p->h;
+                    if (q == 0.0 || q >= 1.0) continue;
+                    const double fp = q <= 0.5 ? q * (3.0 * q - 2.0) : -(1.0 - q) * (1.0 - q);   // f'(q) / 6
+                    const double g = m * k6 * fp;
+                    dsum += g * g;
+                }
+        c->kc.d_min = (float)(1e-12 * dsum);
+    }
     if (p->solver == SPH_SOLVER_PCISPH) c->pci_c = (float)pcisph_factor(*p);
 
     const int64_t nf = c->nf, nb = c->nb;

@@ -26,6 +26,7 @@ struct Kern {
     float m;         // fluid particle mass rho0 (2r)^3
     float rho0;
     float alpha_max;  // cap of the DFSPH factor alpha (0: none)
+    float d_min;      // alpha = 0 unless its denominator exceeds this (1e-12 of a bulk particle's)
 };
 
 // neighbour statistics: [min, max, sum, sum_fluid]

@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(kBlock) k_density_alpha(
     const float D = gx * gx + gy * gy + gz * gz + sq;
     rho[i] = rr;
     // PCISPH (pci_c > 0): the prototype factor c / rho replaces alpha
-    float a = D > 0.0f ? rr / D : 0.0f;
+    float a = D > kc.d_min ? rr / D : 0.0f;
     if (kc.alpha_max > 0.0f) a = fminf(a, kc.alpha_max);
     alpha[i] = pci_c > 0.0f ? pci_c / rr : a;
     float4 vi = v[i];

@@ -359,6 +359,15 @@ def test_alpha_cap_on_a_lone_pair_near_the_support_edge():
     # an isolated particle has no gradient at all: alpha = 0, cap or not
     _, a_iso, _ = O.density_alpha(dict(pd, alpha_max_factor=4.0), xf[:1], np.zeros((0, 3), np.float32))
     assert a_iso[0] == 0.0
+    # a pair 1 - 2^-18 of the support apart: D = 2 (m k f'/h)^2 ~ 1e-21 of a
+    # bulk particle's, below the 1e-12 cut-off, so alpha = 0 (not the cap)
+    edge = np.array([[0.5, 0.5, 0.5], [0.5 + (1 - 2.0 ** -18) * H, 0.5, 0.5]], np.float32)
+    qe = (float(edge[1, 0]) - 0.5) / H
+    assert 1 - 2.0 ** -17 < qe < 1.0
+    d_ratio = 2 * fp(qe) ** 2 / sf2
+    assert d_ratio < 1e-12
+    _, a_edge, _ = O.density_alpha(dict(pd, alpha_max_factor=10.0), edge, np.zeros((0, 3), np.float32))
+    assert np.all(a_edge == 0.0)
 
 
 # ------------------------------------- the density solve's bound on the maximum
