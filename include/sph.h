@@ -150,6 +150,20 @@ typedef struct sph_mlp sph_mlp;
  *                   bodies between the two solves; the pose moves at the
  *                   step's end.  The reported force and torque are the
  *                   step's summed reaction either way.
+ *   rigid_contact   0: the bodies meet only the tank, through a stand-in
+ *                   that pushes a body back inside the interior shrunk by r
+ *                   and drops its velocity into the wall.  1: frictionless
+ *                   contact without restitution between bodies and with the
+ *                   tank (the paper takes contact from a physics engine,
+ *                   Sec. 4.2).  The bodies' sample points are the contact
+ *                   geometry: a point within s = 2r of the shrunk interior's
+ *                   planes, or within 2s of another body's point, is a
+ *                   contact whose gap (distance to the plane; distance minus
+ *                   s) may close by at most itself in one step.  Normal
+ *                   impulses by projected Gauss-Seidel, 30 sweeps in a fixed
+ *                   order, on the host in FP64 at the step's end, before
+ *                   the pose moves.  Host cost grows with the number of
+ *                   point pairs of bodies within reach of each other.
  */
 typedef struct sph_params {
     double r, h, rho0;
@@ -173,6 +187,7 @@ typedef struct sph_params {
     double alpha_max_factor;
     double eta_density_max;
     int32_t rigid_coupling;
+    int32_t rigid_contact;
 } sph_params;
 
 /* A rigid body (Sec. 3.5): mass, principal moments of inertia (body frame,

@@ -55,6 +55,7 @@ class Params(C.Structure):
         ("alpha_max_factor", C.c_double),
         ("eta_density_max", C.c_double),
         ("rigid_coupling", C.c_int32),
+        ("rigid_contact", C.c_int32),
     ]
 
 
@@ -186,6 +187,7 @@ def make_params(pd: Dict, forced_div: int = -1, forced_dens: int = -1, n_rigid: 
     p.alpha_max_factor = pd.get("alpha_max_factor", 0.0)
     p.eta_density_max = pd.get("eta_density_max", 0.0)
     p.rigid_coupling = pd.get("rigid_coupling", 0)
+    p.rigid_contact = pd.get("rigid_contact", 0)
     return p
 
 

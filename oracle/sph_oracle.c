@@ -66,6 +66,7 @@ typedef struct or_params {
     double eta_density_max;       /* > 0: the density solve also bounds the largest compression */
     int32_t rigid_coupling;       /* 0 weak (bodies move after the fluid solve), 1 strong (every
                                      pressure pass moves them, reading R24) */
+    int32_t rigid_contact;        /* 0 the tank-contact stand-in (R19), 1 sample-point contact (R25) */
 } or_params;
 
 typedef struct or_rigid {
@@ -858,6 +859,147 @@ double or_pcisph_factor(const or_params *p) {
     return p->rho0 * p->rho0 / (2.0 * sum);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Rigid contact (reading R25; the paper leaves rigid dynamics to PyBullet,   */
+/* Sec. 4.2).  Bodies touch through their own sample points (their Akinci     */
+/* boundary particles): a point within one sampling spacing s = 2r of the     */
+/* interior shrunk by r (the tank), or within 2s of another body's point, is  */
+/* a contact with normal n (the inward axis, or from the other point to this  */
+/* one) and gap g (its distance to the plane, or the points' distance minus   */
+/* s).  Frictionless and without restitution, each contact asks that the      */
+/* point not close more than its gap within the step: v_n >= -g / dt, v_n the */
+/* relative normal velocity at the point.  Normal impulses lambda >= 0 are    */
+/* found by projected Gauss-Seidel, 30 sweeps in a fixed order (tank contacts */
+/* by body, point, axis, side; then body pairs a < b by point of a and point  */
+/* of b), on the velocities the step gave the bodies, at the pose of the step's */
+/* start.                                                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct rc_contact {
+    int32_t a, b;              /* bodies (b = -1: the tank) */
+    double n[3], ra[3], rb[3]; /* normal, lever arms from the centres */
+    double bias, K, lam;
+} rc_contact;
+
+static void rc_push(rc_contact **c, int64_t *n, int64_t *cap, rc_contact v) {
+    if (*n == *cap) {
+        *cap = *cap ? 2 * *cap : 256;
+        *c = realloc(*c, sizeof(rc_contact) * (size_t)*cap);
+    }
+    (*c)[(*n)++] = v;
+}
+
+static void rc_apply(or_rigid *s, const double *Iv, const double r[3], const double n[3], double lam) {
+    double rn[3];
+    cross(r, n, rn);
+    for (int a = 0; a < 3; ++a) {
+        s->vel[a] += lam * n[a] / s->mass;
+        s->omega[a] += lam * (Iv[3 * a] * rn[0] + Iv[3 * a + 1] * rn[1] + Iv[3 * a + 2] * rn[2]);
+    }
+}
+
+/* normal velocity of body s at lever arm r */
+static double rc_vn(const or_rigid *s, const double r[3], const double n[3]) {
+    double wr[3];
+    cross(s->omega, r, wr);
+    return (s->vel[0] + wr[0]) * n[0] + (s->vel[1] + wr[1]) * n[1] + (s->vel[2] + wr[2]) * n[2];
+}
+
+/* 1/M + (r x n) . I^-1 (r x n) */
+static double rc_inv_mass(const or_rigid *s, const double *Iv, const double r[3], const double n[3]) {
+    double rn[3], t[3];
+    cross(r, n, rn);
+    for (int a = 0; a < 3; ++a) t[a] = Iv[3 * a] * rn[0] + Iv[3 * a + 1] * rn[1] + Iv[3 * a + 2] * rn[2];
+    return 1.0 / s->mass + rn[0] * t[0] + rn[1] * t[1] + rn[2] * t[2];
+}
+
+static void rigid_contacts(const or_params *p, const or_in *in, double dt, or_rigid *bs) {
+    const int32_t nr = p->n_rigid;
+    const int64_t nb = in->nb;
+    const double s2 = 2.0 * p->r;
+    if (nr <= 0) return;
+    double *P = malloc(sizeof(double) * 3 * (size_t)(nb ? nb : 1));
+    double *Iv = calloc((size_t)(9 * nr), sizeof(double));
+    double *reach = calloc((size_t)nr, sizeof(double));
+    for (int32_t b = 0; b < nr; ++b) {
+        double R[9];
+        quat_to_R(bs[b].quat, R);
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c)
+                for (int q = 0; q < 3; ++q) Iv[9 * b + 3 * a + c] += R[3 * a + q] / bs[b].inertia[q] * R[3 * c + q];
+        for (int64_t k = 0; k < nb; ++k) {
+            if (in->body[k] != b) continue;
+            const double *l = in->local + 3 * k;
+            double r2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                P[3 * k + a] = bs[b].com[a] + (R[3 * a] * l[0] + R[3 * a + 1] * l[1] + R[3 * a + 2] * l[2]);
+                r2 += l[a] * l[a];
+            }
+            if (sqrt(r2) > reach[b]) reach[b] = sqrt(r2);
+        }
+    }
+    rc_contact *cs = NULL;
+    int64_t nc = 0, cap = 0;
+    for (int32_t b = 0; b < nr; ++b)
+        for (int64_t k = 0; k < nb; ++k) {
+            if (in->body[k] != b) continue;
+            for (int a = 0; a < 3; ++a)
+                for (int side = 0; side < 2; ++side) {
+                    const double plane = side == 0 ? p->domain_min[a] + p->r : p->domain_max[a] - p->r;
+                    const double g = side == 0 ? P[3 * k + a] - plane : plane - P[3 * k + a];
+                    if (g >= s2) continue;
+                    rc_contact c;
+                    memset(&c, 0, sizeof(c));
+                    c.a = b; c.b = -1;
+                    c.n[a] = side == 0 ? 1.0 : -1.0;
+                    for (int q = 0; q < 3; ++q) c.ra[q] = P[3 * k + q] - bs[b].com[q];
+                    c.bias = -g / dt;
+                    c.K = rc_inv_mass(&bs[b], Iv + 9 * b, c.ra, c.n);
+                    rc_push(&cs, &nc, &cap, c);
+                }
+        }
+    for (int32_t a = 0; a < nr; ++a)
+        for (int32_t b = a + 1; b < nr; ++b) {
+            double dc = 0.0;
+            for (int q = 0; q < 3; ++q) dc += (bs[a].com[q] - bs[b].com[q]) * (bs[a].com[q] - bs[b].com[q]);
+            if (sqrt(dc) >= reach[a] + reach[b] + 2.0 * s2) continue;
+            for (int64_t k = 0; k < nb; ++k) {
+                if (in->body[k] != a) continue;
+                for (int64_t j = 0; j < nb; ++j) {
+                    if (in->body[j] != b) continue;
+                    double d[3], dd = 0.0;
+                    for (int q = 0; q < 3; ++q) { d[q] = P[3 * k + q] - P[3 * j + q]; dd += d[q] * d[q]; }
+                    dd = sqrt(dd);
+                    if (!(dd < 2.0 * s2) || dd == 0.0) continue;
+                    rc_contact c;
+                    memset(&c, 0, sizeof(c));
+                    c.a = a; c.b = b;
+                    for (int q = 0; q < 3; ++q) {
+                        c.n[q] = d[q] / dd;
+                        c.ra[q] = P[3 * k + q] - bs[a].com[q];
+                        c.rb[q] = P[3 * j + q] - bs[b].com[q];
+                    }
+                    c.bias = -(dd - s2) / dt;
+                    c.K = rc_inv_mass(&bs[a], Iv + 9 * a, c.ra, c.n) + rc_inv_mass(&bs[b], Iv + 9 * b, c.rb, c.n);
+                    rc_push(&cs, &nc, &cap, c);
+                }
+            }
+        }
+    for (int sweep = 0; sweep < 30; ++sweep)
+        for (int64_t i = 0; i < nc; ++i) {
+            rc_contact *c = &cs[i];
+            double vn = rc_vn(&bs[c->a], c->ra, c->n);
+            if (c->b >= 0) vn -= rc_vn(&bs[c->b], c->rb, c->n);
+            double lam = c->lam + (c->bias - vn) / c->K;
+            if (lam < 0.0) lam = 0.0;
+            const double dl = lam - c->lam;
+            c->lam = lam;
+            if (dl == 0.0) continue;
+            rc_apply(&bs[c->a], Iv + 9 * c->a, c->ra, c->n, dl);
+            if (c->b >= 0) rc_apply(&bs[c->b], Iv + 9 * c->b, c->rb, c->n, -dl);
+        }
+    free(cs); free(P); free(Iv); free(reach);
+}
+
 int or_step(const or_params *p, const or_in *in, or_out *out) {
     if (p->solver == 2 && p->warm_start == 2) return -2;   /* the learned start is DFSPH's */
     if (in->nf < 0 || in->nb < 0) return -3;
@@ -1311,28 +1453,27 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     }
     if (out->psi) memcpy(out->psi, w->psi, sizeof(double) * nb);
 
-    /* -- rigid bodies: Newton-Euler in FP64 (weak coupling: the body velocity
-     *    was held fixed during the fluid solve), then the tank-contact
-     *    stand-in, then the boundary particles of the new pose. */
+    /* -- rigid bodies, FP64: (1) the velocities (weak coupling: the step's
+     *    reaction, gravity and the gyroscopic term now; strong: advanced
+     *    during the step), (2) rigid contact (R25) on those velocities, (3)
+     *    the pose; then the boundary particles of the new pose.  Without
+     *    rigid contact the tank-contact stand-in of R19 replaces (2). */
     for (int32_t b = 0; b < p->n_rigid; ++b) {
         or_rigid s = in->rigid[b];
-        double R[9], Iw[9], Iwinv[9], tmp[9];
-        quat_to_R(s.quat, R);
-        /* world inertia R diag(I) R^T and its inverse R diag(1/I) R^T */
-        for (int a = 0; a < 3; ++a)
-            for (int c = 0; c < 3; ++c) {
-                Iw[3 * a + c] = 0.0; Iwinv[3 * a + c] = 0.0;
-                for (int q = 0; q < 3; ++q) {
-                    Iw[3 * a + c] += R[3 * a + q] * s.inertia[q] * R[3 * c + q];
-                    Iwinv[3 * a + c] += R[3 * a + q] / s.inertia[q] * R[3 * c + q];
-                }
-            }
-        (void)tmp;
         if (w->strong) {
-            /* the velocities were advanced by every pressure pass, gravity
-             * and the gyroscopic term during the step */
             for (int a = 0; a < 3; ++a) { s.vel[a] = w->bs[b].vel[a]; s.omega[a] = w->bs[b].omega[a]; }
         } else {
+            double R[9], Iw[9], Iwinv[9];
+            quat_to_R(s.quat, R);
+            /* world inertia R diag(I) R^T and its inverse R diag(1/I) R^T */
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) {
+                    Iw[3 * a + c] = 0.0; Iwinv[3 * a + c] = 0.0;
+                    for (int q = 0; q < 3; ++q) {
+                        Iw[3 * a + c] += R[3 * a + q] * s.inertia[q] * R[3 * c + q];
+                        Iwinv[3 * a + c] += R[3 * a + q] / s.inertia[q] * R[3 * c + q];
+                    }
+                }
             for (int a = 0; a < 3; ++a) s.vel[a] += dt * (out->force[3 * b + a] / s.mass + gr[a]);
             double Lw[3], gyro[3], rhs[3];
             for (int a = 0; a < 3; ++a) Lw[a] = Iw[3 * a] * s.omega[0] + Iw[3 * a + 1] * s.omega[1] + Iw[3 * a + 2] * s.omega[2];
@@ -1341,6 +1482,12 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
             for (int a = 0; a < 3; ++a)
                 s.omega[a] += dt * (Iwinv[3 * a] * rhs[0] + Iwinv[3 * a + 1] * rhs[1] + Iwinv[3 * a + 2] * rhs[2]);
         }
+        out->rigid_new[b] = s;
+    }
+    if (p->rigid_contact == 1) rigid_contacts(p, in, dt, out->rigid_new);
+    for (int32_t b = 0; b < p->n_rigid; ++b) {
+        or_rigid s = out->rigid_new[b];
+        double R[9];
         for (int a = 0; a < 3; ++a) s.com[a] += dt * s.vel[a];
         {
             double qw = s.quat[0], qx = s.quat[1], qy = s.quat[2], qz = s.quat[3];
@@ -1353,21 +1500,23 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
             double nq = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
             s.quat[0] = qw / nq; s.quat[1] = qx / nq; s.quat[2] = qy / nq; s.quat[3] = qz / nq;
         }
-        /* tank-contact stand-in: push the body back inside [min + r, max - r]
-         * along each axis and drop the velocity component into the wall */
-        quat_to_R(s.quat, R);
-        for (int a = 0; a < 3; ++a) {
-            double lo = 1e300, hi = -1e300;
-            for (int64_t k = 0; k < nb; ++k) {
-                if (in->body[k] != b) continue;
-                const double *l = in->local + 3 * k;
-                double xa = s.com[a] + (R[3 * a] * l[0] + R[3 * a + 1] * l[1] + R[3 * a + 2] * l[2]);
-                if (xa < lo) lo = xa;
-                if (xa > hi) hi = xa;
+        if (p->rigid_contact != 1) {
+            /* tank-contact stand-in: push the body back inside [min + r, max - r]
+             * along each axis and drop the velocity component into the wall */
+            quat_to_R(s.quat, R);
+            for (int a = 0; a < 3; ++a) {
+                double lo = 1e300, hi = -1e300;
+                for (int64_t k = 0; k < nb; ++k) {
+                    if (in->body[k] != b) continue;
+                    const double *l = in->local + 3 * k;
+                    double xa = s.com[a] + (R[3 * a] * l[0] + R[3 * a + 1] * l[1] + R[3 * a + 2] * l[2]);
+                    if (xa < lo) lo = xa;
+                    if (xa > hi) hi = xa;
+                }
+                double wl = p->domain_min[a] + p->r, wh = p->domain_max[a] - p->r;
+                if (lo < wl) { s.com[a] += wl - lo; if (s.vel[a] < 0.0) s.vel[a] = 0.0; }
+                else if (hi > wh) { s.com[a] -= hi - wh; if (s.vel[a] > 0.0) s.vel[a] = 0.0; }
             }
-            double wl = p->domain_min[a] + p->r, wh = p->domain_max[a] - p->r;
-            if (lo < wl) { s.com[a] += wl - lo; if (s.vel[a] < 0.0) s.vel[a] = 0.0; }
-            else if (hi > wh) { s.com[a] -= hi - wh; if (s.vel[a] > 0.0) s.vel[a] = 0.0; }
         }
         out->rigid_new[b] = s;
     }

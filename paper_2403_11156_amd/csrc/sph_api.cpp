@@ -13,6 +13,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <unordered_map>
 #include <new>
 #include <string>
 #include <vector>
@@ -283,15 +284,198 @@ int upload_poses(sph_ctx *c) {
     return SPH_OK;
 }
 
-// Newton-Euler in FP64 with the world inertia R diag(I) R^T, then the
-// tank-contact stand-in: push the body back inside [min + r, max - r] along
-// each axis and drop the velocity component into the wall.
+// Rigid contact in FP64 (the paper takes rigid dynamics from a physics
+// engine, Sec. 4.2; this is a frictionless contact model of our own).  The
+// bodies' sample points are their contact geometry: a point closer than one
+// sampling spacing s = 2r to the interior shrunk by r (the tank), or closer
+// than 2s to another body's point, makes a contact with normal n and gap g
+// (distance to the plane; point distance minus s).  Each contact asks that
+// the point close by at most g within the step, v_n >= -g / dt, with v_n the
+// relative normal velocity there.  Projected Gauss-Seidel on accumulated
+// normal impulses, 30 sweeps in a fixed order (tank contacts by body, point,
+// axis, side; then body pairs a < b by point of a, point of b), applied to
+// the velocities the step gave the bodies, at the step's starting pose.
+struct Contact {
+    int a, b;                 // bodies; b = -1 for the tank
+    double n[3], ra[3], rb[3];
+    double bias, K, lam;
+};
+
+namespace {
+double contact_inv_mass(const sph_rigid_desc &s, const double *Iv, const double r[3], const double n[3]) {
+    double rn[3];
+    cross3(r, n, rn);
+    double q = 0.0;
+    for (int a = 0; a < 3; ++a) q += rn[a] * (Iv[3 * a] * rn[0] + Iv[3 * a + 1] * rn[1] + Iv[3 * a + 2] * rn[2]);
+    return 1.0 / s.mass + q;
+}
+
+double contact_vn(const sph_rigid_desc &s, const double r[3], const double n[3]) {
+    double w[3];
+    cross3(s.omega, r, w);
+    return (s.vel[0] + w[0]) * n[0] + (s.vel[1] + w[1]) * n[1] + (s.vel[2] + w[2]) * n[2];
+}
+
+void contact_impulse(sph_rigid_desc &s, const double *Iv, const double r[3], const double n[3], double lam) {
+    double rn[3];
+    cross3(r, n, rn);
+    for (int a = 0; a < 3; ++a) {
+        s.vel[a] += lam * n[a] / s.mass;
+        s.omega[a] += lam * (Iv[3 * a] * rn[0] + Iv[3 * a + 1] * rn[1] + Iv[3 * a + 2] * rn[2]);
+    }
+}
+}  // namespace
+
+void rigid_contact(sph_ctx *c, double dt, std::vector<sph_rigid_desc> &bs) {
+    const int nr = c->nr;
+    const double s2 = 2.0 * c->P.r;
+    std::vector<std::vector<double>> P(nr);
+    std::vector<double> Iv(9 * (size_t)nr, 0.0), reach(nr, 0.0);
+    for (int b = 0; b < nr; ++b) {
+        double R[9];
+        quat_to_R(bs[b].quat, R);
+        for (int a = 0; a < 3; ++a)
+            for (int q = 0; q < 3; ++q)
+                for (int k = 0; k < 3; ++k) Iv[9 * b + 3 * a + q] += R[3 * a + k] / bs[b].inertia[k] * R[3 * q + k];
+        const std::vector<double> &pts = c->body_points[b];
+        P[b].resize(pts.size());
+        for (size_t k = 0; k + 2 < pts.size(); k += 3) {
+            const double *l = &pts[k];
+            for (int a = 0; a < 3; ++a)
+                P[b][k + a] = bs[b].com[a] + (R[3 * a] * l[0] + R[3 * a + 1] * l[1] + R[3 * a + 2] * l[2]);
+            reach[b] = std::max(reach[b], std::sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]));
+        }
+    }
+    std::vector<Contact> cs;
+    std::vector<std::vector<Contact>> pair_contacts((size_t)nr * nr);
+    for (int b = 0; b < nr; ++b)
+        for (size_t k = 0; k + 2 < P[b].size(); k += 3)
+            for (int a = 0; a < 3; ++a)
+                for (int side = 0; side < 2; ++side) {
+                    const double plane = side == 0 ? c->P.domain_min[a] + c->P.r : c->P.domain_max[a] - c->P.r;
+                    const double g = side == 0 ? P[b][k + a] - plane : plane - P[b][k + a];
+                    if (g >= s2) continue;
+                    Contact t{};
+                    t.a = b;
+                    t.b = -1;
+                    t.n[a] = side == 0 ? 1.0 : -1.0;
+                    for (int q = 0; q < 3; ++q) t.ra[q] = P[b][k + q] - bs[b].com[q];
+                    t.bias = -g / dt;
+                    t.K = contact_inv_mass(bs[b], &Iv[9 * b], t.ra, t.n);
+                    cs.push_back(t);
+                }
+    // body pairs: b's points hashed into cells a little wider than the
+    // contact range 2s, so every point of b within 2s of a point of a lies in
+    // the 27 cells around it; the candidates are taken in ascending index, so
+    // the contacts come in the order of a plain double loop over (k, j).
+    // Only a's points within 2s of b's bounding box can have a partner (the
+    // box is widened by the cell width, a hair more than 2s, against rounding).
+    const double cell = 2.0 * s2 * (1.0 + 1e-9);
+    std::vector<double> box(6 * (size_t)nr);
+    for (int b = 0; b < nr; ++b) {
+        for (int q = 0; q < 3; ++q) {
+            box[6 * b + q] = 1e300;
+            box[6 * b + 3 + q] = -1e300;
+        }
+        for (size_t j = 0; j + 2 < P[b].size(); j += 3)
+            for (int q = 0; q < 3; ++q) {
+                box[6 * b + q] = std::min(box[6 * b + q], P[b][j + q] - cell);
+                box[6 * b + 3 + q] = std::max(box[6 * b + 3 + q], P[b][j + q] + cell);
+            }
+    }
+    auto in_box = [&](int b, const double *x) {
+        for (int q = 0; q < 3; ++q)
+            if (!(x[q] >= box[6 * b + q] && x[q] <= box[6 * b + 3 + q])) return false;
+        return true;
+    };
+    std::unordered_map<uint64_t, std::vector<uint32_t>> grid;
+    std::vector<uint32_t> cand;
+    auto cell_of = [&](const double *x, int64_t o[3]) {
+        for (int q = 0; q < 3; ++q) o[q] = (int64_t)std::floor(x[q] / cell);
+    };
+    auto key_of = [](int64_t x, int64_t y, int64_t z) {
+        return ((uint64_t)(x & 0x1FFFFF) << 42) | ((uint64_t)(y & 0x1FFFFF) << 21) | (uint64_t)(z & 0x1FFFFF);
+    };
+    for (int b = 1; b < nr; ++b) {
+        bool hashed = false;
+        for (int a = 0; a < b; ++a) {
+            double dc = 0.0;
+            for (int q = 0; q < 3; ++q) dc += (bs[a].com[q] - bs[b].com[q]) * (bs[a].com[q] - bs[b].com[q]);
+            if (std::sqrt(dc) >= reach[a] + reach[b] + 2.0 * s2) continue;
+            if (!hashed) {
+                grid.clear();
+                for (size_t j = 0; j + 2 < P[b].size(); j += 3) {
+                    int64_t o[3];
+                    cell_of(&P[b][j], o);
+                    grid[key_of(o[0], o[1], o[2])].push_back((uint32_t)j);
+                }
+                hashed = true;
+            }
+            for (size_t k = 0; k + 2 < P[a].size(); k += 3) {
+                if (!in_box(b, &P[a][k])) continue;
+                int64_t o[3];
+                cell_of(&P[a][k], o);
+                cand.clear();
+                for (int64_t dz = -1; dz <= 1; ++dz)
+                    for (int64_t dy = -1; dy <= 1; ++dy)
+                        for (int64_t dx = -1; dx <= 1; ++dx) {
+                            auto it = grid.find(key_of(o[0] + dx, o[1] + dy, o[2] + dz));
+                            if (it != grid.end()) cand.insert(cand.end(), it->second.begin(), it->second.end());
+                        }
+                std::sort(cand.begin(), cand.end());
+                for (const uint32_t j : cand) {
+                    double d[3], dd = 0.0;
+                    for (int q = 0; q < 3; ++q) {
+                        d[q] = P[a][k + q] - P[b][j + q];
+                        dd += d[q] * d[q];
+                    }
+                    dd = std::sqrt(dd);
+                    if (!(dd < 2.0 * s2) || dd == 0.0) continue;
+                    Contact t{};
+                    t.a = a;
+                    t.b = b;
+                    for (int q = 0; q < 3; ++q) {
+                        t.n[q] = d[q] / dd;
+                        t.ra[q] = P[a][k + q] - bs[a].com[q];
+                        t.rb[q] = P[b][j + q] - bs[b].com[q];
+                    }
+                    t.bias = -(dd - s2) / dt;
+                    t.K = contact_inv_mass(bs[a], &Iv[9 * a], t.ra, t.n) + contact_inv_mass(bs[b], &Iv[9 * b], t.rb, t.n);
+                    pair_contacts[(size_t)a * nr + b].push_back(t);
+                }
+            }
+        }
+    }
+    // pairs in the order a < b, a outer
+    for (int a = 0; a < nr; ++a)
+        for (int b = a + 1; b < nr; ++b) {
+            std::vector<Contact> &v = pair_contacts[(size_t)a * nr + b];
+            cs.insert(cs.end(), v.begin(), v.end());
+        }
+    for (int sweep = 0; sweep < 30; ++sweep)
+        for (Contact &t : cs) {
+            double vn = contact_vn(bs[t.a], t.ra, t.n);
+            if (t.b >= 0) vn -= contact_vn(bs[t.b], t.rb, t.n);
+            const double lam = std::max(0.0, t.lam + (t.bias - vn) / t.K);
+            const double dl = lam - t.lam;
+            t.lam = lam;
+            if (dl == 0.0) continue;
+            contact_impulse(bs[t.a], &Iv[9 * t.a], t.ra, t.n, dl);
+            if (t.b >= 0) contact_impulse(bs[t.b], &Iv[9 * t.b], t.rb, t.n, -dl);
+        }
+}
+
+// Newton-Euler in FP64 with the world inertia R diag(I) R^T for every body;
+// then rigid contact on the new velocities (or, without it, the tank-contact
+// stand-in after the pose moves: push the body back inside [min + r, max - r]
+// along each axis and drop the velocity component into the wall).
 // advance_velocity false (strong coupling): the velocities were advanced
-// during the step, only the pose moves.
+// during the step, only contact and the pose remain.
 void rigid_integrate(sph_ctx *c, double dt, bool advance_velocity) {
     const double *gr = c->P.gravity;
-    for (int b = 0; b < c->nr; ++b) {
-        sph_rigid_desc s = c->rigid[b];
+    std::vector<sph_rigid_desc> bs(c->rigid.begin(), c->rigid.begin() + c->nr);
+    for (int b = 0; b < c->nr && advance_velocity; ++b) {
+        sph_rigid_desc &s = bs[b];
         double R[9], Iw[9], Iwinv[9];
         quat_to_R(s.quat, R);
         for (int a = 0; a < 3; ++a)
@@ -303,16 +487,19 @@ void rigid_integrate(sph_ctx *c, double dt, bool advance_velocity) {
                     Iwinv[3 * a + q] += R[3 * a + k] / s.inertia[k] * R[3 * q + k];
                 }
             }
-        if (advance_velocity) {
-            for (int a = 0; a < 3; ++a) s.vel[a] += dt * (c->force[3 * b + a] / s.mass + gr[a]);
-            double Lw[3], gyro[3], rhs[3];
-            for (int a = 0; a < 3; ++a)
-                Lw[a] = Iw[3 * a] * s.omega[0] + Iw[3 * a + 1] * s.omega[1] + Iw[3 * a + 2] * s.omega[2];
-            cross3(s.omega, Lw, gyro);
-            for (int a = 0; a < 3; ++a) rhs[a] = c->torque[3 * b + a] - gyro[a];
-            for (int a = 0; a < 3; ++a)
-                s.omega[a] += dt * (Iwinv[3 * a] * rhs[0] + Iwinv[3 * a + 1] * rhs[1] + Iwinv[3 * a + 2] * rhs[2]);
-        }
+        for (int a = 0; a < 3; ++a) s.vel[a] += dt * (c->force[3 * b + a] / s.mass + gr[a]);
+        double Lw[3], gyro[3], rhs[3];
+        for (int a = 0; a < 3; ++a)
+            Lw[a] = Iw[3 * a] * s.omega[0] + Iw[3 * a + 1] * s.omega[1] + Iw[3 * a + 2] * s.omega[2];
+        cross3(s.omega, Lw, gyro);
+        for (int a = 0; a < 3; ++a) rhs[a] = c->torque[3 * b + a] - gyro[a];
+        for (int a = 0; a < 3; ++a)
+            s.omega[a] += dt * (Iwinv[3 * a] * rhs[0] + Iwinv[3 * a + 1] * rhs[1] + Iwinv[3 * a + 2] * rhs[2]);
+    }
+    if (c->P.rigid_contact == 1) rigid_contact(c, dt, bs);
+    for (int b = 0; b < c->nr; ++b) {
+        sph_rigid_desc s = bs[b];
+        double R[9];
         for (int a = 0; a < 3; ++a) s.com[a] += dt * s.vel[a];
         {
             double qw = s.quat[0], qx = s.quat[1], qy = s.quat[2], qz = s.quat[3];
@@ -325,23 +512,25 @@ void rigid_integrate(sph_ctx *c, double dt, bool advance_velocity) {
             const double nq = std::sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
             s.quat[0] = qw / nq; s.quat[1] = qx / nq; s.quat[2] = qy / nq; s.quat[3] = qz / nq;
         }
-        quat_to_R(s.quat, R);
-        const std::vector<double> &pts = c->body_points[b];
-        for (int a = 0; a < 3; ++a) {
-            double lo = 1e300, hi = -1e300;
-            for (size_t k = 0; k + 2 < pts.size(); k += 3) {
-                const double *l = &pts[k];
-                const double xa = s.com[a] + (R[3 * a] * l[0] + R[3 * a + 1] * l[1] + R[3 * a + 2] * l[2]);
-                lo = std::min(lo, xa);
-                hi = std::max(hi, xa);
-            }
-            const double wl = c->P.domain_min[a] + c->P.r, wh = c->P.domain_max[a] - c->P.r;
-            if (lo < wl) {
-                s.com[a] += wl - lo;
-                if (s.vel[a] < 0.0) s.vel[a] = 0.0;
-            } else if (hi > wh) {
-                s.com[a] -= hi - wh;
-                if (s.vel[a] > 0.0) s.vel[a] = 0.0;
+        if (c->P.rigid_contact != 1) {
+            quat_to_R(s.quat, R);
+            const std::vector<double> &pts = c->body_points[b];
+            for (int a = 0; a < 3; ++a) {
+                double lo = 1e300, hi = -1e300;
+                for (size_t k = 0; k + 2 < pts.size(); k += 3) {
+                    const double *l = &pts[k];
+                    const double xa = s.com[a] + (R[3 * a] * l[0] + R[3 * a + 1] * l[1] + R[3 * a + 2] * l[2]);
+                    lo = std::min(lo, xa);
+                    hi = std::max(hi, xa);
+                }
+                const double wl = c->P.domain_min[a] + c->P.r, wh = c->P.domain_max[a] - c->P.r;
+                if (lo < wl) {
+                    s.com[a] += wl - lo;
+                    if (s.vel[a] < 0.0) s.vel[a] = 0.0;
+                } else if (hi > wh) {
+                    s.com[a] -= hi - wh;
+                    if (s.vel[a] > 0.0) s.vel[a] = 0.0;
+                }
             }
         }
         c->rigid[b] = s;
@@ -1060,6 +1249,8 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
         return fail(nullptr, SPH_ERR_INVALID, "cg_warm_factor outside [0, 4]");
     if (p->rigid_coupling != 0 && p->rigid_coupling != 1)
         return fail(nullptr, SPH_ERR_INVALID, "rigid_coupling must be 0 (weak) or 1 (strong)");
+    if (p->rigid_contact != 0 && p->rigid_contact != 1)
+        return fail(nullptr, SPH_ERR_INVALID, "rigid_contact must be 0 (tank stand-in) or 1 (contact)");
     if (!(p->eta_density_max >= 0.0))
         return fail(nullptr, SPH_ERR_INVALID, "eta_density_max must be >= 0");
     if (!(p->alpha_max_factor >= 0.0 && p->alpha_max_factor <= 1e6))

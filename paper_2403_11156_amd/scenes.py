@@ -153,6 +153,9 @@ def default_params(r: float, lo, hi, **kw) -> Dict:
         # their configured lengths (a pair meeting at the support's edge, and
         # pockets of compression the mean error over a million particles hides)
         alpha_max_factor=10.0, eta_density_max=0.02,
+        # bodies meet each other and the tank through frictionless contact
+        # of their sample points, not the push-back into the tank
+        rigid_contact=1,
     )
     p.update(kw)
     return p

@@ -44,6 +44,7 @@ class sph_params(C.Structure):
         ("alpha_max_factor", C.c_double),
         ("eta_density_max", C.c_double),
         ("rigid_coupling", C.c_int32),
+        ("rigid_contact", C.c_int32),
     ]
 
 
@@ -219,6 +220,7 @@ def make_params(pd: Dict) -> sph_params:
     p.alpha_max_factor = pd.get("alpha_max_factor", 0.0)
     p.eta_density_max = pd.get("eta_density_max", 0.0)
     p.rigid_coupling = pd.get("rigid_coupling", 0)
+    p.rigid_contact = pd.get("rigid_contact", 0)
     return p
 
 
