@@ -4,16 +4,21 @@ import numpy as np
 
 from oracle import oracle as O
 
-# Single-step fields: |f_gpu - f_ref| <= REL * (|f_ref| + S_f), S_f the oracle's
-# running error scale (zero for rho and alpha, which are sums of positive terms).
+# Single-step fields: |f_gpu - f_ref| <= REL * (|f_ref| + S_f) + ULP_MIN, S_f the
+# oracle's running error scale (zero for rho and alpha, which are sums of
+# positive terms), ULP_MIN the spacing of FP32's subnormal numbers: the device
+# keeps its fields in FP32, so a value that has decayed below FP32's normal
+# range (an isolated particle's warm-started K halves every step) carries an
+# absolute rounding of up to that spacing whatever its relative scale.
 REL = 1e-5
+ULP_MIN = 2.0 ** -149
 
 
 def ratio(gpu, ref, scale=None):
     gpu = np.asarray(gpu, np.float64)
     ref = np.asarray(ref, np.float64)
     s = np.abs(ref) if scale is None else np.abs(ref) + np.asarray(scale, np.float64)
-    tol = REL * s
+    tol = REL * s + ULP_MIN
     d = np.abs(gpu - ref)
     with np.errstate(divide="ignore", invalid="ignore"):
         r = np.where(tol > 0, d / np.where(tol > 0, tol, 1.0), np.where(d > 0, np.inf, 0.0))
