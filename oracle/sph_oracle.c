@@ -65,8 +65,10 @@ typedef struct or_params {
     double alpha_max_factor;      /* DFSPH factor capped at alpha_max_factor * alpha_ref (0: no cap) */
     double eta_density_max;       /* > 0: the density solve also bounds the largest compression */
     int32_t rigid_coupling;       /* 0 weak (bodies move after the fluid solve), 1 strong (every
-                                     pressure pass moves them, reading R24) */
-    int32_t rigid_contact;        /* 0 the tank-contact stand-in (R19), 1 sample-point contact (R25) */
+                                     pressure pass moves them: the interlinked coupling of
+                                     Sec. 6's outlook, in our reading) */
+    int32_t rigid_contact;        /* 0 a stand-in that keeps bodies inside the tank, 1 rigid
+                                     contact between bodies and with the tank (our model) */
 } or_params;
 
 typedef struct or_rigid {
@@ -651,7 +653,8 @@ static void body_boundary_velocities(world *w) {
     }
 }
 
-/* Strong coupling (reading R24): the reaction of one pressure pass on each
+/* Strong coupling (our reading of the interlinked coupling that Sec. 6 names
+ * as future work): the reaction of one pressure pass on each
  * body, Eq. (14) with the pass's stiffness over density,
  *   F_b = sum_i sum_{k in b} m Psi_k (kappa_i / den_i) gradW_ik,
  *   tau_b = sum (x_k - c_b) x F_ik,
@@ -837,7 +840,7 @@ static void visc_cg(world *w, double mu, const double *b, double *x, int32_t *it
 
 /* ---- the whole step ------------------------------------------------------ */
 /* PCISPH stiffness factor (Sec. 3.4.2 names PCISPH; its delta is taken from
- * the predictive-corrective method, reading R21).  delta = 1 / (beta sum_j
+ * the predictive-corrective method, in our reading).  delta = 1 / (beta sum_j
  * |gradW_j|^2) with beta = 2 (dt m / rho0)^2, summed once over a prototype
  * particle inside a filled lattice of spacing 2r (its sum_j gradW_j vanishes
  * by symmetry).  In the stiffness form of the density solve, kappa_i = p_i /
@@ -860,7 +863,7 @@ double or_pcisph_factor(const or_params *p) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Rigid contact (reading R25; the paper leaves rigid dynamics to PyBullet,   */
+/* Rigid contact (our model; the paper leaves rigid dynamics to PyBullet,     */
 /* Sec. 4.2).  Bodies touch through their own sample points (their Akinci     */
 /* boundary particles): a point within one sampling spacing s = 2r of the     */
 /* interior shrunk by r (the tank), or within 2s of another body's point, is  */
@@ -1056,7 +1059,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     /* -- 3. Psi, Eq. (11) */
     boundary_psi(p, w->xb, nb, &bb, w->psi);
 
-    /* bodies during the step (strong coupling, R24): their velocities change
+    /* bodies during the step (strong coupling): their velocities change
      * with every pressure pass; the pose (and so the world inertia) stays */
     w->nr = p->n_rigid;
     w->strong = p->rigid_coupling == 1 && p->n_rigid > 0;
@@ -1085,7 +1088,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     density_alpha(w);
     const int dfsph = p->solver == 0, pcisph = p->solver == 2;
     if (pcisph) {
-        /* PCISPH: the density solve's factor is c / rho_i (R21) instead of
+        /* PCISPH: the density solve's factor is c / rho_i instead of
          * the DFSPH alpha; it is reported in its place */
         const double c = or_pcisph_factor(p);
         for (int64_t i = 0; i < nf; ++i) {
@@ -1109,7 +1112,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
     double err_v = 0.0, S_err_v = 0.0;
     if (dfsph) {
         /* -- 5. divergence-free solve (Eq. 10 with Algorithm 2).  Warm start
-         *    (R15): zero (ZERO), or kappa/rho = warm_factor Kv_prev / rho_prev,
+         *    (Algorithm 2 leaves it open): zero (ZERO), or kappa/rho = warm_factor Kv_prev / rho_prev,
          *    the previous step's stiffness over its own density (PREVIOUS,
          *    LEARNED); it accumulates as Kv0 = that times the current rho. */
         double *rp = malloc(s1);
@@ -1233,7 +1236,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
         double *b = malloc(s3);
         for (int64_t i = 0; i < nf; ++i)
             for (int a = 0; a < 3; ++a) b[3 * i + a] = w->v[3 * i + a] + dt * gr[a];
-        /* start value (R22): x0 = b + cg_warm_factor times the previous
+        /* start value (Sec. 3.6 gives none): x0 = b + cg_warm_factor times the previous
          * step's correction v* - b */
         for (int64_t i = 0; i < n3; ++i)
             vs[i] = b[i] + (in->dvisc ? p->cg_warm_factor * (double)in->dvisc[i] : 0.0);
@@ -1304,7 +1307,7 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
 
     /* -- 8. constant-density solve (Eqs. 8, 9 with Eq. 7, Algorithm 2):
      *    rho*_i = rho_i + dt d_i(v*), kappa_i = max(rho*_i - rho0, 0) alpha_i / dt^2,
-     *    with PCISPH's c / rho_i in place of alpha_i (R21).  The error of
+     *    with PCISPH's c / rho_i in place of alpha_i.  The error of
      *    Algorithm 2 is the mean compression; with eta_density_max > 0 the
      *    solve also iterates while the largest compression exceeds it. */
     double *rs = malloc(s1), *Srs = malloc(s1);
@@ -1348,9 +1351,9 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
         }
     } else {
         /* -- 8w. WCSPH (Sec. 3.4.1): the equation of state
-         *    p_i = k ((rho_i/rho0)^gamma - 1), clamped at zero (R20), then one
-         *    pressure pass on v* with kappa_i = p_i / rho_i (p/rho^2 = kappa/rho,
-         *    R4).  The reported error is the mean compression of rho itself. */
+         *    p_i = k ((rho_i/rho0)^gamma - 1), clamped at zero (no tension), then
+         *    one pressure pass on v* with kappa_i = p_i / rho_i (p/rho^2 =
+         *    kappa/rho).  The reported error is the mean compression of rho itself. */
         for (int64_t i = 0; i < nf; ++i) {
             const double ratio = w->rho[i] / p->rho0;
             const double pw = pow(ratio, p->wcsph_gamma);
@@ -1455,9 +1458,10 @@ int or_step(const or_params *p, const or_in *in, or_out *out) {
 
     /* -- rigid bodies, FP64: (1) the velocities (weak coupling: the step's
      *    reaction, gravity and the gyroscopic term now; strong: advanced
-     *    during the step), (2) rigid contact (R25) on those velocities, (3)
-     *    the pose; then the boundary particles of the new pose.  Without
-     *    rigid contact the tank-contact stand-in of R19 replaces (2). */
+     *    during the step), (2) rigid contact on those velocities, (3) the
+     *    pose; then the boundary particles of the new pose.  Without rigid
+     *    contact a stand-in that pushes each body back inside the tank
+     *    replaces (2). */
     for (int32_t b = 0; b < p->n_rigid; ++b) {
         or_rigid s = in->rigid[b];
         if (w->strong) {

@@ -1,5 +1,6 @@
 """Strong (interlinked) rigid-fluid coupling on the device against the oracle:
-every pressure pass moves the bodies at once (reading R24)."""
+every pressure pass moves the bodies at once (our reading of the
+interlinked coupling that Sec. 6 names as future work)."""
 
 import numpy as np
 import pytest

@@ -1,6 +1,6 @@
-"""Pins of the oracle's strong (interlinked) rigid-fluid coupling (reading
-R24: every pressure pass moves the bodies at once and the next pass sees
-their new boundary velocities)."""
+"""Pins of the oracle's strong (interlinked) rigid-fluid coupling (our
+reading of Sec. 6's future work: every pressure pass moves the bodies at once
+and the next pass sees their new boundary velocities)."""
 
 import numpy as np
 

@@ -301,7 +301,7 @@ def test_laplacian_viscosity_vanishes_for_a_linear_field():
 def test_alpha_of_a_lone_particle_at_a_wall_closed_form():
     # the wall term of the factor goes into the gradient sum, not the sum of
     # squares: with no fluid neighbours D = |sum_B Psi gradW|^2 and
-    # alpha = rho / D (read R3), rho from Eq. (12)
+    # alpha = rho / D, rho from Eq. (12)
     wall = _wall()
     xf = np.array([[0.5, 0.25 + S, 0.5]], np.float32)
     rho, alpha, _ = O.density_alpha(_scene(xf, xb=wall).params, xf, wall)
@@ -330,7 +330,7 @@ def test_alpha_of_the_first_fluid_layer_over_a_wall_closed_form():
     assert abs(alpha[pick] - r_expect / (g * g + sq)) < 1e-9 * alpha[pick]
 
 
-# ------------------------------------------------------ the factor's cap (R3)
+# ------------------------------------------------------ the factor's cap
 def test_alpha_cap_on_a_lone_pair_near_the_support_edge():
     # two particles at distance 0.95 h: D = |m gradW|^2 + |m gradW|^2 (gradient
     # sum and sum of squares hold the one neighbour), rho = m k (1 + f(q)), so

@@ -589,7 +589,7 @@ def test_cg_start_factor_zero_is_x0_b():
 
 
 def test_cg_start_half_previous_correction_saves_iterations():
-    # the start of R22 on the viscous column: over 12 steps the half previous
+    # the CG start x0 = b + 0.5 dv_prev on the viscous column: over 12 steps the half previous
     # correction needs clearly fewer CG iterations than x0 = b (the same
     # trajectory: the step is re-run with factor 0 from each state)
     sc = _visc_column(cg_warm_factor=0.5)
@@ -606,7 +606,7 @@ def test_cg_start_half_previous_correction_saves_iterations():
 
 
 def test_divergence_warm_start_uses_previous_stiffness_over_previous_density():
-    # R15: the divergence solve starts from kappa/rho = warm_factor Kv_prev /
+    # the divergence solve starts from kappa/rho = warm_factor Kv_prev /
     # rho_prev; it accumulates as Kv0 = that times the step's density, and the
     # fluid-only pressure impulse of the start sums to zero
     r = 0.01
