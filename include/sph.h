@@ -205,7 +205,15 @@ typedef struct sph_rigid_desc {
 /* Initial scene (Sec. 4.1: fluid blocks and rigid bodies sampled as Akinci
  * boundary particles).  body_of_boundary[k] = -1 for the static tank, else
  * the index of the rigid body particle k samples; rigid particles move with
- * their body. */
+ * their body.
+ *
+ * device_arena (optional): device memory the caller lends the context, e.g.
+ * a tensor its framework allocated, of device_arena_bytes bytes on the
+ * current device, at least sph_required_bytes() of them.  The context then
+ * carves every device buffer it needs from it (256-byte aligned) and calls
+ * no hipMalloc; it never frees the arena, which must stay valid and
+ * otherwise untouched until sph_destroy.  NULL: the context allocates and
+ * frees its own buffers. */
 typedef struct sph_scene {
     int64_t n_fluid, n_boundary;
     int32_t n_rigid;
@@ -214,6 +222,8 @@ typedef struct sph_scene {
     const float *x_boundary;         /* [n_boundary][3] */
     const int32_t *body_of_boundary; /* [n_boundary], NULL = all static */
     const sph_rigid_desc *rigid;     /* [n_rigid] */
+    void *device_arena;              /* device pointer, borrowed; NULL = allocate */
+    int64_t device_arena_bytes;
 } sph_scene;
 
 /* Host statistics of one sph_step. */
@@ -280,6 +290,13 @@ typedef struct sph_info {
  * hip_stream is a hipStream_t (borrowed) or NULL.  On failure *out stays
  * NULL and a negative status is returned. */
 int sph_create(const sph_params *params, const sph_scene *scene, void *hip_stream, sph_ctx **out);
+
+/* Device bytes sph_create needs for these parameters and scene sizes (the
+ * arrays and the arena of the scene are not read), the size of a
+ * scene->device_arena.  Validates like sph_create; SPH_ERR_INVALID on
+ * invalid input.  A too-small arena makes sph_create fail with
+ * SPH_ERR_OOM. */
+int sph_required_bytes(const sph_params *params, const sph_scene *scene, int64_t *bytes);
 
 void sph_destroy(sph_ctx *ctx);
 

@@ -111,6 +111,11 @@ struct sph_ctx {
     std::vector<std::vector<double>> body_points;   // per body: its particles' body-frame offsets
     std::vector<void *> allocs;
     int64_t dev_bytes = 0;
+    // a borrowed arena (sph_scene::device_arena) or, with counting set, no
+    // memory at all: dev_alloc only adds up the aligned sizes
+    char *arena = nullptr;
+    int64_t arena_bytes = 0;
+    bool counting = false;
 
     bool nbr_fresh = false, boundary_dirty = true, sorted_once = false;
     bool vb_moving = false;   // some boundary velocity may be non-zero (rigid bodies, or written)
@@ -173,6 +178,15 @@ int fail(sph_ctx *c, int code, const std::string &msg) {
 template <typename T>
 int dev_alloc(sph_ctx *c, T **p, int64_t count) {
     size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+    if (c->arena || c->counting) {   // 256-byte aligned pieces of the arena
+        const int64_t at = c->dev_bytes;
+        const int64_t need = ((int64_t)bytes + 255) / 256 * 256;
+        if (c->arena && at + need > c->arena_bytes)
+            return fail(c, SPH_ERR_OOM, "device arena of " + std::to_string(c->arena_bytes) + " bytes is too small");
+        c->dev_bytes += need;
+        *p = c->arena ? (T *)(c->arena + at) : nullptr;
+        return SPH_OK;
+    }
     void *q = nullptr;
     hipError_t e = hipMalloc(&q, bytes);
     if (e != hipSuccess) return fail(c, SPH_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
@@ -1235,7 +1249,10 @@ const char *sph_strerror(int status) {
 
 const char *sph_last_error(const sph_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
 
-int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_ctx **out) {
+// sph_create, or with count_bytes the device bytes it would allocate (the
+// same validation and the same allocation sequence, no memory touched)
+static int create_impl(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_ctx **out,
+                       int64_t *count_bytes) {
     g_create_error.clear();
     if (!out) return fail(nullptr, SPH_ERR_INVALID, "out is NULL");
     *out = nullptr;
@@ -1263,21 +1280,25 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
         if (!(p->domain_max[a] > p->domain_min[a])) return fail(nullptr, SPH_ERR_INVALID, "empty domain");
     if (sc->n_fluid < 0 || sc->n_boundary < 0 || sc->n_rigid < 0 || sc->n_rigid > sph::kMaxBodies)
         return fail(nullptr, SPH_ERR_INVALID, "invalid scene sizes (at most 16 rigid bodies)");
-    if ((sc->n_fluid > 0 && !sc->x_fluid) || (sc->n_boundary > 0 && !sc->x_boundary) ||
-        (sc->n_rigid > 0 && (!sc->rigid || !sc->body_of_boundary)))
+    if (!count_bytes && ((sc->n_fluid > 0 && !sc->x_fluid) || (sc->n_boundary > 0 && !sc->x_boundary) ||
+                         (sc->n_rigid > 0 && (!sc->rigid || !sc->body_of_boundary))))
         return fail(nullptr, SPH_ERR_INVALID, "missing scene array");
+    if (!count_bytes && sc->device_arena && sc->device_arena_bytes <= 0)
+        return fail(nullptr, SPH_ERR_INVALID, "device_arena given with no bytes");
     if (sc->n_fluid >= (int64_t)0x7fffffff || sc->n_boundary >= (int64_t)0x7fffffff)
         return fail(nullptr, SPH_ERR_INVALID, "too many particles for 32-bit indices");
-    if (sc->n_fluid > 0 && !finite3(sc->x_fluid, sc->n_fluid))
-        return fail(nullptr, SPH_ERR_INVALID, "non-finite fluid position");
-    if (sc->body_of_boundary)
-        for (int64_t k = 0; k < sc->n_boundary; ++k)
-            if (sc->body_of_boundary[k] < -1 || sc->body_of_boundary[k] >= sc->n_rigid)
-                return fail(nullptr, SPH_ERR_INVALID, "body_of_boundary out of range");
-    for (int b = 0; b < sc->n_rigid; ++b)
-        if (!(sc->rigid[b].mass > 0) || !(sc->rigid[b].inertia[0] > 0) || !(sc->rigid[b].inertia[1] > 0) ||
-            !(sc->rigid[b].inertia[2] > 0))
-            return fail(nullptr, SPH_ERR_INVALID, "rigid body mass and inertia must be positive");
+    if (!count_bytes) {   // the scene's arrays
+        if (sc->n_fluid > 0 && !finite3(sc->x_fluid, sc->n_fluid))
+            return fail(nullptr, SPH_ERR_INVALID, "non-finite fluid position");
+        if (sc->body_of_boundary)
+            for (int64_t k = 0; k < sc->n_boundary; ++k)
+                if (sc->body_of_boundary[k] < -1 || sc->body_of_boundary[k] >= sc->n_rigid)
+                    return fail(nullptr, SPH_ERR_INVALID, "body_of_boundary out of range");
+        for (int b = 0; b < sc->n_rigid; ++b)
+            if (!(sc->rigid[b].mass > 0) || !(sc->rigid[b].inertia[0] > 0) || !(sc->rigid[b].inertia[1] > 0) ||
+                !(sc->rigid[b].inertia[2] > 0))
+                return fail(nullptr, SPH_ERR_INVALID, "rigid body mass and inertia must be positive");
+    }
 
     sph_ctx *c = new (std::nothrow) sph_ctx();
     if (!c) return fail(nullptr, SPH_ERR_OOM, "host allocation failed");
@@ -1341,6 +1362,9 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     // reductions run over up to four lanes per fluid particle
     const int64_t nred = std::max<int64_t>(sph::reduction_blocks(std::max(4 * nf, nb)), 8);
     int rc = SPH_OK;
+    c->counting = count_bytes != nullptr;
+    c->arena = count_bytes ? nullptr : (char *)sc->device_arena;
+    c->arena_bytes = sc->device_arena_bytes;
 #define ALLOC(ptr, n)                       \
     if ((rc = dev_alloc(c, &(ptr), (n)))) { \
         std::string m_ = c->err;            \
@@ -1374,6 +1398,11 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
         ALLOC(c->cg_part, sph::visc_matvec_parts(nf) + 4 * (int64_t)sph::reduction_blocks(nf) + 16);
     }
 #undef ALLOC
+    if (count_bytes) {
+        *count_bytes = c->dev_bytes;
+        delete c;
+        return SPH_OK;
+    }
     if (hipHostMalloc((void **)&c->hs, sizeof(sph::HostStatus), hipHostMallocMapped | hipHostMallocCoherent) !=
             hipSuccess ||
         hipHostGetDevicePointer((void **)&c->hs_dev, c->hs, 0) != hipSuccess) {
@@ -1460,6 +1489,17 @@ int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_c
     }
     *out = c;
     return SPH_OK;
+}
+
+int sph_create(const sph_params *p, const sph_scene *sc, void *hip_stream, sph_ctx **out) {
+    return create_impl(p, sc, hip_stream, out, nullptr);
+}
+
+int sph_required_bytes(const sph_params *p, const sph_scene *sc, int64_t *bytes) {
+    if (!bytes) return fail(nullptr, SPH_ERR_INVALID, "bytes is NULL");
+    sph_ctx *unused = nullptr;
+    *bytes = 0;
+    return create_impl(p, sc, nullptr, &unused, bytes);
 }
 
 void sph_destroy(sph_ctx *c) {

@@ -58,6 +58,7 @@ class sph_scene(C.Structure):
         ("n_fluid", C.c_int64), ("n_boundary", C.c_int64), ("n_rigid", C.c_int32),
         ("x_fluid", C.c_void_p), ("v_fluid", C.c_void_p), ("x_boundary", C.c_void_p),
         ("body_of_boundary", C.c_void_p), ("rigid", C.c_void_p),
+        ("device_arena", C.c_void_p), ("device_arena_bytes", C.c_int64),
     ]
 
 
@@ -121,6 +122,7 @@ def _load():
     P = C.c_void_p
     sig = {
         "sph_create": (C.c_int, [C.POINTER(sph_params), C.POINTER(sph_scene), P, C.POINTER(P)]),
+        "sph_required_bytes": (C.c_int, [C.POINTER(sph_params), C.POINTER(sph_scene), C.POINTER(C.c_int64)]),
         "sph_destroy": (None, [P]),
         "sph_build_neighbors": (C.c_int, [P]),
         "sph_step": (C.c_int, [P, C.POINTER(sph_step_stats)]),
@@ -158,6 +160,7 @@ lib = _load()
 
 # the C entry points under their own names
 sph_create = lib.sph_create
+sph_required_bytes = lib.sph_required_bytes
 sph_destroy = lib.sph_destroy
 sph_build_neighbors = lib.sph_build_neighbors
 sph_step = lib.sph_step
@@ -255,10 +258,25 @@ def current_stream_handle() -> Optional[int]:
     return None
 
 
-class Simulation:
-    """One sph_ctx: create from a scene, build neighbours, step, read state."""
+def required_bytes(scene, params: Optional[Dict] = None) -> int:
+    """sph_required_bytes: the device arena a context of this scene needs."""
+    sc = sph_scene()
+    sc.n_fluid, sc.n_boundary, sc.n_rigid = scene.n_fluid, scene.n_boundary, len(scene.rigid)
+    p = make_params(dict(scene.params if params is None else params))
+    out = C.c_int64()
+    rc = sph_required_bytes(C.byref(p), C.byref(sc), C.byref(out))
+    if rc != SPH_OK:
+        raise SphError(rc, sph_last_error(None).decode())
+    return out.value
 
-    def __init__(self, scene, params: Optional[Dict] = None, stream: Optional[int] = None):
+
+class Simulation:
+    """One sph_ctx: create from a scene, build neighbours, step, read state.
+    arena: optional device tensor (any dtype, contiguous, on the current
+    device) lent to the context for all its device buffers; it must hold at
+    least required_bytes(scene, params) bytes and is kept alive here."""
+
+    def __init__(self, scene, params: Optional[Dict] = None, stream: Optional[int] = None, arena=None):
         pd = dict(scene.params if params is None else params)
         self.params = pd
         self.nf = scene.n_fluid
@@ -273,6 +291,10 @@ class Simulation:
         sc.n_fluid, sc.n_boundary, sc.n_rigid = self.nf, self.nb, self.nr
         sc.x_fluid, sc.v_fluid, sc.x_boundary, sc.body_of_boundary = (_ptr(a) for a in self._keep)
         sc.rigid = C.cast(self._rigid, C.c_void_p)
+        self._arena = arena
+        if arena is not None:
+            sc.device_arena = C.c_void_p(arena.data_ptr())
+            sc.device_arena_bytes = arena.numel() * arena.element_size()
         self._p = make_params(pd)
         ctx = C.c_void_p()
         if stream is None:
