@@ -360,17 +360,22 @@ __device__ __forceinline__ void load_fields(int64_t n, int64_t base, const float
                                             const float* __restrict__ alpha, const float* __restrict__ K,
                                             const uint32_t* __restrict__ ncnt, const uint32_t* __restrict__ bcnt,
                                             const float* __restrict__ d, const Kern& kc, float dt, float alpha_ref,
-                                            float fr[4]) {
+                                            float fr[4], float raw[3]) {
     const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
     const int64_t i = base + p;
     fr[0] = fr[1] = fr[2] = fr[3] = 0.f;
+    raw[0] = raw[1] = raw[2] = 0.f;
     if (i >= n) return;
     const float a = alpha[i];
-    if (h == 0) {
-        fr[0] = (rho[i] - kc.rho0) / kc.rho0;
+    if (h == 0) {   // these lanes also store the start: rho, alpha and K stay in registers for it
+        const float r = rho[i], k = K[i];
+        fr[0] = (r - kc.rho0) / kc.rho0;
         fr[1] = dt * d[i] / kc.rho0;
         fr[2] = (float)(ncnt[i] + bcnt[i]) / 26.0f;
-        fr[3] = a > 0.0f ? K[i] * dt * dt / (a * kc.rho0) : 0.0f;
+        fr[3] = a > 0.0f ? k * dt * dt / (a * kc.rho0) : 0.0f;
+        raw[0] = r;
+        raw[1] = a;
+        raw[2] = k;
     } else {
         fr[0] = a / alpha_ref;
     }
@@ -392,23 +397,26 @@ __global__ void __launch_bounds__(256) k_mlp_warm_start(const uint32_t* __restri
     for (int q = 0; q < kImageWords; ++q) img[q] = packed[q * 64 + lane];
     __syncthreads();
     const int64_t tiles = (n + 31) / 32, stride = (int64_t)gridDim.x * 4;
-    float cur[4] = {0.f, 0.f, 0.f, 0.f};
+    float cur[4] = {0.f, 0.f, 0.f, 0.f}, craw[3] = {0.f, 0.f, 0.f};
     int64_t t = (int64_t)blockIdx.x * 4 + wave;
-    if (t < tiles) load_fields(n, 32 * t, rho, alpha, K, ncnt, bcnt, d, kc, dt, alpha_ref, cur);
+    if (t < tiles) load_fields(n, 32 * t, rho, alpha, K, ncnt, bcnt, d, kc, dt, alpha_ref, cur, craw);
     for (; t < tiles; t += stride) {
-        float nxt[4] = {0.f, 0.f, 0.f, 0.f};
-        if (t + stride < tiles) load_fields(n, 32 * (t + stride), rho, alpha, K, ncnt, bcnt, d, kc, dt, alpha_ref, nxt);
+        float nxt[4] = {0.f, 0.f, 0.f, 0.f}, nraw[3] = {0.f, 0.f, 0.f};
+        if (t + stride < tiles)
+            load_fields(n, 32 * (t + stride), rho, alpha, K, ncnt, bcnt, d, kc, dt, alpha_ref, nxt, nraw);
         const float yv = forward_infer(W, R, cur, n, 32 * t);
         const int64_t i = 32 * t + lane;
-        if (lane < 32 && i < n) {
-            const float k0 = fmaxf(yv * alpha[i] * kc.rho0 / (dt * dt), 0.0f);
+        if (lane < 32 && i < n) {   // rho, alpha, K of particle i from the feature loads
+            const float k0 = fmaxf(yv * craw[1] * kc.rho0 / (dt * dt), 0.0f);
             kappa[i] = k0;
-            if (Ksave) Ksave[i] = K[i];
+            if (Ksave) Ksave[i] = craw[2];
             K[i] = 0.0f;
-            x[i].w = k0 / rho[i];
+            x[i].w = k0 / craw[0];
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) cur[c] = nxt[c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) craw[c] = nraw[c];
     }
 }
 
