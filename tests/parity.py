@@ -6,12 +6,15 @@ from oracle import oracle as O
 
 # Single-step fields: |f_gpu - f_ref| <= REL * (|f_ref| + S_f) + ULP_MIN, S_f the
 # oracle's running error scale (zero for rho and alpha, which are sums of
-# positive terms), ULP_MIN the spacing of FP32's subnormal numbers: the device
-# keeps its fields in FP32, so a value that has decayed below FP32's normal
-# range (an isolated particle's warm-started K halves every step) carries an
-# absolute rounding of up to that spacing whatever its relative scale.
+# positive terms).  ULP_MIN covers FP32's subnormal range: the device keeps
+# its fields in FP32, so a value that has decayed below FP32's normal range
+# (an isolated particle's warm-started K or Kv shrinks by the warm factor
+# every step) is rounded to the subnormal spacing 2^-149 whatever its
+# relative scale, and the divergence start carries Kv as stiffness over
+# density (x.w) and multiplies it back by the density, up to ~2000 kg/m^3 =
+# 2^11: an absolute rounding of up to 2^-149 * 2^11.
 REL = 1e-5
-ULP_MIN = 2.0 ** -149
+ULP_MIN = 2.0 ** -138
 
 
 def ratio(gpu, ref, scale=None):
