@@ -17,7 +17,15 @@
  *     Euler);
  *   - explicit viscosity Eq. (15), implicit viscosity Eqs. (16)-(19) solved by
  *     matrix-free conjugate gradients (Sec. 4.2);
- *   - the uniform grid with prefix sums (Sec. 5.6) for the neighbour search.
+ *   - the uniform grid with prefix sums (Sec. 5.6) for the neighbour search;
+ *   - the rigid bodies the paper leaves to a physics engine (Sec. 4.2):
+ *     Newton-Euler in FP64, the weak coupling of Sec. 3.5, the interlinked
+ *     (strong) coupling that Sec. 6 names as future work, and frictionless
+ *     contact of the bodies' sample points; these are our own models, each
+ *     pinned by closed forms and conservation laws in the tests (a body at
+ *     rest takes its weight, head-on boxes stop one spacing apart, impulse
+ *     pairs keep momentum and angular momentum, a body a trillion times
+ *     heavier reproduces the weak coupling).
  *
  * Neighbour membership and cell keys are decided in FP32 (the state is FP32)
  * exactly as the readings fix them; everything else is FP64 from the FP32
