@@ -13,7 +13,6 @@
 #include <cstring>
 #include <functional>
 #include <map>
-#include <unordered_map>
 #include <new>
 #include <string>
 #include <vector>
@@ -378,12 +377,13 @@ void rigid_contact(sph_ctx *c, double dt, std::vector<sph_rigid_desc> &bs) {
                     t.K = contact_inv_mass(bs[b], &Iv[9 * b], t.ra, t.n);
                     cs.push_back(t);
                 }
-    // body pairs: b's points hashed into cells a little wider than the
-    // contact range 2s, so every point of b within 2s of a point of a lies in
-    // the 27 cells around it; the candidates are taken in ascending index, so
-    // the contacts come in the order of a plain double loop over (k, j).
-    // Only a's points within 2s of b's bounding box can have a partner (the
-    // box is widened by the cell width, a hair more than 2s, against rounding).
+    // Body pairs.  Two points closer than 2s differ by less than the cell
+    // width (a hair over 2s, against rounding) on every axis, so only a's
+    // points inside b's bounding box widened by a cell, and b's points inside
+    // a's widened box, can touch.  b's points there are binned into a dense
+    // grid of such cells (counting sort, ascending index within a cell); each
+    // of a's points takes the candidates of its 27 cells in ascending index,
+    // so the contacts come in the order of a plain double loop over (k, j).
     const double cell = 2.0 * s2 * (1.0 + 1e-9);
     std::vector<double> box(6 * (size_t)nr);
     for (int b = 0; b < nr; ++b) {
@@ -402,39 +402,50 @@ void rigid_contact(sph_ctx *c, double dt, std::vector<sph_rigid_desc> &bs) {
             if (!(x[q] >= box[6 * b + q] && x[q] <= box[6 * b + 3 + q])) return false;
         return true;
     };
-    std::unordered_map<uint64_t, std::vector<uint32_t>> grid;
-    std::vector<uint32_t> cand;
-    auto cell_of = [&](const double *x, int64_t o[3]) {
-        for (int q = 0; q < 3; ++q) o[q] = (int64_t)std::floor(x[q] / cell);
-    };
-    auto key_of = [](int64_t x, int64_t y, int64_t z) {
-        return ((uint64_t)(x & 0x1FFFFF) << 42) | ((uint64_t)(y & 0x1FFFFF) << 21) | (uint64_t)(z & 0x1FFFFF);
-    };
-    for (int b = 1; b < nr; ++b) {
-        bool hashed = false;
-        for (int a = 0; a < b; ++a) {
+    std::vector<uint32_t> near_b, cstart, cidx, cand;
+    for (int a = 0; a < nr; ++a)
+        for (int b = a + 1; b < nr; ++b) {
             double dc = 0.0;
             for (int q = 0; q < 3; ++q) dc += (bs[a].com[q] - bs[b].com[q]) * (bs[a].com[q] - bs[b].com[q]);
             if (std::sqrt(dc) >= reach[a] + reach[b] + 2.0 * s2) continue;
-            if (!hashed) {
-                grid.clear();
-                for (size_t j = 0; j + 2 < P[b].size(); j += 3) {
-                    int64_t o[3];
-                    cell_of(&P[b][j], o);
-                    grid[key_of(o[0], o[1], o[2])].push_back((uint32_t)j);
+            // b's points that may touch a, binned over a's widened box
+            near_b.clear();
+            for (size_t j = 0; j + 2 < P[b].size(); j += 3)
+                if (in_box(a, &P[b][j])) near_b.push_back((uint32_t)j);
+            if (near_b.empty()) continue;
+            double o[3];
+            int64_t dim[3];
+            for (int q = 0; q < 3; ++q) {
+                o[q] = box[6 * a + q];
+                dim[q] = (int64_t)std::floor((box[6 * a + 3 + q] - o[q]) / cell) + 1;
+            }
+            auto coord = [&](const double *x, int q) {
+                const int64_t v = (int64_t)std::floor((x[q] - o[q]) / cell);
+                return std::min<int64_t>(std::max<int64_t>(v, 0), dim[q] - 1);
+            };
+            const int64_t ncell = dim[0] * dim[1] * dim[2];
+            cstart.assign((size_t)ncell + 1, 0u);
+            for (const uint32_t j : near_b)
+                ++cstart[(size_t)((coord(&P[b][j], 2) * dim[1] + coord(&P[b][j], 1)) * dim[0] + coord(&P[b][j], 0)) + 1];
+            for (int64_t t = 0; t < ncell; ++t) cstart[(size_t)t + 1] += cstart[(size_t)t];
+            cidx.resize(near_b.size());
+            {
+                std::vector<uint32_t> fill(cstart.begin(), cstart.end() - 1);
+                for (const uint32_t j : near_b) {
+                    const size_t t = (size_t)((coord(&P[b][j], 2) * dim[1] + coord(&P[b][j], 1)) * dim[0] +
+                                              coord(&P[b][j], 0));
+                    cidx[fill[t]++] = j;
                 }
-                hashed = true;
             }
             for (size_t k = 0; k + 2 < P[a].size(); k += 3) {
                 if (!in_box(b, &P[a][k])) continue;
-                int64_t o[3];
-                cell_of(&P[a][k], o);
+                const int64_t cx = coord(&P[a][k], 0), cy = coord(&P[a][k], 1), cz = coord(&P[a][k], 2);
                 cand.clear();
-                for (int64_t dz = -1; dz <= 1; ++dz)
-                    for (int64_t dy = -1; dy <= 1; ++dy)
-                        for (int64_t dx = -1; dx <= 1; ++dx) {
-                            auto it = grid.find(key_of(o[0] + dx, o[1] + dy, o[2] + dz));
-                            if (it != grid.end()) cand.insert(cand.end(), it->second.begin(), it->second.end());
+                for (int64_t z = std::max<int64_t>(cz - 1, 0); z <= std::min(cz + 1, dim[2] - 1); ++z)
+                    for (int64_t y = std::max<int64_t>(cy - 1, 0); y <= std::min(cy + 1, dim[1] - 1); ++y)
+                        for (int64_t x = std::max<int64_t>(cx - 1, 0); x <= std::min(cx + 1, dim[0] - 1); ++x) {
+                            const size_t t = (size_t)((z * dim[1] + y) * dim[0] + x);
+                            cand.insert(cand.end(), cidx.begin() + cstart[t], cidx.begin() + cstart[t + 1]);
                         }
                 std::sort(cand.begin(), cand.end());
                 for (const uint32_t j : cand) {
@@ -459,7 +470,6 @@ void rigid_contact(sph_ctx *c, double dt, std::vector<sph_rigid_desc> &bs) {
                 }
             }
         }
-    }
     // pairs in the order a < b, a outer
     for (int a = 0; a < nr; ++a)
         for (int b = a + 1; b < nr; ++b) {
