@@ -5,6 +5,9 @@
    1000 steps); each traced step appends, per fluid particle, the five
    features at the start of the density solve and the step's final stiffness
    (sph_enable_trace) into device tensors.
+   With --dagger WEIGHTS the same runs are traced again with the learned
+   start of those weights, and both sets of traces are trained on (the
+   network then also sees the states its own trajectories reach).
 2. Training: mean squared error of the normalised prediction, Adam on the
    device (sph_mlp_train_step: bf16 matrix-core forward and backward, FP32
    master weights), shuffled mini-batches.
@@ -38,8 +41,10 @@ def init_params(seed, shift, scale, out_scale):
     return np.concatenate([np.asarray(a, np.float64).reshape(-1) for a in parts]).astype(np.float32)
 
 
-def collect(runs, torch, sph, scenes, log=print):
-    """runs: list of (scene name, steps, trace every k-th step)."""
+def collect(runs, torch, sph, scenes, log=print, net_params=None):
+    """runs: list of (scene name, steps, trace every k-th step).  With
+    net_params the runs take the learned start of that network, so the
+    traces cover the states its own trajectories reach."""
     total = 0
     for name, steps, every in runs:
         total += scenes.scene(name).n_fluid * len(range(0, steps, every))
@@ -49,6 +54,10 @@ def collect(runs, torch, sph, scenes, log=print):
     for name, steps, every in runs:
         sc = scenes.scene(name)
         sim = sph.Simulation(sc)
+        net = None
+        if net_params is not None:
+            net = sph.MLP(net_params)
+            sim.set_warm_start(2, net)
         t0 = time.time()
         iters = []
         for s in range(steps):
@@ -62,9 +71,11 @@ def collect(runs, torch, sph, scenes, log=print):
                 row += sc.n_fluid
                 sim.enable_trace(None, None, 0)
         torch.cuda.synchronize()
-        log(f"[trace] {sc.name}: {steps} steps in {time.time() - t0:.1f} s, "
-            f"mean density iterations {np.mean(iters):.2f}, rows so far {row}")
+        log(f"[trace] {sc.name}{' (learned start)' if net is not None else ''}: {steps} steps in "
+            f"{time.time() - t0:.1f} s, mean density iterations {np.mean(iters):.2f}, rows so far {row}")
         sim.close()
+        if net is not None:
+            net.close()
     return F, T
 
 
@@ -123,6 +134,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--quick", action="store_true", help="c1 only, 2 epochs (smoke of the driver)")
     ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--dagger", default="",
+                    help="weights whose learned start also runs the trace scenes; its traces join the plain ones")
     ap.add_argument("--commit", default=os.environ.get("TRACE_COMMIT", ""),
                     help="the repository commit whose solver produced the traces (recorded)")
     args = ap.parse_args()
@@ -131,12 +144,20 @@ def main():
     torch.cuda.set_device(0)
     runs = [("c1", 100, 1)] if args.quick else [("c1", 100, 1), ("c2", 1000, 10)]
     F, T = collect(runs, torch, sph, scenes)
+    if args.dagger:
+        dagger = np.fromfile(args.dagger, dtype=np.float32)
+        F2, T2 = collect(runs, torch, sph, scenes, net_params=dagger)
+        F, T = torch.cat([F, F2]), torch.cat([T, T2])
+        del F2, T2
     params, rec = train(F, T, torch, sph, epochs=2 if args.quick else args.epochs)
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     params.astype(np.float32).tofile(args.out)
     rec["runs"] = runs
     rec["trace_windows"] = [f"{name}: steps 0..{steps - 1}, every {every}" for name, steps, every in runs]
     rec["source_digest"] = source_digest()
+    if args.dagger:
+        import hashlib
+        rec["dagger_from"] = hashlib.sha256(open(args.dagger, "rb").read()).hexdigest()[:16]
     rec["commit"] = args.commit
     keys = ("warm_start", "warm_factor", "alpha_max_factor", "eta_density", "eta_density_max", "eta_divergence",
             "cfl_lambda", "dt_max", "visc_model", "visc")
