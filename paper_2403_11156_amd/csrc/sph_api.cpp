@@ -413,13 +413,21 @@ void rigid_contact(sph_ctx *c, double dt, std::vector<sph_rigid_desc> &bs) {
             for (size_t j = 0; j + 2 < P[b].size(); j += 3)
                 if (in_box(a, &P[b][j])) near_b.push_back((uint32_t)j);
             if (near_b.empty()) continue;
-            double o[3];
-            int64_t dim[3];
+            // the grid spans the overlap of the two widened boxes, which holds
+            // every point either side keeps; a body many cells across in
+            // every direction would make it too large: then every kept point
+            // of b is a candidate (the same contacts, found more slowly)
+            double o[3], ext[3];
             for (int q = 0; q < 3; ++q) {
-                o[q] = box[6 * a + q];
-                dim[q] = (int64_t)std::floor((box[6 * a + 3 + q] - o[q]) / cell) + 1;
+                o[q] = std::max(box[6 * a + q], box[6 * b + q]);
+                ext[q] = std::min(box[6 * a + 3 + q], box[6 * b + 3 + q]) - o[q];
             }
+            const bool gridded = ext[0] < 64.0 * cell && ext[1] < 64.0 * cell && ext[2] < 64.0 * cell;
+            int64_t dim[3] = {1, 1, 1};
+            if (gridded)
+                for (int q = 0; q < 3; ++q) dim[q] = std::max<int64_t>((int64_t)std::floor(ext[q] / cell) + 1, 1);
             auto coord = [&](const double *x, int q) {
+                if (!gridded) return (int64_t)0;
                 const int64_t v = (int64_t)std::floor((x[q] - o[q]) / cell);
                 return std::min<int64_t>(std::max<int64_t>(v, 0), dim[q] - 1);
             };
