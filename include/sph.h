@@ -209,11 +209,12 @@ typedef struct sph_rigid_desc {
  *
  * device_arena (optional): device memory the caller lends the context, e.g.
  * a tensor its framework allocated, of device_arena_bytes bytes on the
- * current device, at least sph_required_bytes() of them.  The context then
- * carves every device buffer it needs from it (256-byte aligned) and calls
- * no hipMalloc; it never frees the arena, which must stay valid and
- * otherwise untouched until sph_destroy.  NULL: the context allocates and
- * frees its own buffers. */
+ * current device, at least sph_required_bytes() of them, starting at a
+ * 256-byte aligned address (SPH_ERR_INVALID otherwise; a smaller arena is
+ * SPH_ERR_OOM).  The context then carves every device buffer it needs from
+ * it (256-byte aligned pieces) and calls no hipMalloc; it never frees the
+ * arena, which must stay valid and otherwise untouched until sph_destroy.
+ * NULL: the context allocates and frees its own buffers. */
 typedef struct sph_scene {
     int64_t n_fluid, n_boundary;
     int32_t n_rigid;

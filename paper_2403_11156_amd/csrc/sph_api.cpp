@@ -1303,6 +1303,8 @@ static int create_impl(const sph_params *p, const sph_scene *sc, void *hip_strea
         return fail(nullptr, SPH_ERR_INVALID, "missing scene array");
     if (!count_bytes && sc->device_arena && sc->device_arena_bytes <= 0)
         return fail(nullptr, SPH_ERR_INVALID, "device_arena given with no bytes");
+    if (!count_bytes && sc->device_arena && (uintptr_t)sc->device_arena % 256 != 0)
+        return fail(nullptr, SPH_ERR_INVALID, "device_arena must be 256-byte aligned");
     if (sc->n_fluid >= (int64_t)0x7fffffff || sc->n_boundary >= (int64_t)0x7fffffff)
         return fail(nullptr, SPH_ERR_INVALID, "too many particles for 32-bit indices");
     if (!count_bytes) {   // the scene's arrays

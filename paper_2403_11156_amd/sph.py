@@ -273,8 +273,9 @@ def required_bytes(scene, params: Optional[Dict] = None) -> int:
 class Simulation:
     """One sph_ctx: create from a scene, build neighbours, step, read state.
     arena: optional device tensor (any dtype, contiguous, on the current
-    device) lent to the context for all its device buffers; it must hold at
-    least required_bytes(scene, params) bytes and is kept alive here."""
+    device, starting 256-byte aligned, as a freshly allocated tensor does)
+    lent to the context for all its device buffers; it must hold at least
+    required_bytes(scene, params) bytes and is kept alive here."""
 
     def __init__(self, scene, params: Optional[Dict] = None, stream: Optional[int] = None, arena=None):
         pd = dict(scene.params if params is None else params)

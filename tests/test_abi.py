@@ -95,3 +95,32 @@ def test_required_bytes_without_device():
         raise AssertionError("accepted a negative radius")
     except sph.SphError as e:
         assert e.code == sph.SPH_ERR_INVALID
+
+
+def test_misaligned_arena_is_rejected_before_any_device_call():
+    # the arena's pieces are 256-byte aligned only if the arena is; a lent
+    # pointer that is not is refused by the validation that precedes every
+    # device call (the fake address below is never dereferenced; the case is
+    # left to machines without a GPU all the same)
+    import ctypes as C
+    import numpy as np
+    import pytest
+    import torch
+    from paper_2403_11156_amd import scenes, sph
+    if torch.cuda.device_count() > 0:
+        pytest.skip("uses a fake device address; run where no GPU is visible")
+    s = scenes.small_scene(4, 4, 4)
+    keep = [np.ascontiguousarray(s.x_fluid, np.float32), np.ascontiguousarray(s.v_fluid, np.float32),
+            np.ascontiguousarray(s.x_boundary, np.float32).reshape(-1, 3),
+            np.ascontiguousarray(s.body_of_boundary, np.int32)]
+    sc = sph.sph_scene()
+    sc.n_fluid, sc.n_boundary, sc.n_rigid = s.n_fluid, s.n_boundary, 0
+    sc.x_fluid, sc.v_fluid, sc.x_boundary, sc.body_of_boundary = (sph._ptr(a) for a in keep)
+    need = sph.required_bytes(s)
+    sc.device_arena = C.c_void_p(0x7f0000000010)   # 16-byte, not 256-byte, aligned
+    sc.device_arena_bytes = need + 4096
+    p = sph.make_params(dict(s.params))
+    ctx = C.c_void_p()
+    rc = sph.sph_create(C.byref(p), C.byref(sc), None, C.byref(ctx))
+    assert rc == sph.SPH_ERR_INVALID and not ctx.value
+    assert b"256-byte aligned" in sph.sph_last_error(None)
