@@ -17,6 +17,9 @@
 // atomics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
+
 #include "sph_internal.h"
 
 namespace sph {
@@ -352,14 +355,17 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const uint32_t* __restrict_
 }
 
 // The learned warm start in one pass (when no training trace is recorded):
-// each particle's features computed from its fields exactly as k_features
-// does, the network, and the start stiffness exactly as k_warm_learned sets
-// it: kappa = K0 = max(0, y alpha rho0 / dt^2), K = 0, x.w = K0 / rho.
+// each particle's features from its fields, the network, and the start
+// stiffness kappa = K0 = max(0, y alpha rho0 / dt^2), K = 0, x.w = K0 / rho,
+// as k_features and k_warm_learned compute them except that a division by
+// a constant (rho0, alpha_ref, 26, dt^2 / rho0 ...) is a product with its
+// FP32 reciprocal here, cf below (within two units in the last place: the
+// IEEE divisions were a third of the pass's vector instructions).
 // Lane half 0 holds features 0..3 of its sample, half 1 feature 4.
 __device__ __forceinline__ void load_fields(int64_t n, int64_t base, const float* __restrict__ rho,
                                             const float* __restrict__ alpha, const float* __restrict__ K,
                                             const uint32_t* __restrict__ ncnt, const uint32_t* __restrict__ bcnt,
-                                            const float* __restrict__ d, const Kern& kc, float dt, float alpha_ref,
+                                            const float* __restrict__ d, const Kern& kc, const float cf[5],
                                             float fr[4], float raw[3]) {
     const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
     const int64_t i = base + p;
@@ -369,15 +375,15 @@ __device__ __forceinline__ void load_fields(int64_t n, int64_t base, const float
     const float a = alpha[i];
     if (h == 0) {   // these lanes also store the start: rho, alpha and K stay in registers for it
         const float r = rho[i], k = K[i];
-        fr[0] = (r - kc.rho0) / kc.rho0;
-        fr[1] = dt * d[i] / kc.rho0;
-        fr[2] = (float)(ncnt[i] + bcnt[i]) / 26.0f;
-        fr[3] = a > 0.0f ? k * dt * dt / (a * kc.rho0) : 0.0f;
+        fr[0] = (r - kc.rho0) * cf[0];
+        fr[1] = d[i] * cf[1];
+        fr[2] = (float)(ncnt[i] + bcnt[i]) * (1.0f / 26.0f);
+        fr[3] = a > 0.0f ? k * cf[2] / a : 0.0f;
         raw[0] = r;
         raw[1] = a;
         raw[2] = k;
     } else {
-        fr[0] = a / alpha_ref;
+        fr[0] = a * cf[3];
     }
 }
 
@@ -396,18 +402,20 @@ __global__ void __launch_bounds__(256) k_mlp_warm_start(const uint32_t* __restri
 #pragma unroll
     for (int q = 0; q < kImageWords; ++q) img[q] = packed[q * 64 + lane];
     __syncthreads();
+    // 1/rho0, dt/rho0, dt^2/rho0, 1/alpha_ref, rho0/dt^2
+    const float cf[5] = {1.0f / kc.rho0, dt / kc.rho0, dt * dt / kc.rho0, 1.0f / alpha_ref, kc.rho0 / (dt * dt)};
     const int64_t tiles = (n + 31) / 32, stride = (int64_t)gridDim.x * 4;
     float cur[4] = {0.f, 0.f, 0.f, 0.f}, craw[3] = {0.f, 0.f, 0.f};
     int64_t t = (int64_t)blockIdx.x * 4 + wave;
-    if (t < tiles) load_fields(n, 32 * t, rho, alpha, K, ncnt, bcnt, d, kc, dt, alpha_ref, cur, craw);
+    if (t < tiles) load_fields(n, 32 * t, rho, alpha, K, ncnt, bcnt, d, kc, cf, cur, craw);
     for (; t < tiles; t += stride) {
         float nxt[4] = {0.f, 0.f, 0.f, 0.f}, nraw[3] = {0.f, 0.f, 0.f};
         if (t + stride < tiles)
-            load_fields(n, 32 * (t + stride), rho, alpha, K, ncnt, bcnt, d, kc, dt, alpha_ref, nxt, nraw);
+            load_fields(n, 32 * (t + stride), rho, alpha, K, ncnt, bcnt, d, kc, cf, nxt, nraw);
         const float yv = forward_infer(W, R, cur, n, 32 * t);
         const int64_t i = 32 * t + lane;
         if (lane < 32 && i < n) {   // rho, alpha, K of particle i from the feature loads
-            const float k0 = fmaxf(yv * craw[1] * kc.rho0 / (dt * dt), 0.0f);
+            const float k0 = fmaxf(yv * craw[1] * cf[4], 0.0f);
             kappa[i] = k0;
             if (Ksave) Ksave[i] = craw[2];
             K[i] = 0.0f;
@@ -606,13 +614,42 @@ hipError_t launch_mlp_pack(const float* P, uint32_t* packed, hipStream_t s) {
     return hipGetLastError();
 }
 
+namespace {
+// Workgroups of 256 threads of `kernel` that the current device holds at
+// once (its compute units times the occupancy the kernel's registers
+// allow), looked up once per device; 0 when the runtime cannot say.  A
+// grid-stride pass launched with exactly that many runs in one wave of
+// workgroups: one more would leave a partial second round at the end.
+constexpr int kMaxResidentDevices = 64;
+int64_t resident_blocks(const void* kernel, std::atomic<int64_t>* cache) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxResidentDevices) return 0;
+    int64_t v = cache[dev].load(std::memory_order_relaxed);
+    if (v > 0) return v;
+    int ncu = 0, per = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess || ncu <= 0 || per <= 0)
+        return 0;
+    v = (int64_t)ncu * per;
+    cache[dev].store(v, std::memory_order_relaxed);
+    return v;
+}
+std::atomic<int64_t> g_resident_warm[kMaxResidentDevices], g_resident_forward[kMaxResidentDevices];
+
+// at most one resident round of four-wave workgroups (1024 if the runtime cannot say)
+int64_t mlp_grid(int64_t n, const void* kernel, std::atomic<int64_t>* cache) {
+    const int64_t tiles = (n + 31) / 32;
+    int64_t cap = resident_blocks(kernel, cache);
+    if (cap <= 0) cap = 1024;
+    return std::min((tiles + 3) / 4, cap);
+}
+}  // namespace
+
 hipError_t launch_mlp_warm_start(const uint32_t* packed, int64_t n, float4* x, const float* rho, const float* alpha,
                                  float* K, float* kappa, const uint32_t* ncnt, const uint32_t* bcnt, const float* d,
                                  Kern kc, float dt, float alpha_ref, float* Ksave, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int64_t tiles = (n + 31) / 32;
-    int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 1024) blocks = 1024;
+    const int64_t blocks = mlp_grid(n, reinterpret_cast<const void*>(k_mlp_warm_start), g_resident_warm);
     hipLaunchKernelGGL(k_mlp_warm_start, dim3((uint32_t)blocks), dim3(256), 0, s, packed, n, x, rho, alpha, K, kappa,
                        ncnt, bcnt, d, kc, dt, alpha_ref, Ksave);
     return hipGetLastError();
@@ -620,9 +657,8 @@ hipError_t launch_mlp_warm_start(const uint32_t* packed, int64_t n, float4* x, c
 
 hipError_t launch_mlp_forward(const uint32_t* packed, const float* feat, int64_t n, float* y, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int64_t tiles = (n + 31) / 32;
-    int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 1024) blocks = 1024;   // four resident blocks per CU (at most 128 VGPRs); weights staged once per block
+    // weights staged once per workgroup, so as few workgroups as fill the device
+    const int64_t blocks = mlp_grid(n, reinterpret_cast<const void*>(k_mlp_forward), g_resident_forward);
     hipLaunchKernelGGL(k_mlp_forward, dim3((uint32_t)blocks), dim3(256), 0, s, packed, feat, n, y);
     return hipGetLastError();
 }
