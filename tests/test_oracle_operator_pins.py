@@ -6,7 +6,8 @@ distance is exact in FP32):
 
 * the DFSPH density change rate (Eqs. 6 and 9 in the form the stiffness
   derivation needs), from fluid neighbours and from a moving wall;
-* the pressure acceleration of Eq. (7) and its boundary term, Eq. (13);
+* the pressure acceleration of Eq. (7) and its boundary term, Eq. (13),
+  including its odd-even null space and the push of a hydrostatic profile;
 * the XSPH velocity filter of the configurations;
 * the explicit viscosity of Eq. (15);
 * the DFSPH factor alpha next to a flat Akinci wall (Eq. 12's boundary
@@ -207,6 +208,49 @@ def test_pressure_acceleration_in_the_bulk_sees_only_the_stiff_particle():
     np.testing.assert_allclose(out["v"][idx], mag[:, None] * d / dist[:, None], rtol=1e-9, atol=0)
     far = np.setdiff1d(np.arange(len(x)), np.append(idx, c))
     assert np.all(out["v"][far] == 0.0)
+
+
+def test_layer_alternating_stiffness_exerts_no_force_in_the_bulk():
+    # the discrete pressure problem on the lattice has an odd-even null
+    # space: a stiffness that alternates between y layers gives every bulk
+    # particle the same value at the mirror image -o of each neighbour offset
+    # o, so the pair terms of Eq. (7) cancel and the field moves nothing
+    # there, whatever its amplitude (the reason a tightly converged step on
+    # a resting column can carry alternating layer pressures).  A ramp in y
+    # of the same size does push the bulk, as a pressure gradient should:
+    # for kappa/rho = c0 + b y the pair terms leave
+    #   dv_y = dt m |b| (k/h) sum_j |f'(q_j)| dy_j^2 / r_j
+    # (the constant part cancels in the bulk), and with the lattice sum
+    # sum_j |f'| dy^2/r = s (2 |f'(1/2)| + 8 |f'(1/sqrt2)|/sqrt2 + 8 |f'(sqrt3/2)|/sqrt3)
+    # a stiffness K = p/rho falling by g per metre of height, the hydrostatic
+    # profile, pushes every bulk particle up by dt g F with
+    # F = (m/rho)(k/h) sum = 1.0201: the discrete pressure force balances
+    # gravity to 2% on this lattice.
+    wf = 0.5
+    x, c = _lattice()
+    layer = np.rint((x[:, 1].astype(np.float64) - x[:, 1].min()) / S).astype(int)
+    idx3 = np.rint((x.astype(np.float64) - x.min(axis=0)) / S).astype(int)
+    bulk = np.all((idx3 >= 2) & (idx3 <= 6), axis=1)   # whole neighbourhoods of bulk density
+    assert bulk.sum() == 125
+    for K in (np.where(layer % 2 == 0, 64.0, 16.0), np.where(layer % 2 == 0, 0.0, 40.0)):
+        sc = _scene(x, warm_start=scenes.WARM_PREVIOUS, warm_factor=wf)
+        st = O.State(sc)
+        st.K[:] = K
+        out = O.step(st, forced_div=0, forced_dens=0)
+        scale = out["dt"] * M * wf * K.max() / RHO_LAT * KN / H * 6.0 * 27
+        assert np.abs(out["v"][bulk]).max() < 1e-12 * scale
+    sc = _scene(x, warm_start=scenes.WARM_PREVIOUS, warm_factor=wf)
+    st = O.State(sc)
+    st.K[:] = 64.0 - 6.0 * layer          # 64 down to 16 over the eight spacings
+    out = O.step(st, forced_div=0, forced_dens=0)
+    vy = out["v"][bulk, 1]
+    lat = S * (2.0 * abs(fp(Q1)) + 8.0 * abs(fp(Q2)) / math.sqrt(2.0) + 8.0 * abs(fp(Q3)) / math.sqrt(3.0))
+    F = M / RHO_LAT * KN / H * lat
+    assert abs(F - 1.0200697602806867) < 1e-12
+    b = wf * 6.0 / S / RHO_LAT                # |d(kappa/rho)/dy|
+    np.testing.assert_allclose(vy, out["dt"] * M * b * KN / H * lat, rtol=1e-9, atol=0)
+    np.testing.assert_allclose(vy, out["dt"] * (wf * 6.0 / S) * F, rtol=1e-9, atol=0)
+    assert np.abs(out["v"][bulk][:, [0, 2]]).max() < 1e-12 * vy.mean()
 
 
 def test_pressure_boundary_term_closed_form():
