@@ -162,7 +162,11 @@ def main():
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
-        print(f"[bench] calibration copy: {args.calib_copy_mb} MiB read + {args.calib_copy_mb} MiB written", flush=True)
+        # a read-only pass over the same bytes (a sum): a second kernel of
+        # known traffic for the read counter
+        total = float(b.sum())
+        print(f"[bench] calibration copy: {args.calib_copy_mb} MiB read + {args.calib_copy_mb} MiB written; "
+              f"then a sum reading {args.calib_copy_mb} MiB ({total:.0f})", flush=True)
         del a, b
     sc = scenes.scene(args.config)
     weights = os.path.join(ROOT, "paper_2403_11156_amd", "weights", "warm_start_mlp.f32")
