@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstddef>
 
 #include "sph_internal.h"
 
@@ -283,8 +284,11 @@ __device__ __forceinline__ void load_features(const float* __restrict__ feat, in
 
 // y of the 32 samples base..base+31 (valid in lanes 0..31 for sample lane)
 // from the raw features fr of load_features
-__device__ __forceinline__ float forward_infer(const InferConst& W, const InferRegs& R, const float fr[4], int64_t n,
-                                               int64_t base) {
+// w2(t, c), w3(u, off): the layer-2 A operand of tile t, chunk c, and the
+// layer-3 chunk u (off: the tile's opaque zero, for operands read from LDS)
+template <typename W2, typename W3>
+__device__ __forceinline__ float forward_infer_ops(const InferConst& W, const bf16x4 (&w1)[2], W2 w2, W3 w3,
+                                                   const float fr[4], int64_t n, int64_t base) {
     const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
     const int64_t s = base + p;
     uint16_t xv[4];
@@ -299,14 +303,15 @@ __device__ __forceinline__ float forward_infer(const InferConst& W, const InferR
         xv[c] = to_bf16(v);
     }
     const bf16x4 xb = pack4(xv);
-    // the bias rows are re-read from LDS every tile (an opaque offset keeps
-    // the compiler from holding them in 64 registers across the tile loop)
+    // the bias rows (and operands read from LDS) are re-read every tile: an
+    // opaque offset keeps the compiler from holding them in registers across
+    // the tile loop (64 for the biases)
     int boff = 0;
     asm volatile("" : "+v"(boff));
     const float* bp = &W.bperm[0][0][h][0] + boff;
     f32x16 z1[2];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) z1[t] = mfma(R.w1[t], xb, *reinterpret_cast<const f32x16*>(bp + 32 * t));
+    for (int t = 0; t < 2; ++t) z1[t] = mfma(w1[t], xb, *reinterpret_cast<const f32x16*>(bp + 32 * t));
     bf16x8 hb[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) hb[c] = relu_bf16x8(z1[c >> 1], 8 * (c & 1));
@@ -318,12 +323,51 @@ __device__ __forceinline__ float forward_infer(const InferConst& W, const InferR
     for (int t = 0; t < 2; ++t) {
         f32x16 acc = *reinterpret_cast<const f32x16*>(bp + 64 + 32 * t);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w2[t][c], hb[c], acc, 0, 0, 0);
+        for (int c = 0; c < 4; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2(t, c, boff), hb[c], acc, 0, 0, 0);
 #pragma unroll
         for (int u = 0; u < 2; ++u)
-            d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w3[2 * t + u], relu_bf16x8(acc, 8 * u), d, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w3(2 * t + u, boff), relu_bf16x8(acc, 8 * u), d, 0, 0, 0);
     }
     return (d[0] + W.b3) * W.out_scale;
+}
+
+// every operand in registers (the forward pass: 124 VGPRs, four waves per SIMD)
+__device__ __forceinline__ float forward_infer(const InferConst& W, const InferRegs& R, const float fr[4], int64_t n,
+                                               int64_t base) {
+    return forward_infer_ops(
+        W, R.w1, [&](int t, int c, int) { return R.w2[t][c]; }, [&](int u, int) { return R.w3[u]; }, fr, n, base);
+}
+
+// The layer-2 and layer-3 operands of every lane in LDS, chunk k of lane l
+// at [k][l] (w2[t][c] at k = 4 t + c, w3[u] at k = 8 + u): 16-byte reads
+// that 64 lanes make at 64 consecutive addresses.  Read per tile (through
+// the tile's opaque zero, so that the compiler does not keep them in
+// registers across the loop), they take 36 VGPRs off the warm-start pass,
+// which then holds four waves per SIMD instead of three.
+constexpr int kLdsChunks = 12;
+static_assert(sizeof(bf16x8) == 16 && offsetof(InferRegs, w2) == 16 && offsetof(InferRegs, w3) == 144,
+              "operand image layout");
+
+// stage the chunks of the image (dwords 4.. of every lane) into img; w1 stays in registers
+__device__ __forceinline__ void stage_operands(const uint32_t* __restrict__ packed, bf16x8 (*img)[64], bf16x4 (&w1)[2]) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t* w = reinterpret_cast<uint32_t*>(&w1[0]);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) w[d] = packed[d * 64 + lane];
+    for (int k = wave; k < kLdsChunks; k += (int)(blockDim.x >> 6)) {
+        u32x4 v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = packed[(4 + 4 * k + e) * 64 + lane];
+        img[k][lane] = __builtin_bit_cast(bf16x8, v);
+    }
+}
+
+__device__ __forceinline__ float forward_infer_lds(const InferConst& W, const bf16x8 (*img)[64], const bf16x4 (&w1)[2],
+                                                   const float fr[4], int64_t n, int64_t base) {
+    const int lane = threadIdx.x & 63;
+    return forward_infer_ops(
+        W, w1, [&](int t, int c, int off) { return img[4 * t + c][lane + off]; },
+        [&](int u, int off) { return img[8 + u][lane + off]; }, fr, n, base);
 }
 
 __global__ void __launch_bounds__(256) k_mlp_forward(const uint32_t* __restrict__ packed,
@@ -394,13 +438,12 @@ __global__ void __launch_bounds__(256) k_mlp_warm_start(const uint32_t* __restri
                                                         const uint32_t* __restrict__ bcnt, const float* __restrict__ d,
                                                         Kern kc, float dt, float alpha_ref, float* __restrict__ Ksave) {
     __shared__ InferConst W;
+    __shared__ bf16x8 img[kLdsChunks][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int q = threadIdx.x; q < kConstWords; q += blockDim.x)
         reinterpret_cast<uint32_t*>(&W)[q] = packed[64 * kImageWords + q];
-    InferRegs R;
-    uint32_t* img = reinterpret_cast<uint32_t*>(&R);
-#pragma unroll
-    for (int q = 0; q < kImageWords; ++q) img[q] = packed[q * 64 + lane];
+    bf16x4 w1[2];
+    stage_operands(packed, img, w1);
     __syncthreads();
     // 1/rho0, dt/rho0, dt^2/rho0, 1/alpha_ref, rho0/dt^2
     const float cf[5] = {1.0f / kc.rho0, dt / kc.rho0, dt * dt / kc.rho0, 1.0f / alpha_ref, kc.rho0 / (dt * dt)};
@@ -412,7 +455,7 @@ __global__ void __launch_bounds__(256) k_mlp_warm_start(const uint32_t* __restri
         float nxt[4] = {0.f, 0.f, 0.f, 0.f}, nraw[3] = {0.f, 0.f, 0.f};
         if (t + stride < tiles)
             load_fields(n, 32 * (t + stride), rho, alpha, K, ncnt, bcnt, d, kc, cf, nxt, nraw);
-        const float yv = forward_infer(W, R, cur, n, 32 * t);
+        const float yv = forward_infer_lds(W, img, w1, cur, n, 32 * t);
         const int64_t i = 32 * t + lane;
         if (lane < 32 && i < n) {   // rho, alpha, K of particle i from the feature loads
             const float k0 = fmaxf(yv * craw[1] * cf[4], 0.0f);
