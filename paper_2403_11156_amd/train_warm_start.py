@@ -14,6 +14,7 @@
 3. The FP32 parameters go to weights/warm_start_mlp.f32 with a JSON record.
 
     python -m paper_2403_11156_amd.train_warm_start [--epochs 40] [--quick]
+        [--runs c1:100:1,c2:1000:10] [--dagger WEIGHTS] [--out PATH]
 """
 
 from __future__ import annotations
@@ -136,6 +137,8 @@ def main():
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--dagger", default="",
                     help="weights whose learned start also runs the trace scenes; its traces join the plain ones")
+    ap.add_argument("--runs", default="",
+                    help="trace runs as name:steps:every,... (default c1:100:1,c2:1000:10)")
     ap.add_argument("--commit", default=os.environ.get("TRACE_COMMIT", ""),
                     help="the repository commit whose solver produced the traces (recorded)")
     args = ap.parse_args()
@@ -143,6 +146,8 @@ def main():
     from paper_2403_11156_amd import scenes, sph
     torch.cuda.set_device(0)
     runs = [("c1", 100, 1)] if args.quick else [("c1", 100, 1), ("c2", 1000, 10)]
+    if args.runs:
+        runs = [(a, int(b), int(c)) for a, b, c in (r.split(":") for r in args.runs.split(","))]
     F, T = collect(runs, torch, sph, scenes)
     if args.dagger:
         dagger = np.fromfile(args.dagger, dtype=np.float32)
