@@ -2,11 +2,15 @@
 whole-run statistics against the oracle's own run (SPH is chaotic, so a
 trajectory over many steps is compared by its statistics, not pointwise)."""
 
+import os
+
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2403_11156_amd import scenes
+
+WEIGHTS = os.path.join(os.path.dirname(scenes.__file__), "weights", "warm_start_mlp.f32")
 
 pytestmark = pytest.mark.gpu
 
@@ -19,14 +23,19 @@ def sph():
     return mod
 
 
-def _run_bounded(sph, name, steps, report_every):
+def _run_bounded(sph, name, steps, report_every, learned=False):
     """Every step meets the density solve's stop rule (mean and largest
     compression) and the divergence solve's, or hits the cap; the state stays
     finite and no particle exceeds 60 m/s (the dam breaks' fastest spray is
-    ~26 m/s; a runaway passes hundreds)."""
+    ~26 m/s, the surge over c3's bodies ~35 m/s; a runaway passes hundreds).
+    learned: the density solve starts from the trained network's stiffness."""
     sc = scenes.scene(name)
     p = sc.params
     sim = sph.Simulation(sc, params=dict(sc.params, auto_rebuild=1))
+    net = None
+    if learned:
+        net = sph.MLP(np.fromfile(WEIGHTS, dtype=np.float32))
+        sim.set_warm_start(2, net)
     t = 0.0
     iters = np.zeros(2)
     for k in range(steps):
@@ -36,6 +45,7 @@ def _run_bounded(sph, name, steps, report_every):
         capped = st["iters_dens"] == p["max_iters"]
         assert (st["err_dens"] <= p["eta_density"] and st["err_dens_max"] <= p["eta_density_max"]) or capped, (k, st)
         assert st["err_div"] <= p["eta_divergence"] or st["iters_div"] == p["max_iters"], (k, st)
+        assert st["warm_fallback"] == 0, (k, st)
         if (k + 1) % report_every == 0:
             v = sim.read(("v",))["v"].astype(np.float64)
             vmax = float(np.sqrt((v * v).sum(axis=1)).max())
@@ -43,6 +53,8 @@ def _run_bounded(sph, name, steps, report_every):
                   f"iterations/step div {iters[0] / (k + 1):.2f} dens {iters[1] / (k + 1):.2f}", flush=True)
             assert np.isfinite(vmax) and vmax < 60.0, (k, vmax)
     sim.close()
+    if net is not None:
+        net.close()
     return t
 
 
@@ -52,10 +64,28 @@ def test_c2_runs_its_configured_length(sph):
     assert t > 0.5
 
 
-def test_c5_runs_past_the_far_wall_impact(sph):
-    # the front reaches the far wall near step 226; 500 steps run well past it
-    t = _run_bounded(sph, "c5", 500, 100)
+def test_c5_runs_its_configured_length(sph):
+    # the front reaches the far wall near step 226 and the whole run of 1000
+    # steps goes on well past it
+    sc = scenes.scene("c5")
+    t = _run_bounded(sph, "c5", sc.steps, 100)
+    assert t > 0.35
+
+
+@pytest.mark.parametrize("name", ["c3", "c3i", "c4"])
+def test_rigid_and_viscous_workloads_run_their_configured_length(sph, name):
+    # the rigid-coupling workloads (bodies beside and inside the block, with
+    # contact) and the implicit-viscosity column, 500 steps each
+    sc = scenes.scene(name)
+    t = _run_bounded(sph, name, sc.steps, 100)
     assert t > 0.25
+
+
+@pytest.mark.parametrize("name", ["c5", "c2"])
+def test_learned_start_runs_its_configured_length(sph, name):
+    sc = scenes.scene(name)
+    t = _run_bounded(sph, name, sc.steps, 200, learned=True)
+    assert t > 0.35
 
 
 def test_c2_hundred_steps_statistics(sph):
